@@ -1,0 +1,235 @@
+/*
+ * gdm.h -- graph-partitioned density matrices on MI355X (gfx950).
+ *
+ * C ABI of the data-parallel hot path of graph-based linear-scaling
+ * electronic structure (SEDACS, "Graph-Based Linear-Scaling Electronic-
+ * Structure Theory" and "Dynamic Graph Adaption" sections):
+ *
+ *   neighbour graph -> spatial cores -> core+halo subgraphs -> per-subgraph
+ *   D = Z f(Z^T H Z) Z^T at one global chemical potential mu -> collected
+ *   core rows of D -> Mulliken charges -> graph of the next step from D.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every array argument is a DEVICE pointer owned by the caller unless the
+ *   comment says HOST.  The library never frees caller memory.  It owns only
+ *   its context and a workspace arena sized by gdm_plan (allocated there, not
+ *   in the solve calls).
+ * - All device work is enqueued on the stream given to gdm_create (or
+ *   gdm_set_stream).  Calls that return a size or a scalar to a HOST pointer
+ *   synchronise that stream before returning.
+ * - Return value: GDM_OK (0) or a negative GDM_E_* code.  Arguments are
+ *   validated on the host before anything is enqueued; on a validation error
+ *   nothing is enqueued.  Conditions detected on the device (non-positive-
+ *   definite overlap, non-converged iteration, NaN, capacity) are recorded
+ *   in the context's device status word and reported by gdm_check and by the
+ *   next call that synchronises.  gdm_last_error gives a message.
+ * - Matrices are row-major.  Orbitals of an atom are ordered s, px, py, pz
+ *   (hydrogen-like species have s only).  A subgraph's atoms are its core
+ *   atoms in ascending order followed by its halo atoms in ascending order;
+ *   its orbitals follow its atoms.
+ * - Density matrices are per spin (occupations in [0, 1]); the electron count
+ *   is 2 Tr[D S] (the paper writes Tr[D] = N_occ for an orthonormal basis).
+ */
+#ifndef GDM_H
+#define GDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GDM_OK = 0,
+    GDM_E_ARG = -1,           /* bad argument (null, size, range)                  */
+    GDM_E_CAPACITY = -2,      /* output capacity too small; required size returned */
+    GDM_E_NOT_PD = -3,        /* a subgraph overlap matrix is not positive definite */
+    GDM_E_NO_BRACKET = -4,    /* electron count cannot be matched inside the bracket */
+    GDM_E_NOT_CONVERGED = -5, /* an iteration hit its cap                          */
+    GDM_E_NAN = -6,           /* NaN or Inf produced                               */
+    GDM_E_HIP = -7,           /* HIP runtime error                                 */
+    GDM_E_STATE = -8          /* call order violated (e.g. density before find_mu) */
+};
+
+enum { GDM_GRAPH_CUTOFF = 0, GDM_GRAPH_DM = 1, GDM_GRAPH_ADAPTIVE = 2 };
+
+/* Subgraph solver.  GDM_FP64_EIG: FP64 Cholesky basis + FP64 symmetric
+ * eigendecomposition (the "direct diagonalization" option).  GDM_MIXED_F16:
+ * GEMM-only recursive Fermi-operator expansion with split FP16 operands and
+ * FP32 accumulation on the matrix cores, FP64 for bounds, traces, mu and
+ * the final step (the recursive-FOE option). */
+enum { GDM_FP64_EIG = 0, GDM_MIXED_F16 = 1 };
+
+typedef struct gdm_ctx gdm_ctx;
+
+/* The full system (Interface section: coordinates, atom types, lattice
+ * vectors, orbital indices). */
+typedef struct {
+    int32_t n_atoms;
+    const double* pos;        /* [n_atoms*3] A, wrapped into [0, box)            */
+    const int32_t* species;   /* [n_atoms] 0 (O-like: s,p) or 1 (H-like: s)      */
+    const int32_t* anchor;    /* [n_atoms] atom whose position picks the core cell
+                                 (the O of a water for both its H)              */
+    const int32_t* orb_ptr;   /* [n_atoms+1] first global orbital of each atom   */
+    double box[3];            /* orthorhombic periodic box edges, A              */
+    double inv_box[3];        /* 1/box as computed by the caller; used as given so
+                                 that minimum images are reproducible bit for bit */
+} gdm_system;
+
+/* Synthetic two-centre tight-binding model (stand-in for the SCC-DFTB tables):
+ * V(r) = v0 exp(-(r - v_r0)/v_decay), S(r) = s0 exp(-(r - s_r0)/s_decay) for
+ * r < cutoff, Slater-Koster sigma blocks with direction cosines from the row
+ * atom, V_pp_pi = 0. */
+typedef struct {
+    double onsite[2][4];      /* eV per species and orbital type (s, px, py, pz) */
+    int32_t n_orb[2];         /* orbitals per species: 4 and 1                  */
+    double v0, v_r0, v_decay;
+    double s0, s_r0, s_decay;
+    double cutoff;            /* A, strict r < cutoff                            */
+    int32_t orthogonal;       /* 1: S = I                                        */
+} gdm_tb_params;
+
+/* Subgraph set.  Device arrays plus HOST copies of the per-subgraph sizes
+ * (planning needs them on the host). */
+typedef struct {
+    int32_t n_sub;
+    const int32_t* atom_ptr;     /* [n_sub+1]                                      */
+    const int32_t* atoms;        /* [atom_ptr[n_sub]] core ascending, then halo ascending */
+    const int32_t* n_core;       /* [n_sub] core atoms per subgraph                 */
+    const int32_t* h_norb;       /* HOST [n_sub] orbitals n_s of each subgraph       */
+    const int32_t* h_ncore_orb;  /* HOST [n_sub] core orbitals nc_s                  */
+} gdm_subgraphs;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL:
+ * the default stream).  Allocates the device status word. */
+int gdm_create(gdm_ctx** out, int device, void* hip_stream);
+int gdm_destroy(gdm_ctx* ctx);
+int gdm_set_stream(gdm_ctx* ctx, void* hip_stream);
+/* Message of the last error recorded in the context (never NULL). */
+const char* gdm_last_error(const gdm_ctx* ctx);
+/* Synchronise the stream and return the device status word as a GDM code
+ * (GDM_OK if no device-side condition was raised); clears it. */
+int gdm_check(gdm_ctx* ctx);
+
+/* ------------------------------------------------------------ graph: a1, a3 */
+
+/* Build the atom graph as CSR (rows ascending, columns ascending, no self
+ * edges).
+ *  mode GDM_GRAPH_CUTOFF: edge (i, j) iff r_ij^2 < cutoff^2 with the minimum
+ *    image d = x_j - x_i, d -= L rint(d inv_L), r^2 = (dx dx + dy dy) + dz dz
+ *    evaluated without contraction (Determining the Subgraphs: initial graph
+ *    from a distance neighbour list).  Cell-list search.
+ *  mode GDM_GRAPH_DM: edge iff max(G^D_ij, G^D_ji) > tau, where G^D is the
+ *    atom-condensed |D| (largest |D_ab| of each atom-atom block) taken from the
+ *    collected core rows `D_core` of subgraph set `prev` (packed as written by
+ *    gdm_subgraph_density).
+ *  mode GDM_GRAPH_ADAPTIVE: edge iff max(W_ij, W_ji) > tau with
+ *    W = G^N G^D + G^D G^N, G^N_ij = exp(-alpha r_ij^2) on the neighbour CSR
+ *    (nbr_row_ptr, nbr_col) plus G^N_ii = 1 (Eq. neigh_mat, Eq.
+ *    Graph_Adaptation).
+ * `union_row_ptr/union_col` (nullable, DM and ADAPTIVE modes): edges of this
+ * graph are kept as well (the initial-SCF rule: edges are only added).
+ * Output: row_ptr [n_atoms+1], col [cap].  *nnz_out (HOST) receives the edge
+ * count; if it exceeds cap the call returns GDM_E_CAPACITY and col is not
+ * written. */
+int gdm_build_graph(gdm_ctx* ctx, const gdm_system* sys, int mode, double cutoff,
+                    double alpha, double tau,
+                    const gdm_subgraphs* prev, const double* D_core,
+                    const int32_t* nbr_row_ptr, const int32_t* nbr_col,
+                    const int32_t* union_row_ptr, const int32_t* union_col,
+                    int32_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz_out);
+
+/* ----------------------------------------------------- partition: a4, a5 */
+
+/* Spatial-grid core partition (stand-in for the community detection of
+ * Determining the Subgraphs): per axis cell = min(g-1, floor((x inv_L) g)) of
+ * the anchor atom's position, id = (i g_y + j) g_z + k; empty cells skipped,
+ * remaining cells numbered in ascending id.  core_of_atom [n_atoms];
+ * *n_cores_out HOST. */
+int gdm_grid_cores(gdm_ctx* ctx, const gdm_system* sys, const int32_t grid[3],
+                   int32_t* core_of_atom, int32_t* n_cores_out);
+
+/* Core+halo subgraphs (Fig. graph_partition b-c; SI section A): the halo of a
+ * core is every atom outside it with an edge to one of its atoms.  Outputs
+ * atom_ptr [n_cores+1], atoms [cap_atoms], n_core [n_cores]; HOST outputs
+ * h_norb [n_cores], h_ncore_orb [n_cores] (orbital counts, nullable) and
+ * *total_atoms_out.  GDM_E_CAPACITY if the packed atom list exceeds
+ * cap_atoms (nothing written to atoms).  n_atoms <= 1,000,000. */
+int gdm_extract_subgraphs(gdm_ctx* ctx, const gdm_system* sys, const gdm_tb_params* tb,
+                          const int32_t* row_ptr, const int32_t* col,
+                          const int32_t* core_of_atom, int32_t n_cores,
+                          int32_t* atom_ptr, int32_t* atoms, int64_t cap_atoms,
+                          int32_t* n_core, int32_t* h_norb, int32_t* h_ncore_orb,
+                          int64_t* total_atoms_out);
+
+/* ------------------------------------------------------- H and S: a2 */
+
+/* Block-sparse H and S over the neighbour CSR (row_ptr, col, nnz edges):
+ * block k < nnz is edge k, block nnz + i is atom i's on-site block; every
+ * block is 4x4 doubles row-major over (s, px, py, pz) (unused entries 0).
+ * V_atom (nullable, eV per atom) adds the SCC shift 1/2 S_ab (V_I + V_J)
+ * (SI section D).  H, S: [(nnz + n_atoms) * 16]; S may be NULL when
+ * tb->orthogonal. */
+int gdm_build_hs(gdm_ctx* ctx, const gdm_system* sys, const gdm_tb_params* tb,
+                 const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                 const double* V_atom, double* H, double* S);
+
+/* ------------------------------------------------- subgraph solve: a6-a14 */
+
+/* Size the workspace for subgraph set `sg` and solver `precision` and record
+ * the plan (size buckets, offsets).  The only call of the solve path that
+ * allocates.  Required before gdm_find_mu. */
+int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision);
+
+/* Gather every subgraph's principal submatrices h, s from the block-sparse
+ * H, S (LDS-staged), solve it with `precision`, and find the global chemical
+ * potential mu with N(mu) = 2 sum_s sum_k w_k f(lam_k) = n_electrons
+ * (Density Matrix Evaluation on Partitioned Graphs: mu fixes the occupation).
+ * FP64_EIG: multisection on the eigenvalues and core weights to an interval
+ * of 1e-12 eV, mu_guess ignored.  MIXED_F16: Newton steps from mu_guess on
+ * FP64 core traces with a bisection safeguard, one full expansion per pass,
+ * until |N - n_electrons| <= tol_N.  *mu_out, *n_out HOST.  The factorisation
+ * / expansion state is cached in the context for gdm_subgraph_density. */
+int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
+                const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                const double* H, const double* S, double n_electrons, double kT,
+                int precision, double mu_guess, double tol_N,
+                double* mu_out, double* n_out);
+
+/* Collected core rows D[core, :] of every subgraph (Eq. 3) at chemical
+ * potential mu, from the state cached by gdm_find_mu (same precision).
+ * Output packed in subgraph order: subgraph s occupies nc_s * n_s doubles,
+ * row-major (core orbital, subgraph orbital), at offset sum_{t<s} nc_t n_t.
+ * eig_out (nullable): FP64_EIG only, eigenvalues packed at sum_{t<s} n_t. */
+int gdm_subgraph_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT,
+                         int precision, double* D_core, double* eig_out);
+
+/* Mulliken charges from the collected core rows (SI section D):
+ * q_I = 2 sum_{a in I} sum_b D_ab S_ba - n0[species_I] for every atom (each
+ * atom is a core atom of exactly one subgraph).  S is read from the
+ * block-sparse overlap (NULL: orthogonal).  n0 HOST [2]; q_out [n_atoms]. */
+int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
+                         const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                         const double* S, const double* D_core, const double n0[2],
+                         double* q_out);
+
+/* ------------------------------------------------------------- tracing */
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every kernel launch of the solve path.  gdm_profile(ctx, 1) clears and
+ * starts recording, gdm_profile(ctx, 0) stops.  gdm_profile_query
+ * synchronises and returns, for the kernel named `kernel` (e.g. "sytrd"),
+ * the summed duration in ms and the number of launches since recording
+ * started (HOST outputs).  Unknown names give 0 launches.  At most 65536
+ * launches are recorded; later ones are not timed. */
+int gdm_profile(gdm_ctx* ctx, int enable);
+int gdm_profile_query(gdm_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GDM_H */

@@ -105,6 +105,25 @@ def neighbour_list(pos: np.ndarray, L: float, cutoff: float = 4.0, chunk: int = 
     return row_ptr, cols.astype(np.int64)
 
 
+def neighbour_list_kdtree(pos: np.ndarray, L: float, cutoff: float = 4.0):
+    """Same CSR as neighbour_list, with candidate pairs from a periodic k-d tree
+    (library routine) and the pair test redone with the exact expression above."""
+    from scipy.spatial import cKDTree
+    n = pos.shape[0]
+    pairs = cKDTree(pos, boxsize=L).query_pairs(cutoff * (1.0 + 1e-9), output_type="ndarray")
+    i = np.concatenate([pairs[:, 0], pairs[:, 1]])
+    j = np.concatenate([pairs[:, 1], pairs[:, 0]])
+    inv_L = 1.0 / L
+    r2 = r2_of(min_image(pos[j] - pos[i], L, inv_L))
+    keep = r2 < cutoff * cutoff
+    i, j = i[keep], j[keep]
+    order = np.lexsort((j, i))
+    i, j = i[order], j[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, i + 1, 1)
+    return np.cumsum(row_ptr), j.astype(np.int64)
+
+
 def _pair_factor(u: np.ndarray, ta: np.ndarray, tb: np.ndarray) -> np.ndarray:
     """Slater-Koster angular factor g[a, b] for row orbital type ta[a] and
     column orbital type tb[b], given direction cosines u[a, b, :] (x_J - x_I)/r."""

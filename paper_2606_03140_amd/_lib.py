@@ -1,0 +1,346 @@
+"""ctypes binding of libgdm (include/gdm.h).
+
+Argument marshalling only: every step of the density-matrix path runs in the
+HIP kernels of libgdm.so.  PyTorch provides device memory and the stream.
+The library must be built (``python -m paper_2606_03140_amd.build``);
+importing this module without it, or without a ROCm GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgdm.so")
+
+GDM_OK = 0
+ERRORS = {-1: "E_ARG", -2: "E_CAPACITY", -3: "E_NOT_PD", -4: "E_NO_BRACKET", -5: "E_NOT_CONVERGED",
+          -6: "E_NAN", -7: "E_HIP", -8: "E_STATE"}
+GRAPH_CUTOFF, GRAPH_DM, GRAPH_ADAPTIVE = 0, 1, 2
+FP64_EIG, MIXED_F16 = 0, 1
+
+EXPORTED = ["gdm_create", "gdm_destroy", "gdm_set_stream", "gdm_last_error", "gdm_check", "gdm_build_graph",
+            "gdm_grid_cores", "gdm_extract_subgraphs", "gdm_build_hs", "gdm_plan", "gdm_find_mu",
+            "gdm_subgraph_density", "gdm_mulliken_charges", "gdm_profile", "gdm_profile_query"]
+
+
+class GDMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SystemT(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("pos", C.c_void_p), ("species", C.c_void_p), ("anchor", C.c_void_p),
+                ("orb_ptr", C.c_void_p), ("box", C.c_double * 3), ("inv_box", C.c_double * 3)]
+
+
+class TBParamsT(C.Structure):
+    _fields_ = [("onsite", (C.c_double * 4) * 2), ("n_orb", C.c_int32 * 2), ("v0", C.c_double),
+                ("v_r0", C.c_double), ("v_decay", C.c_double), ("s0", C.c_double), ("s_r0", C.c_double),
+                ("s_decay", C.c_double), ("cutoff", C.c_double), ("orthogonal", C.c_int32)]
+
+
+class SubgraphsT(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("atom_ptr", C.c_void_p), ("atoms", C.c_void_p), ("n_core", C.c_void_p),
+                ("h_norb", C.c_void_p), ("h_ncore_orb", C.c_void_p)]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgdm is not built ({path} missing): run python -m paper_2606_03140_amd.build")
+    lib = C.CDLL(path)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "gdm_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, P]),
+        "gdm_destroy": (C.c_int, [P]),
+        "gdm_set_stream": (C.c_int, [P, P]),
+        "gdm_last_error": (C.c_char_p, [P]),
+        "gdm_check": (C.c_int, [P]),
+        "gdm_build_graph": (C.c_int, [P, C.POINTER(SystemT), C.c_int, D, D, D, C.POINTER(SubgraphsT), P, P, P, P, P,
+                                      P, P, I64, C.POINTER(C.c_int64)]),
+        "gdm_grid_cores": (C.c_int, [P, C.POINTER(SystemT), C.POINTER(C.c_int32), P, C.POINTER(C.c_int32)]),
+        "gdm_extract_subgraphs": (C.c_int, [P, C.POINTER(SystemT), C.POINTER(TBParamsT), P, P, P, I32, P, P, I64, P,
+                                            P, P, C.POINTER(C.c_int64)]),
+        "gdm_build_hs": (C.c_int, [P, C.POINTER(SystemT), C.POINTER(TBParamsT), P, P, I64, P, P, P]),
+        "gdm_plan": (C.c_int, [P, C.POINTER(SubgraphsT), C.c_int]),
+        "gdm_find_mu": (C.c_int, [P, C.POINTER(SystemT), C.POINTER(SubgraphsT), P, P, I64, P, P, D, D, C.c_int, D, D,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "gdm_subgraph_density": (C.c_int, [P, C.POINTER(SubgraphsT), D, D, C.c_int, P, P]),
+        "gdm_mulliken_charges": (C.c_int, [P, C.POINTER(SystemT), C.POINTER(SubgraphsT), P, P, I64, P, P,
+                                           C.POINTER(C.c_double), P]),
+    }
+    sig["gdm_profile"] = (C.c_int, [P, C.c_int])
+    sig["gdm_profile_query"] = (C.c_int, [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)])
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _ptr(t):
+    return C.c_void_p(0) if t is None else C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class TBParams:
+    """Synthetic two-centre model (water-like stand-in for SCC-DFTB tables)."""
+    eps_s_O: float = -23.9
+    eps_p_O: float = -9.0
+    eps_s_H: float = -6.4
+    v0: float = -4.0
+    v_r0: float = 1.0
+    v_decay: float = 0.5
+    s0: float = 0.3
+    s_r0: float = 1.0
+    s_decay: float = 0.6
+    cutoff: float = 4.0
+    orthogonal: bool = False
+
+    def struct(self) -> TBParamsT:
+        p = TBParamsT()
+        for a, v in enumerate((self.eps_s_O, self.eps_p_O, self.eps_p_O, self.eps_p_O)):
+            p.onsite[0][a] = v
+        p.onsite[1][0] = self.eps_s_H
+        p.n_orb[0], p.n_orb[1] = 4, 1
+        p.v0, p.v_r0, p.v_decay = self.v0, self.v_r0, self.v_decay
+        p.s0, p.s_r0, p.s_decay = self.s0, self.s_r0, self.s_decay
+        p.cutoff = self.cutoff
+        p.orthogonal = int(self.orthogonal)
+        return p
+
+
+N_ORB = (4, 1)
+VALENCE = (6.0, 1.0)
+
+
+class System:
+    """Device-resident system description (positions, species, anchors, orbital offsets)."""
+
+    def __init__(self, pos, species, anchor, box, device="cuda"):
+        species = np.asarray(species, dtype=np.int32)
+        self.n_atoms = int(species.shape[0])
+        self.pos = torch.as_tensor(np.ascontiguousarray(pos, dtype=np.float64)).to(device)
+        self.species = torch.as_tensor(species).to(device)
+        self.anchor = torch.as_tensor(np.asarray(anchor, dtype=np.int32)).to(device)
+        norb = np.array(N_ORB, dtype=np.int32)[species]
+        orb_ptr = np.zeros(self.n_atoms + 1, dtype=np.int32)
+        orb_ptr[1:] = np.cumsum(norb)
+        self.n_orb = int(orb_ptr[-1])
+        self.orb_ptr = torch.as_tensor(orb_ptr).to(device)
+        self.box = [float(b) for b in box]
+        self.inv_box = [1.0 / b for b in self.box]
+        self.n_electrons = float(np.array(VALENCE)[species].sum())
+        self.h_species = species
+
+    def set_positions(self, pos):
+        self.pos.copy_(torch.as_tensor(np.ascontiguousarray(pos, dtype=np.float64)))
+
+    def struct(self) -> SystemT:
+        s = SystemT()
+        s.n_atoms = self.n_atoms
+        s.pos, s.species, s.anchor, s.orb_ptr = (self.pos.data_ptr(), self.species.data_ptr(),
+                                                 self.anchor.data_ptr(), self.orb_ptr.data_ptr())
+        for a in range(3):
+            s.box[a] = self.box[a]
+            s.inv_box[a] = self.inv_box[a]
+        return s
+
+
+@dataclass
+class Graph:
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+
+class Subgraphs:
+    def __init__(self, atom_ptr, atoms, n_core, norb, ncore_orb):
+        self.atom_ptr, self.atoms, self.n_core = atom_ptr, atoms, n_core
+        self.norb = np.ascontiguousarray(norb, dtype=np.int32)
+        self.ncore_orb = np.ascontiguousarray(ncore_orb, dtype=np.int32)
+        self.n_sub = int(self.norb.shape[0])
+        dc = (self.norb.astype(np.int64) * self.ncore_orb)
+        self.dcore_off = np.concatenate([[0], np.cumsum(dc)])
+        self.eig_off = np.concatenate([[0], np.cumsum(self.norb.astype(np.int64))])
+
+    def struct(self) -> SubgraphsT:
+        s = SubgraphsT()
+        s.n_sub = self.n_sub
+        s.atom_ptr, s.atoms, s.n_core = self.atom_ptr.data_ptr(), self.atoms.data_ptr(), self.n_core.data_ptr()
+        s.h_norb = self.norb.ctypes.data
+        s.h_ncore_orb = self.ncore_orb.ctypes.data
+        return s
+
+    def host_lists(self):
+        ap = self.atom_ptr.cpu().numpy()
+        at = self.atoms.cpu().numpy()
+        nc = self.n_core.cpu().numpy()
+        return [(at[ap[s]:ap[s + 1]].astype(np.int64), int(nc[s])) for s in range(self.n_sub)]
+
+
+class Context:
+    """One libgdm context on a device and the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgdm needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = device
+        self.dev = torch.device("cuda", device)
+        self.lib = lib()
+        h = C.c_void_p()
+        stream = torch.cuda.current_stream(self.dev).cuda_stream
+        self._check(self.lib.gdm_create(C.byref(h), device, C.c_void_p(stream)), ctx=None)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gdm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, ctx="self"):
+        if rc != GDM_OK:
+            msg = "" if ctx is None else self.lib.gdm_last_error(self.h).decode()
+            raise GDMError(rc, msg)
+
+    def sync_stream(self):
+        self._check(self.lib.gdm_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)))
+
+    # ---------------------------------------------------------------- graph
+    def build_graph_cutoff(self, system: System, cutoff: float = 4.0) -> Graph:
+        row_ptr = torch.empty(system.n_atoms + 1, dtype=torch.int32, device=self.dev)
+        nnz = C.c_int64(0)
+        cap = 64 * system.n_atoms
+        for _ in range(2):
+            col = torch.empty(max(cap, 1), dtype=torch.int32, device=self.dev)
+            rc = self.lib.gdm_build_graph(self.h, C.byref(system.struct()), GRAPH_CUTOFF, cutoff, 0.0, 0.0, None, None,
+                                          None, None, None, None, _ptr(row_ptr), _ptr(col), cap, C.byref(nnz))
+            if rc == -2:
+                cap = int(nnz.value)
+                continue
+            self._check(rc)
+            break
+        return Graph(row_ptr, col[:nnz.value])
+
+    def build_graph_dm(self, system: System, mode: int, prev: "Subgraphs", D_core: torch.Tensor, tau: float,
+                       alpha: float = 0.7, nbr: Graph | None = None, union: Graph | None = None) -> Graph:
+        row_ptr = torch.empty(system.n_atoms + 1, dtype=torch.int32, device=self.dev)
+        nnz = C.c_int64(0)
+        cap = 128 * system.n_atoms
+        for _ in range(2):
+            col = torch.empty(max(cap, 1), dtype=torch.int32, device=self.dev)
+            rc = self.lib.gdm_build_graph(
+                self.h, C.byref(system.struct()), mode, 0.0, alpha, tau, C.byref(prev.struct()), _ptr(D_core),
+                _ptr(nbr.row_ptr if nbr else None), _ptr(nbr.col if nbr else None),
+                _ptr(union.row_ptr if union else None), _ptr(union.col if union else None),
+                _ptr(row_ptr), _ptr(col), cap, C.byref(nnz))
+            if rc == -2 and nnz.value > cap:
+                cap = int(nnz.value)
+                continue
+            self._check(rc)
+            break
+        return Graph(row_ptr, col[:nnz.value])
+
+    # ------------------------------------------------------------ partition
+    def grid_cores(self, system: System, grid) -> tuple[torch.Tensor, int]:
+        core = torch.empty(system.n_atoms, dtype=torch.int32, device=self.dev)
+        g = (C.c_int32 * 3)(*[int(x) for x in grid])
+        n = C.c_int32(0)
+        self._check(self.lib.gdm_grid_cores(self.h, C.byref(system.struct()), g, _ptr(core), C.byref(n)))
+        return core, int(n.value)
+
+    def extract_subgraphs(self, system: System, tb: TBParams, graph: Graph, core_of_atom, n_cores) -> Subgraphs:
+        atom_ptr = torch.empty(n_cores + 1, dtype=torch.int32, device=self.dev)
+        n_core = torch.empty(n_cores, dtype=torch.int32, device=self.dev)
+        norb = np.zeros(n_cores, dtype=np.int32)
+        ncore_orb = np.zeros(n_cores, dtype=np.int32)
+        total = C.c_int64(0)
+        cap = 16 * system.n_atoms
+        for _ in range(2):
+            atoms = torch.empty(max(cap, 1), dtype=torch.int32, device=self.dev)
+            rc = self.lib.gdm_extract_subgraphs(self.h, C.byref(system.struct()), C.byref(tb.struct()),
+                                                _ptr(graph.row_ptr), _ptr(graph.col), _ptr(core_of_atom), n_cores,
+                                                _ptr(atom_ptr), _ptr(atoms), cap, _ptr(n_core),
+                                                C.c_void_p(norb.ctypes.data), C.c_void_p(ncore_orb.ctypes.data),
+                                                C.byref(total))
+            if rc == -2 and total.value > cap:
+                cap = int(total.value)
+                continue
+            self._check(rc)
+            break
+        return Subgraphs(atom_ptr, atoms[:total.value], n_core, norb, ncore_orb)
+
+    # --------------------------------------------------------------- H and S
+    def build_hs(self, system: System, tb: TBParams, graph: Graph, V_atom: torch.Tensor | None = None):
+        nb = (graph.nnz + system.n_atoms) * 16
+        H = torch.empty(nb, dtype=torch.float64, device=self.dev)
+        S = None if tb.orthogonal else torch.empty(nb, dtype=torch.float64, device=self.dev)
+        self._check(self.lib.gdm_build_hs(self.h, C.byref(system.struct()), C.byref(tb.struct()), _ptr(graph.row_ptr),
+                                          _ptr(graph.col), graph.nnz, _ptr(V_atom), _ptr(H), _ptr(S)))
+        return H, S
+
+    # ----------------------------------------------------------------- solve
+    def plan(self, sg: Subgraphs, precision: int):
+        self._check(self.lib.gdm_plan(self.h, C.byref(sg.struct()), precision))
+
+    def find_mu(self, system: System, sg: Subgraphs, graph: Graph, H, S, kT: float, precision: int,
+                mu_guess: float = 0.0, tol_N: float = 1e-6, n_electrons: float | None = None):
+        mu = C.c_double(0.0)
+        n = C.c_double(0.0)
+        ne = system.n_electrons if n_electrons is None else n_electrons
+        self._check(self.lib.gdm_find_mu(self.h, C.byref(system.struct()), C.byref(sg.struct()), _ptr(graph.row_ptr),
+                                         _ptr(graph.col), graph.nnz, _ptr(H), _ptr(S), ne, kT, precision, mu_guess,
+                                         tol_N, C.byref(mu), C.byref(n)))
+        return mu.value, n.value
+
+    def subgraph_density(self, sg: Subgraphs, mu: float, kT: float, precision: int, eig: bool = False,
+                         out: torch.Tensor | None = None):
+        D = out if out is not None else torch.empty(int(sg.dcore_off[-1]), dtype=torch.float64, device=self.dev)
+        E = torch.empty(int(sg.eig_off[-1]), dtype=torch.float64, device=self.dev) if eig else None
+        self._check(self.lib.gdm_subgraph_density(self.h, C.byref(sg.struct()), mu, kT, precision, _ptr(D), _ptr(E)))
+        return (D, E) if eig else D
+
+    def mulliken_charges(self, system: System, sg: Subgraphs, graph: Graph, S, D_core, out=None):
+        q = out if out is not None else torch.empty(system.n_atoms, dtype=torch.float64, device=self.dev)
+        n0 = (C.c_double * 2)(*VALENCE)
+        self._check(self.lib.gdm_mulliken_charges(self.h, C.byref(system.struct()), C.byref(sg.struct()),
+                                                  _ptr(graph.row_ptr), _ptr(graph.col), graph.nnz, _ptr(S),
+                                                  _ptr(D_core), n0, _ptr(q)))
+        return q
+
+    def check(self):
+        self._check(self.lib.gdm_check(self.h))
+
+    # --------------------------------------------------------------- tracing
+    def profile(self, enable: bool):
+        self._check(self.lib.gdm_profile(self.h, int(enable)))
+
+    def profile_query(self, kernel: str):
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._check(self.lib.gdm_profile_query(self.h, kernel.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, int(n.value)

@@ -1,0 +1,173 @@
+// Internal declarations shared by the HIP translation units of libgdm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/gdm.h"
+
+#define GDM_STATUS_NOT_PD 1
+#define GDM_STATUS_NOT_CONVERGED 2
+#define GDM_STATUS_NAN 4
+#define GDM_STATUS_CAPACITY 8
+#define GDM_STATUS_NO_BRACKET 16
+
+// Per-subgraph descriptor for the dense solve (device resident).
+struct SubDesc {
+    int32_t n;        // orbitals
+    int32_t nc;       // core orbitals
+    int32_t ld;       // leading dimension of the dense n x n tiles
+    int32_t natoms;   // atoms (core + halo)
+    int32_t ncore_atoms;
+    int32_t atom0;    // offset into the packed atom list
+    int64_t off2;     // offset of the ld*ld tiles
+    int64_t offv;     // offset of length-ld vectors
+    int64_t offc;     // offset of nc*ld core blocks
+    int64_t offd;     // offset of the packed D core rows (nc*n)
+    int64_t offe;     // offset of packed eigenvalues (n)
+    int64_t offr;     // offset of the rotation record
+    int64_t rot_cap;  // rotation record capacity
+};
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Plan {
+    int precision = -1;
+    int n_sub = 0;
+    std::vector<int32_t> n, nc;
+    std::vector<SubDesc> desc;
+    std::vector<int32_t> order;     // subgraph processing order (largest first)
+    int64_t tot2 = 0, totv = 0, totc = 0, totd = 0, tote = 0, totr = 0;
+    int32_t max_n = 0, max_nc = 0, max_natoms = 0;
+    int generation = 0;
+};
+
+struct ProfRec {
+    const char* name;
+    hipEvent_t start, stop;
+};
+
+struct gdm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int* d_status = nullptr;
+    std::string err;
+    Plan plan;
+    // named device buffers (grown on demand at plan / graph time)
+    DevBuf b[64];
+    bool solved = false;        // find_mu has run on the current plan
+    int solved_precision = -1;
+    double mu_solved = 0.0;
+    double kT_solved = 0.0;
+    // tracing
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_pool;
+    std::vector<ProfRec> prof;
+};
+
+// Record events around one launch when tracing is on.
+struct GdmTimed {
+    gdm_ctx* ctx;
+    int idx = -1;
+    GdmTimed(gdm_ctx* c, const char* name) : ctx(c) {
+        if (!c->prof_on || 2 * (c->prof.size() + 1) > c->prof_pool.size()) return;
+        idx = (int)c->prof.size();
+        ProfRec r{name, c->prof_pool[2 * idx], c->prof_pool[2 * idx + 1]};
+        c->prof.push_back(r);
+        (void)hipEventRecord(r.start, c->stream);
+    }
+    ~GdmTimed() {
+        if (idx >= 0) (void)hipEventRecord(ctx->prof[idx].stop, ctx->stream);
+    }
+};
+#define GDM_TIMED(ctx, name) GdmTimed gdm_timed_scope_(ctx, name)
+
+// Buffer slots.
+enum {
+    BUF_DESC = 0, BUF_ORDER, BUF_A, BUF_S, BUF_L, BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W,
+    BUF_ROTC, BUF_ROTS, BUF_ROTI, BUF_ROTN, BUF_QC, BUF_CC, BUF_MU, BUF_MUPART,
+    BUF_G_CELL, BUF_G_CELLCNT, BUF_G_CELLSTART, BUF_G_CELLATOMS, BUF_G_CNT, BUF_G_TMP,
+    BUF_G_FLAGS, BUF_G_COUNTS, BUF_G_SCAN, BUF_G_TOTAL, BUF_G_W,
+    BUF_X_HI, BUF_X_LO, BUF_X_F, BUF_Y_HI, BUF_Y_LO, BUF_Y_F, BUF_T_HI, BUF_T_LO, BUF_T_F,
+    BUF_Z_HI, BUF_Z_LO, BUF_Z_F, BUF_H_HI, BUF_H_LO, BUF_H_F, BUF_TR, BUF_GERSH, BUF_NDBL,
+    BUF_TILES, BUF_PASS,
+    BUF_COUNT_
+};
+
+int gdm_fail(gdm_ctx* ctx, int code, const char* fmt, ...);
+int gdm_hip(gdm_ctx* ctx, hipError_t e, const char* what);
+void* gdm_buf(gdm_ctx* ctx, int slot, size_t bytes, bool* ok);
+
+#define GDM_HIP(ctx, call)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return gdm_hip((ctx), e_, #call); \
+    } while (0)
+
+#define GDM_STR2_(x) #x
+#define GDM_STR_(x) GDM_STR2_(x)
+#define GDM_LAUNCH_CHECK(ctx)                                                         \
+    do {                                                                              \
+        hipError_t e_ = hipGetLastError();                                            \
+        if (e_ != hipSuccess) return gdm_hip((ctx), e_, "launch at " __FILE__ ":" GDM_STR_(__LINE__)); \
+    } while (0)
+
+// exclusive scan over n int32 (out has n+1 entries, out[n] = total) on stream
+int gdm_scan_i32(gdm_ctx* ctx, const int32_t* in, int32_t* out, int64_t n);
+int gdm_scan_i64(gdm_ctx* ctx, const int64_t* in, int64_t* out, int64_t n);
+
+// solve paths
+int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
+                     const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                     const double* H, const double* S, double n_e, double kT,
+                     double* mu_out, double* n_out);
+int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT,
+                     double* D_core, double* eig_out);
+int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
+                      const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                      const double* H, const double* S, double n_e, double kT,
+                      double mu_guess, double tol_N, double* mu_out, double* n_out);
+int gdm_mixed_plan(gdm_ctx* ctx);
+int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT,
+                      double* D_core);
+
+// gather of principal submatrices (shared by both solvers)
+int gdm_launch_gather(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
+                      const int32_t* row_ptr, const int32_t* col, int64_t nnz,
+                      const double* H, const double* S, double* A, double* Sd, int orthogonal);
+
+// ---- device helpers
+__device__ __forceinline__ int gdm_lower_bound(const int32_t* a, int n, int32_t key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double gdm_wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float gdm_wave_sumf(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int gdm_wave_sumi(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void gdm_raise(int* status, int flag) {
+    atomicOr(status, flag);
+}

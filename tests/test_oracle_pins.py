@@ -300,3 +300,11 @@ def test_tau_error_decreases(box96):
         errs.append(np.max(np.abs(res.q - full.q)))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 1e-3
+
+
+def test_kdtree_neighbour_list_equals_bruteforce():
+    b = waterbox.water_box(400, 9)
+    L = b.box[0]
+    a = model.neighbour_list(b.pos, L)
+    k = model.neighbour_list_kdtree(b.pos, L)
+    assert np.array_equal(a[0], k[0]) and np.array_equal(a[1], k[1])
