@@ -191,7 +191,9 @@ int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision);
  * FP64_EIG: multisection on the eigenvalues and core weights to an interval
  * of 1e-12 eV, mu_guess ignored.  MIXED_F16: Newton steps from mu_guess on
  * FP64 core traces with a bisection safeguard, one full expansion per pass,
- * until |N - n_electrons| <= tol_N.  *mu_out, *n_out HOST.  The factorisation
+ * until |N - n_electrons| <= max(tol_N, 1e-7 n_electrons) (the rounding
+ * level of the traces); if the pass budget runs out first, the first-order
+ * correction mu + (n_electrons - N)/N'(mu) is applied when it lies within kT.  *mu_out, *n_out HOST.  The factorisation
  * / expansion state is cached in the context for gdm_subgraph_density. */
 int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
                 const int32_t* row_ptr, const int32_t* col, int64_t nnz,
@@ -215,6 +217,29 @@ int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
                          const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                          const double* S, const double* D_core, const double n0[2],
                          double* q_out);
+
+/* Options of the mixed-precision expansion (GDM_MIXED_F16): coupled
+ * Newton-Schulz iterations for s^-1/2 (ns_z, default 7), Newton-Schulz
+ * iterations per inverse in each doubling (ns_inv, default 3; the start has
+ * error <= 1/17, so k iterations reach (1/17)^(2^k)), and the number of
+ * expansion passes allowed while matching the electron count (max_passes,
+ * default 10).  Values <= 0 keep the current setting. */
+int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes);
+
+/* Statistics of the last GDM_MIXED_F16 gdm_find_mu (HOST outputs, nullable):
+ * expansion passes, doublings per pass, split GEMM launches, and the mean
+ * flops of one split GEMM launch counted once per product (2 P^2 per output
+ * tile row of P, over the tiles computed: products of commuting symmetric
+ * matrices compute the upper tiles only); each launch executes three FP16
+ * products. */
+int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int64_t* gemm_launches,
+                    double* flops_per_launch);
+
+/* Diagnostics: copy the FP32 matrix `which` (0 s, 1 h, 2 Y, 3 Z, 4 T, 5-6
+ * Newton-Schulz ping-pong, 7 h_perp, 8 W = Z s, 9 X, 10 X^2, 11 A, 12 R, 13
+ * inverse) of subgraph `sub` of the last GDM_MIXED_F16 solve into `out`
+ * (device, P*P floats, P the padded size = 64 ceil(n/64)). */
+int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out);
 
 /* ------------------------------------------------------------- tracing */
 

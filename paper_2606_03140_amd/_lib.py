@@ -25,7 +25,8 @@ FP64_EIG, MIXED_F16 = 0, 1
 
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_set_stream", "gdm_last_error", "gdm_check", "gdm_build_graph",
             "gdm_grid_cores", "gdm_extract_subgraphs", "gdm_build_hs", "gdm_plan", "gdm_find_mu",
-            "gdm_subgraph_density", "gdm_mulliken_charges", "gdm_profile", "gdm_profile_query"]
+            "gdm_subgraph_density", "gdm_mulliken_charges", "gdm_profile", "gdm_profile_query",
+            "gdm_set_mixed_options", "gdm_mixed_stats", "gdm_debug_slot"]
 
 
 class GDMError(RuntimeError):
@@ -74,6 +75,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gdm_mulliken_charges": (C.c_int, [P, C.POINTER(SystemT), C.POINTER(SubgraphsT), P, P, I64, P, P,
                                            C.POINTER(C.c_double), P]),
     }
+    sig["gdm_set_mixed_options"] = (C.c_int, [P, C.c_int, C.c_int, C.c_int])
+    sig["gdm_mixed_stats"] = (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_double)])
+    sig["gdm_debug_slot"] = (C.c_int, [P, C.c_int, C.c_int, P])
     sig["gdm_profile"] = (C.c_int, [P, C.c_int])
     sig["gdm_profile_query"] = (C.c_int, [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)])
     for name, (res, args) in sig.items():
@@ -334,6 +339,20 @@ class Context:
 
     def check(self):
         self._check(self.lib.gdm_check(self.h))
+
+    def set_mixed_options(self, ns_z: int = 0, ns_inv: int = 0, max_passes: int = 0):
+        self._check(self.lib.gdm_set_mixed_options(self.h, ns_z, ns_inv, max_passes))
+
+    def debug_slot(self, which: int, sub: int, P: int) -> torch.Tensor:
+        out = torch.empty(P * P, dtype=torch.float32, device=self.dev)
+        self._check(self.lib.gdm_debug_slot(self.h, which, sub, _ptr(out)))
+        return out.view(P, P)
+
+    def mixed_stats(self) -> dict:
+        p, nd, g, f = C.c_int(0), C.c_int(0), C.c_int64(0), C.c_double(0.0)
+        self._check(self.lib.gdm_mixed_stats(self.h, C.byref(p), C.byref(nd), C.byref(g), C.byref(f)))
+        return {"passes": p.value, "n_doublings": nd.value, "gemm_launches": g.value,
+                "flops_per_launch": f.value}
 
     # --------------------------------------------------------------- tracing
     def profile(self, enable: bool):

@@ -265,8 +265,9 @@ extern "C" int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgra
     if (rc) return rc;
     if ((rc = gdm_check(ctx))) return rc;
     if (!std::isfinite(*mu_out) || !std::isfinite(*n_out)) return gdm_fail(ctx, GDM_E_NAN, "gdm_find_mu: NaN result");
-    const double tol = precision == GDM_FP64_EIG ? 1e-6 * std::max(1.0, n_electrons) : std::max(tol_N, 1e-12);
-    if (std::fabs(*n_out - n_electrons) > std::max(tol, 1e-6 * n_electrons))
+    const double tol = precision == GDM_FP64_EIG ? 1e-6 * std::max(1.0, n_electrons)
+                                                 : std::max(tol_N, 1e-7 * n_electrons);
+    if (std::fabs(*n_out - n_electrons) > tol)
         return gdm_fail(ctx, GDM_E_NO_BRACKET, "gdm_find_mu: electron count %.12g, wanted %.12g", *n_out,
                         n_electrons);
     ctx->solved = true;

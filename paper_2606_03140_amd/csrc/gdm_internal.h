@@ -66,6 +66,18 @@ struct gdm_ctx {
     int solved_precision = -1;
     double mu_solved = 0.0;
     double kT_solved = 0.0;
+    // mixed path: options and the state of the last find_mu
+    int mixed_ns_z = 7;          // coupled Newton-Schulz iterations for s^-1/2
+    int mixed_ns_inv = 3;        // Newton-Schulz iterations per inverse
+    int mixed_max_passes = 10;   // expansion passes allowed for mu
+    int64_t mixed_tiles = 0, mixed_tiles_sym = 0;
+    double mixed_flops_full = 0, mixed_flops_sym = 0;  // one product per launch
+    double mixed_flops = 0;      // summed over the launches of the last find_mu
+    int64_t mixed_gemms = 0;
+    int mixed_passes = 0;
+    int mixed_nd = 0;
+    double mixed_mu_pass = 0.0;
+    double mixed_slope = 0.0;
     // tracing
     bool prof_on = false;
     std::vector<hipEvent_t> prof_pool;

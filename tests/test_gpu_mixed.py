@@ -1,0 +1,71 @@
+"""GPU parity of the mixed-precision recursive Fermi expansion (split FP16
+MFMA, FP32 accumulation, FP64 bounds/traces/final step) against the FP64
+oracle: D core rows within 1e-4 max-abs and Mulliken charges within 1e-4 e,
+electron count within the requested tolerance."""
+import numpy as np
+import pytest
+
+import waterbox
+from oracle import graph as og
+from oracle import model as om
+from oracle import solve as osv
+from tests.gpu_common import ctx, log, oracle_model, system_of, tb_params, unpack_dcore
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c():
+    return ctx()
+
+
+@pytest.mark.parametrize("nw,seed,grid,orth", [(96, 1, (2, 2, 2), False), (96, 1, (3, 3, 3), True),
+                                               (300, 21, (3, 3, 3), False)])
+def test_mixed_matches_fp64_oracle(c, nw, seed, grid, orth):
+    log(f"mixed solve {nw} waters grid {grid} orthogonal={orth}")
+    from paper_2606_03140_amd import pipeline
+    box = waterbox.water_box(nw, seed)
+    sysm = system_of(box)
+    L = box.box[0]
+    tb = tb_params(orth)
+    part = pipeline.cutoff_partition(c, sysm, tb, grid)
+    H, S = c.build_hs(sysm, tb, part.nbr)
+    rp, col = om.neighbour_list(box.pos, L)
+    core, nco = og.grid_cores(box.pos, box.anchor, L, grid)
+    subs = og.extract_subgraphs(rp, col, core, nco)
+    ref = osv.solve_system(box.pos, box.species, L, oracle_model(orth), subs)
+    sol = pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.MIXED_F16, mu_guess=ref.mu + 0.05, tol_N=1e-6)
+    st = c.mixed_stats()
+    gd = unpack_dcore(part.sg, sol.D_core)
+    err_d = max(np.abs(a - b).max() for a, b in zip(gd, ref.d_core))
+    err_q = np.abs(sol.q.cpu().numpy() - ref.q).max()
+    log(f"  mu {sol.mu:.6f} (oracle {ref.mu:.6f}) N {sol.n_count:.9f} passes {st['passes']} n_d "
+        f"{st['n_doublings']} gemms {st['gemm_launches']}  max|dD| {err_d:.2e} max|dq| {err_q:.2e}")
+    assert abs(sol.n_count - sysm.n_electrons) <= 1e-7 * sysm.n_electrons + 1e-9
+    assert err_d < 1e-4
+    assert err_q < 1e-4
+
+
+def test_mixed_mu_search_from_far_guess(c):
+    """mu found from a guess inside a band: Newton + bisection passes still
+    land within tolerance, and D matches the FP64 oracle to 1e-4."""
+    log("mixed mu search from a far guess")
+    from paper_2606_03140_amd import pipeline
+    box = waterbox.water_box(96, 1)
+    sysm = system_of(box)
+    L = box.box[0]
+    tb = tb_params(False)
+    part = pipeline.cutoff_partition(c, sysm, tb, (2, 2, 2))
+    H, S = c.build_hs(sysm, tb, part.nbr)
+    rp, col = om.neighbour_list(box.pos, L)
+    core, nco = og.grid_cores(box.pos, box.anchor, L, (2, 2, 2))
+    subs = og.extract_subgraphs(rp, col, core, nco)
+    ref = osv.solve_system(box.pos, box.species, L, oracle_model(False), subs)
+    c.set_mixed_options(max_passes=16)
+    sol = pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.MIXED_F16, mu_guess=-15.0, tol_N=1e-6)
+    c.set_mixed_options(max_passes=10)
+    st = c.mixed_stats()
+    err_q = np.abs(sol.q.cpu().numpy() - ref.q).max()
+    log(f"  passes {st['passes']} mu {sol.mu:.6f} N {sol.n_count:.9f} max|dq| {err_q:.2e}")
+    assert abs(sol.n_count - sysm.n_electrons) <= 1e-7 * sysm.n_electrons + 1e-9
+    assert err_q < 1e-4
