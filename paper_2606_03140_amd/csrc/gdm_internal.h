@@ -70,7 +70,7 @@ struct gdm_ctx {
     int mixed_ns_z = 7;          // coupled Newton-Schulz iterations for s^-1/2
     int mixed_ns_inv = 3;        // Newton-Schulz iterations per inverse
     int mixed_max_passes = 10;   // expansion passes allowed for mu
-    int64_t mixed_tiles = 0, mixed_tiles_sym = 0;
+    int64_t mixed_tiles = 0, mixed_tiles_sym = 0, mixed_tiles_core = 0;
     double mixed_flops_full = 0, mixed_flops_sym = 0;  // one product per launch
     double mixed_flops = 0;      // summed over the launches of the last find_mu
     int64_t mixed_gemms = 0;

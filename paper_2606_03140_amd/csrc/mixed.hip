@@ -46,7 +46,7 @@ struct GemmArgs {
     SplitMat A, B;       // operands (hi/lo used)
     SplitMat O1;         // raw product (nullable members)
     SplitMat O2;         // alpha*AB + beta*E + gamma*I
-    const float* E;
+    SplitMat E;          // read as f32 if present, else as hi + 2^-11 lo
     float alpha, beta, gamma;
     int sym;             // tiles cover i <= j only; results mirrored (exactly symmetric output)
 };
@@ -60,13 +60,50 @@ __device__ __forceinline__ void store_split(const SplitMat& m, int64_t idx, floa
     }
 }
 
-// Tile list entries: (subgraph, tile row, tile col)
+// Tile list entries: (subgraph, tile row, tile col).  Each workgroup forms a
+// 64 x 64 output tile with four waves (2 x 2 blocks of 32 x 32, each 2 x 2
+// MFMA 16x16x32 tiles, three products per k-step).  The next k-step is
+// prefetched into registers while the current one is multiplied; the result
+// is staged in LDS and written as coalesced rows, for the tile and, in
+// symmetric mode, for its mirror image.
+constexpr int kOperandLds = 4 * kTile * kLdsRow * 2;        // bytes of the four operand tiles
+constexpr int kOutLds = kTile * (kTile + 1) * 4;             // bytes of the staged output tile
+constexpr int kGemmLds = kOperandLds > kOutLds ? kOperandLds : kOutLds;
+
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void store4(const SplitMat& m, int64_t idx, float4 v) {
+    if (m.f) *(float4*)(m.f + idx) = v;
+    if (m.hi) {
+        half4 h, l;
+        const float x[4] = {v.x, v.y, v.z, v.w};
+        for (int q = 0; q < 4; ++q) {
+            const _Float16 hh = (_Float16)x[q];
+            h[q] = hh;
+            l[q] = (_Float16)((x[q] - (float)hh) * kLoScale);
+        }
+        *(half4*)(m.hi + idx) = h;
+        *(half4*)(m.lo + idx) = l;
+    }
+}
+
+// x = hi + 2^-11 lo for four consecutive elements
+__device__ __forceinline__ float4 load4(const SplitMat& m, int64_t idx) {
+    if (m.f) return *(const float4*)(m.f + idx);
+    const half4 h = *(const half4*)(m.hi + idx);
+    const half4 l = *(const half4*)(m.lo + idx);
+    return make_float4((float)h[0] + kLoInv * (float)l[0], (float)h[1] + kLoInv * (float)l[1],
+                       (float)h[2] + kLoInv * (float)l[2], (float)h[3] + kLoInv * (float)l[3]);
+}
+
 __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __restrict__ desc,
                                                             const int4* __restrict__ tiles, GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) _Float16 sAh[kTile * kLdsRow];
-    __shared__ __attribute__((aligned(16))) _Float16 sAl[kTile * kLdsRow];
-    __shared__ __attribute__((aligned(16))) _Float16 sBh[kTile * kLdsRow];
-    __shared__ __attribute__((aligned(16))) _Float16 sBl[kTile * kLdsRow];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[kGemmLds];
+    _Float16* sAh = (_Float16*)lds;
+    _Float16* sAl = sAh + kTile * kLdsRow;
+    _Float16* sBh = sAl + kTile * kLdsRow;
+    _Float16* sBl = sBh + kTile * kLdsRow;
+    float* sC = (float*)lds;                    // reused after the k loop: [64][65]
     const int4 tl = tiles[blockIdx.x];
     const SubDesc d = desc[tl.x];
     const int P = d.ld;
@@ -75,7 +112,6 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    // global -> LDS assignment: thread t loads 16 B (8 halves) of row t/4, chunk t%4
     const int lr = t >> 2, lc = (t & 3) * 8;
     const _Float16* gAh = g.A.hi + base + (int64_t)(m0 + lr) * P + lc;
     const _Float16* gAl = g.A.lo + base + (int64_t)(m0 + lr) * P + lc;
@@ -88,17 +124,23 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
             acc_x[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
         }
     const int fr = lane & 15, fk = (lane >> 4) * 8;
+    uint4 va = *(const uint4*)(gAh);
+    uint4 vb = *(const uint4*)(gAl);
+    uint4 vc = *(const uint4*)(gBh);
+    uint4 vd = *(const uint4*)(gBl);
     for (int k0 = 0; k0 < P; k0 += kK) {
-        uint4 va = *(const uint4*)(gAh + k0);
-        uint4 vb = *(const uint4*)(gAl + k0);
-        uint4 vc = *(const uint4*)(gBh + k0);
-        uint4 vd = *(const uint4*)(gBl + k0);
         __syncthreads();
         *(uint4*)(sAh + lr * kLdsRow + lc) = va;
         *(uint4*)(sAl + lr * kLdsRow + lc) = vb;
         *(uint4*)(sBh + lr * kLdsRow + lc) = vc;
         *(uint4*)(sBl + lr * kLdsRow + lc) = vd;
         __syncthreads();
+        if (k0 + kK < P) {
+            va = *(const uint4*)(gAh + k0 + kK);
+            vb = *(const uint4*)(gAl + k0 + kK);
+            vc = *(const uint4*)(gBh + k0 + kK);
+            vd = *(const uint4*)(gBl + k0 + kK);
+        }
         half8 ah[2], al[2], bh[2], bl[2];
         for (int i = 0; i < 2; ++i) {
             const int r = wm * 32 + i * 16 + fr;
@@ -117,34 +159,48 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
                 acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc_x[i][j], 0, 0, 0);
             }
     }
-    // epilogue.  In symmetric mode the tile list holds tile rows <= tile
-    // columns; every value is written at (m, n) and mirrored to (n, m), and in
-    // a diagonal tile only m <= n is taken, so the output is exactly symmetric.
-    const bool diag_tile = tl.y == tl.z;
+    __syncthreads();
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
             for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
-                const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-                if (g.sym && diag_tile && m > n) continue;
-                const int64_t idx = base + (int64_t)m * P + n;
-                const int64_t tdx = base + (int64_t)n * P + m;
-                const bool mirror = g.sym && m != n;
-                const float v = acc_hh[i][j][r] + kLoInv * acc_x[i][j][r];
-                if (g.O1.f || g.O1.hi) {
-                    store_split(g.O1, idx, v);
-                    if (mirror) store_split(g.O1, tdx, v);
-                }
-                if (g.O2.f || g.O2.hi) {
-                    float o = g.alpha * v;
-                    if (g.E) o += g.beta * g.E[idx];
-                    if (m == n) o += g.gamma;
-                    store_split(g.O2, idx, o);
-                    if (mirror) store_split(g.O2, tdx, o);
-                }
+                const int ml = wm * 32 + i * 16 + (lane >> 4) * 4 + r;
+                const int nl = wn * 32 + j * 16 + (lane & 15);
+                sC[ml * (kTile + 1) + nl] = acc_hh[i][j][r] + kLoInv * acc_x[i][j][r];
             }
+    __syncthreads();
+    // Rows of the tile (and, for off-diagonal symmetric tiles, of its mirror),
+    // four floats per lane, 16 lanes per 64-wide row: coalesced rows.  In a
+    // diagonal symmetric tile, (m, n) with m > n takes the value of (n, m).
+    const bool diag_tile = tl.y == tl.z;
+    const int npass = (g.sym && !diag_tile) ? 2 : 1;
+    const int c4 = (t & 15) * 4;
+    const bool has_e = g.E.f || g.E.hi;
+    for (int pass = 0; pass < npass; ++pass)
+        for (int rb = 0; rb < kTile; rb += kGemmThreads / 16) {
+            const int rl = rb + (t >> 4);
+            float x[4];
+            for (int q = 0; q < 4; ++q) {
+                const int cl = c4 + q;
+                if (pass == 1) x[q] = sC[cl * (kTile + 1) + rl];
+                else if (g.sym && diag_tile && rl > cl) x[q] = sC[cl * (kTile + 1) + rl];
+                else x[q] = sC[rl * (kTile + 1) + cl];
+            }
+            const int gm = (pass == 0 ? m0 : n0) + rl;
+            const int gn = (pass == 0 ? n0 : m0) + c4;
+            const int64_t idx = base + (int64_t)gm * P + gn;
+            if (g.O1.f || g.O1.hi) store4(g.O1, idx, make_float4(x[0], x[1], x[2], x[3]));
+            if (g.O2.f || g.O2.hi) {
+                float4 e = has_e ? load4(g.E, idx) : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float ev[4] = {e.x, e.y, e.z, e.w};
+                float o[4];
+                for (int q = 0; q < 4; ++q) {
+                    o[q] = g.alpha * x[q] + g.beta * ev[q];
+                    if (gm == gn + q) o[q] += g.gamma;
+                }
+                store4(g.O2, idx, make_float4(o[0], o[1], o[2], o[3]));
+            }
+        }
 }
-
 
 // ------------------------------------------------------------ FP64 GEMM
 // C = alpha A B + beta Cin + gamma I on the padded P x P tiles, true product
@@ -209,6 +265,63 @@ __global__ void __launch_bounds__(256) k_f32_to_f64(const SubDesc* __restrict__ 
     const SubDesc d = desc[blockIdx.x];
     const int P = d.ld;
     for (int64_t e = threadIdx.x; e < (int64_t)P * P; e += 256) dst[d.off2 + e] = (double)src[d.off2 + e];
+}
+
+// N_s = 2 sum_{a<nc, c<n} G_ac V_ac,  M_s = 2 sum (G - G2)_ac V_ac   (FP64)
+// with G = Z[core,:] X, G2 = Z[core,:] X^2, V = s[core,:] Z, so that
+// sum_c G_ac V_ac = (Z X Z s)_aa, the core diagonal of D s.
+__global__ void __launch_bounds__(256) k_trace_dot(const SubDesc* __restrict__ desc, const double* __restrict__ G,
+                                                  const double* __restrict__ G2, const double* __restrict__ V,
+                                                  double* __restrict__ part) {
+    __shared__ double red[4];
+    const SubDesc d = desc[blockIdx.x];
+    const int n = d.n, P = d.ld, nc = d.nc;
+    double an = 0.0, am = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)nc * n; e += 256) {
+        const int a = (int)(e / n), c = (int)(e - (int64_t)a * n);
+        const int64_t idx = d.off2 + (int64_t)a * P + c;
+        const double g = G[idx], v = V[idx];
+        an += g * v;
+        am += (g - G2[idx]) * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        an += __shfl_xor(an, o, 64);
+        am += __shfl_xor(am, o, 64);
+    }
+    __shared__ double red2[4];
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = an;
+        red2[threadIdx.x >> 6] = am;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = 2.0 * (red[0] + red[1] + red[2] + red[3]);
+        part[2 * blockIdx.x + 1] = 2.0 * (red2[0] + red2[1] + red2[2] + red2[3]);
+    }
+}
+
+// Gk <- G + kappa (G - G2) on the core rows (first-order mu correction of Z X)
+__global__ void __launch_bounds__(256) k_combine(const SubDesc* __restrict__ desc, const double* __restrict__ G,
+                                                const double* __restrict__ G2, double* __restrict__ Gk,
+                                                double kappa) {
+    const SubDesc d = desc[blockIdx.x];
+    const int P = d.ld, nc = d.nc;
+    const int rows = (nc + 63) / 64 * 64;
+    for (int64_t e = threadIdx.x; e < (int64_t)rows * P; e += 256) {
+        const int64_t idx = d.off2 + e;
+        Gk[idx] = G[idx] + kappa * (G[idx] - G2[idx]);
+    }
+}
+
+// D_core (packed nc x n) <- rows of the P-strided product
+__global__ void __launch_bounds__(256) k_pack_core(const SubDesc* __restrict__ desc, const double* __restrict__ Dp,
+                                                  double* __restrict__ Dout) {
+    const SubDesc d = desc[blockIdx.x];
+    const int n = d.n, P = d.ld, nc = d.nc;
+    for (int64_t e = threadIdx.x; e < (int64_t)nc * n; e += 256) {
+        const int a = (int)(e / n), c = (int)(e - (int64_t)a * n);
+        Dout[d.offd + e] = Dp[d.off2 + (int64_t)a * P + c];
+    }
 }
 
 // ------------------------------------------------------- elementwise kernels
@@ -346,45 +459,6 @@ __global__ void __launch_bounds__(kEw) k_x0(const SubDesc* __restrict__ desc, co
     }
 }
 
-// Per subgraph (FP64, refined Z):
-//   N_s = 2 sum_{a<nc} sum_c G_ac W_ca,  M_s = 2 sum_{a<nc} sum_c Gp_ac W_ca
-//   G = Z[core,:] X, Gp = Z[core,:] (X - X2), W[:, a] = Z s[:, a] (core columns).
-__global__ void __launch_bounds__(kEw) k_traces(const SubDesc* __restrict__ desc, const double* __restrict__ Z64,
-                                               const float* __restrict__ Xf, const float* __restrict__ X2f,
-                                               const double* __restrict__ s64, double* __restrict__ part) {
-    __shared__ double red[kEw / 64];
-    extern __shared__ double sm[];
-    double* zrow = sm;           // [n]
-    const SubDesc d = desc[blockIdx.x];
-    const int n = d.n, P = d.ld, nc = d.nc;
-    const int64_t base = d.off2;
-    double accN = 0.0, accM = 0.0;
-    for (int a = 0; a < nc; ++a) {
-        __syncthreads();
-        for (int b = threadIdx.x; b < n; b += kEw) zrow[b] = Z64[base + (int64_t)a * P + b];
-        __syncthreads();
-        for (int c = threadIdx.x; c < n; c += kEw) {
-            double gx = 0.0, gp = 0.0, w = 0.0;
-            const double* zc = Z64 + base + (int64_t)c * P;
-            for (int b = 0; b < n; ++b) {
-                const double x = (double)Xf[base + (int64_t)b * P + c];
-                const double x2 = (double)X2f[base + (int64_t)b * P + c];
-                gx += zrow[b] * x;
-                gp += zrow[b] * (x - x2);
-                w += zc[b] * s64[base + (int64_t)b * P + a];
-            }
-            accN += gx * w;
-            accM += gp * w;
-        }
-    }
-    accN = block_reduce_sum(accN, red);
-    accM = block_reduce_sum(accM, red);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = 2.0 * accN;
-        part[2 * blockIdx.x + 1] = 2.0 * accM;
-    }
-}
-
 __global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* __restrict__ out) {
     __shared__ double red[kEw / 64];
     double a = 0.0, b = 0.0;
@@ -397,44 +471,6 @@ __global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* 
     if (threadIdx.x == 0) {
         out[0] = a;
         out[1] = b;
-    }
-}
-
-// D_core[a][j] = sum_c G[a][c] Z[c][j],  G[a][c] = sum_b Z[a][b] (X + kappa (X - X2))[b][c]   (FP64)
-__global__ void __launch_bounds__(kEw) k_dcore_mixed(const SubDesc* __restrict__ desc, const double* __restrict__ Zf,
-                                                    const float* __restrict__ Xf, const float* __restrict__ X2f,
-                                                    double kappa, double* __restrict__ Gbuf,
-                                                    double* __restrict__ Dout) {
-    extern __shared__ double zrow[];
-    const SubDesc d = desc[blockIdx.x];
-    const int n = d.n, P = d.ld, nc = d.nc;
-    const int64_t base = d.off2;
-    double* G = Gbuf + d.offc;                // nc x n (ld = n)
-    for (int a = 0; a < nc; ++a) {
-        __syncthreads();
-        for (int b = threadIdx.x; b < n; b += kEw) zrow[b] = Zf[base + (int64_t)a * P + b];
-        __syncthreads();
-        for (int c = threadIdx.x; c < n; c += kEw) {
-            double g = 0.0;
-            for (int b = 0; b < n; ++b) {
-                const double x = (double)Xf[base + (int64_t)b * P + c];
-                const double x2 = (double)X2f[base + (int64_t)b * P + c];
-                g += zrow[b] * (x + kappa * (x - x2));
-            }
-            G[(int64_t)a * n + c] = g;
-        }
-    }
-    __syncthreads();
-    double* out = Dout + d.offd;
-    for (int a = 0; a < nc; ++a) {
-        __syncthreads();
-        for (int c = threadIdx.x; c < n; c += kEw) zrow[c] = G[(int64_t)a * n + c];
-        __syncthreads();
-        for (int j = threadIdx.x; j < n; j += kEw) {
-            double acc = 0.0;
-            for (int c = 0; c < n; ++c) acc += zrow[c] * Zf[base + (int64_t)c * P + j];
-            out[(int64_t)a * n + j] = acc;
-        }
     }
 }
 
@@ -477,6 +513,14 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
     }
     const size_t nfull = tiles.size();
     tiles.insert(tiles.end(), utiles.begin(), utiles.end());
+    std::vector<int4> ctiles;      // core-row tiles for the skinny FP64 products
+    for (int s : order) {
+        const int nt = P.desc[s].ld / kTile;
+        const int nr = (P.desc[s].nc + kTile - 1) / kTile;
+        for (int i = 0; i < nr; ++i)
+            for (int j = 0; j < nt; ++j) ctiles.push_back(make_int4(s, i, j, 0));
+    }
+    tiles.insert(tiles.end(), ctiles.begin(), ctiles.end());
     bool ok = true;
     int4* dt = (int4*)gdm_buf(ctx, BUF_TILES, sizeof(int4) * tiles.size(), &ok);
     gdm_buf(ctx, BUF_A, sizeof(double) * P.tot2, &ok);
@@ -488,11 +532,12 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
     gdm_buf(ctx, BUF_TR, sizeof(double) * (2 * (size_t)P.n_sub + 8), &ok);
     gdm_buf(ctx, BUF_NDBL, sizeof(double) * (size_t)P.n_sub, &ok);
     gdm_buf(ctx, BUF_CC, sizeof(double) * (size_t)P.totc, &ok);
-    gdm_buf(ctx, BUF_L, sizeof(double) * P.tot2 * 3, &ok);     // F, E, Z64 of the FP64 refinement
+    gdm_buf(ctx, BUF_L, sizeof(double) * P.tot2 * 5, &ok);     // F/V, E/G, Z64, G2, D (FP64)
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_plan: mixed workspace allocation failed");
     GDM_HIP(ctx, hipMemcpyAsync(dt, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, ctx->stream));
     ctx->mixed_tiles = (int64_t)nfull;
     ctx->mixed_tiles_sym = (int64_t)utiles.size();
+    ctx->mixed_tiles_core = (int64_t)ctiles.size();
     ctx->mixed_flops_full = ffull;
     ctx->mixed_flops_sym = fsym;
     return GDM_OK;
@@ -501,7 +546,9 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
 // C = A B for symmetric B (read row-major as B^T).  sym = 1 when A and B
 // commute (products of polynomials in the same matrix): only upper tiles are
 // computed and mirrored.
-static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, const float* E, float alpha,
+static SplitMat hl(SplitMat m) { return SplitMat{nullptr, m.hi, m.lo}; }
+
+static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, SplitMat E, float alpha,
                 float beta, float gamma, const char* tag, int sym = 1) {
     GemmArgs g{A, B, O1, O2, E, alpha, beta, gamma, sym};
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + (sym ? ctx->mixed_tiles : 0);
@@ -541,21 +588,21 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
     SplitMat Y = slot(ctx, SL_Y), Yn = slot(ctx, SL_YI);
     for (int it = 0; it < nd; ++it) {
         // X2 = X X ; A = 2 X2 - 2 X + I
-        GDM_TRY(gemm(ctx, X, X, X2, A, X.f, 2.0f, -2.0f, 1.0f, "foe_gemm"));
+        GDM_TRY(gemm(ctx, X, X, hl(X2), hl(A), hl(X), 2.0f, -2.0f, 1.0f, "foe_gemm"));
         // Newton-Schulz inverse of A from Y0 = c0 I + c1 A:
         //   R = 2I - A Y0 = 2I - c0 A - c1 A A ;  Y1 = Y0 R = c0 R + c1 A R
-        GDM_TRY(gemm(ctx, A, A, none(), Rm, A.f, -c1, -c0, 2.0f, "foe_gemm"));
-        GDM_TRY(gemm(ctx, A, Rm, none(), Y, Rm.f, c1, c0, 0.0f, "foe_gemm"));
+        GDM_TRY(gemm(ctx, A, A, none(), hl(Rm), hl(A), -c1, -c0, 2.0f, "foe_gemm"));
+        GDM_TRY(gemm(ctx, A, Rm, none(), hl(Y), hl(Rm), c1, c0, 0.0f, "foe_gemm"));
         for (int k = 1; k < ctx->mixed_ns_inv; ++k) {
-            GDM_TRY(gemm(ctx, A, Y, none(), Rm, nullptr, -1.0f, 0.0f, 2.0f, "foe_gemm"));
-            GDM_TRY(gemm(ctx, Y, Rm, Yn, none(), nullptr, 1.0f, 0.0f, 0.0f, "foe_gemm"));
+            GDM_TRY(gemm(ctx, A, Y, none(), hl(Rm), none(), -1.0f, 0.0f, 2.0f, "foe_gemm"));
+            GDM_TRY(gemm(ctx, Y, Rm, hl(Yn), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
             std::swap(Y, Yn);
         }
         // X <- X2 Y
-        GDM_TRY(gemm(ctx, X2, Y, X, none(), nullptr, 1.0f, 0.0f, 0.0f, "foe_gemm"));
+        GDM_TRY(gemm(ctx, X2, Y, it + 1 == nd ? X : hl(X), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
     }
     // X^2 of the final X (for N'(mu) and the first-order mu correction)
-    GDM_TRY(gemm(ctx, X, X, X2, none(), nullptr, 1.0f, 0.0f, 0.0f, "foe_gemm"));
+    GDM_TRY(gemm(ctx, X, X, X2, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
     return GDM_OK;
 }
 
@@ -581,14 +628,30 @@ static int gemm64_dd(gdm_ctx* ctx, const double* A, const double* B, const doubl
     return GDM_OK;
 }
 
+template <typename TB>
+static int gemm64_core(gdm_ctx* ctx, const double* A, const TB* B, double* C, const char* tag) {
+    GDM_TIMED(ctx, tag);
+    const int4* tl = (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles + ctx->mixed_tiles_sym;
+    hipLaunchKernelGGL((k_gemm64<double, TB>), dim3((unsigned)ctx->mixed_tiles_core), dim3(256), 0, ctx->stream,
+                       (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, (const double*)nullptr, C, 1.0, 0.0, 0.0);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+static double* fp64_region(gdm_ctx* ctx, int k) { return (double*)ctx->b[BUF_L].p + (int64_t)k * ctx->plan.tot2; }
+
 static int traces(gdm_ctx* ctx, double* N, double* M) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
     double* part = (double*)ctx->b[BUF_TR].p;
+    double* G = fp64_region(ctx, 1);
+    double* G2 = fp64_region(ctx, 3);
+    double* V = fp64_region(ctx, 0);
+    GDM_TRY(gemm64_core<float>(ctx, z64(ctx), slot(ctx, SL_X).f, G, "traces"));
+    GDM_TRY(gemm64_core<float>(ctx, z64(ctx), slot(ctx, SL_X2).f, G2, "traces"));
     {
         GDM_TIMED(ctx, "traces");
-        hipLaunchKernelGGL(k_traces, dim3(P.n_sub), dim3(kEw), sizeof(double) * P.max_n, ctx->stream, desc,
-                           z64(ctx), slot(ctx, SL_X).f, slot(ctx, SL_X2).f, (const double*)ctx->b[BUF_S].p, part);
+        hipLaunchKernelGGL(k_trace_dot, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, G, G2, V, part);
         GDM_LAUNCH_CHECK(ctx);
         hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kEw), 0, ctx->stream, P.n_sub, part,
                            part + 2 * (size_t)P.n_sub);
@@ -627,9 +690,9 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
              Z2 = slot(ctx, SL_Z2);
     if (!orth) {
         for (int it = 0; it < ctx->mixed_ns_z; ++it) {
-            GDM_TRY(gemm(ctx, Z, Y, none(), T, nullptr, -0.5f, 0.0f, 1.5f, "ns_gemm"));
-            GDM_TRY(gemm(ctx, Y, T, Y2, none(), nullptr, 1.0f, 0.0f, 0.0f, "ns_gemm"));
-            GDM_TRY(gemm(ctx, T, Z, Z2, none(), nullptr, 1.0f, 0.0f, 0.0f, "ns_gemm"));
+            GDM_TRY(gemm(ctx, Z, Y, none(), hl(T), none(), -0.5f, 0.0f, 1.5f, "ns_gemm"));
+            GDM_TRY(gemm(ctx, Y, T, hl(Y2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
+            GDM_TRY(gemm(ctx, T, Z, it + 1 == ctx->mixed_ns_z ? Z2 : hl(Z2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
             std::swap(Y, Y2);
             std::swap(Z, Z2);
         }
@@ -670,10 +733,11 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
             hipLaunchKernelGGL(k_z64_to_split, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Z64, Z);
         }
         GDM_LAUNCH_CHECK(ctx);
+        GDM_TRY(gemm64_core<double>(ctx, s64, Z64, F, "refine64"));   // V = s[core,:] Z
     }
     // h_perp = Z h Z (T = Z h, then T Z)
-    GDM_TRY(gemm(ctx, Z, slot(ctx, SL_H), T, none(), nullptr, 1.0f, 0.0f, 0.0f, "ns_gemm", 0));
-    GDM_TRY(gemm(ctx, T, Z, slot(ctx, SL_HP), none(), nullptr, 1.0f, 0.0f, 0.0f, "ns_gemm"));
+    GDM_TRY(gemm(ctx, Z, slot(ctx, SL_H), hl(T), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm", 0));
+    GDM_TRY(gemm(ctx, T, Z, slot(ctx, SL_HP), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
     {
         GDM_TIMED(ctx, "mixed_misc");
         hipLaunchKernelGGL(k_sym_bounds, dim3(P.n_sub), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP), bounds);
@@ -728,12 +792,24 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
 
 int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT, double* D_core) {
     const Plan& P = ctx->plan;
+    const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
     const double beta = 1.0 / kT;
     const double kappa = (mu - ctx->mixed_mu_pass) * beta;
-    GDM_TIMED(ctx, "dcore");
-    hipLaunchKernelGGL(k_dcore_mixed, dim3(P.n_sub), dim3(kEw), sizeof(double) * P.max_n, ctx->stream,
-                       (const SubDesc*)ctx->b[BUF_DESC].p, z64(ctx), slot(ctx, SL_X).f, slot(ctx, SL_X2).f,
-                       kappa, (double*)ctx->b[BUF_CC].p, D_core);
+    double* G = fp64_region(ctx, 1);
+    double* G2 = fp64_region(ctx, 3);
+    double* Gk = fp64_region(ctx, 0);
+    double* Dp = fp64_region(ctx, 4);
+    // D[core,:] = (G + kappa (G - G2)) Z,  G = Z[core,:] X, G2 = Z[core,:] X^2 of the last pass
+    {
+        GDM_TIMED(ctx, "dcore");
+        hipLaunchKernelGGL(k_combine, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, G, G2, Gk, kappa);
+    }
+    GDM_LAUNCH_CHECK(ctx);
+    GDM_TRY(gemm64_core<double>(ctx, Gk, z64(ctx), Dp, "dcore"));
+    {
+        GDM_TIMED(ctx, "dcore");
+        hipLaunchKernelGGL(k_pack_core, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Dp, D_core);
+    }
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }
