@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--paths", default="fp64,mixed")
+    ap.add_argument("--traffic", type=float, default=None,
+                    help="measured HBM bytes per split-GEMM launch (rocprofv3 FETCH/WRITE, calibrated)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the per-subgraph "
@@ -197,19 +199,26 @@ def main():
         roof = {"bound": "alu", "kernel": kname, "achieved": work / (avg_ms * 1e-3) / 1e12,
                 "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s", "traffic": None}
     else:
-        # the split GEMM: every launch runs 3 FP16 products of 2 P^3 flops per subgraph
+        # the split GEMM: three FP16 products per output tile (executed flops) and
+        # its algorithmic HBM bytes; at ~90 flop/B it sits below the MI355X ridge
+        # (2.5 PF / 8 TB/s = 312 flop/B), so the bound is HBM
         st = R["stats"]
         g = {k: v for k, v in R["kernels"].items() if k in ("foe_gemm", "ns_gemm")}
         ms_g = sum(v["ms_total"] for v in g.values())
         n_g = sum(v["launches"] for v in g.values())
-        kname = "gemm_split (foe_gemm + ns_gemm)"
+        kname = "k_gemm_split (split-FP16 MFMA GEMM)"
         avg_ms = ms_g / n_g
-        work = 3.0 * st["flops_per_launch"]
-        roof = {"bound": "mfma", "kernel": kname, "achieved": work / (avg_ms * 1e-3) / 1e12,
-                "peak": PEAK["fp16_mfma"] / 1e12, "unit": "TFLOP/s", "traffic": None,
+        flops = 3.0 * st["flops_per_launch"]
+        byts = st["bytes_per_launch"]
+        intensity = flops / byts
+        roof = {"bound": "hbm", "kernel": kname, "achieved": byts / (avg_ms * 1e-3) / 1e9,
+                "peak": PEAK["hbm"] / 1e9, "unit": "GB/s", "traffic": args.traffic,
+                "mfma_tflops": flops / (avg_ms * 1e-3) / 1e12, "mfma_peak_tflops": PEAK["fp16_mfma"] / 1e12,
+                "mfma_frac": flops / (avg_ms * 1e-3) / PEAK["fp16_mfma"],
                 "useful_tflops": st["flops_per_launch"] / (avg_ms * 1e-3) / 1e12,
-                "gemm_launches_per_step": n_g / args.steps, "passes": st["passes"],
-                "n_doublings": st["n_doublings"]}
+                "flop_per_byte": intensity, "algorithmic_bytes_per_launch": byts,
+                "mean_launch_ms": avg_ms, "gemm_launches_per_step": n_g / args.steps,
+                "passes": st["passes"], "n_doublings": st["n_doublings"]}
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {
         "metric": "subgraph DM solves/s + % MFMA peak at 60k orbitals, mixed vs FP64 at 1e-4 e",

@@ -231,15 +231,96 @@ int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes);
  * flops of one split GEMM launch counted once per product (2 P^2 per output
  * tile row of P, over the tiles computed: products of commuting symmetric
  * matrices compute the upper tiles only); each launch executes three FP16
- * products. */
+ * products.  bytes_per_launch: mean algorithmic HBM bytes of a launch (each
+ * operand, E matrix and output read or written once). */
 int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int64_t* gemm_launches,
-                    double* flops_per_launch);
+                    double* flops_per_launch, double* bytes_per_launch);
 
 /* Diagnostics: copy the FP32 matrix `which` (0 s, 1 h, 2 Y, 3 Z, 4 T, 5-6
  * Newton-Schulz ping-pong, 7 h_perp, 8 W = Z s, 9 X, 10 X^2, 11 A, 12 R, 13
  * inverse) of subgraph `sub` of the last GDM_MIXED_F16 solve into `out`
  * (device, P*P floats, P the padded size = 64 ceil(n/64)). */
 int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out);
+
+/* -------------------------------------------- SCC shell: Coulomb and mixing */
+
+/* Periodic Coulomb potential of point charges q (e) for the self-consistent-
+ * charge Hamiltonian (SI section D, the charge-dependent shift; the paper's
+ * all-to-all Coulomb sum of the Scalability section), in eV:
+ *   V_I = U[species_I] q_I + k_e [ sum_{J != I, r < rcut} q_J erfc(eta r)/r
+ *         + (4 pi / vol) sum_{k != 0, |k| <= 2 pi k_max / max(L)} exp(-k^2/4eta^2)/k^2
+ *           sum_J q_J cos(k . (R_J - R_I))  -  2 eta / sqrt(pi) q_I ],
+ * k_e = 14.399645 eV A, neutralising background (k = 0 dropped), minimum
+ * image in the real-space sum.  row_ptr/col: a neighbour CSR containing every
+ * pair with r < rcut (e.g. gdm_build_graph CUTOFF at rcut).  Requires
+ * 2 rcut < every box side, eta > 0, 1 <= k_max <= 64; hubbard_U HOST [2] eV
+ * (species 0, 1).  q, V: [n_atoms] FP64.  Accuracy is the caller's choice
+ * of (rcut, eta, k_max): erfc(eta rcut) and exp(-(pi k_max / (eta L))^2)
+ * bound the truncation.  Synchronises the stream. */
+int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr,
+                        const int32_t* col, double rcut, double eta, int32_t k_max,
+                        const double hubbard_U[2], const double* q, double* V);
+
+/* Linear charge mixing of the SCC iteration, the scaled-delta kernel
+ * K = -c I of the Shadow MD section: n <- n + mix (q0 - n), and the RMS of
+ * the residual q0 - n before the update (HOST *rms_out).  n_vec, q0: [n].
+ * Synchronises the stream. */
+int gdm_scc_mix(gdm_ctx* ctx, int32_t n, double* n_vec, const double* q0, double mix,
+                double* rms_out);
+
+/* ------------------------------------- learned starting charges (MLP) */
+
+/* Per-atom radial descriptors for the charge network, FP64 [n_atoms, 32]:
+ * feats[I, 16 s + k] = sum over neighbours J of species s with r < 5 A of
+ * exp(-(r - c_k)^2 / (2 * 0.3^2)) (cos(pi r / 5) + 1) / 2,
+ * c_k = 0.8 + 3.2 k / 15 (k = 0..15), minimum image.  row_ptr/col: a
+ * neighbour CSR containing every pair with r < 5 A (e.g. gdm_build_graph
+ * CUTOFF at 5.0). */
+int gdm_descriptors(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr,
+                    const int32_t* col, double* feats);
+
+/* Accumulate per-species feature statistics for standardisation:
+ * stats[(s*3 + m)*32 + f] += count (m = 0), sum (m = 1), sum of squares
+ * (m = 2) of feats[:, f] over the atoms of species s.  stats FP64 [192],
+ * zeroed by the caller before the first call.  gdm_feature_norm turns them
+ * into norm FP32 [2][64]: per species the 32 means, then the 32 population
+ * standard deviations (floored at 1e-6). */
+int gdm_feature_sums(gdm_ctx* ctx, int32_t n, const double* feats, const int32_t* species,
+                     double* stats);
+int gdm_feature_norm(gdm_ctx* ctx, const double* stats, float* norm);
+
+/* One network per central species (0, 1), each 32 -> 64 -> 64 -> 1 with
+ * SiLU; params FP32 [2][6337], per species W1 [64][32], b1 [64], W2
+ * [64][64], b2 [64], W3 [64], b3 [1] (row-major, output index first).
+ * x = (feats - mean) / std with norm from gdm_feature_norm.
+ * gdm_mlp_forward: y[i] = net_{species[i]}(x_i) for i < n; bf16 != 0 rounds
+ * weights, inputs and hidden activations to bfloat16 (inference) with FP32
+ * accumulation; bf16 = 0 is the FP32 training forward.  y FP32 [n]. */
+int gdm_mlp_forward(gdm_ctx* ctx, int32_t n, const int32_t* species, const double* feats,
+                    const float* params, const float* norm, int bf16, float* y);
+
+/* Neutral predicted charges q = y - mean(y) (FP64 [n]): the starting
+ * charges of the SCC iteration. */
+int gdm_mlp_charges(gdm_ctx* ctx, int32_t n, const float* y, double* q);
+
+/* Loss of the neutral prediction q = y - mean(y) against q_ref over the n
+ * atoms of one configuration: stats3[0] = mean(y), stats3[1] = mean(r),
+ * stats3[2] = mean(r^2) with r = q - q_ref (FP64, device). */
+int gdm_mlp_loss(gdm_ctx* ctx, int32_t n, const float* y, const double* q_ref, double* stats3);
+
+/* Gradient of mean(r^2) with respect to both networks' parameters, from the
+ * FP32 forward y and gdm_mlp_loss's stats3 (dL/dy_i = 2/n (r_i - mean r)).
+ * partial: FP32 workspace [ceil(n/64)][2][6337]; grad FP32 [2][6337]
+ * (overwritten; per-block partial sums added in a fixed order, so the
+ * result is deterministic). */
+int gdm_mlp_backward(gdm_ctx* ctx, int32_t n, const int32_t* species, const double* feats,
+                     const float* params, const float* norm, const float* y,
+                     const double* q_ref, const double* stats3, float* partial, float* grad);
+
+/* One Adam update of n parameters at step t >= 1 (bias-corrected first and
+ * second moments m, v, FP32, zero before the first step). */
+int gdm_adam_step(gdm_ctx* ctx, int32_t n, float* params, const float* grad, float* m, float* v,
+                  int32_t t, float lr, float b1, float b2, float eps);
 
 /* ------------------------------------------------------------- tracing */
 

@@ -77,8 +77,18 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     }
     sig["gdm_set_mixed_options"] = (C.c_int, [P, C.c_int, C.c_int, C.c_int])
     sig["gdm_mixed_stats"] = (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int64),
-                                        C.POINTER(C.c_double)])
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)])
     sig["gdm_debug_slot"] = (C.c_int, [P, C.c_int, C.c_int, P])
+    sig["gdm_ewald_potential"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double), P, P])
+    sig["gdm_scc_mix"] = (C.c_int, [P, I32, P, P, D, C.POINTER(C.c_double)])
+    sig["gdm_descriptors"] = (C.c_int, [P, C.POINTER(SystemT), P, P, P])
+    sig["gdm_feature_sums"] = (C.c_int, [P, I32, P, P, P])
+    sig["gdm_feature_norm"] = (C.c_int, [P, P, P])
+    sig["gdm_mlp_forward"] = (C.c_int, [P, I32, P, P, P, P, C.c_int, P])
+    sig["gdm_mlp_charges"] = (C.c_int, [P, I32, P, P])
+    sig["gdm_mlp_loss"] = (C.c_int, [P, I32, P, P, P])
+    sig["gdm_mlp_backward"] = (C.c_int, [P, I32, P, P, P, P, P, P, P, P, P])
+    sig["gdm_adam_step"] = (C.c_int, [P, I32, P, P, P, P, I32, C.c_float, C.c_float, C.c_float, C.c_float])
     sig["gdm_profile"] = (C.c_int, [P, C.c_int])
     sig["gdm_profile_query"] = (C.c_int, [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)])
     for name, (res, args) in sig.items():
@@ -349,10 +359,57 @@ class Context:
         return out.view(P, P)
 
     def mixed_stats(self) -> dict:
-        p, nd, g, f = C.c_int(0), C.c_int(0), C.c_int64(0), C.c_double(0.0)
-        self._check(self.lib.gdm_mixed_stats(self.h, C.byref(p), C.byref(nd), C.byref(g), C.byref(f)))
+        p, nd, g, f, b = C.c_int(0), C.c_int(0), C.c_int64(0), C.c_double(0.0), C.c_double(0.0)
+        self._check(self.lib.gdm_mixed_stats(self.h, C.byref(p), C.byref(nd), C.byref(g), C.byref(f), C.byref(b)))
         return {"passes": p.value, "n_doublings": nd.value, "gemm_launches": g.value,
-                "flops_per_launch": f.value}
+                "flops_per_launch": f.value, "bytes_per_launch": b.value}
+
+    # ------------------------------------------------------------ SCC shell
+    def ewald_potential(self, system: System, graph: Graph, rcut: float, eta: float, k_max: int, hubbard_U, q,
+                        out=None):
+        V = out if out is not None else torch.empty(system.n_atoms, dtype=torch.float64, device=self.dev)
+        U = (C.c_double * 2)(*[float(u) for u in hubbard_U])
+        self._check(self.lib.gdm_ewald_potential(self.h, C.byref(system.struct()), _ptr(graph.row_ptr),
+                                                 _ptr(graph.col), rcut, eta, int(k_max), U, _ptr(q), _ptr(V)))
+        return V
+
+    def scc_mix(self, n_vec, q0, mix: float) -> float:
+        rms = C.c_double(0.0)
+        self._check(self.lib.gdm_scc_mix(self.h, int(n_vec.numel()), _ptr(n_vec), _ptr(q0), mix, C.byref(rms)))
+        return rms.value
+
+    # ------------------------------------------------------ learned guess
+    def descriptors(self, system: System, graph: Graph, out=None):
+        F = out if out is not None else torch.empty(system.n_atoms, 32, dtype=torch.float64, device=self.dev)
+        self._check(self.lib.gdm_descriptors(self.h, C.byref(system.struct()), _ptr(graph.row_ptr), _ptr(graph.col),
+                                             _ptr(F)))
+        return F
+
+    def feature_sums(self, feats, species, stats):
+        self._check(self.lib.gdm_feature_sums(self.h, int(feats.shape[0]), _ptr(feats), _ptr(species), _ptr(stats)))
+
+    def feature_norm(self, stats, norm):
+        self._check(self.lib.gdm_feature_norm(self.h, _ptr(stats), _ptr(norm)))
+
+    def mlp_forward(self, species, feats, params, norm, bf16: bool, y):
+        self._check(self.lib.gdm_mlp_forward(self.h, int(species.numel()), _ptr(species), _ptr(feats), _ptr(params),
+                                             _ptr(norm), int(bf16), _ptr(y)))
+
+    def mlp_charges(self, y, q):
+        self._check(self.lib.gdm_mlp_charges(self.h, int(y.numel()), _ptr(y), _ptr(q)))
+
+    def mlp_loss(self, y, q_ref, stats3):
+        self._check(self.lib.gdm_mlp_loss(self.h, int(y.numel()), _ptr(y), _ptr(q_ref), _ptr(stats3)))
+
+    def mlp_backward(self, species, feats, params, norm, y, q_ref, stats3, partial, grad):
+        self._check(self.lib.gdm_mlp_backward(self.h, int(species.numel()), _ptr(species), _ptr(feats),
+                                              _ptr(params), _ptr(norm), _ptr(y), _ptr(q_ref), _ptr(stats3),
+                                              _ptr(partial), _ptr(grad)))
+
+    def adam_step(self, params, grad, m, v, t: int, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999,
+                  eps: float = 1e-8):
+        self._check(self.lib.gdm_adam_step(self.h, int(params.numel()), _ptr(params), _ptr(grad), _ptr(m), _ptr(v),
+                                           int(t), lr, b1, b2, eps))
 
     # --------------------------------------------------------------- tracing
     def profile(self, enable: bool):

@@ -73,6 +73,7 @@ struct gdm_ctx {
     int64_t mixed_tiles = 0, mixed_tiles_sym = 0, mixed_tiles_core = 0;
     double mixed_flops_full = 0, mixed_flops_sym = 0;  // one product per launch
     double mixed_flops = 0;      // summed over the launches of the last find_mu
+    double mixed_bytes = 0;      // algorithmic HBM bytes of those launches
     int64_t mixed_gemms = 0;
     int mixed_passes = 0;
     int mixed_nd = 0;
@@ -109,7 +110,7 @@ enum {
     BUF_G_FLAGS, BUF_G_COUNTS, BUF_G_SCAN, BUF_G_TOTAL, BUF_G_W,
     BUF_X_HI, BUF_X_LO, BUF_X_F, BUF_Y_HI, BUF_Y_LO, BUF_Y_F, BUF_T_HI, BUF_T_LO, BUF_T_F,
     BUF_Z_HI, BUF_Z_LO, BUF_Z_F, BUF_H_HI, BUF_H_LO, BUF_H_F, BUF_TR, BUF_GERSH, BUF_NDBL,
-    BUF_TILES, BUF_PASS,
+    BUF_TILES, BUF_PASS, BUF_EWALD, BUF_MIXPART,
     BUF_COUNT_
 };
 

@@ -1,0 +1,577 @@
+// Self-consistent-charge shell and the learned starting charges.
+//
+// SCC (SI section D; the scaled-delta kernel K = -c I of the Shadow MD
+// section is the linear mixer): V_I = U_I q_I + k_e sum_J q_J psi(R_J - R_I)
+// with the Ewald split psi = real-space erfc(eta r)/r over a cutoff CSR +
+// reciprocal sum over k != 0 + self term -2 eta / sqrt(pi); mixing
+// n <- n + c (q0[n] - n).
+//
+// Learned guess: per-atom radial descriptors (16 Gaussians x 2 neighbour
+// species), one 32-64-64-1 SiLU network per central species, prediction
+// shifted to zero net charge.  FP32 training kernels (forward, loss,
+// backward with a deterministic block-partial reduction, Adam) and a BF16
+// inference forward (BF16 weights, inputs and activations, FP32
+// accumulation).
+#include "gdm_internal.h"
+
+#include <cmath>
+
+namespace {
+
+constexpr int kNR = 16;            // Gaussians per species
+constexpr int kNF = 32;            // features
+constexpr int kH = 64;             // hidden width
+constexpr int kNP = kH * kNF + kH + kH * kH + kH + kH + 1;   // 6337 parameters per network
+constexpr int kOffB1 = kH * kNF;
+constexpr int kOffW2 = kOffB1 + kH;
+constexpr int kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH;
+constexpr int kOffB3 = kOffW3 + kH;
+
+__device__ __forceinline__ void min_image(const double* pos, int i, int j, double3 L, double3 iL, double* dx,
+                                          double* dy, double* dz) {
+    double x = pos[3 * j] - pos[3 * i], y = pos[3 * j + 1] - pos[3 * i + 1], z = pos[3 * j + 2] - pos[3 * i + 2];
+    x -= L.x * rint(x * iL.x);
+    y -= L.y * rint(y * iL.y);
+    z -= L.z * rint(z * iL.z);
+    *dx = x;
+    *dy = y;
+    *dz = z;
+}
+
+// ---------------------------------------------------------------- descriptors
+__global__ void k_descriptors(int n, const double* __restrict__ pos, const int32_t* __restrict__ species,
+                              double3 L, double3 iL, const int32_t* __restrict__ rp, const int32_t* __restrict__ cl,
+                              double rcut, double width, double c0, double dc, double* __restrict__ feats) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a0[kNR], a1[kNR];
+#pragma unroll
+    for (int q = 0; q < kNR; ++q) a0[q] = a1[q] = 0.0;
+    const double inv2w2 = 1.0 / (2.0 * width * width);
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = cl[k];
+        double dx, dy, dz;
+        min_image(pos, i, j, L, iL, &dx, &dy, &dz);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(r < rcut)) continue;
+        const double fc = 0.5 * (cos(M_PI * r / rcut) + 1.0);
+        const double w0 = species[j] == 0 ? fc : 0.0, w1 = fc - w0;
+#pragma unroll
+        for (int q = 0; q < kNR; ++q) {
+            const double t = r - (c0 + q * dc);
+            const double g = exp(-t * t * inv2w2);
+            a0[q] += g * w0;
+            a1[q] += g * w1;
+        }
+    }
+    double* out = feats + (int64_t)i * kNF;
+#pragma unroll
+    for (int q = 0; q < kNR; ++q) {
+        out[q] = a0[q];
+        out[kNR + q] = a1[q];
+    }
+}
+
+// Per-species feature sums for standardisation, stats[(s*3 + m)*32 + f]:
+// m = 0 count, 1 sum, 2 sum of squares.  Block = 32 threads (one feature
+// each); blocks stride over atoms and add their partials atomically.
+__global__ void k_feature_sums(int n, const double* __restrict__ feats, const int32_t* __restrict__ species,
+                               double* __restrict__ stats) {
+    const int f = threadIdx.x;
+    if (f >= kNF) return;
+    double c[2] = {0, 0}, s1[2] = {0, 0}, s2[2] = {0, 0};
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int sp = species[i] != 0;
+        const double x = feats[(int64_t)i * kNF + f];
+        c[sp] += 1.0;
+        s1[sp] += x;
+        s2[sp] += x * x;
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        atomicAdd(&stats[(sp * 3 + 0) * kNF + f], c[sp]);
+        atomicAdd(&stats[(sp * 3 + 1) * kNF + f], s1[sp]);
+        atomicAdd(&stats[(sp * 3 + 2) * kNF + f], s2[sp]);
+    }
+}
+
+// norm[s][0..31] = mean, norm[s][32..63] = max(std, 1e-6) (population std)
+__global__ void k_feature_norm(const double* __restrict__ stats, float* __restrict__ norm) {
+    const int t = threadIdx.x;
+    if (t >= 2 * kNF) return;
+    const int sp = t / kNF, f = t % kNF;
+    const double c = stats[(sp * 3 + 0) * kNF + f];
+    const double mean = c > 0 ? stats[(sp * 3 + 1) * kNF + f] / c : 0.0;
+    const double var = c > 0 ? stats[(sp * 3 + 2) * kNF + f] / c - mean * mean : 0.0;
+    norm[sp * 2 * kNF + f] = (float)mean;
+    norm[sp * 2 * kNF + kNF + f] = (float)fmax(sqrt(fmax(var, 0.0)), 1e-6);
+}
+
+// ---------------------------------------------------------------------- MLP
+__device__ __forceinline__ float silu(float x) { return x / (1.0f + expf(-x)); }
+__device__ __forceinline__ float dsilu(float x) {
+    const float s = 1.0f / (1.0f + expf(-x));
+    return s * (1.0f + x * (1.0f - s));
+}
+
+template <bool BF16>
+__device__ __forceinline__ float rnd(float x) {
+    if (!BF16) return x;
+    return (float)(__bf16)x;
+}
+
+// y_i = net_{species_i}(x_i) for every atom; both networks and both feature
+// normalisations staged in LDS (weights read as wave-wide broadcasts).
+template <bool BF16>
+__global__ void __launch_bounds__(256) k_mlp_forward(int n, const int32_t* __restrict__ species,
+                                                    const double* __restrict__ feats,
+                                                    const float* __restrict__ params, const float* __restrict__ norm,
+                                                    float* __restrict__ y) {
+    __shared__ float w[2 * kNP];
+    __shared__ float nm[4 * kNF];
+    for (int k = threadIdx.x; k < 2 * kNP; k += 256) w[k] = rnd<BF16>(params[k]);
+    for (int k = threadIdx.x; k < 4 * kNF; k += 256) nm[k] = norm[k];
+    __syncthreads();
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int sp = species[i] != 0;
+    const float* W = w + sp * kNP;
+    const float* N = nm + sp * 2 * kNF;
+    float x[kNF];
+    for (int f = 0; f < kNF; ++f) x[f] = rnd<BF16>(((float)feats[(int64_t)i * kNF + f] - N[f]) / N[kNF + f]);
+    float h1[kH];
+    for (int j = 0; j < kH; ++j) {
+        float acc = W[kOffB1 + j];
+        for (int f = 0; f < kNF; ++f) acc = fmaf(W[j * kNF + f], x[f], acc);
+        h1[j] = rnd<BF16>(silu(acc));
+    }
+    float out = W[kOffB3];
+    for (int j = 0; j < kH; ++j) {
+        float acc = W[kOffB2 + j];
+        for (int k = 0; k < kH; ++k) acc = fmaf(W[kOffW2 + j * kH + k], h1[k], acc);
+        out = fmaf(W[kOffW3 + j], rnd<BF16>(silu(acc)), out);
+    }
+    y[i] = out;
+}
+
+__device__ double block_sum_1024(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// residual statistics over all n atoms (one block of 1024):
+// out[0] = mean(y), out[1] = mean(r), out[2] = mean(r^2), r = y - mean(y) - q_ref
+__global__ void __launch_bounds__(1024) k_loss(int n, const float* __restrict__ y, const double* __restrict__ qref,
+                                              double* __restrict__ out) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s += (double)y[i];
+    const double ybar = block_sum_1024(s, red) / n;
+    double sr = 0.0, sr2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const double r = (double)y[i] - ybar - qref[i];
+        sr += r;
+        sr2 += r * r;
+    }
+    const double rbar = block_sum_1024(sr, red) / n;
+    const double l = block_sum_1024(sr2, red) / n;
+    if (threadIdx.x == 0) {
+        out[0] = ybar;
+        out[1] = rbar;
+        out[2] = l;
+    }
+}
+
+// neutral charges q = y - mean(y) in FP64 (one block of 1024)
+__global__ void __launch_bounds__(1024) k_center(int n, const float* __restrict__ y, double* __restrict__ q) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s += (double)y[i];
+    const double ybar = block_sum_1024(s, red) / n;
+    for (int i = threadIdx.x; i < n; i += 1024) q[i] = (double)y[i] - ybar;
+}
+
+// Backward over a block of 64 consecutive atoms: activations of each atom
+// with its own species' network in LDS, then each thread accumulates its
+// share of both networks' parameter gradients over the block (atoms of the
+// other species contribute nothing) into partial[block][2][kNP]; the blocks
+// are summed in a fixed order by k_reduce_partials.
+constexpr int kBA = 64;
+
+__global__ void __launch_bounds__(256) k_mlp_backward(int n, const int32_t* __restrict__ species,
+                                                     const double* __restrict__ feats,
+                                                     const float* __restrict__ params,
+                                                     const float* __restrict__ norm, const float* __restrict__ y,
+                                                     const double* __restrict__ qref, const double* __restrict__ st,
+                                                     double scale, float* __restrict__ partial) {
+    __shared__ float sx[kBA][kNF + 1];
+    __shared__ float sa1[kBA][kH + 1];    // silu(z1)
+    __shared__ float sz1[kBA][kH + 1];
+    __shared__ float sa2[kBA][kH + 1];    // silu(z2)
+    __shared__ float sd2[kBA][kH + 1];
+    __shared__ float sd1[kBA][kH + 1];
+    __shared__ float sg[kBA];
+    __shared__ int ssp[kBA];
+    const int t = threadIdx.x;
+    const int a0 = blockIdx.x * kBA;
+    const int na = min(kBA, n - a0);
+    for (int a = t; a < kBA; a += 256) {
+        float g = 0.f;
+        int sp = 0;
+        if (a < na) {
+            const int i = a0 + a;
+            sp = species[i] != 0;
+            const double r = (double)y[i] - st[0] - qref[i];
+            g = (float)(scale * (r - st[1]));
+        }
+        sg[a] = g;
+        ssp[a] = sp;
+    }
+    __syncthreads();
+    for (int e = t; e < kBA * kNF; e += 256) {
+        const int a = e / kNF, f = e % kNF;
+        const float* N = norm + ssp[a] * 2 * kNF;
+        sx[a][f] = a < na ? ((float)feats[(int64_t)(a0 + a) * kNF + f] - N[f]) / N[kNF + f] : 0.f;
+    }
+    __syncthreads();
+    for (int e = t; e < kBA * kH; e += 256) {           // z1 = W1 x + b1
+        const int a = e / kH, j = e % kH;
+        const float* W = params + ssp[a] * kNP;
+        float acc = W[kOffB1 + j];
+        for (int f = 0; f < kNF; ++f) acc = fmaf(W[j * kNF + f], sx[a][f], acc);
+        sz1[a][j] = acc;
+        sa1[a][j] = silu(acc);
+    }
+    __syncthreads();
+    for (int e = t; e < kBA * kH; e += 256) {           // z2, d2 = g W3 silu'(z2)
+        const int a = e / kH, j = e % kH;
+        const float* W = params + ssp[a] * kNP;
+        float acc = W[kOffB2 + j];
+        for (int k = 0; k < kH; ++k) acc = fmaf(W[kOffW2 + j * kH + k], sa1[a][k], acc);
+        sa2[a][j] = silu(acc);
+        sd2[a][j] = sg[a] * W[kOffW3 + j] * dsilu(acc);
+    }
+    __syncthreads();
+    for (int e = t; e < kBA * kH; e += 256) {           // d1 = (W2^T d2) silu'(z1)
+        const int a = e / kH, k = e % kH;
+        const float* W = params + ssp[a] * kNP;
+        float acc = 0.f;
+        for (int j = 0; j < kH; ++j) acc = fmaf(W[kOffW2 + j * kH + k], sd2[a][j], acc);
+        sd1[a][k] = acc * dsilu(sz1[a][k]);
+    }
+    __syncthreads();
+    float* gp = partial + (int64_t)blockIdx.x * 2 * kNP;
+    for (int pp = t; pp < 2 * kNP; pp += 256) {
+        const int sp = pp / kNP, p = pp % kNP;
+        float acc = 0.f;
+        if (p < kOffB1) {                       // W1[j][f]
+            const int j = p / kNF, f = p % kNF;
+            for (int a = 0; a < kBA; ++a)
+                if (ssp[a] == sp) acc = fmaf(sd1[a][j], sx[a][f], acc);
+        } else if (p < kOffW2) {                // b1
+            const int j = p - kOffB1;
+            for (int a = 0; a < kBA; ++a)
+                if (ssp[a] == sp) acc += sd1[a][j];
+        } else if (p < kOffB2) {                // W2[j][k]
+            const int q = p - kOffW2, j = q / kH, k = q % kH;
+            for (int a = 0; a < kBA; ++a)
+                if (ssp[a] == sp) acc = fmaf(sd2[a][j], sa1[a][k], acc);
+        } else if (p < kOffW3) {                // b2
+            const int j = p - kOffB2;
+            for (int a = 0; a < kBA; ++a)
+                if (ssp[a] == sp) acc += sd2[a][j];
+        } else if (p < kOffB3) {                // W3[j]
+            const int j = p - kOffW3;
+            for (int a = 0; a < kBA; ++a)
+                if (ssp[a] == sp) acc = fmaf(sg[a], sa2[a][j], acc);
+        } else {                                // b3
+            for (int a = 0; a < kBA; ++a)
+                if (ssp[a] == sp) acc += sg[a];
+        }
+        gp[pp] = acc;
+    }
+}
+
+__global__ void k_reduce_partials(int nblocks, const float* __restrict__ partial, float* __restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= 2 * kNP) return;
+    float acc = 0.f;
+    for (int b = 0; b < nblocks; ++b) acc += partial[(int64_t)b * 2 * kNP + p];
+    grad[p] = acc;
+}
+
+__global__ void k_adam(int n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------------ Ewald
+// real space (cutoff CSR, r < rc): sum_J q_J erfc(eta r)/r
+__global__ void k_ewald_real(int n, const double* __restrict__ pos, double3 L, double3 iL,
+                             const int32_t* __restrict__ rp, const int32_t* __restrict__ cl, double rc, double eta,
+                             const double* __restrict__ q, double* __restrict__ V) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = cl[k];
+        double dx, dy, dz;
+        min_image(pos, i, j, L, iL, &dx, &dy, &dz);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r < rc) acc += q[j] * erfc(eta * r) / r;
+    }
+    V[i] = acc;
+}
+
+// structure factors over the half space of k-vectors: C(k) = sum q cos(k.R), S(k) = sum q sin(k.R)
+__global__ void __launch_bounds__(256) k_ewald_sk(int n, const double* __restrict__ pos,
+                                                 const double* __restrict__ q, const double4* __restrict__ kv,
+                                                 double* __restrict__ CS) {
+    __shared__ double rc_[256], rs_[256];
+    const double4 k = kv[blockIdx.x];
+    double c = 0.0, s = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const double ph = k.x * pos[3 * j] + k.y * pos[3 * j + 1] + k.z * pos[3 * j + 2];
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        c += q[j] * cs;
+        s += q[j] * sn;
+    }
+    rc_[threadIdx.x] = c;
+    rs_[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            rc_[threadIdx.x] += rc_[threadIdx.x + o];
+            rs_[threadIdx.x] += rs_[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        CS[2 * blockIdx.x] = rc_[0];
+        CS[2 * blockIdx.x + 1] = rs_[0];
+    }
+}
+
+// V_I = U_I q_I + ke [ real_I + 2 sum_{k in half space} w(k) (cos(k.R_I) C + sin(k.R_I) S) - 2 eta/sqrt(pi) q_I ]
+// with w(k) = (4 pi / V) exp(-k^2 / 4 eta^2) / k^2 stored in kv[].w
+__global__ void k_ewald_recip(int n, int nk, const double* __restrict__ pos, const int32_t* __restrict__ species,
+                              const double* __restrict__ q, const double4* __restrict__ kv,
+                              const double* __restrict__ CS, double eta, double ke, double U0, double U1,
+                              double* __restrict__ V) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < nk; ++k) {
+        const double4 kk = kv[k];
+        const double ph = kk.x * pos[3 * i] + kk.y * pos[3 * i + 1] + kk.z * pos[3 * i + 2];
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        acc += kk.w * (cs * CS[2 * k] + sn * CS[2 * k + 1]);
+    }
+    const double self = -2.0 * eta / sqrt(M_PI) * q[i];
+    V[i] = (species[i] == 0 ? U0 : U1) * q[i] + ke * (V[i] + 2.0 * acc + self);
+}
+
+// n <- n + c (q0 - n); partial sums of (q0 - n)^2 per block
+__global__ void k_mix(int n, double* __restrict__ nv, const double* __restrict__ q0, double c,
+                      double* __restrict__ part) {
+    __shared__ double red[256];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double r2 = 0.0;
+    if (i < n) {
+        const double r = q0[i] - nv[i];
+        r2 = r * r;
+        nv[i] += c * r;
+    }
+    red[threadIdx.x] = r2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------- host
+
+static int check_ctx_sys(gdm_ctx* ctx, const gdm_system* sys) {
+    if (!sys || !sys->pos || !sys->species || sys->n_atoms <= 0)
+        return gdm_fail(ctx, GDM_E_ARG, "null system or no atoms");
+    return GDM_OK;
+}
+
+extern "C" int gdm_descriptors(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, const int32_t* col,
+                               double* feats) {
+    if (!ctx) return GDM_E_ARG;
+    int rc = check_ctx_sys(ctx, sys);
+    if (rc) return rc;
+    if (!row_ptr || !col || !feats) return gdm_fail(ctx, GDM_E_ARG, "gdm_descriptors: null argument");
+    const int n = sys->n_atoms;
+    GDM_TIMED(ctx, "descriptors");
+    hipLaunchKernelGGL(k_descriptors, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos, sys->species,
+                       make_double3(sys->box[0], sys->box[1], sys->box[2]),
+                       make_double3(sys->inv_box[0], sys->inv_box[1], sys->inv_box[2]), row_ptr, col, 5.0, 0.3, 0.8,
+                       3.2 / 15.0, feats);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_feature_sums(gdm_ctx* ctx, int32_t n, const double* feats, const int32_t* species,
+                                double* stats) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !feats || !species || !stats) return gdm_fail(ctx, GDM_E_ARG, "gdm_feature_sums: bad argument");
+    hipLaunchKernelGGL(k_feature_sums, dim3(256), dim3(kNF), 0, ctx->stream, n, feats, species, stats);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_feature_norm(gdm_ctx* ctx, const double* stats, float* norm) {
+    if (!ctx) return GDM_E_ARG;
+    if (!stats || !norm) return gdm_fail(ctx, GDM_E_ARG, "gdm_feature_norm: null argument");
+    hipLaunchKernelGGL(k_feature_norm, dim3(1), dim3(2 * kNF), 0, ctx->stream, stats, norm);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_mlp_forward(gdm_ctx* ctx, int32_t n, const int32_t* species, const double* feats,
+                               const float* params, const float* norm, int bf16, float* y) {
+    if (!ctx) return GDM_E_ARG;
+    if (n < 0 || (n > 0 && (!species || !feats || !params || !norm || !y)))
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_mlp_forward: bad argument");
+    if (n == 0) return GDM_OK;
+    GDM_TIMED(ctx, "mlp_forward");
+    if (bf16)
+        hipLaunchKernelGGL(k_mlp_forward<true>, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, species, feats,
+                           params, norm, y);
+    else
+        hipLaunchKernelGGL(k_mlp_forward<false>, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, species, feats,
+                           params, norm, y);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_mlp_loss(gdm_ctx* ctx, int32_t n, const float* y, const double* q_ref, double* stats3) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !y || !q_ref || !stats3) return gdm_fail(ctx, GDM_E_ARG, "gdm_mlp_loss: bad argument");
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, ctx->stream, n, y, q_ref, stats3);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_mlp_charges(gdm_ctx* ctx, int32_t n, const float* y, double* q) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !y || !q) return gdm_fail(ctx, GDM_E_ARG, "gdm_mlp_charges: bad argument");
+    hipLaunchKernelGGL(k_center, dim3(1), dim3(1024), 0, ctx->stream, n, y, q);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_mlp_backward(gdm_ctx* ctx, int32_t n, const int32_t* species, const double* feats,
+                                const float* params, const float* norm, const float* y, const double* q_ref,
+                                const double* stats3, float* partial, float* grad) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !species || !feats || !params || !norm || !y || !q_ref || !stats3 || !partial || !grad)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_mlp_backward: bad argument");
+    const int nb = (n + kBA - 1) / kBA;
+    GDM_TIMED(ctx, "mlp_backward");
+    hipLaunchKernelGGL(k_mlp_backward, dim3(nb), dim3(256), 0, ctx->stream, n, species, feats, params, norm, y, q_ref,
+                       stats3, 2.0 / n, partial);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((2 * kNP + 255) / 256), dim3(256), 0, ctx->stream, nb, partial, grad);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_adam_step(gdm_ctx* ctx, int32_t n, float* params, const float* grad, float* m, float* v,
+                             int32_t t, float lr, float b1, float b2, float eps) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || t <= 0 || !params || !grad || !m || !v) return gdm_fail(ctx, GDM_E_ARG, "gdm_adam_step: bad argument");
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, params, grad, m, v, lr, b1, b2,
+                       eps, c1, c2);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, const int32_t* col,
+                                   double rcut, double eta, int32_t k_max, const double hubbard_U[2],
+                                   const double* q, double* V) {
+    if (!ctx) return GDM_E_ARG;
+    int rc = check_ctx_sys(ctx, sys);
+    if (rc) return rc;
+    if (!row_ptr || !col || !q || !V || !hubbard_U || !(rcut > 0) || !(eta > 0) || k_max < 1 || k_max > 64)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_potential: bad argument");
+    for (int a = 0; a < 3; ++a)
+        if (sys->box[a] <= 2.0 * rcut) return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_potential: box must exceed 2 rcut");
+    // half space of k = 2 pi (a/Lx, b/Ly, c/Lz): (a > 0) or (a = 0, b > 0) or (a = b = 0, c > 0)
+    const double V3 = sys->box[0] * sys->box[1] * sys->box[2];
+    const double kc2 = std::pow(2.0 * M_PI * k_max / std::max(sys->box[0], std::max(sys->box[1], sys->box[2])), 2);
+    std::vector<double4> kv;
+    for (int a = 0; a <= k_max; ++a)
+        for (int b = -k_max; b <= k_max; ++b)
+            for (int c = -k_max; c <= k_max; ++c) {
+                if (a == 0 && (b < 0 || (b == 0 && c <= 0))) continue;
+                const double kx = 2 * M_PI * a / sys->box[0], ky = 2 * M_PI * b / sys->box[1],
+                             kz = 2 * M_PI * c / sys->box[2];
+                const double k2 = kx * kx + ky * ky + kz * kz;
+                if (k2 > kc2) continue;
+                const double w = 4.0 * M_PI / V3 * std::exp(-k2 / (4.0 * eta * eta)) / k2;
+                kv.push_back(make_double4(kx, ky, kz, w));
+            }
+    const int nk = (int)kv.size();
+    bool ok = true;
+    double4* dkv = (double4*)gdm_buf(ctx, BUF_EWALD, sizeof(double4) * nk + sizeof(double) * 2 * nk, &ok);
+    if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_ewald_potential: workspace allocation failed");
+    double* CS = (double*)(dkv + nk);
+    GDM_HIP(ctx, hipMemcpyAsync(dkv, kv.data(), sizeof(double4) * nk, hipMemcpyHostToDevice, ctx->stream));
+    const int n = sys->n_atoms;
+    const double3 L = make_double3(sys->box[0], sys->box[1], sys->box[2]);
+    const double3 iL = make_double3(sys->inv_box[0], sys->inv_box[1], sys->inv_box[2]);
+    GDM_TIMED(ctx, "ewald");
+    hipLaunchKernelGGL(k_ewald_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos, L, iL, row_ptr,
+                       col, rcut, eta, q, V);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, q, dkv, CS);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_recip, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nk, sys->pos,
+                       sys->species, q, dkv, CS, eta, 14.399645, hubbard_U[0], hubbard_U[1], V);
+    GDM_LAUNCH_CHECK(ctx);
+    // keep the staging vector alive until the copy has been consumed
+    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GDM_OK;
+}
+
+extern "C" int gdm_scc_mix(gdm_ctx* ctx, int32_t n, double* n_vec, const double* q0, double mix, double* rms_out) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !n_vec || !q0 || !rms_out) return gdm_fail(ctx, GDM_E_ARG, "gdm_scc_mix: bad argument");
+    const int nb = (n + 255) / 256;
+    bool ok = true;
+    double* part = (double*)gdm_buf(ctx, BUF_MIXPART, sizeof(double) * nb, &ok);
+    if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_scc_mix: workspace allocation failed");
+    hipLaunchKernelGGL(k_mix, dim3(nb), dim3(256), 0, ctx->stream, n, n_vec, q0, mix, part);
+    GDM_LAUNCH_CHECK(ctx);
+    std::vector<double> h(nb);
+    GDM_HIP(ctx, hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double s = 0.0;
+    for (double v : h) s += v;
+    *rms_out = std::sqrt(s / n);
+    return GDM_OK;
+}

@@ -33,6 +33,7 @@ constexpr int kTile = 64;       // output tile edge per workgroup
 constexpr int kK = 32;          // k-step (one MFMA k)
 constexpr int kLdsRow = kK + 8; // padded LDS row (halves)
 constexpr int kGemmThreads = 256;
+constexpr int kXcds = 8;        // workgroup b is dispatched to XCD b mod 8
 constexpr float kLoScale = 2048.0f;            // 2^11
 constexpr float kLoInv = 1.0f / 2048.0f;
 
@@ -105,6 +106,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
     _Float16* sBl = sBh + kTile * kLdsRow;
     float* sC = (float*)lds;                    // reused after the k loop: [64][65]
     const int4 tl = tiles[blockIdx.x];
+    if (tl.x < 0) return;
     const SubDesc d = desc[tl.x];
     const int P = d.ld;
     const int64_t base = d.off2;
@@ -214,6 +216,7 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
     __shared__ double sA[16][64 + 1];   // sA[k][m]
     __shared__ double sB[16][64 + 1];   // sB[k][n]
     const int4 tl = tiles[blockIdx.x];
+    if (tl.x < 0) return;
     const SubDesc d = desc[tl.x];
     const int P = d.ld;
     const int64_t base = d.off2;
@@ -358,21 +361,24 @@ __device__ __forceinline__ double block_reduce_sum(double v, double* red) {
 }
 
 // From the gathered FP64 h, s (leading dimension P): the Gershgorin upper
-// bound c of s, then S = s, H = h, Y0 = s / c, Z0 = I (padding: identity for
-// S, Y, Z and zero for H).
+// bound c of s, then H = h, Y0 = s / c, Z0 = I as split operands (padding:
+// identity for Y, Z and zero for H; the FP64 tiles get h = 0, s = I there).
+// Z also gets its FP32 copy when s = I, since Newton-Schulz is skipped then.
 __global__ void __launch_bounds__(kEw) k_prep(const SubDesc* __restrict__ desc, double* __restrict__ h64,
-                                             double* __restrict__ s64, SplitMat S, SplitMat H, SplitMat Y,
-                                             SplitMat Z, double* __restrict__ scale, int orthogonal) {
+                                             double* __restrict__ s64, SplitMat H, SplitMat Y, SplitMat Z,
+                                             double* __restrict__ scale, int orthogonal) {
     __shared__ double red[kEw / 64];
     const SubDesc d = desc[blockIdx.x];
     const int n = d.n, P = d.ld;
     const int64_t base = d.off2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double rmax = 0.0;
     if (!orthogonal)
-        for (int i = threadIdx.x; i < n; i += kEw) {
+        for (int i = wave; i < n; i += kEw / 64) {
             const double* row = s64 + base + (int64_t)i * P;
             double acc = 0.0;
-            for (int j = 0; j < n; ++j) acc += fabs(row[j]);
+            for (int j = lane; j < n; j += 64) acc += fabs(row[j]);
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
             rmax = fmax(rmax, acc);
         }
     const double c = orthogonal ? 1.0 : block_reduce_max(rmax, red);
@@ -382,13 +388,11 @@ __global__ void __launch_bounds__(kEw) k_prep(const SubDesc* __restrict__ desc, 
         const int i = (int)(e / P), j = (int)(e - (int64_t)i * P);
         const int64_t idx = base + e;
         const bool in = i < n && j < n;
-        float sv = in ? (orthogonal ? (i == j ? 1.f : 0.f) : (float)s64[idx]) : (i == j ? 1.f : 0.f);
-        float hv = in ? (float)h64[idx] : 0.f;
-        store_split(S, idx, sv);
-        store_split(H, idx, hv);
+        const float sv = in ? (orthogonal ? (i == j ? 1.f : 0.f) : (float)s64[idx]) : (i == j ? 1.f : 0.f);
+        store_split(H, idx, in ? (float)h64[idx] : 0.f);
         store_split(Y, idx, in ? sv * ic : (i == j ? 1.f : 0.f));
         store_split(Z, idx, i == j ? 1.f : 0.f);
-        if (!in) {     // padding of the FP64 tiles: h = 0, s = I
+        if (!in) {
             h64[idx] = 0.0;
             s64[idx] = i == j ? 1.0 : 0.0;
         }
@@ -409,29 +413,25 @@ __global__ void __launch_bounds__(kEw) k_scale_z(const SubDesc* __restrict__ des
     }
 }
 
-// H <- (H + H^T)/2 on the n x n block; Gershgorin bounds in FP64 -> bounds[2s], bounds[2s+1]
+// Gershgorin bounds of h_perp in FP64 -> bounds[2s], bounds[2s+1] (h_perp
+// comes out of the symmetric-mode product exactly symmetric); one wave per row.
 __global__ void __launch_bounds__(kEw) k_sym_bounds(const SubDesc* __restrict__ desc, SplitMat H,
                                                    double* __restrict__ bounds) {
     __shared__ double red[kEw / 64];
     const SubDesc d = desc[blockIdx.x];
     const int n = d.n, P = d.ld;
     const int64_t base = d.off2;
-    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kEw) {
-        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-        if (j <= i) continue;
-        const float v = 0.5f * (H.f[base + (int64_t)i * P + j] + H.f[base + (int64_t)j * P + i]);
-        store_split(H, base + (int64_t)i * P + j, v);
-        store_split(H, base + (int64_t)j * P + i, v);
-    }
-    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double lo = INFINITY, hi = -INFINITY;
-    for (int i = threadIdx.x; i < n; i += kEw) {
+    for (int i = wave; i < n; i += kEw / 64) {
         const float* row = H.f + base + (int64_t)i * P;
         double r = 0.0;
-        for (int j = 0; j < n; ++j)
+        for (int j = lane; j < n; j += 64)
             if (j != i) r += fabs((double)row[j]);
-        lo = fmin(lo, (double)row[i] - r);
-        hi = fmax(hi, (double)row[i] + r);
+        for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+        const double dii = (double)row[i];
+        lo = fmin(lo, dii - r);
+        hi = fmax(hi, dii + r);
     }
     lo = block_reduce_min(lo, red);
     hi = block_reduce_max(hi, red);
@@ -496,30 +496,43 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
     std::vector<int> order(P.n_sub);
     for (int s = 0; s < P.n_sub; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P.n[a] > P.n[b]; });
-    std::vector<int4> tiles, utiles;
-    double ffull = 0.0, fsym = 0.0;
-    for (int s : order) {
-        const int nt = P.desc[s].ld / kTile;
-        const double pt = 2.0 * kTile * kTile * (double)P.desc[s].ld;   // flops of one output tile
-        for (int i = 0; i < nt; ++i)
-            for (int j = 0; j < nt; ++j) {
-                tiles.push_back(make_int4(s, i, j, 0));
-                ffull += pt;
-                if (i <= j) {
-                    utiles.push_back(make_int4(s, i, j, 0));
-                    fsym += pt;
+    // XCD-aware tile lists: workgroup b runs on XCD b mod 8, so each subgraph is
+    // assigned to one of 8 queues (largest first, to the least loaded queue) and
+    // position 8k + x of a list holds the k-th tile of queue x.  All tiles of a
+    // subgraph then share one XCD's L2 and reuse its panels; queues are padded
+    // with empty entries (x = -1) that exit at once.
+    auto build = [&](int mode, double* flops) {
+        std::vector<std::vector<int4>> q(kXcds);
+        std::vector<double> load(kXcds, 0.0);
+        *flops = 0.0;
+        for (int s : order) {
+            const int nt = P.desc[s].ld / kTile;
+            const int nr = mode == 2 ? (P.desc[s].nc + kTile - 1) / kTile : nt;
+            const double pt = 2.0 * kTile * kTile * (double)P.desc[s].ld;
+            int x = 0;
+            for (int k = 1; k < kXcds; ++k)
+                if (load[k] < load[x]) x = k;
+            for (int i = 0; i < nr; ++i)
+                for (int j = 0; j < nt; ++j) {
+                    if (mode == 1 && i > j) continue;
+                    q[x].push_back(make_int4(s, i, j, 0));
+                    load[x] += pt;
+                    *flops += pt;
                 }
-            }
-    }
+        }
+        size_t len = 0;
+        for (auto& v : q) len = std::max(len, v.size());
+        std::vector<int4> out(len * kXcds, make_int4(-1, 0, 0, 0));
+        for (int x = 0; x < kXcds; ++x)
+            for (size_t k = 0; k < q[x].size(); ++k) out[k * kXcds + x] = q[x][k];
+        return out;
+    };
+    double ffull, fsym, fcore;
+    std::vector<int4> tiles = build(0, &ffull);
+    std::vector<int4> utiles = build(1, &fsym);
+    std::vector<int4> ctiles = build(2, &fcore);
     const size_t nfull = tiles.size();
     tiles.insert(tiles.end(), utiles.begin(), utiles.end());
-    std::vector<int4> ctiles;      // core-row tiles for the skinny FP64 products
-    for (int s : order) {
-        const int nt = P.desc[s].ld / kTile;
-        const int nr = (P.desc[s].nc + kTile - 1) / kTile;
-        for (int i = 0; i < nr; ++i)
-            for (int j = 0; j < nt; ++j) ctiles.push_back(make_int4(s, i, j, 0));
-    }
     tiles.insert(tiles.end(), ctiles.begin(), ctiles.end());
     bool ok = true;
     int4* dt = (int4*)gdm_buf(ctx, BUF_TILES, sizeof(int4) * tiles.size(), &ok);
@@ -559,6 +572,14 @@ static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, 
     GDM_LAUNCH_CHECK(ctx);
     ctx->mixed_gemms += 1;
     ctx->mixed_flops += sym ? ctx->mixed_flops_sym : ctx->mixed_flops_full;
+    // algorithmic HBM bytes: each operand and E read once, each output written once
+    double per = 8.0;                                   // A and B as FP16 hi + lo
+    if (E.f) per += 4.0; else if (E.hi) per += 4.0;
+    for (const SplitMat* o : {&O1, &O2}) {
+        if (o->f) per += 4.0;
+        if (o->hi) per += 4.0;
+    }
+    ctx->mixed_bytes += per * (double)ctx->plan.tot2;
     return GDM_OK;
 }
 
@@ -678,11 +699,12 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
     double* bounds = (double*)ctx->b[BUF_GERSH].p;
     ctx->mixed_gemms = 0;
     ctx->mixed_flops = 0.0;
+    ctx->mixed_bytes = 0.0;
     GDM_TRY(gdm_launch_gather(ctx, sys, sg, row_ptr, col, nnz, H, S, h64, s64, orth));
     {
         GDM_TIMED(ctx, "mixed_misc");
-        hipLaunchKernelGGL(k_prep, dim3(P.n_sub), dim3(kEw), 0, ctx->stream, desc, h64, s64, slot(ctx, SL_S),
-                           slot(ctx, SL_H), slot(ctx, SL_Y), slot(ctx, SL_Z), scale, orth);
+        hipLaunchKernelGGL(k_prep, dim3(P.n_sub), dim3(kEw), 0, ctx->stream, desc, h64, s64, hl(slot(ctx, SL_H)),
+                           hl(slot(ctx, SL_Y)), orth ? slot(ctx, SL_Z) : hl(slot(ctx, SL_Z)), scale, orth);
     }
     GDM_LAUNCH_CHECK(ctx);
     // coupled Newton-Schulz: Z -> (s/c)^-1/2
@@ -825,12 +847,13 @@ extern "C" int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max
 }
 
 extern "C" int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int64_t* gemm_launches,
-                               double* flops_per_launch) {
+                               double* flops_per_launch, double* bytes_per_launch) {
     if (!ctx) return GDM_E_ARG;
     if (passes) *passes = ctx->mixed_passes;
     if (n_doublings) *n_doublings = ctx->mixed_nd;
     if (gemm_launches) *gemm_launches = ctx->mixed_gemms;
     if (flops_per_launch) *flops_per_launch = ctx->mixed_gemms ? ctx->mixed_flops / (double)ctx->mixed_gemms : 0.0;
+    if (bytes_per_launch) *bytes_per_launch = ctx->mixed_gemms ? ctx->mixed_bytes / (double)ctx->mixed_gemms : 0.0;
     return GDM_OK;
 }
 

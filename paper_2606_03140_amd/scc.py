@@ -1,0 +1,80 @@
+"""Self-consistent-charge loop over the libgdm kernels.
+
+The charge vector n of SI section D is iterated to self-consistency: the
+Coulomb potential V = gamma n (periodic Ewald sum plus on-site Hubbard U,
+gdm_ewald_potential) shifts H by 1/2 S_ab (V_I + V_J) (gdm_build_hs), one
+density solve at a global mu gives the Mulliken charges q0[n], and the
+scaled-delta update K = -c I of the Shadow MD section (linear mixing,
+gdm_scc_mix) moves n <- n + c (q0[n] - n) until the RMS residual is below
+the tolerance.  Only orchestration lives here.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+from ._lib import FP64_EIG, Context, Graph, System, TBParams
+from .pipeline import Partition, solve
+
+HARTREE_EV = 27.211386
+HUBBARD_U = (0.5 * HARTREE_EV, 0.4 * HARTREE_EV)      # O-like, H-like (eV)
+
+
+@dataclass
+class EwaldSetup:
+    rcut: float
+    eta: float
+    k_max: int
+    graph: Graph
+
+
+def ewald_setup(ctx: Context, system: System, rcut_max: float = 12.0, tol: float = 1e-10) -> EwaldSetup:
+    """Split parameters for a truncation error of about `tol` in both sums:
+    erfc(eta rcut) ~ tol and exp(-k_c^2 / 4 eta^2) ~ tol, rcut below half the
+    shortest box edge, plus the real-space neighbour CSR at rcut."""
+    L = system.box
+    rcut = min(rcut_max, 0.499 * min(L))
+    a = math.sqrt(-math.log(tol))
+    eta = a / rcut
+    k_c = 2.0 * eta * a
+    k_max = int(math.ceil(k_c * max(L) / (2.0 * math.pi)))
+    graph = ctx.build_graph_cutoff(system, rcut)
+    return EwaldSetup(rcut=rcut, eta=eta, k_max=k_max, graph=graph)
+
+
+@dataclass
+class SCCResult:
+    q: torch.Tensor
+    iterations: int
+    converged: bool
+    history: list = field(default_factory=list)
+    mu: float = 0.0
+
+
+def scc_loop(ctx: Context, system: System, tb: TBParams, part: Partition, kT: float, precision: int = FP64_EIG,
+             q_start: torch.Tensor | None = None, mix: float = 0.3, tol: float = 1e-5, max_iter: int = 200,
+             ewald: EwaldSetup | None = None, hubbard_U=HUBBARD_U, mu_guess: float = 0.0,
+             plan: bool = True) -> SCCResult:
+    """Returns q0[n] at the first n whose residual RMS(q0[n] - n) < tol."""
+    ew = ewald if ewald is not None else ewald_setup(ctx, system)
+    n = torch.zeros(system.n_atoms, dtype=torch.float64, device=ctx.dev) if q_start is None \
+        else q_start.to(device=ctx.dev, dtype=torch.float64).clone()
+    V = torch.empty_like(n)
+    hist = []
+    mu = mu_guess
+    sol = None
+    for it in range(1, max_iter + 1):
+        ctx.ewald_potential(system, ew.graph, ew.rcut, ew.eta, ew.k_max, hubbard_U, n, out=V)
+        H, S = ctx.build_hs(system, tb, part.nbr, V)
+        sol = solve(ctx, system, part, H, S, kT, precision, mu_guess=mu, plan=plan and it == 1)
+        mu = sol.mu
+        rms = ctx.scc_mix(n, sol.q, mix)
+        hist.append(rms)
+        if rms < tol:
+            return SCCResult(q=sol.q, iterations=it, converged=True, history=hist, mu=mu)
+    return SCCResult(q=n, iterations=max_iter, converged=False, history=hist, mu=mu)
+
+
+__all__ = ["HUBBARD_U", "EwaldSetup", "ewald_setup", "SCCResult", "scc_loop"]
