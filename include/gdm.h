@@ -244,22 +244,27 @@ int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out);
 
 /* -------------------------------------------- SCC shell: Coulomb and mixing */
 
-/* Periodic Coulomb potential of point charges q (e) for the self-consistent-
- * charge Hamiltonian (SI section D, the charge-dependent shift; the paper's
- * all-to-all Coulomb sum of the Scalability section), in eV:
- *   V_I = U[species_I] q_I + k_e [ sum_{J != I, r < rcut} q_J erfc(eta r)/r
+/* Periodic Coulomb potential of the net Mulliken charges q (e) for the
+ * self-consistent-charge Hamiltonian (SI section D: 1/R at large separation,
+ * screened where the charge densities overlap, Hubbard U on site; the
+ * paper's all-to-all Coulomb sum of the Scalability section), in eV:
+ *   V_I = U[species_I] q_I + k_e [ sum_{J != I, r < rcut} q_J (erfc(eta r)/r - S_IJ(r))
  *         + (4 pi / vol) sum_{k != 0, |k| <= 2 pi k_max / max(L)} exp(-k^2/4eta^2)/k^2
  *           sum_J q_J cos(k . (R_J - R_I))  -  2 eta / sqrt(pi) q_I ],
  * k_e = 14.399645 eV A, neutralising background (k = 0 dropped), minimum
- * image in the real-space sum.  row_ptr/col: a neighbour CSR containing every
- * pair with r < rcut (e.g. gdm_build_graph CUTOFF at rcut).  Requires
- * 2 rcut < every box side, eta > 0, 1 <= k_max <= 64; hubbard_U HOST [2] eV
- * (species 0, 1).  q, V: [n_atoms] FP64.  Accuracy is the caller's choice
- * of (rcut, eta, k_max): erfc(eta rcut) and exp(-(pi k_max / (eta L))^2)
- * bound the truncation.  Synchronises the stream. */
+ * image in the real-space sum.  S_IJ(r): the short-range part of the
+ * interaction of two exponential charge densities tau^3/(8 pi) exp(-tau r)
+ * with tau = tau[species] (HOST [2], 1/A; 16/5 U in atomic units), so that
+ * 1/r - S -> U as r -> 0; tau NULL gives bare point charges.
+ * row_ptr/col: a neighbour CSR containing every pair with r < rcut (e.g.
+ * gdm_build_graph CUTOFF at rcut).  Requires 2 rcut < every box side,
+ * eta > 0, 1 <= k_max <= 64; hubbard_U HOST [2] eV.  q, V: [n_atoms] FP64.
+ * Accuracy is the caller's choice of (rcut, eta, k_max): erfc(eta rcut),
+ * exp(-(pi k_max / (eta L))^2) and S(rcut) bound the truncation.
+ * Synchronises the stream. */
 int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr,
                         const int32_t* col, double rcut, double eta, int32_t k_max,
-                        const double hubbard_U[2], const double* q, double* V);
+                        const double hubbard_U[2], const double* tau, const double* q, double* V);
 
 /* Linear charge mixing of the SCC iteration, the scaled-delta kernel
  * K = -c I of the Shadow MD section: n <- n + mix (q0 - n), and the RMS of
@@ -267,6 +272,19 @@ int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_
  * Synchronises the stream. */
 int gdm_scc_mix(gdm_ctx* ctx, int32_t n, double* n_vec, const double* q0, double mix,
                 double* rms_out);
+
+/* Anderson-accelerated update of the same fixed-point iteration (memory
+ * depth <= 8, mixing mix): with F = q0 - n stored as the k-th iterate
+ * (k = 0, 1, ... counts the calls of one SCC run) and the differences dF_j,
+ * dn_j of the last min(depth, k) consecutive iterates,
+ * gamma = argmin || F - sum_j gamma_j dF_j || (QR by modified Gram-Schmidt;
+ * columns that are numerically dependent are dropped) and
+ * n <- n + mix F - sum_j gamma_j (dn_j + mix dF_j).  depth 0 is linear
+ * mixing.  work: caller-owned FP64 [(3 depth + 2) n], kept between the calls
+ * of one run (the iterate history).  *rms_out (HOST): RMS of F.
+ * Synchronises the stream. */
+int gdm_scc_anderson(gdm_ctx* ctx, int32_t n, double* n_vec, const double* q0, double mix,
+                     int32_t depth, int32_t k, double* work, double* rms_out);
 
 /* ------------------------------------- learned starting charges (MLP) */
 

@@ -1,19 +1,28 @@
-"""Periodic point-charge Coulomb potential by Ewald summation (oracle).
+"""Periodic charge-charge interaction for the SCC Hamiltonian (oracle).
 
-The SCC-DFTB engine couples Mulliken charges through a Coulomb interaction
-that decays as 1/R, summed over the periodic system (SI section D; the paper
-uses a GPU Ewald solver for this all-to-all sum, Scalability section).  The
-stand-in drops the short-range screening and keeps the on-site Hubbard U:
+The SCC-DFTB engine couples net Mulliken charges through a Coulomb
+interaction that decays as 1/R at large separation and is screened at
+short range, where the interacting charge densities overlap, with the
+on-site value set by the Hubbard U (SI section D; the paper uses a GPU
+Ewald solver for the all-to-all sum, Scalability section).  Here:
 
   V_I = U_I q_I + k_e [ sum_J q_J psi(R_J - R_I) ]
+        - k_e sum_{J, images, (J, n) != (I, 0)} q_J S(tau_I, tau_J, |R_J - R_I + nL|)
   psi(r) = sum_n' erfc(eta |r + nL|)/|r + nL|
          + (4 pi / V) sum_{k != 0} exp(-k^2 / (4 eta^2)) / k^2 cos(k . r)
          - 2 eta / sqrt(pi) [r = 0],
   the n' sum skipping the J = I, n = 0 term, with k_e = 14.399645 eV A and
-  a neutralising background (k = 0 term dropped).
+  a neutralising background (k = 0 term dropped), the screening sum taken
+  over pairs closer than a cutoff (its tail is below 1e-12 eV beyond 12 A).
+  gamma = 1/R - S(R) is the
+  Coulomb energy of two normalised exponential (Slater 1s) charge densities
+  with exponents tau = 16/5 U (atomic units), the screening of SCC-DFTB:
+  gamma -> U as R -> 0 and S decays exponentially.
 
 Pins: the rock-salt Madelung constant 1.747565 and independence of the
-splitting parameter eta (tests/test_oracle_pins.py).
+splitting parameter eta; the closed form of S against direct numerical
+quadrature of the two-density Coulomb integral, and gamma(0) = U
+(tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 
@@ -22,7 +31,9 @@ import math
 import numpy as np
 from scipy.special import erfc
 
-from .model import COULOMB_EV_A
+from .model import COULOMB_EV_A, HARTREE_EV
+
+BOHR_A = 0.529177210903
 
 
 def ewald_psi_matrix(pos: np.ndarray, L: float, eta: float, n_real: int, k_max: int) -> np.ndarray:
@@ -57,10 +68,58 @@ def ewald_psi_matrix(pos: np.ndarray, L: float, eta: float, n_real: int, k_max: 
     return psi
 
 
+def slater_tau(U_ev) -> np.ndarray:
+    """Exponent of the Slater charge density of each species, 1/A, from the
+    Hubbard U in eV: tau = 16/5 U in atomic units."""
+    return 16.0 / 5.0 * (np.asarray(U_ev, dtype=np.float64) / HARTREE_EV) / BOHR_A
+
+
+def slater_short(ta: float, tb: float, R):
+    """S(R) with gamma(R) = 1/R - S(R) the Coulomb energy of two unit
+    exponential densities tau^3/(8 pi) exp(-tau r) at distance R > 0 (any
+    consistent length unit: S and 1/R in 1/length)."""
+    R = np.asarray(R, dtype=np.float64)
+    if abs(ta - tb) < 1e-6 * (ta + tb):
+        t = 0.5 * (ta + tb)
+        return np.exp(-t * R) * (1.0 / R + 11.0 * t / 16.0 + 3.0 * t * t * R / 16.0 + t ** 3 * R * R / 48.0)
+
+    def part(a, b):
+        d = a * a - b * b
+        return np.exp(-a * R) * (b ** 4 * a / (2.0 * d * d) - (b ** 6 - 3.0 * b ** 4 * a * a) / (d ** 3 * R))
+
+    return part(ta, tb) + part(tb, ta)
+
+
+def short_range_matrix(pos: np.ndarray, species: np.ndarray, L: float, tau: np.ndarray, n_real: int,
+                       short_cut: float = np.inf) -> np.ndarray:
+    """Dense [N, N] sum over images of S(tau_I, tau_J, |R_J - R_I + nL|) for
+    distances below short_cut, skipping J = I, n = 0."""
+    n = pos.shape[0]
+    d = pos[None, :, :] - pos[:, None, :]
+    out = np.zeros((n, n))
+    rng = range(-n_real, n_real + 1)
+    pair = [(si, sj, (species[:, None] == si) & (species[None, :] == sj)) for si in (0, 1) for sj in (0, 1)]
+    for a in rng:
+        for b in rng:
+            for c in rng:
+                r = np.linalg.norm(d + np.array([a, b, c], dtype=np.float64) * L, axis=2)
+                if a == 0 and b == 0 and c == 0:
+                    np.fill_diagonal(r, np.inf)
+                for si, sj, m in pair:
+                    mm = m & (r < short_cut)
+                    if mm.any():
+                        out[mm] += slater_short(tau[si], tau[sj], r[mm])
+    return out
+
+
 def coulomb_potential(pos: np.ndarray, species: np.ndarray, q: np.ndarray, L: float, U: np.ndarray,
-                      eta: float | None = None, n_real: int = 2, k_max: int = 8) -> np.ndarray:
+                      eta: float | None = None, n_real: int = 2, k_max: int = 8,
+                      screened: bool = True, short_cut: float = np.inf) -> np.ndarray:
+    """V [N] in eV; the screening term covers pairs closer than short_cut (A)."""
     eta = eta if eta is not None else 5.6 / L
     psi = ewald_psi_matrix(pos, L, eta, n_real, k_max)
+    if screened:
+        psi = psi - short_range_matrix(pos, species, L, slater_tau(U), n_real, short_cut)
     return U[species] * q + COULOMB_EV_A * (psi @ q)
 
 

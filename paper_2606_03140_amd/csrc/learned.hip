@@ -320,19 +320,40 @@ __global__ void k_adam(int n, float* __restrict__ p, const float* __restrict__ g
 }
 
 // ------------------------------------------------------------------ Ewald
-// real space (cutoff CSR, r < rc): sum_J q_J erfc(eta r)/r
-__global__ void k_ewald_real(int n, const double* __restrict__ pos, double3 L, double3 iL,
-                             const int32_t* __restrict__ rp, const int32_t* __restrict__ cl, double rc, double eta,
-                             const double* __restrict__ q, double* __restrict__ V) {
+// S(R) of the screened interaction gamma = 1/R - S: Coulomb energy of two
+// unit exponential densities tau^3/(8 pi) exp(-tau r) (Slater 1s), closed
+// form in any length unit (tau in 1/length, S in 1/length).
+__device__ double slater_short(double ta, double tb, double R) {
+    if (fabs(ta - tb) < 1e-6 * (ta + tb)) {
+        const double t = 0.5 * (ta + tb);
+        return exp(-t * R) * (1.0 / R + 11.0 * t / 16.0 + 3.0 * t * t * R / 16.0 + t * t * t * R * R / 48.0);
+    }
+    const double a2 = ta * ta, b2 = tb * tb;
+    const double dab = a2 - b2, dba = -dab;
+    const double pa = exp(-ta * R) * (b2 * b2 * ta / (2.0 * dab * dab) - (b2 * b2 * b2 - 3.0 * b2 * b2 * a2) / (dab * dab * dab * R));
+    const double pb = exp(-tb * R) * (a2 * a2 * tb / (2.0 * dba * dba) - (a2 * a2 * a2 - 3.0 * a2 * a2 * b2) / (dba * dba * dba * R));
+    return pa + pb;
+}
+
+// real space over the cutoff CSR (r < rc): sum_J q_J (erfc(eta r)/r - S(tau_I, tau_J, r)),
+// the screening term only when screened != 0
+__global__ void k_ewald_real(int n, const double* __restrict__ pos, const int32_t* __restrict__ species, double3 L,
+                             double3 iL, const int32_t* __restrict__ rp, const int32_t* __restrict__ cl, double rc,
+                             double eta, int screened, double tau0, double tau1, const double* __restrict__ q,
+                             double* __restrict__ V) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const double ti = species[i] == 0 ? tau0 : tau1;
     double acc = 0.0;
     for (int k = rp[i]; k < rp[i + 1]; ++k) {
         const int j = cl[k];
         double dx, dy, dz;
         min_image(pos, i, j, L, iL, &dx, &dy, &dz);
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
-        if (r < rc) acc += q[j] * erfc(eta * r) / r;
+        if (!(r < rc)) continue;
+        double g = erfc(eta * r) / r;
+        if (screened) g -= slater_short(ti, species[j] == 0 ? tau0 : tau1, r);
+        acc += q[j] * g;
     }
     V[i] = acc;
 }
@@ -405,6 +426,113 @@ __global__ void k_mix(int n, double* __restrict__ nv, const double* __restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Anderson acceleration of the SCC fixed-point map (type II, memory m,
+// mixing c), one block of 1024 threads over all n entries:
+//   F = q0 - n; ring slot k % (depth+1) <- (n, F);
+//   dF_j, dn_j: differences of consecutive stored iterates (j < m = min(depth, k));
+//   gamma = argmin || F - dF gamma || by modified Gram-Schmidt QR of dF;
+//   n <- n + c F - sum_j gamma_j (dn_j + c dF_j).
+// work: [depth+1][n] iterates, [depth+1][n] residuals, [depth][n] Q columns.
+constexpr int kAT = 1024;
+constexpr int kMaxDepth = 8;
+
+__device__ double block_sum_kat(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < kAT / 64; ++w) r += red[w];
+    return r;
+}
+
+__global__ void __launch_bounds__(kAT) k_anderson(int n, double* __restrict__ nv, const double* __restrict__ q0,
+                                                 double c, int depth, int k, double* __restrict__ work,
+                                                 double* __restrict__ out) {
+    __shared__ double red[kAT / 64];
+    __shared__ double R[kMaxDepth][kMaxDepth];
+    __shared__ double gam[kMaxDepth];
+    __shared__ int keep[kMaxDepth];
+    const int slots = depth + 1;
+    double* Nh = work;
+    double* Fh = work + (int64_t)slots * n;
+    double* Qc = work + (int64_t)2 * slots * n;
+    const int cur = k % slots;
+    double s2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += kAT) {
+        const double f = q0[i] - nv[i];
+        Nh[(int64_t)cur * n + i] = nv[i];
+        Fh[(int64_t)cur * n + i] = f;
+        s2 += f * f;
+    }
+    const double fnorm2 = block_sum_kat(s2, red);
+    if (threadIdx.x == 0) out[0] = sqrt(fnorm2 / n);
+    const int m = min(depth, k);
+    // QR of the residual differences, column by column
+    for (int j = 0; j < m; ++j) {
+        const int a = (k - m + j) % slots, b = (k - m + j + 1) % slots;
+        double* qj = Qc + (int64_t)j * n;
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += kAT) {
+            const double v = Fh[(int64_t)b * n + i] - Fh[(int64_t)a * n + i];
+            qj[i] = v;
+            s += v * v;
+        }
+        const double orig = sqrt(block_sum_kat(s, red));
+        for (int l = 0; l < j; ++l) {
+            const double* ql = Qc + (int64_t)l * n;
+            double d = 0.0;
+            for (int i = threadIdx.x; i < n; i += kAT) d += ql[i] * qj[i];
+            const double rl = keep[l] ? block_sum_kat(d, red) : 0.0;
+            if (threadIdx.x == 0) R[l][j] = rl;
+            for (int i = threadIdx.x; i < n; i += kAT) qj[i] -= rl * ql[i];
+        }
+        double t = 0.0;
+        for (int i = threadIdx.x; i < n; i += kAT) t += qj[i] * qj[i];
+        const double rjj = sqrt(block_sum_kat(t, red));
+        const bool ok = rjj > 1e-12 * orig && rjj > 0.0;
+        if (threadIdx.x == 0) {
+            R[j][j] = rjj;
+            keep[j] = ok;
+        }
+        const double inv = ok ? 1.0 / rjj : 0.0;
+        for (int i = threadIdx.x; i < n; i += kAT) qj[i] *= inv;
+        __syncthreads();
+    }
+    // rhs Q^T F_k, then back substitution R gamma = rhs over the kept columns
+    for (int j = 0; j < m; ++j) {
+        const double* qj = Qc + (int64_t)j * n;
+        double d = 0.0;
+        for (int i = threadIdx.x; i < n; i += kAT) d += qj[i] * Fh[(int64_t)cur * n + i];
+        const double rhs = block_sum_kat(d, red);
+        if (threadIdx.x == 0) gam[j] = rhs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = m - 1; j >= 0; --j) {
+            if (!keep[j]) {
+                gam[j] = 0.0;
+                continue;
+            }
+            double v = gam[j];
+            for (int l = j + 1; l < m; ++l) v -= R[j][l] * gam[l];
+            gam[j] = v / R[j][j];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kAT) {
+        const double f = Fh[(int64_t)cur * n + i];
+        double x = nv[i] + c * f;
+        for (int j = 0; j < m; ++j) {
+            const int a = (k - m + j) % slots, b = (k - m + j + 1) % slots;
+            const double dn = Nh[(int64_t)b * n + i] - Nh[(int64_t)a * n + i];
+            const double df = Fh[(int64_t)b * n + i] - Fh[(int64_t)a * n + i];
+            x -= gam[j] * (dn + c * df);
+        }
+        nv[i] = x;
+    }
 }
 
 }  // namespace
@@ -512,12 +640,13 @@ extern "C" int gdm_adam_step(gdm_ctx* ctx, int32_t n, float* params, const float
 
 extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, const int32_t* col,
                                    double rcut, double eta, int32_t k_max, const double hubbard_U[2],
-                                   const double* q, double* V) {
+                                   const double* tau, const double* q, double* V) {
     if (!ctx) return GDM_E_ARG;
     int rc = check_ctx_sys(ctx, sys);
     if (rc) return rc;
     if (!row_ptr || !col || !q || !V || !hubbard_U || !(rcut > 0) || !(eta > 0) || k_max < 1 || k_max > 64)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_potential: bad argument");
+    if (tau && !(tau[0] > 0 && tau[1] > 0)) return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_potential: tau must be positive");
     for (int a = 0; a < 3; ++a)
         if (sys->box[a] <= 2.0 * rcut) return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_potential: box must exceed 2 rcut");
     // half space of k = 2 pi (a/Lx, b/Ly, c/Lz): (a > 0) or (a = 0, b > 0) or (a = b = 0, c > 0)
@@ -545,8 +674,8 @@ extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const in
     const double3 L = make_double3(sys->box[0], sys->box[1], sys->box[2]);
     const double3 iL = make_double3(sys->inv_box[0], sys->inv_box[1], sys->inv_box[2]);
     GDM_TIMED(ctx, "ewald");
-    hipLaunchKernelGGL(k_ewald_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos, L, iL, row_ptr,
-                       col, rcut, eta, q, V);
+    hipLaunchKernelGGL(k_ewald_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos, sys->species, L,
+                       iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0, tau ? tau[1] : 0.0, q, V);
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, q, dkv, CS);
     GDM_LAUNCH_CHECK(ctx);
@@ -573,5 +702,20 @@ extern "C" int gdm_scc_mix(gdm_ctx* ctx, int32_t n, double* n_vec, const double*
     double s = 0.0;
     for (double v : h) s += v;
     *rms_out = std::sqrt(s / n);
+    return GDM_OK;
+}
+
+extern "C" int gdm_scc_anderson(gdm_ctx* ctx, int32_t n, double* n_vec, const double* q0, double mix, int32_t depth,
+                                int32_t k, double* work, double* rms_out) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !n_vec || !q0 || !work || !rms_out || depth < 0 || depth > kMaxDepth || k < 0)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_scc_anderson: bad argument");
+    bool ok = true;
+    double* out = (double*)gdm_buf(ctx, BUF_MIXPART, sizeof(double), &ok);
+    if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_scc_anderson: workspace allocation failed");
+    hipLaunchKernelGGL(k_anderson, dim3(1), dim3(kAT), 0, ctx->stream, n, n_vec, q0, mix, depth, k, work, out);
+    GDM_LAUNCH_CHECK(ctx);
+    GDM_HIP(ctx, hipMemcpyAsync(rms_out, out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return GDM_OK;
 }

@@ -11,7 +11,9 @@
   bias-corrected moments are g and g^2), and training a student network on
   a teacher of the same shape drives the loss down;
 * SCC: the returned charges are a fixed point of the charge map to the
-  tolerance, sum to zero, and do not depend on the start.
+  tolerance, sum to zero, and do not depend on the start; Anderson
+  acceleration reaches the closed-form fixed point of an affine map on
+  which linear mixing diverges, and with memory 0 it is linear mixing.
 """
 import math
 
@@ -162,17 +164,39 @@ def test_scc_fixed_point_independent_of_start():
     core, nco = og.grid_cores(box.pos, box.anchor, L, (2, 2, 1))
     subs = og.extract_subgraphs(rp, col, core, nco)
     q, it, hist = osc.scc(box.pos, box.species, L, m, subs)
-    assert it < 200 and hist[-1] < 1e-5
-    assert all(b < a for a, b in zip(hist[2:], hist[3:]))        # linear mixing contracts
+    assert it < 60 and hist[-1] < 1e-5
     assert abs(q.sum()) < 1e-9
-    # one more application of the charge map moves q by no more than the tolerance allows
+    # the screened interaction gives water-like polarity: O gains electrons, H loses them
+    assert np.all(q[box.species == 0] > 0.3) and np.all(q[box.species == 1] < -0.1)
+    # one more application of the charge map stays at the fixed point: q = q0[n] with
+    # RMS(q0[n] - n) < 1e-5 e, so q0[q] - q ~ J (q0[n] - n), J the (strong) charge response
     from oracle.ewald import coulomb_potential
     from oracle.solve import solve_system
     V = coulomb_potential(box.pos, box.species, q, L, np.asarray(m.hubbard_U))
     q1 = solve_system(box.pos, box.species, L, m, subs, V_atom=V).q
-    assert math.sqrt(np.mean((q1 - q) ** 2)) < 1e-5
+    assert math.sqrt(np.mean((q1 - q) ** 2)) < 1e-4
     # a different start reaches the same charges
     start = q + 0.01 * np.random.default_rng(0).standard_normal(len(q))
     q2, it2, _ = osc.scc(box.pos, box.species, L, m, subs, q_start=start)
     assert it2 < it
-    assert np.abs(q2 - q).max() < 1e-5
+    # both stop at an RMS residual below 1e-5 e, so they agree at that level
+    assert math.sqrt(np.mean((q2 - q) ** 2)) < 1e-5 and np.abs(q2 - q).max() < 5e-5
+
+
+def test_anderson_on_affine_map():
+    rng = np.random.default_rng(0)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * -np.linspace(0.1, 8.0, n)) @ Q.T          # response eigenvalues down to -8
+    b = rng.standard_normal(n)
+    x = np.linalg.solve(np.eye(n) - A, b)
+    G = lambda v: A @ v + b
+    q, it, hist, ok = osc.fixed_point(G, np.zeros(n), mix=0.3, tol=1e-10, mixer="anderson", depth=5)
+    assert ok and np.abs(q - x).max() < 1e-9
+    # linear mixing at c = 0.3 diverges here (|1 - 0.3 (1 + 8)| > 1)
+    _, _, hist_lin, ok_lin = osc.fixed_point(G, np.zeros(n), mix=0.3, tol=1e-10, max_iter=60)
+    assert not ok_lin and hist_lin[-1] > hist_lin[0]
+    # memory 0 is the linear update, step for step
+    h0 = osc.fixed_point(G, np.zeros(n), mix=0.05, tol=1e-10, max_iter=30, mixer="anderson", depth=0)[2]
+    h1 = osc.fixed_point(G, np.zeros(n), mix=0.05, tol=1e-10, max_iter=30)[2]
+    assert h0 == h1

@@ -226,14 +226,49 @@ def test_ewald_madelung_and_eta():
     q -= q.mean()
     U = np.array([13.6057, 10.8846])
     L = b.box[0]
-    v1 = ewald.coulomb_potential(b.pos, b.species, q, L, U, eta=4.0 / L, n_real=2, k_max=6)
-    v2 = ewald.coulomb_potential(b.pos, b.species, q, L, U, eta=6.0 / L, n_real=2, k_max=9)
-    assert np.max(np.abs(v1 - v2)) < 1e-8
-    # far-apart pair limit: two opposite charges at 1 A in a huge box ~ k_e / r
+    for screened in (False, True):
+        v1 = ewald.coulomb_potential(b.pos, b.species, q, L, U, eta=4.0 / L, n_real=2, k_max=6, screened=screened)
+        v2 = ewald.coulomb_potential(b.pos, b.species, q, L, U, eta=6.0 / L, n_real=2, k_max=9, screened=screened)
+        assert np.max(np.abs(v1 - v2)) < 1e-8
+    # isolated pair limit: two opposite point charges at 1 A in a huge box ~ k_e / r
     pos = np.array([[50.0, 50, 50], [51.0, 50, 50]])
     qq = np.array([1.0, -1.0])
-    v = ewald.coulomb_potential(pos, np.array([1, 1]), qq, 100.0, np.zeros(2), eta=0.06, n_real=1, k_max=8)
+    v = ewald.coulomb_potential(pos, np.array([1, 1]), qq, 100.0, np.zeros(2), eta=0.06, n_real=1, k_max=8,
+                                screened=False)
     assert abs(v[0] - (-14.399645 * 1.0)) < 2e-3
+
+
+def _slater_gamma_quadrature(ta, tb, R):
+    """Coulomb energy of two unit densities t^3/(8 pi) exp(-t r) at distance R,
+    by nested quadrature: shell averages of the second density's potential
+    1/s - exp(-tb s) (1/s + tb/2) over the first density."""
+    from scipy import integrate
+
+    def phi(s):          # 1/s - exp(-tb s)/s written without cancellation
+        return -np.expm1(-tb * s) / s - 0.5 * tb * np.exp(-tb * s) if s > 1e-12 else tb / 2.0
+
+    def shell(r):
+        v, _ = integrate.quad(lambda s: s * phi(s), abs(r - R), r + R, limit=200)
+        return v / (2.0 * r * R)
+
+    v, _ = integrate.quad(lambda r: r * r * ta ** 3 / 2.0 * np.exp(-ta * r) * shell(r), 0.0, 60.0 / ta, limit=400,
+                          points=[R])
+    return v
+
+
+def test_slater_screening_closed_form():
+    """gamma = 1/R - S of the screened interaction against direct quadrature,
+    gamma -> U at R -> 0, S -> 0 at large R, and the species symmetry."""
+    tau = ewald.slater_tau([13.6057, 10.8846])
+    for ta, tb in ((tau[0], tau[0]), (tau[0], tau[1]), (tau[1], tau[1])):
+        for R in (0.3, 0.96, 2.5, 6.0):
+            g = 1.0 / R - ewald.slater_short(ta, tb, R)
+            assert abs(g - _slater_gamma_quadrature(ta, tb, R)) < 1e-9 * max(1.0, g)
+        assert abs(ewald.slater_short(ta, tb, 0.96) - ewald.slater_short(tb, ta, 0.96)) < 1e-15
+        assert ewald.slater_short(ta, tb, 15.0) < 1e-12
+    # on-site limit: gamma(0) = 5 tau / 16 = U (atomic units), i.e. U / k_e in 1/A
+    R = 1e-6
+    assert abs((1.0 / R - ewald.slater_short(tau[0], tau[0], R)) * 14.399645 - 13.6057) < 1e-4
 
 
 def test_grid_cores_and_halos_bruteforce(box96):
