@@ -126,6 +126,35 @@ def cpu_baseline(box, wl, max_seconds: float = 20.0):
     }
 
 
+def copy_calibration():
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_split_water10000_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per split-GEMM dispatch from the committed rocprofv3 counter
+    summary, or None when the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        with open(os.path.join(ROOT, "paper_2606_03140_amd", "csrc", "mixed.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return float(t["hbm_bytes_per_dispatch"]) if t.get("source_sha256") == sha else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,9 +163,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--paths", default="fp64,mixed")
-    ap.add_argument("--traffic", type=float, default=None,
-                    help="measured HBM bytes per split-GEMM launch (rocprofv3 FETCH/WRITE, calibrated)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the reference kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the per-subgraph "
               f"solve would shard over GPUs by subgraph, which is not built here.", file=sys.stderr)
@@ -212,7 +245,7 @@ def main():
         byts = st["bytes_per_launch"]
         intensity = flops / byts
         roof = {"bound": "hbm", "kernel": kname, "achieved": byts / (avg_ms * 1e-3) / 1e9,
-                "peak": PEAK["hbm"] / 1e9, "unit": "GB/s", "traffic": args.traffic,
+                "peak": PEAK["hbm"] / 1e9, "unit": "GB/s", "traffic": measured_traffic(),
                 "mfma_tflops": flops / (avg_ms * 1e-3) / 1e12, "mfma_peak_tflops": PEAK["fp16_mfma"] / 1e12,
                 "mfma_frac": flops / (avg_ms * 1e-3) / PEAK["fp16_mfma"],
                 "useful_tflops": st["flops_per_launch"] / (avg_ms * 1e-3) / 1e12,
