@@ -236,9 +236,9 @@ int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes);
 int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int64_t* gemm_launches,
                     double* flops_per_launch, double* bytes_per_launch);
 
-/* Diagnostics: copy the FP32 matrix `which` (0 s, 1 h, 2 Y, 3 Z, 4 T, 5-6
- * Newton-Schulz ping-pong, 7 h_perp, 8 W = Z s, 9 X, 10 X^2, 11 A, 12 R, 13
- * inverse) of subgraph `sub` of the last GDM_MIXED_F16 solve into `out`
+/* Diagnostics: copy the FP32 matrix `which` (0 Z, the inverse-overlap
+ * factor before FP64 refinement; 1 h_perp; 2 X, 3 X^2 of the last expansion
+ * pass) of subgraph `sub` of the last GDM_MIXED_F16 solve into `out`
  * (device, P*P floats, P the padded size = 64 ceil(n/64)). */
 int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out);
 
@@ -257,7 +257,8 @@ int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out);
  * with tau = tau[species] (HOST [2], 1/A; 16/5 U in atomic units), so that
  * 1/r - S -> U as r -> 0; tau NULL gives bare point charges.
  * row_ptr/col: a neighbour CSR containing every pair with r < rcut (e.g.
- * gdm_build_graph CUTOFF at rcut).  Requires 2 rcut < every box side,
+ * gdm_build_graph CUTOFF at rcut, or at rcut + skin: pairs at r >= rcut are
+ * skipped).  Requires 2 rcut < every box side,
  * eta > 0, 1 <= k_max <= 64; hubbard_U HOST [2] eV.  q, V: [n_atoms] FP64.
  * Accuracy is the caller's choice of (rcut, eta, k_max): erfc(eta rcut),
  * exp(-(pi k_max / (eta L))^2) and S(rcut) bound the truncation.
@@ -293,7 +294,7 @@ int gdm_scc_anderson(gdm_ctx* ctx, int32_t n, double* n_vec, const double* q0, d
  * exp(-(r - c_k)^2 / (2 * 0.3^2)) (cos(pi r / 5) + 1) / 2,
  * c_k = 0.8 + 3.2 k / 15 (k = 0..15), minimum image.  row_ptr/col: a
  * neighbour CSR containing every pair with r < 5 A (e.g. gdm_build_graph
- * CUTOFF at 5.0). */
+ * CUTOFF at 5.0, or wider: pairs at r >= 5 A are skipped). */
 int gdm_descriptors(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr,
                     const int32_t* col, double* feats);
 

@@ -31,6 +31,13 @@ int gdm_hip(gdm_ctx* ctx, hipError_t e, const char* what) {
     return gdm_fail(ctx, GDM_E_HIP, "HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
 }
 
+void gdm_buf_release(gdm_ctx* ctx, int slot) {
+    DevBuf& b = ctx->b[slot];
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
 void* gdm_buf(gdm_ctx* ctx, int slot, size_t bytes, bool* ok) {
     DevBuf& b = ctx->b[slot];
     if (bytes == 0) bytes = 8;
@@ -204,6 +211,16 @@ extern "C" int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         P.max_nc = std::max(P.max_nc, nc);
         P.max_natoms = std::max(P.max_natoms, d.natoms);
     }
+    // release the other solver's exclusive workspace, so that switching
+    // solvers on one context holds one solver's arena, not both
+    static const int kFp64Only[] = {BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W, BUF_ROTC, BUF_ROTS,
+                                    BUF_ROTI, BUF_ROTN, BUF_QC, BUF_MU, BUF_MUPART};
+    static const int kMixedOnly[] = {BUF_X_F, BUF_X_HI, BUF_X_LO, BUF_GERSH, BUF_TR, BUF_NDBL, BUF_TILES};
+    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (precision == GDM_FP64_EIG)
+        for (int s : kMixedOnly) gdm_buf_release(ctx, s);
+    else
+        for (int s : kFp64Only) gdm_buf_release(ctx, s);
     bool ok = true;
     void* desc = gdm_buf(ctx, BUF_DESC, sizeof(SubDesc) * ns, &ok);
     if (precision == GDM_FP64_EIG) {

@@ -117,6 +117,7 @@ enum {
 int gdm_fail(gdm_ctx* ctx, int code, const char* fmt, ...);
 int gdm_hip(gdm_ctx* ctx, hipError_t e, const char* what);
 void* gdm_buf(gdm_ctx* ctx, int slot, size_t bytes, bool* ok);
+void gdm_buf_release(gdm_ctx* ctx, int slot);
 
 #define GDM_HIP(ctx, call)                                   \
     do {                                                     \

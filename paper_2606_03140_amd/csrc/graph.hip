@@ -93,6 +93,9 @@ __global__ void k_cell_scatter(int n, const int32_t* __restrict__ cell, int32_t*
     cellatoms[slot] = i;
 }
 
+constexpr int kShortRow = 64;
+constexpr int kSortMax = 8192;
+
 template <bool FILL>
 __global__ void k_cell_pairs(const double* __restrict__ pos, int n, Grid3 G, double3 L, double3 iL,
                              double c2, const int32_t* __restrict__ cell,
@@ -125,8 +128,9 @@ __global__ void k_cell_pairs(const double* __restrict__ pos, int n, Grid3 G, dou
             }
     if (!FILL) {
         cnt[i] = count;
-    } else {
-        // ascending columns: insertion sort of the (short) row
+    } else if (count <= kShortRow || count > kSortMax) {
+        // ascending columns: insertion sort of a short row (rows of
+        // kShortRow..kSortMax entries are sorted by k_sort_long_rows)
         int b = row_ptr[i];
         for (int a = 1; a < count; ++a) {
             int v = col[b + a];
@@ -138,6 +142,35 @@ __global__ void k_cell_pairs(const double* __restrict__ pos, int n, Grid3 G, dou
             col[b + p + 1] = v;
         }
     }
+}
+
+// Bitonic sort in LDS of every row with kShortRow < length <= kSortMax (one
+// workgroup per row; shorter and longer rows were sorted by k_cell_pairs).
+__global__ void __launch_bounds__(256) k_sort_long_rows(const int32_t* __restrict__ row_ptr,
+                                                       int32_t* __restrict__ col) {
+    __shared__ int32_t s[kSortMax];
+    const int i = blockIdx.x;
+    const int b = row_ptr[i], cnt = row_ptr[i + 1] - b;
+    if (cnt <= kShortRow || cnt > kSortMax) return;
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    for (int e = threadIdx.x; e < P; e += 256) s[e] = e < cnt ? col[b + e] : INT32_MAX;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int e = threadIdx.x; e < P; e += 256) {
+                const int x = e ^ j;
+                if (x > e) {
+                    const int a = s[e], c = s[x];
+                    if ((a > c) == ((e & k) == 0)) {
+                        s[e] = c;
+                        s[x] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int e = threadIdx.x; e < cnt; e += 256) col[b + e] = s[e];
 }
 
 // ---------------------------------------------------------------- cores
@@ -358,6 +391,8 @@ int gdm_cutoff_graph(gdm_ctx* ctx, const gdm_system* sys, double cutoff, int32_t
                                      (long long)total, (long long)cap);
     hipLaunchKernelGGL(k_cell_pairs<true>, dim3(blocks_for(n, 128)), dim3(128), 0, ctx->stream, sys->pos, n, G, L,
                        iL, c2, cell, cellstart, cellatoms, nullptr, row_ptr, col);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_sort_long_rows, dim3(n), dim3(256), 0, ctx->stream, row_ptr, col);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }

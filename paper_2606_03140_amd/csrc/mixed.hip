@@ -478,11 +478,28 @@ __global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* 
 
 // --------------------------------------------------------------------- host
 
-enum { SL_S = 0, SL_H, SL_Y, SL_Z, SL_T, SL_Y2, SL_Z2, SL_HP, SL_W, SL_X, SL_X2, SL_A, SL_R, SL_YI, SL_COUNT };
+enum { SL_H = 0, SL_Y, SL_Z, SL_T, SL_Y2, SL_Z2, SL_HP, SL_X, SL_X2, SL_A, SL_R, SL_YI, SL_COUNT };
+
+// Every slot holds the FP16 hi/lo split; only the matrices read back in FP32
+// (the inverse-overlap factor and its Newton-Schulz partner, h_perp, X and
+// X^2) also keep an FP32 copy.  Slots without one have f = nullptr, which
+// every writer skips.
+constexpr int kF32Slots = 5;
+static int f32_index(int k) {
+    switch (k) {
+        case SL_Z: return 0;
+        case SL_Z2: return 1;
+        case SL_HP: return 2;
+        case SL_X: return 3;
+        case SL_X2: return 4;
+        default: return -1;
+    }
+}
 
 static SplitMat slot(gdm_ctx* ctx, int k) {
     const int64_t tot = ctx->plan.tot2;
-    float* f = (float*)ctx->b[BUF_X_F].p + (int64_t)k * tot;
+    const int fi = f32_index(k);
+    float* f = fi < 0 ? nullptr : (float*)ctx->b[BUF_X_F].p + (int64_t)fi * tot;
     _Float16* hi = (_Float16*)ctx->b[BUF_X_HI].p + (int64_t)k * tot;
     _Float16* lo = (_Float16*)ctx->b[BUF_X_LO].p + (int64_t)k * tot;
     return SplitMat{f, hi, lo};
@@ -538,7 +555,7 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
     int4* dt = (int4*)gdm_buf(ctx, BUF_TILES, sizeof(int4) * tiles.size(), &ok);
     gdm_buf(ctx, BUF_A, sizeof(double) * P.tot2, &ok);
     gdm_buf(ctx, BUF_S, sizeof(double) * P.tot2, &ok);
-    gdm_buf(ctx, BUF_X_F, sizeof(float) * P.tot2 * SL_COUNT, &ok);
+    gdm_buf(ctx, BUF_X_F, sizeof(float) * P.tot2 * kF32Slots, &ok);
     gdm_buf(ctx, BUF_X_HI, sizeof(_Float16) * P.tot2 * SL_COUNT, &ok);
     gdm_buf(ctx, BUF_X_LO, sizeof(_Float16) * P.tot2 * SL_COUNT, &ok);
     gdm_buf(ctx, BUF_GERSH, sizeof(double) * 2 * (size_t)P.n_sub, &ok);
@@ -860,10 +877,11 @@ extern "C" int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int6
 extern "C" int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out) {
     if (!ctx) return GDM_E_ARG;
     const Plan& P = ctx->plan;
-    if (P.precision != GDM_MIXED_F16 || which < 0 || which >= SL_COUNT || sub < 0 || sub >= P.n_sub || !out)
+    static const int kDebugSlots[4] = {SL_Z, SL_HP, SL_X, SL_X2};
+    if (P.precision != GDM_MIXED_F16 || which < 0 || which >= 4 || sub < 0 || sub >= P.n_sub || !out)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_debug_slot: bad argument");
     const SubDesc& d = P.desc[sub];
-    GDM_HIP(ctx, hipMemcpyAsync(out, slot(ctx, which).f + d.off2, sizeof(float) * (size_t)d.ld * d.ld,
+    GDM_HIP(ctx, hipMemcpyAsync(out, slot(ctx, kDebugSlots[which]).f + d.off2, sizeof(float) * (size_t)d.ld * d.ld,
                                 hipMemcpyDeviceToDevice, ctx->stream));
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return GDM_OK;

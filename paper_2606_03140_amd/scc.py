@@ -40,17 +40,20 @@ class EwaldSetup:
     graph: Graph
 
 
-def ewald_setup(ctx: Context, system: System, rcut_max: float = 12.0, tol: float = 1e-10) -> EwaldSetup:
+def ewald_setup(ctx: Context, system: System, rcut_max: float = 12.0, tol: float = 1e-10,
+                skin: float = 0.0) -> EwaldSetup:
     """Split parameters for a truncation error of about `tol` in both sums:
-    erfc(eta rcut) ~ tol and exp(-k_c^2 / 4 eta^2) ~ tol, rcut below half the
-    shortest box edge, plus the real-space neighbour CSR at rcut."""
+    erfc(eta rcut) ~ tol and exp(-k_c^2 / 4 eta^2) ~ tol, rcut + skin below
+    half the shortest box edge, plus the real-space pair CSR at rcut + skin
+    (the kernel skips pairs at r >= rcut, so the list stays valid while no
+    atom moves more than skin / 2)."""
     L = system.box
-    rcut = min(rcut_max, 0.499 * min(L))
+    rcut = min(rcut_max, 0.499 * min(L) - skin)
     a = math.sqrt(-math.log(tol))
     eta = a / rcut
     k_c = 2.0 * eta * a
     k_max = int(math.ceil(k_c * max(L) / (2.0 * math.pi)))
-    graph = ctx.build_graph_cutoff(system, rcut)
+    graph = ctx.build_graph_cutoff(system, rcut + skin)
     return EwaldSetup(rcut=rcut, eta=eta, k_max=k_max, graph=graph)
 
 

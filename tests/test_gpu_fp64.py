@@ -38,6 +38,21 @@ def test_cutoff_graph_bitexact(c, nw, seed):
     assert np.array_equal(col, ocol)
 
 
+@pytest.mark.parametrize("nw,seed,cutoff", [(300, 21, 7.0), (300, 21, 10.0), (3000, 2, 12.0)])
+def test_long_row_graph_bitexact(c, nw, seed, cutoff):
+    """Wide cutoffs (Ewald real space, descriptors with a skin): rows of 140 to
+    1,100 neighbours take the LDS bitonic row sort."""
+    log(f"cutoff graph {nw} waters at {cutoff} A")
+    box = waterbox.water_box(nw, seed)
+    sysm = system_of(box)
+    g = c.build_graph_cutoff(sysm, cutoff)
+    rp, col = csr_host(g)
+    orp, ocol = om.neighbour_list(box.pos, box.box[0], cutoff=cutoff)
+    log(f"  {len(ocol)} edges, {len(ocol) / len(box.species):.0f} per atom")
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(col, ocol)
+
+
 @pytest.mark.parametrize("nw,seed,grid", [(96, 1, (2, 2, 2)), (10000, 3, (10, 10, 10)), (3000, 2, (5, 5, 6))])
 def test_cores_and_subgraphs_bitexact(c, nw, seed, grid):
     log(f"cores/subgraphs {nw} waters grid {grid}")
