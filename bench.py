@@ -141,15 +141,26 @@ def copy_calibration():
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_split_water10000_traffic.json")
 
 
+GEMM_SOURCE_END = "// ------------------------------------------------------------ FP64 GEMM"
+
+
+def gemm_source_sha256():
+    """SHA-256 of the split GEMM's source: mixed.hip from its start (constants,
+    split helpers) to the end of k_gemm_split."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2606_03140_amd", "csrc", "mixed.hip")) as f:
+        text = f.read()
+    end = text.find(GEMM_SOURCE_END)
+    return hashlib.sha256(text[:end if end >= 0 else len(text)].encode()).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per split-GEMM dispatch from the committed rocprofv3 counter
     summary, or None when the kernel source has changed since it was taken."""
-    import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        with open(os.path.join(ROOT, "paper_2606_03140_amd", "csrc", "mixed.hip"), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = gemm_source_sha256()
     except (OSError, ValueError):
         return None
     return float(t["hbm_bytes_per_dispatch"]) if t.get("source_sha256") == sha else None

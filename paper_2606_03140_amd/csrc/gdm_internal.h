@@ -136,6 +136,9 @@ void gdm_buf_release(gdm_ctx* ctx, int slot);
 // exclusive scan over n int32 (out has n+1 entries, out[n] = total) on stream
 int gdm_scan_i32(gdm_ctx* ctx, const int32_t* in, int32_t* out, int64_t n);
 int gdm_scan_i64(gdm_ctx* ctx, const int64_t* in, int64_t* out, int64_t n);
+// fill n entries with v on the stream (a kernel, no memset node)
+int gdm_fill_i32(gdm_ctx* ctx, int32_t* p, int64_t n, int32_t v);
+int gdm_fill_f64(gdm_ctx* ctx, double* p, int64_t n, double v);
 
 // solve paths
 int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,

@@ -205,16 +205,21 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
 }
 
 // ------------------------------------------------------------ FP64 GEMM
-// C = alpha A B + beta Cin + gamma I on the padded P x P tiles, true product
-// (no symmetry assumed), FP64 FMA.  64 x 64 output tile per workgroup, each
-// thread a 4 x 4 block, k-steps of 16 staged in LDS.  TA / TB: double or float.
-template <typename TA, typename TB>
+// C = alpha A B + beta Cin + gamma I on the padded P x P tiles, true product,
+// FP64 FMA.  64 x 64 output tile per workgroup, each thread a 4 x 4 block,
+// k-steps of 16 staged in LDS.  TA / TB: double or float.  SYM: the product
+// is symmetric (Z s Z, and Z E of commuting factors): launched on the upper
+// tiles only; the tile is staged in LDS and written with its mirror, the
+// lower half of a diagonal tile taken from its upper half, so C is exactly
+// symmetric (Cin must then be symmetric too).
+template <typename TA, typename TB, bool SYM>
 __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
                                                const TA* __restrict__ A, const TB* __restrict__ B,
                                                const double* __restrict__ Cin, double* __restrict__ C,
                                                double alpha, double beta, double gamma) {
     __shared__ double sA[16][64 + 1];   // sA[k][m]
     __shared__ double sB[16][64 + 1];   // sB[k][n]
+    __shared__ double sC[SYM ? 64 : 1][65];
     const int4 tl = tiles[blockIdx.x];
     if (tl.x < 0) return;
     const SubDesc d = desc[tl.x];
@@ -243,31 +248,43 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
                 for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
         }
     }
+    if (!SYM) {
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
+                const int64_t idx = base + (int64_t)m * P + n;
+                double v = alpha * acc[i][j];
+                if (Cin) v += beta * Cin[idx];
+                if (m == n) v += gamma;
+                C[idx] = v;
+            }
+        return;
+    }
     for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) {
-            const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
+        for (int j = 0; j < 4; ++j) sC[ty * 4 + i][tx * 4 + j] = acc[i][j];
+    __syncthreads();
+    const bool diag = tl.y == tl.z;
+    for (int pass = 0; pass < (diag ? 1 : 2); ++pass)
+        for (int e = t; e < 64 * 64; e += 256) {
+            const int r = e >> 6, c = e & 63;
+            double a;
+            if (pass == 1 || (diag && r > c)) a = sC[c][r];
+            else a = sC[r][c];
+            const int m = (pass == 0 ? m0 : n0) + r, n = (pass == 0 ? n0 : m0) + c;
             const int64_t idx = base + (int64_t)m * P + n;
-            double v = alpha * acc[i][j];
+            double v = alpha * a;
             if (Cin) v += beta * Cin[idx];
             if (m == n) v += gamma;
             C[idx] = v;
         }
 }
 
-// Z64 (FP64) <- its FP32 split copy for the expansion
-__global__ void __launch_bounds__(256) k_z64_to_split(const SubDesc* __restrict__ desc, const double* __restrict__ Z64,
-                                                     SplitMat Z) {
-    const SubDesc d = desc[blockIdx.x];
-    const int P = d.ld;
-    for (int64_t e = threadIdx.x; e < (int64_t)P * P; e += 256) store_split(Z, d.off2 + e, (float)Z64[d.off2 + e]);
-}
-
-// FP32 -> FP64 copy (the Newton-Schulz Z before refinement)
-__global__ void __launch_bounds__(256) k_f32_to_f64(const SubDesc* __restrict__ desc, const float* __restrict__ src,
-                                                   double* __restrict__ dst) {
-    const SubDesc d = desc[blockIdx.x];
-    const int P = d.ld;
-    for (int64_t e = threadIdx.x; e < (int64_t)P * P; e += 256) dst[d.off2 + e] = (double)src[d.off2 + e];
+// Z (FP16 hi/lo split) <- Z64, flat over every packed tile (padding included)
+__global__ void __launch_bounds__(256) k_z64_to_split(int64_t n4, const double* __restrict__ Z64, SplitMat Z) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256) {
+        const double4 v = *(const double4*)(Z64 + 4 * e);
+        store4(Z, 4 * e, make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w));
+    }
 }
 
 // N_s = 2 sum_{a<nc, c<n} G_ac V_ac,  M_s = 2 sum (G - G2)_ac V_ac   (FP64)
@@ -360,56 +377,84 @@ __device__ __forceinline__ double block_reduce_sum(double v, double* red) {
     return r;
 }
 
-// From the gathered FP64 h, s (leading dimension P): the Gershgorin upper
-// bound c of s, then H = h, Y0 = s / c, Z0 = I as split operands (padding:
-// identity for Y, Z and zero for H; the FP64 tiles get h = 0, s = I there).
-// Z also gets its FP32 copy when s = I, since Newton-Schulz is skipped then.
+// The elementwise kernels below run on a (subgraph, 64-row strip) grid: block
+// (x, y) covers rows 64y .. 64y+63 of subgraph x's padded P x P tile, four
+// consecutive columns per thread and step (P is a multiple of 64).
+
+// Gershgorin upper bound of s: max_i sum_j |s_ij| per subgraph, one wave per
+// row; the maximum is combined with an unsigned atomic max on the bit pattern
+// (order-preserving for non-negative doubles) into cbits, zeroed beforehand.
+__global__ void __launch_bounds__(kEw) k_rowabs_max(const SubDesc* __restrict__ desc, const double* __restrict__ s64,
+                                                   unsigned long long* __restrict__ cbits) {
+    const SubDesc d = desc[blockIdx.x];
+    const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
+    if (r0 >= n) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r1 = min(r0 + 64, n);
+    double m = 0.0;
+    for (int r = r0 + wave; r < r1; r += kEw / 64) {
+        const double* row = s64 + d.off2 + (int64_t)r * P;
+        double acc = 0.0;
+        for (int j = lane; j < n; j += 64) acc += fabs(row[j]);
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        m = fmax(m, acc);
+    }
+    if (lane == 0 && m > 0.0) atomicMax(&cbits[blockIdx.x], (unsigned long long)__double_as_longlong(m));
+}
+
+// H = h, Y0 = s / c, Z0 = I as split operands (padding: identity for Y, Z and
+// zero for H; the FP64 tiles get h = 0, s = I there).  c = scale[sub] (the
+// Gershgorin bound of s; 1 when s = I).  Z also gets its FP32 copy when
+// s = I, since Newton-Schulz is skipped then.
 __global__ void __launch_bounds__(kEw) k_prep(const SubDesc* __restrict__ desc, double* __restrict__ h64,
                                              double* __restrict__ s64, SplitMat H, SplitMat Y, SplitMat Z,
-                                             double* __restrict__ scale, int orthogonal) {
-    __shared__ double red[kEw / 64];
+                                             const double* __restrict__ scale, int orthogonal) {
     const SubDesc d = desc[blockIdx.x];
-    const int n = d.n, P = d.ld;
-    const int64_t base = d.off2;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double rmax = 0.0;
-    if (!orthogonal)
-        for (int i = wave; i < n; i += kEw / 64) {
-            const double* row = s64 + base + (int64_t)i * P;
-            double acc = 0.0;
-            for (int j = lane; j < n; j += 64) acc += fabs(row[j]);
-            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-            rmax = fmax(rmax, acc);
+    const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
+    if (r0 >= P) return;
+    const float ic = orthogonal ? 1.f : (float)(1.0 / scale[blockIdx.x]);
+    const int q4 = P >> 2;
+    for (int e = threadIdx.x; e < 64 * q4; e += kEw) {
+        const int i = r0 + e / q4, j0 = (e % q4) * 4;
+        const int64_t idx = d.off2 + (int64_t)i * P + j0;
+        float hv[4], yv[4], zv[4];
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + q;
+            const bool in = i < n && j < n;
+            const float id = i == j ? 1.f : 0.f;
+            const float sv = in ? (orthogonal ? id : (float)s64[idx + q]) : id;
+            hv[q] = in ? (float)h64[idx + q] : 0.f;
+            yv[q] = in ? sv * ic : id;
+            zv[q] = id;
+            if (!in) {
+                h64[idx + q] = 0.0;
+                s64[idx + q] = id;
+            }
         }
-    const double c = orthogonal ? 1.0 : block_reduce_max(rmax, red);
-    if (threadIdx.x == 0) scale[blockIdx.x] = c;
-    const float ic = (float)(1.0 / c);
-    for (int64_t e = threadIdx.x; e < (int64_t)P * P; e += kEw) {
-        const int i = (int)(e / P), j = (int)(e - (int64_t)i * P);
-        const int64_t idx = base + e;
-        const bool in = i < n && j < n;
-        const float sv = in ? (orthogonal ? (i == j ? 1.f : 0.f) : (float)s64[idx]) : (i == j ? 1.f : 0.f);
-        store_split(H, idx, in ? (float)h64[idx] : 0.f);
-        store_split(Y, idx, in ? sv * ic : (i == j ? 1.f : 0.f));
-        store_split(Z, idx, i == j ? 1.f : 0.f);
-        if (!in) {
-            h64[idx] = 0.0;
-            s64[idx] = i == j ? 1.0 : 0.0;
-        }
+        store4(H, idx, make_float4(hv[0], hv[1], hv[2], hv[3]));
+        store4(Y, idx, make_float4(yv[0], yv[1], yv[2], yv[3]));
+        store4(Z, idx, make_float4(zv[0], zv[1], zv[2], zv[3]));
     }
 }
 
-// Z <- Z / sqrt(c) on the n x n block (padding stays identity)
-__global__ void __launch_bounds__(kEw) k_scale_z(const SubDesc* __restrict__ desc, SplitMat Z,
-                                                const double* __restrict__ scale) {
+// Z64 <- the Newton-Schulz Z / sqrt(c) in FP64 on the n x n block (padding
+// copied: it stays the identity through the iteration)
+__global__ void __launch_bounds__(kEw) k_scale_to_f64(const SubDesc* __restrict__ desc, const float* __restrict__ Zf,
+                                                     const double* __restrict__ scale, int orthogonal,
+                                                     double* __restrict__ Z64) {
     const SubDesc d = desc[blockIdx.x];
-    const int n = d.n, P = d.ld;
-    const float f = (float)(1.0 / sqrt(scale[blockIdx.x]));
-    for (int64_t e = threadIdx.x; e < (int64_t)P * P; e += kEw) {
-        const int i = (int)(e / P), j = (int)(e - (int64_t)i * P);
-        if (i >= n || j >= n) continue;
-        const int64_t idx = d.off2 + e;
-        store_split(Z, idx, Z.f[idx] * f);
+    const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
+    if (r0 >= P) return;
+    const double f = orthogonal ? 1.0 : 1.0 / sqrt(scale[blockIdx.x]);
+    const int q4 = P >> 2;
+    for (int e = threadIdx.x; e < 64 * q4; e += kEw) {
+        const int i = r0 + e / q4, j0 = (e % q4) * 4;
+        const int64_t idx = d.off2 + (int64_t)i * P + j0;
+        const float4 z = *(const float4*)(Zf + idx);
+        const double zs[4] = {z.x, z.y, z.z, z.w};
+        double o[4];
+        for (int q = 0; q < 4; ++q) o[q] = (i < n && j0 + q < n) ? zs[q] * f : zs[q];
+        *(double4*)(Z64 + idx) = make_double4(o[0], o[1], o[2], o[3]);
     }
 }
 
@@ -445,17 +490,21 @@ __global__ void __launch_bounds__(kEw) k_sym_bounds(const SubDesc* __restrict__ 
 __global__ void __launch_bounds__(kEw) k_x0(const SubDesc* __restrict__ desc, const float* __restrict__ Hf,
                                            SplitMat X, double mu, double b) {
     const SubDesc d = desc[blockIdx.x];
-    const int n = d.n, P = d.ld;
+    const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
+    if (r0 >= P) return;
     const double q = b / 4.0;
-    for (int64_t e = threadIdx.x; e < (int64_t)P * P; e += kEw) {
-        const int i = (int)(e / P), j = (int)(e - (int64_t)i * P);
-        const int64_t idx = d.off2 + e;
-        float v = 0.f;
-        if (i < n && j < n) {
-            double hv = (double)Hf[idx];
-            v = (float)((i == j ? 0.5 : 0.0) - q * (hv - (i == j ? mu : 0.0)));
+    const int q4 = P >> 2;
+    for (int e = threadIdx.x; e < 64 * q4; e += kEw) {
+        const int i = r0 + e / q4, j0 = (e % q4) * 4;
+        const int64_t idx = d.off2 + (int64_t)i * P + j0;
+        const float4 h = *(const float4*)(Hf + idx);
+        const float hs[4] = {h.x, h.y, h.z, h.w};
+        float v[4];
+        for (int k = 0; k < 4; ++k) {
+            const int j = j0 + k;
+            v[k] = (i < n && j < n) ? (float)((i == j ? 0.5 : 0.0) - q * ((double)hs[k] - (i == j ? mu : 0.0))) : 0.f;
         }
-        store_split(X, idx, v);
+        store4(X, idx, make_float4(v[0], v[1], v[2], v[3]));
     }
 }
 
@@ -506,6 +555,9 @@ static SplitMat slot(gdm_ctx* ctx, int k) {
 }
 
 static SplitMat none() { return SplitMat{nullptr, nullptr, nullptr}; }
+
+// (subgraph, 64-row strip) grid of the elementwise kernels
+static dim3 strip_grid(const Plan& P) { return dim3((unsigned)P.n_sub, (unsigned)((P.max_n + 63) / 64)); }
 
 int gdm_mixed_plan(gdm_ctx* ctx) {
     Plan& P = ctx->plan;
@@ -617,7 +669,7 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
     *nd_out = nd;
     {
         GDM_TIMED(ctx, "mixed_misc");
-        hipLaunchKernelGGL(k_x0, dim3(P.n_sub), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP).f, slot(ctx, SL_X),
+        hipLaunchKernelGGL(k_x0, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP).f, slot(ctx, SL_X),
                            mu, b);
     }
     GDM_LAUNCH_CHECK(ctx);
@@ -646,22 +698,19 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
 
 static double* z64(gdm_ctx* ctx) { return (double*)ctx->b[BUF_L].p + 2 * ctx->plan.tot2; }
 
-static int gemm64_ff(gdm_ctx* ctx, const double* A, const float* B, const double* Cin, double* C, double alpha,
-                     double beta, double gamma) {
-    GDM_TIMED(ctx, "refine64");
-    hipLaunchKernelGGL((k_gemm64<double, float>), dim3((unsigned)ctx->mixed_tiles), dim3(256), 0, ctx->stream,
-                       (const SubDesc*)ctx->b[BUF_DESC].p, (const int4*)ctx->b[BUF_TILES].p, A, B, Cin, C, alpha,
-                       beta, gamma);
-    GDM_LAUNCH_CHECK(ctx);
-    return GDM_OK;
-}
-
+// FP64 products on all tiles (sym = 0) or on the upper tiles with mirrored
+// output (sym = 1, symmetric products only)
 static int gemm64_dd(gdm_ctx* ctx, const double* A, const double* B, const double* Cin, double* C, double alpha,
-                     double beta, double gamma) {
+                     double beta, double gamma, int sym) {
     GDM_TIMED(ctx, "refine64");
-    hipLaunchKernelGGL((k_gemm64<double, double>), dim3((unsigned)ctx->mixed_tiles), dim3(256), 0, ctx->stream,
-                       (const SubDesc*)ctx->b[BUF_DESC].p, (const int4*)ctx->b[BUF_TILES].p, A, B, Cin, C, alpha,
-                       beta, gamma);
+    const int4* tl = (const int4*)ctx->b[BUF_TILES].p + (sym ? ctx->mixed_tiles : 0);
+    const unsigned nt = (unsigned)(sym ? ctx->mixed_tiles_sym : ctx->mixed_tiles);
+    if (sym)
+        hipLaunchKernelGGL((k_gemm64<double, double, true>), dim3(nt), dim3(256), 0, ctx->stream,
+                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma);
+    else
+        hipLaunchKernelGGL((k_gemm64<double, double, false>), dim3(nt), dim3(256), 0, ctx->stream,
+                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }
@@ -670,7 +719,7 @@ template <typename TB>
 static int gemm64_core(gdm_ctx* ctx, const double* A, const TB* B, double* C, const char* tag) {
     GDM_TIMED(ctx, tag);
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles + ctx->mixed_tiles_sym;
-    hipLaunchKernelGGL((k_gemm64<double, TB>), dim3((unsigned)ctx->mixed_tiles_core), dim3(256), 0, ctx->stream,
+    hipLaunchKernelGGL((k_gemm64<double, TB, false>), dim3((unsigned)ctx->mixed_tiles_core), dim3(256), 0, ctx->stream,
                        (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, (const double*)nullptr, C, 1.0, 0.0, 0.0);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
@@ -720,7 +769,13 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
     GDM_TRY(gdm_launch_gather(ctx, sys, sg, row_ptr, col, nnz, H, S, h64, s64, orth));
     {
         GDM_TIMED(ctx, "mixed_misc");
-        hipLaunchKernelGGL(k_prep, dim3(P.n_sub), dim3(kEw), 0, ctx->stream, desc, h64, s64, hl(slot(ctx, SL_H)),
+        GDM_TRY(gdm_fill_f64(ctx, scale, P.n_sub, 0.0));
+        if (!orth) {
+            hipLaunchKernelGGL(k_rowabs_max, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, s64,
+                               (unsigned long long*)scale);
+            GDM_LAUNCH_CHECK(ctx);
+        }
+        hipLaunchKernelGGL(k_prep, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, h64, s64, hl(slot(ctx, SL_H)),
                            hl(slot(ctx, SL_Y)), orth ? slot(ctx, SL_Z) : hl(slot(ctx, SL_Z)), scale, orth);
     }
     GDM_LAUNCH_CHECK(ctx);
@@ -735,41 +790,28 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
             std::swap(Y, Y2);
             std::swap(Z, Z2);
         }
-        {
-            GDM_TIMED(ctx, "mixed_misc");
-            hipLaunchKernelGGL(k_scale_z, dim3(P.n_sub), dim3(kEw), 0, ctx->stream, desc, Z, scale);
-        }
-        GDM_LAUNCH_CHECK(ctx);
     }
-    // keep the final Z in SL_Z
-    if (Z.f != slot(ctx, SL_Z).f) {
-        const int64_t tot = P.tot2;
-        GDM_HIP(ctx, hipMemcpyAsync(slot(ctx, SL_Z).f, Z.f, sizeof(float) * tot, hipMemcpyDeviceToDevice, ctx->stream));
-        GDM_HIP(ctx, hipMemcpyAsync(slot(ctx, SL_Z).hi, Z.hi, sizeof(_Float16) * tot, hipMemcpyDeviceToDevice,
-                                    ctx->stream));
-        GDM_HIP(ctx, hipMemcpyAsync(slot(ctx, SL_Z).lo, Z.lo, sizeof(_Float16) * tot, hipMemcpyDeviceToDevice,
-                                    ctx->stream));
-    }
-    Z = slot(ctx, SL_Z);
-    // FP64 residual refinement of Z (Z s Z = I): F = s Z, E = Z F - I,
-    // Z64 = Z - Z E / 2 (error O(E^2)); Z64 serves the traces and the final
-    // step, its FP32 split copy the expansion.
+    // FP64 residual refinement of Z (Z s Z = I): Z64 = Z / sqrt(c) in FP64,
+    // F = s Z64, E = Z64 F - I, Z64 <- Z64 - Z64 E / 2 (error O(E^2)); E and
+    // the update are symmetric products (upper tiles, mirrored).  Z64 serves
+    // the traces and the final step, its split copy (in SL_Z) the expansion.
     {
-        double* F = (double*)ctx->b[BUF_L].p;
-        double* E = F + P.tot2;
-        double* Z64 = E + P.tot2;
+        double* F = fp64_region(ctx, 0);
+        double* E = fp64_region(ctx, 1);
+        double* Z64 = z64(ctx);
         {
             GDM_TIMED(ctx, "refine64");
-            hipLaunchKernelGGL(k_f32_to_f64, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Z.f, Z64);
+            hipLaunchKernelGGL(k_scale_to_f64, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, Z.f, scale, orth, Z64);
         }
         GDM_LAUNCH_CHECK(ctx);
-        GDM_TRY(gemm64_ff(ctx, s64, Z.f, nullptr, F, 1.0, 0.0, 0.0));
-        GDM_TRY(gemm64_dd(ctx, Z64, F, nullptr, E, 1.0, 0.0, -1.0));     // E = Z (s Z) - I
-        GDM_TRY(gemm64_dd(ctx, Z64, E, Z64, F, -0.5, 1.0, 0.0));        // F <- Z - Z E / 2
+        GDM_TRY(gemm64_dd(ctx, s64, Z64, nullptr, F, 1.0, 0.0, 0.0, 0));     // F = s Z
+        GDM_TRY(gemm64_dd(ctx, Z64, F, nullptr, E, 1.0, 0.0, -1.0, 1));     // E = Z (s Z) - I
+        GDM_TRY(gemm64_dd(ctx, Z64, E, Z64, F, -0.5, 1.0, 0.0, 1));        // F <- Z - Z E / 2
         GDM_HIP(ctx, hipMemcpyAsync(Z64, F, sizeof(double) * P.tot2, hipMemcpyDeviceToDevice, ctx->stream));
+        Z = slot(ctx, SL_Z);
         {
             GDM_TIMED(ctx, "refine64");
-            hipLaunchKernelGGL(k_z64_to_split, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Z64, Z);
+            hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, P.tot2 / 4, Z64, hl(Z));
         }
         GDM_LAUNCH_CHECK(ctx);
         GDM_TRY(gemm64_core<double>(ctx, s64, Z64, F, "refine64"));   // V = s[core,:] Z
