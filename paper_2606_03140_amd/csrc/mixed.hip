@@ -206,19 +206,26 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
 
 // ------------------------------------------------------------ FP64 GEMM
 // C = alpha A B + beta Cin + gamma I on the padded P x P tiles, true product,
-// FP64 FMA.  64 x 64 output tile per workgroup, each thread a 4 x 4 block,
-// k-steps of 16 staged in LDS.  TA / TB: double or float.  SYM: the product
-// is symmetric (Z s Z, and Z E of commuting factors): launched on the upper
-// tiles only; the tile is staged in LDS and written with its mirror, the
-// lower half of a diagonal tile taken from its upper half, so C is exactly
-// symmetric (Cin must then be symmetric too).
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  64 x 64 output tile per
+// workgroup: four waves, each a 32 x 32 block of 2 x 2 MFMA tiles; k-steps of
+// 16 staged in LDS (A row-major [m][k], B [k][n]).  Lane layout of the
+// instruction (checked on the device): A lane l holds A[l % 16][l / 16], B
+// lane l holds B[l / 16][l % 16], accumulator register r of lane l holds
+// D[4 r + l / 16][l % 16].  TA / TB: double or float (converted when staged).
+// SYM: the product is symmetric (Z s Z, and Z E of commuting factors):
+// launched on the upper tiles only; the tile is staged in LDS and written with
+// its mirror, the lower half of a diagonal tile taken from its upper half, so
+// C is exactly symmetric (Cin must then be symmetric too).
+typedef double double4v __attribute__((ext_vector_type(4)));
+constexpr int kK64 = 16;
+
 template <typename TA, typename TB, bool SYM>
 __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
                                                const TA* __restrict__ A, const TB* __restrict__ B,
                                                const double* __restrict__ Cin, double* __restrict__ C,
                                                double alpha, double beta, double gamma) {
-    __shared__ double sA[16][64 + 1];   // sA[k][m]
-    __shared__ double sB[16][64 + 1];   // sB[k][n]
+    __shared__ double sA[64][kK64 + 1];
+    __shared__ double sB[kK64][64 + 1];
     __shared__ double sC[SYM ? 64 : 1][65];
     const int4 tl = tiles[blockIdx.x];
     if (tl.x < 0) return;
@@ -227,41 +234,46 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
     const int64_t base = d.off2;
     const int m0 = tl.y * 64, n0 = tl.z * 64;
     const int t = threadIdx.x;
-    const int tx = t & 15, ty = t >> 4;
-    double acc[4][4];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int k0 = 0; k0 < P; k0 += 16) {
+    const int lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int fr = lane & 15, fk = lane >> 4;
+    double4v acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = double4v{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < P; k0 += kK64) {
         __syncthreads();
-        for (int e = t; e < 16 * 64; e += 256) {
+        for (int e = t; e < 64 * kK64; e += 256) {
             const int r = e >> 4, k = e & 15;             // A: row m0+r, col k0+k
-            sA[k][r] = (double)A[base + (int64_t)(m0 + r) * P + k0 + k];
+            sA[r][k] = (double)A[base + (int64_t)(m0 + r) * P + k0 + k];
             const int kb = e >> 6, c = e & 63;            // B: row k0+kb, col n0+c
             sB[kb][c] = (double)B[base + (int64_t)(k0 + kb) * P + n0 + c];
         }
         __syncthreads();
-        for (int k = 0; k < 16; ++k) {
-            double a[4], b[4];
-            for (int i = 0; i < 4; ++i) a[i] = sA[k][ty * 4 + i];
-            for (int j = 0; j < 4; ++j) b[j] = sB[k][tx * 4 + j];
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int kk = 0; kk < kK64; kk += 4) {
+            double a[2], b[2];
+            for (int i = 0; i < 2; ++i) a[i] = sA[wm * 32 + i * 16 + fr][kk + fk];
+            for (int j = 0; j < 2; ++j) b[j] = sB[kk + fk][wn * 32 + j * 16 + fr];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     }
     if (!SYM) {
-        for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) {
-                const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
-                const int64_t idx = base + (int64_t)m * P + n;
-                double v = alpha * acc[i][j];
-                if (Cin) v += beta * Cin[idx];
-                if (m == n) v += gamma;
-                C[idx] = v;
-            }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m0 + wm * 32 + i * 16 + 4 * r + fk, n = n0 + wn * 32 + j * 16 + fr;
+                    const int64_t idx = base + (int64_t)m * P + n;
+                    double v = alpha * acc[i][j][r];
+                    if (Cin) v += beta * Cin[idx];
+                    if (m == n) v += gamma;
+                    C[idx] = v;
+                }
         return;
     }
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) sC[ty * 4 + i][tx * 4 + j] = acc[i][j];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 4; ++r) sC[wm * 32 + i * 16 + 4 * r + fk][wn * 32 + j * 16 + fr] = acc[i][j][r];
     __syncthreads();
     const bool diag = tl.y == tl.z;
     for (int pass = 0; pass < (diag ? 1 : 2); ++pass)
