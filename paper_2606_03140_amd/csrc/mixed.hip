@@ -30,8 +30,8 @@ typedef float float4v __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int kTile = 64;       // output tile edge per workgroup
-constexpr int kK = 32;          // k-step (one MFMA k)
-constexpr int kLdsRow = kK + 8; // padded LDS row (halves)
+constexpr int kK = 64;          // k-step per LDS stage (two MFMA k-steps of 32)
+constexpr int kLdsRow = kK + 8; // padded LDS row (halves): 144 B, conflict-free MFMA operand reads
 constexpr int kGemmThreads = 256;
 constexpr int kXcds = 8;        // workgroup b is dispatched to XCD b mod 8
 constexpr float kLoScale = 2048.0f;            // 2^11
@@ -52,7 +52,7 @@ struct GemmArgs {
     int sym;             // tiles cover i <= j only; results mirrored (exactly symmetric output)
 };
 
-__device__ __forceinline__ void store_split(const SplitMat& m, int64_t idx, float v) {
+__device__ __forceinline__ void store_split(SplitMat m, int64_t idx, float v) {
     if (m.f) m.f[idx] = v;
     if (m.hi) {
         _Float16 h = (_Float16)v;
@@ -63,17 +63,25 @@ __device__ __forceinline__ void store_split(const SplitMat& m, int64_t idx, floa
 
 // Tile list entries: (subgraph, tile row, tile col).  Each workgroup forms a
 // 64 x 64 output tile with four waves (2 x 2 blocks of 32 x 32, each 2 x 2
-// MFMA 16x16x32 tiles, three products per k-step).  The next k-step is
-// prefetched into registers while the current one is multiplied; the result
-// is staged in LDS and written as coalesced rows, for the tile and, in
-// symmetric mode, for its mirror image.
+// MFMA 16x16x32 tiles, three products per k-step).  Operands move through
+// LDS in k-slabs of 64 (each thread carries two 16-byte row segments per
+// operand array; a row segment of 128 B is read by 8 consecutive lanes); the
+// next slab is prefetched into registers while the current one is
+// multiplied.  The accumulator register r of lane l holds row 4 r + l / 16,
+// column l % 16 of its 16 x 16 tile.  Epilogue: the tile is staged in LDS
+// (row stride 68 floats: conflict-free writes from the accumulator layout and
+// 16-byte row reads) and written as coalesced rows; in symmetric mode the
+// mirror image of an off-diagonal tile is written straight from registers,
+// where the accumulator layout already holds four consecutive elements of a
+// mirrored row per lane.
 constexpr int kOperandLds = 4 * kTile * kLdsRow * 2;        // bytes of the four operand tiles
-constexpr int kOutLds = kTile * (kTile + 1) * 4;             // bytes of the staged output tile
+constexpr int kOutRow = kTile + 4;                           // staged output row stride (floats)
+constexpr int kOutLds = kTile * kOutRow * 4;                 // bytes of the staged output tile
 constexpr int kGemmLds = kOperandLds > kOutLds ? kOperandLds : kOutLds;
 
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void store4(const SplitMat& m, int64_t idx, float4 v) {
+__device__ __forceinline__ void store4(SplitMat m, int64_t idx, float4 v) {
     if (m.f) *(float4*)(m.f + idx) = v;
     if (m.hi) {
         half4 h, l;
@@ -89,7 +97,7 @@ __device__ __forceinline__ void store4(const SplitMat& m, int64_t idx, float4 v)
 }
 
 // x = hi + 2^-11 lo for four consecutive elements
-__device__ __forceinline__ float4 load4(const SplitMat& m, int64_t idx) {
+__device__ __forceinline__ float4 load4(SplitMat m, int64_t idx) {
     if (m.f) return *(const float4*)(m.f + idx);
     const half4 h = *(const half4*)(m.hi + idx);
     const half4 l = *(const half4*)(m.lo + idx);
@@ -104,7 +112,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
     _Float16* sAl = sAh + kTile * kLdsRow;
     _Float16* sBh = sAl + kTile * kLdsRow;
     _Float16* sBl = sBh + kTile * kLdsRow;
-    float* sC = (float*)lds;                    // reused after the k loop: [64][65]
+    float* sC = (float*)lds;                    // reused after the k loop: [64][kOutRow]
     const int4 tl = tiles[blockIdx.x];
     if (tl.x < 0) return;
     const SubDesc d = desc[tl.x];
@@ -114,92 +122,137 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int lr = t >> 2, lc = (t & 3) * 8;
-    const _Float16* gAh = g.A.hi + base + (int64_t)(m0 + lr) * P + lc;
-    const _Float16* gAl = g.A.lo + base + (int64_t)(m0 + lr) * P + lc;
-    const _Float16* gBh = g.B.hi + base + (int64_t)(n0 + lr) * P + lc;
-    const _Float16* gBl = g.B.lo + base + (int64_t)(n0 + lr) * P + lc;
+    // global -> LDS: rows lr and lr + 32 of the slab, columns lc .. lc + 7
+    const int lr = t >> 3, lc = (t & 7) * 8;
+    const int64_t rA = base + (int64_t)(m0 + lr) * P + lc;
+    const int64_t rB = base + (int64_t)(n0 + lr) * P + lc;
+    const int64_t r32 = (int64_t)32 * P;
     float4v acc_hh[2][2], acc_x[2][2];
+    #pragma unroll
     for (int i = 0; i < 2; ++i)
+        #pragma unroll
         for (int j = 0; j < 2; ++j) {
             acc_hh[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
             acc_x[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
         }
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    uint4 va = *(const uint4*)(gAh);
-    uint4 vb = *(const uint4*)(gAl);
-    uint4 vc = *(const uint4*)(gBh);
-    uint4 vd = *(const uint4*)(gBl);
+    uint4 v0, v1, v2, v3, v4, v5, v6, v7;
+    v0 = *(const uint4*)(g.A.hi + rA);
+    v1 = *(const uint4*)(g.A.hi + rA + r32);
+    v2 = *(const uint4*)(g.A.lo + rA);
+    v3 = *(const uint4*)(g.A.lo + rA + r32);
+    v4 = *(const uint4*)(g.B.hi + rB);
+    v5 = *(const uint4*)(g.B.hi + rB + r32);
+    v6 = *(const uint4*)(g.B.lo + rB);
+    v7 = *(const uint4*)(g.B.lo + rB + r32);
     for (int k0 = 0; k0 < P; k0 += kK) {
         __syncthreads();
-        *(uint4*)(sAh + lr * kLdsRow + lc) = va;
-        *(uint4*)(sAl + lr * kLdsRow + lc) = vb;
-        *(uint4*)(sBh + lr * kLdsRow + lc) = vc;
-        *(uint4*)(sBl + lr * kLdsRow + lc) = vd;
+        *(uint4*)(sAh + lr * kLdsRow + lc) = v0;
+        *(uint4*)(sAh + (lr + 32) * kLdsRow + lc) = v1;
+        *(uint4*)(sAl + lr * kLdsRow + lc) = v2;
+        *(uint4*)(sAl + (lr + 32) * kLdsRow + lc) = v3;
+        *(uint4*)(sBh + lr * kLdsRow + lc) = v4;
+        *(uint4*)(sBh + (lr + 32) * kLdsRow + lc) = v5;
+        *(uint4*)(sBl + lr * kLdsRow + lc) = v6;
+        *(uint4*)(sBl + (lr + 32) * kLdsRow + lc) = v7;
         __syncthreads();
         if (k0 + kK < P) {
-            va = *(const uint4*)(gAh + k0 + kK);
-            vb = *(const uint4*)(gAl + k0 + kK);
-            vc = *(const uint4*)(gBh + k0 + kK);
-            vd = *(const uint4*)(gBl + k0 + kK);
+            const int64_t o = k0 + kK;
+            v0 = *(const uint4*)(g.A.hi + rA + o);
+            v1 = *(const uint4*)(g.A.hi + rA + r32 + o);
+            v2 = *(const uint4*)(g.A.lo + rA + o);
+            v3 = *(const uint4*)(g.A.lo + rA + r32 + o);
+            v4 = *(const uint4*)(g.B.hi + rB + o);
+            v5 = *(const uint4*)(g.B.hi + rB + r32 + o);
+            v6 = *(const uint4*)(g.B.lo + rB + o);
+            v7 = *(const uint4*)(g.B.lo + rB + r32 + o);
         }
-        half8 ah[2], al[2], bh[2], bl[2];
-        for (int i = 0; i < 2; ++i) {
-            const int r = wm * 32 + i * 16 + fr;
-            ah[i] = *(const half8*)(sAh + r * kLdsRow + fk);
-            al[i] = *(const half8*)(sAl + r * kLdsRow + fk);
-        }
-        for (int j = 0; j < 2; ++j) {
-            const int c = wn * 32 + j * 16 + fr;
-            bh[j] = *(const half8*)(sBh + c * kLdsRow + fk);
-            bl[j] = *(const half8*)(sBl + c * kLdsRow + fk);
-        }
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) {
-                acc_hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
-                acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc_x[i][j], 0, 0, 0);
-                acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc_x[i][j], 0, 0, 0);
+        #pragma unroll
+        for (int ks = 0; ks < kK; ks += 32) {
+            half8 ah[2], al[2], bh[2], bl[2];
+            #pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int r = wm * 32 + i * 16 + fr;
+                ah[i] = *(const half8*)(sAh + r * kLdsRow + ks + fk);
+                al[i] = *(const half8*)(sAl + r * kLdsRow + ks + fk);
             }
+            #pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int c = wn * 32 + j * 16 + fr;
+                bh[j] = *(const half8*)(sBh + c * kLdsRow + ks + fk);
+                bl[j] = *(const half8*)(sBl + c * kLdsRow + ks + fk);
+            }
+            #pragma unroll
+            for (int i = 0; i < 2; ++i)
+                #pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc_hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
+                    acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc_x[i][j], 0, 0, 0);
+                    acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc_x[i][j], 0, 0, 0);
+                }
+        }
     }
     __syncthreads();
+    const int gq = lane >> 4;                   // accumulator row group
+    #pragma unroll
     for (int i = 0; i < 2; ++i)
+        #pragma unroll
         for (int j = 0; j < 2; ++j)
+            #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int ml = wm * 32 + i * 16 + (lane >> 4) * 4 + r;
-                const int nl = wn * 32 + j * 16 + (lane & 15);
-                sC[ml * (kTile + 1) + nl] = acc_hh[i][j][r] + kLoInv * acc_x[i][j][r];
+                const int ml = wm * 32 + i * 16 + 4 * gq + r;
+                const int nl = wn * 32 + j * 16 + fr;
+                sC[ml * kOutRow + nl] = acc_hh[i][j][r] + kLoInv * acc_x[i][j][r];
             }
     __syncthreads();
-    // Rows of the tile (and, for off-diagonal symmetric tiles, of its mirror),
-    // four floats per lane, 16 lanes per 64-wide row: coalesced rows.  In a
-    // diagonal symmetric tile, (m, n) with m > n takes the value of (n, m).
     const bool diag_tile = tl.y == tl.z;
-    const int npass = (g.sym && !diag_tile) ? 2 : 1;
-    const int c4 = (t & 15) * 4;
     const bool has_e = g.E.f || g.E.hi;
-    for (int pass = 0; pass < npass; ++pass)
-        for (int rb = 0; rb < kTile; rb += kGemmThreads / 16) {
-            const int rl = rb + (t >> 4);
-            float x[4];
+    const bool out1 = g.O1.f || g.O1.hi, out2 = g.O2.f || g.O2.hi;
+    // rows of the tile, four floats per lane, 16 lanes per 64-wide row; in a
+    // diagonal symmetric tile, (m, n) with m > n takes the value of (n, m)
+    const int c4 = (t & 15) * 4;
+    for (int rb = 0; rb < kTile; rb += kGemmThreads / 16) {
+        const int rl = rb + (t >> 4);
+        const float4 xv = *(const float4*)(sC + rl * kOutRow + c4);
+        float x[4] = {xv.x, xv.y, xv.z, xv.w};
+        if (g.sym && diag_tile)
+            #pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (rl > c4 + q) x[q] = sC[(c4 + q) * kOutRow + rl];
+        const int gm = m0 + rl, gn = n0 + c4;
+        const int64_t idx = base + (int64_t)gm * P + gn;
+        if (out1) store4(g.O1, idx, make_float4(x[0], x[1], x[2], x[3]));
+        if (out2) {
+            const float4 e = has_e ? load4(g.E, idx) : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float ev[4] = {e.x, e.y, e.z, e.w};
+            float o[4];
+            #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int cl = c4 + q;
-                if (pass == 1) x[q] = sC[cl * (kTile + 1) + rl];
-                else if (g.sym && diag_tile && rl > cl) x[q] = sC[cl * (kTile + 1) + rl];
-                else x[q] = sC[rl * (kTile + 1) + cl];
+                o[q] = g.alpha * x[q] + g.beta * ev[q];
+                if (gm == gn + q) o[q] += g.gamma;
             }
-            const int gm = (pass == 0 ? m0 : n0) + rl;
-            const int gn = (pass == 0 ? n0 : m0) + c4;
+            store4(g.O2, idx, make_float4(o[0], o[1], o[2], o[3]));
+        }
+    }
+    if (!g.sym || diag_tile) return;
+    // mirror image of an off-diagonal tile from registers: register r of lane
+    // l is element (4 gq + r, fr) of its 16 x 16 block, i.e. element
+    // (fr, 4 gq + r) of the mirrored block: four consecutive columns of row fr
+    #pragma unroll
+    for (int i = 0; i < 2; ++i)
+        #pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            float x[4];
+            #pragma unroll
+            for (int r = 0; r < 4; ++r) x[r] = acc_hh[i][j][r] + kLoInv * acc_x[i][j][r];
+            const int gm = n0 + wn * 32 + j * 16 + fr;
+            const int gn = m0 + wm * 32 + i * 16 + 4 * gq;
             const int64_t idx = base + (int64_t)gm * P + gn;
-            if (g.O1.f || g.O1.hi) store4(g.O1, idx, make_float4(x[0], x[1], x[2], x[3]));
-            if (g.O2.f || g.O2.hi) {
-                float4 e = has_e ? load4(g.E, idx) : make_float4(0.f, 0.f, 0.f, 0.f);
-                const float ev[4] = {e.x, e.y, e.z, e.w};
-                float o[4];
-                for (int q = 0; q < 4; ++q) {
-                    o[q] = g.alpha * x[q] + g.beta * ev[q];
-                    if (gm == gn + q) o[q] += g.gamma;
-                }
-                store4(g.O2, idx, make_float4(o[0], o[1], o[2], o[3]));
+            if (out1) store4(g.O1, idx, make_float4(x[0], x[1], x[2], x[3]));
+            if (out2) {
+                const float4 e = has_e ? load4(g.E, idx) : make_float4(0.f, 0.f, 0.f, 0.f);
+                store4(g.O2, idx, make_float4(g.alpha * x[0] + g.beta * e.x, g.alpha * x[1] + g.beta * e.y,
+                                              g.alpha * x[2] + g.beta * e.z, g.alpha * x[3] + g.beta * e.w));
             }
         }
 }
