@@ -266,9 +266,9 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
 // lane l holds B[l / 16][l % 16], accumulator register r of lane l holds
 // D[4 r + l / 16][l % 16].  TA / TB: double or float (converted when staged).
 // SYM: the product is symmetric (Z s Z, and Z E of commuting factors):
-// launched on the upper tiles only; the tile is staged in LDS and written with
-// its mirror, the lower half of a diagonal tile taken from its upper half, so
-// C is exactly symmetric (Cin must then be symmetric too).
+// launched on the upper tiles only and written with its mirror, the lower
+// half of a diagonal tile taken from its upper half, so C is exactly
+// symmetric (Cin must then be symmetric too).
 typedef double double4v __attribute__((ext_vector_type(4)));
 constexpr int kK64 = 16;
 
@@ -279,7 +279,6 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
                                                double alpha, double beta, double gamma) {
     __shared__ double sA[64][kK64 + 1];
     __shared__ double sB[kK64][64 + 1];
-    __shared__ double sC[SYM ? 64 : 1][65];
     const int4 tl = tiles[blockIdx.x];
     if (tl.x < 0) return;
     const SubDesc d = desc[tl.x];
@@ -311,37 +310,33 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     }
-    if (!SYM) {
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j)
-                for (int r = 0; r < 4; ++r) {
-                    const int m = m0 + wm * 32 + i * 16 + 4 * r + fk, n = n0 + wn * 32 + j * 16 + fr;
+    // accumulator register r of lane l: element (4 r + fk, fr) of its 16 x 16
+    // block; rows of 16 consecutive columns per store.  SYM: the mirror image
+    // (fr, 4 r + fk) is stored too; on a diagonal tile only the upper half is
+    // taken, for both the element and its mirror, so C is exactly symmetric.
+    const bool diag = SYM && tl.y == tl.z;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm * 32 + i * 16 + 4 * r + fk, n = n0 + wn * 32 + j * 16 + fr;
+                const double x = acc[i][j][r];
+                if (!diag || m <= n) {
                     const int64_t idx = base + (int64_t)m * P + n;
-                    double v = alpha * acc[i][j][r];
+                    double v = alpha * x;
                     if (Cin) v += beta * Cin[idx];
                     if (m == n) v += gamma;
                     C[idx] = v;
                 }
-        return;
-    }
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-            for (int r = 0; r < 4; ++r) sC[wm * 32 + i * 16 + 4 * r + fk][wn * 32 + j * 16 + fr] = acc[i][j][r];
-    __syncthreads();
-    const bool diag = tl.y == tl.z;
-    for (int pass = 0; pass < (diag ? 1 : 2); ++pass)
-        for (int e = t; e < 64 * 64; e += 256) {
-            const int r = e >> 6, c = e & 63;
-            double a;
-            if (pass == 1 || (diag && r > c)) a = sC[c][r];
-            else a = sC[r][c];
-            const int m = (pass == 0 ? m0 : n0) + r, n = (pass == 0 ? n0 : m0) + c;
-            const int64_t idx = base + (int64_t)m * P + n;
-            double v = alpha * a;
-            if (Cin) v += beta * Cin[idx];
-            if (m == n) v += gamma;
-            C[idx] = v;
-        }
+                if (SYM && (!diag || m < n)) {
+                    const int64_t idx = base + (int64_t)n * P + m;
+                    double v = alpha * x;
+                    if (Cin) v += beta * Cin[idx];
+                    C[idx] = v;
+                }
+            }
 }
 
 // Z (FP16 hi/lo split) <- Z64, flat over every packed tile (padding included)
