@@ -281,70 +281,100 @@ __global__ void __launch_bounds__(64) k_steqr(const SubDesc* __restrict__ desc, 
 }
 
 // --------------------------------------- core rows through Hh and R
-// G holds 2*nc rows of length n in column-interleaved layout G[i*R + r]
-// (R = 2*nc rows), so a wave of row-threads touches consecutive addresses.
-// Rows 0..nc-1 start as I[core,:], rows nc..2nc-1 as (L^-T)[core,:].
-__global__ void __launch_bounds__(kThreads) k_core_vectors(const SubDesc* __restrict__ desc,
-                                                    const double* __restrict__ Lm, const double* __restrict__ A,
-                                                    const double* __restrict__ Tau,
-                                                    const double* __restrict__ RotC, const double* __restrict__ RotS,
-                                                    const int32_t* __restrict__ RotI,
-                                                    const int64_t* __restrict__ RotN, double* __restrict__ G,
-                                                    double* __restrict__ W) {
-    extern __shared__ double sv[];       // reflector v [n]
+// The 2*nc rows to be transformed (rows 0..nc-1 start as I[core,:], rows
+// nc..2nc-1 as (L^-T)[core,:]) are independent, so they are processed in
+// chunks held in LDS: block (s, c) takes rows c*RC .. of subgraph s, one lane
+// per row, row stride n + 1 doubles.  Each row is initialised (unit row, or
+// forward substitution L y = e_c), multiplied by the reflectors H_0 ...
+// H_{n-3} and the recorded QL rotations in order, and written to G in the
+// column-interleaved layout G[i*R + r] (R = 2*nc).
+constexpr int kRowLds = 144 * 1024;     // LDS bytes for one chunk of rows
+constexpr int kRowThreads = 64;
+
+__host__ __device__ inline int chunk_rows(int n) {
+    const int r = kRowLds / (8 * (n + 1));
+    return r > kRowThreads ? kRowThreads : (r < 1 ? 1 : r);
+}
+
+// row <- row - t (row . v) v on row[off .. off+m), v = (1, vk[1..m-1]); one
+// lane per row (act); the reflector entries are uniform loads
+__device__ __forceinline__ void reflect_row(double* row, bool act, int off, int m, const double* vk, double t) {
+    if (!act) return;
+    double* x = row + off;
+    double dot = x[0];
+    for (int i = 1; i < m; ++i) dot += x[i] * vk[i];
+    dot *= t;
+    x[0] -= dot;
+    for (int i = 1; i < m; ++i) x[i] -= dot * vk[i];
+}
+
+__global__ void __launch_bounds__(kRowThreads) k_core_rows(const SubDesc* __restrict__ desc,
+                                                      const double* __restrict__ Lm, const double* __restrict__ A,
+                                                      const double* __restrict__ Tau,
+                                                      const double* __restrict__ RotC,
+                                                      const double* __restrict__ RotS,
+                                                      const int32_t* __restrict__ RotI,
+                                                      const int64_t* __restrict__ RotN, double* __restrict__ G) {
+    extern __shared__ double rows[];
+    const SubDesc d = desc[blockIdx.x];
+    const int n = d.n, nc = d.nc, ld = d.ld, R = 2 * nc;
+    const int RC = chunk_rows(n), S = n + 1;
+    const int r0 = blockIdx.y * RC;
+    if (r0 >= R) return;
+    const int nr = min(RC, R - r0);
+    const int lane = threadIdx.x;
+    const bool act = lane < nr;
+    const int r = r0 + lane;
+    double* row = rows + (int64_t)(act ? lane : 0) * S;
+    const double* l = Lm + d.off2;
+    // initial rows: unit rows, or columns of L^-1 by forward substitution
+    // (y_k = 0 for k < c)
+    if (act)
+        for (int i = 0; i < n; ++i) row[i] = (r < nc && i == r) ? 1.0 : 0.0;
+    if (act && r >= nc) {
+        const int c = r - nc;
+        for (int i = c; i < n; ++i) {
+            const double* li = l + (int64_t)i * ld;
+            double acc = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) acc -= li[k] * row[k];
+            row[i] = acc / li[i];
+        }
+    }
+    const double* a = A + d.off2;
+    const double* tau = Tau + d.offv;
+    for (int k = 0; k < n - 2; ++k) {
+        const double t = tau[k];
+        if (t == 0.0) continue;
+        reflect_row(row, act, k + 1, n - k - 1, a + (int64_t)k * ld + k + 1, t);
+    }
+    // rotations in order
+    if (act) {
+        const int64_t nrot = RotN[blockIdx.x];
+        const double* rc = RotC + d.offr;
+        const double* rs = RotS + d.offr;
+        const int32_t* ri = RotI + d.offr;
+        for (int64_t q = 0; q < nrot; ++q) {
+            const int i = ri[q];
+            const double c = rc[q], sn = rs[q];
+            const double gi = row[i], gj = row[i + 1];
+            row[i] = c * gi - sn * gj;
+            row[i + 1] = sn * gi + c * gj;
+        }
+    }
+    double* g = G + 2 * d.offc;
+    for (int i = 0; i < n; ++i)
+        if (act) g[(int64_t)i * R + r] = row[i];
+}
+
+// w_k = sum_{a<nc} C[a][k] * (L_cc Q_core)[a][k]: the core weight of
+// eigenvector k, (C^T s C)_core diagonal contribution, with s C = L Q
+__global__ void __launch_bounds__(kThreads) k_core_weights(const SubDesc* __restrict__ desc,
+                                                          const double* __restrict__ Lm,
+                                                          const double* __restrict__ G, double* __restrict__ W) {
     const SubDesc d = desc[blockIdx.x];
     const int n = d.n, nc = d.nc, ld = d.ld, R = 2 * nc;
     const double* l = Lm + d.off2;
-    const double* a = A + d.off2;
-    const double* tau = Tau + d.offv;
-    double* g = G + 2 * d.offc;
-    // rows nc.. : Y = L^-1[:, 0:nc] by forward substitution, Y[i][c] -> G[i*R + nc + c]
-    for (int c = threadIdx.x; c < nc; c += kThreads) {
-        for (int i = 0; i < n; ++i) {
-            double acc = 0.0;
-            const double* li = l + (int64_t)i * ld;
-            for (int k = c; k < i; ++k) acc += li[k] * g[(int64_t)k * R + nc + c];
-            double b = (i == c) ? 1.0 : 0.0;
-            g[(int64_t)i * R + nc + c] = i < c ? 0.0 : (b - acc) / li[i];
-        }
-    }
-    for (int64_t e = threadIdx.x; e < (int64_t)n * nc; e += kThreads) {
-        int i = (int)(e / nc), r = (int)(e - (int64_t)i * nc);
-        g[(int64_t)i * R + r] = (i == r) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    // G <- G H_0 H_1 ... H_{n-3}
-    for (int k = 0; k < n - 2; ++k) {
-        const int m = n - k - 1;
-        for (int i = threadIdx.x; i < m; i += kThreads) sv[i] = i == 0 ? 1.0 : a[(int64_t)k * ld + (k + 1 + i)];
-        __syncthreads();
-        const double t = tau[k];
-        if (t != 0.0) {
-            for (int r = threadIdx.x; r < R; r += kThreads) {
-                double acc = 0.0;
-                for (int i = 0; i < m; ++i) acc += g[(int64_t)(k + 1 + i) * R + r] * sv[i];
-                acc *= t;
-                for (int i = 0; i < m; ++i) g[(int64_t)(k + 1 + i) * R + r] -= acc * sv[i];
-            }
-        }
-        __syncthreads();
-    }
-    // G <- G R (recorded rotations in order)
-    const int64_t nrot = RotN[blockIdx.x];
-    const double* rc = RotC + d.offr;
-    const double* rs = RotS + d.offr;
-    const int32_t* ri = RotI + d.offr;
-    for (int r = threadIdx.x; r < R; r += kThreads) {
-        for (int64_t q = 0; q < nrot; ++q) {
-            const int i = ri[q];
-            const double c = rc[q], s = rs[q];
-            double gi = g[(int64_t)i * R + r], gj = g[(int64_t)(i + 1) * R + r];
-            g[(int64_t)i * R + r] = c * gi - s * gj;
-            g[(int64_t)(i + 1) * R + r] = s * gi + c * gj;
-        }
-    }
-    __syncthreads();
-    // w_k = sum_{a<nc} C[a][k] * (L_cc Q_core)[a][k]
+    const double* g = G + 2 * d.offc;
     for (int k = threadIdx.x; k < n; k += kThreads) {
         double acc = 0.0;
         for (int aa = 0; aa < nc; ++aa) {
@@ -368,71 +398,65 @@ __device__ __forceinline__ double fermi_fp64(double x, double beta) {
     return 1.0 / (1.0 + e);
 }
 
-__global__ void __launch_bounds__(kThreads) k_dcore(const SubDesc* __restrict__ desc, const double* __restrict__ Lm,
-                                             const double* __restrict__ A, const double* __restrict__ Tau,
-                                             const double* __restrict__ RotC, const double* __restrict__ RotS,
-                                             const int32_t* __restrict__ RotI, const int64_t* __restrict__ RotN,
-                                             const double* __restrict__ G, const double* __restrict__ Lam,
-                                             double* __restrict__ U, double mu, double beta,
-                                             double* __restrict__ Dout, double* __restrict__ EigOut) {
-    extern __shared__ double sv[];
+// Core rows r < nc in LDS chunks as above: u = C[r,:] diag(f), then
+// u <- u R^T (rotations in reverse order, transposed), u <- u H_{n-3} ... H_0,
+// and D[r,:] from D L = u (columns from the right), written row-wise.
+__global__ void __launch_bounds__(kRowThreads) k_dcore(const SubDesc* __restrict__ desc,
+                                                  const double* __restrict__ Lm, const double* __restrict__ A,
+                                                  const double* __restrict__ Tau, const double* __restrict__ RotC,
+                                                  const double* __restrict__ RotS, const int32_t* __restrict__ RotI,
+                                                  const int64_t* __restrict__ RotN, const double* __restrict__ G,
+                                                  const double* __restrict__ Lam, double mu, double beta,
+                                                  double* __restrict__ Dout, double* __restrict__ EigOut) {
+    extern __shared__ double rows[];
     const SubDesc d = desc[blockIdx.x];
     const int n = d.n, nc = d.nc, ld = d.ld, R2 = 2 * nc;
+    const int RC = chunk_rows(n), S = n + 1;
+    const int r0 = blockIdx.y * RC;
+    if (r0 >= nc) return;
+    const int nr = min(RC, nc - r0);
+    const int lane = threadIdx.x;
+    const bool act = lane < nr;
+    const int r = r0 + lane;
+    double* row = rows + (int64_t)(act ? lane : 0) * S;
     const double* l = Lm + d.off2;
-    const double* a = A + d.off2;
-    const double* tau = Tau + d.offv;
     const double* g = G + 2 * d.offc;
-    double* u = U + d.offc;                  // [n][nc] interleaved
-    for (int64_t e = threadIdx.x; e < (int64_t)n * nc; e += kThreads) {
-        int k = (int)(e / nc), r = (int)(e - (int64_t)k * nc);
-        double f = fermi_fp64(Lam[d.offv + k] - mu, beta);
-        u[(int64_t)k * nc + r] = g[(int64_t)k * R2 + nc + r] * f;
-    }
-    if (EigOut)
-        for (int k = threadIdx.x; k < n; k += kThreads) EigOut[d.offe + k] = Lam[d.offv + k];
-    __syncthreads();
-    // U <- U R^T : rotations in reverse order, transposed
-    const int64_t nrot = RotN[blockIdx.x];
-    const double* rc = RotC + d.offr;
-    const double* rs = RotS + d.offr;
-    const int32_t* ri = RotI + d.offr;
-    for (int r = threadIdx.x; r < nc; r += kThreads) {
+    if (EigOut && blockIdx.y == 0)
+        for (int k = lane; k < n; k += kRowThreads) EigOut[d.offe + k] = Lam[d.offv + k];
+    for (int k = 0; k < n; ++k)
+        if (act) row[k] = g[(int64_t)k * R2 + nc + r] * fermi_fp64(Lam[d.offv + k] - mu, beta);
+    // rotations in reverse order, transposed
+    if (act) {
+        const int64_t nrot = RotN[blockIdx.x];
+        const double* rc = RotC + d.offr;
+        const double* rs = RotS + d.offr;
+        const int32_t* ri = RotI + d.offr;
         for (int64_t q = nrot - 1; q >= 0; --q) {
             const int i = ri[q];
-            const double c = rc[q], s = rs[q];
-            double ui = u[(int64_t)i * nc + r], uj = u[(int64_t)(i + 1) * nc + r];
-            u[(int64_t)i * nc + r] = c * ui + s * uj;
-            u[(int64_t)(i + 1) * nc + r] = -s * ui + c * uj;
+            const double c = rc[q], sn = rs[q];
+            const double ui = row[i], uj = row[i + 1];
+            row[i] = c * ui + sn * uj;
+            row[i + 1] = -sn * ui + c * uj;
         }
     }
-    __syncthreads();
-    // U <- U Hh^T = U H_{n-3} ... H_0
+    const double* a = A + d.off2;
+    const double* tau = Tau + d.offv;
     for (int k = n - 3; k >= 0; --k) {
-        const int m = n - k - 1;
-        for (int i = threadIdx.x; i < m; i += kThreads) sv[i] = i == 0 ? 1.0 : a[(int64_t)k * ld + (k + 1 + i)];
-        __syncthreads();
         const double t = tau[k];
-        if (t != 0.0) {
-            for (int r = threadIdx.x; r < nc; r += kThreads) {
-                double acc = 0.0;
-                for (int i = 0; i < m; ++i) acc += u[(int64_t)(k + 1 + i) * nc + r] * sv[i];
-                acc *= t;
-                for (int i = 0; i < m; ++i) u[(int64_t)(k + 1 + i) * nc + r] -= acc * sv[i];
-            }
-        }
-        __syncthreads();
+        if (t == 0.0) continue;
+        reflect_row(row, act, k + 1, n - k - 1, a + (int64_t)k * ld + k + 1, t);
     }
-    // D L = M, columns from the right:  D[:, j] = (M[:, j] - sum_{i>j} D[:, i] L[i][j]) / L[j][j]
-    double* out = Dout + d.offd;
-    for (int r = threadIdx.x; r < nc; r += kThreads) {
+    // D L = u: D_j = (u_j - sum_{i>j} D_i L_ij) / L_jj, from the last column
+    if (act)
         for (int j = n - 1; j >= 0; --j) {
-            double acc = u[(int64_t)j * nc + r];
-            for (int i = j + 1; i < n; ++i) acc -= u[(int64_t)i * nc + r] * l[(int64_t)i * ld + j];
-            double v = acc / l[(int64_t)j * ld + j];
-            u[(int64_t)j * nc + r] = v;
+            double acc = row[j];
+            for (int i = j + 1; i < n; ++i) acc -= row[i] * l[(int64_t)i * ld + j];
+            row[j] = acc / l[(int64_t)j * ld + j];
         }
-        for (int j = 0; j < n; ++j) out[(int64_t)r * n + j] = u[(int64_t)j * nc + r];
-    }
+    __syncthreads();
+    double* out = Dout + d.offd;
+    for (int rr = 0; rr < nr; ++rr)
+        for (int jj = lane; jj < n; jj += kRowThreads) out[(int64_t)(r0 + rr) * n + jj] = rows[(int64_t)rr * S + jj];
 }
 
 // ------------------------------------------------ chemical potential
@@ -587,10 +611,21 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
                        RotN, ctx->d_status);
     }
     GDM_LAUNCH_CHECK(ctx);
-    if ((rc = set_lds(ctx, (const void*)k_core_vectors, lds_n))) return rc;
-    { GDM_TIMED(ctx, "core_vectors");
-    hipLaunchKernelGGL(k_core_vectors, dim3(ns), dim3(kThreads), lds_n, ctx->stream, desc, Sd, A, Tau, RotC, RotS, RotI,
-                       RotN, G, Wt);
+    {
+        size_t lds_rows = 0;
+        int chunks = 1;
+        for (int s = 0; s < ns; ++s) {
+            const SubDesc& dd = P.desc[s];
+            const int rcn = chunk_rows(dd.n);
+            lds_rows = std::max(lds_rows, sizeof(double) * (size_t)rcn * (dd.n + 1));
+            chunks = std::max(chunks, (2 * dd.nc + rcn - 1) / rcn);
+        }
+        if ((rc = set_lds(ctx, (const void*)k_core_rows, lds_rows))) return rc;
+        GDM_TIMED(ctx, "core_vectors");
+        hipLaunchKernelGGL(k_core_rows, dim3(ns, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, Sd, A, Tau,
+                           RotC, RotS, RotI, RotN, G);
+        GDM_LAUNCH_CHECK(ctx);
+        hipLaunchKernelGGL(k_core_weights, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, Sd, G, Wt);
     }
     GDM_LAUNCH_CHECK(ctx);
     // chemical potential: multisection rounds
@@ -627,16 +662,23 @@ int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT
                      double* eig_out) {
     Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
-    const size_t lds_n = sizeof(double) * (size_t)P.max_n;
     int rc;
-    if ((rc = set_lds(ctx, (const void*)k_dcore, lds_n))) return rc;
+    size_t lds_rows = 0;
+    int chunks = 1;
+    for (int s = 0; s < P.n_sub; ++s) {
+        const SubDesc& dd = P.desc[s];
+        const int rcn = chunk_rows(dd.n);
+        lds_rows = std::max(lds_rows, sizeof(double) * (size_t)rcn * (dd.n + 1));
+        chunks = std::max(chunks, (dd.nc + rcn - 1) / rcn);
+    }
+    if ((rc = set_lds(ctx, (const void*)k_dcore, lds_rows))) return rc;
     { GDM_TIMED(ctx, "dcore");
-    hipLaunchKernelGGL(k_dcore, dim3(P.n_sub), dim3(kThreads), lds_n, ctx->stream, desc, (const double*)ctx->b[BUF_S].p,
-                       (const double*)ctx->b[BUF_A].p, (const double*)ctx->b[BUF_TAU].p,
+    hipLaunchKernelGGL(k_dcore, dim3(P.n_sub, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc,
+                       (const double*)ctx->b[BUF_S].p, (const double*)ctx->b[BUF_A].p, (const double*)ctx->b[BUF_TAU].p,
                        (const double*)ctx->b[BUF_ROTC].p, (const double*)ctx->b[BUF_ROTS].p,
                        (const int32_t*)ctx->b[BUF_ROTI].p, (const int64_t*)ctx->b[BUF_ROTN].p,
-                       (const double*)ctx->b[BUF_QC].p, (const double*)ctx->b[BUF_LAM].p, (double*)ctx->b[BUF_CC].p,
-                       mu, 1.0 / kT, D_core, eig_out);
+                       (const double*)ctx->b[BUF_QC].p, (const double*)ctx->b[BUF_LAM].p, mu, 1.0 / kT, D_core,
+                       eig_out);
     }
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
