@@ -23,6 +23,9 @@ defines, written in NumPy/SciPy with float64 throughout:
 * ewald.py   periodic point-charge Ewald potential with on-site Hubbard U.
 * scc.py     self-consistent-charge loop with linear mixing (the scaled-delta
              kernel of the Shadow MD section and SI section B).
+* response.py canonical first-order charge response (fractional
+             occupations), the low-rank preconditioned Krylov kernel and the
+             quasi-Newton SCF built on it (SI sections B and C).
 * learned.py per-atom radial descriptors and the per-species MLP with
              analytic gradients and Adam.
 

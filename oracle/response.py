@@ -1,0 +1,192 @@
+"""Charge response and the kernel-accelerated SCF (oracle; test infrastructure only).
+
+Response (SI section B: the directional derivatives that build the low-rank
+kernel, by quantum perturbation theory with fractional occupations).  A
+change dV of the atomic potentials changes the SCC Hamiltonian of SI
+section D by dH_ab = 1/2 s_ab (dV_I(a) + dV_J(b)).  In one subgraph, with
+the generalized eigenpairs of the solve (h C = s C diag(lam), C^T s C = I)
+and occupations f_k = f(lam_k - mu), first-order perturbation theory at
+fixed mu gives
+
+    dD = C (F o (C^T dH C)) C^T,   F_jk = (f_j - f_k) / (lam_j - lam_k),
+                                   F_jk = -beta f_j (1 - f_j) when lam_j = lam_k,
+
+and a shift dmu of the chemical potential adds dmu C diag(beta f (1 - f)) C^T
+(d f / d mu).  The electron count is held fixed (canonical response): dmu is
+chosen so that the collected charge changes sum to zero.  The charge
+response is the Mulliken map of the collected core rows,
+dq_I = 2 sum_{a in I} (dD s)_aa over core orbitals.
+
+Kernel and SCF (SI sections B and C).  With the residual f(n) = q0[n] - n
+and its Jacobian J (J v = dq[gamma v] - v, gamma the Coulomb map of
+ewald.coulomb_potential, which is linear in the charges), a preconditioner
+K0 ~ J^-1 and the orthonormalised preconditioned Krylov vectors
+v_1 ~ K0 f, v_{j+1} ~ K0 J v_j (each orthogonalised against the earlier
+ones), the low-rank kernel acting on r = K0 f is
+
+    (K0 J)^-1 r ~ sum_ij v_i M_ij f_vj^T r,  f_vj = K0 J v_j,  M = O^-1,  O_ij = f_vi^T f_vj,
+
+i.e. V c with c the least-squares solution of F_v c = r.  Vectors are added
+until || F_v c - r || <= rank_tol || r || or the rank cap is hit.  The
+quasi-Newton SCF step is n <- n - V c.  Here K0 = -I (the scaled-delta
+kernel -c I: the low-rank update does not depend on c).
+
+Pins (tests/test_oracle_response.py): the response equals central finite
+differences of the full solve (solve.solve_system with mu re-solved) for
+orthogonal and non-orthogonal models; the full-system susceptibility
+dq_I / dV_J is symmetric; the response conserves charge; on an affine
+charge map the quasi-Newton step with a full-rank kernel lands on the
+closed-form fixed point in one step; on a water box the SCF reaches the
+fixed point of the Anderson-mixed SCC.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .ewald import coulomb_potential
+from .model import N_ORB, TBModel, dense_hs
+from .solve import fermi, solve_system
+
+
+def delta_h(s: np.ndarray | None, dv_orb: np.ndarray) -> np.ndarray:
+    """dH_ab = 1/2 s_ab (dv_a + dv_b) (s = I when orthogonal)."""
+    if s is None:
+        return np.diag(dv_orb)
+    return 0.5 * s * (dv_orb[:, None] + dv_orb[None, :])
+
+
+def occupation_differences(lam: np.ndarray, f: np.ndarray, beta: float, tie: float = 1e-9) -> np.ndarray:
+    """F_jk = (f_j - f_k) / (lam_j - lam_k), and the derivative -beta f (1 - f)
+    where the eigenvalues coincide (|lam_j - lam_k| <= tie)."""
+    dl = lam[:, None] - lam[None, :]
+    df = f[:, None] - f[None, :]
+    deriv = -beta * f * (1.0 - f)
+    close = np.abs(dl) <= tie
+    F = np.where(close, 0.5 * (deriv[:, None] + deriv[None, :]), df / np.where(close, 1.0, dl))
+    return F
+
+
+def subgraph_response_rows(sol, s, dH: np.ndarray, mu: float, beta: float):
+    """(dq at fixed mu, d pop / d mu) over the core orbitals of one subgraph:
+    populations 2 (dD s)_aa of the core rows a."""
+    C = sol.C
+    f = fermi(sol.lam - mu, beta)
+    F = occupation_differences(sol.lam, f, beta)
+    H1 = C.T @ dH @ C
+    dD_core = C[:sol.nc] @ (F * H1) @ C.T
+    dmu_core = (C[:sol.nc] * (beta * f * (1.0 - f))) @ C.T
+    s_core = sol.s_core
+    return 2.0 * np.einsum("ab,ab->a", dD_core, s_core), 2.0 * np.einsum("ab,ab->a", dmu_core, s_core)
+
+
+def charge_response(pos, species, L, model: TBModel, subs, V_atom, dV, mu=None, sols=None):
+    """Canonical first-order change of the collected Mulliken charges for a
+    change dV (eV per atom) of the atomic potentials at potentials V_atom.
+    mu: the chemical potential of the unperturbed solve (None: found by
+    bisection as in solve_system).  Returns (dq [N], dmu, mu)."""
+    beta = model.beta
+    if sols is None or mu is None:
+        res = solve_system(pos, species, L, model, subs, V_atom=V_atom, workers=1)
+        sols = res.sols
+        mu = res.mu if mu is None else mu
+    dq_mu0 = np.zeros(len(species))
+    dq_mu1 = np.zeros(len(species))
+    for (atoms, ncore), sol in zip(subs, sols):
+        _, s = dense_hs(pos, species, L, model, atoms, V_atom)
+        norb = N_ORB[species[atoms]]
+        dv_orb = np.repeat(np.asarray(dV, dtype=np.float64)[atoms], norb)
+        p0, p1 = subgraph_response_rows(sol, s, delta_h(s, dv_orb), mu, beta)
+        owner = np.repeat(atoms[:ncore], N_ORB[species[atoms[:ncore]]])
+        np.add.at(dq_mu0, owner, p0)
+        np.add.at(dq_mu1, owner, p1)
+    # canonical: sum dq = 0 fixes dmu
+    t1 = dq_mu1.sum()
+    dmu = -dq_mu0.sum() / t1 if t1 != 0.0 else 0.0
+    return dq_mu0 + dmu * dq_mu1, dmu, mu
+
+
+def krylov_step(f: np.ndarray, jv, rank_tol: float = 1e-2, max_rank: int = 8):
+    """Quasi-Newton update -(K0 J)^-1 K0 f from the low-rank preconditioned
+    Krylov kernel with K0 = -I.  jv(v) returns J v.  Returns (dn, rank,
+    relative residual of the low-rank fit)."""
+    r = -f
+    nr = np.linalg.norm(r)
+    if nr == 0.0:
+        return np.zeros_like(f), 0, 0.0
+    V, FV = [], []
+    v = r / nr
+    rel = 1.0
+    c = np.zeros(0)
+    for _ in range(max_rank):
+        fv = -jv(v)                                   # K0 J v
+        V.append(v)
+        FV.append(fv)
+        Fm = np.stack(FV, axis=1)
+        O = Fm.T @ Fm                                 # O_ij = f_vi . f_vj
+        c = np.linalg.solve(O, Fm.T @ r)              # c = M F_v^T r
+        rel = float(np.linalg.norm(Fm @ c - r) / nr)
+        if rel <= rank_tol:
+            break
+        # next Krylov direction: f_v orthogonalised against the earlier v (twice)
+        w = fv.copy()
+        for _ in range(2):
+            for u in V:
+                w -= np.dot(u, w) * u
+        nw = np.linalg.norm(w)
+        if nw <= 1e-14 * np.linalg.norm(fv):
+            break
+        v = w / nw
+    dn = -np.stack(V, axis=1) @ c                     # n <- n - V c
+    return dn, len(V), rel
+
+
+def quasi_newton(charge_map, jacobian_vector, n0, tol: float = 1e-5, max_iter: int = 100,
+                 rank_tol: float = 1e-2, max_rank: int = 8):
+    """Kernel-accelerated SCF: n <- n - (K0 J)^-1 K0 f(n).  charge_map(n)
+    returns q0[n]; jacobian_vector(n, v) returns J(n) v.  Stops at RMS(f) <
+    tol.  Returns (q0 at the converged n, iterations, residual history,
+    ranks, converged)."""
+    n = np.array(n0, dtype=np.float64)
+    hist, ranks = [], []
+    for it in range(1, max_iter + 1):
+        q = charge_map(n)
+        f = q - n
+        rms = float(np.sqrt(np.mean(f * f)))
+        hist.append(rms)
+        if rms < tol:
+            return q, it, hist, ranks, True
+        dn, rank, _ = krylov_step(f, lambda v: jacobian_vector(n, v), rank_tol, max_rank)
+        ranks.append(rank)
+        n = n + dn
+    return n, max_iter, hist, ranks, False
+
+
+def scc_quasi_newton(pos, species, L, model: TBModel, subs, q_start=None, tol: float = 1e-5,
+                     max_iter: int = 100, rank_tol: float = 1e-2, max_rank: int = 8, eta=None, n_real: int = 2,
+                     k_max: int = 8, short_cut: float = np.inf):
+    """The SCC problem of scc.scc solved by the quasi-Newton iteration, the
+    Jacobian-vector products from charge_response.  Returns (q, iterations,
+    residual history, ranks)."""
+    U = np.asarray(model.hubbard_U)
+
+    def gamma(q):
+        return coulomb_potential(pos, species, q, L, U, eta=eta, n_real=n_real, k_max=k_max, short_cut=short_cut)
+
+    state = {}
+
+    def charge_map(n):
+        V = gamma(n)
+        res = solve_system(pos, species, L, model, subs, V_atom=V)
+        state.update(n=n, V=V, sols=res.sols, mu=res.mu)
+        return res.q
+
+    def jacobian_vector(n, v):
+        assert state["n"] is n
+        dq, _, _ = charge_response(pos, species, L, model, subs, state["V"], gamma(v), mu=state["mu"],
+                                   sols=state["sols"])
+        return dq - v
+
+    n0 = np.zeros(len(species)) if q_start is None else q_start
+    q, it, hist, ranks, _ = quasi_newton(charge_map, jacobian_vector, n0, tol=tol, max_iter=max_iter,
+                                         rank_tol=rank_tol, max_rank=max_rank)
+    return q, it, hist, ranks
