@@ -287,6 +287,63 @@ int gdm_scc_mix(gdm_ctx* ctx, int32_t n, double* n_vec, const double* q0, double
 int gdm_scc_anderson(gdm_ctx* ctx, int32_t n, double* n_vec, const double* q0, double mix,
                      int32_t depth, int32_t k, double* work, double* rms_out);
 
+/* ------------------------------- charge response and kernel-accelerated SCF */
+
+/* Keep the doubling history of the mixed-precision expansion (GDM_MIXED_F16)
+ * so that gdm_density_response can differentiate it: every later
+ * gdm_find_mu stores X_k and the inverse Y_k = (2 X_k^2 - 2 X_k + I)^-1 of
+ * each doubling of its last expansion pass, if the pass has at most
+ * max_doublings doublings (ceil(log2(beta * spectral radius)): 9 for
+ * kT = 0.1 eV and a 30 eV half-width).  Allocates 8 * max_doublings bytes
+ * per padded matrix element (P = 64 ceil(n/64), sum of P^2 over the
+ * subgraphs) plus the FP64 response workspace, now if a GDM_MIXED_F16 plan
+ * exists, else at the next gdm_plan; max_doublings = 0 stops recording and
+ * frees it.  0 <= max_doublings <= 40. */
+int gdm_set_response(gdm_ctx* ctx, int max_doublings);
+
+/* Canonical first-order response of the collected Mulliken charges to a
+ * change dV of the atomic potentials (SI section B: the directional
+ * derivatives of the charge residual that build the low-rank kernel, by
+ * perturbation theory at fractional occupation).  The SCC Hamiltonian
+ * changes by dH_ab = 1/2 S_ab (dV_I + dV_J); in each subgraph
+ * dD = d/dlambda Z f(Z^T (h + lambda dh) Z) Z^T at fixed mu, computed as the
+ * exact derivative of the recorded recursive expansion of the last
+ * gdm_find_mu (three split-FP16 products per doubling), plus the chemical
+ * potential shift dmu dD/dmu with dmu chosen so that the electron count
+ * 2 sum_s Tr_core[dD s] stays unchanged.  dq_I = 2 sum_{a in I} (dD S)_aa.
+ * Requires gdm_find_mu with GDM_MIXED_F16 after gdm_set_response with room
+ * for its doublings (GDM_E_STATE otherwise); the state it reads is that of
+ * the last find_mu and the last gdm_subgraph_density.  row_ptr/col/nnz/S as
+ * for gdm_mulliken_charges; dV, dq_out [n_atoms] FP64; *dmu_out (HOST,
+ * nullable) receives dmu.  The response is linear in dV.  Synchronises the
+ * stream. */
+int gdm_density_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
+                         const int32_t* row_ptr, const int32_t* col, int64_t nnz, const double* S,
+                         const double* dV, double* dq_out, double* dmu_out);
+
+/* Quasi-Newton SCF step with the low-rank preconditioned Krylov kernel (SI
+ * sections B and C): n <- n - (K0 J)^-1 K0 f(n), f = q0[n] - n, J = df/dn,
+ * K0 = -I, and (K0 J)^-1 on r = K0 f approximated by sum_ij v_i M_ij f_vj^T r
+ * over orthonormal preconditioned Krylov vectors v_0 ~ r,
+ * v_{j+1} ~ K0 J v_j, f_vj = K0 J v_j, M = (F_v^T F_v)^-1 (computed as the
+ * least-squares fit F_v c = r by QR).  One step:
+ *   gdm_krylov_begin: r and v_0 from n_vec and q0 = q0[n]; *rms_out (HOST)
+ *     = RMS(f).
+ *   for j = 0, 1, ...: the caller evaluates J v_j + v_j = dq_j, the charge
+ *     response to the potential of the charges v_j (v_j is work + n + j n),
+ *     and gdm_krylov_add fits it; *rel_out (HOST) = ||F_v c - r|| / ||r||,
+ *     *exhausted_out (HOST, nullable) = 1 when no new direction exists.
+ *     Stop when rel_out is small enough or j + 1 = max_rank.
+ *   gdm_krylov_apply: n_vec <- n_vec - V c with the first `rank` vectors.
+ * work: caller-owned FP64 [(2 max_rank + 1) n + max_rank^2 + max_rank + 1],
+ * kept over the calls of one step.  1 <= max_rank <= 16.  begin and add
+ * synchronise the stream. */
+int gdm_krylov_begin(gdm_ctx* ctx, int32_t n, const double* n_vec, const double* q0, int32_t max_rank,
+                     double* work, double* rms_out);
+int gdm_krylov_add(gdm_ctx* ctx, int32_t n, int32_t j, const double* dq, int32_t max_rank, double* work,
+                   double* rel_out, int32_t* exhausted_out);
+int gdm_krylov_apply(gdm_ctx* ctx, int32_t n, int32_t rank, int32_t max_rank, double* n_vec, const double* work);
+
 /* ------------------------------------- learned starting charges (MLP) */
 
 /* Per-atom radial descriptors for the charge network, FP64 [n_atoms, 32]:

@@ -83,6 +83,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                             C.POINTER(C.c_double), P, P])
     sig["gdm_scc_mix"] = (C.c_int, [P, I32, P, P, D, C.POINTER(C.c_double)])
     sig["gdm_scc_anderson"] = (C.c_int, [P, I32, P, P, D, I32, I32, P, C.POINTER(C.c_double)])
+    sig["gdm_set_response"] = (C.c_int, [P, C.c_int])
+    sig["gdm_density_response"] = (C.c_int, [P, C.POINTER(SystemT), C.POINTER(SubgraphsT), P, P, I64, P, P, P,
+                                             C.POINTER(C.c_double)])
+    sig["gdm_krylov_begin"] = (C.c_int, [P, I32, P, P, I32, P, C.POINTER(C.c_double)])
+    sig["gdm_krylov_add"] = (C.c_int, [P, I32, I32, P, I32, P, C.POINTER(C.c_double), C.POINTER(C.c_int32)])
+    sig["gdm_krylov_apply"] = (C.c_int, [P, I32, I32, I32, P, P])
     sig["gdm_descriptors"] = (C.c_int, [P, C.POINTER(SystemT), P, P, P])
     sig["gdm_feature_sums"] = (C.c_int, [P, I32, P, P, P])
     sig["gdm_feature_norm"] = (C.c_int, [P, P, P])
@@ -386,6 +392,43 @@ class Context:
         self._check(self.lib.gdm_scc_anderson(self.h, int(n_vec.numel()), _ptr(n_vec), _ptr(q0), mix, int(depth),
                                               int(k), _ptr(work), C.byref(rms)))
         return rms.value
+
+    # ---------------------------------------- response and quasi-Newton SCF
+    def set_response(self, max_doublings: int):
+        self._check(self.lib.gdm_set_response(self.h, int(max_doublings)))
+
+    def density_response(self, system: System, sg: Subgraphs, graph: Graph, S, dV, out=None):
+        """(dq, dmu): canonical charge response to potential change dV."""
+        dq = out if out is not None else torch.empty(system.n_atoms, dtype=torch.float64, device=self.dev)
+        dmu = C.c_double(0.0)
+        self._check(self.lib.gdm_density_response(self.h, C.byref(system.struct()), C.byref(sg.struct()),
+                                                  _ptr(graph.row_ptr), _ptr(graph.col), graph.nnz, _ptr(S),
+                                                  _ptr(dV), _ptr(dq), C.byref(dmu)))
+        return dq, dmu.value
+
+    @staticmethod
+    def krylov_work_size(n: int, max_rank: int) -> int:
+        return (2 * max_rank + 1) * n + max_rank * max_rank + max_rank + 1
+
+    @staticmethod
+    def krylov_vector(work, n: int, j: int):
+        return work[n + j * n: n + (j + 1) * n]
+
+    def krylov_begin(self, n_vec, q0, max_rank: int, work) -> float:
+        rms = C.c_double(0.0)
+        self._check(self.lib.gdm_krylov_begin(self.h, int(n_vec.numel()), _ptr(n_vec), _ptr(q0), int(max_rank),
+                                              _ptr(work), C.byref(rms)))
+        return rms.value
+
+    def krylov_add(self, n: int, j: int, dq, max_rank: int, work) -> tuple[float, bool]:
+        rel, ex = C.c_double(0.0), C.c_int32(0)
+        self._check(self.lib.gdm_krylov_add(self.h, int(n), int(j), _ptr(dq), int(max_rank), _ptr(work),
+                                            C.byref(rel), C.byref(ex)))
+        return rel.value, bool(ex.value)
+
+    def krylov_apply(self, n_vec, rank: int, max_rank: int, work):
+        self._check(self.lib.gdm_krylov_apply(self.h, int(n_vec.numel()), int(rank), int(max_rank), _ptr(n_vec),
+                                              _ptr(work)))
 
     # ------------------------------------------------------ learned guess
     def descriptors(self, system: System, graph: Graph, out=None):

@@ -13,9 +13,6 @@ int gdm_dm_graph(gdm_ctx* ctx, const gdm_system* sys, int mode, double alpha, do
                  const double* D_core, const int32_t* nbr_row_ptr, const int32_t* nbr_col,
                  const int32_t* union_row_ptr, const int32_t* union_col, int32_t* row_ptr, int32_t* col, int64_t cap,
                  int64_t* nnz_out);
-int gdm_launch_mulliken(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg, const int32_t* row_ptr,
-                        const int32_t* col, int64_t nnz, const double* S, const double* D_core, const double n0[2],
-                        double* q_out);
 
 int gdm_fail(gdm_ctx* ctx, int code, const char* fmt, ...) {
     char buf[512];
@@ -215,7 +212,8 @@ extern "C" int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
     // solvers on one context holds one solver's arena, not both
     static const int kFp64Only[] = {BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W, BUF_ROTC, BUF_ROTS,
                                     BUF_ROTI, BUF_ROTN, BUF_QC, BUF_MU, BUF_MUPART};
-    static const int kMixedOnly[] = {BUF_X_F, BUF_X_HI, BUF_X_LO, BUF_GERSH, BUF_TR, BUF_NDBL, BUF_TILES};
+    static const int kMixedOnly[] = {BUF_X_F, BUF_X_HI, BUF_X_LO, BUF_GERSH, BUF_TR, BUF_NDBL, BUF_TILES,
+                                     BUF_HIST_HI, BUF_HIST_LO, BUF_RESP};
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (precision == GDM_FP64_EIG)
         for (int s : kMixedOnly) gdm_buf_release(ctx, s);
@@ -317,6 +315,31 @@ extern "C" int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const g
     if (!sg || sg->n_sub != ctx->plan.n_sub || !row_ptr || (!col && nnz > 0) || !D_core || !n0 || !q_out)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_mulliken_charges: null argument or subgraph set differs from plan");
     return gdm_launch_mulliken(ctx, sys, sg, row_ptr, col, nnz, S, D_core, n0, q_out);
+}
+
+extern "C" int gdm_set_response(gdm_ctx* ctx, int max_doublings) {
+    if (!ctx) return GDM_E_ARG;
+    if (max_doublings < 0 || max_doublings > 40)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_set_response: max_doublings %d outside 0..40", max_doublings);
+    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->mixed_rec_cap = max_doublings;
+    ctx->mixed_rec_nd = -1;
+    return gdm_mixed_response_alloc(ctx);
+}
+
+extern "C" int gdm_density_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
+                                    const int32_t* row_ptr, const int32_t* col, int64_t nnz, const double* S,
+                                    const double* dV, double* dq_out, double* dmu_out) {
+    if (!ctx) return GDM_E_ARG;
+    int rc = check_system(ctx, sys, "gdm_density_response");
+    if (rc) return rc;
+    if ((rc = check_plan(ctx, sg, GDM_MIXED_F16, "gdm_density_response"))) return rc;
+    if (!row_ptr || (!col && nnz > 0) || !dV || !dq_out)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_density_response: null argument");
+    if (!ctx->solved || ctx->solved_precision != GDM_MIXED_F16)
+        return gdm_fail(ctx, GDM_E_STATE, "gdm_density_response: call gdm_find_mu (GDM_MIXED_F16) first");
+    if ((rc = gdm_mixed_response(ctx, sys, sg, row_ptr, col, nnz, S, dV, dq_out, dmu_out))) return rc;
+    return gdm_check(ctx);
 }
 
 extern "C" int gdm_profile(gdm_ctx* ctx, int enable) {

@@ -79,6 +79,12 @@ struct gdm_ctx {
     int mixed_nd = 0;
     double mixed_mu_pass = 0.0;
     double mixed_slope = 0.0;
+    double mixed_beta = 0.0;
+    // charge response: doubling history of the last expansion pass
+    int mixed_rec_cap = 0;       // doublings that fit the history buffer (0: not recorded)
+    int mixed_rec_nd = -1;       // doublings recorded by the last pass (-1: none)
+    double mixed_x0_slope = 0.0; // dX_0 / dh_perp of that pass (X_0 = I/2 - q (h_perp - mu I))
+    bool resp_v_ready = false;   // s[core,:] Z of the last find_mu is in the response buffer
     // tracing
     bool prof_on = false;
     std::vector<hipEvent_t> prof_pool;
@@ -111,6 +117,7 @@ enum {
     BUF_X_HI, BUF_X_LO, BUF_X_F, BUF_Y_HI, BUF_Y_LO, BUF_Y_F, BUF_T_HI, BUF_T_LO, BUF_T_F,
     BUF_Z_HI, BUF_Z_LO, BUF_Z_F, BUF_H_HI, BUF_H_LO, BUF_H_F, BUF_TR, BUF_GERSH, BUF_NDBL,
     BUF_TILES, BUF_PASS, BUF_EWALD, BUF_MIXPART,
+    BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_KRYLOV,
     BUF_COUNT_
 };
 
@@ -154,6 +161,13 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
 int gdm_mixed_plan(gdm_ctx* ctx);
 int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT,
                       double* D_core);
+int gdm_mixed_response_alloc(gdm_ctx* ctx);
+int gdm_mixed_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
+                       const int32_t* row_ptr, const int32_t* col, int64_t nnz, const double* S,
+                       const double* dV, double* dq, double* dmu);
+int gdm_launch_mulliken(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
+                        const int32_t* row_ptr, const int32_t* col, int64_t nnz, const double* S,
+                        const double* D_core, const double n0[2], double* q_out);
 
 // gather of principal submatrices (shared by both solvers)
 int gdm_launch_gather(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,

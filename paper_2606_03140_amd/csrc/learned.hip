@@ -535,6 +535,150 @@ __global__ void __launch_bounds__(kAT) k_anderson(int n, double* __restrict__ nv
     }
 }
 
+// Low-rank preconditioned Krylov kernel of the quasi-Newton SCF step with
+// K0 = -I (one block of 1024 threads over all n entries; the directional
+// derivatives come from the charge response, one call per rank):
+//   begin: r = K0 f = n - q0 (f = q0 - n), v_0 = r / |r|;
+//   add j: f_vj = K0 J v_j = v_j - dq_j (J v_j = dq_j - v_j); QR of
+//          [f_v0 .. f_vj] by modified Gram-Schmidt, one column per call
+//          (two passes; a numerically dependent column is dropped);
+//          c = argmin || F_v c - r ||, its relative residual; next direction
+//          v_{j+1} = f_vj orthogonalised against v_0 .. v_j (two passes);
+//   apply: n <- n - V c.
+// work (caller-owned, kept over the calls of one step): r [n], V [cap][n],
+// Q [cap][n], R [cap][cap], c [cap], |r|.
+constexpr int kMaxRank = 16;
+
+struct KrylovWork {
+    double *r, *V, *Q, *R, *c, *rn;
+};
+
+__device__ __forceinline__ KrylovWork krylov_work(double* w, int n, int cap) {
+    KrylovWork k;
+    k.r = w;
+    k.V = w + n;
+    k.Q = k.V + (int64_t)cap * n;
+    k.R = k.Q + (int64_t)cap * n;
+    k.c = k.R + cap * cap;
+    k.rn = k.c + cap;
+    return k;
+}
+
+__global__ void __launch_bounds__(kAT) k_krylov_begin(int n, const double* __restrict__ nv,
+                                                     const double* __restrict__ q0, int cap, double* work,
+                                                     double* __restrict__ out) {
+    __shared__ double red[kAT / 64];
+    const KrylovWork w = krylov_work(work, n, cap);
+    double s2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += kAT) {
+        const double r = nv[i] - q0[i];
+        w.r[i] = r;
+        s2 += r * r;
+    }
+    const double rn = sqrt(block_sum_kat(s2, red));
+    const double inv = rn > 0.0 ? 1.0 / rn : 0.0;
+    for (int i = threadIdx.x; i < n; i += kAT) w.V[i] = w.r[i] * inv;
+    if (threadIdx.x == 0) {
+        w.rn[0] = rn;
+        out[0] = sqrt(rn * rn / n);
+    }
+}
+
+__global__ void __launch_bounds__(kAT) k_krylov_add(int n, int j, const double* __restrict__ dq, int cap,
+                                                   double* work, double* __restrict__ out) {
+    __shared__ double red[kAT / 64];
+    __shared__ double g[kMaxRank];
+    const KrylovWork w = krylov_work(work, n, cap);
+    const double* vj = w.V + (int64_t)j * n;
+    double* qj = w.Q + (int64_t)j * n;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kAT) {
+        const double f = vj[i] - dq[i];
+        qj[i] = f;
+        s += f * f;
+    }
+    const double orig = sqrt(block_sum_kat(s, red));
+    // column j of R: projections on the earlier Q columns, twice
+    for (int l = 0; l < j; ++l)
+        if (threadIdx.x == 0) w.R[l * cap + j] = 0.0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int l = 0; l < j; ++l) {
+            const double* ql = w.Q + (int64_t)l * n;
+            double d = 0.0;
+            for (int i = threadIdx.x; i < n; i += kAT) d += ql[i] * qj[i];
+            const double rl = block_sum_kat(d, red);
+            for (int i = threadIdx.x; i < n; i += kAT) qj[i] -= rl * ql[i];
+            if (threadIdx.x == 0) w.R[l * cap + j] += rl;
+        }
+    double t = 0.0;
+    for (int i = threadIdx.x; i < n; i += kAT) t += qj[i] * qj[i];
+    const double rjj = sqrt(block_sum_kat(t, red));
+    const bool keep = rjj > 1e-12 * orig && rjj > 0.0;
+    const double inv = keep ? 1.0 / rjj : 0.0;
+    for (int i = threadIdx.x; i < n; i += kAT) qj[i] *= inv;
+    if (threadIdx.x == 0) w.R[j * cap + j] = keep ? rjj : 0.0;
+    // g = Q^T r, c = R^-1 g over the kept columns
+    for (int l = 0; l <= j; ++l) {
+        const double* ql = w.Q + (int64_t)l * n;
+        double d = 0.0;
+        for (int i = threadIdx.x; i < n; i += kAT) d += ql[i] * w.r[i];
+        const double gl = block_sum_kat(d, red);
+        if (threadIdx.x == 0) g[l] = gl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int l = j; l >= 0; --l) {
+            const double rll = w.R[l * cap + l];
+            if (rll == 0.0) {
+                w.c[l] = 0.0;
+                continue;
+            }
+            double v = g[l];
+            for (int m = l + 1; m <= j; ++m) v -= w.R[l * cap + m] * w.c[m];
+            w.c[l] = v / rll;
+        }
+    }
+    __syncthreads();
+    // relative residual || r - Q g || / || r ||
+    double e2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += kAT) {
+        double e = w.r[i];
+        for (int l = 0; l <= j; ++l) e -= g[l] * w.Q[(int64_t)l * n + i];
+        e2 += e * e;
+    }
+    const double res = sqrt(block_sum_kat(e2, red));
+    const double rn = w.rn[0];
+    if (threadIdx.x == 0) out[0] = rn > 0.0 ? res / rn : 0.0;
+    if (j + 1 >= cap) return;
+    // next Krylov direction
+    double* vn = w.V + (int64_t)(j + 1) * n;
+    for (int i = threadIdx.x; i < n; i += kAT) vn[i] = vj[i] - dq[i];
+    for (int pass = 0; pass < 2; ++pass)
+        for (int l = 0; l <= j; ++l) {
+            const double* vl = w.V + (int64_t)l * n;
+            double d = 0.0;
+            for (int i = threadIdx.x; i < n; i += kAT) d += vl[i] * vn[i];
+            const double p = block_sum_kat(d, red);
+            for (int i = threadIdx.x; i < n; i += kAT) vn[i] -= p * vl[i];
+        }
+    double u = 0.0;
+    for (int i = threadIdx.x; i < n; i += kAT) u += vn[i] * vn[i];
+    const double un = sqrt(block_sum_kat(u, red));
+    const double ui = un > 1e-14 * orig && un > 0.0 ? 1.0 / un : 0.0;
+    for (int i = threadIdx.x; i < n; i += kAT) vn[i] *= ui;
+    if (threadIdx.x == 0) out[1] = ui > 0.0 ? 0.0 : 1.0;     // 1: the Krylov space is exhausted
+}
+
+__global__ void k_krylov_apply(int n, int rank, int cap, const double* __restrict__ work, double* __restrict__ nv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* V = work + n;
+    const double* c = work + n + (int64_t)2 * cap * n + cap * cap;
+    double x = nv[i];
+    for (int l = 0; l < rank; ++l) x -= c[l] * V[(int64_t)l * n + i];
+    nv[i] = x;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------- host
@@ -717,5 +861,53 @@ extern "C" int gdm_scc_anderson(gdm_ctx* ctx, int32_t n, double* n_vec, const do
     GDM_LAUNCH_CHECK(ctx);
     GDM_HIP(ctx, hipMemcpyAsync(rms_out, out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GDM_OK;
+}
+
+extern "C" int gdm_krylov_begin(gdm_ctx* ctx, int32_t n, const double* n_vec, const double* q0, int32_t max_rank,
+                                double* work, double* rms_out) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !n_vec || !q0 || !work || !rms_out || max_rank < 1 || max_rank > kMaxRank)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_krylov_begin: bad argument");
+    bool ok = true;
+    double* out = (double*)gdm_buf(ctx, BUF_KRYLOV, sizeof(double) * 2, &ok);
+    if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_krylov_begin: workspace allocation failed");
+    hipLaunchKernelGGL(k_krylov_begin, dim3(1), dim3(kAT), 0, ctx->stream, n, n_vec, q0, max_rank, work, out);
+    GDM_LAUNCH_CHECK(ctx);
+    GDM_HIP(ctx, hipMemcpyAsync(rms_out, out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GDM_OK;
+}
+
+extern "C" int gdm_krylov_add(gdm_ctx* ctx, int32_t n, int32_t j, const double* dq, int32_t max_rank, double* work,
+                              double* rel_out, int32_t* exhausted_out) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !dq || !work || !rel_out || max_rank < 1 || max_rank > kMaxRank || j < 0 || j >= max_rank)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_krylov_add: bad argument");
+    bool ok = true;
+    double* out = (double*)gdm_buf(ctx, BUF_KRYLOV, sizeof(double) * 2, &ok);
+    if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_krylov_add: workspace allocation failed");
+    {
+        const int rc = gdm_fill_f64(ctx, out, 2, 0.0);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_krylov_add, dim3(1), dim3(kAT), 0, ctx->stream, n, j, dq, max_rank, work, out);
+    GDM_LAUNCH_CHECK(ctx);
+    double h[2];
+    GDM_HIP(ctx, hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *rel_out = h[0];
+    if (exhausted_out) *exhausted_out = h[1] != 0.0;
+    return GDM_OK;
+}
+
+extern "C" int gdm_krylov_apply(gdm_ctx* ctx, int32_t n, int32_t rank, int32_t max_rank, double* n_vec,
+                                const double* work) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !n_vec || !work || max_rank < 1 || max_rank > kMaxRank || rank < 1 || rank > max_rank)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_krylov_apply: bad argument");
+    hipLaunchKernelGGL(k_krylov_apply, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, rank, max_rank, work,
+                       n_vec);
+    GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }

@@ -380,16 +380,18 @@ __global__ void __launch_bounds__(256) k_trace_dot(const SubDesc* __restrict__ d
     }
 }
 
-// Gk <- G + kappa (G - G2) on the core rows (first-order mu correction of Z X)
-__global__ void __launch_bounds__(256) k_combine(const SubDesc* __restrict__ desc, const double* __restrict__ G,
-                                                const double* __restrict__ G2, double* __restrict__ Gk,
-                                                double kappa) {
+// Gk <- Base + kappa (G - G2) on the core rows: the first-order mu
+// correction of Z X (Base = G), or the chemical-potential term of the
+// canonical response (Base = Z dX); Gk may alias Base
+__global__ void __launch_bounds__(256) k_combine(const SubDesc* __restrict__ desc, const double* Base,
+                                                const double* __restrict__ G, const double* __restrict__ G2,
+                                                double* Gk, double kappa) {
     const SubDesc d = desc[blockIdx.x];
     const int P = d.ld, nc = d.nc;
     const int rows = (nc + 63) / 64 * 64;
     for (int64_t e = threadIdx.x; e < (int64_t)rows * P; e += 256) {
         const int64_t idx = d.off2 + e;
-        Gk[idx] = G[idx] + kappa * (G[idx] - G2[idx]);
+        Gk[idx] = Base[idx] + kappa * (G[idx] - G2[idx]);
     }
 }
 
@@ -583,6 +585,97 @@ __global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* 
     }
 }
 
+// ------------------------------------------------------- charge response
+// Potential change of every subgraph orbital, dv[offv + a] = dV[atom of a]
+// (atoms in subgraph order, orbital counts from orb_ptr); 0 on the padding.
+__global__ void __launch_bounds__(64) k_orb_dv(const SubDesc* __restrict__ desc, const int32_t* __restrict__ atoms_all,
+                                               const int32_t* __restrict__ orb_ptr, const double* __restrict__ dV,
+                                               double* __restrict__ dv) {
+    const SubDesc d = desc[blockIdx.x];
+    const int lane = threadIdx.x;
+    double* out = dv + d.offv;
+    int run = 0;
+    for (int base = 0; base < d.natoms; base += 64) {
+        const int i = base + lane;
+        const int g = i < d.natoms ? atoms_all[d.atom0 + i] : 0;
+        const int no = i < d.natoms ? orb_ptr[g + 1] - orb_ptr[g] : 0;
+        int incl = no;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        const double v = i < d.natoms ? dV[g] : 0.0;
+        for (int t = 0; t < no; ++t) {
+            const int a = run + incl - no + t;
+            if (a < d.ld) out[a] = v;
+        }
+        run += __shfl(incl, 63, 64);
+    }
+    for (int a = d.n + lane; a < d.ld; a += 64) out[a] = 0.0;
+}
+
+// dh_ab = 1/2 s_ab (dv_a + dv_b), the change of the SCC shift (s is the
+// identity for an orthogonal model); 0 on the padding
+__global__ void __launch_bounds__(kEw) k_dh(const SubDesc* __restrict__ desc, const double* __restrict__ S64,
+                                           const double* __restrict__ dv, SplitMat out) {
+    const SubDesc d = desc[blockIdx.x];
+    const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
+    if (r0 >= P) return;
+    const double* v = dv + d.offv;
+    const int q4 = P >> 2;
+    for (int e = threadIdx.x; e < 64 * q4; e += kEw) {
+        const int i = r0 + e / q4, j0 = (e % q4) * 4;
+        const int64_t idx = d.off2 + (int64_t)i * P + j0;
+        float w[4];
+        for (int k = 0; k < 4; ++k) {
+            const int j = j0 + k;
+            w[k] = (i < n && j < n) ? (float)(0.5 * S64[idx + k] * (v[i] + v[j])) : 0.f;
+        }
+        store4(out, idx, make_float4(w[0], w[1], w[2], w[3]));
+    }
+}
+
+// On the tile pair (I, J), (J, I) of an upper-tile list entry (I <= J):
+// dX2 = Pm + Pm^T and Dl = dX - dX2, both tiles of Pm staged in LDS
+// (row stride 65 floats: the transposed reads hit distinct banks).
+__global__ void __launch_bounds__(256) k_sym_pair(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
+                                                 SplitMat Pm, SplitMat dX, SplitMat dX2, SplitMat Dl) {
+    __shared__ float a[64][65];
+    __shared__ float b[64][65];
+    const int4 tl = tiles[blockIdx.x];
+    if (tl.x < 0) return;
+    const SubDesc d = desc[tl.x];
+    const int P = d.ld;
+    const int I0 = tl.y * 64, J0 = tl.z * 64;
+    const int t = threadIdx.x;
+    for (int e = t; e < 64 * 16; e += 256) {
+        const int r = e >> 4, c = (e & 15) * 4;
+        const float4 x = load4(Pm, d.off2 + (int64_t)(I0 + r) * P + J0 + c);
+        const float4 y = load4(Pm, d.off2 + (int64_t)(J0 + r) * P + I0 + c);
+        a[r][c] = x.x; a[r][c + 1] = x.y; a[r][c + 2] = x.z; a[r][c + 3] = x.w;
+        b[r][c] = y.x; b[r][c + 1] = y.y; b[r][c + 2] = y.z; b[r][c + 3] = y.w;
+    }
+    __syncthreads();
+    for (int e = t; e < 64 * 16; e += 256) {
+        const int r = e >> 4, c = (e & 15) * 4;
+        float s1[4], s2[4];
+        for (int k = 0; k < 4; ++k) {
+            s1[k] = a[r][c + k] + b[c + k][r];
+            s2[k] = b[r][c + k] + a[c + k][r];
+        }
+        const int64_t i1 = d.off2 + (int64_t)(I0 + r) * P + J0 + c;
+        const float4 x1 = load4(dX, i1);
+        store4(dX2, i1, make_float4(s1[0], s1[1], s1[2], s1[3]));
+        store4(Dl, i1, make_float4(x1.x - s1[0], x1.y - s1[1], x1.z - s1[2], x1.w - s1[3]));
+        if (I0 != J0) {
+            const int64_t i2 = d.off2 + (int64_t)(J0 + r) * P + I0 + c;
+            const float4 x2 = load4(dX, i2);
+            store4(dX2, i2, make_float4(s2[0], s2[1], s2[2], s2[3]));
+            store4(Dl, i2, make_float4(x2.x - s2[0], x2.y - s2[1], x2.z - s2[2], x2.w - s2[3]));
+        }
+    }
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------- host
@@ -615,6 +708,12 @@ static SplitMat slot(gdm_ctx* ctx, int k) {
 }
 
 static SplitMat none() { return SplitMat{nullptr, nullptr, nullptr}; }
+
+#define GDM_TRY(x)          \
+    do {                    \
+        int rc_ = (x);      \
+        if (rc_) return rc_; \
+    } while (0)
 
 // (subgraph, 64-row strip) grid of the elementwise kernels
 static dim3 strip_grid(const Plan& P) { return dim3((unsigned)P.n_sub, (unsigned)((P.max_n + 63) / 64)); }
@@ -676,6 +775,7 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
     gdm_buf(ctx, BUF_CC, sizeof(double) * (size_t)P.totc, &ok);
     gdm_buf(ctx, BUF_L, sizeof(double) * P.tot2 * 5, &ok);     // F/V, E/G, Z64, G2, D (FP64)
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_plan: mixed workspace allocation failed");
+    GDM_TRY(gdm_mixed_response_alloc(ctx));
     GDM_HIP(ctx, hipMemcpyAsync(dt, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, ctx->stream));
     ctx->mixed_tiles = (int64_t)nfull;
     ctx->mixed_tiles_sym = (int64_t)utiles.size();
@@ -712,13 +812,18 @@ static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, 
     return GDM_OK;
 }
 
-#define GDM_TRY(x)          \
-    do {                    \
-        int rc_ = (x);      \
-        if (rc_) return rc_; \
-    } while (0)
+// Doubling history for the charge response: X_k (which = 0), the input of
+// doubling k, and Y_k (which = 1), its inverse (2 X_k^2 - 2 X_k + I)^-1, as
+// FP16 hi/lo pairs.
+static SplitMat hist(gdm_ctx* ctx, int k, int which) {
+    const int64_t off = (int64_t)(2 * k + which) * ctx->plan.tot2;
+    return SplitMat{nullptr, (_Float16*)ctx->b[BUF_HIST_HI].p + off, (_Float16*)ctx->b[BUF_HIST_LO].p + off};
+}
 
-// One full recursive expansion at chemical potential mu; leaves X in SL_X and X^2 in SL_X2.
+// One full recursive expansion at chemical potential mu; leaves X in SL_X and
+// X^2 in SL_X2.  With a history buffer large enough for the nd doublings,
+// every X_k and Y_k is kept there (the products write into the history in
+// place of the working slots, so recording adds no traffic).
 static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, int* nd_out) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
@@ -727,32 +832,41 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
     nd = std::max(1, std::min(nd, 40));
     const double b = beta / std::ldexp(1.0, nd);
     *nd_out = nd;
+    const bool rec = ctx->mixed_rec_cap >= nd;
+    ctx->mixed_rec_nd = -1;
+    ctx->mixed_x0_slope = b / 4.0;
+    SplitMat X = slot(ctx, SL_X), X2 = slot(ctx, SL_X2), A = slot(ctx, SL_A), Rm = slot(ctx, SL_R);
+    const SplitMat Ya = slot(ctx, SL_Y), Yb = slot(ctx, SL_YI);
     {
         GDM_TIMED(ctx, "mixed_misc");
-        hipLaunchKernelGGL(k_x0, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP).f, slot(ctx, SL_X),
-                           mu, b);
+        hipLaunchKernelGGL(k_x0, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP).f,
+                           rec ? hist(ctx, 0, 0) : X, mu, b);
     }
     GDM_LAUNCH_CHECK(ctx);
     const float c0 = 48.0f / 17.0f, c1 = -32.0f / 17.0f;
-    SplitMat X = slot(ctx, SL_X), X2 = slot(ctx, SL_X2), A = slot(ctx, SL_A), Rm = slot(ctx, SL_R);
-    SplitMat Y = slot(ctx, SL_Y), Yn = slot(ctx, SL_YI);
+    const int ns = ctx->mixed_ns_inv;
     for (int it = 0; it < nd; ++it) {
+        const SplitMat Xk = rec ? hist(ctx, it, 0) : X;
         // X2 = X X ; A = 2 X2 - 2 X + I
-        GDM_TRY(gemm(ctx, X, X, hl(X2), hl(A), hl(X), 2.0f, -2.0f, 1.0f, "foe_gemm"));
+        GDM_TRY(gemm(ctx, Xk, Xk, hl(X2), hl(A), hl(Xk), 2.0f, -2.0f, 1.0f, "foe_gemm"));
         // Newton-Schulz inverse of A from Y0 = c0 I + c1 A:
         //   R = 2I - A Y0 = 2I - c0 A - c1 A A ;  Y1 = Y0 R = c0 R + c1 A R
         GDM_TRY(gemm(ctx, A, A, none(), hl(Rm), hl(A), -c1, -c0, 2.0f, "foe_gemm"));
+        SplitMat Y = (rec && ns == 1) ? hist(ctx, it, 1) : Ya;
         GDM_TRY(gemm(ctx, A, Rm, none(), hl(Y), hl(Rm), c1, c0, 0.0f, "foe_gemm"));
-        for (int k = 1; k < ctx->mixed_ns_inv; ++k) {
+        for (int k = 1; k < ns; ++k) {
             GDM_TRY(gemm(ctx, A, Y, none(), hl(Rm), none(), -1.0f, 0.0f, 2.0f, "foe_gemm"));
+            const SplitMat Yn = (rec && k == ns - 1) ? hist(ctx, it, 1) : (Y.hi == Ya.hi ? Yb : Ya);
             GDM_TRY(gemm(ctx, Y, Rm, hl(Yn), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
-            std::swap(Y, Yn);
+            Y = Yn;
         }
         // X <- X2 Y
-        GDM_TRY(gemm(ctx, X2, Y, it + 1 == nd ? X : hl(X), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
+        const SplitMat Xn = it + 1 == nd ? X : (rec ? hist(ctx, it + 1, 0) : hl(X));
+        GDM_TRY(gemm(ctx, X2, Y, Xn, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
     }
     // X^2 of the final X (for N'(mu) and the first-order mu correction)
     GDM_TRY(gemm(ctx, X, X, X2, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
+    if (rec) ctx->mixed_rec_nd = nd;
     return GDM_OK;
 }
 
@@ -826,6 +940,8 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
     ctx->mixed_gemms = 0;
     ctx->mixed_flops = 0.0;
     ctx->mixed_bytes = 0.0;
+    ctx->mixed_rec_nd = -1;
+    ctx->resp_v_ready = false;
     GDM_TRY(gdm_launch_gather(ctx, sys, sg, row_ptr, col, nnz, H, S, h64, s64, orth));
     {
         GDM_TIMED(ctx, "mixed_misc");
@@ -920,6 +1036,7 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
     ctx->mixed_nd = nd;
     ctx->mixed_mu_pass = mu;
     ctx->mixed_slope = beta * M;
+    ctx->mixed_beta = beta;
     // first-order correction mu* = mu + dmu, used only inside its linear range (|dmu| <= kT)
     double dmu = 0.0;
     if (std::fabs(n_e - N) > tol && beta * M > 0.0) {
@@ -943,7 +1060,7 @@ int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double k
     // D[core,:] = (G + kappa (G - G2)) Z,  G = Z[core,:] X, G2 = Z[core,:] X^2 of the last pass
     {
         GDM_TIMED(ctx, "dcore");
-        hipLaunchKernelGGL(k_combine, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, G, G2, Gk, kappa);
+        hipLaunchKernelGGL(k_combine, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, G, G, G2, Gk, kappa);
     }
     GDM_LAUNCH_CHECK(ctx);
     GDM_TRY(gemm64_core<double>(ctx, Gk, z64(ctx), Dp, "dcore"));
@@ -952,6 +1069,128 @@ int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double k
         hipLaunchKernelGGL(k_pack_core, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Dp, D_core);
     }
     GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+// ---------------------------------------------------------- charge response
+
+// History buffers for up to mixed_rec_cap doublings (X_k, Y_k: 8 B per padded
+// element each doubling) and the FP64 work of the response: s[core,:] Z and
+// the padded response rows (tot2 each), the packed response rows (totd) and
+// the orbital potentials (totv).  Released when recording is off.
+int gdm_mixed_response_alloc(gdm_ctx* ctx) {
+    const Plan& P = ctx->plan;
+    if (ctx->mixed_rec_cap <= 0 || P.precision != GDM_MIXED_F16 || P.n_sub <= 0) {
+        GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        for (int b : {BUF_HIST_HI, BUF_HIST_LO, BUF_RESP}) gdm_buf_release(ctx, b);
+        return GDM_OK;
+    }
+    bool ok = true;
+    const size_t halves = (size_t)2 * ctx->mixed_rec_cap * (size_t)P.tot2;
+    gdm_buf(ctx, BUF_HIST_HI, sizeof(_Float16) * halves, &ok);
+    gdm_buf(ctx, BUF_HIST_LO, sizeof(_Float16) * halves, &ok);
+    gdm_buf(ctx, BUF_RESP, sizeof(double) * (size_t)(2 * P.tot2 + P.totd + P.totv), &ok);
+    if (!ok) return gdm_fail(ctx, GDM_E_HIP, "charge response: history allocation failed");
+    return GDM_OK;
+}
+
+// Canonical first-order response of the collected charges to a change dV of
+// the atomic potentials, by differentiating the recorded expansion:
+//   dh = 1/2 s o (dv 1^T + 1 dv^T),  dh_perp = Z dh Z,  dX_0 = -q dh_perp,
+//   per doubling (X_{k+1} = X_k^2 Y_k, Y_k = (2 X_k^2 - 2 X_k + I)^-1):
+//     dX2 = X_k dX_k + dX_k X_k,
+//     dX_{k+1} = (dX2 - X_{k+1} dA_k) Y_k with dA_k = 2 dX2 - 2 dX_k,
+//              = (2 X_{k+1} (dX_k - dX2) + dX2) Y_k   (X_{k+1}, Y_k commute),
+// then dD[core,:] = Z[core,:] (dX + beta dmu (X - X^2)) Z with dmu from a
+// constant electron count, and dq = 2 diag(dD S) per atom.
+int gdm_mixed_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg, const int32_t* row_ptr,
+                       const int32_t* col, int64_t nnz, const double* S, const double* dV, double* dq, double* dmu) {
+    const Plan& P = ctx->plan;
+    const int nd = ctx->mixed_rec_nd;
+    if (nd < 1)
+        return gdm_fail(ctx, GDM_E_STATE,
+                        "gdm_density_response: the last expansion (%d doublings) was not recorded; call "
+                        "gdm_set_response with room for it before gdm_find_mu", ctx->mixed_nd);
+    const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
+    double* s64 = (double*)ctx->b[BUF_S].p;
+    double* R0 = (double*)ctx->b[BUF_RESP].p;   // s[core,:] Z
+    double* R1 = R0 + P.tot2;                    // padded response rows
+    double* dDp = R1 + P.tot2;                   // packed response rows
+    double* dv = dDp + P.totd;                   // orbital potentials
+    double* Gd = fp64_region(ctx, 4);
+    double* G = fp64_region(ctx, 1);
+    double* G2 = fp64_region(ctx, 3);
+    // the response GEMMs are not part of the expansion statistics
+    const int64_t gemms0 = ctx->mixed_gemms;
+    const double flops0 = ctx->mixed_flops, bytes0 = ctx->mixed_bytes;
+    if (!ctx->resp_v_ready) {
+        GDM_TRY(gemm64_core<double>(ctx, s64, z64(ctx), R0, "response"));
+        ctx->resp_v_ready = true;
+    }
+    {
+        GDM_TIMED(ctx, "response");
+        hipLaunchKernelGGL(k_orb_dv, dim3(P.n_sub), dim3(64), 0, ctx->stream, desc, sg->atoms, sys->orb_ptr, dV, dv);
+        GDM_LAUNCH_CHECK(ctx);
+        hipLaunchKernelGGL(k_dh, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, s64, dv, hl(slot(ctx, SL_H)));
+        GDM_LAUNCH_CHECK(ctx);
+    }
+    const SplitMat Z = slot(ctx, SL_Z), T = slot(ctx, SL_T), Pm = slot(ctx, SL_R), dX2 = slot(ctx, SL_Y2),
+                   Dl = slot(ctx, SL_Y);
+    SplitMat dX = slot(ctx, SL_A), dXn = slot(ctx, SL_YI);
+    GDM_TRY(gemm(ctx, Z, slot(ctx, SL_H), hl(T), none(), none(), 1.0f, 0.0f, 0.0f, "response", 0));
+    GDM_TRY(gemm(ctx, T, Z, none(), hl(dX), none(), (float)-ctx->mixed_x0_slope, 0.0f, 0.0f, "response"));
+    const int4* sym_tiles = (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles;
+    for (int k = 0; k < nd; ++k) {
+        const SplitMat Xk = hist(ctx, k, 0), Yk = hist(ctx, k, 1);
+        const SplitMat Xn = k + 1 == nd ? slot(ctx, SL_X) : hist(ctx, k + 1, 0);
+        GDM_TRY(gemm(ctx, Xk, dX, hl(Pm), none(), none(), 1.0f, 0.0f, 0.0f, "response", 0));
+        {
+            GDM_TIMED(ctx, "response");
+            hipLaunchKernelGGL(k_sym_pair, dim3((unsigned)ctx->mixed_tiles_sym), dim3(256), 0, ctx->stream, desc,
+                               sym_tiles, hl(Pm), hl(dX), hl(dX2), hl(Dl));
+        }
+        GDM_LAUNCH_CHECK(ctx);
+        GDM_TRY(gemm(ctx, Xn, Dl, none(), hl(T), hl(dX2), 2.0f, 1.0f, 0.0f, "response", 0));
+        GDM_TRY(gemm(ctx, T, Yk, k + 1 == nd ? slot(ctx, SL_Z2) : hl(dXn), none(), none(), 1.0f, 0.0f, 0.0f,
+                     "response", 0));
+        std::swap(dX, dXn);
+    }
+    ctx->mixed_gemms = gemms0;
+    ctx->mixed_flops = flops0;
+    ctx->mixed_bytes = bytes0;
+    // Gd = Z[core,:] dX at fixed mu, its electron count, and the canonical shift
+    GDM_TRY(gemm64_core<float>(ctx, z64(ctx), slot(ctx, SL_Z2).f, Gd, "response"));
+    double* part = (double*)ctx->b[BUF_TR].p;
+    {
+        GDM_TIMED(ctx, "response");
+        hipLaunchKernelGGL(k_trace_dot, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Gd, Gd, R0, part);
+        GDM_LAUNCH_CHECK(ctx);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kEw), 0, ctx->stream, P.n_sub, part,
+                           part + 2 * (size_t)P.n_sub);
+        GDM_LAUNCH_CHECK(ctx);
+    }
+    double h[2];
+    GDM_HIP(ctx, hipMemcpyAsync(h, part + 2 * (size_t)P.n_sub, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    // N'(mu) = beta M (slope of the last pass): dmu = -dN0 / (beta M), and the
+    // shift adds beta dmu Z(X - X^2)Z^T, i.e. kappa = beta dmu = -dN0 / M
+    const double slope = ctx->mixed_slope;
+    const double dm = slope > 0.0 ? -h[0] / slope : 0.0;
+    const double kappa = slope > 0.0 ? dm * ctx->mixed_beta : 0.0;
+    {
+        GDM_TIMED(ctx, "response");
+        hipLaunchKernelGGL(k_combine, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Gd, G, G2, Gd, kappa);
+    }
+    GDM_LAUNCH_CHECK(ctx);
+    GDM_TRY(gemm64_core<double>(ctx, Gd, z64(ctx), R1, "response"));
+    {
+        GDM_TIMED(ctx, "response");
+        hipLaunchKernelGGL(k_pack_core, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, R1, dDp);
+    }
+    GDM_LAUNCH_CHECK(ctx);
+    const double zero[2] = {0.0, 0.0};
+    GDM_TRY(gdm_launch_mulliken(ctx, sys, sg, row_ptr, col, nnz, S, dDp, zero, dq));
+    if (dmu) *dmu = dm;
     return GDM_OK;
 }
 

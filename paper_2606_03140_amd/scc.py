@@ -8,6 +8,10 @@ density solve at a global mu gives the Mulliken charges q0[n], and the
 update moves n towards the fixed point q0[n] = n: Anderson acceleration
 (memory 8, mixing 0.03, gdm_scc_anderson) by default, or the scaled-delta
 kernel K = -c I of the Shadow MD section (linear mixing, gdm_scc_mix).
+scc_quasi_newton is the kernel-accelerated SCF of SI section C: each step
+n <- n - (K0 J)^-1 K0 f(n) uses the low-rank preconditioned Krylov kernel
+(gdm_krylov_*), whose directional derivatives J v are charge responses of
+the mixed-precision solve (gdm_density_response) to the potential of v.
 Iteration stops when the RMS residual is below the tolerance.  Only
 orchestration lives here.
 """
@@ -18,7 +22,7 @@ from dataclasses import dataclass, field
 
 import torch
 
-from ._lib import FP64_EIG, Context, Graph, System, TBParams
+from ._lib import FP64_EIG, MIXED_F16, Context, Graph, System, TBParams
 from .pipeline import Partition, solve
 
 HARTREE_EV = 27.211386
@@ -95,4 +99,62 @@ def scc_loop(ctx: Context, system: System, tb: TBParams, part: Partition, kT: fl
     return SCCResult(q=n, iterations=max_iter, converged=False, history=hist, mu=mu)
 
 
-__all__ = ["HUBBARD_U", "slater_tau", "EwaldSetup", "ewald_setup", "SCCResult", "scc_loop"]
+@dataclass
+class QuasiNewtonResult(SCCResult):
+    ranks: list = field(default_factory=list)        # Krylov vectors per step
+    fits: list = field(default_factory=list)         # relative residual of each step's low-rank fit
+
+
+def scc_quasi_newton(ctx: Context, system: System, tb: TBParams, part: Partition, kT: float,
+                     q_start: torch.Tensor | None = None, tol: float = 1e-5, max_iter: int = 100,
+                     rank_tol: float = 1e-2, max_rank: int = 8, ewald: EwaldSetup | None = None,
+                     hubbard_U=HUBBARD_U, mu_guess: float = 0.0, plan: bool = True, screened: bool = True,
+                     max_doublings: int = 12) -> QuasiNewtonResult:
+    """Kernel-accelerated SCF on the mixed-precision path.  Per step: the
+    solve at H[n] (doubling history recorded), begin the Krylov kernel with
+    r = K0 f, then for j = 0, 1, ...: the potential of v_j, its charge
+    response dq_j, fit; stop the rank at a relative fit residual <= rank_tol
+    (or max_rank), then n <- n - V c.  Returns q0[n] at the first n with
+    RMS(q0[n] - n) < tol."""
+    ew = ewald if ewald is not None else ewald_setup(ctx, system)
+    tau = slater_tau(hubbard_U) if screened else None
+    N = system.n_atoms
+    n = torch.zeros(N, dtype=torch.float64, device=ctx.dev) if q_start is None \
+        else q_start.to(device=ctx.dev, dtype=torch.float64).clone()
+    V = torch.empty_like(n)
+    dV = torch.empty_like(n)
+    dq = torch.empty_like(n)
+    work = torch.empty(Context.krylov_work_size(N, max_rank), dtype=torch.float64, device=ctx.dev)
+    ctx.set_response(max_doublings)
+    hist, ranks, fits = [], [], []
+    mu = mu_guess
+    try:
+        for it in range(1, max_iter + 1):
+            ctx.ewald_potential(system, ew.graph, ew.rcut, ew.eta, ew.k_max, hubbard_U, n, tau=tau, out=V)
+            H, S = ctx.build_hs(system, tb, part.nbr, V)
+            sol = solve(ctx, system, part, H, S, kT, MIXED_F16, mu_guess=mu, plan=plan and it == 1)
+            mu = sol.mu
+            rms = ctx.krylov_begin(n, sol.q, max_rank, work)
+            hist.append(rms)
+            if rms < tol:
+                return QuasiNewtonResult(q=sol.q, iterations=it, converged=True, history=hist, mu=mu, ranks=ranks,
+                                         fits=fits)
+            rank, rel = 0, 1.0
+            for j in range(max_rank):
+                v = Context.krylov_vector(work, N, j)
+                ctx.ewald_potential(system, ew.graph, ew.rcut, ew.eta, ew.k_max, hubbard_U, v, tau=tau, out=dV)
+                ctx.density_response(system, part.sg, part.nbr, S, dV, out=dq)
+                rel, exhausted = ctx.krylov_add(N, j, dq, max_rank, work)
+                rank = j + 1
+                if rel <= rank_tol or exhausted:
+                    break
+            ranks.append(rank)
+            fits.append(rel)
+            ctx.krylov_apply(n, rank, max_rank, work)
+    finally:
+        ctx.set_response(0)
+    return QuasiNewtonResult(q=n, iterations=max_iter, converged=False, history=hist, mu=mu, ranks=ranks, fits=fits)
+
+
+__all__ = ["HUBBARD_U", "slater_tau", "EwaldSetup", "ewald_setup", "SCCResult", "scc_loop", "QuasiNewtonResult",
+           "scc_quasi_newton"]
