@@ -174,6 +174,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--paths", default="fp64,mixed")
+    ap.add_argument("--ns-z", type=int, default=0, help="coupled Newton-Schulz iterations for s^-1/2 (0: library "
+                                                        "default)")
+    ap.add_argument("--ns-inv", type=int, default=0, help="Newton-Schulz iterations per inverse in each doubling "
+                                                          "(0: library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
@@ -211,6 +215,7 @@ def main():
     log(f"[bench] partition: {part.sg.n_sub} subgraphs, n {n.min()}-{n.max()} (median {int(np.median(n))}), "
         f"setup {setup_s:.1f} s")
 
+    ctx.set_mixed_options(ns_z=args.ns_z, ns_inv=args.ns_inv)
     results = {}
     paths = [p for p in args.paths.split(",") if p]
     for path in paths:
@@ -281,7 +286,8 @@ def main():
                                f"orbitals, non-orthogonal, kT {wl['kT']} eV, {wl['grid'][0]}x{wl['grid'][1]}x"
                                f"{wl['grid'][2]} cores, tau {wl['tau']} ({wl['rounds']} graph rounds)",
                    "n_subgraphs": part.sg.n_sub, "orbitals_min": int(n.min()), "orbitals_median": int(np.median(n)),
-                   "orbitals_max": int(n.max()), "path": head},
+                   "orbitals_max": int(n.max()), "path": head,
+                   "mixed_options": {"ns_z": args.ns_z or 5, "ns_inv": args.ns_inv or 3}},
         "paths": {k: {"ms_per_step": v["ms_per_step"], "solves_per_s": v["solves_per_s"], "mu": v["mu"],
                       "electron_count": v["n_count"],
                       "kernels_ms_per_step": {kk: round(vv["ms_per_step"], 4) for kk, vv in v["kernels"].items()}}

@@ -219,7 +219,12 @@ int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
                          double* q_out);
 
 /* Options of the mixed-precision expansion (GDM_MIXED_F16): coupled
- * Newton-Schulz iterations for s^-1/2 (ns_z, default 7), Newton-Schulz
+ * Newton-Schulz iterations for s^-1/2 (ns_z, default 5: from the scaled
+ * start s/c, c the largest absolute row sum, the error falls as
+ * e -> 3/4 e^2 + 1/4 e^3 from e0 = 1 - lambda_min(s)/c, and one FP64
+ * refinement step then squares it; gdm_find_mu returns GDM_E_NOT_CONVERGED
+ * when some |(Z s Z - I)_ij| before that step exceeds 3e-3, i.e. when
+ * lambda_min(s)/c is too small for ns_z), Newton-Schulz
  * iterations per inverse in each doubling (ns_inv, default 3; the start has
  * error <= 1/17, so k iterations reach (1/17)^(2^k)), and the number of
  * expansion passes allowed while matching the electron count (max_passes,
@@ -322,27 +327,33 @@ int gdm_density_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
                          const double* dV, double* dq_out, double* dmu_out);
 
 /* Quasi-Newton SCF step with the low-rank preconditioned Krylov kernel (SI
- * sections B and C): n <- n - (K0 J)^-1 K0 f(n), f = q0[n] - n, J = df/dn,
- * K0 = -I, and (K0 J)^-1 on r = K0 f approximated by sum_ij v_i M_ij f_vj^T r
- * over orthonormal preconditioned Krylov vectors v_0 ~ r,
- * v_{j+1} ~ K0 J v_j, f_vj = K0 J v_j, M = (F_v^T F_v)^-1 (computed as the
- * least-squares fit F_v c = r by QR).  One step:
+ * sections B and C): n <- n - alpha (K0 J)^-1 K0 f(n), f = q0[n] - n,
+ * J = df/dn, K0 = -k0 I (the scaled-delta kernel), and (K0 J)^-1 on
+ * r = K0 f approximated by sum_ij v_i M_ij f_vj^T r over orthonormal
+ * preconditioned Krylov vectors v_0 ~ r, v_{j+1} ~ K0 J v_j, f_vj = K0 J v_j,
+ * M = (F_v^T F_v)^-1 (computed as the least-squares fit F_v c = r by QR).
+ * Optionally ("complete") the part of r the vectors do not fit, r - F_v c,
+ * is added as is, taking (K0 J)^-1 as the identity there (exact when
+ * K0 = J^-1; with a complete basis the remainder is zero).  One step:
  *   gdm_krylov_begin: r and v_0 from n_vec and q0 = q0[n]; *rms_out (HOST)
- *     = RMS(f).
+ *     = RMS(f).  k0 > 0.
  *   for j = 0, 1, ...: the caller evaluates J v_j + v_j = dq_j, the charge
  *     response to the potential of the charges v_j (v_j is work + n + j n),
  *     and gdm_krylov_add fits it; *rel_out (HOST) = ||F_v c - r|| / ||r||,
  *     *exhausted_out (HOST, nullable) = 1 when no new direction exists.
  *     Stop when rel_out is small enough or j + 1 = max_rank.
- *   gdm_krylov_apply: n_vec <- n_vec - V c with the first `rank` vectors.
- * work: caller-owned FP64 [(2 max_rank + 1) n + max_rank^2 + max_rank + 1],
+ *   gdm_krylov_apply: n_vec <- n_vec - alpha (V c + complete (r - F_v c))
+ *     with the first `rank` vectors; may be called again on a saved n_vec
+ *     with a smaller alpha (line search) until the next begin.
+ * work: caller-owned FP64 [(2 max_rank + 1) n + max_rank^2 + 2 max_rank + 2],
  * kept over the calls of one step.  1 <= max_rank <= 16.  begin and add
  * synchronise the stream. */
-int gdm_krylov_begin(gdm_ctx* ctx, int32_t n, const double* n_vec, const double* q0, int32_t max_rank,
-                     double* work, double* rms_out);
+int gdm_krylov_begin(gdm_ctx* ctx, int32_t n, const double* n_vec, const double* q0, double k0,
+                     int32_t max_rank, double* work, double* rms_out);
 int gdm_krylov_add(gdm_ctx* ctx, int32_t n, int32_t j, const double* dq, int32_t max_rank, double* work,
                    double* rel_out, int32_t* exhausted_out);
-int gdm_krylov_apply(gdm_ctx* ctx, int32_t n, int32_t rank, int32_t max_rank, double* n_vec, const double* work);
+int gdm_krylov_apply(gdm_ctx* ctx, int32_t n, int32_t rank, int32_t max_rank, double alpha, int32_t complete,
+                     double* n_vec, double* work);
 
 /* ------------------------------------- learned starting charges (MLP) */
 

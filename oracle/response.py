@@ -27,17 +27,25 @@ ones), the low-rank kernel acting on r = K0 f is
     (K0 J)^-1 r ~ sum_ij v_i M_ij f_vj^T r,  f_vj = K0 J v_j,  M = O^-1,  O_ij = f_vi^T f_vj,
 
 i.e. V c with c the least-squares solution of F_v c = r.  Vectors are added
-until || F_v c - r || <= rank_tol || r || or the rank cap is hit.  The
-quasi-Newton SCF step is n <- n - V c.  Here K0 = -I (the scaled-delta
-kernel -c I: the low-rank update does not depend on c).
+until || F_v c - r || <= rank_tol || r || or the rank cap is hit.  K0 is
+the scaled-delta kernel -c I.  With K0 ~ J^-1 the operator (K0 J)^-1 is
+close to the identity, so on the part of r that the vectors do not fit
+(r - F_v c, orthogonal to every f_v) it is taken as the identity: the step
+is n <- n - alpha (V c + (r - F_v c)), exact Newton on the fitted subspace
+and the plain preconditioned update K0 f on the rest (with a complete basis
+the remainder vanishes and the step is the paper's).  alpha = 1, halved
+while the residual norm does not decrease (at most 4 times), a
+backtracking line search for starts far from the fixed point.
 
 Pins (tests/test_oracle_response.py): the response equals central finite
 differences of the full solve (solve.solve_system with mu re-solved) for
 orthogonal and non-orthogonal models; the full-system susceptibility
 dq_I / dV_J is symmetric; the response conserves charge; on an affine
 charge map the quasi-Newton step with a full-rank kernel lands on the
-closed-form fixed point in one step; on a water box the SCF reaches the
-fixed point of the Anderson-mixed SCC.
+closed-form fixed point in one step, a rank-m step is the minimiser over
+the Krylov space, and the completed step adds exactly the unfitted
+remainder; on a water box the SCF reaches the fixed point of the
+Anderson-mixed SCC.
 """
 from __future__ import annotations
 
@@ -105,11 +113,13 @@ def charge_response(pos, species, L, model: TBModel, subs, V_atom, dV, mu=None, 
     return dq_mu0 + dmu * dq_mu1, dmu, mu
 
 
-def krylov_step(f: np.ndarray, jv, rank_tol: float = 1e-2, max_rank: int = 8):
+def krylov_step(f: np.ndarray, jv, rank_tol: float = 1e-2, max_rank: int = 8, k0: float = 1.0,
+                complete: bool = False):
     """Quasi-Newton update -(K0 J)^-1 K0 f from the low-rank preconditioned
-    Krylov kernel with K0 = -I.  jv(v) returns J v.  Returns (dn, rank,
-    relative residual of the low-rank fit)."""
-    r = -f
+    Krylov kernel with K0 = -k0 I; complete=True adds the unfitted remainder
+    -(r - F_v c).  jv(v) returns J v.  Returns (dn, rank, relative residual
+    of the low-rank fit)."""
+    r = -k0 * f
     nr = np.linalg.norm(r)
     if nr == 0.0:
         return np.zeros_like(f), 0, 0.0
@@ -118,7 +128,7 @@ def krylov_step(f: np.ndarray, jv, rank_tol: float = 1e-2, max_rank: int = 8):
     rel = 1.0
     c = np.zeros(0)
     for _ in range(max_rank):
-        fv = -jv(v)                                   # K0 J v
+        fv = -k0 * jv(v)                              # K0 J v
         V.append(v)
         FV.append(fv)
         Fm = np.stack(FV, axis=1)
@@ -136,34 +146,55 @@ def krylov_step(f: np.ndarray, jv, rank_tol: float = 1e-2, max_rank: int = 8):
         if nw <= 1e-14 * np.linalg.norm(fv):
             break
         v = w / nw
+    Fm = np.stack(FV, axis=1)
     dn = -np.stack(V, axis=1) @ c                     # n <- n - V c
+    if complete:
+        dn -= r - Fm @ c
     return dn, len(V), rel
 
 
 def quasi_newton(charge_map, jacobian_vector, n0, tol: float = 1e-5, max_iter: int = 100,
-                 rank_tol: float = 1e-2, max_rank: int = 8):
-    """Kernel-accelerated SCF: n <- n - (K0 J)^-1 K0 f(n).  charge_map(n)
-    returns q0[n]; jacobian_vector(n, v) returns J(n) v.  Stops at RMS(f) <
-    tol.  Returns (q0 at the converged n, iterations, residual history,
-    ranks, converged)."""
+                 rank_tol: float = 1e-2, max_rank: int = 8, k0: float = 1.0, complete: bool = False,
+                 backtrack: int = 0):
+    """Kernel-accelerated SCF: n <- n - alpha (K0 J)^-1 K0 f(n).  charge_map(n)
+    returns q0[n] (or raises ArithmeticError where it has no solution);
+    jacobian_vector(n, v) returns J(n) v at the n of the last accepted
+    charge_map call.  backtrack: halvings of alpha allowed while RMS(f) does
+    not decrease.  Stops at RMS(f) < tol.  Returns (q0 at the converged n,
+    iterations, residual history, ranks, converged)."""
     n = np.array(n0, dtype=np.float64)
     hist, ranks = [], []
+    q = charge_map(n)
+    f = q - n
+    rms = float(np.sqrt(np.mean(f * f)))
     for it in range(1, max_iter + 1):
-        q = charge_map(n)
-        f = q - n
-        rms = float(np.sqrt(np.mean(f * f)))
         hist.append(rms)
         if rms < tol:
             return q, it, hist, ranks, True
-        dn, rank, _ = krylov_step(f, lambda v: jacobian_vector(n, v), rank_tol, max_rank)
+        dn, rank, _ = krylov_step(f, lambda v: jacobian_vector(n, v), rank_tol, max_rank, k0, complete)
         ranks.append(rank)
-        n = n + dn
+        alpha = 1.0
+        for k in range(backtrack + 1):
+            n_try = n + alpha * dn
+            try:
+                q_try = charge_map(n_try)
+                f_try = q_try - n_try
+                rms_try = float(np.sqrt(np.mean(f_try * f_try)))
+            except ArithmeticError:
+                rms_try = np.inf
+            if rms_try < rms or k == backtrack:
+                break
+            alpha *= 0.5
+        if not np.isfinite(rms_try):
+            break
+        n, q, f, rms = n_try, q_try, f_try, rms_try
     return n, max_iter, hist, ranks, False
 
 
 def scc_quasi_newton(pos, species, L, model: TBModel, subs, q_start=None, tol: float = 1e-5,
-                     max_iter: int = 100, rank_tol: float = 1e-2, max_rank: int = 8, eta=None, n_real: int = 2,
-                     k_max: int = 8, short_cut: float = np.inf):
+                     max_iter: int = 100, rank_tol: float = 1e-2, max_rank: int = 8, k0: float = 0.1,
+                     complete: bool = True, backtrack: int = 4, eta=None, n_real: int = 2, k_max: int = 8,
+                     short_cut: float = np.inf):
     """The SCC problem of scc.scc solved by the quasi-Newton iteration, the
     Jacobian-vector products from charge_response.  Returns (q, iterations,
     residual history, ranks)."""
@@ -188,5 +219,6 @@ def scc_quasi_newton(pos, species, L, model: TBModel, subs, q_start=None, tol: f
 
     n0 = np.zeros(len(species)) if q_start is None else q_start
     q, it, hist, ranks, _ = quasi_newton(charge_map, jacobian_vector, n0, tol=tol, max_iter=max_iter,
-                                         rank_tol=rank_tol, max_rank=max_rank)
+                                         rank_tol=rank_tol, max_rank=max_rank, k0=k0, complete=complete,
+                                         backtrack=backtrack)
     return q, it, hist, ranks

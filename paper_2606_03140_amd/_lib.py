@@ -86,9 +86,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     sig["gdm_set_response"] = (C.c_int, [P, C.c_int])
     sig["gdm_density_response"] = (C.c_int, [P, C.POINTER(SystemT), C.POINTER(SubgraphsT), P, P, I64, P, P, P,
                                              C.POINTER(C.c_double)])
-    sig["gdm_krylov_begin"] = (C.c_int, [P, I32, P, P, I32, P, C.POINTER(C.c_double)])
+    sig["gdm_krylov_begin"] = (C.c_int, [P, I32, P, P, D, I32, P, C.POINTER(C.c_double)])
     sig["gdm_krylov_add"] = (C.c_int, [P, I32, I32, P, I32, P, C.POINTER(C.c_double), C.POINTER(C.c_int32)])
-    sig["gdm_krylov_apply"] = (C.c_int, [P, I32, I32, I32, P, P])
+    sig["gdm_krylov_apply"] = (C.c_int, [P, I32, I32, I32, D, I32, P, P])
     sig["gdm_descriptors"] = (C.c_int, [P, C.POINTER(SystemT), P, P, P])
     sig["gdm_feature_sums"] = (C.c_int, [P, I32, P, P, P])
     sig["gdm_feature_norm"] = (C.c_int, [P, P, P])
@@ -408,16 +408,16 @@ class Context:
 
     @staticmethod
     def krylov_work_size(n: int, max_rank: int) -> int:
-        return (2 * max_rank + 1) * n + max_rank * max_rank + max_rank + 1
+        return (2 * max_rank + 1) * n + max_rank * max_rank + 2 * max_rank + 2
 
     @staticmethod
     def krylov_vector(work, n: int, j: int):
         return work[n + j * n: n + (j + 1) * n]
 
-    def krylov_begin(self, n_vec, q0, max_rank: int, work) -> float:
+    def krylov_begin(self, n_vec, q0, max_rank: int, work, k0: float = 1.0) -> float:
         rms = C.c_double(0.0)
-        self._check(self.lib.gdm_krylov_begin(self.h, int(n_vec.numel()), _ptr(n_vec), _ptr(q0), int(max_rank),
-                                              _ptr(work), C.byref(rms)))
+        self._check(self.lib.gdm_krylov_begin(self.h, int(n_vec.numel()), _ptr(n_vec), _ptr(q0), float(k0),
+                                              int(max_rank), _ptr(work), C.byref(rms)))
         return rms.value
 
     def krylov_add(self, n: int, j: int, dq, max_rank: int, work) -> tuple[float, bool]:
@@ -426,9 +426,9 @@ class Context:
                                             C.byref(rel), C.byref(ex)))
         return rel.value, bool(ex.value)
 
-    def krylov_apply(self, n_vec, rank: int, max_rank: int, work):
-        self._check(self.lib.gdm_krylov_apply(self.h, int(n_vec.numel()), int(rank), int(max_rank), _ptr(n_vec),
-                                              _ptr(work)))
+    def krylov_apply(self, n_vec, rank: int, max_rank: int, work, alpha: float = 1.0, complete: bool = False):
+        self._check(self.lib.gdm_krylov_apply(self.h, int(n_vec.numel()), int(rank), int(max_rank), float(alpha),
+                                              int(bool(complete)), _ptr(n_vec), _ptr(work)))
 
     # ------------------------------------------------------ learned guess
     def descriptors(self, system: System, graph: Graph, out=None):

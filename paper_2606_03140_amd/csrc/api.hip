@@ -102,7 +102,10 @@ static int status_to_code(gdm_ctx* ctx, int st) {
     if (st == 0) return GDM_OK;
     if (st & GDM_STATUS_NOT_PD) return gdm_fail(ctx, GDM_E_NOT_PD, "a subgraph overlap matrix is not positive definite");
     if (st & GDM_STATUS_CAPACITY) return gdm_fail(ctx, GDM_E_CAPACITY, "a device-side record exceeded its capacity");
-    if (st & GDM_STATUS_NOT_CONVERGED) return gdm_fail(ctx, GDM_E_NOT_CONVERGED, "an iteration did not converge");
+    if (st & GDM_STATUS_NOT_CONVERGED) return gdm_fail(ctx, GDM_E_NOT_CONVERGED,
+                                                         "an iteration did not converge (mixed path: the inverse-"
+                                                         "overlap factor needs more Newton-Schulz iterations, "
+                                                         "gdm_set_mixed_options ns_z)");
     if (st & GDM_STATUS_NO_BRACKET) return gdm_fail(ctx, GDM_E_NO_BRACKET, "electron count outside the bracket");
     if (st & GDM_STATUS_NAN) return gdm_fail(ctx, GDM_E_NAN, "NaN produced");
     return gdm_fail(ctx, GDM_E_STATE, "unknown device status %d", st);

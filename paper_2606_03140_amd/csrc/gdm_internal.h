@@ -67,7 +67,7 @@ struct gdm_ctx {
     double mu_solved = 0.0;
     double kT_solved = 0.0;
     // mixed path: options and the state of the last find_mu
-    int mixed_ns_z = 7;          // coupled Newton-Schulz iterations for s^-1/2
+    int mixed_ns_z = 5;          // coupled Newton-Schulz iterations for s^-1/2
     int mixed_ns_inv = 3;        // Newton-Schulz iterations per inverse
     int mixed_max_passes = 10;   // expansion passes allowed for mu
     int64_t mixed_tiles = 0, mixed_tiles_sym = 0, mixed_tiles_core = 0;

@@ -536,21 +536,22 @@ __global__ void __launch_bounds__(kAT) k_anderson(int n, double* __restrict__ nv
 }
 
 // Low-rank preconditioned Krylov kernel of the quasi-Newton SCF step with
-// K0 = -I (one block of 1024 threads over all n entries; the directional
+// K0 = -k0 I (one block of 1024 threads over all n entries; the directional
 // derivatives come from the charge response, one call per rank):
-//   begin: r = K0 f = n - q0 (f = q0 - n), v_0 = r / |r|;
-//   add j: f_vj = K0 J v_j = v_j - dq_j (J v_j = dq_j - v_j); QR of
+//   begin: r = K0 f = k0 (n - q0) (f = q0 - n), v_0 = r / |r|;
+//   add j: f_vj = K0 J v_j = k0 (v_j - dq_j) (J v_j = dq_j - v_j); QR of
 //          [f_v0 .. f_vj] by modified Gram-Schmidt, one column per call
 //          (two passes; a numerically dependent column is dropped);
-//          c = argmin || F_v c - r ||, its relative residual; next direction
-//          v_{j+1} = f_vj orthogonalised against v_0 .. v_j (two passes);
-//   apply: n <- n - V c.
+//          g = Q^T r, c = R^-1 g = argmin || F_v c - r ||, its relative
+//          residual; next direction v_{j+1} = f_vj orthogonalised against
+//          v_0 .. v_j (two passes);
+//   apply: n <- n - alpha (V c + complete (r - Q g)).
 // work (caller-owned, kept over the calls of one step): r [n], V [cap][n],
-// Q [cap][n], R [cap][cap], c [cap], |r|.
+// Q [cap][n], R [cap][cap], c [cap], g [cap], |r|, k0.
 constexpr int kMaxRank = 16;
 
 struct KrylovWork {
-    double *r, *V, *Q, *R, *c, *rn;
+    double *r, *V, *Q, *R, *c, *g, *sc;
 };
 
 __device__ __forceinline__ KrylovWork krylov_work(double* w, int n, int cap) {
@@ -560,27 +561,30 @@ __device__ __forceinline__ KrylovWork krylov_work(double* w, int n, int cap) {
     k.Q = k.V + (int64_t)cap * n;
     k.R = k.Q + (int64_t)cap * n;
     k.c = k.R + cap * cap;
-    k.rn = k.c + cap;
+    k.g = k.c + cap;
+    k.sc = k.g + cap;
     return k;
 }
 
 __global__ void __launch_bounds__(kAT) k_krylov_begin(int n, const double* __restrict__ nv,
-                                                     const double* __restrict__ q0, int cap, double* work,
-                                                     double* __restrict__ out) {
+                                                     const double* __restrict__ q0, double k0, int cap,
+                                                     double* work, double* __restrict__ out) {
     __shared__ double red[kAT / 64];
     const KrylovWork w = krylov_work(work, n, cap);
     double s2 = 0.0;
     for (int i = threadIdx.x; i < n; i += kAT) {
-        const double r = nv[i] - q0[i];
-        w.r[i] = r;
-        s2 += r * r;
+        const double f = q0[i] - nv[i];
+        w.r[i] = -k0 * f;
+        s2 += f * f;
     }
-    const double rn = sqrt(block_sum_kat(s2, red));
+    const double fn = sqrt(block_sum_kat(s2, red));
+    const double rn = k0 * fn;
     const double inv = rn > 0.0 ? 1.0 / rn : 0.0;
     for (int i = threadIdx.x; i < n; i += kAT) w.V[i] = w.r[i] * inv;
     if (threadIdx.x == 0) {
-        w.rn[0] = rn;
-        out[0] = sqrt(rn * rn / n);
+        w.sc[0] = rn;
+        w.sc[1] = k0;
+        out[0] = fn / sqrt((double)n);
     }
 }
 
@@ -591,9 +595,10 @@ __global__ void __launch_bounds__(kAT) k_krylov_add(int n, int j, const double* 
     const KrylovWork w = krylov_work(work, n, cap);
     const double* vj = w.V + (int64_t)j * n;
     double* qj = w.Q + (int64_t)j * n;
+    const double k0 = w.sc[1];
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += kAT) {
-        const double f = vj[i] - dq[i];
+        const double f = k0 * (vj[i] - dq[i]);
         qj[i] = f;
         s += f * f;
     }
@@ -623,7 +628,10 @@ __global__ void __launch_bounds__(kAT) k_krylov_add(int n, int j, const double* 
         double d = 0.0;
         for (int i = threadIdx.x; i < n; i += kAT) d += ql[i] * w.r[i];
         const double gl = block_sum_kat(d, red);
-        if (threadIdx.x == 0) g[l] = gl;
+        if (threadIdx.x == 0) {
+            g[l] = gl;
+            w.g[l] = gl;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -647,12 +655,12 @@ __global__ void __launch_bounds__(kAT) k_krylov_add(int n, int j, const double* 
         e2 += e * e;
     }
     const double res = sqrt(block_sum_kat(e2, red));
-    const double rn = w.rn[0];
+    const double rn = w.sc[0];
     if (threadIdx.x == 0) out[0] = rn > 0.0 ? res / rn : 0.0;
     if (j + 1 >= cap) return;
     // next Krylov direction
     double* vn = w.V + (int64_t)(j + 1) * n;
-    for (int i = threadIdx.x; i < n; i += kAT) vn[i] = vj[i] - dq[i];
+    for (int i = threadIdx.x; i < n; i += kAT) vn[i] = k0 * (vj[i] - dq[i]);
     for (int pass = 0; pass < 2; ++pass)
         for (int l = 0; l <= j; ++l) {
             const double* vl = w.V + (int64_t)l * n;
@@ -669,14 +677,19 @@ __global__ void __launch_bounds__(kAT) k_krylov_add(int n, int j, const double* 
     if (threadIdx.x == 0) out[1] = ui > 0.0 ? 0.0 : 1.0;     // 1: the Krylov space is exhausted
 }
 
-__global__ void k_krylov_apply(int n, int rank, int cap, const double* __restrict__ work, double* __restrict__ nv) {
+__global__ void k_krylov_apply(int n, int rank, int cap, double alpha, int complete, double* work,
+                               double* __restrict__ nv) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double* V = work + n;
-    const double* c = work + n + (int64_t)2 * cap * n + cap * cap;
-    double x = nv[i];
-    for (int l = 0; l < rank; ++l) x -= c[l] * V[(int64_t)l * n + i];
-    nv[i] = x;
+    const KrylovWork w = krylov_work(work, n, cap);
+    double d = 0.0;
+    for (int l = 0; l < rank; ++l) d += w.c[l] * w.V[(int64_t)l * n + i];
+    if (complete) {
+        double e = w.r[i];
+        for (int l = 0; l < rank; ++l) e -= w.g[l] * w.Q[(int64_t)l * n + i];
+        d += e;
+    }
+    nv[i] -= alpha * d;
 }
 
 }  // namespace
@@ -864,15 +877,15 @@ extern "C" int gdm_scc_anderson(gdm_ctx* ctx, int32_t n, double* n_vec, const do
     return GDM_OK;
 }
 
-extern "C" int gdm_krylov_begin(gdm_ctx* ctx, int32_t n, const double* n_vec, const double* q0, int32_t max_rank,
-                                double* work, double* rms_out) {
+extern "C" int gdm_krylov_begin(gdm_ctx* ctx, int32_t n, const double* n_vec, const double* q0, double k0,
+                                int32_t max_rank, double* work, double* rms_out) {
     if (!ctx) return GDM_E_ARG;
-    if (n <= 0 || !n_vec || !q0 || !work || !rms_out || max_rank < 1 || max_rank > kMaxRank)
+    if (n <= 0 || !n_vec || !q0 || !work || !rms_out || max_rank < 1 || max_rank > kMaxRank || !(k0 > 0.0))
         return gdm_fail(ctx, GDM_E_ARG, "gdm_krylov_begin: bad argument");
     bool ok = true;
     double* out = (double*)gdm_buf(ctx, BUF_KRYLOV, sizeof(double) * 2, &ok);
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_krylov_begin: workspace allocation failed");
-    hipLaunchKernelGGL(k_krylov_begin, dim3(1), dim3(kAT), 0, ctx->stream, n, n_vec, q0, max_rank, work, out);
+    hipLaunchKernelGGL(k_krylov_begin, dim3(1), dim3(kAT), 0, ctx->stream, n, n_vec, q0, k0, max_rank, work, out);
     GDM_LAUNCH_CHECK(ctx);
     GDM_HIP(ctx, hipMemcpyAsync(rms_out, out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -901,13 +914,14 @@ extern "C" int gdm_krylov_add(gdm_ctx* ctx, int32_t n, int32_t j, const double* 
     return GDM_OK;
 }
 
-extern "C" int gdm_krylov_apply(gdm_ctx* ctx, int32_t n, int32_t rank, int32_t max_rank, double* n_vec,
-                                const double* work) {
+extern "C" int gdm_krylov_apply(gdm_ctx* ctx, int32_t n, int32_t rank, int32_t max_rank, double alpha,
+                                int32_t complete, double* n_vec, double* work) {
     if (!ctx) return GDM_E_ARG;
-    if (n <= 0 || !n_vec || !work || max_rank < 1 || max_rank > kMaxRank || rank < 1 || rank > max_rank)
+    if (n <= 0 || !n_vec || !work || max_rank < 1 || max_rank > kMaxRank || rank < 1 || rank > max_rank ||
+        !std::isfinite(alpha))
         return gdm_fail(ctx, GDM_E_ARG, "gdm_krylov_apply: bad argument");
-    hipLaunchKernelGGL(k_krylov_apply, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, rank, max_rank, work,
-                       n_vec);
+    hipLaunchKernelGGL(k_krylov_apply, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, rank, max_rank, alpha,
+                       complete, work, n_vec);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }

@@ -408,6 +408,7 @@ __global__ void __launch_bounds__(256) k_pack_core(const SubDesc* __restrict__ d
 
 // ------------------------------------------------------- elementwise kernels
 constexpr int kEw = 256;
+constexpr double kZResidMax = 3e-3;   // largest |Z s Z - I| entry accepted before refinement
 
 __device__ __forceinline__ double block_reduce_max(double v, double* red) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -583,6 +584,23 @@ __global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* 
         out[0] = a;
         out[1] = b;
     }
+}
+
+// Residual check of the inverse-overlap factor before its FP64 refinement:
+// raises NOT_CONVERGED when some |E_ij| = |(Z s Z - I)_ij| exceeds emax (the
+// refinement leaves an error of order E^2, so emax = 3e-3 bounds it near 1e-5).
+__global__ void __launch_bounds__(kEw) k_resid_check(const SubDesc* __restrict__ desc, const double* __restrict__ E,
+                                                    double emax, int* __restrict__ status) {
+    const SubDesc d = desc[blockIdx.x];
+    const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
+    if (r0 >= n) return;
+    double m = 0.0;
+    for (int e = threadIdx.x; e < 64 * P; e += kEw) {
+        const int i = r0 + e / P, j = e % P;
+        if (i < n && j < n) m = fmax(m, fabs(E[d.off2 + (int64_t)i * P + j]));
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && !(m <= emax)) gdm_raise(status, GDM_STATUS_NOT_CONVERGED);
 }
 
 // ------------------------------------------------------- charge response
@@ -982,6 +1000,12 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
         GDM_LAUNCH_CHECK(ctx);
         GDM_TRY(gemm64_dd(ctx, s64, Z64, nullptr, F, 1.0, 0.0, 0.0, 0));     // F = s Z
         GDM_TRY(gemm64_dd(ctx, Z64, F, nullptr, E, 1.0, 0.0, -1.0, 1));     // E = Z (s Z) - I
+        if (!orth) {
+            GDM_TIMED(ctx, "refine64");
+            hipLaunchKernelGGL(k_resid_check, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, E, kZResidMax,
+                               ctx->d_status);
+        }
+        GDM_LAUNCH_CHECK(ctx);
         GDM_TRY(gemm64_dd(ctx, Z64, E, Z64, F, -0.5, 1.0, 0.0, 1));        // F <- Z - Z E / 2
         GDM_HIP(ctx, hipMemcpyAsync(Z64, F, sizeof(double) * P.tot2, hipMemcpyDeviceToDevice, ctx->stream));
         Z = slot(ctx, SL_Z);

@@ -103,57 +103,111 @@ def scc_loop(ctx: Context, system: System, tb: TBParams, part: Partition, kT: fl
 class QuasiNewtonResult(SCCResult):
     ranks: list = field(default_factory=list)        # Krylov vectors per step
     fits: list = field(default_factory=list)         # relative residual of each step's low-rank fit
+    alphas: list = field(default_factory=list)       # accepted step lengths
+    solves: int = 0                                  # density solves (including line-search trials)
+    responses: int = 0                               # charge-response solves
+
+
+E_NO_BRACKET = -4
 
 
 def scc_quasi_newton(ctx: Context, system: System, tb: TBParams, part: Partition, kT: float,
                      q_start: torch.Tensor | None = None, tol: float = 1e-5, max_iter: int = 100,
-                     rank_tol: float = 1e-2, max_rank: int = 8, ewald: EwaldSetup | None = None,
-                     hubbard_U=HUBBARD_U, mu_guess: float = 0.0, plan: bool = True, screened: bool = True,
-                     max_doublings: int = 12) -> QuasiNewtonResult:
-    """Kernel-accelerated SCF on the mixed-precision path.  Per step: the
-    solve at H[n] (doubling history recorded), begin the Krylov kernel with
-    r = K0 f, then for j = 0, 1, ...: the potential of v_j, its charge
+                     rank_tol: float = 1e-2, max_rank: int = 8, k0: float = 0.1, complete: bool = True,
+                     backtrack: int = 4, ewald: EwaldSetup | None = None, hubbard_U=HUBBARD_U,
+                     mu_guess: float = 0.0, plan: bool = True, screened: bool = True, max_doublings: int = 20,
+                     log=None) -> QuasiNewtonResult:
+    """Kernel-accelerated SCF on the mixed-precision path.  Per step: begin
+    the Krylov kernel with r = K0 f at the current solve (doubling history
+    recorded), then for j = 0, 1, ...: the potential of v_j, its charge
     response dq_j, fit; stop the rank at a relative fit residual <= rank_tol
-    (or max_rank), then n <- n - V c.  Returns q0[n] at the first n with
-    RMS(q0[n] - n) < tol."""
+    (or max_rank); then n <- n - alpha (V c + complete (r - F_v c)) with
+    alpha = 1, halved up to `backtrack` times while RMS(q0[n] - n) does not
+    decrease (or no chemical potential matches the electron count).  The
+    accepted trial's solve is the next step's.  Returns q0[n] at the first n
+    with RMS(q0[n] - n) < tol."""
+    from ._lib import GDMError
     ew = ewald if ewald is not None else ewald_setup(ctx, system)
     tau = slater_tau(hubbard_U) if screened else None
     N = system.n_atoms
     n = torch.zeros(N, dtype=torch.float64, device=ctx.dev) if q_start is None \
         else q_start.to(device=ctx.dev, dtype=torch.float64).clone()
+    n_base = torch.empty_like(n)
     V = torch.empty_like(n)
     dV = torch.empty_like(n)
     dq = torch.empty_like(n)
     work = torch.empty(Context.krylov_work_size(N, max_rank), dtype=torch.float64, device=ctx.dev)
-    ctx.set_response(max_doublings)
-    hist, ranks, fits = [], [], []
-    mu = mu_guess
+    res = QuasiNewtonResult(q=n, iterations=0, converged=False)
+    state = {"cap": max_doublings}
+
+    def evaluate(mu):
+        """H[n] and the solve there; (None, None) when no chemical potential matches."""
+        ctx.ewald_potential(system, ew.graph, ew.rcut, ew.eta, ew.k_max, hubbard_U, n, tau=tau, out=V)
+        H, S = ctx.build_hs(system, tb, part.nbr, V)
+        res.solves += 1
+        try:
+            sol = solve(ctx, system, part, H, S, kT, MIXED_F16, mu_guess=mu, plan=False)
+            nd = ctx.mixed_stats()["n_doublings"]
+            if nd > state["cap"]:
+                # a wide spectrum (large potentials early in the iteration) took more
+                # doublings than the history holds: grow it and solve again
+                state["cap"] = nd + 2
+                ctx.set_response(state["cap"])
+                res.solves += 1
+                sol = solve(ctx, system, part, H, S, kT, MIXED_F16, mu_guess=sol.mu, plan=False)
+        except GDMError as e:
+            if e.code != E_NO_BRACKET:
+                raise
+            return None, None
+        return sol, S
+
+    if plan:
+        ctx.plan(part.sg, MIXED_F16)
+    ctx.set_response(state["cap"])
     try:
+        sol, S = evaluate(mu_guess)
+        if sol is None:
+            raise RuntimeError("scc_quasi_newton: no chemical potential at the starting charges")
         for it in range(1, max_iter + 1):
-            ctx.ewald_potential(system, ew.graph, ew.rcut, ew.eta, ew.k_max, hubbard_U, n, tau=tau, out=V)
-            H, S = ctx.build_hs(system, tb, part.nbr, V)
-            sol = solve(ctx, system, part, H, S, kT, MIXED_F16, mu_guess=mu, plan=plan and it == 1)
-            mu = sol.mu
-            rms = ctx.krylov_begin(n, sol.q, max_rank, work)
-            hist.append(rms)
+            rms = ctx.krylov_begin(n, sol.q, max_rank, work, k0)
+            res.history.append(rms)
+            res.iterations = it
+            res.mu = sol.mu
             if rms < tol:
-                return QuasiNewtonResult(q=sol.q, iterations=it, converged=True, history=hist, mu=mu, ranks=ranks,
-                                         fits=fits)
+                res.q, res.converged = sol.q, True
+                return res
             rank, rel = 0, 1.0
             for j in range(max_rank):
                 v = Context.krylov_vector(work, N, j)
                 ctx.ewald_potential(system, ew.graph, ew.rcut, ew.eta, ew.k_max, hubbard_U, v, tau=tau, out=dV)
                 ctx.density_response(system, part.sg, part.nbr, S, dV, out=dq)
+                res.responses += 1
                 rel, exhausted = ctx.krylov_add(N, j, dq, max_rank, work)
                 rank = j + 1
                 if rel <= rank_tol or exhausted:
                     break
-            ranks.append(rank)
-            fits.append(rel)
-            ctx.krylov_apply(n, rank, max_rank, work)
+            res.ranks.append(rank)
+            res.fits.append(rel)
+            n_base.copy_(n)
+            alpha = 1.0
+            for k in range(backtrack + 1):
+                n.copy_(n_base)
+                ctx.krylov_apply(n, rank, max_rank, work, alpha, complete)
+                trial, S_t = evaluate(sol.mu)
+                rms_t = ctx.scc_mix(n, trial.q, 0.0) if trial is not None else math.inf
+                if rms_t < rms or k == backtrack:
+                    break
+                alpha *= 0.5
+            res.alphas.append(alpha)
+            if log is not None:
+                log(it, rms, rank, rel, alpha, sol.mu)
+            if trial is None:
+                break
+            sol, S = trial, S_t
+        res.q = n
+        return res
     finally:
         ctx.set_response(0)
-    return QuasiNewtonResult(q=n, iterations=max_iter, converged=False, history=hist, mu=mu, ranks=ranks, fits=fits)
 
 
 __all__ = ["HUBBARD_U", "slater_tau", "EwaldSetup", "ewald_setup", "SCCResult", "scc_loop", "QuasiNewtonResult",

@@ -69,3 +69,27 @@ def test_mixed_mu_search_from_far_guess(c):
     log(f"  passes {st['passes']} mu {sol.mu:.6f} N {sol.n_count:.9f} max|dq| {err_q:.2e}")
     assert abs(sol.n_count - sysm.n_electrons) <= 1e-7 * sysm.n_electrons + 1e-9
     assert err_q < 1e-4
+
+
+def test_inverse_overlap_residual_guard(c):
+    """Too few Newton-Schulz iterations for s^-1/2 leave |Z s Z - I| above
+    the refinement's range: gdm_find_mu reports GDM_E_NOT_CONVERGED instead
+    of a silently inaccurate density, and the next solve with the default
+    count succeeds."""
+    log("inverse-overlap residual guard (ns_z = 1, then the default)")
+    from paper_2606_03140_amd import pipeline
+    from paper_2606_03140_amd._lib import GDMError
+    box = waterbox.water_box(96, 1)
+    sysm = system_of(box)
+    tb = tb_params(False)
+    part = pipeline.cutoff_partition(c, sysm, tb, (2, 2, 2))
+    H, S = c.build_hs(sysm, tb, part.nbr)
+    c.set_mixed_options(ns_z=1)
+    try:
+        with pytest.raises(GDMError) as e:
+            pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.MIXED_F16, mu_guess=-7.0)
+        assert e.value.code == -5
+    finally:
+        c.set_mixed_options(ns_z=5)
+    sol = pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.MIXED_F16, mu_guess=-7.0)
+    assert abs(sol.n_count - sysm.n_electrons) <= 1e-7 * sysm.n_electrons + 1e-9

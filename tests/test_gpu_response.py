@@ -110,8 +110,9 @@ def test_density_response_needs_recording(c):
         c.set_response(0)
 
 
-@pytest.mark.parametrize("n,max_rank", [(200, 1), (200, 4), (1000, 8), (40, 16)])
-def test_krylov_kernels_match_oracle(c, n, max_rank):
+@pytest.mark.parametrize("n,max_rank,k0,complete", [(200, 1, 1.0, False), (200, 4, 0.1, True), (1000, 8, 1.0, True),
+                                                     (1000, 8, 0.1, False), (40, 16, 0.5, True)])
+def test_krylov_kernels_match_oracle(c, n, max_rank, k0, complete):
     from paper_2606_03140_amd._lib import Context
     rng = np.random.default_rng(n + max_rank)
     Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
@@ -121,10 +122,11 @@ def test_krylov_kernels_match_oracle(c, n, max_rank):
     q0 = rng.standard_normal(n)
     f = q0 - nv0
     rank_tol = 1e-3
-    dn_ref, rank_ref, rel_ref = orsp.krylov_step(f, lambda v: Jm @ v, rank_tol=rank_tol, max_rank=max_rank)
+    dn_ref, rank_ref, rel_ref = orsp.krylov_step(f, lambda v: Jm @ v, rank_tol=rank_tol, max_rank=max_rank,
+                                                 k0=k0, complete=complete)
     nv = torch.as_tensor(nv0).to(c.dev)
     work = torch.empty(Context.krylov_work_size(n, max_rank), dtype=torch.float64, device=c.dev)
-    rms = c.krylov_begin(nv, torch.as_tensor(q0).to(c.dev), max_rank, work)
+    rms = c.krylov_begin(nv, torch.as_tensor(q0).to(c.dev), max_rank, work, k0)
     assert abs(rms - math.sqrt(np.mean(f * f))) < 1e-12 * max(1.0, rms)
     Ad = torch.as_tensor(A).to(c.dev)
     rank = 0
@@ -135,13 +137,19 @@ def test_krylov_kernels_match_oracle(c, n, max_rank):
         rank = j + 1
         if rel <= rank_tol or exhausted:
             break
-    c.krylov_apply(nv, rank, max_rank, work)
+    # a line-search trial at half length, then the full step from the same start
+    c.krylov_apply(nv, rank, max_rank, work, 0.5, complete)
+    half = nv.cpu().numpy() - nv0
+    nv.copy_(torch.as_tensor(nv0).to(c.dev))
+    c.krylov_apply(nv, rank, max_rank, work, 1.0, complete)
     got = nv.cpu().numpy() - nv0
-    log(f"  Krylov n={n} cap {max_rank}: rank {rank} (oracle {rank_ref}), fit {rel:.3e} (oracle {rel_ref:.3e}), "
-        f"max|dn - oracle| {np.abs(got - dn_ref).max():.2e}")
+    scale = max(1.0, np.abs(dn_ref).max())
+    log(f"  Krylov n={n} cap {max_rank} k0 {k0} complete {complete}: rank {rank} (oracle {rank_ref}), "
+        f"fit {rel:.3e} (oracle {rel_ref:.3e}), max|dn - oracle| {np.abs(got - dn_ref).max():.2e}")
     assert rank == rank_ref
     assert abs(rel - rel_ref) < 1e-9
-    assert np.abs(got - dn_ref).max() < 1e-9 * max(1.0, np.abs(dn_ref).max())
+    assert np.abs(got - dn_ref).max() < 1e-9 * scale
+    assert np.abs(half - 0.5 * dn_ref).max() < 1e-9 * scale
 
 
 def test_quasi_newton_scc_matches_oracle(c):
@@ -158,8 +166,12 @@ def test_quasi_newton_scc_matches_oracle(c):
     subs = oracle_subs(box, (2, 2, 1))
     q_ref, it_ref, _ = osc.scc(box.pos, box.species, L, om.TBModel(), subs, short_cut=ew.rcut)
     err = np.abs(res.q.cpu().numpy() - q_ref).max()
-    log(f"  quasi-Newton {res.iterations} iterations, ranks {res.ranks}; Anderson GPU {ra.iterations}, "
+    _, it_qn_ref, _, ranks_ref = orsp.scc_quasi_newton(box.pos, box.species, L, om.TBModel(), subs,
+                                                         short_cut=ew.rcut)
+    log(f"  quasi-Newton {res.iterations} iterations (oracle {it_qn_ref}), ranks {res.ranks} (oracle {ranks_ref}), "
+        f"steps {res.alphas}, {res.solves} solves, {res.responses} responses; Anderson GPU {ra.iterations}, "
         f"oracle {it_ref}; max|q - oracle| {err:.2e}")
     assert res.converged and ra.converged
     assert res.iterations * 3 < ra.iterations
+    assert abs(res.iterations - it_qn_ref) <= 2
     assert err < 1e-4

@@ -9,7 +9,9 @@
 * on an affine charge map the full-rank low-rank kernel is the exact
   inverse Jacobian: one quasi-Newton step lands on the closed-form fixed
   point, and the rank-m step equals the GMRES-type minimiser over the
-  Krylov space built from explicit powers of J;
+  Krylov space built from explicit powers of J; the completed step adds
+  k0 (f + J dn); with a Jacobian model wrong by 4x the full steps diverge
+  and the backtracking line search restores a decreasing residual;
 * on a water box the quasi-Newton SCF reaches the Anderson fixed point.
 """
 import math
@@ -125,6 +127,30 @@ def test_low_rank_step_is_krylov_minimiser():
         ref = K @ y
         assert np.abs(dn - ref).max() < 1e-8 * np.abs(ref).max()
         assert abs(rel - np.linalg.norm(Jm @ ref + f) / np.linalg.norm(f)) < 1e-8
+        # the completed step adds the unfitted remainder -(r - F_v c), which with
+        # r = -k0 f and F_v c = k0 J dn is k0 (f + J dn); it does not depend on k0's
+        # Krylov space (the space of K0 J on K0 f is that of J on f for any k0)
+        for k0 in (1.0, 0.1):
+            dc, rank_c, rel_c = orsp.krylov_step(f, lambda v: Jm @ v, rank_tol=0.0, max_rank=m, k0=k0,
+                                                 complete=True)
+            assert rank_c == m and abs(rel_c - rel) < 1e-10
+            assert np.abs(dc - (ref + k0 * (f + Jm @ ref))).max() < 1e-8 * np.abs(ref).max()
+
+
+def test_backtracking_halves_a_bad_step():
+    # a map whose Jacobian model is wrong by a factor 4 (the "response" passed
+    # in is J/4): the full step overshoots, and halving recovers monotone
+    # decrease of the residual
+    A, b = affine_problem(n=20, seed=2)
+    n = len(b)
+    G = lambda v: A @ v + b
+    wrong = lambda _n, v: 0.25 * (A @ v - v)
+    _, _, hist0, _, ok0 = orsp.quasi_newton(G, wrong, np.zeros(n), tol=1e-10, max_iter=30, rank_tol=1e-13,
+                                            max_rank=n, backtrack=0)
+    _, _, hist4, _, ok4 = orsp.quasi_newton(G, wrong, np.zeros(n), tol=1e-10, max_iter=60, rank_tol=1e-13,
+                                            max_rank=n, backtrack=4)
+    assert not ok0 and hist0[-1] > hist0[0]
+    assert ok4 and all(b_ < a_ for a_, b_ in zip(hist4, hist4[1:]))
 
 
 @pytest.mark.slow
