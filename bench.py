@@ -267,7 +267,7 @@ def main():
                 "useful_tflops": st["flops_per_launch"] / (avg_ms * 1e-3) / 1e12,
                 "flop_per_byte": intensity, "algorithmic_bytes_per_launch": byts,
                 "mean_launch_ms": avg_ms, "gemm_launches_per_step": n_g / args.steps,
-                "passes": st["passes"], "n_doublings": st["n_doublings"]}
+                "passes": st["passes"], "n_doublings": st["n_doublings"], "ns_z_used": st["ns_z_used"]}
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {
         "metric": "subgraph DM solves/s + % MFMA peak at 60k orbitals, mixed vs FP64 at 1e-4 e",

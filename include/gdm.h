@@ -218,18 +218,19 @@ int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
                          const double* S, const double* D_core, const double n0[2],
                          double* q_out);
 
-/* Options of the mixed-precision expansion (GDM_MIXED_F16): coupled
- * Newton-Schulz iterations for s^-1/2 (ns_z, default 5: from the scaled
- * start s/c, c the largest absolute row sum, the error falls as
- * e -> 3/4 e^2 + 1/4 e^3 from e0 = 1 - lambda_min(s)/c, and one FP64
- * refinement step then squares it; gdm_find_mu returns GDM_E_NOT_CONVERGED
- * when some |(Z s Z - I)_ij| before that step exceeds 3e-3, i.e. when
- * lambda_min(s)/c is too small for ns_z), Newton-Schulz
- * iterations per inverse in each doubling (ns_inv, default 3; the start has
- * error <= 1/17, so k iterations reach (1/17)^(2^k)), and the number of
- * expansion passes allowed while matching the electron count (max_passes,
- * default 10).  Values <= 0 keep the current setting. */
-int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes);
+/* Options of the mixed-precision expansion (GDM_MIXED_F16).  ns_z: coupled
+ * Newton-Schulz iterations for s^-1/2 to try first (default 5).  From the
+ * scaled start s/c (c the largest absolute row sum) the error falls as
+ * e -> 3/4 e^2 + 1/4 e^3 from e0 = 1 - lambda_min(s)/c, and one residual
+ * refinement step then squares it; before that step gdm_find_mu checks
+ * max |(Z s Z - I)_ij| and, while it exceeds 3e-3, runs one more iteration,
+ * at most ns_z_extra times (default 8), after which it returns
+ * GDM_E_NOT_CONVERGED (overlap too ill-conditioned).  ns_inv: Newton-Schulz
+ * iterations per inverse in each doubling (default 3; the start has error
+ * <= 1/17, so k iterations reach (1/17)^(2^k)).  max_passes: expansion
+ * passes allowed while matching the electron count (default 10).  Values
+ * <= 0 (ns_z_extra: < 0) keep the current setting. */
+int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes, int ns_z_extra);
 
 /* Statistics of the last GDM_MIXED_F16 gdm_find_mu (HOST outputs, nullable):
  * expansion passes, doublings per pass, split GEMM launches, and the mean
@@ -237,9 +238,10 @@ int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes);
  * tile row of P, over the tiles computed: products of commuting symmetric
  * matrices compute the upper tiles only); each launch executes three FP16
  * products.  bytes_per_launch: mean algorithmic HBM bytes of a launch (each
- * operand, E matrix and output read or written once). */
+ * operand, E matrix and output read or written once).  ns_z_used: coupled
+ * Newton-Schulz iterations taken for s^-1/2. */
 int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int64_t* gemm_launches,
-                    double* flops_per_launch, double* bytes_per_launch);
+                    double* flops_per_launch, double* bytes_per_launch, int* ns_z_used);
 
 /* Diagnostics: copy the FP32 matrix `which` (0 Z, the inverse-overlap
  * factor before FP64 refinement; 1 h_perp; 2 X, 3 X^2 of the last expansion

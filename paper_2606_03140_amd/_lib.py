@@ -75,9 +75,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gdm_mulliken_charges": (C.c_int, [P, C.POINTER(SystemT), C.POINTER(SubgraphsT), P, P, I64, P, P,
                                            C.POINTER(C.c_double), P]),
     }
-    sig["gdm_set_mixed_options"] = (C.c_int, [P, C.c_int, C.c_int, C.c_int])
+    sig["gdm_set_mixed_options"] = (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int])
     sig["gdm_mixed_stats"] = (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int64),
-                                        C.POINTER(C.c_double), C.POINTER(C.c_double)])
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)])
     sig["gdm_debug_slot"] = (C.c_int, [P, C.c_int, C.c_int, P])
     sig["gdm_ewald_potential"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double),
                                             C.POINTER(C.c_double), P, P])
@@ -358,8 +358,8 @@ class Context:
     def check(self):
         self._check(self.lib.gdm_check(self.h))
 
-    def set_mixed_options(self, ns_z: int = 0, ns_inv: int = 0, max_passes: int = 0):
-        self._check(self.lib.gdm_set_mixed_options(self.h, ns_z, ns_inv, max_passes))
+    def set_mixed_options(self, ns_z: int = 0, ns_inv: int = 0, max_passes: int = 0, ns_z_extra: int = -1):
+        self._check(self.lib.gdm_set_mixed_options(self.h, ns_z, ns_inv, max_passes, ns_z_extra))
 
     def debug_slot(self, which: int, sub: int, P: int) -> torch.Tensor:
         out = torch.empty(P * P, dtype=torch.float32, device=self.dev)
@@ -367,10 +367,11 @@ class Context:
         return out.view(P, P)
 
     def mixed_stats(self) -> dict:
-        p, nd, g, f, b = C.c_int(0), C.c_int(0), C.c_int64(0), C.c_double(0.0), C.c_double(0.0)
-        self._check(self.lib.gdm_mixed_stats(self.h, C.byref(p), C.byref(nd), C.byref(g), C.byref(f), C.byref(b)))
+        p, nd, g, f, b, z = C.c_int(0), C.c_int(0), C.c_int64(0), C.c_double(0.0), C.c_double(0.0), C.c_int(0)
+        self._check(self.lib.gdm_mixed_stats(self.h, C.byref(p), C.byref(nd), C.byref(g), C.byref(f), C.byref(b),
+                                             C.byref(z)))
         return {"passes": p.value, "n_doublings": nd.value, "gemm_launches": g.value,
-                "flops_per_launch": f.value, "bytes_per_launch": b.value}
+                "flops_per_launch": f.value, "bytes_per_launch": b.value, "ns_z_used": z.value}
 
     # ------------------------------------------------------------ SCC shell
     def ewald_potential(self, system: System, graph: Graph, rcut: float, eta: float, k_max: int, hubbard_U, q,

@@ -586,21 +586,24 @@ __global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* 
     }
 }
 
-// Residual check of the inverse-overlap factor before its FP64 refinement:
-// raises NOT_CONVERGED when some |E_ij| = |(Z s Z - I)_ij| exceeds emax (the
-// refinement leaves an error of order E^2, so emax = 3e-3 bounds it near 1e-5).
-__global__ void __launch_bounds__(kEw) k_resid_check(const SubDesc* __restrict__ desc, const double* __restrict__ E,
-                                                    double emax, int* __restrict__ status) {
+// Largest |E_ij| = |(Z s Z - I)_ij| over every subgraph's n x n block, as an
+// atomic max on the bit pattern (non-negative doubles order as integers; NaN
+// counts as infinite).
+__global__ void __launch_bounds__(kEw) k_resid_max(const SubDesc* __restrict__ desc, const double* __restrict__ E,
+                                                  unsigned long long* __restrict__ out) {
     const SubDesc d = desc[blockIdx.x];
     const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
     if (r0 >= n) return;
     double m = 0.0;
     for (int e = threadIdx.x; e < 64 * P; e += kEw) {
         const int i = r0 + e / P, j = e % P;
-        if (i < n && j < n) m = fmax(m, fabs(E[d.off2 + (int64_t)i * P + j]));
+        if (i < n && j < n) {
+            const double v = fabs(E[d.off2 + (int64_t)i * P + j]);
+            m = v == v ? fmax(m, v) : INFINITY;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0 && !(m <= emax)) gdm_raise(status, GDM_STATUS_NOT_CONVERGED);
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
 }
 
 // ------------------------------------------------------- charge response
@@ -973,41 +976,67 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
                            hl(slot(ctx, SL_Y)), orth ? slot(ctx, SL_Z) : hl(slot(ctx, SL_Z)), scale, orth);
     }
     GDM_LAUNCH_CHECK(ctx);
-    // coupled Newton-Schulz: Z -> (s/c)^-1/2
+    // coupled Newton-Schulz: Z -> (s/c)^-1/2, ns_z iterations, then more (at
+    // most mixed_ns_z_extra) while the residual before refinement is too large
+    // for one refinement step to remove
     SplitMat Y = slot(ctx, SL_Y), Z = slot(ctx, SL_Z), T = slot(ctx, SL_T), Y2 = slot(ctx, SL_Y2),
              Z2 = slot(ctx, SL_Z2);
-    if (!orth) {
-        for (int it = 0; it < ctx->mixed_ns_z; ++it) {
-            GDM_TRY(gemm(ctx, Z, Y, none(), hl(T), none(), -0.5f, 0.0f, 1.5f, "ns_gemm"));
-            GDM_TRY(gemm(ctx, Y, T, hl(Y2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
-            GDM_TRY(gemm(ctx, T, Z, it + 1 == ctx->mixed_ns_z ? Z2 : hl(Z2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
-            std::swap(Y, Y2);
-            std::swap(Z, Z2);
-        }
-    }
+    auto ns_step = [&](bool full_z) -> int {
+        GDM_TRY(gemm(ctx, Z, Y, none(), hl(T), none(), -0.5f, 0.0f, 1.5f, "ns_gemm"));
+        GDM_TRY(gemm(ctx, Y, T, hl(Y2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
+        GDM_TRY(gemm(ctx, T, Z, full_z ? Z2 : hl(Z2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
+        std::swap(Y, Y2);
+        std::swap(Z, Z2);
+        return GDM_OK;
+    };
+    if (!orth)
+        for (int it = 0; it < ctx->mixed_ns_z; ++it) GDM_TRY(ns_step(it + 1 == ctx->mixed_ns_z));
+    ctx->mixed_ns_z_used = orth ? 0 : ctx->mixed_ns_z;
     // FP64 residual refinement of Z (Z s Z = I): Z64 = Z / sqrt(c) in FP64,
     // F = s Z64, E = Z64 F - I, Z64 <- Z64 - Z64 E / 2 (error O(E^2)); E and
-    // the update are symmetric products (upper tiles, mirrored).  Z64 serves
-    // the traces and the final step, its split copy (in SL_Z) the expansion.
+    // the update are symmetric products (upper tiles, mirrored).  The
+    // refinement also removes any systematic bias of the split products from
+    // Z64, which the electron count (and so mu) depends on.  While max |E_ij|
+    // is too large for one step, the coupled iteration continues first.
+    // Z64 serves the traces and the final step, its split copy (in SL_Z) the
+    // expansion.
     {
         double* F = fp64_region(ctx, 0);
         double* E = fp64_region(ctx, 1);
         double* Z64 = z64(ctx);
-        {
-            GDM_TIMED(ctx, "refine64");
-            hipLaunchKernelGGL(k_scale_to_f64, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, Z.f, scale, orth, Z64);
+        double* emax_d = (double*)ctx->b[BUF_TR].p + 2 * (size_t)P.n_sub + 4;
+        for (int extra = 0;; ++extra) {
+            {
+                GDM_TIMED(ctx, "refine64");
+                hipLaunchKernelGGL(k_scale_to_f64, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, Z.f, scale, orth,
+                                   Z64);
+            }
+            GDM_LAUNCH_CHECK(ctx);
+            if (orth) break;                                                  // Z = I exactly
+            GDM_TRY(gemm64_dd(ctx, s64, Z64, nullptr, F, 1.0, 0.0, 0.0, 0));     // F = s Z
+            GDM_TRY(gemm64_dd(ctx, Z64, F, nullptr, E, 1.0, 0.0, -1.0, 1));     // E = Z (s Z) - I
+            double emax = 0.0;
+            {
+                GDM_TIMED(ctx, "refine64");
+                GDM_TRY(gdm_fill_f64(ctx, emax_d, 1, 0.0));
+                hipLaunchKernelGGL(k_resid_max, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, E,
+                                   (unsigned long long*)emax_d);
+            }
+            GDM_LAUNCH_CHECK(ctx);
+            GDM_HIP(ctx, hipMemcpyAsync(&emax, emax_d, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+            GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            if (emax <= kZResidMax) {
+                GDM_TRY(gemm64_dd(ctx, Z64, E, Z64, F, -0.5, 1.0, 0.0, 1));        // F <- Z - Z E / 2
+                GDM_HIP(ctx, hipMemcpyAsync(Z64, F, sizeof(double) * P.tot2, hipMemcpyDeviceToDevice, ctx->stream));
+                break;
+            }
+            if (extra >= ctx->mixed_ns_z_extra || !std::isfinite(emax))
+                return gdm_fail(ctx, GDM_E_NOT_CONVERGED,
+                                "mixed: inverse-overlap factor residual %.3g after %d Newton-Schulz iterations "
+                                "(overlap too ill-conditioned)", emax, ctx->mixed_ns_z_used);
+            GDM_TRY(ns_step(true));
+            ++ctx->mixed_ns_z_used;
         }
-        GDM_LAUNCH_CHECK(ctx);
-        GDM_TRY(gemm64_dd(ctx, s64, Z64, nullptr, F, 1.0, 0.0, 0.0, 0));     // F = s Z
-        GDM_TRY(gemm64_dd(ctx, Z64, F, nullptr, E, 1.0, 0.0, -1.0, 1));     // E = Z (s Z) - I
-        if (!orth) {
-            GDM_TIMED(ctx, "refine64");
-            hipLaunchKernelGGL(k_resid_check, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, E, kZResidMax,
-                               ctx->d_status);
-        }
-        GDM_LAUNCH_CHECK(ctx);
-        GDM_TRY(gemm64_dd(ctx, Z64, E, Z64, F, -0.5, 1.0, 0.0, 1));        // F <- Z - Z E / 2
-        GDM_HIP(ctx, hipMemcpyAsync(Z64, F, sizeof(double) * P.tot2, hipMemcpyDeviceToDevice, ctx->stream));
         Z = slot(ctx, SL_Z);
         {
             GDM_TIMED(ctx, "refine64");
@@ -1218,24 +1247,26 @@ int gdm_mixed_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs*
     return GDM_OK;
 }
 
-extern "C" int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes) {
+extern "C" int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes, int ns_z_extra) {
     if (!ctx) return GDM_E_ARG;
-    if (ns_z > 64 || ns_inv > 16 || max_passes > 64)
+    if (ns_z > 64 || ns_inv > 16 || max_passes > 64 || ns_z_extra > 32)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_set_mixed_options: values out of range");
     if (ns_z > 0) ctx->mixed_ns_z = ns_z;
     if (ns_inv > 0) ctx->mixed_ns_inv = ns_inv;
     if (max_passes > 0) ctx->mixed_max_passes = max_passes;
+    if (ns_z_extra >= 0) ctx->mixed_ns_z_extra = ns_z_extra;
     return GDM_OK;
 }
 
 extern "C" int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int64_t* gemm_launches,
-                               double* flops_per_launch, double* bytes_per_launch) {
+                               double* flops_per_launch, double* bytes_per_launch, int* ns_z_used) {
     if (!ctx) return GDM_E_ARG;
     if (passes) *passes = ctx->mixed_passes;
     if (n_doublings) *n_doublings = ctx->mixed_nd;
     if (gemm_launches) *gemm_launches = ctx->mixed_gemms;
     if (flops_per_launch) *flops_per_launch = ctx->mixed_gemms ? ctx->mixed_flops / (double)ctx->mixed_gemms : 0.0;
     if (bytes_per_launch) *bytes_per_launch = ctx->mixed_gemms ? ctx->mixed_bytes / (double)ctx->mixed_gemms : 0.0;
+    if (ns_z_used) *ns_z_used = ctx->mixed_ns_z_used;
     return GDM_OK;
 }
 
