@@ -80,6 +80,43 @@ def time_path(ctx, system, part, H, S, kT, precision, steps, warmup, mu_guess=0.
     return sol, ms, wall / steps, prof
 
 
+def time_response(ctx, system, part, H, S, kT, steps, warmup, mu_guess):
+    """Charge response on the mixed path (the directional derivative of the
+    kernel-accelerated SCF): one recorded solve, then `steps` responses to a
+    seeded potential change, timed with HIP events on the library's stream."""
+    import torch
+    from paper_2606_03140_amd import pipeline
+    ctx.set_response(16)
+    try:
+        ctx.plan(part.sg, pipeline.MIXED_F16)
+        pipeline.solve(ctx, system, part, H, S, kT, pipeline.MIXED_F16, mu_guess=mu_guess, plan=False)
+        g = torch.Generator(device="cpu").manual_seed(7)
+        dV = (0.1 * torch.randn(system.n_atoms, generator=g, dtype=torch.float64)).to(ctx.dev)
+        dq = torch.empty_like(dV)
+        for _ in range(warmup):
+            ctx.density_response(system, part.sg, part.nbr, S, dV, out=dq)
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(steps):
+            ctx.density_response(system, part.sg, part.nbr, S, dV, out=dq)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        tot, n = ctx.profile_query("response")
+        ctx.profile(False)
+        return {"ms_per_response": ms, "kernel_launches_per_response": n / steps,
+                "max_abs_dq_e": float(dq.abs().max()),
+                "note": "canonical charge response to a seeded 0.1 eV potential change: derivative of the recorded "
+                        "expansion (3 split GEMMs per doubling + 2 for the perturbation), FP64 core rows, "
+                        "Mulliken"}
+    finally:
+        ctx.set_response(0)
+
+
 def cpu_baseline(box, wl, max_seconds: float = 20.0):
     """The oracle (untuned) on a bounded sample of the same workload: it builds
     its own partition (neighbour list, cores, the same adaptive rounds), then
@@ -178,6 +215,8 @@ def main():
                                                         "default)")
     ap.add_argument("--ns-inv", type=int, default=0, help="Newton-Schulz iterations per inverse in each doubling "
                                                           "(0: library default)")
+    ap.add_argument("--no-response", dest="response", action="store_false",
+                    help="skip timing the charge response (the kernel-accelerated SCF's directional derivative)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
@@ -287,13 +326,18 @@ def main():
                                f"{wl['grid'][2]} cores, tau {wl['tau']} ({wl['rounds']} graph rounds)",
                    "n_subgraphs": part.sg.n_sub, "orbitals_min": int(n.min()), "orbitals_median": int(np.median(n)),
                    "orbitals_max": int(n.max()), "path": head,
-                   "mixed_options": {"ns_z": args.ns_z or 5, "ns_inv": args.ns_inv or 3}},
+                   "mixed_options": {"ns_z": args.ns_z or 5, "ns_inv": args.ns_inv or 2}},
         "paths": {k: {"ms_per_step": v["ms_per_step"], "solves_per_s": v["solves_per_s"], "mu": v["mu"],
                       "electron_count": v["n_count"],
                       "kernels_ms_per_step": {kk: round(vv["ms_per_step"], 4) for kk, vv in v["kernels"].items()}}
                   for k, v in results.items()},
         "roofline": roof,
     }
+    if args.response and "mixed" in results:
+        log(f"[bench] timing the charge response: warmup {args.warmup}, steps {args.steps}")
+        out["response"] = time_response(ctx, system, part, H, S, wl["kT"], args.steps, args.warmup,
+                                        results["mixed"]["mu"])
+        log(f"[bench] response: {out['response']['ms_per_response']:.2f} ms")
     if "mixed" in results and "fp64" in results:
         # (a) self-consistent: each path with its own mu
         dq = np.abs(results["mixed"]["q"] - results["fp64"]["q"]).max()
@@ -308,7 +352,8 @@ def main():
         ctx.set_mixed_options(max_passes=10)
         out["mixed_vs_fp64"] = {
             "at_fp64_mu": {"max_abs_dD": (Dm - results["fp64"]["D"]).abs().max().item(),
-                           "max_abs_dq_e": float(np.abs(qm - results["fp64"]["q"]).max())},
+                           "max_abs_dq_e": float(np.abs(qm - results["fp64"]["q"]).max()),
+                           "mixed_count_error_e": float(qm.sum())},
             "self_consistent_mu": {"mu_mixed": results["mixed"]["mu"], "mu_fp64": mu64,
                                    "max_abs_dD": dD, "max_abs_dq_e": float(dq)}}
     if not args.no_cpu:

@@ -226,8 +226,9 @@ int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
  * max |(Z s Z - I)_ij| and, while it exceeds 3e-3, runs one more iteration,
  * at most ns_z_extra times (default 8), after which it returns
  * GDM_E_NOT_CONVERGED (overlap too ill-conditioned).  ns_inv: Newton-Schulz
- * iterations per inverse in each doubling (default 3; the start has error
- * <= 1/17, so k iterations reach (1/17)^(2^k)).  max_passes: expansion
+ * iterations per inverse in each doubling after the minimax quadratic start
+ * (default 2; the start has error <= 1/99, so k iterations reach
+ * (1/99)^(2^k)).  max_passes: expansion
  * passes allowed while matching the electron count (default 10).  Values
  * <= 0 (ns_z_extra: < 0) keep the current setting. */
 int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes, int ns_z_extra);

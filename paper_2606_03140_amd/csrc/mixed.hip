@@ -864,18 +864,18 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
                            rec ? hist(ctx, 0, 0) : X, mu, b);
     }
     GDM_LAUNCH_CHECK(ctx);
-    const float c0 = 48.0f / 17.0f, c1 = -32.0f / 17.0f;
     const int ns = ctx->mixed_ns_inv;
     for (int it = 0; it < nd; ++it) {
         const SplitMat Xk = rec ? hist(ctx, it, 0) : X;
         // X2 = X X ; A = 2 X2 - 2 X + I
         GDM_TRY(gemm(ctx, Xk, Xk, hl(X2), hl(A), hl(Xk), 2.0f, -2.0f, 1.0f, "foe_gemm"));
-        // Newton-Schulz inverse of A from Y0 = c0 I + c1 A:
-        //   R = 2I - A Y0 = 2I - c0 A - c1 A A ;  Y1 = Y0 R = c0 R + c1 A R
-        GDM_TRY(gemm(ctx, A, A, none(), hl(Rm), hl(A), -c1, -c0, 2.0f, "foe_gemm"));
-        SplitMat Y = (rec && ns == 1) ? hist(ctx, it, 1) : Ya;
-        GDM_TRY(gemm(ctx, A, Rm, none(), hl(Y), hl(Rm), c1, c0, 0.0f, "foe_gemm"));
-        for (int k = 1; k < ns; ++k) {
+        // Newton-Schulz inverse of A (eigenvalues in [1/2, 1]) from the minimax
+        // quadratic start Y0 = (420 I - 576 A + 256 A^2) / 99: 1 - a y0(a) is the
+        // Chebyshev T3 on [1/2, 1] scaled to 1 at a = 0, so |1 - a y0| <= 1/99;
+        // each iteration R = 2I - A Y, Y <- Y R squares the error
+        SplitMat Y = (rec && ns == 0) ? hist(ctx, it, 1) : Ya;
+        GDM_TRY(gemm(ctx, A, A, none(), hl(Y), hl(A), 256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f, "foe_gemm"));
+        for (int k = 0; k < ns; ++k) {
             GDM_TRY(gemm(ctx, A, Y, none(), hl(Rm), none(), -1.0f, 0.0f, 2.0f, "foe_gemm"));
             const SplitMat Yn = (rec && k == ns - 1) ? hist(ctx, it, 1) : (Y.hi == Ya.hi ? Yb : Ya);
             GDM_TRY(gemm(ctx, Y, Rm, hl(Yn), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
