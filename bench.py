@@ -355,7 +355,8 @@ def main():
                            "max_abs_dq_e": float(np.abs(qm - results["fp64"]["q"]).max()),
                            "mixed_count_error_e": float(qm.sum())},
             "self_consistent_mu": {"mu_mixed": results["mixed"]["mu"], "mu_fp64": mu64,
-                                   "max_abs_dD": dD, "max_abs_dq_e": float(dq)}}
+                                   "max_abs_dD": dD, "max_abs_dq_e": float(dq),
+                                   "mixed_count_error_e": float(results["mixed"]["q"].sum())}}
     if not args.no_cpu:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s sample)")
         out["cpu_baseline"] = cpu_baseline(box, wl, args.cpu_seconds)
