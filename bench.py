@@ -326,7 +326,7 @@ def main():
                                f"{wl['grid'][2]} cores, tau {wl['tau']} ({wl['rounds']} graph rounds)",
                    "n_subgraphs": part.sg.n_sub, "orbitals_min": int(n.min()), "orbitals_median": int(np.median(n)),
                    "orbitals_max": int(n.max()), "path": head,
-                   "mixed_options": {"ns_z": args.ns_z or 5, "ns_inv": args.ns_inv or 2}},
+                   "mixed_options": {"ns_z": args.ns_z or 3, "ns_inv": args.ns_inv or 2}},
         "paths": {k: {"ms_per_step": v["ms_per_step"], "solves_per_s": v["solves_per_s"], "mu": v["mu"],
                       "electron_count": v["n_count"],
                       "kernels_ms_per_step": {kk: round(vv["ms_per_step"], 4) for kk, vv in v["kernels"].items()}}

@@ -67,7 +67,7 @@ struct gdm_ctx {
     double mu_solved = 0.0;
     double kT_solved = 0.0;
     // mixed path: options and the state of the last find_mu
-    int mixed_ns_z = 5;          // coupled Newton-Schulz iterations for s^-1/2 (first try)
+    int mixed_ns_z = 3;          // coupled Newton-Schulz iterations for s^-1/2 (first try)
     int mixed_ns_z_extra = 8;    // iterations that may be added while the residual is too large
     int mixed_ns_z_used = 0;     // iterations the last find_mu took
     int mixed_ns_inv = 2;        // Newton-Schulz iterations per inverse after the quadratic start

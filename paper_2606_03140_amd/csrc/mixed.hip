@@ -465,10 +465,16 @@ __global__ void __launch_bounds__(kEw) k_rowabs_max(const SubDesc* __restrict__ 
     if (lane == 0 && m > 0.0) atomicMax(&cbits[blockIdx.x], (unsigned long long)__double_as_longlong(m));
 }
 
-// H = h, Y0 = s / c, Z0 = I as split operands (padding: identity for Y, Z and
-// zero for H; the FP64 tiles get h = 0, s = I there).  c = scale[sub] (the
-// Gershgorin bound of s; 1 when s = I).  Z also gets its FP32 copy when
-// s = I, since Newton-Schulz is skipped then.
+// Start of the coupled Newton-Schulz iteration for (s/c)^-1/2: Z0 = a I + b
+// (s/c), the linear minimax approximation of x^-1/2 in the error measure
+// |1 - x z(x)^2| on [0.1, 1] (error <= 0.417 there, against 1 - x for Z0 =
+// I; x z^2 <= 1.42 on [0, 1], inside the iteration's convergence region).
+constexpr float kZ0a = 2.598551f, kZ0b = -1.834840f;
+
+// H = h, Y = s / c, Z0 = a I + b s / c as split operands (padding: identity
+// for Y, a + b on Z's diagonal, zero for H; the FP64 tiles get h = 0, s = I
+// there).  c = scale[sub] (the Gershgorin bound of s; 1 when s = I).  When
+// s = I, Z0 = I with its FP32 copy, since Newton-Schulz is skipped then.
 __global__ void __launch_bounds__(kEw) k_prep(const SubDesc* __restrict__ desc, double* __restrict__ h64,
                                              double* __restrict__ s64, SplitMat H, SplitMat Y, SplitMat Z,
                                              const double* __restrict__ scale, int orthogonal) {
@@ -488,7 +494,7 @@ __global__ void __launch_bounds__(kEw) k_prep(const SubDesc* __restrict__ desc, 
             const float sv = in ? (orthogonal ? id : (float)s64[idx + q]) : id;
             hv[q] = in ? (float)h64[idx + q] : 0.f;
             yv[q] = in ? sv * ic : id;
-            zv[q] = id;
+            zv[q] = orthogonal ? id : kZ0a * id + kZ0b * yv[q];
             if (!in) {
                 h64[idx + q] = 0.0;
                 s64[idx + q] = id;
@@ -521,17 +527,20 @@ __global__ void __launch_bounds__(kEw) k_scale_to_f64(const SubDesc* __restrict_
     }
 }
 
-// Gershgorin bounds of h_perp in FP64 -> bounds[2s], bounds[2s+1] (h_perp
-// comes out of the symmetric-mode product exactly symmetric); one wave per row.
-__global__ void __launch_bounds__(kEw) k_sym_bounds(const SubDesc* __restrict__ desc, SplitMat H,
+// Gershgorin bounds of h_perp in FP64 over the rows of one 64-row strip of
+// one subgraph -> bounds[2 (s strips + strip) + {0, 1}] (+inf / -inf for a
+// strip past the last row); h_perp comes out of the symmetric-mode product
+// exactly symmetric.  One wave per row.
+__global__ void __launch_bounds__(kEw) k_sym_bounds(const SubDesc* __restrict__ desc, SplitMat H, int strips,
                                                    double* __restrict__ bounds) {
     __shared__ double red[kEw / 64];
     const SubDesc d = desc[blockIdx.x];
-    const int n = d.n, P = d.ld;
+    const int n = d.n, P = d.ld, r0 = blockIdx.y * 64;
+    const int r1 = min(r0 + 64, n);
     const int64_t base = d.off2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double lo = INFINITY, hi = -INFINITY;
-    for (int i = wave; i < n; i += kEw / 64) {
+    for (int i = r0 + wave; i < r1; i += kEw / 64) {
         const float* row = H.f + base + (int64_t)i * P;
         double r = 0.0;
         for (int j = lane; j < n; j += 64)
@@ -544,8 +553,9 @@ __global__ void __launch_bounds__(kEw) k_sym_bounds(const SubDesc* __restrict__ 
     lo = block_reduce_min(lo, red);
     hi = block_reduce_max(hi, red);
     if (threadIdx.x == 0) {
-        bounds[2 * blockIdx.x] = lo;
-        bounds[2 * blockIdx.x + 1] = hi;
+        const int64_t k = 2 * ((int64_t)blockIdx.x * strips + blockIdx.y);
+        bounds[k] = lo;
+        bounds[k + 1] = hi;
     }
 }
 
@@ -790,7 +800,7 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
     gdm_buf(ctx, BUF_X_F, sizeof(float) * P.tot2 * kF32Slots, &ok);
     gdm_buf(ctx, BUF_X_HI, sizeof(_Float16) * P.tot2 * SL_COUNT, &ok);
     gdm_buf(ctx, BUF_X_LO, sizeof(_Float16) * P.tot2 * SL_COUNT, &ok);
-    gdm_buf(ctx, BUF_GERSH, sizeof(double) * 2 * (size_t)P.n_sub, &ok);
+    gdm_buf(ctx, BUF_GERSH, sizeof(double) * 2 * (size_t)P.n_sub * strip_grid(P).y, &ok);
     gdm_buf(ctx, BUF_TR, sizeof(double) * (2 * (size_t)P.n_sub + 8), &ok);
     gdm_buf(ctx, BUF_NDBL, sizeof(double) * (size_t)P.n_sub, &ok);
     gdm_buf(ctx, BUF_CC, sizeof(double) * (size_t)P.totc, &ok);
@@ -989,8 +999,12 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
         std::swap(Z, Z2);
         return GDM_OK;
     };
-    if (!orth)
+    if (!orth) {
+        // Y0 = (s/c) Z0 = a (s/c) + b (s/c)^2 (Z0 from k_prep)
+        GDM_TRY(gemm(ctx, Y, Y, none(), hl(Y2), hl(Y), kZ0b, kZ0a, 0.0f, "ns_gemm"));
+        std::swap(Y, Y2);
         for (int it = 0; it < ctx->mixed_ns_z; ++it) GDM_TRY(ns_step(it + 1 == ctx->mixed_ns_z));
+    }
     ctx->mixed_ns_z_used = orth ? 0 : ctx->mixed_ns_z;
     // FP64 residual refinement of Z (Z s Z = I): Z64 = Z / sqrt(c) in FP64,
     // F = s Z64, E = Z64 F - I, Z64 <- Z64 - Z64 E / 2 (error O(E^2)); E and
@@ -1050,16 +1064,17 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
     GDM_TRY(gemm(ctx, T, Z, slot(ctx, SL_HP), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
     {
         GDM_TIMED(ctx, "mixed_misc");
-        hipLaunchKernelGGL(k_sym_bounds, dim3(P.n_sub), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP), bounds);
+        hipLaunchKernelGGL(k_sym_bounds, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP),
+                           (int)strip_grid(P).y, bounds);
     }
     GDM_LAUNCH_CHECK(ctx);
-    std::vector<double> hb(2 * (size_t)P.n_sub);
+    std::vector<double> hb(2 * (size_t)P.n_sub * strip_grid(P).y);
     GDM_HIP(ctx, hipMemcpyAsync(hb.data(), bounds, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, ctx->stream));
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     double lo = INFINITY, hi = -INFINITY;
-    for (int s = 0; s < P.n_sub; ++s) {
-        lo = std::min(lo, hb[2 * s]);
-        hi = std::max(hi, hb[2 * s + 1]);
+    for (size_t k = 0; k < hb.size(); k += 2) {
+        lo = std::min(lo, hb[k]);
+        hi = std::max(hi, hb[k + 1]);
     }
     if (!std::isfinite(lo) || !std::isfinite(hi)) return gdm_fail(ctx, GDM_E_NAN, "mixed: non-finite spectral bounds");
     // mu: safeguarded Newton steps on the FP64 traces (refined Z, count error
