@@ -181,7 +181,9 @@ int gdm_build_hs(gdm_ctx* ctx, const gdm_system* sys, const gdm_tb_params* tb,
 
 /* Size the workspace for subgraph set `sg` and solver `precision` and record
  * the plan (size buckets, offsets).  The only call of the solve path that
- * allocates.  Required before gdm_find_mu. */
+ * allocates.  Required before gdm_find_mu.  Subgraphs hold at most 8,192
+ * orbitals (GDM_E_ARG otherwise); a failed plan leaves no plan, so the
+ * solve calls then return GDM_E_STATE until a plan succeeds. */
 int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision);
 
 /* Gather every subgraph's principal submatrices h, s from the block-sparse

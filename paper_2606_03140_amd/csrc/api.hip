@@ -163,8 +163,7 @@ extern "C" int gdm_build_graph(gdm_ctx* ctx, const gdm_system* sys, int mode, do
 
 static int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-extern "C" int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
-    if (!ctx) return GDM_E_ARG;
+static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
     if (!sg || sg->n_sub <= 0 || !sg->atom_ptr || !sg->atoms || !sg->n_core || !sg->h_norb || !sg->h_ncore_orb)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_plan: incomplete subgraph set");
     if (precision != GDM_FP64_EIG && precision != GDM_MIXED_F16)
@@ -245,8 +244,15 @@ extern "C" int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
     GDM_HIP(ctx, hipMemcpyAsync(desc, P.desc.data(), sizeof(SubDesc) * ns, hipMemcpyHostToDevice, ctx->stream));
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     P.generation++;
-    ctx->solved = false;
     return GDM_OK;
+}
+
+extern "C" int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
+    if (!ctx) return GDM_E_ARG;
+    ctx->solved = false;
+    const int rc = plan_impl(ctx, sg, precision);
+    if (rc) ctx->plan = Plan();      // a failed plan leaves no plan: the solve calls report GDM_E_STATE
+    return rc;
 }
 
 static int check_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision, const char* who) {
