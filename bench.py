@@ -349,7 +349,7 @@ def main():
         ctx.find_mu(system, part.sg, part.nbr, H, S, wl["kT"], pipeline.MIXED_F16, mu64, 1e9)
         Dm = ctx.subgraph_density(part.sg, mu64, wl["kT"], pipeline.MIXED_F16)
         qm = ctx.mulliken_charges(system, part.sg, part.nbr, S, Dm).cpu().numpy()
-        ctx.set_mixed_options(max_passes=10)
+        ctx.set_mixed_options(max_passes=16)
         out["mixed_vs_fp64"] = {
             "at_fp64_mu": {"max_abs_dD": (Dm - results["fp64"]["D"]).abs().max().item(),
                            "max_abs_dq_e": float(np.abs(qm - results["fp64"]["q"]).max()),

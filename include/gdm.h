@@ -233,7 +233,9 @@ int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
  * iterations per inverse in each doubling after the minimax quadratic start
  * (default 2; the start has error <= 1/99, so k iterations reach
  * (1/99)^(2^k)).  max_passes: expansion
- * passes allowed while matching the electron count (default 10).  Values
+ * passes allowed while matching the electron count (default 16: a cold
+ * start next to subgraph states near mu can need 9 Newton/bisection passes;
+ * a warm start from the previous mu takes 1).  Values
  * <= 0 (ns_z_extra: < 0) keep the current setting. */
 int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes, int ns_z_extra);
 
@@ -249,9 +251,9 @@ int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int64_t* gemm_l
                     double* flops_per_launch, double* bytes_per_launch, int* ns_z_used);
 
 /* Diagnostics: copy the FP32 matrix `which` (0 Z, the inverse-overlap
- * factor before FP64 refinement; 1 h_perp; 2 X, 3 X^2 of the last expansion
- * pass) of subgraph `sub` of the last GDM_MIXED_F16 solve into `out`
- * (device, P*P floats, P the padded size = 64 ceil(n/64)). */
+ * factor before FP64 refinement; 1 h_perp; 2 X of the last expansion pass)
+ * of subgraph `sub` of the last GDM_MIXED_F16 solve into `out` (device, P*P
+ * floats, P the padded size = 64 ceil(n/64)). */
 int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out);
 
 /* -------------------------------------------- SCC shell: Coulomb and mixing */

@@ -71,7 +71,7 @@ struct gdm_ctx {
     int mixed_ns_z_extra = 8;    // iterations that may be added while the residual is too large
     int mixed_ns_z_used = 0;     // iterations the last find_mu took
     int mixed_ns_inv = 2;        // Newton-Schulz iterations per inverse after the quadratic start
-    int mixed_max_passes = 10;   // expansion passes allowed for mu
+    int mixed_max_passes = 16;   // expansion passes allowed for mu
     int64_t mixed_tiles = 0, mixed_tiles_sym = 0, mixed_tiles_core = 0;
     double mixed_flops_full = 0, mixed_flops_sym = 0;  // one product per launch
     double mixed_flops = 0;      // summed over the launches of the last find_mu

@@ -714,17 +714,16 @@ __global__ void __launch_bounds__(256) k_sym_pair(const SubDesc* __restrict__ de
 enum { SL_H = 0, SL_Y, SL_Z, SL_T, SL_Y2, SL_Z2, SL_HP, SL_X, SL_X2, SL_A, SL_R, SL_YI, SL_COUNT };
 
 // Every slot holds the FP16 hi/lo split; only the matrices read back in FP32
-// (the inverse-overlap factor and its Newton-Schulz partner, h_perp, X and
-// X^2) also keep an FP32 copy.  Slots without one have f = nullptr, which
-// every writer skips.
-constexpr int kF32Slots = 5;
+// (the inverse-overlap factor and its Newton-Schulz partner, h_perp and X)
+// also keep an FP32 copy.  Slots without one have f = nullptr, which every
+// writer skips.
+constexpr int kF32Slots = 4;
 static int f32_index(int k) {
     switch (k) {
         case SL_Z: return 0;
         case SL_Z2: return 1;
         case SL_HP: return 2;
         case SL_X: return 3;
-        case SL_X2: return 4;
         default: return -1;
     }
 }
@@ -851,15 +850,17 @@ static SplitMat hist(gdm_ctx* ctx, int k, int which) {
     return SplitMat{nullptr, (_Float16*)ctx->b[BUF_HIST_HI].p + off, (_Float16*)ctx->b[BUF_HIST_LO].p + off};
 }
 
-// One full recursive expansion at chemical potential mu; leaves X in SL_X and
-// X^2 in SL_X2.  With a history buffer large enough for the nd doublings,
+// One full recursive expansion at chemical potential mu; leaves X (with its
+// FP32 copy) in SL_X.  With a history buffer large enough for the nd doublings,
 // every X_k and Y_k is kept there (the products write into the history in
 // place of the working slots, so recording adds no traffic).
 static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, int* nd_out) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
+    // X0 = I/2 - (b/4)(h_perp - mu I) must have its spectrum in [0, 1], i.e.
+    // b R <= 2 with R the spectral half-width about mu: n_d = ceil(log2(beta R / 2))
     const double R = std::max(std::fabs(lo - mu), std::fabs(hi - mu));
-    int nd = (int)std::ceil(std::log2(beta * R));
+    int nd = (int)std::ceil(std::log2(0.5 * beta * R));
     nd = std::max(1, std::min(nd, 40));
     const double b = beta / std::ldexp(1.0, nd);
     *nd_out = nd;
@@ -895,8 +896,6 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
         const SplitMat Xn = it + 1 == nd ? X : (rec ? hist(ctx, it + 1, 0) : hl(X));
         GDM_TRY(gemm(ctx, X2, Y, Xn, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
     }
-    // X^2 of the final X (for N'(mu) and the first-order mu correction)
-    GDM_TRY(gemm(ctx, X, X, X2, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
     if (rec) ctx->mixed_rec_nd = nd;
     return GDM_OK;
 }
@@ -940,7 +939,7 @@ static int traces(gdm_ctx* ctx, double* N, double* M) {
     double* G2 = fp64_region(ctx, 3);
     double* V = fp64_region(ctx, 0);
     GDM_TRY(gemm64_core<float>(ctx, z64(ctx), slot(ctx, SL_X).f, G, "traces"));
-    GDM_TRY(gemm64_core<float>(ctx, z64(ctx), slot(ctx, SL_X2).f, G2, "traces"));
+    GDM_TRY(gemm64_core<float>(ctx, G, slot(ctx, SL_X).f, G2, "traces"));     // Z[core,:] X^2 = G X
     {
         GDM_TIMED(ctx, "traces");
         hipLaunchKernelGGL(k_trace_dot, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, G, G2, V, part);
@@ -1288,8 +1287,8 @@ extern "C" int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int6
 extern "C" int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out) {
     if (!ctx) return GDM_E_ARG;
     const Plan& P = ctx->plan;
-    static const int kDebugSlots[4] = {SL_Z, SL_HP, SL_X, SL_X2};
-    if (P.precision != GDM_MIXED_F16 || which < 0 || which >= 4 || sub < 0 || sub >= P.n_sub || !out)
+    static const int kDebugSlots[3] = {SL_Z, SL_HP, SL_X};
+    if (P.precision != GDM_MIXED_F16 || which < 0 || which >= 3 || sub < 0 || sub >= P.n_sub || !out)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_debug_slot: bad argument");
     const SubDesc& d = P.desc[sub];
     GDM_HIP(ctx, hipMemcpyAsync(out, slot(ctx, kDebugSlots[which]).f + d.off2, sizeof(float) * (size_t)d.ld * d.ld,

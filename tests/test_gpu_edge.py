@@ -102,7 +102,7 @@ def test_one_large_subgraph_mixed(c):
         D = c.subgraph_density(part.sg, ref.mu, 0.1, pipeline.MIXED_F16)
         q = c.mulliken_charges(sysm, part.sg, part.nbr, S, D).cpu().numpy()
     finally:
-        c.set_mixed_options(max_passes=10)
+        c.set_mixed_options(max_passes=16)
     err_d = np.abs(unpack_dcore(part.sg, D)[0] - ref.d_core[0]).max()
     err_q = np.abs(q - ref.q).max()
     st = c.mixed_stats()

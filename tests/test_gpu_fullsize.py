@@ -64,7 +64,7 @@ def test_fullsize_fp64_and_mixed(c, nw, seed, grid):
         Dm = c.subgraph_density(part.sg, ref.mu, 0.1, pipeline.MIXED_F16)
         qm = c.mulliken_charges(sysm, part.sg, part.nbr, S, Dm).cpu().numpy()
     finally:
-        c.set_mixed_options(max_passes=10)
+        c.set_mixed_options(max_passes=16)
     md = unpack_dcore(part.sg, Dm)
     err_dm = max(np.abs(a - b).max() for a, b in zip(md, ref.d_core))
     err_qm = np.abs(qm - ref.q).max()

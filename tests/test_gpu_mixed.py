@@ -63,7 +63,7 @@ def test_mixed_mu_search_from_far_guess(c):
     ref = osv.solve_system(box.pos, box.species, L, oracle_model(False), subs)
     c.set_mixed_options(max_passes=16)
     sol = pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.MIXED_F16, mu_guess=-15.0, tol_N=1e-6)
-    c.set_mixed_options(max_passes=10)
+    c.set_mixed_options(max_passes=16)
     st = c.mixed_stats()
     err_q = np.abs(sol.q.cpu().numpy() - ref.q).max()
     log(f"  passes {st['passes']} mu {sol.mu:.6f} N {sol.n_count:.9f} max|dq| {err_q:.2e}")
