@@ -270,15 +270,40 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
 // half of a diagonal tile taken from its upper half, so C is exactly
 // symmetric (Cin must then be symmetric too).
 typedef double double4v __attribute__((ext_vector_type(4)));
-constexpr int kK64 = 16;
+// FP64 MFMA GEMM C = alpha A B + beta Cin + gamma I on 64 x 64 output tiles
+// (four waves of 32 x 32, each 2 x 2 v_mfma_f64_16x16x4f64 blocks).  Operands
+// stream through LDS in k-slabs of 32: each thread loads 8 consecutive
+// elements of A and of B with 16-byte loads, and the next slab is held in
+// registers while the current one is multiplied.  LDS rows are padded to 36
+// (A) and 80 (B) doubles, so the operand reads of a wave (rows fr, k fk of
+// A; k fk, columns fr of B) hit every bank exactly twice.  The tile is staged
+// in LDS (row stride 65) and written as coalesced rows; SYM (products of
+// commuting symmetric matrices, upper tiles only) also writes the mirror
+// tile from the transposed LDS read, and on a diagonal tile takes both
+// halves from the upper triangle, so C is exactly symmetric.
+constexpr int kK64 = 32;
+constexpr int kA64Row = kK64 + 4;        // doubles per LDS row of the A slab
+constexpr int kB64Row = 64 + 16;         // doubles per LDS row of the B slab
+constexpr int kC64Row = 64 + 1;          // doubles per LDS row of the staged tile
+constexpr int kG64Lds = 64 * kA64Row + kK64 * kB64Row;    // doubles
+
+__device__ __forceinline__ void load8(const double* p, double* v) {
+    const double4 x = *(const double4*)p, y = *(const double4*)(p + 4);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w; v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+}
+__device__ __forceinline__ void load8(const float* p, double* v) {
+    const float4 x = *(const float4*)p, y = *(const float4*)(p + 4);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w; v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+}
 
 template <typename TA, typename TB, bool SYM>
 __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
                                                const TA* __restrict__ A, const TB* __restrict__ B,
                                                const double* __restrict__ Cin, double* __restrict__ C,
                                                double alpha, double beta, double gamma) {
-    __shared__ double sA[64][kK64 + 1];
-    __shared__ double sB[kK64][64 + 1];
+    __shared__ double lds[kG64Lds];
+    double* sA = lds;                        // [64][kA64Row]
+    double* sB = lds + 64 * kA64Row;         // [kK64][kB64Row]
     const int4 tl = tiles[blockIdx.x];
     if (tl.x < 0) return;
     const SubDesc d = desc[tl.x];
@@ -289,54 +314,70 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int fr = lane & 15, fk = lane >> 4;
+    // this thread's share of a slab: A row ra, columns ca..ca+7; B row rb, columns cb..cb+7
+    const int ra = t >> 2, ca = (t & 3) * 8;
+    const int rb = t >> 3, cb = (t & 7) * 8;
+    const TA* pa = A + base + (int64_t)(m0 + ra) * P + ca;
+    const TB* pb = B + base + (int64_t)rb * P + n0 + cb;
+    double va[8], vb[8];
+    load8(pa, va);
+    load8(pb, vb);
     double4v acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = double4v{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < P; k0 += kK64) {
         __syncthreads();
-        for (int e = t; e < 64 * kK64; e += 256) {
-            const int r = e >> 4, k = e & 15;             // A: row m0+r, col k0+k
-            sA[r][k] = (double)A[base + (int64_t)(m0 + r) * P + k0 + k];
-            const int kb = e >> 6, c = e & 63;            // B: row k0+kb, col n0+c
-            sB[kb][c] = (double)B[base + (int64_t)(k0 + kb) * P + n0 + c];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            sA[ra * kA64Row + ca + q] = va[q];
+            sB[rb * kB64Row + cb + q] = vb[q];
         }
         __syncthreads();
+        if (k0 + kK64 < P) {
+            load8(pa + k0 + kK64, va);
+            load8(pb + (int64_t)(k0 + kK64) * P, vb);
+        }
+#pragma unroll
         for (int kk = 0; kk < kK64; kk += 4) {
             double a[2], b[2];
-            for (int i = 0; i < 2; ++i) a[i] = sA[wm * 32 + i * 16 + fr][kk + fk];
-            for (int j = 0; j < 2; ++j) b[j] = sB[kk + fk][wn * 32 + j * 16 + fr];
+            for (int i = 0; i < 2; ++i) a[i] = sA[(wm * 32 + i * 16 + fr) * kA64Row + kk + fk];
+            for (int j = 0; j < 2; ++j) b[j] = sB[(kk + fk) * kB64Row + wn * 32 + j * 16 + fr];
             for (int i = 0; i < 2; ++i)
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     }
-    // accumulator register r of lane l: element (4 r + fk, fr) of its 16 x 16
-    // block; rows of 16 consecutive columns per store.  SYM: the mirror image
-    // (fr, 4 r + fk) is stored too; on a diagonal tile only the upper half is
-    // taken, for both the element and its mirror, so C is exactly symmetric.
-    const bool diag = SYM && tl.y == tl.z;
+    // stage the tile: accumulator register r of lane l is element (4 r + fk, fr)
+    // of its 16 x 16 block
+    __syncthreads();
+    double* sC = lds;                        // [64][kC64Row]
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm * 32 + i * 16 + 4 * r + fk, n = n0 + wn * 32 + j * 16 + fr;
-                const double x = acc[i][j][r];
-                if (!diag || m <= n) {
-                    const int64_t idx = base + (int64_t)m * P + n;
-                    double v = alpha * x;
-                    if (Cin) v += beta * Cin[idx];
-                    if (m == n) v += gamma;
-                    C[idx] = v;
-                }
-                if (SYM && (!diag || m < n)) {
-                    const int64_t idx = base + (int64_t)n * P + m;
-                    double v = alpha * x;
-                    if (Cin) v += beta * Cin[idx];
-                    C[idx] = v;
-                }
-            }
+            for (int r = 0; r < 4; ++r)
+                sC[(wm * 32 + i * 16 + 4 * r + fk) * kC64Row + wn * 32 + j * 16 + fr] = acc[i][j][r];
+    __syncthreads();
+    const bool diag = SYM && tl.y == tl.z;
+    for (int e = t; e < 64 * 64; e += 256) {
+        const int m = e >> 6, n = e & 63;
+        // on a diagonal tile of a symmetric product both halves come from m <= n
+        const double x = (diag && m > n) ? sC[n * kC64Row + m] : sC[m * kC64Row + n];
+        const int64_t idx = base + (int64_t)(m0 + m) * P + n0 + n;
+        double v = alpha * x;
+        if (Cin) v += beta * Cin[idx];
+        if (m0 + m == n0 + n) v += gamma;
+        C[idx] = v;
+    }
+    if (SYM && !diag)
+        for (int e = t; e < 64 * 64; e += 256) {
+            const int nn = e >> 6, mm = e & 63;      // mirror tile row n0 + nn, column m0 + mm
+            const int64_t idx = base + (int64_t)(n0 + nn) * P + m0 + mm;
+            double v = alpha * sC[mm * kC64Row + nn];
+            if (Cin) v += beta * Cin[idx];
+            C[idx] = v;
+        }
 }
 
 // Z (FP16 hi/lo split) <- Z64, flat over every packed tile (padding included)
