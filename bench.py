@@ -42,7 +42,7 @@ def fp64_flops(n: np.ndarray, nc: np.ndarray) -> dict:
         "potrf": float(np.sum(n ** 3 / 3)),
         "trsm": float(np.sum(n ** 3)),          # per launch (two launches)
         "sytrd": float(np.sum(4.0 * n ** 3 / 3)),
-        "core_vectors": float(np.sum(8 * nc * n * n + 12 * 0.8 * n * n * 2 * nc)),
+        "core_rows": float(np.sum(8 * nc * n * n + 12 * 0.8 * n * n * 2 * nc)),
         "dcore": float(np.sum(4 * nc * n * n + 6 * 0.8 * n * n * nc + nc * n * n)),
         "total_nominal": float(np.sum(6.7 * n ** 3)),
     }
@@ -71,7 +71,7 @@ def time_path(ctx, system, part, H, S, kT, precision, steps, warmup, mu_guess=0.
     wall = time.perf_counter() - w0
     ms = t0.elapsed_time(t1) / steps
     prof = {}
-    for name in ("gather", "potrf", "trsm", "symmetrize", "sytrd", "steqr", "core_vectors", "dcore", "mu",
+    for name in ("gather", "potrf", "trsm", "symmetrize", "sytrd", "steqr", "core_rows", "dcore", "mu",
                  "mulliken", "foe_gemm", "ns_gemm", "mixed_misc", "refine64", "traces"):
         tot, n = ctx.profile_query(name)
         if n:

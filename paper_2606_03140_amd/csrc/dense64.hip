@@ -621,7 +621,7 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
             chunks = std::max(chunks, (2 * dd.nc + rcn - 1) / rcn);
         }
         if ((rc = set_lds(ctx, (const void*)k_core_rows, lds_rows))) return rc;
-        GDM_TIMED(ctx, "core_vectors");
+        GDM_TIMED(ctx, "core_rows");
         hipLaunchKernelGGL(k_core_rows, dim3(ns, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, Sd, A, Tau,
                            RotC, RotS, RotI, RotN, G);
         GDM_LAUNCH_CHECK(ctx);
