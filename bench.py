@@ -33,7 +33,7 @@ def log(msg):
 
 
 def fp64_flops(n: np.ndarray, nc: np.ndarray) -> dict:
-    """Nominal FP64 flops of the executed route per subgraph (see DESIGN.md):
+    """Nominal FP64 flops of the executed route per subgraph:
     Cholesky n^3/3, two triangular solves 2 n^3, tridiagonalisation 4/3 n^3,
     core-row back-transforms O(nc n^2)."""
     n = n.astype(np.float64)

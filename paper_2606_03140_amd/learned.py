@@ -3,9 +3,10 @@
 Per-atom radial descriptors (16 Gaussians x 2 neighbour species, 5 A
 cutoff) feed one 32-64-64-1 SiLU network per central species; the
 prediction, shifted to zero net charge, starts the SCC iteration in place of
-zero charges (the plain loop stays the fallback and judges the guess by its
-residual).  Training runs the FP32 forward, loss, backward and Adam kernels
-of libgdm; inference runs the BF16 forward.  Only orchestration lives here.
+zero charges (the plain loop stays the fallback; the number of iterations
+each start takes measures the guess).  Training runs the FP32 forward,
+loss, backward and Adam kernels of libgdm; inference runs the BF16 forward.
+Only orchestration lives here.
 """
 from __future__ import annotations
 
