@@ -600,13 +600,13 @@ __global__ void __launch_bounds__(kEw) k_sym_bounds(const SubDesc* __restrict__ 
     }
 }
 
-// X0 = I/2 - (b/4)(H - mu I) on the n x n block, zero padding
+// X <- c0 I - q (H - mu I) on the n x n block, zero padding (the linear start
+// X0 = I/2 - (b/4)(H - mu I), or K = b (H - mu I) for the cubic start)
 __global__ void __launch_bounds__(kEw) k_x0(const SubDesc* __restrict__ desc, const float* __restrict__ Hf,
-                                           SplitMat X, double mu, double b) {
+                                           SplitMat X, double mu, double q, double c0) {
     const SubDesc d = desc[blockIdx.x];
     const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
     if (r0 >= P) return;
-    const double q = b / 4.0;
     const int q4 = P >> 2;
     for (int e = threadIdx.x; e < 64 * q4; e += kEw) {
         const int i = r0 + e / q4, j0 = (e % q4) * 4;
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(kEw) k_x0(const SubDesc* __restrict__ desc, co
         float v[4];
         for (int k = 0; k < 4; ++k) {
             const int j = j0 + k;
-            v[k] = (i < n && j < n) ? (float)((i == j ? 0.5 : 0.0) - q * ((double)hs[k] - (i == j ? mu : 0.0))) : 0.f;
+            v[k] = (i < n && j < n) ? (float)((i == j ? c0 : 0.0) - q * ((double)hs[k] - (i == j ? mu : 0.0))) : 0.f;
         }
         store4(X, idx, make_float4(v[0], v[1], v[2], v[3]));
     }
@@ -898,10 +898,18 @@ static SplitMat hist(gdm_ctx* ctx, int k, int which) {
 static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, int* nd_out) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
-    // X0 = I/2 - (b/4)(h_perp - mu I) must have its spectrum in [0, 1], i.e.
-    // b R <= 2 with R the spectral half-width about mu: n_d = ceil(log2(beta R / 2))
+    // Each doubling maps X = f(u) to f(2u) (f the Fermi function), so n_d
+    // doublings from X0 = f(u0) give f(2^n_d u0), and u0 must be b (h - mu),
+    // b = beta / 2^n_d, to first order near mu, with X0's spectrum in [0, 1].
+    // The linear start X0 = I/2 - (b/4)(h - mu I) needs b R <= 2 (R the
+    // spectral half-width about mu); the cubic start with K = b (h - mu I),
+    // X0 = I/2 - K/4 + K^3/108, stays in [0, 1] for b R <= 4 (its minimum, 0,
+    // is at K = +-3), which saves one doubling (7 products) for 2.  The
+    // response differentiates the linear start, so a recorded pass uses it.
     const double R = std::max(std::fabs(lo - mu), std::fabs(hi - mu));
-    int nd = (int)std::ceil(std::log2(0.5 * beta * R));
+    const bool rec_wanted = ctx->mixed_rec_cap > 0;
+    const bool cubic = !rec_wanted;
+    int nd = (int)std::ceil(std::log2((cubic ? 0.25 : 0.5) * beta * R));
     nd = std::max(1, std::min(nd, 40));
     const double b = beta / std::ldexp(1.0, nd);
     *nd_out = nd;
@@ -910,10 +918,20 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
     ctx->mixed_x0_slope = b / 4.0;
     SplitMat X = slot(ctx, SL_X), X2 = slot(ctx, SL_X2), A = slot(ctx, SL_A), Rm = slot(ctx, SL_R);
     const SplitMat Ya = slot(ctx, SL_Y), Yb = slot(ctx, SL_YI);
-    {
+    if (cubic) {
+        const SplitMat K = slot(ctx, SL_T);
+        {
+            GDM_TIMED(ctx, "mixed_misc");
+            hipLaunchKernelGGL(k_x0, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP).f, hl(K), mu, -b,
+                               0.0);
+        }
+        GDM_LAUNCH_CHECK(ctx);
+        GDM_TRY(gemm(ctx, K, K, hl(Rm), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
+        GDM_TRY(gemm(ctx, K, Rm, none(), hl(X), hl(K), 1.0f / 108.0f, -0.25f, 0.5f, "foe_gemm"));
+    } else {
         GDM_TIMED(ctx, "mixed_misc");
         hipLaunchKernelGGL(k_x0, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP).f,
-                           rec ? hist(ctx, 0, 0) : X, mu, b);
+                           rec ? hist(ctx, 0, 0) : X, mu, b / 4.0, 0.5);
     }
     GDM_LAUNCH_CHECK(ctx);
     const int ns = ctx->mixed_ns_inv;
