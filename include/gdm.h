@@ -30,6 +30,14 @@
  *   its orbitals follow its atoms.
  * - Density matrices are per spin (occupations in [0, 1]); the electron count
  *   is 2 Tr[D S] (the paper writes Tr[D] = N_occ for an orthonormal basis).
+ * - Stream capture: after gdm_find_mu, gdm_subgraph_density and
+ *   gdm_mulliken_charges enqueue kernels only (no allocation, host
+ *   synchronisation or memset), so both may be captured into a hipGraph on
+ *   a non-default stream and replayed; a replay reads the context's state of
+ *   the last gdm_find_mu and the mu given at capture.  gdm_find_mu itself is
+ *   not capturable: the mixed path decides expansion passes, doubling counts
+ *   and inverse-overlap iterations on the host, and both paths return mu to
+ *   a HOST pointer.
  */
 #ifndef GDM_H
 #define GDM_H
