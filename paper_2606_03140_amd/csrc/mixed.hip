@@ -883,6 +883,16 @@ static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, 
     return GDM_OK;
 }
 
+// Coefficients a3, a5, a7 of the degree-7 start X0 = 1/2 - K/4 + a3 K^3 +
+// a5 K^5 + a7 K^7 of the expansion, K = b (h - mu I) with |K| <= 8: chosen
+// (minimax, numerically) so that after n_d >= 5 doublings the occupations
+// f(2^n_d u0(K)), u0 = log((1 - X0) / X0), differ from f(2^n_d K) by at most
+// 6.1e-8 over the whole range, with X0 in (0, 1/2) for K in (0, 8] (odd
+// about 1/2).  a3 is close to the Taylor value 1/48 of the Fermi function,
+// which keeps the states near mu exact to high order; the start is not
+// monotone in K, which the doublings do not need.
+static constexpr float kStart7[3] = {0.0208103713f, -0.000615022611f, 5.41684949e-06f};
+
 // Doubling history for the charge response: X_k (which = 0), the input of
 // doubling k, and Y_k (which = 1), its inverse (2 X_k^2 - 2 X_k + I)^-1, as
 // FP16 hi/lo pairs.
@@ -908,8 +918,13 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
     // response differentiates the linear start, so a recorded pass uses it.
     const double R = std::max(std::fabs(lo - mu), std::fabs(hi - mu));
     const bool rec_wanted = ctx->mixed_rec_cap > 0;
-    const bool cubic = !rec_wanted;
-    int nd = (int)std::ceil(std::log2((cubic ? 0.25 : 0.5) * beta * R));
+    // The degree-7 start of kStart7 reaches b R <= 8 (one doubling fewer than
+    // the cubic for two more products) but is tuned for at least 5 doublings:
+    // states near |K| = 8 start well inside (0, 1/2) and need them to settle.
+    const int nd7 = (int)std::ceil(std::log2(0.125 * beta * R));
+    const bool septic = !rec_wanted && nd7 >= 5;
+    const bool cubic = !rec_wanted && !septic;
+    int nd = septic ? nd7 : (int)std::ceil(std::log2((cubic ? 0.25 : 0.5) * beta * R));
     nd = std::max(1, std::min(nd, 40));
     const double b = beta / std::ldexp(1.0, nd);
     *nd_out = nd;
@@ -918,7 +933,7 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
     ctx->mixed_x0_slope = b / 4.0;
     SplitMat X = slot(ctx, SL_X), X2 = slot(ctx, SL_X2), A = slot(ctx, SL_A), Rm = slot(ctx, SL_R);
     const SplitMat Ya = slot(ctx, SL_Y), Yb = slot(ctx, SL_YI);
-    if (cubic) {
+    if (septic || cubic) {
         const SplitMat K = slot(ctx, SL_T);
         {
             GDM_TIMED(ctx, "mixed_misc");
@@ -926,8 +941,16 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
                                0.0);
         }
         GDM_LAUNCH_CHECK(ctx);
-        GDM_TRY(gemm(ctx, K, K, hl(Rm), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
-        GDM_TRY(gemm(ctx, K, Rm, none(), hl(X), hl(K), 1.0f / 108.0f, -0.25f, 0.5f, "foe_gemm"));
+        if (septic) {
+            // X0 = I/2 - K/4 + K (K^2 (K^2 (a7 K^2 + a5 I) + a3 I)), four products
+            GDM_TRY(gemm(ctx, K, K, hl(Rm), hl(A), none(), kStart7[2], 0.0f, kStart7[1], "foe_gemm"));
+            GDM_TRY(gemm(ctx, Rm, A, none(), hl(Ya), none(), 1.0f, 0.0f, kStart7[0], "foe_gemm"));
+            GDM_TRY(gemm(ctx, Rm, Ya, hl(Yb), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
+            GDM_TRY(gemm(ctx, K, Yb, none(), hl(X), hl(K), 1.0f, -0.25f, 0.5f, "foe_gemm"));
+        } else {
+            GDM_TRY(gemm(ctx, K, K, hl(Rm), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
+            GDM_TRY(gemm(ctx, K, Rm, none(), hl(X), hl(K), 1.0f / 108.0f, -0.25f, 0.5f, "foe_gemm"));
+        }
     } else {
         GDM_TIMED(ctx, "mixed_misc");
         hipLaunchKernelGGL(k_x0, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP).f,
