@@ -34,10 +34,13 @@
  *   gdm_mulliken_charges enqueue kernels only (no allocation, host
  *   synchronisation or memset), so both may be captured into a hipGraph on
  *   a non-default stream and replayed; a replay reads the context's state of
- *   the last gdm_find_mu and the mu given at capture.  gdm_find_mu itself is
- *   not capturable: the mixed path decides expansion passes, doubling counts
- *   and inverse-overlap iterations on the host, and both paths return mu to
- *   a HOST pointer.
+ *   the last gdm_find_mu and the mu given at capture.  On the FP64_EIG path
+ *   with gdm_set_mu_outputs(ctx, 1), gdm_find_mu enqueues kernels only as
+ *   well, so the whole solve (gather, factorisation, eigensolver, mu search,
+ *   gdm_subgraph_density_dmu at the device mu, charges) captures into one
+ *   graph that a replay runs on the current contents of H and S.  The mixed path's
+ *   gdm_find_mu is not capturable: it decides expansion passes, doubling
+ *   counts and inverse-overlap iterations on the host.
  */
 #ifndef GDM_H
 #define GDM_H
@@ -203,13 +206,26 @@ int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision);
  * FP64 core traces with a bisection safeguard, one full expansion per pass,
  * until |N - n_electrons| <= max(tol_N, 1e-7 n_electrons) (the rounding
  * level of the traces); if the pass budget runs out first, the first-order
- * correction mu + (n_electrons - N)/N'(mu) is applied when it lies within kT.  *mu_out, *n_out HOST.  The factorisation
- * / expansion state is cached in the context for gdm_subgraph_density. */
+ * correction mu + (n_electrons - N)/N'(mu) is applied when it lies within kT.  *mu_out, *n_out HOST (DEVICE
+ * scalars after gdm_set_mu_outputs(ctx, 1), FP64_EIG only).  The
+ * factorisation / expansion state is cached in the context for
+ * gdm_subgraph_density. */
 int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
                 const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                 const double* H, const double* S, double n_electrons, double kT,
                 int precision, double mu_guess, double tol_N,
                 double* mu_out, double* n_out);
+
+/* Where gdm_find_mu puts mu and N(mu).  device = 0 (default): HOST pointers;
+ * the call synchronises the stream and checks the electron count on the
+ * host.  device = 1: DEVICE pointers to one double each, FP64_EIG only
+ * (MIXED_F16 returns GDM_E_ARG); the whole search is enqueued without host
+ * synchronisation, so gdm_find_mu can be captured into a hipGraph with the
+ * density and charge calls, and a count off by more than 1e-6 n_electrons (or
+ * a NaN) is recorded in the device status word, reported by gdm_check.  A
+ * setting of the context, kept until changed.  Returns GDM_E_ARG for other
+ * values of device. */
+int gdm_set_mu_outputs(gdm_ctx* ctx, int device);
 
 /* Collected core rows D[core, :] of every subgraph (Eq. 3) at chemical
  * potential mu, from the state cached by gdm_find_mu (same precision).
@@ -218,6 +234,15 @@ int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
  * eig_out (nullable): FP64_EIG only, eigenvalues packed at sum_{t<s} n_t. */
 int gdm_subgraph_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT,
                          int precision, double* D_core, double* eig_out);
+
+/* gdm_subgraph_density on the FP64_EIG path at a chemical potential held in
+ * DEVICE memory (*mu_device, read when the kernel runs), e.g. the mu_out of
+ * a gdm_find_mu in device-output mode (gdm_set_mu_outputs), so that a
+ * captured graph of gdm_find_mu, this call and gdm_mulliken_charges uses the
+ * mu each replay finds.  D_core as for gdm_subgraph_density.  GDM_E_ARG for
+ * other precisions or null pointers; GDM_E_STATE before gdm_find_mu. */
+int gdm_subgraph_density_dmu(gdm_ctx* ctx, const gdm_subgraphs* sg, const double* mu_device, double kT,
+                             int precision, double* D_core);
 
 /* Mulliken charges from the collected core rows (SI section D):
  * q_I = 2 sum_{a in I} sum_b D_ab S_ba - n0[species_I] for every atom (each

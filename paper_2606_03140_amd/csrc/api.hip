@@ -236,6 +236,10 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         gdm_buf(ctx, BUF_CC, sizeof(double) * P.totc, &ok);
         gdm_buf(ctx, BUF_MU, sizeof(double) * 8, &ok);
         gdm_buf(ctx, BUF_MUPART, sizeof(double) * 256 * (size_t)ns, &ok);
+        if (ok) {
+            const int rc = gdm_fp64_plan_lds(ctx);
+            if (rc) return rc;
+        }
     } else {
         int rc = gdm_mixed_plan(ctx);
         if (rc) return rc;
@@ -279,6 +283,8 @@ extern "C" int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgra
     if (n_electrons >= cap)
         return gdm_fail(ctx, GDM_E_NO_BRACKET, "gdm_find_mu: %g electrons do not fit in %g core spin-orbitals",
                         n_electrons, cap);
+    if (ctx->mu_out_device && precision != GDM_FP64_EIG)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_find_mu: device outputs exist only for GDM_FP64_EIG");
     ctx->solved = false;
     (void)hipGetLastError();   // a stale error of an earlier, unrelated call must not be blamed here
     if (precision == GDM_FP64_EIG)
@@ -287,6 +293,15 @@ extern "C" int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgra
         rc = gdm_mixed_find_mu(ctx, sys, sg, row_ptr, col, nnz, H, S, n_electrons, kT, mu_guess, tol_N, mu_out,
                                n_out);
     if (rc) return rc;
+    if (ctx->mu_out_device) {
+        // enqueued only: mu and N are written on the stream, and a count or
+        // NaN failure is left in the status word for gdm_check
+        ctx->solved = true;
+        ctx->solved_precision = precision;
+        ctx->mu_solved = NAN;
+        ctx->kT_solved = kT;
+        return GDM_OK;
+    }
     if ((rc = gdm_check(ctx))) return rc;
     if (!std::isfinite(*mu_out) || !std::isfinite(*n_out)) return gdm_fail(ctx, GDM_E_NAN, "gdm_find_mu: NaN result");
     const double tol = precision == GDM_FP64_EIG ? 1e-6 * std::max(1.0, n_electrons)
@@ -301,6 +316,13 @@ extern "C" int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgra
     return GDM_OK;
 }
 
+extern "C" int gdm_set_mu_outputs(gdm_ctx* ctx, int device) {
+    if (!ctx) return GDM_E_ARG;
+    if (device != 0 && device != 1) return gdm_fail(ctx, GDM_E_ARG, "gdm_set_mu_outputs: device must be 0 or 1");
+    ctx->mu_out_device = device;
+    return GDM_OK;
+}
+
 extern "C" int gdm_subgraph_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT, int precision,
                                     double* D_core, double* eig_out) {
     if (!ctx) return GDM_E_ARG;
@@ -310,9 +332,23 @@ extern "C" int gdm_subgraph_density(gdm_ctx* ctx, const gdm_subgraphs* sg, doubl
         return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density: null output or bad mu / kT");
     if (!ctx->solved || ctx->solved_precision != precision)
         return gdm_fail(ctx, GDM_E_STATE, "gdm_subgraph_density: call gdm_find_mu first");
-    if (precision == GDM_FP64_EIG) return gdm_fp64_density(ctx, sg, mu, kT, D_core, eig_out);
+    if (precision == GDM_FP64_EIG) return gdm_fp64_density(ctx, sg, mu, nullptr, kT, D_core, eig_out);
     if (eig_out) return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density: eigenvalues exist only for FP64_EIG");
     return gdm_mixed_density(ctx, sg, mu, kT, D_core);
+}
+
+extern "C" int gdm_subgraph_density_dmu(gdm_ctx* ctx, const gdm_subgraphs* sg, const double* mu_device, double kT,
+                                        int precision, double* D_core) {
+    if (!ctx) return GDM_E_ARG;
+    int rc;
+    if ((rc = check_plan(ctx, sg, precision, "gdm_subgraph_density_dmu"))) return rc;
+    if (!D_core || !mu_device || !(kT > 0.0))
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density_dmu: null argument or bad kT");
+    if (precision != GDM_FP64_EIG)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density_dmu: only GDM_FP64_EIG reads mu from device memory");
+    if (!ctx->solved || ctx->solved_precision != precision)
+        return gdm_fail(ctx, GDM_E_STATE, "gdm_subgraph_density_dmu: call gdm_find_mu first");
+    return gdm_fp64_density(ctx, sg, 0.0, mu_device, kT, D_core, nullptr);
 }
 
 extern "C" int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,

@@ -10,6 +10,9 @@
 // The basis Z = L^-T gives the same D as Z = s^-1/2 (any Z with Z Z^T = s^-1).
 #include "gdm_internal.h"
 
+#include <map>
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 
@@ -406,9 +409,11 @@ __global__ void __launch_bounds__(kRowThreads) k_dcore(const SubDesc* __restrict
                                                   const double* __restrict__ Tau, const double* __restrict__ RotC,
                                                   const double* __restrict__ RotS, const int32_t* __restrict__ RotI,
                                                   const int64_t* __restrict__ RotN, const double* __restrict__ G,
-                                                  const double* __restrict__ Lam, double mu, double beta,
+                                                  const double* __restrict__ Lam, double mu_host,
+                                                  const double* __restrict__ mu_dev, double beta,
                                                   double* __restrict__ Dout, double* __restrict__ EigOut) {
     extern __shared__ double rows[];
+    const double mu = mu_dev ? *mu_dev : mu_host;      // mu from device memory when given
     const SubDesc d = desc[blockIdx.x];
     const int n = d.n, nc = d.nc, ld = d.ld, R2 = 2 * nc;
     const int RC = chunk_rows(n), S = n + 1;
@@ -547,14 +552,70 @@ __global__ void __launch_bounds__(kMuK) k_mu_pick(int n_sub, const double* __res
     }
 }
 
+// Final step of the device-output mode of the search: copy mu and N(mu) to
+// the caller's device scalars and raise the status word when the count
+// misses n_e by more than tol (or is not finite).
+__global__ void k_mu_out(const double* __restrict__ state, double n_e, double tol, double* __restrict__ mu_out,
+                         double* __restrict__ n_out, int* __restrict__ status) {
+    if (threadIdx.x != 0) return;
+    const double mu = state[2], n = state[3];
+    mu_out[0] = mu;
+    n_out[0] = n;
+    if (!isfinite(mu) || !isfinite(n)) gdm_raise(status, GDM_STATUS_NAN);
+    else if (fabs(n - n_e) > tol) gdm_raise(status, GDM_STATUS_NO_BRACKET);
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- host
 
+// Dynamic LDS above 64 KiB needs the kernel attribute raised first.  The
+// largest value set so far is remembered per device and kernel, so the
+// attribute call happens at plan time and never inside a solve call (which
+// may be under stream capture).
 static int set_lds(gdm_ctx* ctx, const void* fn, size_t bytes) {
-    if (bytes > 64 * 1024)
-        GDM_HIP(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    if (bytes <= 64 * 1024) return GDM_OK;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, size_t> raised;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& have = raised[{ctx->device, fn}];
+    if (bytes <= have) return GDM_OK;
+    GDM_HIP(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    have = bytes;
     return GDM_OK;
+}
+
+// LDS bytes of the FP64 kernels for a plan: one matrix row or column
+// (lds_n), the core-row kernel's row chunks and the density kernel's.
+struct Fp64Lds {
+    size_t n = 0, core_rows = 0, dcore = 0;
+    int core_chunks = 1, dcore_chunks = 1;
+};
+
+static Fp64Lds fp64_lds(const Plan& P) {
+    Fp64Lds L;
+    L.n = sizeof(double) * (size_t)P.max_n;
+    for (int s = 0; s < P.n_sub; ++s) {
+        const SubDesc& dd = P.desc[s];
+        const int rcn = chunk_rows(dd.n);
+        const size_t rows = sizeof(double) * (size_t)rcn * (dd.n + 1);
+        L.core_rows = std::max(L.core_rows, rows);
+        L.dcore = std::max(L.dcore, rows);
+        L.core_chunks = std::max(L.core_chunks, (2 * dd.nc + rcn - 1) / rcn);
+        L.dcore_chunks = std::max(L.dcore_chunks, (dd.nc + rcn - 1) / rcn);
+    }
+    return L;
+}
+
+int gdm_fp64_plan_lds(gdm_ctx* ctx) {
+    const Fp64Lds L = fp64_lds(ctx->plan);
+    int rc;
+    if ((rc = set_lds(ctx, (const void*)k_potrf, L.n))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * L.n))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_steqr, 2 * L.n))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_core_rows, L.core_rows))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_mu_partial, 2 * L.n))) return rc;
+    return set_lds(ctx, (const void*)k_dcore, L.dcore);
 }
 
 int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg, const int32_t* row_ptr,
@@ -581,7 +642,8 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     const int orth = S == nullptr;
     int rc;
     if ((rc = gdm_launch_gather(ctx, sys, sg, row_ptr, col, nnz, H, S, A, Sd, orth))) return rc;
-    const size_t lds_n = sizeof(double) * (size_t)P.max_n;
+    const Fp64Lds L = fp64_lds(P);
+    const size_t lds_n = L.n;
     if ((rc = set_lds(ctx, (const void*)k_potrf, lds_n))) return rc;
     GDM_LAUNCH_CHECK(ctx);
     { GDM_TIMED(ctx, "potrf");
@@ -612,14 +674,8 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     }
     GDM_LAUNCH_CHECK(ctx);
     {
-        size_t lds_rows = 0;
-        int chunks = 1;
-        for (int s = 0; s < ns; ++s) {
-            const SubDesc& dd = P.desc[s];
-            const int rcn = chunk_rows(dd.n);
-            lds_rows = std::max(lds_rows, sizeof(double) * (size_t)rcn * (dd.n + 1));
-            chunks = std::max(chunks, (2 * dd.nc + rcn - 1) / rcn);
-        }
+        const size_t lds_rows = L.core_rows;
+        const int chunks = L.core_chunks;
         if ((rc = set_lds(ctx, (const void*)k_core_rows, lds_rows))) return rc;
         GDM_TIMED(ctx, "core_rows");
         hipLaunchKernelGGL(k_core_rows, dim3(ns, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, Sd, A, Tau,
@@ -650,6 +706,14 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     hipLaunchKernelGGL(k_mu_pick, dim3(1), dim3(kMuK), 0, ctx->stream, ns, partial, n_e, 1, 1e-12, state,
                        ctx->d_status);
     GDM_LAUNCH_CHECK(ctx);
+    if (ctx->mu_out_device) {
+        // device scalars, no host synchronisation: the count check raises the
+        // status word, which gdm_check reports
+        hipLaunchKernelGGL(k_mu_out, dim3(1), dim3(64), 0, ctx->stream, state, n_e, 1e-6 * std::max(1.0, n_e), mu_out,
+                           n_out, ctx->d_status);
+        GDM_LAUNCH_CHECK(ctx);
+        return GDM_OK;
+    }
     double hs[4];
     GDM_HIP(ctx, hipMemcpyAsync(hs, state, sizeof(hs), hipMemcpyDeviceToHost, ctx->stream));
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -658,26 +722,21 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     return GDM_OK;
 }
 
-int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT, double* D_core,
-                     double* eig_out) {
+int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const double* mu_dev, double kT,
+                     double* D_core, double* eig_out) {
     Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
     int rc;
-    size_t lds_rows = 0;
-    int chunks = 1;
-    for (int s = 0; s < P.n_sub; ++s) {
-        const SubDesc& dd = P.desc[s];
-        const int rcn = chunk_rows(dd.n);
-        lds_rows = std::max(lds_rows, sizeof(double) * (size_t)rcn * (dd.n + 1));
-        chunks = std::max(chunks, (dd.nc + rcn - 1) / rcn);
-    }
+    const Fp64Lds L = fp64_lds(P);
+    const size_t lds_rows = L.dcore;
+    const int chunks = L.dcore_chunks;
     if ((rc = set_lds(ctx, (const void*)k_dcore, lds_rows))) return rc;
     { GDM_TIMED(ctx, "dcore");
     hipLaunchKernelGGL(k_dcore, dim3(P.n_sub, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc,
                        (const double*)ctx->b[BUF_S].p, (const double*)ctx->b[BUF_A].p, (const double*)ctx->b[BUF_TAU].p,
                        (const double*)ctx->b[BUF_ROTC].p, (const double*)ctx->b[BUF_ROTS].p,
                        (const int32_t*)ctx->b[BUF_ROTI].p, (const int64_t*)ctx->b[BUF_ROTN].p,
-                       (const double*)ctx->b[BUF_QC].p, (const double*)ctx->b[BUF_LAM].p, mu, 1.0 / kT, D_core,
+                       (const double*)ctx->b[BUF_QC].p, (const double*)ctx->b[BUF_LAM].p, mu, mu_dev, 1.0 / kT, D_core,
                        eig_out);
     }
     GDM_LAUNCH_CHECK(ctx);

@@ -70,6 +70,7 @@ struct gdm_ctx {
     int mixed_ns_z = 3;          // coupled Newton-Schulz iterations for s^-1/2 (first try)
     int mixed_ns_z_extra = 8;    // iterations that may be added while the residual is too large
     int mixed_ns_z_used = 0;     // iterations the last find_mu took
+    int mu_out_device = 0;       // gdm_find_mu writes mu and N to device scalars (FP64 path)
     int mixed_ns_inv = 2;        // Newton-Schulz iterations per inverse after the quadratic start
     int mixed_max_passes = 16;   // expansion passes allowed for mu
     int64_t mixed_tiles = 0, mixed_tiles_sym = 0, mixed_tiles_core = 0;
@@ -154,8 +155,11 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
                      const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                      const double* H, const double* S, double n_e, double kT,
                      double* mu_out, double* n_out);
-int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT,
+// mu_dev: when non-null, the kernel reads mu from this device scalar instead
+int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const double* mu_dev, double kT,
                      double* D_core, double* eig_out);
+// raise the dynamic-LDS attributes the FP64 kernels need for the current plan
+int gdm_fp64_plan_lds(gdm_ctx* ctx);
 int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
                       const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                       const double* H, const double* S, double n_e, double kT,
