@@ -272,6 +272,19 @@ int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
  * <= 0 (ns_z_extra: < 0) keep the current setting. */
 int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes, int ns_z_extra);
 
+/* Storage of the symmetric matrices of a MIXED_F16 expansion pass (the start
+ * polynomial, X_k, X_k^2, 2 X_k^2 - 2 X_k + I, its inverse and Newton-Schulz
+ * factors).  upper_tiles = 1 (default): only the upper 64 x 64 tiles are
+ * written, and a product reads a lower tile as the stored upper tile
+ * transposed, which cuts the HBM traffic of those products by about a third
+ * at the benchmark sizes.  With upper_tiles = 0 every product also writes
+ * the mirror tiles, from registers with its own rounding of the epilogue,
+ * so those lower tiles may differ from the upper ones in the last bit; the
+ * two settings agree to FP32 rounding.  The pass's final X and passes
+ * recorded for the charge response are always stored whole.  GDM_E_ARG for
+ * other values. */
+int gdm_set_mixed_storage(gdm_ctx* ctx, int upper_tiles);
+
 /* Statistics of the last GDM_MIXED_F16 gdm_find_mu (HOST outputs, nullable):
  * expansion passes, doublings per pass, split GEMM launches, and the mean
  * flops of one split GEMM launch counted once per product (2 P^2 per output

@@ -71,9 +71,11 @@ struct gdm_ctx {
     int mixed_ns_z_extra = 8;    // iterations that may be added while the residual is too large
     int mixed_ns_z_used = 0;     // iterations the last find_mu took
     int mu_out_device = 0;       // gdm_find_mu writes mu and N to device scalars (FP64 path)
+    int mixed_packed = 1;        // expansion matrices stored as upper tiles (gdm_set_mixed_storage)
     int mixed_ns_inv = 2;        // Newton-Schulz iterations per inverse after the quadratic start
     int mixed_max_passes = 16;   // expansion passes allowed for mu
     int64_t mixed_tiles = 0, mixed_tiles_sym = 0, mixed_tiles_core = 0;
+    int64_t mixed_upper_elems = 0;   // elements of the upper tiles of all subgraphs (packed storage)
     double mixed_flops_full = 0, mixed_flops_sym = 0;  // one product per launch
     double mixed_flops = 0;      // summed over the launches of the last find_mu
     double mixed_bytes = 0;      // algorithmic HBM bytes of those launches

@@ -49,7 +49,12 @@ struct GemmArgs {
     SplitMat O2;         // alpha*AB + beta*E + gamma*I
     SplitMat E;          // read as f32 if present, else as hi + 2^-11 lo
     float alpha, beta, gamma;
-    int sym;             // tiles cover i <= j only; results mirrored (exactly symmetric output)
+    int sym;             // tiles cover i <= j only; results mirrored (the mirror is written from
+                         // registers, so it can differ from the upper tile in the last bit)
+    int packed;          // sym only.  Bit 0: the operands hold valid upper tiles only (a lower
+                         // tile is read as its stored mirror, transposed into LDS).  Bit 1: the
+                         // outputs are written on the upper tiles only (no mirror); E is then
+                         // read on upper tiles only too, so it may be packed as well
 };
 
 __device__ __forceinline__ void store_split(SplitMat m, int64_t idx, float v) {
@@ -105,7 +110,9 @@ __device__ __forceinline__ float4 load4(SplitMat m, int64_t idx) {
                        (float)h[2] + kLoInv * (float)l[2], (float)h[3] + kLoInv * (float)l[3]);
 }
 
-__global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __restrict__ desc,
+// Four waves per SIMD (four workgroups per CU, as the LDS allows): the
+// register budget is held to 128 per lane (no spills).
+__global__ void __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4))) k_gemm_split(const SubDesc* __restrict__ desc,
                                                             const int4* __restrict__ tiles, GemmArgs g) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[kGemmLds];
     _Float16* sAh = (_Float16*)lds;
@@ -136,36 +143,83 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
             acc_x[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
         }
     const int fr = lane & 15, fk = (lane >> 4) * 8;
+    // LDS layout of an operand slab: element (r, c) (row r of the tile, k
+    // column c) at r * kLdsRow + (c ^ sw(r)), sw(r) = 8 ((r / 8) mod 8): an
+    // XOR of the 16-byte chunk index by the row's 8-row group.  Row-wise
+    // 16-byte stores and the MFMA fragment reads (8 consecutive k of one row)
+    // stay aligned and conflict-free, and the column-wise 2-byte stores of a
+    // transposed slab spread over all banks instead of four.
+    //
+    // Slab k0 of the A panel (rows m0.., columns k0..) is a lower tile when
+    // k0 < m0; in packed storage it is read from the stored upper tile (k0, m0)
+    // instead: the thread's rows lr, lr + 32 of that tile hold columns lr,
+    // lr + 32 of the wanted block, so its eight halves go to LDS column-wise.
+    // The same for the B panel with n0.  Both choices are uniform per
+    // workgroup, and every address stays inside the subgraph's P x P matrix.
+    auto addr_a = [&](int k0) -> int64_t {
+        return ((g.packed & 1) && k0 < m0) ? base + (int64_t)(k0 + lr) * P + m0 + lc : rA + k0;
+    };
+    auto addr_b = [&](int k0) -> int64_t {
+        return ((g.packed & 1) && k0 < n0) ? base + (int64_t)(k0 + lr) * P + n0 + lc : rB + k0;
+    };
+    // row-wise stores: rows lr and lr + 32, chunk lc
+    const int w0 = lr * kLdsRow + (lc ^ ((lr & 56))), w1 = (lr + 32) * kLdsRow + (lc ^ ((lr + 32) & 56));
+    // column-wise stores: rows lc + q (one 8-row group, sw = lc), columns lr, lr + 32
+    const int t0 = lc * kLdsRow + (lr ^ lc), t1 = lc * kLdsRow + ((lr + 32) ^ lc);
+    auto store_t = [&](_Float16* dst, uint4 lo32, uint4 hi32) {
+        unsigned short* d = (unsigned short*)dst;
+        const unsigned a[4] = {lo32.x, lo32.y, lo32.z, lo32.w};
+        const unsigned b[4] = {hi32.x, hi32.y, hi32.z, hi32.w};
+        #pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const unsigned sh = (q & 1) * 16;
+            d[t0 + q * kLdsRow] = (unsigned short)(a[q >> 1] >> sh);
+            d[t1 + q * kLdsRow] = (unsigned short)(b[q >> 1] >> sh);
+        }
+    };
     uint4 v0, v1, v2, v3, v4, v5, v6, v7;
-    v0 = *(const uint4*)(g.A.hi + rA);
-    v1 = *(const uint4*)(g.A.hi + rA + r32);
-    v2 = *(const uint4*)(g.A.lo + rA);
-    v3 = *(const uint4*)(g.A.lo + rA + r32);
-    v4 = *(const uint4*)(g.B.hi + rB);
-    v5 = *(const uint4*)(g.B.hi + rB + r32);
-    v6 = *(const uint4*)(g.B.lo + rB);
-    v7 = *(const uint4*)(g.B.lo + rB + r32);
+    {
+        const int64_t a0 = addr_a(0), b0 = addr_b(0);
+        v0 = *(const uint4*)(g.A.hi + a0);
+        v1 = *(const uint4*)(g.A.hi + a0 + r32);
+        v2 = *(const uint4*)(g.A.lo + a0);
+        v3 = *(const uint4*)(g.A.lo + a0 + r32);
+        v4 = *(const uint4*)(g.B.hi + b0);
+        v5 = *(const uint4*)(g.B.hi + b0 + r32);
+        v6 = *(const uint4*)(g.B.lo + b0);
+        v7 = *(const uint4*)(g.B.lo + b0 + r32);
+    }
     for (int k0 = 0; k0 < P; k0 += kK) {
         __syncthreads();
-        *(uint4*)(sAh + lr * kLdsRow + lc) = v0;
-        *(uint4*)(sAh + (lr + 32) * kLdsRow + lc) = v1;
-        *(uint4*)(sAl + lr * kLdsRow + lc) = v2;
-        *(uint4*)(sAl + (lr + 32) * kLdsRow + lc) = v3;
-        *(uint4*)(sBh + lr * kLdsRow + lc) = v4;
-        *(uint4*)(sBh + (lr + 32) * kLdsRow + lc) = v5;
-        *(uint4*)(sBl + lr * kLdsRow + lc) = v6;
-        *(uint4*)(sBl + (lr + 32) * kLdsRow + lc) = v7;
+        if ((g.packed & 1) && k0 < m0) {
+            store_t(sAh, v0, v1);
+            store_t(sAl, v2, v3);
+        } else {
+            *(uint4*)(sAh + w0) = v0;
+            *(uint4*)(sAh + w1) = v1;
+            *(uint4*)(sAl + w0) = v2;
+            *(uint4*)(sAl + w1) = v3;
+        }
+        if ((g.packed & 1) && k0 < n0) {
+            store_t(sBh, v4, v5);
+            store_t(sBl, v6, v7);
+        } else {
+            *(uint4*)(sBh + w0) = v4;
+            *(uint4*)(sBh + w1) = v5;
+            *(uint4*)(sBl + w0) = v6;
+            *(uint4*)(sBl + w1) = v7;
+        }
         __syncthreads();
         if (k0 + kK < P) {
-            const int64_t o = k0 + kK;
-            v0 = *(const uint4*)(g.A.hi + rA + o);
-            v1 = *(const uint4*)(g.A.hi + rA + r32 + o);
-            v2 = *(const uint4*)(g.A.lo + rA + o);
-            v3 = *(const uint4*)(g.A.lo + rA + r32 + o);
-            v4 = *(const uint4*)(g.B.hi + rB + o);
-            v5 = *(const uint4*)(g.B.hi + rB + r32 + o);
-            v6 = *(const uint4*)(g.B.lo + rB + o);
-            v7 = *(const uint4*)(g.B.lo + rB + r32 + o);
+            const int64_t a1 = addr_a(k0 + kK), b1 = addr_b(k0 + kK);
+            v0 = *(const uint4*)(g.A.hi + a1);
+            v1 = *(const uint4*)(g.A.hi + a1 + r32);
+            v2 = *(const uint4*)(g.A.lo + a1);
+            v3 = *(const uint4*)(g.A.lo + a1 + r32);
+            v4 = *(const uint4*)(g.B.hi + b1);
+            v5 = *(const uint4*)(g.B.hi + b1 + r32);
+            v6 = *(const uint4*)(g.B.lo + b1);
+            v7 = *(const uint4*)(g.B.lo + b1 + r32);
         }
         #pragma unroll
         for (int ks = 0; ks < kK; ks += 32) {
@@ -173,14 +227,14 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
             #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int r = wm * 32 + i * 16 + fr;
-                ah[i] = *(const half8*)(sAh + r * kLdsRow + ks + fk);
-                al[i] = *(const half8*)(sAl + r * kLdsRow + ks + fk);
+                ah[i] = *(const half8*)(sAh + r * kLdsRow + ((ks + fk) ^ (r & 56)));
+                al[i] = *(const half8*)(sAl + r * kLdsRow + ((ks + fk) ^ (r & 56)));
             }
             #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int c = wn * 32 + j * 16 + fr;
-                bh[j] = *(const half8*)(sBh + c * kLdsRow + ks + fk);
-                bl[j] = *(const half8*)(sBl + c * kLdsRow + ks + fk);
+                bh[j] = *(const half8*)(sBh + c * kLdsRow + ((ks + fk) ^ (c & 56)));
+                bl[j] = *(const half8*)(sBl + c * kLdsRow + ((ks + fk) ^ (c & 56)));
             }
             #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -234,7 +288,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_split(const SubDesc* __re
             store4(g.O2, idx, make_float4(o[0], o[1], o[2], o[3]));
         }
     }
-    if (!g.sym || diag_tile) return;
+    if (!g.sym || diag_tile || (g.packed & 2)) return;
     // mirror image of an off-diagonal tile from registers: register r of lane
     // l is element (4 gq + r, fr) of its 16 x 16 block, i.e. element
     // (fr, 4 gq + r) of the mirrored block: four consecutive columns of row fr
@@ -851,6 +905,11 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
     ctx->mixed_tiles = (int64_t)nfull;
     ctx->mixed_tiles_sym = (int64_t)utiles.size();
     ctx->mixed_tiles_core = (int64_t)ctiles.size();
+    ctx->mixed_upper_elems = 0;
+    for (const SubDesc& d : P.desc) {
+        const int64_t t = d.ld / kTile;
+        ctx->mixed_upper_elems += t * (t + 1) / 2 * kTile * kTile;
+    }
     ctx->mixed_flops_full = ffull;
     ctx->mixed_flops_sym = fsym;
     return GDM_OK;
@@ -862,8 +921,11 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
 static SplitMat hl(SplitMat m) { return SplitMat{nullptr, m.hi, m.lo}; }
 
 static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, SplitMat E, float alpha,
-                float beta, float gamma, const char* tag, int sym = 1) {
-    GemmArgs g{A, B, O1, O2, E, alpha, beta, gamma, sym};
+                float beta, float gamma, const char* tag, int sym = 1, int packed = 0) {
+    // packed: bit 0 operands in upper-tile storage, bit 1 outputs (and E) on
+    // upper tiles only; symmetric products only
+    if (!sym) packed = 0;
+    GemmArgs g{A, B, O1, O2, E, alpha, beta, gamma, sym, packed};
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + (sym ? ctx->mixed_tiles : 0);
     const int64_t nt = sym ? ctx->mixed_tiles_sym : ctx->mixed_tiles;
     GDM_TIMED(ctx, tag);
@@ -872,14 +934,17 @@ static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, 
     GDM_LAUNCH_CHECK(ctx);
     ctx->mixed_gemms += 1;
     ctx->mixed_flops += sym ? ctx->mixed_flops_sym : ctx->mixed_flops_full;
-    // algorithmic HBM bytes: each operand and E read once, each output written once
-    double per = 8.0;                                   // A and B as FP16 hi + lo
-    if (E.f) per += 4.0; else if (E.hi) per += 4.0;
+    // algorithmic HBM bytes: each operand and E read once, each output written
+    // once, over all elements, or over the upper tiles only in packed storage
+    const double full = (double)ctx->plan.tot2, upper = (double)ctx->mixed_upper_elems;
+    const double ein = (packed & 1) ? upper : full, eout = (packed & 2) ? upper : full;
+    double bytes = 8.0 * ein;                           // A and B as FP16 hi + lo
+    if (E.f || E.hi) bytes += 4.0 * eout;
     for (const SplitMat* o : {&O1, &O2}) {
-        if (o->f) per += 4.0;
-        if (o->hi) per += 4.0;
+        if (o->f) bytes += 4.0 * eout;
+        if (o->hi) bytes += 4.0 * eout;
     }
-    ctx->mixed_bytes += per * (double)ctx->plan.tot2;
+    ctx->mixed_bytes += bytes;
     return GDM_OK;
 }
 
@@ -933,6 +998,9 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
     ctx->mixed_x0_slope = b / 4.0;
     SplitMat X = slot(ctx, SL_X), X2 = slot(ctx, SL_X2), A = slot(ctx, SL_A), Rm = slot(ctx, SL_R);
     const SplitMat Ya = slot(ctx, SL_Y), Yb = slot(ctx, SL_YI);
+    // upper-tile storage of the pass's symmetric matrices (not when recording:
+    // the response reads the recorded X_k, Y_k whole)
+    const int pk = (!rec && ctx->mixed_packed) ? 3 : 0;
     if (septic || cubic) {
         const SplitMat K = slot(ctx, SL_T);
         {
@@ -943,13 +1011,13 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
         GDM_LAUNCH_CHECK(ctx);
         if (septic) {
             // X0 = I/2 - K/4 + K (K^2 (K^2 (a7 K^2 + a5 I) + a3 I)), four products
-            GDM_TRY(gemm(ctx, K, K, hl(Rm), hl(A), none(), kStart7[2], 0.0f, kStart7[1], "foe_gemm"));
-            GDM_TRY(gemm(ctx, Rm, A, none(), hl(Ya), none(), 1.0f, 0.0f, kStart7[0], "foe_gemm"));
-            GDM_TRY(gemm(ctx, Rm, Ya, hl(Yb), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
-            GDM_TRY(gemm(ctx, K, Yb, none(), hl(X), hl(K), 1.0f, -0.25f, 0.5f, "foe_gemm"));
+            GDM_TRY(gemm(ctx, K, K, hl(Rm), hl(A), none(), kStart7[2], 0.0f, kStart7[1], "foe_gemm", 1, pk));
+            GDM_TRY(gemm(ctx, Rm, A, none(), hl(Ya), none(), 1.0f, 0.0f, kStart7[0], "foe_gemm", 1, pk));
+            GDM_TRY(gemm(ctx, Rm, Ya, hl(Yb), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, pk));
+            GDM_TRY(gemm(ctx, K, Yb, none(), hl(X), hl(K), 1.0f, -0.25f, 0.5f, "foe_gemm", 1, pk));
         } else {
-            GDM_TRY(gemm(ctx, K, K, hl(Rm), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
-            GDM_TRY(gemm(ctx, K, Rm, none(), hl(X), hl(K), 1.0f / 108.0f, -0.25f, 0.5f, "foe_gemm"));
+            GDM_TRY(gemm(ctx, K, K, hl(Rm), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, pk));
+            GDM_TRY(gemm(ctx, K, Rm, none(), hl(X), hl(K), 1.0f / 108.0f, -0.25f, 0.5f, "foe_gemm", 1, pk));
         }
     } else {
         GDM_TIMED(ctx, "mixed_misc");
@@ -961,22 +1029,24 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
     for (int it = 0; it < nd; ++it) {
         const SplitMat Xk = rec ? hist(ctx, it, 0) : X;
         // X2 = X X ; A = 2 X2 - 2 X + I
-        GDM_TRY(gemm(ctx, Xk, Xk, hl(X2), hl(A), hl(Xk), 2.0f, -2.0f, 1.0f, "foe_gemm"));
+        GDM_TRY(gemm(ctx, Xk, Xk, hl(X2), hl(A), hl(Xk), 2.0f, -2.0f, 1.0f, "foe_gemm", 1, pk));
         // Newton-Schulz inverse of A (eigenvalues in [1/2, 1]) from the minimax
         // quadratic start Y0 = (420 I - 576 A + 256 A^2) / 99: 1 - a y0(a) is the
         // Chebyshev T3 on [1/2, 1] scaled to 1 at a = 0, so |1 - a y0| <= 1/99;
         // each iteration R = 2I - A Y, Y <- Y R squares the error
         SplitMat Y = (rec && ns == 0) ? hist(ctx, it, 1) : Ya;
-        GDM_TRY(gemm(ctx, A, A, none(), hl(Y), hl(A), 256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f, "foe_gemm"));
+        GDM_TRY(gemm(ctx, A, A, none(), hl(Y), hl(A), 256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f, "foe_gemm", 1,
+                     pk));
         for (int k = 0; k < ns; ++k) {
-            GDM_TRY(gemm(ctx, A, Y, none(), hl(Rm), none(), -1.0f, 0.0f, 2.0f, "foe_gemm"));
+            GDM_TRY(gemm(ctx, A, Y, none(), hl(Rm), none(), -1.0f, 0.0f, 2.0f, "foe_gemm", 1, pk));
             const SplitMat Yn = (rec && k == ns - 1) ? hist(ctx, it, 1) : (Y.hi == Ya.hi ? Yb : Ya);
-            GDM_TRY(gemm(ctx, Y, Rm, hl(Yn), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
+            GDM_TRY(gemm(ctx, Y, Rm, hl(Yn), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, pk));
             Y = Yn;
         }
         // X <- X2 Y
         const SplitMat Xn = it + 1 == nd ? X : (rec ? hist(ctx, it + 1, 0) : hl(X));
-        GDM_TRY(gemm(ctx, X2, Y, Xn, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm"));
+        // the last product writes X whole (its FP32 copy is read by full rows)
+        GDM_TRY(gemm(ctx, X2, Y, Xn, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, it + 1 == nd ? (pk & 1) : pk));
     }
     if (rec) ctx->mixed_rec_nd = nd;
     return GDM_OK;
@@ -1340,6 +1410,14 @@ int gdm_mixed_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs*
     const double zero[2] = {0.0, 0.0};
     GDM_TRY(gdm_launch_mulliken(ctx, sys, sg, row_ptr, col, nnz, S, dDp, zero, dq));
     if (dmu) *dmu = dm;
+    return GDM_OK;
+}
+
+extern "C" int gdm_set_mixed_storage(gdm_ctx* ctx, int upper_tiles) {
+    if (!ctx) return GDM_E_ARG;
+    if (upper_tiles != 0 && upper_tiles != 1)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_set_mixed_storage: upper_tiles must be 0 or 1");
+    ctx->mixed_packed = upper_tiles;
     return GDM_OK;
 }
 

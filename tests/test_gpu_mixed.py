@@ -101,3 +101,45 @@ def test_inverse_overlap_residual_guard(c):
         f"max|dq| vs default {float((sol.q - ref.q).abs().max()):.2e}")
     assert 1 < used <= 9 and used_default >= 3
     assert float((sol.q - ref.q).abs().max()) < 1e-5
+
+
+@pytest.mark.parametrize("nw,seed,grid", [(96, 1, (2, 2, 2)), (300, 21, (3, 3, 3))])
+def test_upper_tile_storage_matches_whole_storage(c, nw, seed, grid):
+    """The expansion with its symmetric matrices stored as upper tiles (a
+    lower tile read as its stored mirror, transposed) against whole storage
+    (every product also writes the mirror tiles): same doublings and
+    launches, D core rows equal to FP32 rounding, fewer bytes per launch.
+    They need not agree bit for bit: whole storage writes a mirror tile from
+    registers with its own rounding of the epilogue (alpha AB + beta E +
+    gamma I), so its lower tiles may differ from the upper ones in the last
+    bit, which upper-tile storage never reads.  Subgraphs of several
+    64-tiles with ragged tails; one pass at a fixed mu."""
+    from paper_2606_03140_amd import pipeline
+    log(f"upper-tile vs whole storage, {nw} waters, grid {grid}")
+    box = waterbox.water_box(nw, seed)
+    sysm = system_of(box)
+    tb = tb_params(False)
+    part = pipeline.cutoff_partition(c, sysm, tb, grid)
+    H, S = c.build_hs(sysm, tb, part.nbr)
+    c.plan(part.sg, pipeline.MIXED_F16)
+    P0 = 64 * ((int(part.sg.norb[0]) + 63) // 64)
+    out = {}
+    try:
+        c.set_mixed_options(max_passes=1)
+        for upper in (False, True):
+            c.set_mixed_storage(upper)
+            c.find_mu(sysm, part.sg, part.nbr, H, S, 0.1, pipeline.MIXED_F16, -6.9, 1e9)
+            D = c.subgraph_density(part.sg, -6.9, 0.1, pipeline.MIXED_F16)
+            X = c.debug_slot(2, 0, P0).cpu().numpy()
+            out[upper] = (D.cpu().numpy(), c.mixed_stats(), float(np.abs(X - X.T).max()))
+    finally:
+        c.set_mixed_storage(True)
+        c.set_mixed_options(max_passes=16)
+    (Dw, sw, aw), (Du, su, au) = out[False], out[True]
+    err = float(np.abs(Dw - Du).max())
+    log(f"  n_d {su['n_doublings']}, launches {su['gemm_launches']}, bytes per launch "
+        f"{sw['bytes_per_launch'] / 1e6:.1f} MB whole, {su['bytes_per_launch'] / 1e6:.1f} MB upper tiles, "
+        f"max|dD| {err:.1e}, max|X - X^T| {aw:.1e} whole, {au:.1e} upper tiles")
+    assert sw["n_doublings"] == su["n_doublings"] and sw["gemm_launches"] == su["gemm_launches"]
+    assert err < 1e-6
+    assert su["bytes_per_launch"] < 0.9 * sw["bytes_per_launch"]
