@@ -291,7 +291,8 @@ int gdm_set_mixed_storage(gdm_ctx* ctx, int upper_tiles);
  * tile row of P, over the tiles computed: products of commuting symmetric
  * matrices compute the upper tiles only); each launch executes three FP16
  * products.  bytes_per_launch: mean algorithmic HBM bytes of a launch (each
- * operand, E matrix and output read or written once).  ns_z_used: coupled
+ * operand, E matrix and output read or written once, over their upper tiles
+ * for matrices in upper-tile storage, gdm_set_mixed_storage).  ns_z_used: coupled
  * Newton-Schulz iterations taken for s^-1/2. */
 int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int64_t* gemm_launches,
                     double* flops_per_launch, double* bytes_per_launch, int* ns_z_used);
