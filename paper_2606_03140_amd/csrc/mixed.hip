@@ -1142,17 +1142,21 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
     // for one refinement step to remove
     SplitMat Y = slot(ctx, SL_Y), Z = slot(ctx, SL_Z), T = slot(ctx, SL_T), Y2 = slot(ctx, SL_Y2),
              Z2 = slot(ctx, SL_Z2);
+    // upper-tile storage for these symmetric products too, except the Z that
+    // the FP64 refinement reads whole (with its FP32 copy)
+    const int pkz = ctx->mixed_packed ? 3 : 0;
     auto ns_step = [&](bool full_z) -> int {
-        GDM_TRY(gemm(ctx, Z, Y, none(), hl(T), none(), -0.5f, 0.0f, 1.5f, "ns_gemm"));
-        GDM_TRY(gemm(ctx, Y, T, hl(Y2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
-        GDM_TRY(gemm(ctx, T, Z, full_z ? Z2 : hl(Z2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm"));
+        GDM_TRY(gemm(ctx, Z, Y, none(), hl(T), none(), -0.5f, 0.0f, 1.5f, "ns_gemm", 1, pkz));
+        GDM_TRY(gemm(ctx, Y, T, hl(Y2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm", 1, pkz));
+        GDM_TRY(gemm(ctx, T, Z, full_z ? Z2 : hl(Z2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm", 1,
+                     full_z ? (pkz & 1) : pkz));
         std::swap(Y, Y2);
         std::swap(Z, Z2);
         return GDM_OK;
     };
     if (!orth) {
         // Y0 = (s/c) Z0 = a (s/c) + b (s/c)^2 (Z0 from k_prep)
-        GDM_TRY(gemm(ctx, Y, Y, none(), hl(Y2), hl(Y), kZ0b, kZ0a, 0.0f, "ns_gemm"));
+        GDM_TRY(gemm(ctx, Y, Y, none(), hl(Y2), hl(Y), kZ0b, kZ0a, 0.0f, "ns_gemm", 1, pkz));
         std::swap(Y, Y2);
         for (int it = 0; it < ctx->mixed_ns_z; ++it) GDM_TRY(ns_step(it + 1 == ctx->mixed_ns_z));
     }
