@@ -1,0 +1,82 @@
+"""The polynomial starts of the mixed path's iterations, checked against the
+mathematics they are built on (no GPU; the constants are read from the
+kernel source, so a change there is checked here).
+
+* Expansion start, degree 7: with K = b (h - mu), X0 = 1/2 - K/4 + a3 K^3 +
+  a5 K^5 + a7 K^7 stays in (0, 1/2) for K in (0, 8] (odd about 1/2), and
+  after n doublings (each mapping f(u) to f(2u), f the Fermi function) the
+  occupation f(2^n u0(K)), u0 = log((1 - X0) / X0), is within 6.1e-8 of
+  f(2^n K) for every K in (0, 8] and n = 5..9.
+* Expansion start, cubic: X0 = 1/2 - K/4 + K^3/108 stays in [0, 1] for
+  |K| <= 4 with its minimum 0 at K = 3, and its occupation error after n
+  doublings is at most 1.4e-5 (n = 6).
+* Inverse start in each doubling: y0(a) = (420 - 576 a + 256 a^2) / 99 has
+  |1 - a y0(a)| <= 1/99 on [1/2, 1] (a Chebyshev T3 residual), attained
+  with alternating signs at four points.
+* Inverse square root start: z0(x) = c0 + c1 x has |1 - x z0(x)^2| <= 0.417
+  on [0.1, 1], the range of s / c.
+"""
+import os
+import re
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = open(os.path.join(ROOT, "paper_2606_03140_amd", "csrc", "mixed.hip")).read()
+
+
+def fermi(u):
+    return 0.5 * (1.0 - np.tanh(0.5 * u))
+
+
+def logit(x):
+    return np.log((1.0 - x) / x)
+
+
+def start7():
+    m = re.search(r"kStart7\[3\]\s*=\s*\{([^}]*)\}", SRC)
+    return np.array([float(v.strip().rstrip("f")) for v in m.group(1).split(",")], dtype=np.float32).astype(np.float64)
+
+
+def test_degree7_start_error_after_doublings():
+    a3, a5, a7 = start7()
+    K = np.linspace(1e-6, 8.0, 400001)
+    X0 = 0.5 - K / 4 + a3 * K**3 + a5 * K**5 + a7 * K**7
+    assert X0.min() > 0.0 and X0.max() < 0.5
+    u0 = logit(X0)
+    for n in range(5, 10):
+        err = np.abs(fermi(2.0**n * u0) - fermi(2.0**n * K)).max()
+        assert err < 6.2e-8, (n, err)
+    # fewer doublings do not settle the states near |K| = 8: the reason the
+    # library falls back to the cubic start below 5
+    assert np.abs(fermi(16.0 * u0) - fermi(16.0 * K)).max() > 1e-5
+
+
+def test_cubic_start_range_and_error():
+    assert "1.0f / 108.0f" in SRC
+    K = np.linspace(-4.0, 4.0, 400001)
+    X0 = 0.5 - K / 4 + K**3 / 108
+    assert X0.min() >= -1e-15 and X0.max() <= 1.0 + 1e-15
+    assert abs(K[np.argmin(X0)] - 3.0) < 1e-4
+    Kp = K[K > 1e-6]
+    u0 = logit(np.clip(0.5 - Kp / 4 + Kp**3 / 108, 1e-300, 0.5))
+    err = np.abs(fermi(64.0 * u0) - fermi(64.0 * Kp)).max()
+    assert err < 1.45e-5
+
+
+def test_quadratic_inverse_start_is_minimax():
+    assert "256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f" in SRC
+    a = np.linspace(0.5, 1.0, 200001)
+    r = 1.0 - a * (420.0 - 576.0 * a + 256.0 * a * a) / 99.0
+    assert np.abs(r).max() <= 1.0 / 99.0 + 1e-15
+    # equioscillation: the residual is the scaled Chebyshev T3 of 4a - 3
+    x = 4.0 * a - 3.0
+    assert np.allclose(r, (4 * x**3 - 3 * x) / -99.0, atol=1e-15)
+
+
+def test_inverse_sqrt_start_bound():
+    m = re.search(r"kZ0a\s*=\s*([-0-9.e]+)f,\s*kZ0b\s*=\s*([-0-9.e]+)f", SRC)
+    c0, c1 = float(np.float32(m.group(1))), float(np.float32(m.group(2)))
+    x = np.linspace(0.1, 1.0, 200001)
+    e = np.abs(1.0 - x * (c0 + c1 * x) ** 2)
+    assert e.max() <= 0.417
