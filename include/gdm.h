@@ -191,14 +191,17 @@ int gdm_build_hs(gdm_ctx* ctx, const gdm_system* sys, const gdm_tb_params* tb,
 /* ------------------------------------------------- subgraph solve: a6-a14 */
 
 /* Size the workspace for subgraph set `sg` and solver `precision` and record
- * the plan (size buckets, offsets).  The only call of the solve path that
- * allocates.  Required before gdm_find_mu.  Subgraphs hold at most 8,192
+ * the plan (per-subgraph offsets of the dense tiles, and for GDM_MIXED_F16 the
+ * tile lists of the matrix-core products, built largest subgraph first over
+ * eight per-XCD queues).  The only call of the solve path that allocates.  Required before gdm_find_mu.  Subgraphs hold at most 8,192
  * orbitals (GDM_E_ARG otherwise); a failed plan leaves no plan, so the
  * solve calls then return GDM_E_STATE until a plan succeeds. */
 int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision);
 
 /* Gather every subgraph's principal submatrices h, s from the block-sparse
- * H, S (LDS-staged), solve it with `precision`, and find the global chemical
+ * H, S (one workgroup per subgraph; its atom list and orbital offsets staged in
+ * LDS, the blocks of each atom's neighbour edges copied into the dense tiles),
+ * solve it with `precision`, and find the global chemical
  * potential mu with N(mu) = 2 sum_s sum_k w_k f(lam_k) = n_electrons
  * (Density Matrix Evaluation on Partitioned Graphs: mu fixes the occupation).
  * FP64_EIG: multisection on the eigenvalues and core weights to an interval
@@ -231,7 +234,14 @@ int gdm_set_mu_outputs(gdm_ctx* ctx, int device);
  * potential mu, from the state cached by gdm_find_mu (same precision).
  * Output packed in subgraph order: subgraph s occupies nc_s * n_s doubles,
  * row-major (core orbital, subgraph orbital), at offset sum_{t<s} nc_t n_t.
- * eig_out (nullable): FP64_EIG only, eigenvalues packed at sum_{t<s} n_t. */
+ * eig_out (nullable): FP64_EIG only, eigenvalues packed at sum_{t<s} n_t.
+ * FP64_EIG: any mu (the eigenpairs are exact for every occupation).
+ * MIXED_F16: the expansion was evaluated at the chemical potential mu_p of
+ * gdm_find_mu's last pass and at its kT; D(mu) is taken to first order,
+ * D(mu_p) + (mu - mu_p) beta Z X (I - X) Z^T, which holds only near mu_p, so
+ * kT must equal gdm_find_mu's (relative 1e-12) and |mu - mu_p| <= kT, else
+ * GDM_E_ARG (nothing enqueued).  The mu that gdm_find_mu returns always
+ * satisfies this. */
 int gdm_subgraph_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT,
                          int precision, double* D_core, double* eig_out);
 

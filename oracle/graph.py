@@ -21,8 +21,10 @@
   Subgraphs: edges are only added in the initial SCF iterations).
 
 Pins: core/halo construction is checked by brute force on small boxes; the
-graph-from-D rules are checked on hand-built matrices; the all-to-all graph
-reproduces the full-system density matrix (tests/test_oracle_pins.py).
+graph-from-D rules are checked on hand-built matrices; G^N of three atoms
+(one pair only through a periodic image) equals exp(-0.7 R^2) worked out by
+hand with the unit diagonal; the all-to-all graph reproduces the full-system
+density matrix (tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 

@@ -21,7 +21,12 @@ computed once; r^2 = (dx*dx + dy*dy) + dz*dz evaluated in exactly this order
 
 Pins: brute-force neighbour list == periodic k-d tree (library); H and S are
 symmetric; S is positive definite; the 6x6 single-water problem equals a
-textbook generalized eigensolve (tests/test_oracle_pins.py).
+textbook generalized eigensolve; every element of an O-H and an O-O pair
+(s-s, s-p, p-s, p-p) equals the Slater-Koster value worked out by hand, and a
+pair's spectrum does not depend on the direction of its axis; the SCC shift
+of an O-H pair equals 1/2 S_ab (V_I + V_J) element by element (H_aa += V_I
+in the orthogonal model), and a uniform potential c moves every generalized
+eigenvalue by exactly c (tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 

@@ -334,6 +334,15 @@ extern "C" int gdm_subgraph_density(gdm_ctx* ctx, const gdm_subgraphs* sg, doubl
         return gdm_fail(ctx, GDM_E_STATE, "gdm_subgraph_density: call gdm_find_mu first");
     if (precision == GDM_FP64_EIG) return gdm_fp64_density(ctx, sg, mu, nullptr, kT, D_core, eig_out);
     if (eig_out) return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density: eigenvalues exist only for FP64_EIG");
+    // the expansion holds X at (mu_pass, kT_solved); other points are reached
+    // by the first-order term only, inside its linear range
+    if (std::fabs(kT - ctx->kT_solved) > 1e-12 * ctx->kT_solved)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density: kT %.17g differs from gdm_find_mu's %.17g (mixed path)",
+                        kT, ctx->kT_solved);
+    if (std::fabs(mu - ctx->mixed_mu_pass) > kT)
+        return gdm_fail(ctx, GDM_E_ARG,
+                        "gdm_subgraph_density: mu %.12g is more than kT from the expansion's %.12g (mixed path: "
+                        "first-order range)", mu, ctx->mixed_mu_pass);
     return gdm_mixed_density(ctx, sg, mu, kT, D_core);
 }
 

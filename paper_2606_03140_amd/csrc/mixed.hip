@@ -3,15 +3,21 @@
 // matrix cores as the paper's accelerator library does for FOE and the
 // inverse overlap).  Per subgraph, padded to P = 64 * ceil(n / 64):
 //
-//   Z = s^-1/2 by coupled Newton-Schulz (Y0 = s/c, Z0 = I,
-//       T = (3I - Z Y)/2, Y <- Y T, Z <- T Z; then Z /= sqrt(c)),
-//   h_perp = Z h Z,  W = Z s,
-//   X0 = I/2 - (b/4)(h_perp - mu I),  b = beta / 2^n_d,
+//   Z = s^-1/2 by coupled Newton-Schulz on s/c (c the largest absolute row
+//       sum of s): Z0 = kZ0a I + kZ0b s/c (linear minimax start), Y0 = (s/c) Z0,
+//       T = (3I - Z Y)/2, Y <- Y T, Z <- T Z; then Z64 = Z / sqrt(c) in FP64
+//       and one FP64 residual step Z64 <- Z64 - Z64 (Z64 s Z64 - I) / 2,
+//   h_perp = Z h Z,
+//   K = b (h_perp - mu I), b = beta / 2^n_d, and the start X0 = f_b(K) to
+//       high order: the degree-7 odd polynomial of kStart7 (n_d >= 5), else
+//       the cubic I/2 - K/4 + K^3/108, or the linear I/2 - K/4 when the pass is
+//       recorded for the charge response,
 //   n_d times:  X2 = X X,  A = 2 X2 - 2 X + I = X^2 + (I - X)^2,
-//               Y = A^-1 by Newton-Schulz from the minimax start
-//               Y0 = 48/17 I - 32/17 A (|I - A Y0| <= 1/17 on [1/2, 1]),
+//               Y = A^-1 by Newton-Schulz from the minimax quadratic start
+//               Y0 = (420 I - 576 A + 256 A^2) / 99 (|I - A Y0| <= 1/99 on
+//               [1/2, 1]), then ns_inv iterations,
 //               X <- X2 Y            (f_b -> f_2b),
-//   N(mu) = 2 sum_core (Z X W)_aa,  N'(mu) = 2 beta sum_core (Z (X - X^2) W)_aa
+//   N(mu) = 2 sum_core (Z X Z s)_aa,  N'(mu) = 2 beta sum_core (Z (X - X^2) Z s)_aa
 //   in FP64, Newton steps on mu with a bisection bracket, and the final
 //   collected core rows D = Z[core,:] (X + dmu beta (X - X^2)) Z in FP64.
 //

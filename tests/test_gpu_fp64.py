@@ -205,5 +205,15 @@ def test_dm_and_adaptive_graph_from_same_D(c):
         rp, col = csr_host(g)
         ties = og.near_ties(w.data, tau)
         log(f"  adaptive tau {tau}: edges gpu {len(col)} oracle {len(ocol)} near-ties {ties}")
+        # every edge is compared: the two edge sets may differ only on pairs
+        # whose summed weight lies within 1e-9 tau of the threshold (with no
+        # near tie they are identical)
+        n = box.n_atoms
+        ek = lambda r_, c_: set((np.repeat(np.arange(n), np.diff(r_)) * n + c_).tolist())
+        diff = ek(rp, col) ^ ek(orp, ocol)
+        near = np.abs(w.data - tau) <= 1e-9 * tau
+        tie_pairs = set((w.row[near].astype(np.int64) * n + w.col[near]).tolist())
+        tie_pairs |= set((w.col[near].astype(np.int64) * n + w.row[near]).tolist())
+        assert diff <= tie_pairs, f"{len(diff - tie_pairs)} edges differ away from the threshold"
         if ties == 0:
             assert np.array_equal(rp, orp) and np.array_equal(col, ocol)

@@ -96,7 +96,7 @@ def test_inverse_overlap_residual_guard(c):
         sol = pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.MIXED_F16, mu_guess=-7.0)
         used = c.mixed_stats()["ns_z_used"]
     finally:
-        c.set_mixed_options(ns_z=5, ns_z_extra=8)
+        c.set_mixed_options(ns_z=3, ns_z_extra=8)   # the library defaults
     log(f"  iterations: default {used_default}, from 1 with extras {used}; "
         f"max|dq| vs default {float((sol.q - ref.q).abs().max()):.2e}")
     assert 1 < used <= 9 and used_default >= 3

@@ -343,3 +343,114 @@ def test_kdtree_neighbour_list_equals_bruteforce():
     a = model.neighbour_list(b.pos, L)
     k = model.neighbour_list_kdtree(b.pos, L)
     assert np.array_equal(a[0], k[0]) and np.array_equal(a[1], k[1])
+
+
+def test_distance_graph_by_hand():
+    # G^N_IJ = exp(-alpha R_IJ^2) over neighbour pairs plus G^N_II = 1 (Eq.
+    # neigh_mat).  Three atoms in a 20 A box; the 0-2 pair is 1.5 A apart only
+    # through the periodic image along z.
+    L = 20.0
+    pos = np.array([[1.0, 1.0, 1.0], [2.5, 1.0, 1.0], [1.0, 1.0, 19.5]])
+    rp, col = model.neighbour_list(pos, L)
+    assert list(np.diff(rp)) == [2, 2, 2]
+    g = graph.distance_graph(pos, L, rp, col, 0.7).toarray()
+    r2 = np.array([[0.0, 2.25, 2.25], [2.25, 0.0, 4.5], [2.25, 4.5, 0.0]])   # by hand
+    want = np.array([[1.0, math.exp(-1.575), math.exp(-1.575)],
+                     [math.exp(-1.575), 1.0, math.exp(-3.15)],
+                     [math.exp(-1.575), math.exp(-3.15), 1.0]])
+    assert np.abs(g - want).max() < 1e-15
+    # the plausible mistakes give other numbers: exp(-alpha R), no unit
+    # diagonal, alpha applied to R^2 without the minus sign
+    off = ~np.eye(3, dtype=bool)
+    assert np.abs(g[off] - np.exp(-0.7 * np.sqrt(r2[off]))).min() > 0.1
+    assert np.all(np.diag(g) == 1.0)
+    assert np.abs(g[off] - np.exp(0.7 * r2[off])).min() > 1.0
+
+
+def _oo_pair(u, r=2.5):
+    pos = np.array([[10.0, 10.0, 10.0], [10.0, 10.0, 10.0] + r * np.asarray(u)])
+    return model.dense_hs(pos, np.array([0, 0], dtype=np.int32), 30.0, model.TBModel(orthogonal=False))
+
+
+def test_hs_pp_block_by_hand():
+    # O-O pair at 2.5 A along u = (2, -3, 6)/7: with V_pp_pi = 0 the p-p block
+    # is u_a u_b V(r) (sigma only), the s-p blocks are +-u_b V with the
+    # direction taken from the row atom, and S follows the same pattern.
+    u = np.array([2.0, -3.0, 6.0]) / 7.0
+    h, s = _oo_pair(u)
+    V = -4.0 * math.exp(-3.0)          # -4 exp(-(2.5 - 1)/0.5)
+    S = 0.3 * math.exp(-2.5)           # 0.3 exp(-(2.5 - 1)/0.6)
+    uu = np.array([[4.0, -6.0, 12.0], [-6.0, 9.0, -18.0], [12.0, -18.0, 36.0]]) / 49.0   # u_a u_b by hand
+    ux = np.array([2.0, -3.0, 6.0]) / 7.0
+    for mat, f in ((h, V), (s, S)):
+        blk = mat[0:4, 4:8]            # rows: atom 0 (s, px, py, pz), columns: atom 1
+        assert abs(blk[0, 0] - f) < 1e-15
+        assert np.abs(blk[0, 1:] - ux * f).max() < 1e-15        # [s_I, p_J^b] = u_b f
+        assert np.abs(blk[1:, 0] + ux * f).max() < 1e-15        # [p_I^a, s_J] = -u_a f
+        assert np.abs(blk[1:, 1:] - uu * f).max() < 1e-15       # [p_I^a, p_J^b] = u_a u_b f
+        # the other atom sees -u: its s-p signs flip, its p-p block is the same
+        rev = mat[4:8, 0:4]
+        assert np.abs(rev[0, 1:] + ux * f).max() < 1e-15
+        assert np.abs(rev[1:, 1:] - uu * f).max() < 1e-15
+        # plausible mistakes are caught: a negative p-p sign, a pi term equal to
+        # the sigma one (which would give f * I on the p-p block)
+        assert np.abs(blk[1:, 1:] + uu * f).max() > 0.1 * abs(f)
+        assert np.abs(blk[1:, 1:] - f * np.eye(3)).max() > 0.1 * abs(f)
+
+
+def test_hs_rotation_invariance():
+    # the spectrum of a pair does not depend on the direction of its axis: a
+    # wrong sign or index in any Slater-Koster block breaks this
+    rng = np.random.default_rng(7)
+    ref = None
+    for k in range(4):
+        u = np.array([0.0, 0.0, 1.0]) if k == 0 else rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        h, s = _oo_pair(u, r=2.2)
+        lam = sla.eigh(h, s, eigvals_only=True)
+        if ref is None:
+            ref = lam
+        assert np.abs(lam - ref).max() < 1e-12
+
+
+def test_scc_shift_by_hand():
+    # SCC shift (SI section D): H_ab += 1/2 S_ab (V_I + V_J); on site S = I
+    # gives H_aa += V_I.  O at the origin, H at 1.2 A along u.
+    m = model.TBModel(orthogonal=False)
+    u = np.array([0.48, 0.6, 0.64])
+    u /= np.linalg.norm(u)
+    pos = np.array([[10.0, 10.0, 10.0], [10.0, 10.0, 10.0] + 1.2 * u])
+    sp_ = np.array([0, 1], dtype=np.int32)
+    vO, vH = 0.7, -0.3
+    h0, _ = model.dense_hs(pos, sp_, 30.0, m)
+    h1, _ = model.dense_hs(pos, sp_, 30.0, m, V_atom=np.array([vO, vH]))
+    dh = h1 - h0
+    S = 0.3 * math.exp(-(1.2 - 1.0) / 0.6)
+    want = np.zeros((5, 5))
+    want[np.arange(4), np.arange(4)] = vO                 # O orbitals: 1/2 * 1 * (vO + vO)
+    want[4, 4] = vH
+    want[0, 4] = want[4, 0] = 0.5 * S * (vO + vH)         # s_O - s_H
+    for a in range(3):                                    # p_O^a - s_H: S_ab = -u_a S
+        want[1 + a, 4] = want[4, 1 + a] = -0.5 * u[a] * S * (vO + vH)
+    assert np.abs(dh - want).max() < 1e-14
+    # a missing 1/2 or a shift by V_I alone would be caught
+    assert abs(dh[0, 4] - S * (vO + vH)) > 1e-3
+    assert abs(dh[0, 4] - 0.5 * S * 2 * vO) > 1e-3
+    # orthogonal model: only the diagonal moves, by V of the orbital's atom
+    mo = model.TBModel(orthogonal=True)
+    g0, _ = model.dense_hs(pos, sp_, 30.0, mo)
+    g1, _ = model.dense_hs(pos, sp_, 30.0, mo, V_atom=np.array([vO, vH]))
+    assert np.abs((g1 - g0) - np.diag([vO] * 4 + [vH])).max() < 1e-15
+
+
+def test_scc_uniform_potential_shifts_spectrum(box16):
+    # a uniform potential c on every atom adds c S to H, so every generalized
+    # eigenvalue moves by exactly c (with the factor 1/2 wrong it would move by 2c)
+    box = box16
+    m = model.TBModel(orthogonal=False)
+    c = 0.37
+    h0, s0 = model.dense_hs(box.pos, box.species, box.box[0], m)
+    h1, _ = model.dense_hs(box.pos, box.species, box.box[0], m, V_atom=np.full(box.n_atoms, c))
+    l0 = sla.eigh(h0, s0, eigvals_only=True)
+    l1 = sla.eigh(h1, s0, eigvals_only=True)
+    assert np.abs(l1 - l0 - c).max() < 1e-11
