@@ -72,7 +72,7 @@ def time_path(ctx, system, part, H, S, kT, precision, steps, warmup, mu_guess=0.
     ms = t0.elapsed_time(t1) / steps
     prof = {}
     for name in ("gather", "potrf", "trsm", "symmetrize", "sytrd", "steqr", "core_rows", "dcore", "mu",
-                 "mulliken", "foe_gemm", "ns_gemm", "mixed_misc", "refine64", "traces"):
+                 "mulliken", "foe_gemm", "ns_gemm", "mixed_misc", "refine64", "last64", "traces"):
         tot, n = ctx.profile_query(name)
         if n:
             prof[name] = {"ms_total": tot, "launches": n, "ms_per_step": tot / steps}
@@ -115,6 +115,82 @@ def time_response(ctx, system, part, H, S, kT, steps, warmup, mu_guess):
                         "Mulliken"}
     finally:
         ctx.set_response(0)
+
+
+def time_cold(ctx, system, part, H, S, kT, mu_guess):
+    """One mixed step whose chemical-potential search starts from a cold guess
+    (the middle of the spectral bounds when mu_guess lies outside them)."""
+    import torch
+    from paper_2606_03140_amd import pipeline
+    ctx.plan(part.sg, pipeline.MIXED_F16)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    sol = pipeline.solve(ctx, system, part, H, S, kT, pipeline.MIXED_F16, mu_guess=mu_guess, plan=False)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    st = ctx.mixed_stats()
+    return {"ms": t0.elapsed_time(t1), "passes": st["passes"], "mu_guess": mu_guess, "mu": sol.mu,
+            "note": "mixed step from a cold chemical-potential guess (one full expansion per pass)"}
+
+
+def time_graph(system, part, H, S, kT, steps, warmup, mu_start):
+    """The whole mixed step with the device-side chemical-potential search
+    (gather, inverse overlap, expansion passes, mu, density at the device mu,
+    charges) captured once into a hipGraph and replayed; each replay starts
+    from the mu the previous one found (as an MD step would)."""
+    import torch
+    from paper_2606_03140_amd import pipeline
+    from paper_2606_03140_amd._lib import Context
+    from paper_2606_03140_amd.hipgraph import StreamGraph
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        c = Context(0)
+        try:
+            c.plan(part.sg, pipeline.MIXED_F16)
+            c.set_mu_outputs(True)
+            c.set_mixed_capture(3, 10)
+            mu_t = torch.full((1,), mu_start, dtype=torch.float64, device=c.dev)
+            n_t = torch.zeros_like(mu_t)
+            D = torch.empty(int(part.sg.dcore_off[-1]), dtype=torch.float64, device=c.dev)
+            q = torch.empty(system.n_atoms, dtype=torch.float64, device=c.dev)
+
+            def step():
+                c.find_mu_device(system, part.sg, part.nbr, H, S, kT, pipeline.MIXED_F16, mu_t, n_t,
+                                 mu_guess=mu_start, tol_N=1e-6)
+                c.subgraph_density_dmu(part.sg, mu_t, kT, pipeline.MIXED_F16, D)
+                c.mulliken_charges(system, part.sg, part.nbr, S, D, out=q)
+
+            step()
+            c.check()
+            g = StreamGraph(side)
+            g.capture(step)
+            try:
+                for _ in range(warmup):
+                    g.replay()
+                g.synchronize()
+                t0 = torch.cuda.Event(enable_timing=True)
+                t1 = torch.cuda.Event(enable_timing=True)
+                t0.record(side)
+                for _ in range(steps):
+                    g.replay()
+                t1.record(side)
+                g.synchronize()
+                c.check()
+                ms = t0.elapsed_time(t1) / steps
+            finally:
+                g.close()
+            st = c.mixed_stats()
+            return {"ms_per_step": ms, "solves_per_s": part.sg.n_sub / (ms * 1e-3), "mu": float(mu_t),
+                    "electron_count": float(n_t), "passes": st["passes"], "n_doublings": st["n_doublings"],
+                    "launch_budget": {"passes": 3, "doublings_per_pass": 10},
+                    "note": "whole mixed step in one captured hipGraph (device-side mu search with predicated "
+                            "passes and doublings), replayed"}, q.cpu().numpy()
+        finally:
+            c.set_mu_outputs(False)
+            c.close()
 
 
 def cpu_baseline(box, wl, max_seconds: float = 20.0):
@@ -191,6 +267,18 @@ def gemm_source_sha256():
     return hashlib.sha256(text[:end if end >= 0 else len(text)].encode()).hexdigest()
 
 
+def profile_mean_ms():
+    """Mean split-GEMM dispatch duration of the committed rocprofv3 trace, or
+    None when the kernel source has changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        sha = gemm_source_sha256()
+    except (OSError, ValueError):
+        return None
+    return float(t["mean_duration_ms_trace"]) if t.get("source_sha256") == sha else None
+
+
 def measured_traffic():
     """HBM bytes per split-GEMM dispatch from the committed rocprofv3 counter
     summary, or None when the kernel source has changed since it was taken."""
@@ -215,6 +303,8 @@ def main():
                                                         "default)")
     ap.add_argument("--ns-inv", type=int, default=0, help="Newton-Schulz iterations per inverse in each doubling "
                                                           "(0: library default)")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="skip timing the whole mixed step as one captured hipGraph")
     ap.add_argument("--no-response", dest="response", action="store_false",
                     help="skip timing the charge response (the kernel-accelerated SCF's directional derivative)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -275,6 +365,20 @@ def main():
         except GDMError as e:
             log(f"[bench] {path} path unavailable: {e}")
 
+    if "fp64" in results:
+        # the FP64 path against the FP64 matrix-core peak: nominal flops of the
+        # route it executes (Cholesky, two triangular solves, tridiagonal
+        # reduction, core-row back-transforms) per step over the step time
+        fl0 = fp64_flops(n, nc)
+        r64 = results["fp64"]
+        work = fl0["potrf"] + 2 * fl0["trsm"] + fl0["sytrd"] + fl0["core_rows"] + fl0["dcore"]
+        dom = max(r64["kernels"].items(), key=lambda kv: kv[1]["ms_total"])
+        r64["roofline"] = {"bound": "fp64", "achieved": work / (r64["ms_per_step"] * 1e-3) / 1e12,
+                           "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
+                           "frac": work / (r64["ms_per_step"] * 1e-3) / PEAK["fp64"],
+                           "flops_per_step": work, "dominant_kernel": dom[0],
+                           "dominant_kernel_ms_per_step": dom[1]["ms_per_step"],
+                           "note": "nominal flops of the executed route / step time"}
     head = "mixed" if "mixed" in results else "fp64"
     R = results[head]
     fl = fp64_flops(n, nc)
@@ -307,6 +411,17 @@ def main():
                 "flop_per_byte": intensity, "algorithmic_bytes_per_launch": byts,
                 "mean_launch_ms": avg_ms, "gemm_launches_per_step": n_g / args.steps,
                 "passes": st["passes"], "n_doublings": st["n_doublings"], "ns_z_used": st["ns_z_used"]}
+        # the same launches counted on the method's own storage: each symmetric
+        # matrix as n (n + 1) / 2 elements instead of the 64-padded upper tiles
+        T = (n.astype(np.float64) + 63) // 64
+        upper = float(np.sum(T * (T + 1) / 2 * 64.0 * 64.0))
+        own = float(np.sum(n.astype(np.float64) * (n + 1) / 2))
+        roof["algorithmic_bytes_per_launch_unpadded"] = byts * own / upper
+        roof["frac_unpadded"] = byts * own / upper / (avg_ms * 1e-3) / PEAK["hbm"]
+        prof = profile_mean_ms()
+        if prof is not None:
+            roof["mean_launch_ms_rocprof"] = prof
+            roof["frac_rocprof"] = byts / (prof * 1e-3) / PEAK["hbm"]
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {
         "metric": "subgraph DM solves/s + % MFMA peak at 60k orbitals, mixed vs FP64 at 1e-4 e",
@@ -329,10 +444,24 @@ def main():
                    "mixed_options": {"ns_z": args.ns_z or 3, "ns_inv": args.ns_inv or 2}},
         "paths": {k: {"ms_per_step": v["ms_per_step"], "solves_per_s": v["solves_per_s"], "mu": v["mu"],
                       "electron_count": v["n_count"],
-                      "kernels_ms_per_step": {kk: round(vv["ms_per_step"], 4) for kk, vv in v["kernels"].items()}}
+                      "kernels_ms_per_step": {kk: round(vv["ms_per_step"], 4) for kk, vv in v["kernels"].items()},
+                      **({"roofline": v["roofline"]} if "roofline" in v else {})}
                   for k, v in results.items()},
         "roofline": roof,
     }
+    if "mixed" in results:
+        log("[bench] mixed step from a cold mu guess")
+        out["paths"]["mixed"]["cold_mu_step"] = time_cold(ctx, system, part, H, S, wl["kT"], -15.0)
+        log(f"[bench] cold: {out['paths']['mixed']['cold_mu_step']['ms']:.1f} ms, "
+            f"{out['paths']['mixed']['cold_mu_step']['passes']} passes")
+        if args.graph:
+            log(f"[bench] timing the whole mixed step as one captured hipGraph: warmup {args.warmup}, "
+                f"steps {args.steps}")
+            gr, q_graph = time_graph(system, part, H, S, wl["kT"], args.steps, args.warmup,
+                                     results["mixed"]["mu"])
+            gr["max_abs_dq_vs_eager_e"] = float(np.abs(q_graph - results["mixed"]["q"]).max())
+            out["paths"]["mixed_graph"] = gr
+            log(f"[bench] mixed hipGraph: {gr['ms_per_step']:.2f} ms/step")
     if args.response and "mixed" in results:
         log(f"[bench] timing the charge response: warmup {args.warmup}, steps {args.steps}")
         out["response"] = time_response(ctx, system, part, H, S, wl["kT"], args.steps, args.warmup,

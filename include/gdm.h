@@ -38,9 +38,10 @@
  *   with gdm_set_mu_outputs(ctx, 1), gdm_find_mu enqueues kernels only as
  *   well, so the whole solve (gather, factorisation, eigensolver, mu search,
  *   gdm_subgraph_density_dmu at the device mu, charges) captures into one
- *   graph that a replay runs on the current contents of H and S.  The mixed path's
- *   gdm_find_mu is not capturable: it decides expansion passes, doubling
- *   counts and inverse-overlap iterations on the host.
+ *   graph that a replay runs on the current contents of H and S.  The same
+ *   holds on the MIXED_F16 path: with device outputs its search launches a
+ *   fixed number of expansion passes, doublings and inverse-overlap rounds
+ *   (gdm_set_mixed_capture) and the device skips those it does not need.
  */
 #ifndef GDM_H
 #define GDM_H
@@ -207,12 +208,18 @@ int gdm_plan(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision);
  * FP64_EIG: multisection on the eigenvalues and core weights to an interval
  * of 1e-12 eV, mu_guess ignored.  MIXED_F16: Newton steps from mu_guess on
  * FP64 core traces with a bisection safeguard, one full expansion per pass,
- * until |N - n_electrons| <= max(tol_N, 1e-7 n_electrons) (the rounding
- * level of the traces); if the pass budget runs out first, the first-order
- * correction mu + (n_electrons - N)/N'(mu) is applied when it lies within kT.  *mu_out, *n_out HOST (DEVICE
- * scalars after gdm_set_mu_outputs(ctx, 1), FP64_EIG only).  The
- * factorisation / expansion state is cached in the context for
- * gdm_subgraph_density. */
+ * until |N - n_electrons| <= max(tol_N, 1e-10 n_electrons), or the Newton
+ * step is below 1e-2 kT, or the pass budget runs out; the first-order
+ * correction mu + (n_electrons - N)/N'(mu) is then applied when the count is
+ * not yet matched and the correction lies within kT, and the result must
+ * count within max(tol_N, 1e-7 n_electrons) (the rounding level of the
+ * traces), else GDM_E_NO_BRACKET.  The search converges to where the mixed
+ * count equals n_electrons (not to the first mu inside the count's rounding
+ * level): inside a gap N(mu) is nearly flat, and only the zero of the count
+ * places mu where the FP64 path does, to the count's rounding bias divided by
+ * N'(mu).  *mu_out, *n_out HOST (DEVICE scalars after
+ * gdm_set_mu_outputs(ctx, 1)).  The factorisation / expansion state is cached
+ * in the context for gdm_subgraph_density. */
 int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
                 const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                 const double* H, const double* S, double n_electrons, double kT,
@@ -221,14 +228,35 @@ int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
 
 /* Where gdm_find_mu puts mu and N(mu).  device = 0 (default): HOST pointers;
  * the call synchronises the stream and checks the electron count on the
- * host.  device = 1: DEVICE pointers to one double each, FP64_EIG only
- * (MIXED_F16 returns GDM_E_ARG); the whole search is enqueued without host
- * synchronisation, so gdm_find_mu can be captured into a hipGraph with the
- * density and charge calls, and a count off by more than 1e-6 n_electrons (or
- * a NaN) is recorded in the device status word, reported by gdm_check.  A
+ * host.  device = 1: DEVICE pointers to one double each; the whole search is
+ * enqueued without host synchronisation, so gdm_find_mu can be captured into
+ * a hipGraph with the density and charge calls (gdm_subgraph_density_dmu at
+ * the device mu), and a count off by more than the tolerance (FP64_EIG
+ * 1e-6 n_electrons, MIXED_F16 max(tol_N, 1e-7 n_electrons)) or a NaN is
+ * recorded in the device status word, reported by gdm_check.  MIXED_F16 with
+ * device outputs: the search starts from *mu_out's value when it is finite
+ * and inside the spectral bounds (the previous result, so a replayed graph
+ * warm-starts from the last step; the caller writes NaN to start from
+ * mu_guess), runs at most the passes set by gdm_set_mixed_capture with the
+ * degree-7 start and at least 5 doublings, and does not record the expansion
+ * for the charge response (GDM_E_ARG while gdm_set_response is on).  A
  * setting of the context, kept until changed.  Returns GDM_E_ARG for other
  * values of device. */
 int gdm_set_mu_outputs(gdm_ctx* ctx, int device);
+
+/* Launch budget of the MIXED_F16 search with device outputs: `passes`
+ * expansion passes (1..16, default 3) of `nd_launch` doublings each (5..40,
+ * default 12); a pass or a doubling the search does not need exits at once
+ * on the device.  A problem needing more doublings than nd_launch (spectral
+ * half-width R with beta R > 8 * 2^nd_launch) raises GDM_E_CAPACITY in the
+ * status word.  The host-driven search (device outputs off) is unaffected. */
+int gdm_set_mixed_capture(gdm_ctx* ctx, int passes, int nd_launch);
+
+/* State of the last MIXED_F16 search (HOST outputs, nullable; synchronises):
+ * the chemical potential of its last expansion pass, the electron count N
+ * there and dN/dmu = beta M.  D of gdm_subgraph_density is evaluated to first
+ * order about mu_pass. */
+int gdm_mixed_mu_state(gdm_ctx* ctx, double* mu_pass, double* n_pass, double* slope);
 
 /* Collected core rows D[core, :] of every subgraph (Eq. 3) at chemical
  * potential mu, from the state cached by gdm_find_mu (same precision).
@@ -245,12 +273,15 @@ int gdm_set_mu_outputs(gdm_ctx* ctx, int device);
 int gdm_subgraph_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT,
                          int precision, double* D_core, double* eig_out);
 
-/* gdm_subgraph_density on the FP64_EIG path at a chemical potential held in
- * DEVICE memory (*mu_device, read when the kernel runs), e.g. the mu_out of
- * a gdm_find_mu in device-output mode (gdm_set_mu_outputs), so that a
- * captured graph of gdm_find_mu, this call and gdm_mulliken_charges uses the
- * mu each replay finds.  D_core as for gdm_subgraph_density.  GDM_E_ARG for
- * other precisions or null pointers; GDM_E_STATE before gdm_find_mu. */
+/* gdm_subgraph_density at a chemical potential held in DEVICE memory
+ * (*mu_device, read when the kernel runs), e.g. the mu_out of a gdm_find_mu in
+ * device-output mode (gdm_set_mu_outputs), so that a captured graph of
+ * gdm_find_mu, this call and gdm_mulliken_charges uses the mu each replay
+ * finds.  MIXED_F16: D is taken to first order about the last pass's mu (read
+ * on the device too), which the mu of a device-side search keeps within kT;
+ * kT must equal gdm_find_mu's.  D_core as for gdm_subgraph_density.
+ * GDM_E_ARG for null pointers or another kT; GDM_E_STATE before
+ * gdm_find_mu. */
 int gdm_subgraph_density_dmu(gdm_ctx* ctx, const gdm_subgraphs* sg, const double* mu_device, double kT,
                              int precision, double* D_core);
 
@@ -263,14 +294,18 @@ int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
                          const double* S, const double* D_core, const double n0[2],
                          double* q_out);
 
-/* Options of the mixed-precision expansion (GDM_MIXED_F16).  ns_z: coupled
+/* Options of the mixed-precision expansion (GDM_MIXED_F16; its last doubling
+ * of every pass runs in FP64 on the matrix cores, which squares away the
+ * split products' errors in the fully occupied and empty states so that the
+ * electron count carries no systematic bias).  ns_z: coupled
  * Newton-Schulz iterations for s^-1/2 to try first (default 3).  With x the
  * eigenvalues of s/c (c the largest absolute row sum) and the start
  * Z0 = 2.598551 I - 1.834840 s/c (the linear minimax approximation of
  * x^-1/2 for |1 - x z^2| on [0.1, 1]: e0 <= 0.417 there), the error falls
- * as e -> 3/4 e^2 + 1/4 e^3, and one residual refinement step then
- * squares it; before that step gdm_find_mu checks
- * max |(Z s Z - I)_ij| and, while it exceeds 3e-3, runs one more iteration,
+ * as e -> 3/4 e^2 + 1/4 e^3, and one third-order FP64 residual refinement
+ * step Z <- Z (I - E/2 + 3/8 E^2), E = Z s Z - I, then cubes it; before that
+ * step gdm_find_mu checks max |E_ij| and, while it exceeds 1e-3, runs one
+ * more iteration,
  * at most ns_z_extra times (default 8), after which it returns
  * GDM_E_NOT_CONVERGED (overlap too ill-conditioned).  ns_inv: Newton-Schulz
  * iterations per inverse in each doubling after the minimax quadratic start

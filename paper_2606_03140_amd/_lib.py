@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     sig["gdm_set_mixed_options"] = (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int])
     sig["gdm_set_mu_outputs"] = (C.c_int, [P, C.c_int])
     sig["gdm_set_mixed_storage"] = (C.c_int, [P, C.c_int])
+    sig["gdm_set_mixed_capture"] = (C.c_int, [P, C.c_int, C.c_int])
+    sig["gdm_mixed_mu_state"] = (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)])
     sig["gdm_subgraph_density_dmu"] = (C.c_int, [P, C.POINTER(SubgraphsT), P, D, C.c_int, P])
     sig["gdm_mixed_stats"] = (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)])
@@ -345,22 +347,34 @@ class Context:
 
     def set_mu_outputs(self, device: bool):
         """device=True: find_mu_device writes mu and N(mu) to device scalars
-        without synchronising (FP64 path only)."""
+        without synchronising (both paths; the mixed path then searches with a
+        fixed number of predicated passes, set_mixed_capture)."""
         self._check(self.lib.gdm_set_mu_outputs(self.h, 1 if device else 0))
 
+    def set_mixed_capture(self, passes: int, nd_launch: int):
+        self._check(self.lib.gdm_set_mixed_capture(self.h, int(passes), int(nd_launch)))
+
+    def mixed_mu_state(self) -> dict:
+        mp, npass, sl = C.c_double(0.0), C.c_double(0.0), C.c_double(0.0)
+        self._check(self.lib.gdm_mixed_mu_state(self.h, C.byref(mp), C.byref(npass), C.byref(sl)))
+        return {"mu_pass": mp.value, "n_pass": npass.value, "slope": sl.value}
+
     def find_mu_device(self, system: System, sg: Subgraphs, graph: Graph, H, S, kT: float, precision: int,
-                       mu_out: torch.Tensor, n_out: torch.Tensor, n_electrons: float | None = None):
+                       mu_out: torch.Tensor, n_out: torch.Tensor, n_electrons: float | None = None,
+                       mu_guess: float = 0.0, tol_N: float = 0.0):
         """gdm_find_mu with DEVICE outputs (after set_mu_outputs(True)): mu_out and
-        n_out are float64 device tensors of one element, written on the stream."""
+        n_out are float64 device tensors of one element, written on the stream
+        (the mixed path starts from mu_out's value when it is finite and inside
+        the spectral bounds, else from mu_guess)."""
         ne = system.n_electrons if n_electrons is None else n_electrons
         self._check(self.lib.gdm_find_mu(self.h, C.byref(system.struct()), C.byref(sg.struct()), _ptr(graph.row_ptr),
-                                         _ptr(graph.col), graph.nnz, _ptr(H), _ptr(S), ne, kT, precision, 0.0, 0.0,
-                                         C.cast(_ptr(mu_out), C.POINTER(C.c_double)),
+                                         _ptr(graph.col), graph.nnz, _ptr(H), _ptr(S), ne, kT, precision, mu_guess,
+                                         tol_N, C.cast(_ptr(mu_out), C.POINTER(C.c_double)),
                                          C.cast(_ptr(n_out), C.POINTER(C.c_double))))
 
     def subgraph_density_dmu(self, sg: Subgraphs, mu_device: torch.Tensor, kT: float, precision: int,
                              out: torch.Tensor):
-        """D core rows at the chemical potential held in the device scalar mu_device (FP64 path)."""
+        """D core rows at the chemical potential held in the device scalar mu_device."""
         self._check(self.lib.gdm_subgraph_density_dmu(self.h, C.byref(sg.struct()), _ptr(mu_device), kT, precision,
                                                       _ptr(out)))
         return out

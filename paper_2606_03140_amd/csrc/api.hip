@@ -215,7 +215,7 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
     static const int kFp64Only[] = {BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W, BUF_ROTC, BUF_ROTS,
                                     BUF_ROTI, BUF_ROTN, BUF_QC, BUF_MU, BUF_MUPART};
     static const int kMixedOnly[] = {BUF_X_F, BUF_X_HI, BUF_X_LO, BUF_GERSH, BUF_TR, BUF_NDBL, BUF_TILES,
-                                     BUF_HIST_HI, BUF_HIST_LO, BUF_RESP};
+                                     BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_MSTATE};
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (precision == GDM_FP64_EIG)
         for (int s : kMixedOnly) gdm_buf_release(ctx, s);
@@ -231,7 +231,8 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         gdm_buf(ctx, BUF_ROTC, sizeof(double) * P.totr, &ok);
         gdm_buf(ctx, BUF_ROTS, sizeof(double) * P.totr, &ok);
         gdm_buf(ctx, BUF_ROTI, sizeof(int32_t) * P.totr, &ok);
-        gdm_buf(ctx, BUF_ROTN, sizeof(int64_t) * ns, &ok);
+        gdm_buf(ctx, BUF_ROTN, sizeof(int64_t) * 2 * ns, &ok);     // rotations and sweeps per subgraph
+        gdm_buf(ctx, BUF_ORDER, sizeof(int32_t) * ns, &ok);        // longest first
         gdm_buf(ctx, BUF_QC, sizeof(double) * 2 * P.totc, &ok);
         gdm_buf(ctx, BUF_CC, sizeof(double) * P.totc, &ok);
         gdm_buf(ctx, BUF_MU, sizeof(double) * 8, &ok);
@@ -246,6 +247,14 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
     }
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_plan: workspace allocation failed");
     GDM_HIP(ctx, hipMemcpyAsync(desc, P.desc.data(), sizeof(SubDesc) * ns, hipMemcpyHostToDevice, ctx->stream));
+    if (precision == GDM_FP64_EIG) {
+        // workgroups take the subgraphs in decreasing size (ties by index)
+        P.order.resize(ns);
+        for (int s = 0; s < ns; ++s) P.order[s] = s;
+        std::stable_sort(P.order.begin(), P.order.end(), [&](int a, int b) { return P.n[a] > P.n[b]; });
+        GDM_HIP(ctx, hipMemcpyAsync(ctx->b[BUF_ORDER].p, P.order.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice,
+                                    ctx->stream));
+    }
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     P.generation++;
     return GDM_OK;
@@ -283,8 +292,6 @@ extern "C" int gdm_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgra
     if (n_electrons >= cap)
         return gdm_fail(ctx, GDM_E_NO_BRACKET, "gdm_find_mu: %g electrons do not fit in %g core spin-orbitals",
                         n_electrons, cap);
-    if (ctx->mu_out_device && precision != GDM_FP64_EIG)
-        return gdm_fail(ctx, GDM_E_ARG, "gdm_find_mu: device outputs exist only for GDM_FP64_EIG");
     ctx->solved = false;
     (void)hipGetLastError();   // a stale error of an earlier, unrelated call must not be blamed here
     if (precision == GDM_FP64_EIG)
@@ -339,11 +346,14 @@ extern "C" int gdm_subgraph_density(gdm_ctx* ctx, const gdm_subgraphs* sg, doubl
     if (std::fabs(kT - ctx->kT_solved) > 1e-12 * ctx->kT_solved)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density: kT %.17g differs from gdm_find_mu's %.17g (mixed path)",
                         kT, ctx->kT_solved);
-    if (std::fabs(mu - ctx->mixed_mu_pass) > kT)
+    double mu_pass = 0.0;
+    if ((rc = gdm_mixed_pass_mu(ctx, &mu_pass))) return rc;
+    if (!(std::fabs(mu - mu_pass) <= kT))
         return gdm_fail(ctx, GDM_E_ARG,
                         "gdm_subgraph_density: mu %.12g is more than kT from the expansion's %.12g (mixed path: "
-                        "first-order range)", mu, ctx->mixed_mu_pass);
-    return gdm_mixed_density(ctx, sg, mu, kT, D_core);
+                        "first-order range)", mu, mu_pass);
+    ctx->mixed_mu_pass = mu_pass;
+    return gdm_mixed_density(ctx, sg, mu, nullptr, kT, D_core);
 }
 
 extern "C" int gdm_subgraph_density_dmu(gdm_ctx* ctx, const gdm_subgraphs* sg, const double* mu_device, double kT,
@@ -353,11 +363,14 @@ extern "C" int gdm_subgraph_density_dmu(gdm_ctx* ctx, const gdm_subgraphs* sg, c
     if ((rc = check_plan(ctx, sg, precision, "gdm_subgraph_density_dmu"))) return rc;
     if (!D_core || !mu_device || !(kT > 0.0))
         return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density_dmu: null argument or bad kT");
-    if (precision != GDM_FP64_EIG)
-        return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density_dmu: only GDM_FP64_EIG reads mu from device memory");
     if (!ctx->solved || ctx->solved_precision != precision)
         return gdm_fail(ctx, GDM_E_STATE, "gdm_subgraph_density_dmu: call gdm_find_mu first");
-    return gdm_fp64_density(ctx, sg, 0.0, mu_device, kT, D_core, nullptr);
+    if (precision == GDM_FP64_EIG) return gdm_fp64_density(ctx, sg, 0.0, mu_device, kT, D_core, nullptr);
+    if (std::fabs(kT - ctx->kT_solved) > 1e-12 * ctx->kT_solved)
+        return gdm_fail(ctx, GDM_E_ARG,
+                        "gdm_subgraph_density_dmu: kT %.17g differs from gdm_find_mu's %.17g (mixed path)", kT,
+                        ctx->kT_solved);
+    return gdm_mixed_density(ctx, sg, 0.0, mu_device, kT, D_core);
 }
 
 extern "C" int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,

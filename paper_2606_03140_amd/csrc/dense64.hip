@@ -8,6 +8,8 @@
 //   D[core,:] = (C[core,:] diag(f) R^T Hh^T) L^-1  (collected core rows, Eq. 3)
 // so after the O(n^3) reductions everything is O(nc n^2).
 // The basis Z = L^-T gives the same D as Z = s^-1/2 (any Z with Z Z^T = s^-1).
+// Workgroups take subgraphs longest first (order[], by n), so the largest
+// problems start first and the short ones fill in behind them.
 #include "gdm_internal.h"
 
 #include <map>
@@ -20,77 +22,199 @@ namespace {
 
 constexpr int kThreads = 256;   // threads per workgroup for the per-subgraph kernels
 
+// subgraph handled by this workgroup (longest first)
+__device__ __forceinline__ int sub_of_block(const int32_t* __restrict__ order) { return order[blockIdx.x]; }
+
+// 32 x 32 tiles staged in LDS with a padded row (33 doubles): the row-wise
+// stores and the column-wise reads of the tile products hit distinct banks.
+constexpr int kTb = 32;
+
+// acc[2][2] += sA[r][k] * sB[c][k] over k < kn for this thread's 2 x 2
+// outputs (rows 2 (t / 16) + {0, 1}, columns 2 (t % 16) + {0, 1} of a
+// 32 x 32 tile, 256 threads; the B operand is staged as rows of the
+// transposed operand)
+__device__ __forceinline__ void tile_nt(double acc[2][2], const double (*sA)[kTb + 1], const double (*sB)[kTb + 1],
+                                        int kn) {
+    const int t = threadIdx.x;
+    const int r = 2 * (t >> 4), c = 2 * (t & 15);
+    for (int k = 0; k < kn; ++k) {
+        const double a0 = sA[r][k], a1 = sA[r + 1][k];
+        const double b0 = sB[c][k], b1 = sB[c + 1][k];
+        acc[0][0] += a0 * b0;
+        acc[0][1] += a0 * b1;
+        acc[1][0] += a1 * b0;
+        acc[1][1] += a1 * b1;
+    }
+}
+
 // ------------------------------------------------------------- Cholesky
-// Left-looking, column by column: row j of L staged in LDS; each wave forms
-// the dot products of the rows below with it (lanes over the inner index).
-__global__ void __launch_bounds__(kThreads) k_potrf(const SubDesc* __restrict__ desc, double* __restrict__ Sd,
-                                             int* __restrict__ status) {
-    extern __shared__ double rowj[];
-    __shared__ double s_diag;
-    const SubDesc d = desc[blockIdx.x];
+// Left-looking blocked Cholesky s = L L^T in place (lower triangle), one
+// workgroup per subgraph, block columns of 32: the panel rows of block column
+// J take the update - L[:, 0:J] L[J, 0:J]^T tile by tile (32 x 32 tiles of the
+// two factors staged in LDS, 2 x 4 outputs per thread), then the 32 x 32
+// diagonal block is factored in LDS and the rows below are solved against it
+// (one thread per row).  A non-positive pivot raises GDM_STATUS_NOT_PD.
+__global__ void __launch_bounds__(kThreads) k_potrf(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                             double* __restrict__ Sd, int* __restrict__ status) {
+    __shared__ double sA[kTb][kTb + 1], sB[kTb][kTb + 1];
+    const SubDesc d = desc[sub_of_block(order)];
     const int n = d.n, ld = d.ld;
     double* a = Sd + d.off2;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j = 0; j < n; ++j) {
-        // diagonal
-        if (wave == 0) {
-            double acc = 0.0;
-            for (int k = lane; k < j; k += 64) {
-                double v = a[(int64_t)j * ld + k];
-                acc += v * v;
+    const int t = threadIdx.x;
+    const int tr = 2 * (t >> 4), tc = 2 * (t & 15);
+    const int nbk = (n + kTb - 1) / kTb;
+    for (int J = 0; J < nbk; ++J) {
+        const int j0 = J * kTb, jn = min(kTb, n - j0);
+        // panel update, row blocks I >= J
+        for (int I = J; I < nbk; ++I) {
+            const int i0 = I * kTb;
+            double acc[2][2] = {{0, 0}, {0, 0}};
+            for (int K = 0; K < J; ++K) {
+                const int k0 = K * kTb;
+                __syncthreads();
+                for (int e = t; e < kTb * kTb; e += kThreads) {
+                    const int rr = e >> 5, kk = e & 31;
+                    sA[rr][kk] = i0 + rr < n ? a[(int64_t)(i0 + rr) * ld + k0 + kk] : 0.0;
+                    sB[rr][kk] = j0 + rr < n ? a[(int64_t)(j0 + rr) * ld + k0 + kk] : 0.0;
+                }
+                __syncthreads();
+                tile_nt(acc, sA, sB, kTb);
             }
-            acc = gdm_wave_sum(acc);
-            if (lane == 0) {
-                double v = a[(int64_t)j * ld + j] - acc;
+            if (J > 0)
+                for (int rr = 0; rr < 2; ++rr)
+                    for (int q = 0; q < 2; ++q) {
+                        const int i = i0 + tr + rr, j = j0 + tc + q;
+                        if (i < n && j < n && j <= i) a[(int64_t)i * ld + j] -= acc[rr][q];
+                    }
+        }
+        __syncthreads();
+        // factor the diagonal block in LDS
+        for (int e = t; e < kTb * kTb; e += kThreads) {
+            const int rr = e >> 5, cc = e & 31;
+            sA[rr][cc] = (rr < jn && cc <= rr) ? a[(int64_t)(j0 + rr) * ld + j0 + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int c = 0; c < jn; ++c) {
+            if (t == 0) {
+                double v = sA[c][c];
                 if (!(v > 0.0)) {
                     gdm_raise(status, GDM_STATUS_NOT_PD);
                     v = 1.0;
                 }
-                v = sqrt(v);
-                a[(int64_t)j * ld + j] = v;
-                s_diag = v;
+                sA[c][c] = sqrt(v);
             }
+            __syncthreads();
+            if (t > c && t < jn) sA[t][c] /= sA[c][c];
+            __syncthreads();
+            for (int e = t; e < kTb * kTb; e += kThreads) {
+                const int rr = e >> 5, cc = e & 31;
+                if (rr > c && cc > c && cc <= rr && rr < jn) sA[rr][cc] -= sA[rr][c] * sA[cc][c];
+            }
+            __syncthreads();
         }
-        for (int k = threadIdx.x; k < j; k += kThreads) rowj[k] = a[(int64_t)j * ld + k];
-        __syncthreads();
-        const double inv = 1.0 / s_diag;
-        for (int i = j + 1 + wave; i < n; i += kThreads / 64) {
-            const double* ri = a + (int64_t)i * ld;
-            double acc = 0.0;
-            for (int k = lane; k < j; k += 64) acc += ri[k] * rowj[k];
-            acc = gdm_wave_sum(acc);
-            if (lane == 0) a[(int64_t)i * ld + j] = (ri[j] - acc) * inv;
+        for (int e = t; e < kTb * kTb; e += kThreads) {
+            const int rr = e >> 5, cc = e & 31;
+            if (rr < jn && cc <= rr) a[(int64_t)(j0 + rr) * ld + j0 + cc] = sA[rr][cc];
+        }
+        // rows below: L[i, J] L_JJ^T = A[i, J], one thread per row
+        for (int i = j0 + jn + t; i < n; i += kThreads) {
+            double* ri = a + (int64_t)i * ld + j0;
+            for (int c = 0; c < jn; ++c) {
+                double v = ri[c];
+                for (int cc = 0; cc < c; ++cc) v -= ri[cc] * sA[c][cc];
+                ri[c] = v / sA[c][c];
+            }
         }
         __syncthreads();
     }
 }
 
 // ------------------------------------------- triangular solves, h_perp
-// X = L^-1 B (forward substitution), one thread per right-hand side column.
-// MODE 0: B = A (h), result into T.   MODE 1: B = T^T, result into A.
+// X = L^-1 B for 64 right-hand-side columns per workgroup (grid: subgraph x
+// column block), left-looking in row blocks of 32: a row block takes
+// B - L[I, 0:I] X[0:I, :] (32 x 32 tiles of L and of the rows of X already
+// solved, staged in LDS), then the 32 x 32 diagonal block is solved in LDS
+// by columns.  MODE 0: B = A (h), result into T.  MODE 1: B = T^T, result
+// into A (so A becomes L^-1 h L^-T).
+constexpr int kTc = 64;
+
 template <int MODE>
-__global__ void __launch_bounds__(kThreads) k_trsm(const SubDesc* __restrict__ desc, const double* __restrict__ Lm,
-                                            double* __restrict__ A, double* __restrict__ T) {
-    const SubDesc d = desc[blockIdx.x];
+__global__ void __launch_bounds__(kThreads) k_trsm(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                            const double* __restrict__ Lm, double* __restrict__ A,
+                                            double* __restrict__ T) {
+    __shared__ double sL[kTb][kTb + 1];
+    __shared__ double sX[kTc][kTb + 1];     // transposed: sX[col][k]
+    __shared__ double sR[kTb][kTc + 1];     // the row block being solved
+    const SubDesc d = desc[sub_of_block(order)];
     const int n = d.n, ld = d.ld;
+    const int c0 = blockIdx.y * kTc;
+    if (c0 >= n) return;
     const double* l = Lm + d.off2;
     double* a = A + d.off2;
-    double* t = T + d.off2;
-    double* X = MODE == 0 ? t : a;
-    for (int c = threadIdx.x; c < n; c += kThreads) {
-        for (int i = 0; i < n; ++i) {
-            double b = MODE == 0 ? a[(int64_t)i * ld + c] : t[(int64_t)c * ld + i];
-            const double* li = l + (int64_t)i * ld;
-            double acc = 0.0;
-            for (int k = 0; k < i; ++k) acc += li[k] * X[(int64_t)k * ld + c];
-            X[(int64_t)i * ld + c] = (b - acc) / li[i];
+    double* tt = T + d.off2;
+    double* X = MODE == 0 ? tt : a;
+    const int t = threadIdx.x;
+    // outputs: rows 2 (t / 16) + {0, 1}, columns 4 (t % 16) + {0..3} of the 32 x 64 block
+    const int tr = 2 * (t >> 4), tc = 4 * (t & 15);
+    const int nbk = (n + kTb - 1) / kTb;
+    for (int I = 0; I < nbk; ++I) {
+        const int i0 = I * kTb, in = min(kTb, n - i0);
+        double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+        for (int K = 0; K < I; ++K) {
+            const int k0 = K * kTb;
+            __syncthreads();
+            for (int e = t; e < kTb * kTb; e += kThreads) {
+                const int rr = e >> 5, kk = e & 31;
+                sL[rr][kk] = i0 + rr < n ? l[(int64_t)(i0 + rr) * ld + k0 + kk] : 0.0;
+            }
+            for (int e = t; e < kTb * kTc; e += kThreads) {
+                const int kk = e >> 6, cc = e & 63;
+                sX[cc][kk] = c0 + cc < n ? X[(int64_t)(k0 + kk) * ld + c0 + cc] : 0.0;
+            }
+            __syncthreads();
+            for (int k = 0; k < kTb; ++k) {
+                const double a0 = sL[tr][k], a1 = sL[tr + 1][k];
+                for (int q = 0; q < 4; ++q) {
+                    const double bq = sX[tc + q][k];
+                    acc[0][q] += a0 * bq;
+                    acc[1][q] += a1 * bq;
+                }
+            }
+        }
+        __syncthreads();
+        // right-hand side minus the update, and the diagonal block of L
+        for (int rr = 0; rr < 2; ++rr)
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + tr + rr, c = c0 + tc + q;
+                double b = 0.0;
+                if (i < n && c < n) b = MODE == 0 ? a[(int64_t)i * ld + c] : tt[(int64_t)c * ld + i];
+                sR[tr + rr][tc + q] = b - acc[rr][q];
+            }
+        for (int e = t; e < kTb * kTb; e += kThreads) {
+            const int rr = e >> 5, kk = e & 31;
+            sL[rr][kk] = (rr < in && kk <= rr) ? l[(int64_t)(i0 + rr) * ld + i0 + kk] : 0.0;
+        }
+        __syncthreads();
+        for (int r = 0; r < in; ++r) {
+            if (t < kTc) sR[r][t] /= sL[r][r];
+            __syncthreads();
+            for (int e = t; e < (in - r - 1) * kTc; e += kThreads) {
+                const int rr = r + 1 + (e >> 6), cc = e & 63;
+                sR[rr][cc] -= sL[rr][r] * sR[r][cc];
+            }
+            __syncthreads();
+        }
+        for (int e = t; e < in * kTc; e += kThreads) {
+            const int rr = e >> 6, cc = e & 63;
+            if (c0 + cc < n) X[(int64_t)(i0 + rr) * ld + c0 + cc] = sR[rr][cc];
         }
     }
 }
 
 // A <- (A + A^T)/2 (exact symmetry for the reduction)
-__global__ void __launch_bounds__(kThreads) k_symmetrize(const SubDesc* __restrict__ desc, double* __restrict__ A) {
-    const SubDesc d = desc[blockIdx.x];
+__global__ void __launch_bounds__(kThreads) k_symmetrize(const SubDesc* __restrict__ desc,
+                                                  const int32_t* __restrict__ order, double* __restrict__ A) {
+    const SubDesc d = desc[sub_of_block(order)];
     const int n = d.n, ld = d.ld;
     double* a = A + d.off2;
     for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kThreads) {
@@ -103,85 +227,165 @@ __global__ void __launch_bounds__(kThreads) k_symmetrize(const SubDesc* __restri
 }
 
 // ------------------------------------------------ Householder tridiagonal
-// Unblocked reduction on full symmetric storage.  Step k reflects x =
-// A[k+1:, k] onto beta e_1 with H = I - tau v v^T, v_0 = 1; v (without the
-// unit) is stored in row k of A from column k+2 on; d, e, tau per subgraph.
-__device__ __forceinline__ double block_sum(double v, double* red) {
+// Reduction on full symmetric storage, blocked in panels of nb columns (the
+// delayed-update form of the Householder tridiagonalisation): step k reflects
+// x = A[k+1:, k] onto beta e_1 with H = I - tau v v^T, v_0 = 1, where within a
+// panel A is kept as it was at the panel's start and the updates of the
+// panel's earlier steps, A - V W^T - W V^T, are applied on the fly to the
+// column being reduced and to the product p = A22 v; w = tau p - tau^2/2
+// (p^T v) v.  The trailing matrix takes the whole panel's rank-2nb update
+// once, in 32 x 32 tiles with the panel rows of V and W staged in LDS.  So
+// the trailing matrix is read once per column (the product) and read and
+// written once per panel, instead of read twice and written once per column.
+// V and W live column-major (n x nb each) in the subgraph's scratch tile W2
+// (needs 2 n nb <= ld^2; nb shrinks for the smallest subgraphs).  v (without
+// the unit) is stored in row k of A from column k+2 on; d, e, tau per
+// subgraph, as the core-row kernels read them.
+constexpr int kTrd = 512;              // threads of the tridiagonalisation
+constexpr int kPanel = 16;             // panel width nb
+
+__device__ __forceinline__ double block_sum_n(double v, double* red, int nthreads) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     v = gdm_wave_sum(v);
     __syncthreads();
     if (lane == 0) red[wave] = v;
     __syncthreads();
     double s = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    for (int w = 0; w < nthreads / 64; ++w) s += red[w];
     return s;
 }
 
-__global__ void __launch_bounds__(kThreads) k_sytrd(const SubDesc* __restrict__ desc, double* __restrict__ A,
-                                             double* __restrict__ Dg, double* __restrict__ Eg,
-                                             double* __restrict__ Tau) {
+__global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                             double* __restrict__ A, double* __restrict__ W2, double* __restrict__ Dg,
+                                             double* __restrict__ Eg, double* __restrict__ Tau) {
     extern __shared__ double sm[];
-    __shared__ double red[kThreads / 64];
-    const SubDesc dsc = desc[blockIdx.x];
+    __shared__ double red[kTrd / 64];
+    __shared__ double corr[4 * kPanel];     // V[k,:], W[k,:], W^T v, V^T v of the current step
+    __shared__ double tV[2][32][kPanel + 1], tW[2][32][kPanel + 1];   // trailing-update staging (rows, cols)
+    const SubDesc dsc = desc[sub_of_block(order)];
     const int n = dsc.n, ld = dsc.ld;
     double* a = A + dsc.off2;
     double* dd = Dg + dsc.offv;
     double* ee = Eg + dsc.offv;
     double* tau = Tau + dsc.offv;
     double* v = sm;          // [n]
-    double* w = sm + n;      // [n]
+    double* p = sm + n;      // [n]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = 0; k < n - 2; ++k) {
-        const int m = n - k - 1;             // length of x
-        const double* rowk = a + (int64_t)k * ld + (k + 1);   // x (row k == column k)
-        double part = 0.0;
-        for (int i = 1 + threadIdx.x; i < m; i += kThreads) {
-            double x = rowk[i];
-            part += x * x;
+    int nb = kPanel;
+    while (nb > 1 && 2LL * n * nb > (int64_t)ld * ld) nb >>= 1;
+    double* Vm = W2 + dsc.off2;              // V[r][l] = Vm[l * n + r]
+    double* Wm = Vm + (int64_t)n * nb;
+    for (int k0 = 0; k0 < n - 2; k0 += nb) {
+        const int kend = min(k0 + nb, n - 2), jb = kend - k0;
+        for (int j = 0; j < jb; ++j) {
+            const int k = k0 + j;
+            const int m = n - k - 1;                   // length of x
+            // row k of V and W (the pending corrections of column k)
+            if (threadIdx.x < j) {
+                corr[threadIdx.x] = Vm[(int64_t)threadIdx.x * n + k];
+                corr[kPanel + threadIdx.x] = Wm[(int64_t)threadIdx.x * n + k];
+            }
+            __syncthreads();
+            // x = A[k+1:, k] - V W[k,:]^T - W V[k,:]^T (held in v), and the diagonal
+            double part = 0.0;
+            for (int i = threadIdx.x; i < m; i += kTrd) {
+                const int r = k + 1 + i;
+                double x = a[(int64_t)k * ld + r];
+                for (int l = 0; l < j; ++l)
+                    x -= Vm[(int64_t)l * n + r] * corr[kPanel + l] + Wm[(int64_t)l * n + r] * corr[l];
+                v[i] = x;
+                if (i > 0) part += x * x;
+            }
+            const double xn2 = block_sum_n(part, red, kTrd);
+            const double alpha = v[0];
+            double beta, t, scale;
+            if (xn2 == 0.0) {
+                beta = alpha;
+                t = 0.0;
+                scale = 0.0;
+            } else {
+                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                t = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            if (threadIdx.x == 0) {
+                double akk = a[(int64_t)k * ld + k];
+                for (int l = 0; l < j; ++l) akk -= 2.0 * corr[l] * corr[kPanel + l];
+                dd[k] = akk;
+                ee[k] = beta;
+                tau[k] = t;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < m; i += kTrd) v[i] = i == 0 ? 1.0 : v[i] * scale;
+            __syncthreads();
+            // p = A22 v, A22 = A[k+1:, k+1:] as at the panel's start; one wave per row
+            for (int i = wave; i < m; i += kTrd / 64) {
+                const double* ri = a + (int64_t)(k + 1 + i) * ld + (k + 1);
+                double a0 = 0.0, a1 = 0.0;
+                int c = lane;
+                for (; c + 64 < m; c += 128) {
+                    a0 += ri[c] * v[c];
+                    a1 += ri[c + 64] * v[c + 64];
+                }
+                if (c < m) a0 += ri[c] * v[c];
+                const double acc = gdm_wave_sum(a0 + a1);
+                if (lane == 0) p[i] = acc;
+            }
+            // W^T v and V^T v over rows k+1.. (one wave per panel column)
+            for (int l = wave; l < 2 * j; l += kTrd / 64) {
+                const double* col = (l < j ? Wm + (int64_t)l * n : Vm + (int64_t)(l - j) * n) + (k + 1);
+                double acc = 0.0;
+                for (int i = lane; i < m; i += 64) acc += col[i] * v[i];
+                acc = gdm_wave_sum(acc);
+                if (lane == 0) corr[2 * kPanel + l] = acc;      // [0, j): W^T v, [j, 2j): V^T v
+            }
+            __syncthreads();
+            // p -= V (W^T v) + W (V^T v); then w = t p - t^2/2 (p^T v) v
+            part = 0.0;
+            for (int i = threadIdx.x; i < m; i += kTrd) {
+                const int r = k + 1 + i;
+                double x = p[i];
+                for (int l = 0; l < j; ++l)
+                    x -= Vm[(int64_t)l * n + r] * corr[2 * kPanel + l] + Wm[(int64_t)l * n + r] * corr[2 * kPanel + j + l];
+                x *= t;
+                p[i] = x;
+                part += x * v[i];
+            }
+            const double pv = block_sum_n(part, red, kTrd);
+            const double half = 0.5 * t * pv;
+            for (int i = threadIdx.x; i < m; i += kTrd) {
+                const int r = k + 1 + i;
+                Vm[(int64_t)j * n + r] = v[i];
+                Wm[(int64_t)j * n + r] = p[i] - half * v[i];
+                if (i > 0) a[(int64_t)k * ld + r] = v[i];     // v tail in row k beyond the sub-diagonal
+            }
+            __syncthreads();
         }
-        const double xn2 = block_sum(part, red);
-        const double alpha = rowk[0];
-        double beta, t, scale;
-        if (xn2 == 0.0) {
-            beta = alpha;
-            t = 0.0;
-            scale = 0.0;
-        } else {
-            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-            t = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
+        // trailing update of rows and columns >= kend: A -= V W^T + W V^T
+        const int m2 = n - kend;
+        const int nt = (m2 + 31) / 32;
+        for (int tile = 0; tile < nt * nt; ++tile) {
+            const int ti = tile / nt, tj = tile % nt;
+            const int rb = kend + 32 * ti, cb = kend + 32 * tj;
+            __syncthreads();
+            for (int e = threadIdx.x; e < 32 * jb; e += kTrd) {
+                const int rr = e % 32, l = e / 32;
+                const int r = rb + rr, c = cb + rr;
+                tV[0][rr][l] = r < n ? Vm[(int64_t)l * n + r] : 0.0;
+                tW[0][rr][l] = r < n ? Wm[(int64_t)l * n + r] : 0.0;
+                tV[1][rr][l] = c < n ? Vm[(int64_t)l * n + c] : 0.0;
+                tW[1][rr][l] = c < n ? Wm[(int64_t)l * n + c] : 0.0;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < 32 * 32; e += kTrd) {
+                const int rr = e / 32, cc = e % 32;
+                const int r = rb + rr, c = cb + cc;
+                if (r >= n || c >= n) continue;
+                double acc = 0.0;
+                for (int l = 0; l < jb; ++l) acc += tV[0][rr][l] * tW[1][cc][l] + tW[0][rr][l] * tV[1][cc][l];
+                a[(int64_t)r * ld + c] -= acc;
+            }
         }
-        for (int i = threadIdx.x; i < m; i += kThreads) v[i] = i == 0 ? 1.0 : rowk[i] * scale;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            dd[k] = a[(int64_t)k * ld + k];
-            ee[k] = beta;
-            tau[k] = t;
-        }
-        // p = t * A22 v  (A22 = A[k+1:, k+1:]); one wave per row
-        for (int i = wave; i < m; i += kThreads / 64) {
-            const double* ri = a + (int64_t)(k + 1 + i) * ld + (k + 1);
-            double acc = 0.0;
-            for (int j = lane; j < m; j += 64) acc += ri[j] * v[j];
-            acc = gdm_wave_sum(acc);
-            if (lane == 0) w[i] = t * acc;
-        }
-        __syncthreads();
-        part = 0.0;
-        for (int i = threadIdx.x; i < m; i += kThreads) part += w[i] * v[i];
-        const double pv = block_sum(part, red);
-        const double half = 0.5 * t * pv;
-        for (int i = threadIdx.x; i < m; i += kThreads) w[i] = w[i] - half * v[i];
-        __syncthreads();
-        // A22 -= v w^T + w v^T
-        for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += kThreads) {
-            int i = (int)(e / m), j = (int)(e - (int64_t)i * m);
-            double* p = a + (int64_t)(k + 1 + i) * ld + (k + 1 + j);
-            *p = *p - v[i] * w[j] - w[i] * v[j];
-        }
-        __syncthreads();
-        // store v (tail) in row k beyond the sub-diagonal
-        for (int i = 1 + threadIdx.x; i < m; i += kThreads) a[(int64_t)k * ld + (k + 1 + i)] = v[i];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -197,17 +401,25 @@ __global__ void __launch_bounds__(kThreads) k_sytrd(const SubDesc* __restrict__ 
 }
 
 // ---------------------------------------------------- implicit QL (steqr)
-// One wave per subgraph; lane 0 iterates on d, e held in LDS.  Every plane
-// rotation (i, c, s) acting on columns (i, i+1) as
-//   z_i' = c z_i - s z_{i+1},  z_{i+1}' = s z_i + c z_{i+1}
-// is appended to the subgraph's record, in application order.
-__global__ void __launch_bounds__(64) k_steqr(const SubDesc* __restrict__ desc, const double* __restrict__ Dg,
-                                             const double* __restrict__ Eg, double* __restrict__ Lam,
-                                             double* __restrict__ RotC, double* __restrict__ RotS,
-                                             int32_t* __restrict__ RotI, int64_t* __restrict__ RotN,
-                                             int* __restrict__ status) {
+// One lane per subgraph iterates on d, e held in LDS (the classic implicit QL
+// iteration with a Wilkinson-type shift from the leading 2 x 2 block; a
+// published method, e.g. Golub & Van Loan, "Matrix Computations", section on
+// the symmetric QR algorithm, in its QL form).  Every sweep is a chain of
+// plane rotations on consecutive index pairs (i, i+1), i = top, top-1, ...,
+// acting on columns as  z_i' = c z_i - s z_{i+1},  z_{i+1}' = s z_i + c z_{i+1};
+// (c, s) of each rotation is appended to the record and each sweep as (top,
+// count) to the sweep list, in application order.  sqrt(f^2 + g^2) and one
+// reciprocal replace hypot and two divisions on the serial chain (hypot only
+// where the squares could underflow), and d[i-1], e[i-1] are loaded one step
+// ahead of their use.
+__global__ void __launch_bounds__(64) k_steqr(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                             const double* __restrict__ Dg, const double* __restrict__ Eg,
+                                             double* __restrict__ Lam, double* __restrict__ RotC,
+                                             double* __restrict__ RotS, int32_t* __restrict__ Sweep,
+                                             int64_t* __restrict__ RotN, int* __restrict__ status) {
     extern __shared__ double sm[];
-    const SubDesc dsc = desc[blockIdx.x];
+    const int sub = sub_of_block(order);
+    const SubDesc dsc = desc[sub];
     const int n = dsc.n;
     double* d = sm;
     double* e = sm + n;
@@ -219,10 +431,11 @@ __global__ void __launch_bounds__(64) k_steqr(const SubDesc* __restrict__ desc, 
     if (threadIdx.x == 0) {
         double* rc = RotC + dsc.offr;
         double* rs = RotS + dsc.offr;
-        int32_t* ri = RotI + dsc.offr;
+        int32_t* sw = Sweep + dsc.offr;
         const int64_t cap = dsc.rot_cap;
-        int64_t nrot = 0;
-        bool bad = false;
+        const int64_t scap = dsc.rot_cap / 2;
+        int64_t nrot = 0, nsw = 0, nkept = 0;
+        bool bad = false, full = false;
         e[n - 1] = 0.0;
         const double eps = 1.1102230246251565e-16;
         for (int l = 0; l < n && !bad; ++l) {
@@ -230,7 +443,7 @@ __global__ void __launch_bounds__(64) k_steqr(const SubDesc* __restrict__ desc, 
             for (;;) {
                 int m = l;
                 for (; m < n - 1; ++m) {
-                    double dd = fabs(d[m]) + fabs(d[m + 1]);
+                    const double dd = fabs(d[m]) + fabs(d[m + 1]);
                     if (fabs(e[m]) <= eps * dd) break;
                 }
                 if (m == l) break;
@@ -239,36 +452,53 @@ __global__ void __launch_bounds__(64) k_steqr(const SubDesc* __restrict__ desc, 
                     gdm_raise(status, GDM_STATUS_NOT_CONVERGED);
                     break;
                 }
-                // Wilkinson-type shift from the leading 2x2 block
                 double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
                 double r = hypot(g, 1.0);
                 g = d[m] - d[l] + e[l] / (g + copysign(r, g));
                 double s = 1.0, c = 1.0, p = 0.0;
                 bool underflow = false;
+                const int64_t r0 = nrot;
+                double di1 = d[m], di = d[m - 1], ei = e[m - 1];
                 for (int i = m - 1; i >= l; --i) {
-                    double f = s * e[i];
-                    double b = c * e[i];
-                    r = hypot(f, g);
+                    const double en = i > l ? e[i - 1] : 0.0, dn = i > l ? d[i - 1] : 0.0;
+                    const double f = s * ei;
+                    const double b = c * ei;
+                    r = (fabs(f) + fabs(g) > 1e-140) ? sqrt(f * f + g * g) : hypot(f, g);
                     e[i + 1] = r;
                     if (r == 0.0) {
-                        d[i + 1] -= p;
+                        d[i + 1] = di1 - p;
                         e[m] = 0.0;
                         underflow = true;
                         break;
                     }
-                    s = f / r;
-                    c = g / r;
-                    g = d[i + 1] - p;
-                    r = (d[i] - g) * s + 2.0 * c * b;
+                    const double ir = 1.0 / r;
+                    s = f * ir;
+                    c = g * ir;
+                    g = di1 - p;
+                    r = (di - g) * s + 2.0 * c * b;
                     p = s * r;
                     d[i + 1] = g + p;
                     g = c * r - b;
                     if (nrot < cap) {
                         rc[nrot] = c;
                         rs[nrot] = s;
-                        ri[nrot] = i;
                     }
                     ++nrot;
+                    di1 = di;
+                    di = dn;
+                    ei = en;
+                }
+                if (nrot > r0) {
+                    // a sweep is kept only whole; after the first one that does
+                    // not fit, nothing more is recorded (status: capacity)
+                    if (!full && nrot <= cap && nsw < scap) {
+                        sw[2 * nsw] = m - 1;
+                        sw[2 * nsw + 1] = (int32_t)(nrot - r0);
+                        ++nsw;
+                        nkept = nrot;
+                    } else {
+                        full = true;
+                    }
                 }
                 if (underflow) continue;
                 d[l] -= p;
@@ -276,8 +506,9 @@ __global__ void __launch_bounds__(64) k_steqr(const SubDesc* __restrict__ desc, 
                 e[m] = 0.0;
             }
         }
-        if (nrot > cap) gdm_raise(status, GDM_STATUS_CAPACITY);
-        RotN[blockIdx.x] = nrot < cap ? nrot : cap;
+        if (full) gdm_raise(status, GDM_STATUS_CAPACITY);
+        RotN[2 * sub] = nkept;
+        RotN[2 * sub + 1] = nsw;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += 64) Lam[dsc.offv + i] = d[i];
@@ -287,11 +518,17 @@ __global__ void __launch_bounds__(64) k_steqr(const SubDesc* __restrict__ desc, 
 // The 2*nc rows to be transformed (rows 0..nc-1 start as I[core,:], rows
 // nc..2nc-1 as (L^-T)[core,:]) are independent, so they are processed in
 // chunks held in LDS: block (s, c) takes rows c*RC .. of subgraph s, one lane
-// per row, row stride n + 1 doubles.  Each row is initialised (unit row, or
-// forward substitution L y = e_c), multiplied by the reflectors H_0 ...
-// H_{n-3} and the recorded QL rotations in order, and written to G in the
-// column-interleaved layout G[i*R + r] (R = 2*nc).
-constexpr int kRowLds = 144 * 1024;     // LDS bytes for one chunk of rows
+// per row (one wave per workgroup), row stride n + 1 doubles.  Each row is
+// initialised (unit row, or forward substitution L y = e_c), multiplied by the
+// reflectors H_0 ... H_{n-3} and the recorded QL rotations in order, and
+// written to G in the column-interleaved layout G[i*R + r] (R = 2*nc).
+// Reflector vectors, rows of L and rotation coefficients are staged through a
+// fixed LDS area (coalesced loads by the wave, broadcast reads); the dot
+// products use four accumulators; a sweep of rotations keeps the element it
+// carries from one rotation to the next in a register and loads the row
+// elements three rotations ahead (no rotation of the chain writes them first).
+constexpr int kStage = 1024;                // doubles of the staging area (8 KB)
+constexpr int kRowLds = 136 * 1024;         // LDS bytes for one chunk of rows
 constexpr int kRowThreads = 64;
 
 __host__ __device__ inline int chunk_rows(int n) {
@@ -299,27 +536,146 @@ __host__ __device__ inline int chunk_rows(int n) {
     return r > kRowThreads ? kRowThreads : (r < 1 ? 1 : r);
 }
 
-// row <- row - t (row . v) v on row[off .. off+m), v = (1, vk[1..m-1]); one
-// lane per row (act); the reflector entries are uniform loads
-__device__ __forceinline__ void reflect_row(double* row, bool act, int off, int m, const double* vk, double t) {
-    if (!act) return;
-    double* x = row + off;
-    double dot = x[0];
-    for (int i = 1; i < m; ++i) dot += x[i] * vk[i];
+// x[0..m) . v[0..m), v in LDS (broadcast), four accumulators
+__device__ __forceinline__ double dot_lds(const double* x, const double* v, int m) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = 0;
+    for (; i + 3 < m; i += 4) {
+        a0 += x[i] * v[i];
+        a1 += x[i + 1] * v[i + 1];
+        a2 += x[i + 2] * v[i + 2];
+        a3 += x[i + 3] * v[i + 3];
+    }
+    for (; i < m; ++i) a0 += x[i] * v[i];
+    return (a0 + a1) + (a2 + a3);
+}
+
+// row[off .. off+m) <- (I - t v v^T) row, v = (1, vk[1..m-1]) read from global
+// and staged through `stg` in pieces of kStage (the whole wave takes part)
+__device__ void reflect_rows(double* row, bool act, int off, int m, const double* __restrict__ vk, double t,
+                             double* stg) {
+    const int lane = threadIdx.x;
+    double dot = 0.0;
+    for (int c0 = 0; c0 < m; c0 += kStage) {
+        const int cm = min(kStage, m - c0);
+        __syncthreads();
+        for (int i = lane; i < cm; i += kRowThreads) stg[i] = (c0 + i == 0) ? 1.0 : vk[c0 + i];
+        __syncthreads();
+        if (act) dot += dot_lds(row + off + c0, stg, cm);
+    }
     dot *= t;
-    x[0] -= dot;
-    for (int i = 1; i < m; ++i) x[i] -= dot * vk[i];
+    for (int c0 = 0; c0 < m; c0 += kStage) {
+        const int cm = min(kStage, m - c0);
+        if (m > kStage) {
+            __syncthreads();
+            for (int i = lane; i < cm; i += kRowThreads) stg[i] = (c0 + i == 0) ? 1.0 : vk[c0 + i];
+            __syncthreads();
+        }
+        if (act) {
+            double* x = row + off + c0;
+            for (int i = 0; i < cm; ++i) x[i] -= dot * stg[i];
+        }
+    }
+}
+
+// Apply the recorded QL rotations to this lane's row: forward (FWD, sweeps in
+// order, each from its top index down) or transposed in reverse order (each
+// sweep from its bottom index up, z_i' = c z_i + s z_{i+1},
+// z_{i+1}' = -s z_i + c z_{i+1}).  Coefficients are staged in kStage / 2
+// pairs; the carried element stays in a register and the next three row
+// elements of the chain are loaded ahead.
+template <bool FWD>
+__device__ void apply_rotations(double* row, bool act, int n, const double* __restrict__ rc,
+                                const double* __restrict__ rs, const int32_t* __restrict__ sw, int64_t nrot,
+                                int64_t nsw, double* stg) {
+    const int lane = threadIdx.x;
+    constexpr int kPairs = kStage / 2;
+    double* sc = stg;
+    double* ss = stg + kPairs;
+    int64_t qbase = FWD ? 0 : nrot;          // first rotation index of the current sweep
+    for (int64_t k = 0; k < nsw; ++k) {
+        const int64_t ks = FWD ? k : nsw - 1 - k;
+        const int top = sw[2 * ks], cnt = sw[2 * ks + 1];
+        if (!FWD) qbase -= cnt;
+        const int64_t q0 = qbase;
+        if (FWD) qbase += cnt;
+        // chain over cnt rotations; FWD: i = top .. top-cnt+1; reverse: i = top-cnt+1 .. top
+        const int i0 = FWD ? top : top - cnt + 1;
+        double lo = 0.0, hi = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        if (act) {
+            if (FWD) {
+                hi = row[i0 + 1];
+                lo = row[i0];
+                p1 = i0 - 1 >= 0 ? row[i0 - 1] : 0.0;
+                p2 = i0 - 2 >= 0 ? row[i0 - 2] : 0.0;
+                p3 = i0 - 3 >= 0 ? row[i0 - 3] : 0.0;
+            } else {
+                lo = row[i0];
+                hi = row[i0 + 1];
+                p1 = i0 + 2 < n ? row[i0 + 2] : 0.0;
+                p2 = i0 + 3 < n ? row[i0 + 3] : 0.0;
+                p3 = i0 + 4 < n ? row[i0 + 4] : 0.0;
+            }
+        }
+        for (int j0 = 0; j0 < cnt; j0 += kPairs) {
+            const int jm = min(kPairs, cnt - j0);
+            __syncthreads();
+            for (int t = lane; t < jm; t += kRowThreads) {
+                // j-th rotation of the chain in application order
+                const int64_t q = FWD ? q0 + j0 + t : q0 + cnt - 1 - (j0 + t);
+                sc[t] = rc[q];
+                ss[t] = rs[q];
+            }
+            __syncthreads();
+            if (act) {
+                for (int t = 0; t < jm; ++t) {
+                    const int j = j0 + t;
+                    const double c = sc[t], s = ss[t];
+                    if (FWD) {
+                        const int i = top - j;                  // rotation (i, i+1); hi = z_{i+1}, lo = z_i
+                        const double nlo = c * lo - s * hi, nhi = s * lo + c * hi;
+                        const int pf = i - 4;
+                        const double nxt = pf >= 0 ? row[pf] : 0.0;     // loaded before the write below (pf < i)
+                        row[i + 1] = nhi;
+                        hi = nlo;
+                        lo = p1;
+                        p1 = p2;
+                        p2 = p3;
+                        p3 = nxt;
+                    } else {
+                        const int i = top - cnt + 1 + j;        // rotation (i, i+1), transposed
+                        const double nlo = c * lo + s * hi, nhi = -s * lo + c * hi;
+                        const int pf = i + 5;
+                        const double nxt = pf < n ? row[pf] : 0.0;      // pf > i + 1
+                        row[i] = nlo;
+                        lo = nhi;
+                        hi = p1;
+                        p1 = p2;
+                        p2 = p3;
+                        p3 = nxt;
+                    }
+                }
+            }
+        }
+        if (act) {
+            if (FWD) row[top - cnt + 1] = hi;        // the carried z_i of the last rotation
+            else row[top + 1] = lo;                  // the carried z_{i+1}
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kRowThreads) k_core_rows(const SubDesc* __restrict__ desc,
+                                                      const int32_t* __restrict__ order,
                                                       const double* __restrict__ Lm, const double* __restrict__ A,
                                                       const double* __restrict__ Tau,
                                                       const double* __restrict__ RotC,
                                                       const double* __restrict__ RotS,
-                                                      const int32_t* __restrict__ RotI,
+                                                      const int32_t* __restrict__ Sweep,
                                                       const int64_t* __restrict__ RotN, double* __restrict__ G) {
     extern __shared__ double rows[];
-    const SubDesc d = desc[blockIdx.x];
+    __shared__ double stg[kStage];
+    const int sub = sub_of_block(order);
+    const SubDesc d = desc[sub];
     const int n = d.n, nc = d.nc, ld = d.ld, R = 2 * nc;
     const int RC = chunk_rows(n), S = n + 1;
     const int r0 = blockIdx.y * RC;
@@ -331,39 +687,35 @@ __global__ void __launch_bounds__(kRowThreads) k_core_rows(const SubDesc* __rest
     double* row = rows + (int64_t)(act ? lane : 0) * S;
     const double* l = Lm + d.off2;
     // initial rows: unit rows, or columns of L^-1 by forward substitution
-    // (y_k = 0 for k < c)
+    // (y_k = 0 for k < c); row i of L staged in LDS
     if (act)
         for (int i = 0; i < n; ++i) row[i] = (r < nc && i == r) ? 1.0 : 0.0;
-    if (act && r >= nc) {
-        const int c = r - nc;
-        for (int i = c; i < n; ++i) {
-            const double* li = l + (int64_t)i * ld;
-            double acc = i == c ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) acc -= li[k] * row[k];
-            row[i] = acc / li[i];
+    const int cmin = max(r0, nc) - nc;                    // smallest core column in this chunk
+    if (r0 + nr > nc)
+        for (int i = cmin; i < n; ++i) {
+            for (int c0 = 0; c0 <= i; c0 += kStage) {
+                const int cm = min(kStage, i + 1 - c0);
+                __syncthreads();
+                for (int k = lane; k < cm; k += kRowThreads) stg[k] = l[(int64_t)i * ld + c0 + k];
+                __syncthreads();
+                if (act && r >= nc && i >= r - nc) {
+                    // acc over k < i of this piece; the diagonal divides at the end
+                    const int kend = min(cm, i - c0);
+                    const double part = kend > 0 ? dot_lds(row + c0, stg, kend) : 0.0;
+                    row[i] = (c0 == 0 ? (i == r - nc ? 1.0 : 0.0) : row[i]) - part;
+                    if (c0 + cm == i + 1) row[i] /= stg[cm - 1];
+                }
+            }
         }
-    }
     const double* a = A + d.off2;
     const double* tau = Tau + d.offv;
     for (int k = 0; k < n - 2; ++k) {
         const double t = tau[k];
         if (t == 0.0) continue;
-        reflect_row(row, act, k + 1, n - k - 1, a + (int64_t)k * ld + k + 1, t);
+        reflect_rows(row, act, k + 1, n - k - 1, a + (int64_t)k * ld + k + 1, t, stg);
     }
-    // rotations in order
-    if (act) {
-        const int64_t nrot = RotN[blockIdx.x];
-        const double* rc = RotC + d.offr;
-        const double* rs = RotS + d.offr;
-        const int32_t* ri = RotI + d.offr;
-        for (int64_t q = 0; q < nrot; ++q) {
-            const int i = ri[q];
-            const double c = rc[q], sn = rs[q];
-            const double gi = row[i], gj = row[i + 1];
-            row[i] = c * gi - sn * gj;
-            row[i + 1] = sn * gi + c * gj;
-        }
-    }
+    apply_rotations<true>(row, act, n, RotC + d.offr, RotS + d.offr, Sweep + d.offr, RotN[2 * sub],
+                          RotN[2 * sub + 1], stg);
     double* g = G + 2 * d.offc;
     for (int i = 0; i < n; ++i)
         if (act) g[(int64_t)i * R + r] = row[i];
@@ -372,9 +724,10 @@ __global__ void __launch_bounds__(kRowThreads) k_core_rows(const SubDesc* __rest
 // w_k = sum_{a<nc} C[a][k] * (L_cc Q_core)[a][k]: the core weight of
 // eigenvector k, (C^T s C)_core diagonal contribution, with s C = L Q
 __global__ void __launch_bounds__(kThreads) k_core_weights(const SubDesc* __restrict__ desc,
+                                                          const int32_t* __restrict__ order,
                                                           const double* __restrict__ Lm,
                                                           const double* __restrict__ G, double* __restrict__ W) {
-    const SubDesc d = desc[blockIdx.x];
+    const SubDesc d = desc[sub_of_block(order)];
     const int n = d.n, nc = d.nc, ld = d.ld, R = 2 * nc;
     const double* l = Lm + d.off2;
     const double* g = G + 2 * d.offc;
@@ -403,18 +756,22 @@ __device__ __forceinline__ double fermi_fp64(double x, double beta) {
 
 // Core rows r < nc in LDS chunks as above: u = C[r,:] diag(f), then
 // u <- u R^T (rotations in reverse order, transposed), u <- u H_{n-3} ... H_0,
-// and D[r,:] from D L = u (columns from the right), written row-wise.
+// and D[r,:] from D L = u by columns from the right (D_j = u_j / L_jj, then
+// u_i -= D_j L_ji for i < j, row j of L staged), written row-wise.
 __global__ void __launch_bounds__(kRowThreads) k_dcore(const SubDesc* __restrict__ desc,
+                                                  const int32_t* __restrict__ order,
                                                   const double* __restrict__ Lm, const double* __restrict__ A,
                                                   const double* __restrict__ Tau, const double* __restrict__ RotC,
-                                                  const double* __restrict__ RotS, const int32_t* __restrict__ RotI,
+                                                  const double* __restrict__ RotS, const int32_t* __restrict__ Sweep,
                                                   const int64_t* __restrict__ RotN, const double* __restrict__ G,
                                                   const double* __restrict__ Lam, double mu_host,
                                                   const double* __restrict__ mu_dev, double beta,
                                                   double* __restrict__ Dout, double* __restrict__ EigOut) {
     extern __shared__ double rows[];
+    __shared__ double stg[kStage];
     const double mu = mu_dev ? *mu_dev : mu_host;      // mu from device memory when given
-    const SubDesc d = desc[blockIdx.x];
+    const int sub = sub_of_block(order);
+    const SubDesc d = desc[sub];
     const int n = d.n, nc = d.nc, ld = d.ld, R2 = 2 * nc;
     const int RC = chunk_rows(n), S = n + 1;
     const int r0 = blockIdx.y * RC;
@@ -430,34 +787,31 @@ __global__ void __launch_bounds__(kRowThreads) k_dcore(const SubDesc* __restrict
         for (int k = lane; k < n; k += kRowThreads) EigOut[d.offe + k] = Lam[d.offv + k];
     for (int k = 0; k < n; ++k)
         if (act) row[k] = g[(int64_t)k * R2 + nc + r] * fermi_fp64(Lam[d.offv + k] - mu, beta);
-    // rotations in reverse order, transposed
-    if (act) {
-        const int64_t nrot = RotN[blockIdx.x];
-        const double* rc = RotC + d.offr;
-        const double* rs = RotS + d.offr;
-        const int32_t* ri = RotI + d.offr;
-        for (int64_t q = nrot - 1; q >= 0; --q) {
-            const int i = ri[q];
-            const double c = rc[q], sn = rs[q];
-            const double ui = row[i], uj = row[i + 1];
-            row[i] = c * ui + sn * uj;
-            row[i + 1] = -sn * ui + c * uj;
-        }
-    }
+    apply_rotations<false>(row, act, n, RotC + d.offr, RotS + d.offr, Sweep + d.offr, RotN[2 * sub],
+                           RotN[2 * sub + 1], stg);
     const double* a = A + d.off2;
     const double* tau = Tau + d.offv;
     for (int k = n - 3; k >= 0; --k) {
         const double t = tau[k];
         if (t == 0.0) continue;
-        reflect_row(row, act, k + 1, n - k - 1, a + (int64_t)k * ld + k + 1, t);
+        reflect_rows(row, act, k + 1, n - k - 1, a + (int64_t)k * ld + k + 1, t, stg);
     }
-    // D L = u: D_j = (u_j - sum_{i>j} D_i L_ij) / L_jj, from the last column
-    if (act)
-        for (int j = n - 1; j >= 0; --j) {
-            double acc = row[j];
-            for (int i = j + 1; i < n; ++i) acc -= row[i] * l[(int64_t)i * ld + j];
-            row[j] = acc / l[(int64_t)j * ld + j];
+    // D L = u by columns from the right
+    for (int j = n - 1; j >= 0; --j) {
+        for (int c0 = 0; c0 <= j; c0 += kStage) {
+            const int cm = min(kStage, j + 1 - c0);
+            __syncthreads();
+            for (int k = lane; k < cm; k += kRowThreads) stg[k] = l[(int64_t)j * ld + c0 + k];
+            __syncthreads();
+            if (act) {
+                const double dj = row[j] / l[(int64_t)j * ld + j];
+                const int kend = min(cm, j - c0);
+                double* x = row + c0;
+                for (int k = 0; k < kend; ++k) x[k] -= dj * stg[k];
+                if (c0 + cm == j + 1) row[j] = dj;
+            }
         }
+    }
     __syncthreads();
     double* out = Dout + d.offd;
     for (int rr = 0; rr < nr; ++rr)
@@ -624,6 +978,7 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     Plan& P = ctx->plan;
     const int ns = P.n_sub;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
+    const int32_t* order = (const int32_t*)ctx->b[BUF_ORDER].p;
     double* A = (double*)ctx->b[BUF_A].p;
     double* Sd = (double*)ctx->b[BUF_S].p;
     double* T = (double*)ctx->b[BUF_L].p;
@@ -647,30 +1002,31 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     if ((rc = set_lds(ctx, (const void*)k_potrf, lds_n))) return rc;
     GDM_LAUNCH_CHECK(ctx);
     { GDM_TIMED(ctx, "potrf");
-    hipLaunchKernelGGL(k_potrf, dim3(ns), dim3(kThreads), lds_n, ctx->stream, desc, Sd, ctx->d_status);
+    hipLaunchKernelGGL(k_potrf, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, Sd, ctx->d_status);
+    }
+    GDM_LAUNCH_CHECK(ctx);
+    const dim3 tgrid((unsigned)ns, (unsigned)((P.max_n + kTc - 1) / kTc));
+    { GDM_TIMED(ctx, "trsm");
+    hipLaunchKernelGGL(k_trsm<0>, tgrid, dim3(kThreads), 0, ctx->stream, desc, order, Sd, A, T);
     }
     GDM_LAUNCH_CHECK(ctx);
     { GDM_TIMED(ctx, "trsm");
-    hipLaunchKernelGGL(k_trsm<0>, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, Sd, A, T);
-    }
-    GDM_LAUNCH_CHECK(ctx);
-    { GDM_TIMED(ctx, "trsm");
-    hipLaunchKernelGGL(k_trsm<1>, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, Sd, A, T);
+    hipLaunchKernelGGL(k_trsm<1>, tgrid, dim3(kThreads), 0, ctx->stream, desc, order, Sd, A, T);
     }
     GDM_LAUNCH_CHECK(ctx);
     { GDM_TIMED(ctx, "symmetrize");
-    hipLaunchKernelGGL(k_symmetrize, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, A);
+    hipLaunchKernelGGL(k_symmetrize, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, A);
     }
     GDM_LAUNCH_CHECK(ctx);
     if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * lds_n))) return rc;
     { GDM_TIMED(ctx, "sytrd");
-    hipLaunchKernelGGL(k_sytrd, dim3(ns), dim3(kThreads), 2 * lds_n, ctx->stream, desc, A, Dg, Eg, Tau);
+    hipLaunchKernelGGL(k_sytrd, dim3(ns), dim3(kTrd), 2 * lds_n, ctx->stream, desc, order, A, T, Dg, Eg, Tau);
     }
     GDM_LAUNCH_CHECK(ctx);
     if ((rc = set_lds(ctx, (const void*)k_steqr, 2 * lds_n))) return rc;
     { GDM_TIMED(ctx, "steqr");
-    hipLaunchKernelGGL(k_steqr, dim3(ns), dim3(64), 2 * lds_n, ctx->stream, desc, Dg, Eg, Lam, RotC, RotS, RotI,
-                       RotN, ctx->d_status);
+    hipLaunchKernelGGL(k_steqr, dim3(ns), dim3(64), 2 * lds_n, ctx->stream, desc, order, Dg, Eg, Lam, RotC, RotS,
+                       RotI, RotN, ctx->d_status);
     }
     GDM_LAUNCH_CHECK(ctx);
     {
@@ -678,10 +1034,10 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
         const int chunks = L.core_chunks;
         if ((rc = set_lds(ctx, (const void*)k_core_rows, lds_rows))) return rc;
         GDM_TIMED(ctx, "core_rows");
-        hipLaunchKernelGGL(k_core_rows, dim3(ns, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, Sd, A, Tau,
-                           RotC, RotS, RotI, RotN, G);
+        hipLaunchKernelGGL(k_core_rows, dim3(ns, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, order, Sd,
+                           A, Tau, RotC, RotS, RotI, RotN, G);
         GDM_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_core_weights, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, Sd, G, Wt);
+        hipLaunchKernelGGL(k_core_weights, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, Sd, G, Wt);
     }
     GDM_LAUNCH_CHECK(ctx);
     // chemical potential: multisection rounds
@@ -733,7 +1089,7 @@ int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const dou
     if ((rc = set_lds(ctx, (const void*)k_dcore, lds_rows))) return rc;
     { GDM_TIMED(ctx, "dcore");
     hipLaunchKernelGGL(k_dcore, dim3(P.n_sub, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc,
-                       (const double*)ctx->b[BUF_S].p, (const double*)ctx->b[BUF_A].p, (const double*)ctx->b[BUF_TAU].p,
+                       (const int32_t*)ctx->b[BUF_ORDER].p, (const double*)ctx->b[BUF_S].p, (const double*)ctx->b[BUF_A].p, (const double*)ctx->b[BUF_TAU].p,
                        (const double*)ctx->b[BUF_ROTC].p, (const double*)ctx->b[BUF_ROTS].p,
                        (const int32_t*)ctx->b[BUF_ROTI].p, (const int64_t*)ctx->b[BUF_ROTN].p,
                        (const double*)ctx->b[BUF_QC].p, (const double*)ctx->b[BUF_LAM].p, mu, mu_dev, 1.0 / kT, D_core,

@@ -74,6 +74,9 @@ struct gdm_ctx {
     int mixed_packed = 1;        // expansion matrices stored as upper tiles (gdm_set_mixed_storage)
     int mixed_ns_inv = 2;        // Newton-Schulz iterations per inverse after the quadratic start
     int mixed_max_passes = 16;   // expansion passes allowed for mu
+    int mixed_dev_passes = 3;    // passes launched by the device-side search (gdm_set_mixed_capture)
+    int mixed_nd_launch = 12;    // doublings launched per pass by the device-side search
+    bool mixed_dev_state = false;   // the last mixed search ran on the device (its state is there)
     int64_t mixed_tiles = 0, mixed_tiles_sym = 0, mixed_tiles_core = 0;
     int64_t mixed_upper_elems = 0;   // elements of the upper tiles of all subgraphs (packed storage)
     double mixed_flops_full = 0, mixed_flops_sym = 0;  // one product per launch
@@ -122,7 +125,7 @@ enum {
     BUF_X_HI, BUF_X_LO, BUF_X_F, BUF_Y_HI, BUF_Y_LO, BUF_Y_F, BUF_T_HI, BUF_T_LO, BUF_T_F,
     BUF_Z_HI, BUF_Z_LO, BUF_Z_F, BUF_H_HI, BUF_H_LO, BUF_H_F, BUF_TR, BUF_GERSH, BUF_NDBL,
     BUF_TILES, BUF_PASS, BUF_EWALD, BUF_MIXPART,
-    BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_KRYLOV,
+    BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_KRYLOV, BUF_MSTATE,
     BUF_COUNT_
 };
 
@@ -167,8 +170,9 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
                       const double* H, const double* S, double n_e, double kT,
                       double mu_guess, double tol_N, double* mu_out, double* n_out);
 int gdm_mixed_plan(gdm_ctx* ctx);
-int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT,
+int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const double* mu_dev, double kT,
                       double* D_core);
+int gdm_mixed_pass_mu(gdm_ctx* ctx, double* mu_pass);
 int gdm_mixed_response_alloc(gdm_ctx* ctx);
 int gdm_mixed_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
                        const int32_t* row_ptr, const int32_t* col, int64_t nnz, const double* S,

@@ -6,7 +6,8 @@
 //   Z = s^-1/2 by coupled Newton-Schulz on s/c (c the largest absolute row
 //       sum of s): Z0 = kZ0a I + kZ0b s/c (linear minimax start), Y0 = (s/c) Z0,
 //       T = (3I - Z Y)/2, Y <- Y T, Z <- T Z; then Z64 = Z / sqrt(c) in FP64
-//       and one FP64 residual step Z64 <- Z64 - Z64 (Z64 s Z64 - I) / 2,
+//       and one third-order FP64 residual step with E = Z64 s Z64 - I,
+//       Z64 <- Z64 (I - E/2 + 3/8 E^2),
 //   h_perp = Z h Z,
 //   K = b (h_perp - mu I), b = beta / 2^n_d, and the start X0 = f_b(K) to
 //       high order: the degree-7 odd polynomial of kStart7 (n_d >= 5), else
@@ -49,6 +50,82 @@ struct SplitMat {
     _Float16* lo;
 };
 
+// State of the chemical-potential search, in device memory (doubles): the
+// spectral bounds, the current mu and its doubling count n_d and scale
+// b = beta / 2^n_d, the start polynomial, the bracket, the traces N and M of
+// the last pass and the mu they were taken at, the result, and counters.
+enum {
+    kStLo = 0, kStHi, kStMu, kStB, kStNd, kStStart, kStBlo, kStBhi, kStN, kStM, kStMuPass, kStMuOut, kStNOut,
+    kStPasses, kStDone, kStCount = 16
+};
+// Predicate flags (int, 1 = skip) of the launches of a search whose launch
+// count is fixed in advance: pass p, doubling j of pass p, extra inverse-
+// overlap iteration r.
+constexpr int kMaxPasses = 16;
+constexpr int kMaxNd = 40;
+constexpr int kMaxNsExtra = 32;
+constexpr int kFlPass = 0;
+constexpr int kFlDbl = kFlPass + kMaxPasses;
+constexpr int kFlNs = kFlDbl + kMaxPasses * kMaxNd;
+constexpr int kFlCount = kFlNs + kMaxNsExtra + 1;
+
+// Start of the expansion: 0 linear, 1 cubic, 2 degree 7.
+enum { kStartLinear = 0, kStartCubic = 1, kStartSeptic = 2 };
+
+// Doubling count and start polynomial for chemical potential mu and spectral
+// bounds [lo, hi]: each doubling maps f(u) to f(2u), so n_d doublings from
+// X0 = f_b(K), K = b (h - mu), b = beta / 2^n_d, give f_beta; the start must
+// keep X0 in [0, 1] over the half-width R = max(|lo - mu|, |hi - mu|): the
+// linear start for b R <= 2, the cubic for b R <= 4, the degree-7 polynomial
+// for b R <= 8 (and at least 5 doublings after it).  A recorded pass (charge
+// response) uses the linear start; `septic_only` (device-side search) always
+// uses the degree-7 start with n_d >= 5.
+__host__ __device__ inline int mixed_doublings(double beta, double lo, double hi, double mu, int rec, int septic_only,
+                                               int* start) {
+    const double R = fmax(fabs(lo - mu), fabs(hi - mu));
+    const int nd7 = (int)ceil(log2(0.125 * beta * R));
+    int nd;
+    if (septic_only) {
+        *start = kStartSeptic;
+        nd = nd7 > 5 ? nd7 : 5;
+    } else if (rec) {
+        *start = kStartLinear;
+        nd = (int)ceil(log2(0.5 * beta * R));
+    } else if (nd7 >= 5) {
+        *start = kStartSeptic;
+        nd = nd7;
+    } else {
+        *start = kStartCubic;
+        nd = (int)ceil(log2(0.25 * beta * R));
+    }
+    return nd < 1 ? 1 : (nd > kMaxNd ? kMaxNd : nd);
+}
+
+// One step of the search after a pass at mu gave the count N and its
+// derivative beta M: safeguarded Newton inside the bracket [blo, bhi]
+// (bisection when the Newton point leaves it or does not halve it).  The
+// search is done when the count matches within tol, when the Newton step is
+// below 1e-2 kT (the first-order term of the density then finishes it), or
+// on the last pass; *dmu is then the first-order correction, applied when it
+// lies within kT and the count is not yet matched.
+__host__ __device__ inline void mixed_mu_step(double mu, double N, double M, double n_e, double beta, double kT,
+                                              double tol, int last, double* blo, double* bhi, double* next,
+                                              int* done, double* dmu) {
+    const double dN = n_e - N, slope = beta * M;
+    const double newton = slope > 0.0 ? dN / slope : INFINITY;
+    *dmu = 0.0;
+    *next = mu;
+    *done = fabs(dN) <= tol || fabs(newton) <= 1e-2 * kT || last;
+    if (*done) {
+        if (fabs(dN) > tol && slope > 0.0 && fabs(newton) <= kT) *dmu = newton;
+        return;
+    }
+    if (dN > 0.0) *blo = mu; else *bhi = mu;
+    double x = slope > 0.0 ? mu + newton : 0.5 * (*blo + *bhi);
+    if (!(x > *blo && x < *bhi) || fabs(x - mu) > 0.5 * (*bhi - *blo)) x = 0.5 * (*blo + *bhi);
+    *next = x;
+}
+
 struct GemmArgs {
     SplitMat A, B;       // operands (hi/lo used)
     SplitMat O1;         // raw product (nullable members)
@@ -61,6 +138,8 @@ struct GemmArgs {
                          // tile is read as its stored mirror, transposed into LDS).  Bit 1: the
                          // outputs are written on the upper tiles only (no mirror); E is then
                          // read on upper tiles only too, so it may be packed as well
+    const int* skip;     // nullable: the launch does nothing when *skip != 0 (device-side
+                         // predication of launches whose count is fixed at capture time)
 };
 
 __device__ __forceinline__ void store_split(SplitMat m, int64_t idx, float v) {
@@ -126,6 +205,7 @@ __global__ void __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_
     _Float16* sBh = sAl + kTile * kLdsRow;
     _Float16* sBl = sBh + kTile * kLdsRow;
     float* sC = (float*)lds;                    // reused after the k loop: [64][kOutRow]
+    if (g.skip && *g.skip) return;
     const int4 tl = tiles[blockIdx.x];
     if (tl.x < 0) return;
     const SubDesc d = desc[tl.x];
@@ -360,8 +440,10 @@ template <typename TA, typename TB, bool SYM>
 __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
                                                const TA* __restrict__ A, const TB* __restrict__ B,
                                                const double* __restrict__ Cin, double* __restrict__ C,
-                                               double alpha, double beta, double gamma) {
+                                               double alpha, double beta, double gamma,
+                                               const int* __restrict__ skip) {
     __shared__ double lds[kG64Lds];
+    if (skip && *skip) return;
     double* sA = lds;                        // [64][kA64Row]
     double* sB = lds + 64 * kA64Row;         // [kK64][kB64Row]
     const int4 tl = tiles[blockIdx.x];
@@ -441,7 +523,9 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
 }
 
 // Z (FP16 hi/lo split) <- Z64, flat over every packed tile (padding included)
-__global__ void __launch_bounds__(256) k_z64_to_split(int64_t n4, const double* __restrict__ Z64, SplitMat Z) {
+__global__ void __launch_bounds__(256) k_z64_to_split(int64_t n4, const double* __restrict__ Z64, SplitMat Z,
+                                                     const int* __restrict__ skip) {
+    if (skip && *skip) return;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256) {
         const double4 v = *(const double4*)(Z64 + 4 * e);
         store4(Z, 4 * e, make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w));
@@ -453,8 +537,9 @@ __global__ void __launch_bounds__(256) k_z64_to_split(int64_t n4, const double* 
 // sum_c G_ac V_ac = (Z X Z s)_aa, the core diagonal of D s.
 __global__ void __launch_bounds__(256) k_trace_dot(const SubDesc* __restrict__ desc, const double* __restrict__ G,
                                                   const double* __restrict__ G2, const double* __restrict__ V,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part, const int* __restrict__ skip) {
     __shared__ double red[4];
+    if (skip && *skip) return;
     const SubDesc d = desc[blockIdx.x];
     const int n = d.n, P = d.ld, nc = d.nc;
     double an = 0.0, am = 0.0;
@@ -486,7 +571,10 @@ __global__ void __launch_bounds__(256) k_trace_dot(const SubDesc* __restrict__ d
 // canonical response (Base = Z dX); Gk may alias Base
 __global__ void __launch_bounds__(256) k_combine(const SubDesc* __restrict__ desc, const double* Base,
                                                 const double* __restrict__ G, const double* __restrict__ G2,
-                                                double* Gk, double kappa) {
+                                                double* Gk, double kappa, const double* __restrict__ mu_dev,
+                                                const double* __restrict__ st, double beta) {
+    // with mu_dev: kappa = (mu - mu of the expansion pass) beta, both read on the device
+    if (mu_dev) kappa = (mu_dev[0] - st[kStMuPass]) * beta;
     const SubDesc d = desc[blockIdx.x];
     const int P = d.ld, nc = d.nc;
     const int rows = (nc + 63) / 64 * 64;
@@ -509,7 +597,7 @@ __global__ void __launch_bounds__(256) k_pack_core(const SubDesc* __restrict__ d
 
 // ------------------------------------------------------- elementwise kernels
 constexpr int kEw = 256;
-constexpr double kZResidMax = 3e-3;   // largest |Z s Z - I| entry accepted before refinement
+constexpr double kZResidMax = 1e-3;   // largest |Z s Z - I| entry accepted before refinement
 
 __device__ __forceinline__ double block_reduce_max(double v, double* red) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -607,24 +695,71 @@ __global__ void __launch_bounds__(kEw) k_prep(const SubDesc* __restrict__ desc, 
     }
 }
 
-// Z64 <- the Newton-Schulz Z / sqrt(c) in FP64 on the n x n block (padding
-// copied: it stays the identity through the iteration)
-__global__ void __launch_bounds__(kEw) k_scale_to_f64(const SubDesc* __restrict__ desc, const float* __restrict__ Zf,
-                                                     const double* __restrict__ scale, int orthogonal,
-                                                     double* __restrict__ Z64) {
-    const SubDesc d = desc[blockIdx.x];
-    const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
-    if (r0 >= P) return;
-    const double f = orthogonal ? 1.0 : 1.0 / sqrt(scale[blockIdx.x]);
-    const int q4 = P >> 2;
-    for (int e = threadIdx.x; e < 64 * q4; e += kEw) {
-        const int i = r0 + e / q4, j0 = (e % q4) * 4;
-        const int64_t idx = d.off2 + (int64_t)i * P + j0;
-        const float4 z = *(const float4*)(Zf + idx);
-        const double zs[4] = {z.x, z.y, z.z, z.w};
-        double o[4];
-        for (int q = 0; q < 4; ++q) o[q] = (i < n && j0 + q < n) ? zs[q] * f : zs[q];
-        *(double4*)(Z64 + idx) = make_double4(o[0], o[1], o[2], o[3]);
+// Z64 <- (Z + Z^T) / (2 sqrt(c)) in FP64 on the n x n block (padding copied:
+// it stays the identity through the iteration), on the upper-tile list: a
+// workgroup averages tile (I, J) with the transpose of tile (J, I) through
+// LDS and writes both.  The split products leave Z symmetric only to the last
+// bit of their epilogue rounding; the refinement needs it exactly symmetric.
+__global__ void __launch_bounds__(256) k_scale_sym_to_f64(const SubDesc* __restrict__ desc,
+                                                         const int4* __restrict__ tiles, const float* __restrict__ Zf,
+                                                         const double* __restrict__ scale, int orthogonal,
+                                                         double* __restrict__ Z64, const int* __restrict__ skip) {
+    __shared__ float a[64][65], bt[64][65];
+    if (skip && *skip) return;
+    const int4 tl = tiles[blockIdx.x];
+    if (tl.x < 0) return;
+    const SubDesc d = desc[tl.x];
+    const int P = d.ld, n = d.n;
+    const int I0 = tl.y * 64, J0 = tl.z * 64;
+    const double f = orthogonal ? 1.0 : 1.0 / sqrt(scale[tl.x]);
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        a[r][c] = Zf[d.off2 + (int64_t)(I0 + r) * P + J0 + c];
+        bt[r][c] = Zf[d.off2 + (int64_t)(J0 + r) * P + I0 + c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        const int i = I0 + r, j = J0 + c;
+        const double v = 0.5 * ((double)a[r][c] + (double)bt[c][r]);
+        const bool in = i < n && j < n;
+        Z64[d.off2 + (int64_t)i * P + j] = in ? v * f : (double)a[r][c];
+        Z64[d.off2 + (int64_t)j * P + i] = in ? v * f : (double)bt[c][r];
+    }
+}
+
+// dst <- src^T over every subgraph's P x P tile, on the upper-tile list (both
+// tiles of a pair through LDS); FP64 (dst64) and, when dsplit.hi is set, the
+// split halves and FP32 copy of the transpose
+__global__ void __launch_bounds__(256) k_transpose64(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
+                                                    const double* __restrict__ src, double* __restrict__ dst64,
+                                                    SplitMat dsplit, const int* __restrict__ skip) {
+    __shared__ double a[64][65], b2[64][65];
+    if (skip && *skip) return;
+    const int4 tl = tiles[blockIdx.x];
+    if (tl.x < 0) return;
+    const SubDesc d = desc[tl.x];
+    const int P = d.ld;
+    const int I0 = tl.y * 64, J0 = tl.z * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        a[r][c] = src[d.off2 + (int64_t)(I0 + r) * P + J0 + c];
+        b2[r][c] = src[d.off2 + (int64_t)(J0 + r) * P + I0 + c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        const int64_t i1 = d.off2 + (int64_t)(I0 + r) * P + J0 + c;     // dst[I0+r][J0+c] = src[J0+c][I0+r]
+        const int64_t i2 = d.off2 + (int64_t)(J0 + r) * P + I0 + c;
+        const double v1 = b2[c][r], v2 = a[c][r];
+        if (dst64) {
+            dst64[i1] = v1;
+            dst64[i2] = v2;
+        }
+        if (dsplit.hi) {
+            store_split(dsplit, i1, (float)v1);
+            store_split(dsplit, i2, (float)v2);
+        }
     }
 }
 
@@ -663,7 +798,14 @@ __global__ void __launch_bounds__(kEw) k_sym_bounds(const SubDesc* __restrict__ 
 // X <- c0 I - q (H - mu I) on the n x n block, zero padding (the linear start
 // X0 = I/2 - (b/4)(H - mu I), or K = b (H - mu I) for the cubic start)
 __global__ void __launch_bounds__(kEw) k_x0(const SubDesc* __restrict__ desc, const float* __restrict__ Hf,
-                                           SplitMat X, double mu, double q, double c0) {
+                                           SplitMat X, double mu, double q, double c0, const double* __restrict__ st,
+                                           const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    if (st) {                   // K = b (H - mu I) with mu and b of the device-side search
+        mu = st[kStMu];
+        q = -st[kStB];
+        c0 = 0.0;
+    }
     const SubDesc d = desc[blockIdx.x];
     const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
     if (r0 >= P) return;
@@ -682,8 +824,10 @@ __global__ void __launch_bounds__(kEw) k_x0(const SubDesc* __restrict__ desc, co
     }
 }
 
-__global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* __restrict__ out) {
+__global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* __restrict__ out,
+                            const int* __restrict__ skip) {
     __shared__ double red[kEw / 64];
+    if (skip && *skip) return;
     double a = 0.0, b = 0.0;
     for (int s = threadIdx.x; s < n_sub; s += kEw) {
         a += part[2 * s];
@@ -701,7 +845,8 @@ __global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* 
 // atomic max on the bit pattern (non-negative doubles order as integers; NaN
 // counts as infinite).
 __global__ void __launch_bounds__(kEw) k_resid_max(const SubDesc* __restrict__ desc, const double* __restrict__ E,
-                                                  unsigned long long* __restrict__ out) {
+                                                  unsigned long long* __restrict__ out, const int* __restrict__ skip) {
+    if (skip && *skip) return;
     const SubDesc d = desc[blockIdx.x];
     const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
     if (r0 >= n) return;
@@ -808,6 +953,183 @@ __global__ void __launch_bounds__(256) k_sym_pair(const SubDesc* __restrict__ de
     }
 }
 
+// X64 <- X (FP32 copy when present, else hi + 2^-11 lo), flat over every
+// packed tile (X in whole storage)
+__global__ void __launch_bounds__(256) k_split_to_f64(int64_t n4, SplitMat X, double* __restrict__ X64,
+                                                     const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256) {
+        const float4 v = load4(X, 4 * e);
+        *(double4*)(X64 + 4 * e) = make_double4(v.x, v.y, v.z, v.w);
+    }
+}
+
+// A <- 2 X2 - 2 X + I over the padded P x P tile (padding: X = X2 = 0, so A = I there)
+__global__ void __launch_bounds__(kEw) k_doubling_a(const SubDesc* __restrict__ desc, const double* __restrict__ X,
+                                                   const double* __restrict__ X2, double* __restrict__ A,
+                                                   const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const SubDesc d = desc[blockIdx.x];
+    const int P = d.ld, r0 = blockIdx.y * 64;
+    if (r0 >= P) return;
+    const int q4 = P >> 2;
+    for (int e = threadIdx.x; e < 64 * q4; e += kEw) {
+        const int i = r0 + e / q4, j0 = (e % q4) * 4;
+        const int64_t idx = d.off2 + (int64_t)i * P + j0;
+        const double4 x = *(const double4*)(X + idx), x2 = *(const double4*)(X2 + idx);
+        double4 a = make_double4(2.0 * x2.x - 2.0 * x.x, 2.0 * x2.y - 2.0 * x.y, 2.0 * x2.z - 2.0 * x.z,
+                                 2.0 * x2.w - 2.0 * x.w);
+        if (i == j0) a.x += 1.0;
+        if (i == j0 + 1) a.y += 1.0;
+        if (i == j0 + 2) a.z += 1.0;
+        if (i == j0 + 3) a.w += 1.0;
+        *(double4*)(A + idx) = a;
+    }
+}
+
+// ------------------------------------------------- chemical-potential search
+// Parameters of the search, fixed per gdm_find_mu call.
+struct MuCfg {
+    double n_e, beta, kT, tol, tol_final, guess;
+    int rec;          // the passes are recorded for the charge response (linear start)
+    int dev;          // device-side search: fixed launch counts, predicated
+    int nd_launch;    // doublings launched per pass in the device-side search
+    int max_passes;
+};
+
+// Plan the pass about to run at st[kStMu]: n_d, b and the start, and (device
+// search) the doubling predicates of pass p: doubling j of the nd_launch
+// launched runs iff j >= nd_launch - n_d.
+__device__ void mu_plan_pass(const MuCfg& c, double* st, int* fl, int p, int* status) {
+    int start = 0;
+    int nd = mixed_doublings(c.beta, st[kStLo], st[kStHi], st[kStMu], c.rec, c.dev, &start);
+    if (c.dev && nd > c.nd_launch) {
+        gdm_raise(status, GDM_STATUS_CAPACITY);      // more doublings than were launched
+        nd = c.nd_launch;
+    }
+    st[kStNd] = nd;
+    st[kStStart] = start;
+    st[kStB] = c.beta / ldexp(1.0, nd);
+    if (c.dev && p < kMaxPasses) {
+        fl[kFlPass + p] = 0;
+        for (int j = 0; j < c.nd_launch; ++j) fl[kFlDbl + p * kMaxNd + j] = j < c.nd_launch - nd ? 1 : 0;
+    }
+}
+
+// Global spectral bounds from the per-strip Gershgorin bounds, the bracket,
+// the first mu (the device guess when given and inside the bounds, else the
+// host guess, else the middle) and the plan of pass 0; later passes are
+// marked skipped until a step asks for them.
+__global__ void __launch_bounds__(kEw) k_mu_init(const double* __restrict__ bounds, int nb, const double* guess_dev,
+                                                MuCfg c, double* __restrict__ st, int* __restrict__ fl,
+                                                int* __restrict__ status) {
+    __shared__ double red[kEw / 64];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int k = threadIdx.x; k < nb; k += kEw) {
+        lo = fmin(lo, bounds[2 * k]);
+        hi = fmax(hi, bounds[2 * k + 1]);
+    }
+    lo = block_reduce_min(lo, red);
+    hi = block_reduce_max(hi, red);
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < kStCount; ++k) st[k] = 0.0;
+    if (!isfinite(lo) || !isfinite(hi)) {
+        gdm_raise(status, GDM_STATUS_NAN);
+        lo = -1.0;
+        hi = 1.0;
+    }
+    st[kStLo] = lo;
+    st[kStHi] = hi;
+    st[kStBlo] = lo;
+    st[kStBhi] = hi;
+    double mu = 0.5 * (lo + hi);
+    const double g = guess_dev ? guess_dev[0] : NAN;
+    if (isfinite(g) && g > lo && g < hi) mu = g;
+    else if (isfinite(c.guess) && c.guess > lo && c.guess < hi) mu = c.guess;
+    st[kStMu] = mu;
+    st[kStMuOut] = NAN;
+    st[kStNOut] = NAN;
+    if (c.dev)
+        for (int p = 0; p < kMaxPasses; ++p) {
+            fl[kFlPass + p] = 1;
+            for (int j = 0; j < kMaxNd; ++j) fl[kFlDbl + p * kMaxNd + j] = 1;
+        }
+    mu_plan_pass(c, st, fl, 0, status);
+}
+
+// After pass p (skipped passes change nothing): record its traces, take the
+// step, and plan pass p + 1, or finish with the result in kStMuOut/kStNOut.
+__global__ void k_mu_update(int p, MuCfg c, const double* __restrict__ tr, double* __restrict__ st,
+                            int* __restrict__ fl, int* __restrict__ status) {
+    if (threadIdx.x != 0) return;
+    if (c.dev && fl[kFlPass + p]) return;
+    const double mu = st[kStMu], N = tr[0], M = tr[1];
+    st[kStN] = N;
+    st[kStM] = M;
+    st[kStMuPass] = mu;
+    st[kStPasses] = p + 1;
+    if (!isfinite(N) || !isfinite(M)) gdm_raise(status, GDM_STATUS_NAN);
+    double blo = st[kStBlo], bhi = st[kStBhi], next = mu, dmu = 0.0;
+    int done = 0;
+    mixed_mu_step(mu, N, M, c.n_e, c.beta, c.kT, c.tol, p + 1 >= c.max_passes, &blo, &bhi, &next, &done, &dmu);
+    st[kStBlo] = blo;
+    st[kStBhi] = bhi;
+    st[kStDone] = done;
+    if (done) {
+        st[kStMuOut] = mu + dmu;
+        st[kStNOut] = N + c.beta * M * dmu;
+        return;
+    }
+    st[kStMu] = next;
+    mu_plan_pass(c, st, fl, p + 1, status);
+}
+
+// Device-side search: copy the result to the caller's device scalars and
+// raise the status word when the count misses n_e by more than tol_final.
+__global__ void k_mu_final(MuCfg c, const double* __restrict__ st, double* __restrict__ mu_out,
+                           double* __restrict__ n_out, int* __restrict__ status) {
+    if (threadIdx.x != 0) return;
+    const double mu = st[kStMuOut], n = st[kStNOut];
+    mu_out[0] = mu;
+    n_out[0] = n;
+    if (!isfinite(mu) || !isfinite(n)) gdm_raise(status, GDM_STATUS_NAN);
+    else if (fabs(n - c.n_e) > c.tol_final) gdm_raise(status, GDM_STATUS_NO_BRACKET);
+}
+
+// Inverse-overlap residual guard of the device-side search: round r > 0 is
+// skipped once an earlier round met the residual bound; a round that runs
+// and still misses it asks for round r + 1; after the last round a miss is
+// a non-converged iteration.
+__global__ void k_resid_flag(const double* __restrict__ emax, double bound, int r, int last, int* __restrict__ fl,
+                             int* __restrict__ status) {
+    if (threadIdx.x != 0) return;
+    const int skipped = r > 0 && fl[kFlNs + r];
+    const int ok = skipped || emax[0] <= bound;       // NaN counts as a miss
+    fl[kFlNs + r + 1] = ok ? 1 : 0;
+    if (last && !ok) gdm_raise(status, GDM_STATUS_NOT_CONVERGED);
+}
+
+// dst <- src over every packed tile (split halves and the FP32 copy when both
+// have one), predicated
+__global__ void __launch_bounds__(256) k_copy_split(int64_t n4, SplitMat src, SplitMat dst, const int* skip) {
+    if (skip && *skip) return;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256) {
+        if (src.f && dst.f) *(float4*)(dst.f + 4 * e) = *(const float4*)(src.f + 4 * e);
+        *(half4*)(dst.hi + 4 * e) = *(const half4*)(src.hi + 4 * e);
+        *(half4*)(dst.lo + 4 * e) = *(const half4*)(src.lo + 4 * e);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_copy_f64(int64_t n4, const double* __restrict__ src,
+                                                 double* __restrict__ dst) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256)
+        *(double4*)(dst + 4 * e) = *(const double4*)(src + 4 * e);
+}
+
+__global__ void k_zero1(double* p, const int* skip) {
+    if (threadIdx.x == 0 && !(skip && *skip)) p[0] = 0.0;
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------- host
@@ -904,7 +1226,8 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
     gdm_buf(ctx, BUF_TR, sizeof(double) * (2 * (size_t)P.n_sub + 8), &ok);
     gdm_buf(ctx, BUF_NDBL, sizeof(double) * (size_t)P.n_sub, &ok);
     gdm_buf(ctx, BUF_CC, sizeof(double) * (size_t)P.totc, &ok);
-    gdm_buf(ctx, BUF_L, sizeof(double) * P.tot2 * 5, &ok);     // F/V, E/G, Z64, G2, D (FP64)
+    gdm_buf(ctx, BUF_L, sizeof(double) * P.tot2 * 9, &ok);     // F/V, E/G, Z64, G2, D, X, X2, A, Z64^T (FP64)
+    gdm_buf(ctx, BUF_MSTATE, sizeof(double) * kStCount + sizeof(int) * kFlCount, &ok);   // mu search state
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_plan: mixed workspace allocation failed");
     GDM_TRY(gdm_mixed_response_alloc(ctx));
     GDM_HIP(ctx, hipMemcpyAsync(dt, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, ctx->stream));
@@ -927,11 +1250,11 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
 static SplitMat hl(SplitMat m) { return SplitMat{nullptr, m.hi, m.lo}; }
 
 static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, SplitMat E, float alpha,
-                float beta, float gamma, const char* tag, int sym = 1, int packed = 0) {
+                float beta, float gamma, const char* tag, int sym = 1, int packed = 0, const int* skip = nullptr) {
     // packed: bit 0 operands in upper-tile storage, bit 1 outputs (and E) on
-    // upper tiles only; symmetric products only
+    // upper tiles only; symmetric products only.  skip: device predicate.
     if (!sym) packed = 0;
-    GemmArgs g{A, B, O1, O2, E, alpha, beta, gamma, sym, packed};
+    GemmArgs g{A, B, O1, O2, E, alpha, beta, gamma, sym, packed, skip};
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + (sym ? ctx->mixed_tiles : 0);
     const int64_t nt = sym ? ctx->mixed_tiles_sym : ctx->mixed_tiles;
     GDM_TIMED(ctx, tag);
@@ -972,34 +1295,28 @@ static SplitMat hist(gdm_ctx* ctx, int k, int which) {
     return SplitMat{nullptr, (_Float16*)ctx->b[BUF_HIST_HI].p + off, (_Float16*)ctx->b[BUF_HIST_LO].p + off};
 }
 
-// One full recursive expansion at chemical potential mu; leaves X (with its
-// FP32 copy) in SL_X.  With a history buffer large enough for the nd doublings,
-// every X_k and Y_k is kept there (the products write into the history in
-// place of the working slots, so recording adds no traffic).
-static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, int* nd_out) {
+static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const int* skip);
+
+// Device state of the search: kStCount doubles, then the kFlCount int flags.
+static double* mu_state(gdm_ctx* ctx) { return (double*)ctx->b[BUF_MSTATE].p; }
+static int* mu_flags(gdm_ctx* ctx) { return (int*)(mu_state(ctx) + kStCount); }
+
+// One full recursive expansion; leaves X (with its FP32 copy) in SL_X.
+// Host-driven search (st == nullptr): at chemical potential mu with nd
+// doublings from the given start, b = beta / 2^nd.  With a history buffer
+// large enough, every X_k and Y_k is kept there (the products write into the
+// history in place of the working slots, so recording adds no traffic).
+// Device-side search (st != nullptr): the degree-7 start with mu and b read
+// from the state, nd = the launched doubling count, the start skipped with
+// the pass (pass_skip) and doubling j skipped while j < nd - n_d (dbl_skip[j]);
+// the skipped doublings come first, so X holds the start when the first one
+// that runs reads it.
+static int foe_pass(gdm_ctx* ctx, double mu, double b, int nd, int start, const double* st, const int* pass_skip,
+                    const int* dbl_skip) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
-    // Each doubling maps X = f(u) to f(2u) (f the Fermi function), so n_d
-    // doublings from X0 = f(u0) give f(2^n_d u0), and u0 must be b (h - mu),
-    // b = beta / 2^n_d, to first order near mu, with X0's spectrum in [0, 1].
-    // The linear start X0 = I/2 - (b/4)(h - mu I) needs b R <= 2 (R the
-    // spectral half-width about mu); the cubic start with K = b (h - mu I),
-    // X0 = I/2 - K/4 + K^3/108, stays in [0, 1] for b R <= 4 (its minimum, 0,
-    // is at K = +-3), which saves one doubling (7 products) for 2.  The
-    // response differentiates the linear start, so a recorded pass uses it.
-    const double R = std::max(std::fabs(lo - mu), std::fabs(hi - mu));
-    const bool rec_wanted = ctx->mixed_rec_cap > 0;
-    // The degree-7 start of kStart7 reaches b R <= 8 (one doubling fewer than
-    // the cubic for two more products) but is tuned for at least 5 doublings:
-    // states near |K| = 8 start well inside (0, 1/2) and need them to settle.
-    const int nd7 = (int)std::ceil(std::log2(0.125 * beta * R));
-    const bool septic = !rec_wanted && nd7 >= 5;
-    const bool cubic = !rec_wanted && !septic;
-    int nd = septic ? nd7 : (int)std::ceil(std::log2((cubic ? 0.25 : 0.5) * beta * R));
-    nd = std::max(1, std::min(nd, 40));
-    const double b = beta / std::ldexp(1.0, nd);
-    *nd_out = nd;
-    const bool rec = ctx->mixed_rec_cap >= nd;
+    const bool dev = st != nullptr;
+    const bool rec = !dev && ctx->mixed_rec_cap >= nd && start == kStartLinear && ctx->mixed_rec_cap > 0;
     ctx->mixed_rec_nd = -1;
     ctx->mixed_x0_slope = b / 4.0;
     SplitMat X = slot(ctx, SL_X), X2 = slot(ctx, SL_X2), A = slot(ctx, SL_A), Rm = slot(ctx, SL_R);
@@ -1007,110 +1324,183 @@ static int foe_pass(gdm_ctx* ctx, double mu, double beta, double lo, double hi, 
     // upper-tile storage of the pass's symmetric matrices (not when recording:
     // the response reads the recorded X_k, Y_k whole)
     const int pk = (!rec && ctx->mixed_packed) ? 3 : 0;
-    if (septic || cubic) {
+    if (start != kStartLinear) {
         const SplitMat K = slot(ctx, SL_T);
         {
             GDM_TIMED(ctx, "mixed_misc");
             hipLaunchKernelGGL(k_x0, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP).f, hl(K), mu, -b,
-                               0.0);
+                               0.0, st, pass_skip);
         }
         GDM_LAUNCH_CHECK(ctx);
-        if (septic) {
+        if (start == kStartSeptic) {
             // X0 = I/2 - K/4 + K (K^2 (K^2 (a7 K^2 + a5 I) + a3 I)), four products
-            GDM_TRY(gemm(ctx, K, K, hl(Rm), hl(A), none(), kStart7[2], 0.0f, kStart7[1], "foe_gemm", 1, pk));
-            GDM_TRY(gemm(ctx, Rm, A, none(), hl(Ya), none(), 1.0f, 0.0f, kStart7[0], "foe_gemm", 1, pk));
-            GDM_TRY(gemm(ctx, Rm, Ya, hl(Yb), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, pk));
-            GDM_TRY(gemm(ctx, K, Yb, none(), hl(X), hl(K), 1.0f, -0.25f, 0.5f, "foe_gemm", 1, pk));
+            GDM_TRY(gemm(ctx, K, K, hl(Rm), hl(A), none(), kStart7[2], 0.0f, kStart7[1], "foe_gemm", 1, pk, pass_skip));
+            GDM_TRY(gemm(ctx, Rm, A, none(), hl(Ya), none(), 1.0f, 0.0f, kStart7[0], "foe_gemm", 1, pk, pass_skip));
+            GDM_TRY(gemm(ctx, Rm, Ya, hl(Yb), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, pk, pass_skip));
+            GDM_TRY(gemm(ctx, K, Yb, none(), hl(X), hl(K), 1.0f, -0.25f, 0.5f, "foe_gemm", 1, nd == 1 ? (pk & 1) : pk,
+                         pass_skip));
         } else {
             GDM_TRY(gemm(ctx, K, K, hl(Rm), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, pk));
-            GDM_TRY(gemm(ctx, K, Rm, none(), hl(X), hl(K), 1.0f / 108.0f, -0.25f, 0.5f, "foe_gemm", 1, pk));
+            GDM_TRY(gemm(ctx, K, Rm, none(), hl(X), hl(K), 1.0f / 108.0f, -0.25f, 0.5f, "foe_gemm", 1,
+                         nd == 1 ? (pk & 1) : pk));
         }
     } else {
         GDM_TIMED(ctx, "mixed_misc");
         hipLaunchKernelGGL(k_x0, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, slot(ctx, SL_HP).f,
-                           rec ? hist(ctx, 0, 0) : X, mu, b / 4.0, 0.5);
+                           rec ? hist(ctx, 0, 0) : X, mu, b / 4.0, 0.5, (const double*)nullptr, (const int*)nullptr);
     }
     GDM_LAUNCH_CHECK(ctx);
     const int ns = ctx->mixed_ns_inv;
-    for (int it = 0; it < nd; ++it) {
+    // the first nd - 1 doublings on the split products, the last in FP64
+    for (int it = 0; it + 1 < nd; ++it) {
+        const int* sk = dev ? dbl_skip + it : nullptr;
         const SplitMat Xk = rec ? hist(ctx, it, 0) : X;
         // X2 = X X ; A = 2 X2 - 2 X + I
-        GDM_TRY(gemm(ctx, Xk, Xk, hl(X2), hl(A), hl(Xk), 2.0f, -2.0f, 1.0f, "foe_gemm", 1, pk));
+        GDM_TRY(gemm(ctx, Xk, Xk, hl(X2), hl(A), hl(Xk), 2.0f, -2.0f, 1.0f, "foe_gemm", 1, pk, sk));
         // Newton-Schulz inverse of A (eigenvalues in [1/2, 1]) from the minimax
         // quadratic start Y0 = (420 I - 576 A + 256 A^2) / 99: 1 - a y0(a) is the
         // Chebyshev T3 on [1/2, 1] scaled to 1 at a = 0, so |1 - a y0| <= 1/99;
         // each iteration R = 2I - A Y, Y <- Y R squares the error
         SplitMat Y = (rec && ns == 0) ? hist(ctx, it, 1) : Ya;
         GDM_TRY(gemm(ctx, A, A, none(), hl(Y), hl(A), 256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f, "foe_gemm", 1,
-                     pk));
+                     pk, sk));
         for (int k = 0; k < ns; ++k) {
-            GDM_TRY(gemm(ctx, A, Y, none(), hl(Rm), none(), -1.0f, 0.0f, 2.0f, "foe_gemm", 1, pk));
+            GDM_TRY(gemm(ctx, A, Y, none(), hl(Rm), none(), -1.0f, 0.0f, 2.0f, "foe_gemm", 1, pk, sk));
             const SplitMat Yn = (rec && k == ns - 1) ? hist(ctx, it, 1) : (Y.hi == Ya.hi ? Yb : Ya);
-            GDM_TRY(gemm(ctx, Y, Rm, hl(Yn), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, pk));
+            GDM_TRY(gemm(ctx, Y, Rm, hl(Yn), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, pk, sk));
             Y = Yn;
         }
         // X <- X2 Y
-        const SplitMat Xn = it + 1 == nd ? X : (rec ? hist(ctx, it + 1, 0) : hl(X));
-        // the last product writes X whole (its FP32 copy is read by full rows)
-        GDM_TRY(gemm(ctx, X2, Y, Xn, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, it + 1 == nd ? (pk & 1) : pk));
+        const SplitMat Xn = rec ? hist(ctx, it + 1, 0) : hl(X);
+        // the input of the FP64 doubling is written whole
+        GDM_TRY(gemm(ctx, X2, Y, Xn, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, it + 2 == nd ? (pk & 1) : pk,
+                     sk));
     }
+    // (the split halves: the FP32 copy of SL_X is written only by the FP64 doubling)
+    GDM_TRY(last_doubling_f64(ctx, rec ? hist(ctx, nd - 1, 0) : hl(X), rec ? hist(ctx, nd - 1, 1) : none(),
+                              pass_skip));
     if (rec) ctx->mixed_rec_nd = nd;
     return GDM_OK;
 }
 
 static double* z64(gdm_ctx* ctx) { return (double*)ctx->b[BUF_L].p + 2 * ctx->plan.tot2; }
+// the transpose of the refined factor (FP64 region 8)
+static double* z64t(gdm_ctx* ctx) { return (double*)ctx->b[BUF_L].p + 8 * ctx->plan.tot2; }
 
 // FP64 products on all tiles (sym = 0) or on the upper tiles with mirrored
 // output (sym = 1, symmetric products only)
 static int gemm64_dd(gdm_ctx* ctx, const double* A, const double* B, const double* Cin, double* C, double alpha,
-                     double beta, double gamma, int sym) {
-    GDM_TIMED(ctx, "refine64");
+                     double beta, double gamma, int sym, const int* skip = nullptr, const char* tag = "refine64") {
+    GDM_TIMED(ctx, tag);
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + (sym ? ctx->mixed_tiles : 0);
     const unsigned nt = (unsigned)(sym ? ctx->mixed_tiles_sym : ctx->mixed_tiles);
     if (sym)
         hipLaunchKernelGGL((k_gemm64<double, double, true>), dim3(nt), dim3(256), 0, ctx->stream,
-                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma);
+                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip);
     else
         hipLaunchKernelGGL((k_gemm64<double, double, false>), dim3(nt), dim3(256), 0, ctx->stream,
-                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma);
+                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }
 
 template <typename TB>
-static int gemm64_core(gdm_ctx* ctx, const double* A, const TB* B, double* C, const char* tag) {
+static int gemm64_core(gdm_ctx* ctx, const double* A, const TB* B, double* C, const char* tag,
+                       const int* skip = nullptr) {
     GDM_TIMED(ctx, tag);
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles + ctx->mixed_tiles_sym;
     hipLaunchKernelGGL((k_gemm64<double, TB, false>), dim3((unsigned)ctx->mixed_tiles_core), dim3(256), 0, ctx->stream,
-                       (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, (const double*)nullptr, C, 1.0, 0.0, 0.0);
+                       (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, (const double*)nullptr, C, 1.0, 0.0, 0.0, skip);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }
 
 static double* fp64_region(gdm_ctx* ctx, int k) { return (double*)ctx->b[BUF_L].p + (int64_t)k * ctx->plan.tot2; }
 
-static int traces(gdm_ctx* ctx, double* N, double* M) {
+// The last doubling of a pass in FP64 on the matrix cores (the final
+// refinement step of the expansion): X2 = X X, A = 2 X2 - 2 X + I,
+// Y = A^-1 from Y0 = 4I - 5A + 2A^2 by kFinalNs Newton-Schulz steps,
+// X <- X2 Y.  1 - a y0(a) = (1 - a)^2 (1 - 2a) vanishes to second order at
+// a = 1 (the occupied and empty states, where X is 1 or 0 to far below FP32
+// rounding) and at a = 1/2, and is at most 1/27 between; k steps leave
+// 27^-(2^k), and since that residual is never negative after a step every
+// partly occupied state comes out low by up to that much, a bias of the
+// electron count: two steps (1.9e-6) shift it by ~1e-3 e at 80,000
+// electrons, three (3.6e-12) do not.  The doubling map is superattracting at 0 and 1, so the FP32-level
+// errors of the split-product doublings in those states are squared away
+// here instead of summing into a systematic bias of the electron count
+// (~2e-8 per orbital), which would move mu inside a gap by that bias over
+// N'(mu).  The result goes to SL_X (FP32 copy and split, whole) and, for the
+// traces and the density, stays in FP64 region 5; a recorded pass also keeps
+// the split Y for the response.  All matrices commute (polynomials in
+// h_perp), so every product computes upper tiles and mirrors them.
+constexpr int kFinalNs = 3;
+
+static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const int* skip) {
+    const Plan& P = ctx->plan;
+    const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
+    double* X = fp64_region(ctx, 5);
+    double* X2 = fp64_region(ctx, 6);
+    double* A = fp64_region(ctx, 7);
+    double* Ya = fp64_region(ctx, 4);
+    double* Yb = fp64_region(ctx, 3);
+    double* R = fp64_region(ctx, 1);
+    const int64_t n4 = P.tot2 / 4;
+    {
+        GDM_TIMED(ctx, "last64");
+        hipLaunchKernelGGL(k_split_to_f64, dim3(4096), dim3(256), 0, ctx->stream, n4, Xin, X, skip);
+    }
+    GDM_LAUNCH_CHECK(ctx);
+    GDM_TRY(gemm64_dd(ctx, X, X, nullptr, X2, 1.0, 0.0, 0.0, 1, skip, "last64"));
+    {
+        GDM_TIMED(ctx, "last64");
+        hipLaunchKernelGGL(k_doubling_a, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, X, X2, A, skip);
+    }
+    GDM_LAUNCH_CHECK(ctx);
+    GDM_TRY(gemm64_dd(ctx, A, A, A, Ya, 2.0, -5.0, 4.0, 1, skip, "last64"));     // Y0 = 2 A^2 - 5 A + 4 I
+    double* Y = Ya;
+    for (int k = 0; k < kFinalNs; ++k) {
+        GDM_TRY(gemm64_dd(ctx, A, Y, nullptr, R, -1.0, 0.0, 2.0, 1, skip, "last64"));   // R = 2I - A Y
+        double* Yn = Y == Ya ? Yb : Ya;
+        GDM_TRY(gemm64_dd(ctx, Y, R, nullptr, Yn, 1.0, 0.0, 0.0, 1, skip, "last64"));   // Y <- Y R
+        Y = Yn;
+    }
+    GDM_TRY(gemm64_dd(ctx, X2, Y, nullptr, X, 1.0, 0.0, 0.0, 1, skip, "last64"));     // X <- X2 Y
+    GDM_TIMED(ctx, "last64");
+    if (Yrec.hi) {
+        hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, n4, Y, Yrec, skip);
+        GDM_LAUNCH_CHECK(ctx);
+    }
+    hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, n4, X, slot(ctx, SL_X), skip);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+// FP64 core traces of the last pass: N = 2 sum_core (Z X Z s)_aa and
+// M = 2 sum_core (Z (X - X^2) Z s)_aa (the count's derivative is beta M),
+// into the trace buffer's two scalars at 2 n_sub (enqueued only).
+static int traces(gdm_ctx* ctx, const int* skip) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
     double* part = (double*)ctx->b[BUF_TR].p;
     double* G = fp64_region(ctx, 1);
     double* G2 = fp64_region(ctx, 3);
     double* V = fp64_region(ctx, 0);
-    GDM_TRY(gemm64_core<float>(ctx, z64(ctx), slot(ctx, SL_X).f, G, "traces"));
-    GDM_TRY(gemm64_core<float>(ctx, G, slot(ctx, SL_X).f, G2, "traces"));     // Z[core,:] X^2 = G X
-    {
-        GDM_TIMED(ctx, "traces");
-        hipLaunchKernelGGL(k_trace_dot, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, G, G2, V, part);
-        GDM_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kEw), 0, ctx->stream, P.n_sub, part,
-                           part + 2 * (size_t)P.n_sub);
-        GDM_LAUNCH_CHECK(ctx);
-    }
-    double h[2];
-    GDM_HIP(ctx, hipMemcpyAsync(h, part + 2 * (size_t)P.n_sub, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    const double* X = fp64_region(ctx, 5);       // X of the pass in FP64 (last_doubling_f64)
+    GDM_TRY(gemm64_core<double>(ctx, z64(ctx), X, G, "traces", skip));
+    GDM_TRY(gemm64_core<double>(ctx, G, X, G2, "traces", skip));     // Z[core,:] X^2 = G X
+    GDM_TIMED(ctx, "traces");
+    hipLaunchKernelGGL(k_trace_dot, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, G, G2, V, part, skip);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kEw), 0, ctx->stream, P.n_sub, part, part + 2 * (size_t)P.n_sub,
+                       skip);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+static int read_state(gdm_ctx* ctx, double* h) {
+    GDM_HIP(ctx, hipMemcpyAsync(h, mu_state(ctx), sizeof(double) * kStCount, hipMemcpyDeviceToHost, ctx->stream));
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    *N = h[0];
-    *M = h[1];
     return GDM_OK;
 }
 
@@ -1119,12 +1509,18 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
                       double mu_guess, double tol_N, double* mu_out, double* n_out) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
+    const bool dev = ctx->mu_out_device != 0;
+    if (dev && ctx->mixed_rec_cap > 0)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_find_mu: the device-side mixed search does not record the expansion "
+                                        "for the charge response (gdm_set_response(ctx, 0) first)");
     const double beta = 1.0 / kT;
     const int orth = S == nullptr;
     double* h64 = (double*)ctx->b[BUF_A].p;
     double* s64 = (double*)ctx->b[BUF_S].p;
     double* scale = (double*)ctx->b[BUF_NDBL].p;
     double* bounds = (double*)ctx->b[BUF_GERSH].p;
+    double* st = mu_state(ctx);
+    int* fl = mu_flags(ctx);
     ctx->mixed_gemms = 0;
     ctx->mixed_flops = 0.0;
     ctx->mixed_bytes = 0.0;
@@ -1151,71 +1547,112 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
     // upper-tile storage for these symmetric products too, except the Z that
     // the FP64 refinement reads whole (with its FP32 copy)
     const int pkz = ctx->mixed_packed ? 3 : 0;
-    auto ns_step = [&](bool full_z) -> int {
-        GDM_TRY(gemm(ctx, Z, Y, none(), hl(T), none(), -0.5f, 0.0f, 1.5f, "ns_gemm", 1, pkz));
-        GDM_TRY(gemm(ctx, Y, T, hl(Y2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm", 1, pkz));
+    auto ns_step = [&](bool full_z, const int* sk) -> int {
+        GDM_TRY(gemm(ctx, Z, Y, none(), hl(T), none(), -0.5f, 0.0f, 1.5f, "ns_gemm", 1, pkz, sk));
+        GDM_TRY(gemm(ctx, Y, T, hl(Y2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm", 1, pkz, sk));
         GDM_TRY(gemm(ctx, T, Z, full_z ? Z2 : hl(Z2), none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm", 1,
-                     full_z ? (pkz & 1) : pkz));
-        std::swap(Y, Y2);
-        std::swap(Z, Z2);
+                     full_z ? (pkz & 1) : pkz, sk));
         return GDM_OK;
     };
     if (!orth) {
         // Y0 = (s/c) Z0 = a (s/c) + b (s/c)^2 (Z0 from k_prep)
         GDM_TRY(gemm(ctx, Y, Y, none(), hl(Y2), hl(Y), kZ0b, kZ0a, 0.0f, "ns_gemm", 1, pkz));
         std::swap(Y, Y2);
-        for (int it = 0; it < ctx->mixed_ns_z; ++it) GDM_TRY(ns_step(it + 1 == ctx->mixed_ns_z));
+        for (int it = 0; it < ctx->mixed_ns_z; ++it) {
+            GDM_TRY(ns_step(it + 1 == ctx->mixed_ns_z, nullptr));
+            std::swap(Y, Y2);
+            std::swap(Z, Z2);
+        }
     }
     ctx->mixed_ns_z_used = orth ? 0 : ctx->mixed_ns_z;
     // FP64 residual refinement of Z (Z s Z = I): Z64 = Z / sqrt(c) in FP64,
-    // F = s Z64, E = Z64 F - I, Z64 <- Z64 - Z64 E / 2 (error O(E^2)); E and
-    // the update are symmetric products (upper tiles, mirrored).  The
-    // refinement also removes any systematic bias of the split products from
-    // Z64, which the electron count (and so mu) depends on.  While max |E_ij|
-    // is too large for one step, the coupled iteration continues first.
-    // Z64 serves the traces and the final step, its split copy (in SL_Z) the
-    // expansion.
+    // F = s Z64, E = Z64 F - I, Z64 <- Z64 (I - E/2 + 3/8 E^2) (residual
+    // O(E^3)); E and the update are symmetric products (upper tiles,
+    // mirrored).  The refinement also removes any systematic bias of the split
+    // products from Z64, which the electron count (and so mu) depends on.
+    // While max |E_ij| is too large for one step, the coupled iteration
+    // continues first: on
+    // the host, or on the device through predicated extra rounds (each with
+    // its iteration written back into the working slots).
     {
         double* F = fp64_region(ctx, 0);
         double* E = fp64_region(ctx, 1);
         double* Z64 = z64(ctx);
         double* emax_d = (double*)ctx->b[BUF_TR].p + 2 * (size_t)P.n_sub + 4;
+        const int extras = std::min(ctx->mixed_ns_z_extra, kMaxNsExtra - 1);
         for (int extra = 0;; ++extra) {
+            const int* sk = (dev && extra > 0) ? fl + kFlNs + extra : nullptr;
+            if (dev && extra > 0 && !orth) {
+                // one more coupled iteration, run only while the last round missed
+                GDM_TRY(ns_step(true, sk));
+                const int64_t n4 = P.tot2 / 4;
+                hipLaunchKernelGGL(k_copy_split, dim3(2048), dim3(256), 0, ctx->stream, n4, hl(Y2), hl(Y), sk);
+                GDM_LAUNCH_CHECK(ctx);
+                hipLaunchKernelGGL(k_copy_split, dim3(2048), dim3(256), 0, ctx->stream, n4, Z2, Z, sk);
+                GDM_LAUNCH_CHECK(ctx);
+            }
             {
                 GDM_TIMED(ctx, "refine64");
-                hipLaunchKernelGGL(k_scale_to_f64, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, Z.f, scale, orth,
-                                   Z64);
+                hipLaunchKernelGGL(k_scale_sym_to_f64, dim3((unsigned)ctx->mixed_tiles_sym), dim3(256), 0, ctx->stream,
+                                   desc, (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles, Z.f, scale, orth, Z64,
+                                   sk);
             }
             GDM_LAUNCH_CHECK(ctx);
             if (orth) break;                                                  // Z = I exactly
-            GDM_TRY(gemm64_dd(ctx, s64, Z64, nullptr, F, 1.0, 0.0, 0.0, 0));     // F = s Z
-            GDM_TRY(gemm64_dd(ctx, Z64, F, nullptr, E, 1.0, 0.0, -1.0, 1));     // E = Z (s Z) - I
-            double emax = 0.0;
+            GDM_TRY(gemm64_dd(ctx, s64, Z64, nullptr, F, 1.0, 0.0, 0.0, 0, sk));     // F = s Z
+            GDM_TRY(gemm64_dd(ctx, Z64, F, nullptr, E, 1.0, 0.0, -1.0, 1, sk));     // E = Z (s Z) - I
             {
                 GDM_TIMED(ctx, "refine64");
-                GDM_TRY(gdm_fill_f64(ctx, emax_d, 1, 0.0));
+                hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, ctx->stream, emax_d, sk);
+                GDM_LAUNCH_CHECK(ctx);
                 hipLaunchKernelGGL(k_resid_max, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, E,
-                                   (unsigned long long*)emax_d);
+                                   (unsigned long long*)emax_d, sk);
             }
             GDM_LAUNCH_CHECK(ctx);
+            if (dev) {
+                hipLaunchKernelGGL(k_resid_flag, dim3(1), dim3(64), 0, ctx->stream, emax_d, kZResidMax, extra,
+                                   extra == extras ? 1 : 0, fl, ctx->d_status);
+                GDM_LAUNCH_CHECK(ctx);
+                if (extra == extras) break;
+                ++ctx->mixed_ns_z_used;       // launched (the stats report those that ran)
+                continue;
+            }
+            double emax = 0.0;
             GDM_HIP(ctx, hipMemcpyAsync(&emax, emax_d, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
             GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            if (emax <= kZResidMax) {
-                GDM_TRY(gemm64_dd(ctx, Z64, E, Z64, F, -0.5, 1.0, 0.0, 1));        // F <- Z - Z E / 2
-                GDM_HIP(ctx, hipMemcpyAsync(Z64, F, sizeof(double) * P.tot2, hipMemcpyDeviceToDevice, ctx->stream));
-                break;
-            }
+            if (emax <= kZResidMax) break;
             if (extra >= ctx->mixed_ns_z_extra || !std::isfinite(emax))
                 return gdm_fail(ctx, GDM_E_NOT_CONVERGED,
                                 "mixed: inverse-overlap factor residual %.3g after %d Newton-Schulz iterations "
                                 "(overlap too ill-conditioned)", emax, ctx->mixed_ns_z_used);
-            GDM_TRY(ns_step(true));
+            GDM_TRY(ns_step(true, nullptr));
+            std::swap(Y, Y2);
+            std::swap(Z, Z2);
             ++ctx->mixed_ns_z_used;
         }
+        if (!orth) {
+            // third-order refinement Z1 = Z (I + E)^-1/2 = Z (I - E/2 + 3/8 E^2 + O(E^3)) with
+            // E = Z s Z - I for the symmetric Z: T = 3/8 E^2 - E/2 is a polynomial in E, so
+            // Z1^T s Z1 = (I + T)(I + E)(I + T) = I + O(E^3) holds exactly in algebra, whatever
+            // the rounding errors of Z (which do not commute with s) are; Z1 itself is not
+            // symmetric, so its product is formed on all tiles and the later steps use
+            // Z1^T h Z1 and Z1 X Z1^T (D does not depend on which factor of s^-1 is used).
+            // A symmetric step would leave those errors in place: Z s Z - I stays at the
+            // FP32 level (1e-7) with a negative trace, a bias of the electron count.
+            double* T64 = fp64_region(ctx, 3);
+            GDM_TRY(gemm64_dd(ctx, E, E, E, T64, 0.375, -0.5, 0.0, 1));        // T = 3/8 E^2 - E/2
+            GDM_TRY(gemm64_dd(ctx, Z64, T64, Z64, F, 1.0, 1.0, 0.0, 0));      // F <- Z + Z T (all tiles)
+            hipLaunchKernelGGL(k_copy_f64, dim3(4096), dim3(256), 0, ctx->stream, P.tot2 / 4, F, Z64);
+            GDM_LAUNCH_CHECK(ctx);
+        }
+        // Z1^T in FP64 (the density's right factor) and as split operands with
+        // an FP32 copy (the split products of h_perp and of the response)
         Z = slot(ctx, SL_Z);
         {
             GDM_TIMED(ctx, "refine64");
-            hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, P.tot2 / 4, Z64, hl(Z));
+            hipLaunchKernelGGL(k_transpose64, dim3((unsigned)ctx->mixed_tiles_sym), dim3(256), 0, ctx->stream, desc,
+                               (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles, Z64, z64t(ctx), Z,
+                               (const int*)nullptr);
         }
         GDM_LAUNCH_CHECK(ctx);
         GDM_TRY(gemm64_core<double>(ctx, s64, Z64, F, "refine64"));   // V = s[core,:] Z
@@ -1229,59 +1666,70 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
                            (int)strip_grid(P).y, bounds);
     }
     GDM_LAUNCH_CHECK(ctx);
-    std::vector<double> hb(2 * (size_t)P.n_sub * strip_grid(P).y);
-    GDM_HIP(ctx, hipMemcpyAsync(hb.data(), bounds, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, ctx->stream));
-    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    double lo = INFINITY, hi = -INFINITY;
-    for (size_t k = 0; k < hb.size(); k += 2) {
-        lo = std::min(lo, hb[k]);
-        hi = std::max(hi, hb[k + 1]);
+    // mu: safeguarded Newton steps on the FP64 traces (k_mu_update, the same
+    // arithmetic whether the host or the device drives the passes)
+    MuCfg cfg;
+    cfg.n_e = n_e;
+    cfg.beta = beta;
+    cfg.kT = kT;
+    cfg.tol = std::max(tol_N, 1e-10 * n_e);
+    cfg.tol_final = std::max(tol_N, 1e-7 * n_e);
+    cfg.guess = mu_guess;
+    cfg.rec = ctx->mixed_rec_cap > 0;
+    cfg.dev = dev;
+    cfg.nd_launch = ctx->mixed_nd_launch;
+    cfg.max_passes = dev ? ctx->mixed_dev_passes : std::min(ctx->mixed_max_passes, kMaxPasses);
+    const double* part_nm = (const double*)ctx->b[BUF_TR].p + 2 * (size_t)P.n_sub;
+    const int nb = (int)(P.n_sub * strip_grid(P).y);
+    hipLaunchKernelGGL(k_mu_init, dim3(1), dim3(kEw), 0, ctx->stream, bounds, nb, dev ? mu_out : nullptr, cfg, st, fl,
+                       ctx->d_status);
+    GDM_LAUNCH_CHECK(ctx);
+    double hs[kStCount];
+    if (dev) {
+        for (int p = 0; p < cfg.max_passes; ++p) {
+            GDM_TRY(foe_pass(ctx, 0.0, 0.0, cfg.nd_launch, kStartSeptic, st, fl + kFlPass + p,
+                             fl + kFlDbl + p * kMaxNd));
+            GDM_TRY(traces(ctx, fl + kFlPass + p));
+            hipLaunchKernelGGL(k_mu_update, dim3(1), dim3(64), 0, ctx->stream, p, cfg, part_nm, st, fl, ctx->d_status);
+            GDM_LAUNCH_CHECK(ctx);
+        }
+        hipLaunchKernelGGL(k_mu_final, dim3(1), dim3(64), 0, ctx->stream, cfg, st, mu_out, n_out, ctx->d_status);
+        GDM_LAUNCH_CHECK(ctx);
+        ctx->mixed_passes = -1;             // on the device; gdm_mixed_stats reads them
+        ctx->mixed_nd = -1;
+        ctx->mixed_beta = beta;
+        ctx->mixed_dev_state = true;
+        return GDM_OK;
     }
-    if (!std::isfinite(lo) || !std::isfinite(hi)) return gdm_fail(ctx, GDM_E_NAN, "mixed: non-finite spectral bounds");
-    // mu: safeguarded Newton steps on the FP64 traces (refined Z, count error
-    // ~1e-7 N_e) until |N - N_e| <= max(tol_N, 1e-7 N_e).  Within that
-    // resolution the count cannot place mu any better (inside a gap N'(mu) is
-    // tiny), so the first-order correction mu* = mu + (N_e - N)/N'(mu) is only
-    // applied when the pass budget ran out, and only within kT.
-    double mu = std::isfinite(mu_guess) && mu_guess > lo && mu_guess < hi ? mu_guess : 0.5 * (lo + hi);
-    double blo = lo, bhi = hi, N = 0.0, M = 0.0;
-    int passes = 0, nd = 0;
-    const double tol = std::max(tol_N, 1e-7 * n_e);
-    for (;;) {
-        GDM_TRY(foe_pass(ctx, mu, beta, lo, hi, &nd));
-        GDM_TRY(traces(ctx, &N, &M));
-        ++passes;
-        const double dN = n_e - N;
-        const double slope = beta * M;
-        if (std::fabs(dN) <= tol || passes >= ctx->mixed_max_passes) break;
-        if (dN > 0) blo = mu; else bhi = mu;
-        // safeguarded Newton: the Newton point if it stays in the bracket and
-        // shrinks it by at least half, else bisection
-        double next = slope > 0.0 ? mu + dN / slope : 0.5 * (blo + bhi);
-        if (!(next > blo && next < bhi) || std::fabs(next - mu) > 0.5 * (bhi - blo)) next = 0.5 * (blo + bhi);
-        mu = next;
+    GDM_TRY(read_state(ctx, hs));
+    for (int p = 0; p < cfg.max_passes; ++p) {
+        GDM_TRY(foe_pass(ctx, hs[kStMu], hs[kStB], (int)hs[kStNd], (int)hs[kStStart], nullptr, nullptr, nullptr));
+        GDM_TRY(traces(ctx, nullptr));
+        hipLaunchKernelGGL(k_mu_update, dim3(1), dim3(64), 0, ctx->stream, p, cfg, part_nm, st, fl, ctx->d_status);
+        GDM_LAUNCH_CHECK(ctx);
+        const int nd_pass = (int)hs[kStNd];
+        GDM_TRY(read_state(ctx, hs));
+        ctx->mixed_nd = nd_pass;
+        if (hs[kStDone] != 0.0) break;
     }
-    ctx->mixed_passes = passes;
-    ctx->mixed_nd = nd;
-    ctx->mixed_mu_pass = mu;
-    ctx->mixed_slope = beta * M;
+    ctx->mixed_dev_state = false;
+    ctx->mixed_passes = (int)hs[kStPasses];
+    ctx->mixed_mu_pass = hs[kStMuPass];
+    ctx->mixed_slope = beta * hs[kStM];
     ctx->mixed_beta = beta;
-    // first-order correction mu* = mu + dmu, used only inside its linear range (|dmu| <= kT)
-    double dmu = 0.0;
-    if (std::fabs(n_e - N) > tol && beta * M > 0.0) {
-        dmu = (n_e - N) / (beta * M);
-        if (std::fabs(dmu) > kT) dmu = 0.0;
-    }
-    *mu_out = mu + dmu;
-    *n_out = N + beta * M * dmu;
+    *mu_out = hs[kStMuOut];
+    *n_out = hs[kStNOut];
     return GDM_OK;
 }
 
-int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT, double* D_core) {
+// mu_dev: when non-null, mu is read on the device (a device-side search's
+// result) and the first-order term uses the device state's pass mu
+int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const double* mu_dev, double kT,
+                      double* D_core) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
     const double beta = 1.0 / kT;
-    const double kappa = (mu - ctx->mixed_mu_pass) * beta;
+    const double kappa = mu_dev ? 0.0 : (mu - ctx->mixed_mu_pass) * beta;
     double* G = fp64_region(ctx, 1);
     double* G2 = fp64_region(ctx, 3);
     double* Gk = fp64_region(ctx, 0);
@@ -1289,10 +1737,11 @@ int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double k
     // D[core,:] = (G + kappa (G - G2)) Z,  G = Z[core,:] X, G2 = Z[core,:] X^2 of the last pass
     {
         GDM_TIMED(ctx, "dcore");
-        hipLaunchKernelGGL(k_combine, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, G, G, G2, Gk, kappa);
+        hipLaunchKernelGGL(k_combine, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, G, G, G2, Gk, kappa, mu_dev,
+                           (const double*)mu_state(ctx), beta);
     }
     GDM_LAUNCH_CHECK(ctx);
-    GDM_TRY(gemm64_core<double>(ctx, Gk, z64(ctx), Dp, "dcore"));
+    GDM_TRY(gemm64_core<double>(ctx, Gk, z64t(ctx), Dp, "dcore"));      // D[core,:] = G Z1^T
     {
         GDM_TIMED(ctx, "dcore");
         hipLaunchKernelGGL(k_pack_core, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Dp, D_core);
@@ -1392,10 +1841,11 @@ int gdm_mixed_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs*
     double* part = (double*)ctx->b[BUF_TR].p;
     {
         GDM_TIMED(ctx, "response");
-        hipLaunchKernelGGL(k_trace_dot, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Gd, Gd, R0, part);
+        hipLaunchKernelGGL(k_trace_dot, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Gd, Gd, R0, part,
+                           (const int*)nullptr);
         GDM_LAUNCH_CHECK(ctx);
         hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kEw), 0, ctx->stream, P.n_sub, part,
-                           part + 2 * (size_t)P.n_sub);
+                           part + 2 * (size_t)P.n_sub, (const int*)nullptr);
         GDM_LAUNCH_CHECK(ctx);
     }
     double h[2];
@@ -1408,10 +1858,11 @@ int gdm_mixed_response(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs*
     const double kappa = slope > 0.0 ? dm * ctx->mixed_beta : 0.0;
     {
         GDM_TIMED(ctx, "response");
-        hipLaunchKernelGGL(k_combine, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Gd, G, G2, Gd, kappa);
+        hipLaunchKernelGGL(k_combine, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, Gd, G, G2, Gd, kappa,
+                           (const double*)nullptr, (const double*)nullptr, 0.0);
     }
     GDM_LAUNCH_CHECK(ctx);
-    GDM_TRY(gemm64_core<double>(ctx, Gd, z64(ctx), R1, "response"));
+    GDM_TRY(gemm64_core<double>(ctx, Gd, z64t(ctx), R1, "response"));
     {
         GDM_TIMED(ctx, "response");
         hipLaunchKernelGGL(k_pack_core, dim3(P.n_sub), dim3(256), 0, ctx->stream, desc, R1, dDp);
@@ -1442,9 +1893,48 @@ extern "C" int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max
     return GDM_OK;
 }
 
+extern "C" int gdm_set_mixed_capture(gdm_ctx* ctx, int passes, int nd_launch) {
+    if (!ctx) return GDM_E_ARG;
+    if (passes < 1 || passes > kMaxPasses || nd_launch < 5 || nd_launch > kMaxNd)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_set_mixed_capture: passes 1..%d, nd_launch 5..%d", kMaxPasses, kMaxNd);
+    ctx->mixed_dev_passes = passes;
+    ctx->mixed_nd_launch = nd_launch;
+    return GDM_OK;
+}
+
+extern "C" int gdm_mixed_mu_state(gdm_ctx* ctx, double* mu_pass, double* n_pass, double* slope) {
+    if (!ctx) return GDM_E_ARG;
+    if (ctx->plan.precision != GDM_MIXED_F16 || !ctx->b[BUF_MSTATE].p)
+        return gdm_fail(ctx, GDM_E_STATE, "gdm_mixed_mu_state: no mixed plan");
+    double hs[kStCount];
+    GDM_TRY(read_state(ctx, hs));
+    if (mu_pass) *mu_pass = hs[kStMuPass];
+    if (n_pass) *n_pass = hs[kStN];
+    if (slope) *slope = ctx->mixed_beta * hs[kStM];
+    return GDM_OK;
+}
+
+// pass mu of the last search (read from the device after a device-side one)
+int gdm_mixed_pass_mu(gdm_ctx* ctx, double* mu_pass) {
+    if (!ctx->mixed_dev_state) {
+        *mu_pass = ctx->mixed_mu_pass;
+        return GDM_OK;
+    }
+    double hs[kStCount];
+    GDM_TRY(read_state(ctx, hs));
+    *mu_pass = hs[kStMuPass];
+    return GDM_OK;
+}
+
 extern "C" int gdm_mixed_stats(gdm_ctx* ctx, int* passes, int* n_doublings, int64_t* gemm_launches,
                                double* flops_per_launch, double* bytes_per_launch, int* ns_z_used) {
     if (!ctx) return GDM_E_ARG;
+    if (ctx->mixed_dev_state && ctx->b[BUF_MSTATE].p) {
+        double hs[kStCount];
+        GDM_TRY(read_state(ctx, hs));
+        ctx->mixed_passes = (int)hs[kStPasses];
+        ctx->mixed_nd = (int)hs[kStNd];
+    }
     if (passes) *passes = ctx->mixed_passes;
     if (n_doublings) *n_doublings = ctx->mixed_nd;
     if (gemm_launches) *gemm_launches = ctx->mixed_gemms;

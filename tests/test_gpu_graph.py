@@ -179,28 +179,106 @@ def test_whole_fp64_solve_replays_from_a_hip_graph():
             c.close()
 
 
-def test_device_mu_refused_on_the_mixed_path():
+def test_whole_mixed_solve_replays_from_a_hip_graph():
+    """Mixed path with device outputs: the chemical-potential search runs a
+    fixed number of passes and doublings whose launches are predicated on the
+    device (gdm_set_mixed_capture), so gather, inverse overlap, expansion
+    passes, mu, density at the device mu and charges capture into one graph.
+    Each replay, with H overwritten by three SCC potentials, must equal the
+    eager device-side solve bit for bit, and that solve must equal the
+    host-driven search when it takes no more passes than were launched."""
     from paper_2606_03140_amd import pipeline
     from paper_2606_03140_amd._lib import Context, GDMError
-    log("device mu outputs and density at a device mu are FP64-only")
-    c = Context(0)
-    box = waterbox.water_box(96, 1)
-    sysm = system_of(box)
-    tb = tb_params(False)
-    part = pipeline.cutoff_partition(c, sysm, tb, (2, 2, 2))
-    H, S = c.build_hs(sysm, tb, part.nbr)
-    c.plan(part.sg, pipeline.MIXED_F16)
-    mu_t = torch.zeros(1, dtype=torch.float64, device=c.dev)
-    n_t = torch.zeros_like(mu_t)
-    c.set_mu_outputs(True)
-    with pytest.raises(GDMError) as e:
-        c.find_mu_device(sysm, part.sg, part.nbr, H, S, 0.1, pipeline.MIXED_F16, mu_t, n_t)
-    assert e.value.code == -1
-    c.set_mu_outputs(False)
-    mu, n = c.find_mu(sysm, part.sg, part.nbr, H, S, 0.1, pipeline.MIXED_F16, -7.0, 1e-6)
-    mu_t.fill_(mu)
-    D = torch.empty(int(part.sg.dcore_off[-1]), dtype=torch.float64, device=c.dev)
-    with pytest.raises(GDMError) as e:
-        c.subgraph_density_dmu(part.sg, mu_t, 0.1, pipeline.MIXED_F16, D)
-    assert e.value.code == -1
-    c.close()
+    prec = pipeline.MIXED_F16
+    log("hipGraph capture of the whole mixed solve (device mu), 96 waters, three potentials")
+    hp = _hip()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        c = Context(0)
+        box = waterbox.water_box(96, 1)
+        sysm = system_of(box)
+        tb = tb_params(False)
+        part = pipeline.cutoff_partition(c, sysm, tb, (2, 2, 2))
+        gen = torch.Generator().manual_seed(7)
+        Hs = []
+        for _ in range(3):
+            V = (0.3 * torch.randn(sysm.n_atoms, generator=gen, dtype=torch.float64)).to(c.dev)
+            Hs.append(c.build_hs(sysm, tb, part.nbr, V)[0])
+        H, S = c.build_hs(sysm, tb, part.nbr)
+        c.plan(part.sg, prec)
+        # the charge response's recording is host-driven only
+        c.set_response(8)
+        c.set_mu_outputs(True)
+        mu_t = torch.full((1,), float("nan"), dtype=torch.float64, device=c.dev)
+        n_t = torch.zeros_like(mu_t)
+        with pytest.raises(GDMError) as e:
+            c.find_mu_device(sysm, part.sg, part.nbr, H, S, 0.1, prec, mu_t, n_t, mu_guess=-7.0, tol_N=1e-6)
+        assert e.value.code == -1
+        c.set_response(0)
+        c.plan(part.sg, prec)
+        c.set_mixed_capture(6, 10)
+        D = torch.empty(int(part.sg.dcore_off[-1]), dtype=torch.float64, device=c.dev)
+        q = torch.empty(sysm.n_atoms, dtype=torch.float64, device=c.dev)
+
+        def solve():
+            mu_t.fill_(float("nan"))          # start every solve from the host guess
+            c.find_mu_device(sysm, part.sg, part.nbr, H, S, 0.1, prec, mu_t, n_t, mu_guess=-7.0, tol_N=1e-6)
+            c.subgraph_density_dmu(part.sg, mu_t, 0.1, prec, D)
+            c.mulliken_charges(sysm, part.sg, part.nbr, S, D, out=q)
+
+        refs = []
+        for Hk in Hs:
+            H.copy_(Hk)
+            solve()
+            c.check()
+            st = c.mixed_stats()
+            refs.append((mu_t.clone(), n_t.clone(), D.clone(), q.clone(), st["passes"], st["n_doublings"]))
+            log(f"  eager device search: mu {float(mu_t):.9f} N {float(n_t):.9f} passes {st['passes']} "
+                f"n_d {st['n_doublings']}")
+            assert abs(float(n_t) - sysm.n_electrons) <= 1e-7 * sysm.n_electrons
+        torch.cuda.synchronize()
+        # the host-driven search does the same arithmetic
+        c.set_mu_outputs(False)
+        H.copy_(Hs[0])
+        mu_h, n_h = c.find_mu(sysm, part.sg, part.nbr, H, S, 0.1, prec, -7.0, 1e-6)
+        sth = c.mixed_stats()
+        log(f"  host search: mu {mu_h:.9f} passes {sth['passes']}")
+        if sth["passes"] <= 6:
+            assert mu_h == float(refs[0][0]) and n_h == float(refs[0][1])
+        c.set_mu_outputs(True)
+        torch.cuda.synchronize()
+        stc = C.c_void_p(side.cuda_stream)
+        assert hp.hipStreamBeginCapture(stc, _CAPTURE_RELAXED) == 0
+        graph = C.c_void_p()
+        try:
+            solve()
+        finally:
+            rc_end = hp.hipStreamEndCapture(stc, C.byref(graph))
+        assert rc_end == 0
+        exe = C.c_void_p()
+        assert hp.hipGraphInstantiate(C.byref(exe), graph, None, None, 0) == 0
+        try:
+            for k, Hk in enumerate(Hs):
+                H.copy_(Hk)
+                for t in (n_t, D, q):
+                    t.fill_(float("nan"))
+                assert hp.hipGraphLaunch(exe, stc) == 0
+                assert hp.hipStreamSynchronize(stc) == 0
+                c.check()
+                mu_r, n_r, D_r, q_r, _, _ = refs[k]
+                log(f"  potential {k}: mu {float(mu_t):.9f} (eager {float(mu_r):.9f}), N {float(n_t):.9f}, "
+                    f"max|q - eager| {float((q - q_r).abs().max()):.1e}")
+                assert torch.equal(mu_t, mu_r) and torch.equal(n_t, n_r)
+                assert torch.equal(D, D_r) and torch.equal(q, q_r)
+                # eager host-driven work between the replays
+                c.set_mu_outputs(False)
+                c.find_mu(sysm, part.sg, part.nbr, H, S, 0.1, prec, -7.0, 1e-6)
+                c.set_mu_outputs(True)
+                torch.cuda.synchronize()
+            assert not torch.equal(refs[0][3], refs[1][3])
+        finally:
+            hp.hipGraphExecDestroy(exe)
+            hp.hipGraphDestroy(graph)
+            torch.cuda.synchronize()
+            c.set_mu_outputs(False)
+            c.close()

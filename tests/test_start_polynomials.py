@@ -80,3 +80,21 @@ def test_inverse_sqrt_start_bound():
     x = np.linspace(0.1, 1.0, 200001)
     e = np.abs(1.0 - x * (c0 + c1 * x) ** 2)
     assert e.max() <= 0.417
+
+
+def test_final_doubling_inverse_start():
+    # the FP64 last doubling: y0(a) = 4 - 5a + 2a^2 (GEMM epilogue 2 A^2 - 5 A + 4 I)
+    assert "gemm64_dd(ctx, A, A, A, Ya, 2.0, -5.0, 4.0" in SRC
+    a = np.linspace(0.5, 1.0, 200001)
+    r = 1.0 - a * (4.0 - 5.0 * a + 2.0 * a * a)
+    # residual (1 - a)^2 (1 - 2a): zero at a = 1/2 and to second order at a = 1
+    # (the occupied and empty states), at most 1/27 (at a = 2/3) in between
+    assert np.allclose(r, (1.0 - a) ** 2 * (1.0 - 2.0 * a), atol=1e-15)
+    assert abs(np.abs(r).max() - 1.0 / 27.0) < 1e-9
+    assert "constexpr int kFinalNs = 3;" in SRC
+    assert (np.abs(r) ** 8).max() <= 27.0 ** -8 + 1e-30 and 27.0 ** -8 < 4e-12
+    # two Newton-Schulz steps would square the residual twice: <= 27^-4 everywhere,
+    # and a state 1e-4 from a = 1 is left with about (1e-8)^4, far below FP64 rounding
+    assert (np.abs(r) ** 4).max() <= 27.0 ** -4 + 1e-18
+    e = 1e-4
+    assert abs((e * e * (1 - 2 * (1 - e))) ** 4) < 1e-31
