@@ -373,6 +373,21 @@ int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_
                         const int32_t* col, double rcut, double eta, int32_t k_max,
                         const double hubbard_U[2], const double* tau, const double* q, double* V);
 
+/* gdm_ewald_potential without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments and result (to FP64
+ * rounding: its k-vector table is built on the device over the full grid
+ * a = 0..k_max, b, c = -k_max..k_max, with zero weight outside the half space
+ * and the sphere), 1 <= k_max <= 32 (GDM_E_ARG above).  Its working memory is
+ * a fixed device array of the library (6.7 MB per GPU, held until the process
+ * ends) rather than context workspace; every call on one GPU shares it, so
+ * calls that overlap on one GPU (two streams, two contexts) race and must be
+ * ordered by the caller.  Enqueues kernels only (no host synchronisation,
+ * allocation or memset), so it may be captured into a hipGraph. */
+int gdm_ewald_potential_noalloc(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr,
+                                const int32_t* col, double rcut, double eta, int32_t k_max,
+                                const double hubbard_U[2], const double* tau, const double* q, double* V);
+
 /* Linear charge mixing of the SCC iteration, the scaled-delta kernel
  * K = -c I of the Shadow MD section: n <- n + mix (q0 - n), and the RMS of
  * the residual q0 - n before the update (HOST *rms_out).  n_vec, q0: [n].

@@ -86,6 +86,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     sig["gdm_debug_slot"] = (C.c_int, [P, C.c_int, C.c_int, P])
     sig["gdm_ewald_potential"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double),
                                             C.POINTER(C.c_double), P, P])
+    sig["gdm_ewald_potential_noalloc"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double),
+                                                    C.POINTER(C.c_double), P, P])
     sig["gdm_scc_mix"] = (C.c_int, [P, I32, P, P, D, C.POINTER(C.c_double)])
     sig["gdm_scc_anderson"] = (C.c_int, [P, I32, P, P, D, I32, I32, P, C.POINTER(C.c_double)])
     sig["gdm_set_response"] = (C.c_int, [P, C.c_int])
@@ -423,6 +425,16 @@ class Context:
         T = None if tau is None else (C.c_double * 2)(*[float(t) for t in tau])
         self._check(self.lib.gdm_ewald_potential(self.h, C.byref(system.struct()), _ptr(graph.row_ptr),
                                                  _ptr(graph.col), rcut, eta, int(k_max), U, T, _ptr(q), _ptr(V)))
+        return V
+
+    def ewald_potential_noalloc(self, system: System, graph: Graph, rcut: float, eta: float, k_max: int, hubbard_U,
+                               q, tau=None, out=None):
+        V = out if out is not None else torch.empty(system.n_atoms, dtype=torch.float64, device=self.dev)
+        U = (C.c_double * 2)(*[float(u) for u in hubbard_U])
+        T = None if tau is None else (C.c_double * 2)(*[float(t) for t in tau])
+        self._check(self.lib.gdm_ewald_potential_noalloc(self.h, C.byref(system.struct()), _ptr(graph.row_ptr),
+                                                         _ptr(graph.col), rcut, eta, int(k_max), U, T, _ptr(q),
+                                                         _ptr(V)))
         return V
 
     def scc_mix(self, n_vec, q0, mix: float) -> float:

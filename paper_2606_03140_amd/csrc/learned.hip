@@ -15,6 +15,7 @@
 #include "gdm_internal.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace {
 
@@ -364,6 +365,13 @@ __global__ void __launch_bounds__(256) k_ewald_sk(int n, const double* __restric
                                                  double* __restrict__ CS) {
     __shared__ double rc_[256], rs_[256];
     const double4 k = kv[blockIdx.x];
+    if (k.w == 0.0) {          // outside the k sphere (full-grid table): no contribution
+        if (threadIdx.x == 0) {
+            CS[2 * blockIdx.x] = 0.0;
+            CS[2 * blockIdx.x + 1] = 0.0;
+        }
+        return;
+    }
     double c = 0.0, s = 0.0;
     for (int j = threadIdx.x; j < n; j += 256) {
         const double ph = k.x * pos[3 * j] + k.y * pos[3 * j + 1] + k.z * pos[3 * j + 2];
@@ -399,6 +407,7 @@ __global__ void k_ewald_recip(int n, int nk, const double* __restrict__ pos, con
     double acc = 0.0;
     for (int k = 0; k < nk; ++k) {
         const double4 kk = kv[k];
+        if (kk.w == 0.0) continue;          // uniform over the wave
         const double ph = kk.x * pos[3 * i] + kk.y * pos[3 * i + 1] + kk.z * pos[3 * i + 2];
         double sn, cs;
         sincos(ph, &sn, &cs);
@@ -406,6 +415,24 @@ __global__ void k_ewald_recip(int n, int nk, const double* __restrict__ pos, con
     }
     const double self = -2.0 * eta / sqrt(M_PI) * q[i];
     V[i] = (species[i] == 0 ? U0 : U1) * q[i] + ke * (V[i] + 2.0 * acc + self);
+}
+
+// k-vector table over the full grid a = 0..K, b, c = -K..K (index
+// (a (2K+1) + b + K) (2K+1) + c + K), with the same half space and sphere
+// k^2 <= kc2 as the host-built table of gdm_ewald_potential; grid points
+// outside them get weight 0 (skipped by k_ewald_sk and k_ewald_recip).
+__global__ void k_ewald_ktable(int K, double Lx, double Ly, double Lz, double eta, double kc2, double V3,
+                               double4* __restrict__ kv) {
+    const int w = 2 * K + 1;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (K + 1) * w * w) return;
+    const int a = g / (w * w), b = (g / w) % w - K, c = g % w - K;
+    const double kx = 2 * M_PI * a / Lx, ky = 2 * M_PI * b / Ly, kz = 2 * M_PI * c / Lz;
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    double wt = 0.0;
+    if (!(a == 0 && (b < 0 || (b == 0 && c <= 0))) && !(k2 > kc2))
+        wt = 4.0 * M_PI / V3 * exp(-k2 / (4.0 * eta * eta)) / k2;
+    kv[g] = make_double4(kx, ky, kz, wt);
 }
 
 // n <- n + c (q0 - n); partial sums of (q0 - n)^2 per block
@@ -795,17 +822,25 @@ extern "C" int gdm_adam_step(gdm_ctx* ctx, int32_t n, float* params, const float
     return GDM_OK;
 }
 
+static int check_ewald(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, const int32_t* col, double rcut,
+                       double eta, int32_t k_max, int32_t k_max_limit, const double hubbard_U[2], const double* tau,
+                       const double* q, double* V, const char* who) {
+    int rc = check_ctx_sys(ctx, sys);
+    if (rc) return rc;
+    if (!row_ptr || !col || !q || !V || !hubbard_U || !(rcut > 0) || !(eta > 0) || k_max < 1 || k_max > k_max_limit)
+        return gdm_fail(ctx, GDM_E_ARG, "%s: bad argument (k_max %d, at most %d)", who, k_max, k_max_limit);
+    if (tau && !(tau[0] > 0 && tau[1] > 0)) return gdm_fail(ctx, GDM_E_ARG, "%s: tau must be positive", who);
+    for (int a = 0; a < 3; ++a)
+        if (sys->box[a] <= 2.0 * rcut) return gdm_fail(ctx, GDM_E_ARG, "%s: box must exceed 2 rcut", who);
+    return GDM_OK;
+}
+
 extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, const int32_t* col,
                                    double rcut, double eta, int32_t k_max, const double hubbard_U[2],
                                    const double* tau, const double* q, double* V) {
     if (!ctx) return GDM_E_ARG;
-    int rc = check_ctx_sys(ctx, sys);
+    int rc = check_ewald(ctx, sys, row_ptr, col, rcut, eta, k_max, 64, hubbard_U, tau, q, V, "gdm_ewald_potential");
     if (rc) return rc;
-    if (!row_ptr || !col || !q || !V || !hubbard_U || !(rcut > 0) || !(eta > 0) || k_max < 1 || k_max > 64)
-        return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_potential: bad argument");
-    if (tau && !(tau[0] > 0 && tau[1] > 0)) return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_potential: tau must be positive");
-    for (int a = 0; a < 3; ++a)
-        if (sys->box[a] <= 2.0 * rcut) return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_potential: box must exceed 2 rcut");
     // half space of k = 2 pi (a/Lx, b/Ly, c/Lz): (a > 0) or (a = 0, b > 0) or (a = b = 0, c > 0)
     const double V3 = sys->box[0] * sys->box[1] * sys->box[2];
     const double kc2 = std::pow(2.0 * M_PI * k_max / std::max(sys->box[0], std::max(sys->box[1], sys->box[2])), 2);
@@ -841,6 +876,72 @@ extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const in
     GDM_LAUNCH_CHECK(ctx);
     // keep the staging vector alive until the copy has been consumed
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GDM_OK;
+}
+
+// ------------------------------------------------ Ewald without allocation
+// Scratch of gdm_ewald_potential_noalloc: the k-vector table (one double4 per
+// point of the full (K+1)(2K+1)^2 grid) followed by the structure factors (two
+// doubles per point), for K <= kNoAllocKMax: 48 B per point, 6.7 MB at K = 32.
+// Every point is rewritten by each call, so nothing needs clearing.  One copy
+// per GPU, held until the process ends, shared by every call on that GPU.
+constexpr int kNoAllocKMax = 32;
+constexpr int64_t kNoAllocGrid = (int64_t)(kNoAllocKMax + 1) * (2 * kNoAllocKMax + 1) * (2 * kNoAllocKMax + 1);
+static __device__ __align__(256) double scratch[kNoAllocGrid * 6];
+
+// Device address of `scratch` on the context's device, looked up once per
+// device (the host-side name of the array is not a device address).
+static int scratch_ptr(gdm_ctx* ctx, double** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    if (ctx->device < 0 || ctx->device >= kMaxDevices)
+        return gdm_fail(ctx, GDM_E_ARG, "scratch: device %d out of range", ctx->device);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[ctx->device]) {
+        int cur = 0;
+        GDM_HIP(ctx, hipGetDevice(&cur));
+        if (cur != ctx->device) GDM_HIP(ctx, hipSetDevice(ctx->device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != ctx->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return gdm_hip(ctx, e, "hipGetSymbolAddress(scratch)");
+        ptr[ctx->device] = p;
+    }
+    *out = (double*)ptr[ctx->device];
+    return GDM_OK;
+}
+
+extern "C" int gdm_ewald_potential_noalloc(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr,
+                                           const int32_t* col, double rcut, double eta, int32_t k_max,
+                                           const double hubbard_U[2], const double* tau, const double* q, double* V) {
+    if (!ctx) return GDM_E_ARG;
+    int rc = check_ewald(ctx, sys, row_ptr, col, rcut, eta, k_max, kNoAllocKMax, hubbard_U, tau, q, V,
+                         "gdm_ewald_potential_noalloc");
+    if (rc) return rc;
+    double* sp = nullptr;
+    if ((rc = scratch_ptr(ctx, &sp))) return rc;
+    const int w = 2 * k_max + 1;
+    const int nk = (k_max + 1) * w * w;
+    double4* dkv = (double4*)sp;
+    double* CS = sp + 4 * (int64_t)nk;
+    const double V3 = sys->box[0] * sys->box[1] * sys->box[2];
+    const double kc2 = std::pow(2.0 * M_PI * k_max / std::max(sys->box[0], std::max(sys->box[1], sys->box[2])), 2);
+    const int n = sys->n_atoms;
+    const double3 L = make_double3(sys->box[0], sys->box[1], sys->box[2]);
+    const double3 iL = make_double3(sys->inv_box[0], sys->inv_box[1], sys->inv_box[2]);
+    GDM_TIMED(ctx, "ewald");
+    hipLaunchKernelGGL(k_ewald_ktable, dim3((nk + 255) / 256), dim3(256), 0, ctx->stream, k_max, sys->box[0],
+                       sys->box[1], sys->box[2], eta, kc2, V3, dkv);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos, sys->species, L,
+                       iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0, tau ? tau[1] : 0.0, q, V);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, q, dkv, CS);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_recip, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nk, sys->pos,
+                       sys->species, q, dkv, CS, eta, 14.399645, hubbard_U[0], hubbard_U[1], V);
+    GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }
 
