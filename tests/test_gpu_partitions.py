@@ -17,6 +17,8 @@ Adaption), each built by the oracle from its own solves.
   doublings than the benchmark).  The graph builder is fed the oracle's D
   bytes.  Same tolerances.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -55,10 +57,15 @@ def _same_subgraphs(part, subs):
 
 def _compare(c, sysm, part, H, S, ref, label, pipeline):
     # FP64 path, own mu
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     sol = pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.FP64_EIG)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
     err_d = max(np.abs(a - b).max() for a, b in zip(unpack_dcore(part.sg, sol.D_core), ref.d_core))
     err_q = np.abs(sol.q.cpu().numpy() - ref.q).max()
-    log(f"  {label} FP64: mu {sol.mu:.6f} (oracle {ref.mu:.6f}) max|dD| {err_d:.2e} max|dq| {err_q:.2e}")
+    log(f"  {label} FP64 ({dt:.2f} s with plan): mu {sol.mu:.6f} (oracle {ref.mu:.6f}) max|dD| {err_d:.2e} "
+        f"max|dq| {err_q:.2e}")
     assert abs(sol.n_count - sysm.n_electrons) <= 1e-9 * sysm.n_electrons
     assert err_d < 1e-9 and err_q < 1e-9
     # mixed path, own mu (cold start)
@@ -158,3 +165,45 @@ def test_md_regime_adaptive_partition_with_potentials(c):
     log(f"  {part.sg.n_sub} subgraphs, n {part.sg.norb.min()}-{part.sg.norb.max()}; oracle round 2 ...")
     ref = osv.solve_system(box.pos, box.species, L, m, subs1, V_atom=V)
     _compare(c, sysm, part, H, S, ref, "MD regime", pipeline)
+
+
+def test_batched_fp64_workload_adaptive_tau_1e5(c):
+    """The batched FP64 workload: 3,000 waters (seed 7), 5x5x6 = 150 cores of
+    about 20 waters, G_tau = (G^N G^D + G^D G^N)|_tau at tau = 1e-5 grown from
+    the neighbour partition's FP64 solve (the GPU uses its own D), giving
+    subgraphs of about 1,200-1,700 orbitals."""
+    from paper_2606_03140_amd import pipeline
+    nw, seed, grid, tau = 3000, 7, (5, 5, 6), 1e-5
+    log(f"batched FP64 workload: {nw} waters, cores {grid}, adaptive G_tau at {tau}")
+    box = waterbox.water_box(nw, seed)
+    L = box.box[0]
+    n_at = box.n_atoms
+    sysm = system_of(box)
+    tb = tb_params(False)
+    m = oracle_model(False)
+    rp0, col0 = om.neighbour_list_kdtree(box.pos, L)
+    core, nco = og.grid_cores(box.pos, box.anchor, L, grid)
+    subs0 = og.extract_subgraphs(rp0, col0, core, nco)
+    log("  oracle round 1 ...")
+    r1 = osv.solve_system(box.pos, box.species, L, m, subs0)
+    gd = og.condensed_dm(subs0, r1.d_core, box.species, n_at)
+    gn = og.distance_graph(box.pos, L, rp0, col0, 0.7)
+    (orp, ocol), w = og.graph_adaptive(gn, gd, tau)
+    subs1 = og.extract_subgraphs(orp, ocol, core, nco)
+    part = pipeline.cutoff_partition(c, sysm, tb, grid)
+    _same_subgraphs(part, subs0)
+    H, S = c.build_hs(sysm, tb, part.nbr)
+    sol = pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.FP64_EIG)
+    g = c.build_graph_dm(sysm, pipeline.GRAPH_ADAPTIVE, part.sg, sol.D_core, tau, alpha=0.7, nbr=part.nbr)
+    rp, col = csr_host(g)
+    diff = _edge_set(rp, col, n_at) ^ _edge_set(orp, ocol, n_at)
+    ties = _tie_pairs(w.data, w.row, w.col, tau, n_at)
+    log(f"  graph: edges gpu {len(col)} oracle {len(ocol)}, differing {len(diff)}, near ties {len(ties)}")
+    assert diff <= ties
+    assert not diff
+    part = pipeline.repartition(c, sysm, tb, part, g)
+    _same_subgraphs(part, subs1)
+    H, S = c.build_hs(sysm, tb, part.nbr)
+    log(f"  {part.sg.n_sub} subgraphs, n {part.sg.norb.min()}-{part.sg.norb.max()}; oracle round 2 ...")
+    ref = osv.solve_system(box.pos, box.species, L, m, subs1)
+    _compare(c, sysm, part, H, S, ref, "batched FP64 workload", pipeline)
