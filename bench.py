@@ -32,19 +32,36 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def dc_block_sum(n: int, leaf: int = 64) -> int:
+    """sum of k^2 over the blocks of every level of the divide-and-conquer
+    tree of an n x n tridiagonal (balanced cuts, leaves of at most 64 rows)."""
+    L = 0
+    while -(-n // (1 << L)) > leaf:
+        L += 1
+    tot = 0
+    for lev in range(L + 1):
+        b = [(i * n) >> lev for i in range((1 << lev) + 1)]
+        tot += sum((b[i + 1] - b[i]) ** 2 for i in range(1 << lev))
+    return tot
+
+
 def fp64_flops(n: np.ndarray, nc: np.ndarray) -> dict:
-    """Nominal FP64 flops of the executed route per subgraph:
-    Cholesky n^3/3, two triangular solves 2 n^3, tridiagonalisation 4/3 n^3,
-    core-row back-transforms O(nc n^2)."""
+    """Nominal FP64 flops of the executed route, summed over subgraphs:
+    Cholesky n^3/3, each triangular solve n^3, tridiagonalisation 4/3 n^3,
+    reflectors and forward substitution on the 2 nc core rows 5 nc n^2, the
+    divide-and-conquer products 2 R sum k^2 (R = 2 nc forward, nc reverse),
+    reverse reflectors and the solve with L 3 nc n^2."""
     n = n.astype(np.float64)
     nc = nc.astype(np.float64)
+    ks = np.array([dc_block_sum(int(v)) for v in n], dtype=np.float64)
     return {
         "potrf": float(np.sum(n ** 3 / 3)),
         "trsm": float(np.sum(n ** 3)),          # per launch (two launches)
         "sytrd": float(np.sum(4.0 * n ** 3 / 3)),
-        "core_rows": float(np.sum(8 * nc * n * n + 12 * 0.8 * n * n * 2 * nc)),
-        "dcore": float(np.sum(4 * nc * n * n + 6 * 0.8 * n * n * nc + nc * n * n)),
-        "total_nominal": float(np.sum(6.7 * n ** 3)),
+        "core_rows": float(np.sum(5 * nc * n * n)),
+        "dc_apply": float(np.sum(2 * 2 * nc * ks)),
+        "dc_apply_rev": float(np.sum(2 * nc * ks)),
+        "dcore": float(np.sum(3 * nc * n * n)),
     }
 
 
@@ -71,7 +88,8 @@ def time_path(ctx, system, part, H, S, kT, precision, steps, warmup, mu_guess=0.
     wall = time.perf_counter() - w0
     ms = t0.elapsed_time(t1) / steps
     prof = {}
-    for name in ("gather", "potrf", "trsm", "symmetrize", "sytrd", "steqr", "core_rows", "dcore", "mu",
+    for name in ("gather", "potrf", "trsm", "symmetrize", "sytrd", "dc_leaf", "dc_merge", "core_rows", "dc_apply",
+                 "core_weights", "dc_apply_rev", "dcore", "mu",
                  "mulliken", "foe_gemm", "ns_gemm", "mixed_misc", "refine64", "last64", "traces"):
         tot, n = ctx.profile_query(name)
         if n:
@@ -193,6 +211,58 @@ def time_graph(system, part, H, S, kT, steps, warmup, mu_start):
             c.close()
 
 
+BATCHED = dict(name="water3000", n_waters=3000, seed=7, grid=(5, 5, 6), tau=1e-5, kT=0.1, alpha=0.7)
+
+
+def fp64_roofline(prof: dict, ms: float, n: np.ndarray, nc: np.ndarray, steps: int) -> dict:
+    """The FP64 path against the FP64 peak: nominal flops of the route it
+    executes per step over the step time, and the dominant kernel."""
+    fl = fp64_flops(n, nc)
+    work = (fl["potrf"] + 2 * fl["trsm"] + fl["sytrd"] + fl["core_rows"] + fl["dc_apply"] + fl["dc_apply_rev"]
+            + fl["dcore"])
+    dom = max(prof.items(), key=lambda kv: kv[1]["ms_total"])
+    return {"bound": "fp64", "achieved": work / (ms * 1e-3) / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
+            "frac": work / (ms * 1e-3) / PEAK["fp64"], "flops_per_step": work, "dominant_kernel": dom[0],
+            "dominant_kernel_ms_per_step": dom[1]["ms_per_step"],
+            "note": "nominal flops of the executed route / step time"}
+
+
+def time_fp64_batched(steps: int, warmup: int):
+    """The batched FP64 workload: 3,000 waters, 5x5x6 cores, halos from the
+    adaptive graph G_tau (tau 1e-5) grown from the neighbour partition's FP64
+    solve: 150 subgraphs of about 1,200-1,700 orbitals, FP64 path only."""
+    import torch
+    import waterbox
+    from paper_2606_03140_amd import pipeline
+    from paper_2606_03140_amd._lib import Context, System, TBParams
+    wl = BATCHED
+    box = waterbox.water_box(wl["n_waters"], wl["seed"])
+    c = Context(0)
+    try:
+        system = System(box.pos, box.species, box.anchor, box.box)
+        tb = TBParams(orthogonal=False)
+        part = pipeline.cutoff_partition(c, system, tb, wl["grid"])
+        H, S = c.build_hs(system, tb, part.nbr)
+        sol = pipeline.solve(c, system, part, H, S, wl["kT"], pipeline.FP64_EIG)
+        g = c.build_graph_dm(system, pipeline.GRAPH_ADAPTIVE, part.sg, sol.D_core, wl["tau"], alpha=wl["alpha"],
+                             nbr=part.nbr)
+        part = pipeline.repartition(c, system, tb, part, g)
+        n, nc = part.sg.norb, part.sg.ncore_orb
+        log(f"[bench] batched FP64 workload: {part.sg.n_sub} subgraphs, n {n.min()}-{n.max()}; warmup {warmup}, "
+            f"steps {steps}")
+        sol, ms, wall, prof = time_path(c, system, part, H, S, wl["kT"], pipeline.FP64_EIG, steps, warmup)
+        return {"workload": f"{wl['name']}: {wl['n_waters']} waters, {system.n_orb} orbitals, non-orthogonal, kT "
+                            f"{wl['kT']} eV, {wl['grid'][0]}x{wl['grid'][1]}x{wl['grid'][2]} cores, adaptive G_tau at "
+                            f"tau {wl['tau']}",
+                "n_subgraphs": part.sg.n_sub, "orbitals_min": int(n.min()), "orbitals_max": int(n.max()),
+                "ms_per_step": ms, "solves_per_s": part.sg.n_sub / (ms * 1e-3), "mu": sol.mu,
+                "electron_count": sol.n_count,
+                "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
+                "roofline": fp64_roofline(prof, ms, n, nc, steps)}
+    finally:
+        c.close()
+
+
 def cpu_baseline(box, wl, max_seconds: float = 20.0):
     """The oracle (untuned) on a bounded sample of the same workload: it builds
     its own partition (neighbour list, cores, the same adaptive rounds), then
@@ -307,6 +377,8 @@ def main():
                     help="skip timing the whole mixed step as one captured hipGraph")
     ap.add_argument("--no-response", dest="response", action="store_false",
                     help="skip timing the charge response (the kernel-accelerated SCF's directional derivative)")
+    ap.add_argument("--no-batched", dest="batched", action="store_false",
+                    help="skip the batched FP64 workload (3,000 waters, adaptive graph at tau 1e-5)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes) and exit")
@@ -366,19 +438,8 @@ def main():
             log(f"[bench] {path} path unavailable: {e}")
 
     if "fp64" in results:
-        # the FP64 path against the FP64 matrix-core peak: nominal flops of the
-        # route it executes (Cholesky, two triangular solves, tridiagonal
-        # reduction, core-row back-transforms) per step over the step time
-        fl0 = fp64_flops(n, nc)
         r64 = results["fp64"]
-        work = fl0["potrf"] + 2 * fl0["trsm"] + fl0["sytrd"] + fl0["core_rows"] + fl0["dcore"]
-        dom = max(r64["kernels"].items(), key=lambda kv: kv[1]["ms_total"])
-        r64["roofline"] = {"bound": "fp64", "achieved": work / (r64["ms_per_step"] * 1e-3) / 1e12,
-                           "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
-                           "frac": work / (r64["ms_per_step"] * 1e-3) / PEAK["fp64"],
-                           "flops_per_step": work, "dominant_kernel": dom[0],
-                           "dominant_kernel_ms_per_step": dom[1]["ms_per_step"],
-                           "note": "nominal flops of the executed route / step time"}
+        r64["roofline"] = fp64_roofline(r64["kernels"], r64["ms_per_step"], n, nc, args.steps)
     head = "mixed" if "mixed" in results else "fp64"
     R = results[head]
     fl = fp64_flops(n, nc)
@@ -387,7 +448,7 @@ def main():
     kname, kinfo = kern
     avg_ms = kinfo["ms_total"] / kinfo["launches"]
     if head == "fp64":
-        work = fl.get(kname, fl["total_nominal"])
+        work = fl.get(kname, sum(fl.values()))
         roof = {"bound": "alu", "kernel": kname, "achieved": work / (avg_ms * 1e-3) / 1e12,
                 "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s", "traffic": None}
     else:
@@ -462,6 +523,9 @@ def main():
             gr["max_abs_dq_vs_eager_e"] = float(np.abs(q_graph - results["mixed"]["q"]).max())
             out["paths"]["mixed_graph"] = gr
             log(f"[bench] mixed hipGraph: {gr['ms_per_step']:.2f} ms/step")
+    if args.batched and "fp64" in paths:
+        out["paths"]["fp64_water3000"] = time_fp64_batched(min(args.steps, 3), min(args.warmup, 1))
+        log(f"[bench] batched FP64: {out['paths']['fp64_water3000']['ms_per_step']:.1f} ms/step")
     if args.response and "mixed" in results:
         log(f"[bench] timing the charge response: warmup {args.warmup}, steps {args.steps}")
         out["response"] = time_response(ctx, system, part, H, S, wl["kT"], args.steps, args.warmup,

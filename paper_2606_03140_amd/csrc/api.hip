@@ -198,22 +198,19 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         d.offc = P.totc;
         d.offd = P.totd;
         d.offe = P.tote;
-        d.offr = P.totr;
-        d.rot_cap = 2LL * n * n + 256;
         P.tot2 += (int64_t)d.ld * d.ld;
         P.totv += d.ld;
         P.totc += (int64_t)nc * d.ld;
         P.totd += (int64_t)nc * n;
         P.tote += n;
-        if (precision == GDM_FP64_EIG) P.totr += d.rot_cap;
         P.max_n = std::max(P.max_n, n);
         P.max_nc = std::max(P.max_nc, nc);
         P.max_natoms = std::max(P.max_natoms, d.natoms);
     }
     // release the other solver's exclusive workspace, so that switching
     // solvers on one context holds one solver's arena, not both
-    static const int kFp64Only[] = {BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W, BUF_ROTC, BUF_ROTS,
-                                    BUF_ROTI, BUF_ROTN, BUF_QC, BUF_MU, BUF_MUPART};
+    static const int kFp64Only[] = {BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W, BUF_DCU, BUF_DCAUX,
+                                    BUF_DCIDX, BUF_DCLIST, BUF_QC, BUF_QC2, BUF_MU, BUF_MUPART};
     static const int kMixedOnly[] = {BUF_X_F, BUF_X_HI, BUF_X_LO, BUF_GERSH, BUF_TR, BUF_NDBL, BUF_TILES,
                                      BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_MSTATE};
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -228,17 +225,19 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         gdm_buf(ctx, BUF_S, sizeof(double) * P.tot2, &ok);
         gdm_buf(ctx, BUF_L, sizeof(double) * P.tot2, &ok);
         for (int slot : {BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W}) gdm_buf(ctx, slot, sizeof(double) * P.totv, &ok);
-        gdm_buf(ctx, BUF_ROTC, sizeof(double) * P.totr, &ok);
-        gdm_buf(ctx, BUF_ROTS, sizeof(double) * P.totr, &ok);
-        gdm_buf(ctx, BUF_ROTI, sizeof(int32_t) * P.totr, &ok);
-        gdm_buf(ctx, BUF_ROTN, sizeof(int64_t) * 2 * ns, &ok);     // rotations and sweeps per subgraph
         gdm_buf(ctx, BUF_ORDER, sizeof(int32_t) * ns, &ok);        // longest first
         gdm_buf(ctx, BUF_QC, sizeof(double) * 2 * P.totc, &ok);
         gdm_buf(ctx, BUF_CC, sizeof(double) * P.totc, &ok);
         gdm_buf(ctx, BUF_MU, sizeof(double) * 8, &ok);
         gdm_buf(ctx, BUF_MUPART, sizeof(double) * 256 * (size_t)ns, &ok);
+        // workgroups take the subgraphs in decreasing size (ties by index)
+        P.order.resize(ns);
+        for (int s = 0; s < ns; ++s) P.order[s] = s;
+        std::stable_sort(P.order.begin(), P.order.end(), [&](int a, int b) { return P.n[a] > P.n[b]; });
         if (ok) {
-            const int rc = gdm_fp64_plan_lds(ctx);
+            int rc = gdm_dc_plan(ctx);
+            if (rc) return rc;
+            rc = gdm_fp64_plan_lds(ctx);
             if (rc) return rc;
         }
     } else {
@@ -248,10 +247,6 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_plan: workspace allocation failed");
     GDM_HIP(ctx, hipMemcpyAsync(desc, P.desc.data(), sizeof(SubDesc) * ns, hipMemcpyHostToDevice, ctx->stream));
     if (precision == GDM_FP64_EIG) {
-        // workgroups take the subgraphs in decreasing size (ties by index)
-        P.order.resize(ns);
-        for (int s = 0; s < ns; ++s) P.order[s] = s;
-        std::stable_sort(P.order.begin(), P.order.end(), [&](int a, int b) { return P.n[a] > P.n[b]; });
         GDM_HIP(ctx, hipMemcpyAsync(ctx->b[BUF_ORDER].p, P.order.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice,
                                     ctx->stream));
     }

@@ -1,11 +1,12 @@
 // FP64 subgraph solver ("direct diagonalization" option of the paper's
 // subgraph step): per subgraph
 //   s = L L^T (Cholesky),  h_perp = L^-1 h L^-T,  h_perp = Hh T Hh^T
-//   (Householder), T = R diag(lam) R^T (implicit QL, rotations recorded),
+//   (Householder), T = V_T diag(lam) V_T^T (divide and conquer, with V_T
+//   kept as block-diagonal factors; tridiag_dc.hip),
 // and only the 2*nc core rows are pushed through the reflectors and the
-// rotations:  C[core,:] = (L^-T)[core,:] Hh R,  Q[core,:] = I[core,:] Hh R,
+// factors:  C[core,:] = (L^-T)[core,:] Hh V_T,  Q[core,:] = I[core,:] Hh V_T,
 //   w_k = sum_{a in core} C_ak (L Q)_ak            (core electron weights)
-//   D[core,:] = (C[core,:] diag(f) R^T Hh^T) L^-1  (collected core rows, Eq. 3)
+//   D[core,:] = (C[core,:] diag(f) V_T^T Hh^T) L^-1  (collected core rows, Eq. 3)
 // so after the O(n^3) reductions everything is O(nc n^2).
 // The basis Z = L^-T gives the same D as Z = s^-1/2 (any Z with Z Z^T = s^-1).
 // Workgroups take subgraphs longest first (order[], by n), so the largest
@@ -400,133 +401,17 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
     }
 }
 
-// ---------------------------------------------------- implicit QL (steqr)
-// One lane per subgraph iterates on d, e held in LDS (the classic implicit QL
-// iteration with a Wilkinson-type shift from the leading 2 x 2 block; a
-// published method, e.g. Golub & Van Loan, "Matrix Computations", section on
-// the symmetric QR algorithm, in its QL form).  Every sweep is a chain of
-// plane rotations on consecutive index pairs (i, i+1), i = top, top-1, ...,
-// acting on columns as  z_i' = c z_i - s z_{i+1},  z_{i+1}' = s z_i + c z_{i+1};
-// (c, s) of each rotation is appended to the record and each sweep as (top,
-// count) to the sweep list, in application order.  sqrt(f^2 + g^2) and one
-// reciprocal replace hypot and two divisions on the serial chain (hypot only
-// where the squares could underflow), and d[i-1], e[i-1] are loaded one step
-// ahead of their use.
-__global__ void __launch_bounds__(64) k_steqr(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
-                                             const double* __restrict__ Dg, const double* __restrict__ Eg,
-                                             double* __restrict__ Lam, double* __restrict__ RotC,
-                                             double* __restrict__ RotS, int32_t* __restrict__ Sweep,
-                                             int64_t* __restrict__ RotN, int* __restrict__ status) {
-    extern __shared__ double sm[];
-    const int sub = sub_of_block(order);
-    const SubDesc dsc = desc[sub];
-    const int n = dsc.n;
-    double* d = sm;
-    double* e = sm + n;
-    for (int i = threadIdx.x; i < n; i += 64) {
-        d[i] = Dg[dsc.offv + i];
-        e[i] = Eg[dsc.offv + i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double* rc = RotC + dsc.offr;
-        double* rs = RotS + dsc.offr;
-        int32_t* sw = Sweep + dsc.offr;
-        const int64_t cap = dsc.rot_cap;
-        const int64_t scap = dsc.rot_cap / 2;
-        int64_t nrot = 0, nsw = 0, nkept = 0;
-        bool bad = false, full = false;
-        e[n - 1] = 0.0;
-        const double eps = 1.1102230246251565e-16;
-        for (int l = 0; l < n && !bad; ++l) {
-            int iter = 0;
-            for (;;) {
-                int m = l;
-                for (; m < n - 1; ++m) {
-                    const double dd = fabs(d[m]) + fabs(d[m + 1]);
-                    if (fabs(e[m]) <= eps * dd) break;
-                }
-                if (m == l) break;
-                if (++iter > 60) {
-                    bad = true;
-                    gdm_raise(status, GDM_STATUS_NOT_CONVERGED);
-                    break;
-                }
-                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = hypot(g, 1.0);
-                g = d[m] - d[l] + e[l] / (g + copysign(r, g));
-                double s = 1.0, c = 1.0, p = 0.0;
-                bool underflow = false;
-                const int64_t r0 = nrot;
-                double di1 = d[m], di = d[m - 1], ei = e[m - 1];
-                for (int i = m - 1; i >= l; --i) {
-                    const double en = i > l ? e[i - 1] : 0.0, dn = i > l ? d[i - 1] : 0.0;
-                    const double f = s * ei;
-                    const double b = c * ei;
-                    r = (fabs(f) + fabs(g) > 1e-140) ? sqrt(f * f + g * g) : hypot(f, g);
-                    e[i + 1] = r;
-                    if (r == 0.0) {
-                        d[i + 1] = di1 - p;
-                        e[m] = 0.0;
-                        underflow = true;
-                        break;
-                    }
-                    const double ir = 1.0 / r;
-                    s = f * ir;
-                    c = g * ir;
-                    g = di1 - p;
-                    r = (di - g) * s + 2.0 * c * b;
-                    p = s * r;
-                    d[i + 1] = g + p;
-                    g = c * r - b;
-                    if (nrot < cap) {
-                        rc[nrot] = c;
-                        rs[nrot] = s;
-                    }
-                    ++nrot;
-                    di1 = di;
-                    di = dn;
-                    ei = en;
-                }
-                if (nrot > r0) {
-                    // a sweep is kept only whole; after the first one that does
-                    // not fit, nothing more is recorded (status: capacity)
-                    if (!full && nrot <= cap && nsw < scap) {
-                        sw[2 * nsw] = m - 1;
-                        sw[2 * nsw + 1] = (int32_t)(nrot - r0);
-                        ++nsw;
-                        nkept = nrot;
-                    } else {
-                        full = true;
-                    }
-                }
-                if (underflow) continue;
-                d[l] -= p;
-                e[l] = g;
-                e[m] = 0.0;
-            }
-        }
-        if (full) gdm_raise(status, GDM_STATUS_CAPACITY);
-        RotN[2 * sub] = nkept;
-        RotN[2 * sub + 1] = nsw;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += 64) Lam[dsc.offv + i] = d[i];
-}
-
-// --------------------------------------- core rows through Hh and R
+// --------------------------------------- core rows through Hh
 // The 2*nc rows to be transformed (rows 0..nc-1 start as I[core,:], rows
 // nc..2nc-1 as (L^-T)[core,:]) are independent, so they are processed in
 // chunks held in LDS: block (s, c) takes rows c*RC .. of subgraph s, one lane
 // per row (one wave per workgroup), row stride n + 1 doubles.  Each row is
 // initialised (unit row, or forward substitution L y = e_c), multiplied by the
-// reflectors H_0 ... H_{n-3} and the recorded QL rotations in order, and
-// written to G in the column-interleaved layout G[i*R + r] (R = 2*nc).
-// Reflector vectors, rows of L and rotation coefficients are staged through a
-// fixed LDS area (coalesced loads by the wave, broadcast reads); the dot
-// products use four accumulators; a sweep of rotations keeps the element it
-// carries from one rotation to the next in a register and loads the row
-// elements three rotations ahead (no rotation of the chain writes them first).
+// reflectors H_0 ... H_{n-3} in order, and written in the column-interleaved
+// layout G[i*R + r] (R = 2*nc) to the buffer the divide-and-conquer products
+// start from.  Reflector vectors and rows of L are staged through a fixed LDS
+// area (coalesced loads by the wave, broadcast reads); the dot products use
+// four accumulators.
 constexpr int kStage = 1024;                // doubles of the staging area (8 KB)
 constexpr int kRowLds = 136 * 1024;         // LDS bytes for one chunk of rows
 constexpr int kRowThreads = 64;
@@ -578,100 +463,11 @@ __device__ void reflect_rows(double* row, bool act, int off, int m, const double
     }
 }
 
-// Apply the recorded QL rotations to this lane's row: forward (FWD, sweeps in
-// order, each from its top index down) or transposed in reverse order (each
-// sweep from its bottom index up, z_i' = c z_i + s z_{i+1},
-// z_{i+1}' = -s z_i + c z_{i+1}).  Coefficients are staged in kStage / 2
-// pairs; the carried element stays in a register and the next three row
-// elements of the chain are loaded ahead.
-template <bool FWD>
-__device__ void apply_rotations(double* row, bool act, int n, const double* __restrict__ rc,
-                                const double* __restrict__ rs, const int32_t* __restrict__ sw, int64_t nrot,
-                                int64_t nsw, double* stg) {
-    const int lane = threadIdx.x;
-    constexpr int kPairs = kStage / 2;
-    double* sc = stg;
-    double* ss = stg + kPairs;
-    int64_t qbase = FWD ? 0 : nrot;          // first rotation index of the current sweep
-    for (int64_t k = 0; k < nsw; ++k) {
-        const int64_t ks = FWD ? k : nsw - 1 - k;
-        const int top = sw[2 * ks], cnt = sw[2 * ks + 1];
-        if (!FWD) qbase -= cnt;
-        const int64_t q0 = qbase;
-        if (FWD) qbase += cnt;
-        // chain over cnt rotations; FWD: i = top .. top-cnt+1; reverse: i = top-cnt+1 .. top
-        const int i0 = FWD ? top : top - cnt + 1;
-        double lo = 0.0, hi = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-        if (act) {
-            if (FWD) {
-                hi = row[i0 + 1];
-                lo = row[i0];
-                p1 = i0 - 1 >= 0 ? row[i0 - 1] : 0.0;
-                p2 = i0 - 2 >= 0 ? row[i0 - 2] : 0.0;
-                p3 = i0 - 3 >= 0 ? row[i0 - 3] : 0.0;
-            } else {
-                lo = row[i0];
-                hi = row[i0 + 1];
-                p1 = i0 + 2 < n ? row[i0 + 2] : 0.0;
-                p2 = i0 + 3 < n ? row[i0 + 3] : 0.0;
-                p3 = i0 + 4 < n ? row[i0 + 4] : 0.0;
-            }
-        }
-        for (int j0 = 0; j0 < cnt; j0 += kPairs) {
-            const int jm = min(kPairs, cnt - j0);
-            __syncthreads();
-            for (int t = lane; t < jm; t += kRowThreads) {
-                // j-th rotation of the chain in application order
-                const int64_t q = FWD ? q0 + j0 + t : q0 + cnt - 1 - (j0 + t);
-                sc[t] = rc[q];
-                ss[t] = rs[q];
-            }
-            __syncthreads();
-            if (act) {
-                for (int t = 0; t < jm; ++t) {
-                    const int j = j0 + t;
-                    const double c = sc[t], s = ss[t];
-                    if (FWD) {
-                        const int i = top - j;                  // rotation (i, i+1); hi = z_{i+1}, lo = z_i
-                        const double nlo = c * lo - s * hi, nhi = s * lo + c * hi;
-                        const int pf = i - 4;
-                        const double nxt = pf >= 0 ? row[pf] : 0.0;     // loaded before the write below (pf < i)
-                        row[i + 1] = nhi;
-                        hi = nlo;
-                        lo = p1;
-                        p1 = p2;
-                        p2 = p3;
-                        p3 = nxt;
-                    } else {
-                        const int i = top - cnt + 1 + j;        // rotation (i, i+1), transposed
-                        const double nlo = c * lo + s * hi, nhi = -s * lo + c * hi;
-                        const int pf = i + 5;
-                        const double nxt = pf < n ? row[pf] : 0.0;      // pf > i + 1
-                        row[i] = nlo;
-                        lo = nhi;
-                        hi = p1;
-                        p1 = p2;
-                        p2 = p3;
-                        p3 = nxt;
-                    }
-                }
-            }
-        }
-        if (act) {
-            if (FWD) row[top - cnt + 1] = hi;        // the carried z_i of the last rotation
-            else row[top + 1] = lo;                  // the carried z_{i+1}
-        }
-    }
-}
-
 __global__ void __launch_bounds__(kRowThreads) k_core_rows(const SubDesc* __restrict__ desc,
                                                       const int32_t* __restrict__ order,
                                                       const double* __restrict__ Lm, const double* __restrict__ A,
-                                                      const double* __restrict__ Tau,
-                                                      const double* __restrict__ RotC,
-                                                      const double* __restrict__ RotS,
-                                                      const int32_t* __restrict__ Sweep,
-                                                      const int64_t* __restrict__ RotN, double* __restrict__ G) {
+                                                      const double* __restrict__ Tau, double* __restrict__ G,
+                                                      double* __restrict__ G2) {
     extern __shared__ double rows[];
     __shared__ double stg[kStage];
     const int sub = sub_of_block(order);
@@ -714,9 +510,8 @@ __global__ void __launch_bounds__(kRowThreads) k_core_rows(const SubDesc* __rest
         if (t == 0.0) continue;
         reflect_rows(row, act, k + 1, n - k - 1, a + (int64_t)k * ld + k + 1, t, stg);
     }
-    apply_rotations<true>(row, act, n, RotC + d.offr, RotS + d.offr, Sweep + d.offr, RotN[2 * sub],
-                          RotN[2 * sub + 1], stg);
-    double* g = G + 2 * d.offc;
+    // into the buffer the leaf level of the divide-and-conquer products reads
+    double* g = (((d.dc_depth + 1) & 1) ? G2 : G) + 2 * d.offc;
     for (int i = 0; i < n; ++i)
         if (act) g[(int64_t)i * R + r] = row[i];
 }
@@ -754,25 +549,40 @@ __device__ __forceinline__ double fermi_fp64(double x, double beta) {
     return 1.0 / (1.0 + e);
 }
 
-// Core rows r < nc in LDS chunks as above: u = C[r,:] diag(f), then
-// u <- u R^T (rotations in reverse order, transposed), u <- u H_{n-3} ... H_0,
-// and D[r,:] from D L = u by columns from the right (D_j = u_j / L_jj, then
-// u_i -= D_j L_ji for i < j, row j of L staged), written row-wise.
+// u = C[core,:] diag(f) (eigenvector order), into the half of the density
+// row buffer that the first (top-level) transposed product reads; the
+// eigenvalues are copied out when asked for.
+__global__ void __launch_bounds__(kThreads) k_dcore_init(const SubDesc* __restrict__ desc,
+                                                        const int32_t* __restrict__ order,
+                                                        const double* __restrict__ G, const double* __restrict__ Lam,
+                                                        double mu_host, const double* __restrict__ mu_dev, double beta,
+                                                        double* __restrict__ Y, double* __restrict__ EigOut) {
+    const double mu = mu_dev ? *mu_dev : mu_host;      // mu from device memory when given
+    const SubDesc d = desc[sub_of_block(order)];
+    const int n = d.n, nc = d.nc, R2 = 2 * nc;
+    const double* g = G + 2 * d.offc;
+    double* y = Y + 2 * d.offc + (((d.dc_depth + 1) & 1) ? (int64_t)nc * d.ld : 0);
+    for (int k = blockIdx.y; k < n; k += gridDim.y) {
+        const double f = fermi_fp64(Lam[d.offv + k] - mu, beta);
+        for (int r = threadIdx.x; r < nc; r += kThreads) y[(int64_t)k * nc + r] = g[(int64_t)k * R2 + nc + r] * f;
+        if (EigOut && threadIdx.x == 0) EigOut[d.offe + k] = Lam[d.offv + k];
+    }
+}
+
+// Core rows r < nc in LDS chunks as above: u = (C[core,:] diag(f) V_T^T)[r,:]
+// from the density row buffer, u <- u H_{n-3} ... H_0, and D[r,:] from
+// D L = u by columns from the right (D_j = u_j / L_jj, then u_i -= D_j L_ji
+// for i < j, row j of L staged), written row-wise.
 __global__ void __launch_bounds__(kRowThreads) k_dcore(const SubDesc* __restrict__ desc,
                                                   const int32_t* __restrict__ order,
                                                   const double* __restrict__ Lm, const double* __restrict__ A,
-                                                  const double* __restrict__ Tau, const double* __restrict__ RotC,
-                                                  const double* __restrict__ RotS, const int32_t* __restrict__ Sweep,
-                                                  const int64_t* __restrict__ RotN, const double* __restrict__ G,
-                                                  const double* __restrict__ Lam, double mu_host,
-                                                  const double* __restrict__ mu_dev, double beta,
-                                                  double* __restrict__ Dout, double* __restrict__ EigOut) {
+                                                  const double* __restrict__ Tau, const double* __restrict__ Y,
+                                                  double* __restrict__ Dout) {
     extern __shared__ double rows[];
     __shared__ double stg[kStage];
-    const double mu = mu_dev ? *mu_dev : mu_host;      // mu from device memory when given
     const int sub = sub_of_block(order);
     const SubDesc d = desc[sub];
-    const int n = d.n, nc = d.nc, ld = d.ld, R2 = 2 * nc;
+    const int n = d.n, nc = d.nc, ld = d.ld;
     const int RC = chunk_rows(n), S = n + 1;
     const int r0 = blockIdx.y * RC;
     if (r0 >= nc) return;
@@ -782,13 +592,9 @@ __global__ void __launch_bounds__(kRowThreads) k_dcore(const SubDesc* __restrict
     const int r = r0 + lane;
     double* row = rows + (int64_t)(act ? lane : 0) * S;
     const double* l = Lm + d.off2;
-    const double* g = G + 2 * d.offc;
-    if (EigOut && blockIdx.y == 0)
-        for (int k = lane; k < n; k += kRowThreads) EigOut[d.offe + k] = Lam[d.offv + k];
+    const double* y = Y + 2 * d.offc;
     for (int k = 0; k < n; ++k)
-        if (act) row[k] = g[(int64_t)k * R2 + nc + r] * fermi_fp64(Lam[d.offv + k] - mu, beta);
-    apply_rotations<false>(row, act, n, RotC + d.offr, RotS + d.offr, Sweep + d.offr, RotN[2 * sub],
-                           RotN[2 * sub + 1], stg);
+        if (act) row[k] = y[(int64_t)k * nc + r];
     const double* a = A + d.off2;
     const double* tau = Tau + d.offv;
     for (int k = n - 3; k >= 0; --k) {
@@ -966,7 +772,6 @@ int gdm_fp64_plan_lds(gdm_ctx* ctx) {
     int rc;
     if ((rc = set_lds(ctx, (const void*)k_potrf, L.n))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * L.n))) return rc;
-    if ((rc = set_lds(ctx, (const void*)k_steqr, 2 * L.n))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_core_rows, L.core_rows))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_mu_partial, 2 * L.n))) return rc;
     return set_lds(ctx, (const void*)k_dcore, L.dcore);
@@ -987,11 +792,8 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     double* Tau = (double*)ctx->b[BUF_TAU].p;
     double* Lam = (double*)ctx->b[BUF_LAM].p;
     double* Wt = (double*)ctx->b[BUF_W].p;
-    double* RotC = (double*)ctx->b[BUF_ROTC].p;
-    double* RotS = (double*)ctx->b[BUF_ROTS].p;
-    int32_t* RotI = (int32_t*)ctx->b[BUF_ROTI].p;
-    int64_t* RotN = (int64_t*)ctx->b[BUF_ROTN].p;
     double* G = (double*)ctx->b[BUF_QC].p;
+    double* G2 = (double*)ctx->b[BUF_QC2].p;
     double* state = (double*)ctx->b[BUF_MU].p;
     double* partial = (double*)ctx->b[BUF_MUPART].p;
     const int orth = S == nullptr;
@@ -1023,20 +825,19 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     hipLaunchKernelGGL(k_sytrd, dim3(ns), dim3(kTrd), 2 * lds_n, ctx->stream, desc, order, A, T, Dg, Eg, Tau);
     }
     GDM_LAUNCH_CHECK(ctx);
-    if ((rc = set_lds(ctx, (const void*)k_steqr, 2 * lds_n))) return rc;
-    { GDM_TIMED(ctx, "steqr");
-    hipLaunchKernelGGL(k_steqr, dim3(ns), dim3(64), 2 * lds_n, ctx->stream, desc, order, Dg, Eg, Lam, RotC, RotS,
-                       RotI, RotN, ctx->d_status);
-    }
-    GDM_LAUNCH_CHECK(ctx);
+    if ((rc = gdm_dc_solve(ctx))) return rc;
     {
         const size_t lds_rows = L.core_rows;
         const int chunks = L.core_chunks;
         if ((rc = set_lds(ctx, (const void*)k_core_rows, lds_rows))) return rc;
-        GDM_TIMED(ctx, "core_rows");
-        hipLaunchKernelGGL(k_core_rows, dim3(ns, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, order, Sd,
-                           A, Tau, RotC, RotS, RotI, RotN, G);
+        {
+            GDM_TIMED(ctx, "core_rows");
+            hipLaunchKernelGGL(k_core_rows, dim3(ns, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, order,
+                               Sd, A, Tau, G, G2);
+        }
         GDM_LAUNCH_CHECK(ctx);
+        if ((rc = gdm_dc_apply(ctx, 0))) return rc;
+        GDM_TIMED(ctx, "core_weights");
         hipLaunchKernelGGL(k_core_weights, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, Sd, G, Wt);
     }
     GDM_LAUNCH_CHECK(ctx);
@@ -1082,18 +883,26 @@ int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const dou
                      double* D_core, double* eig_out) {
     Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
+    const int32_t* order = (const int32_t*)ctx->b[BUF_ORDER].p;
+    double* Y = (double*)ctx->b[BUF_QC2].p;
     int rc;
+    {
+        GDM_TIMED(ctx, "dcore");
+        hipLaunchKernelGGL(k_dcore_init, dim3(P.n_sub, 32), dim3(kThreads), 0, ctx->stream, desc, order,
+                           (const double*)ctx->b[BUF_QC].p, (const double*)ctx->b[BUF_LAM].p, mu, mu_dev, 1.0 / kT, Y,
+                           eig_out);
+    }
+    GDM_LAUNCH_CHECK(ctx);
+    if ((rc = gdm_dc_apply(ctx, 1))) return rc;
     const Fp64Lds L = fp64_lds(P);
     const size_t lds_rows = L.dcore;
     const int chunks = L.dcore_chunks;
     if ((rc = set_lds(ctx, (const void*)k_dcore, lds_rows))) return rc;
-    { GDM_TIMED(ctx, "dcore");
-    hipLaunchKernelGGL(k_dcore, dim3(P.n_sub, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc,
-                       (const int32_t*)ctx->b[BUF_ORDER].p, (const double*)ctx->b[BUF_S].p, (const double*)ctx->b[BUF_A].p, (const double*)ctx->b[BUF_TAU].p,
-                       (const double*)ctx->b[BUF_ROTC].p, (const double*)ctx->b[BUF_ROTS].p,
-                       (const int32_t*)ctx->b[BUF_ROTI].p, (const int64_t*)ctx->b[BUF_ROTN].p,
-                       (const double*)ctx->b[BUF_QC].p, (const double*)ctx->b[BUF_LAM].p, mu, mu_dev, 1.0 / kT, D_core,
-                       eig_out);
+    {
+        GDM_TIMED(ctx, "dcore");
+        hipLaunchKernelGGL(k_dcore, dim3(P.n_sub, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, order,
+                           (const double*)ctx->b[BUF_S].p, (const double*)ctx->b[BUF_A].p,
+                           (const double*)ctx->b[BUF_TAU].p, (const double*)Y, D_core);
     }
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;

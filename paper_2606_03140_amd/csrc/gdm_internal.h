@@ -24,14 +24,27 @@ struct SubDesc {
     int32_t natoms;   // atoms (core + halo)
     int32_t ncore_atoms;
     int32_t atom0;    // offset into the packed atom list
+    int32_t dc_depth; // FP64 path: levels of the divide-and-conquer tree (leaves at this level)
+    int32_t pad_;
     int64_t off2;     // offset of the ld*ld tiles
     int64_t offv;     // offset of length-ld vectors
     int64_t offc;     // offset of nc*ld core blocks
     int64_t offd;     // offset of the packed D core rows (nc*n)
     int64_t offe;     // offset of packed eigenvalues (n)
-    int64_t offr;     // offset of the rotation record
-    int64_t rot_cap;  // rotation record capacity
 };
+
+// FP64 path, tridiagonal divide and conquer: a leaf or merge block [lo, hi)
+// of one subgraph at one tree level (merge: children [lo, mid), [mid, hi)),
+// and one 64 x 64 tile of the products with its factor.
+struct DcNode {
+    int32_t sub, lo, mid, hi, level, pad_;
+    int64_t offu;     // offset of the block's k x k factor
+};
+struct DcTile {
+    int32_t sub, lo, k, level, r0, c0;
+    int64_t offu;
+};
+constexpr int kDcMaxRows = 2048;   // largest subgraph of the FP64 path (LDS of one merge)
 
 struct DevBuf {
     void* p = nullptr;
@@ -44,9 +57,17 @@ struct Plan {
     std::vector<int32_t> n, nc;
     std::vector<SubDesc> desc;
     std::vector<int32_t> order;     // subgraph processing order (largest first)
-    int64_t tot2 = 0, totv = 0, totc = 0, totd = 0, tote = 0, totr = 0;
+    int64_t tot2 = 0, totv = 0, totc = 0, totd = 0, tote = 0;
     int32_t max_n = 0, max_nc = 0, max_natoms = 0;
     int generation = 0;
+    // FP64 path: divide-and-conquer work lists (leaves, then merges by round;
+    // product tiles forward and reverse by round)
+    std::vector<DcNode> dc_nodes;
+    std::vector<DcTile> dc_tiles;
+    std::vector<int> dc_round, dc_fwd, dc_rev;
+    int dc_max_depth = 0;
+    int64_t dc_totu = 0;
+    size_t dc_merge_lds = 0, dc_tiles_off = 0;
 };
 
 struct ProfRec {
@@ -119,7 +140,7 @@ struct GdmTimed {
 // Buffer slots.
 enum {
     BUF_DESC = 0, BUF_ORDER, BUF_A, BUF_S, BUF_L, BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W,
-    BUF_ROTC, BUF_ROTS, BUF_ROTI, BUF_ROTN, BUF_QC, BUF_CC, BUF_MU, BUF_MUPART,
+    BUF_DCU, BUF_DCAUX, BUF_DCIDX, BUF_DCLIST, BUF_QC, BUF_QC2, BUF_CC, BUF_MU, BUF_MUPART,
     BUF_G_CELL, BUF_G_CELLCNT, BUF_G_CELLSTART, BUF_G_CELLATOMS, BUF_G_CNT, BUF_G_TMP,
     BUF_G_FLAGS, BUF_G_COUNTS, BUF_G_SCAN, BUF_G_TOTAL, BUF_G_W,
     BUF_X_HI, BUF_X_LO, BUF_X_F, BUF_Y_HI, BUF_Y_LO, BUF_Y_F, BUF_T_HI, BUF_T_LO, BUF_T_F,
@@ -165,6 +186,14 @@ int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const dou
                      double* D_core, double* eig_out);
 // raise the dynamic-LDS attributes the FP64 kernels need for the current plan
 int gdm_fp64_plan_lds(gdm_ctx* ctx);
+// tridiagonal divide and conquer (FP64 path): work lists and workspace at
+// plan time; eigenvalues and factors from the tridiagonal (BUF_D, BUF_E);
+// products of the core rows with the eigenvector matrix (reverse: with its
+// transpose)
+int gdm_dc_depth(int n);
+int gdm_dc_plan(gdm_ctx* ctx);
+int gdm_dc_solve(gdm_ctx* ctx);
+int gdm_dc_apply(gdm_ctx* ctx, int reverse);
 int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,
                       const int32_t* row_ptr, const int32_t* col, int64_t nnz,
                       const double* H, const double* S, double n_e, double kT,
