@@ -198,11 +198,13 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         d.offc = P.totc;
         d.offd = P.totd;
         d.offe = P.tote;
+        d.offt = P.tott;
         P.tot2 += (int64_t)d.ld * d.ld;
         P.totv += d.ld;
         P.totc += (int64_t)nc * d.ld;
         P.totd += (int64_t)nc * n;
         P.tote += n;
+        P.tott += 4096LL * std::max(0, (n - 2 + 63) / 64);
         P.max_n = std::max(P.max_n, n);
         P.max_nc = std::max(P.max_nc, nc);
         P.max_natoms = std::max(P.max_natoms, d.natoms);
@@ -210,7 +212,8 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
     // release the other solver's exclusive workspace, so that switching
     // solvers on one context holds one solver's arena, not both
     static const int kFp64Only[] = {BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W, BUF_DCU, BUF_DCAUX,
-                                    BUF_DCIDX, BUF_DCLIST, BUF_QC, BUF_QC2, BUF_MU, BUF_MUPART};
+                                    BUF_DCIDX, BUF_DCLIST, BUF_QC, BUF_QC2, BUF_HT, BUF_MU,
+                                    BUF_MUPART};
     static const int kMixedOnly[] = {BUF_X_F, BUF_X_HI, BUF_X_LO, BUF_GERSH, BUF_TR, BUF_NDBL, BUF_TILES,
                                      BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_MSTATE};
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -227,6 +230,7 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         for (int slot : {BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W}) gdm_buf(ctx, slot, sizeof(double) * P.totv, &ok);
         gdm_buf(ctx, BUF_ORDER, sizeof(int32_t) * ns, &ok);        // longest first
         gdm_buf(ctx, BUF_QC, sizeof(double) * 2 * P.totc, &ok);
+        gdm_buf(ctx, BUF_HT, sizeof(double) * (size_t)std::max<int64_t>(P.tott, 1), &ok);
         gdm_buf(ctx, BUF_CC, sizeof(double) * P.totc, &ok);
         gdm_buf(ctx, BUF_MU, sizeof(double) * 8, &ok);
         gdm_buf(ctx, BUF_MUPART, sizeof(double) * 256 * (size_t)ns, &ok);

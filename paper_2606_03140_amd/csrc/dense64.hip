@@ -3,8 +3,8 @@
 //   s = L L^T (Cholesky),  h_perp = L^-1 h L^-T,  h_perp = Hh T Hh^T
 //   (Householder), T = V_T diag(lam) V_T^T (divide and conquer, with V_T
 //   kept as block-diagonal factors; tridiag_dc.hip),
-// and only the 2*nc core rows are pushed through the reflectors and the
-// factors:  C[core,:] = (L^-T)[core,:] Hh V_T,  Q[core,:] = I[core,:] Hh V_T,
+// and only the 2*nc core rows are pushed through the reflectors (64 at a
+// time in compact WY form) and the factors:  C[core,:] = (L^-T)[core,:] Hh V_T,  Q[core,:] = I[core,:] Hh V_T,
 //   w_k = sum_{a in core} C_ak (L Q)_ak            (core electron weights)
 //   D[core,:] = (C[core,:] diag(f) V_T^T Hh^T) L^-1  (collected core rows, Eq. 3)
 // so after the O(n^3) reductions everything is O(nc n^2).
@@ -401,119 +401,236 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
     }
 }
 
-// --------------------------------------- core rows through Hh
-// The 2*nc rows to be transformed (rows 0..nc-1 start as I[core,:], rows
-// nc..2nc-1 as (L^-T)[core,:]) are independent, so they are processed in
-// chunks held in LDS: block (s, c) takes rows c*RC .. of subgraph s, one lane
-// per row (one wave per workgroup), row stride n + 1 doubles.  Each row is
-// initialised (unit row, or forward substitution L y = e_c), multiplied by the
-// reflectors H_0 ... H_{n-3} in order, and written in the column-interleaved
-// layout G[i*R + r] (R = 2*nc) to the buffer the divide-and-conquer products
-// start from.  Reflector vectors and rows of L are staged through a fixed LDS
-// area (coalesced loads by the wave, broadcast reads); the dot products use
-// four accumulators.
-constexpr int kStage = 1024;                // doubles of the staging area (8 KB)
-constexpr int kRowLds = 136 * 1024;         // LDS bytes for one chunk of rows
-constexpr int kRowThreads = 64;
+// --------------------------------------- core rows through Hh (blocked)
+// Rows of the core-row matrix are independent, so workgroup (s, t) owns rows
+// 64 t .. 64 t + 63 of subgraph s across all n columns (column-interleaved
+// layout X[j*R + r]) and works on them in 64 x 64 tiles:
+//   * rows nc..2nc-1 start as (L^-T)[core,:], i.e. x L^T = e: by column
+//     blocks B, rhs = e_B - X[:, <B] L[B, <B]^T (tile products), then a
+//     forward substitution with the 64 x 64 diagonal block of L in LDS;
+//     rows 0..nc-1 are unit rows;
+//   * the reflectors are applied 64 at a time in compact WY form,
+//     H_k0 ... H_k0+63 = I - V T V^T (T upper triangular, k_house_t):
+//     X[:, k0+1:] -= ((X[:, k0+1:] V) T) V^T.
+// The density rows reverse both: Y <- Y (I - V T^T V^T) for the blocks in
+// reverse order, then D L = Y by column blocks from the right.
+constexpr int kBk = 64;          // tile edge, reflectors per block
+constexpr int kBkK = 16;         // depth of one staged slice of a tile product
+constexpr int kBkS = kBk + 1;    // padded LDS row
 
-__host__ __device__ inline int chunk_rows(int n) {
-    const int r = kRowLds / (8 * (n + 1));
-    return r > kRowThreads ? kRowThreads : (r < 1 ? 1 : r);
-}
+struct SliceLds {
+    double a[kBkK][kBkS];
+    double b[kBkK][kBkS];
+};
+union BlockLds {
+    SliceLds s;
+    double m[kBk][kBkS];         // a 64 x 64 block (diagonal block of L, or T)
+};
+constexpr size_t kRowsLds = sizeof(double) * kBk * kBkS + sizeof(BlockLds);
 
-// x[0..m) . v[0..m), v in LDS (broadcast), four accumulators
-__device__ __forceinline__ double dot_lds(const double* x, const double* v, int m) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int i = 0;
-    for (; i + 3 < m; i += 4) {
-        a0 += x[i] * v[i];
-        a1 += x[i + 1] * v[i + 1];
-        a2 += x[i + 2] * v[i + 2];
-        a3 += x[i + 3] * v[i + 3];
-    }
-    for (; i < m; ++i) a0 += x[i] * v[i];
-    return (a0 + a1) + (a2 + a3);
-}
-
-// row[off .. off+m) <- (I - t v v^T) row, v = (1, vk[1..m-1]) read from global
-// and staged through `stg` in pieces of kStage (the whole wave takes part)
-__device__ void reflect_rows(double* row, bool act, int off, int m, const double* __restrict__ vk, double t,
-                             double* stg) {
-    const int lane = threadIdx.x;
-    double dot = 0.0;
-    for (int c0 = 0; c0 < m; c0 += kStage) {
-        const int cm = min(kStage, m - c0);
-        __syncthreads();
-        for (int i = lane; i < cm; i += kRowThreads) stg[i] = (c0 + i == 0) ? 1.0 : vk[c0 + i];
-        __syncthreads();
-        if (act) dot += dot_lds(row + off + c0, stg, cm);
-    }
-    dot *= t;
-    for (int c0 = 0; c0 < m; c0 += kStage) {
-        const int cm = min(kStage, m - c0);
-        if (m > kStage) {
-            __syncthreads();
-            for (int i = lane; i < cm; i += kRowThreads) stg[i] = (c0 + i == 0) ? 1.0 : vk[c0 + i];
-            __syncthreads();
-        }
-        if (act) {
-            double* x = row + off + c0;
-            for (int i = 0; i < cm; ++i) x[i] -= dot * stg[i];
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kRowThreads) k_core_rows(const SubDesc* __restrict__ desc,
-                                                      const int32_t* __restrict__ order,
-                                                      const double* __restrict__ Lm, const double* __restrict__ A,
-                                                      const double* __restrict__ Tau, double* __restrict__ G,
-                                                      double* __restrict__ G2) {
-    extern __shared__ double rows[];
-    __shared__ double stg[kStage];
-    const int sub = sub_of_block(order);
-    const SubDesc d = desc[sub];
-    const int n = d.n, nc = d.nc, ld = d.ld, R = 2 * nc;
-    const int RC = chunk_rows(n), S = n + 1;
-    const int r0 = blockIdx.y * RC;
-    if (r0 >= R) return;
-    const int nr = min(RC, R - r0);
-    const int lane = threadIdx.x;
-    const bool act = lane < nr;
-    const int r = r0 + lane;
-    double* row = rows + (int64_t)(act ? lane : 0) * S;
-    const double* l = Lm + d.off2;
-    // initial rows: unit rows, or columns of L^-1 by forward substitution
-    // (y_k = 0 for k < c); row i of L staged in LDS
-    if (act)
-        for (int i = 0; i < n; ++i) row[i] = (r < nc && i == r) ? 1.0 : 0.0;
-    const int cmin = max(r0, nc) - nc;                    // smallest core column in this chunk
-    if (r0 + nr > nc)
-        for (int i = cmin; i < n; ++i) {
-            for (int c0 = 0; c0 <= i; c0 += kStage) {
-                const int cm = min(kStage, i + 1 - c0);
-                __syncthreads();
-                for (int k = lane; k < cm; k += kRowThreads) stg[k] = l[(int64_t)i * ld + c0 + k];
-                __syncthreads();
-                if (act && r >= nc && i >= r - nc) {
-                    // acc over k < i of this piece; the diagonal divides at the end
-                    const int kend = min(cm, i - c0);
-                    const double part = kend > 0 ? dot_lds(row + c0, stg, kend) : 0.0;
-                    row[i] = (c0 == 0 ? (i == r - nc ? 1.0 : 0.0) : row[i]) - part;
-                    if (c0 + cm == i + 1) row[i] /= stg[cm - 1];
-                }
+// acc[i][j] (rows tr + 16 i, columns tc + 16 j of a 64 x 64 tile, tr = tid % 16,
+// tc = tid / 16) += sum_{t < K} fa(r, t) fb(t, c).  fa / fb return 0 outside
+// their operands; AT / BT: the loaders' contiguous index is t (else r / c).
+template <bool AT, bool BT, class FA, class FB>
+__device__ __forceinline__ void tile_mm(double (&acc)[4][4], int K, FA fa, FB fb, SliceLds& L) {
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+    for (int t0 = 0; t0 < K; t0 += kBkK) {
+        for (int e = tid; e < kBk * kBkK; e += 256) {
+            int rr, tt;
+            if (AT) {
+                tt = e & (kBkK - 1);
+                rr = e >> 4;
+            } else {
+                rr = e & (kBk - 1);
+                tt = e >> 6;
             }
+            L.a[tt][rr] = t0 + tt < K ? fa(rr, t0 + tt) : 0.0;
         }
+        for (int e = tid; e < kBk * kBkK; e += 256) {
+            int cc, tt;
+            if (BT) {
+                tt = e & (kBkK - 1);
+                cc = e >> 4;
+            } else {
+                cc = e & (kBk - 1);
+                tt = e >> 6;
+            }
+            L.b[tt][cc] = t0 + tt < K ? fb(t0 + tt, cc) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tt = 0; tt < kBkK; ++tt) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = L.a[tt][tr + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = L.b[tt][tc + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+}
+
+// element j of reflector k: 0 above k+1, 1 at k+1, A[k][j] below
+__device__ __forceinline__ double refl(const double* __restrict__ a, int ld, int n, int k, int j) {
+    return j <= k || j >= n ? 0.0 : (j == k + 1 ? 1.0 : a[(int64_t)k * ld + j]);
+}
+
+// T of each block of 64 reflectors (forward accumulation): T_ii = tau_i,
+// T[0:i, i] = -tau_i T[0:i, 0:i] (V^T V)[0:i, i].  Stored 64 x 64 row-major
+// at offt + 4096 b (zero outside the block's reflectors).
+__global__ void __launch_bounds__(256) k_house_t(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                                const double* __restrict__ A, const double* __restrict__ Tau,
+                                                double* __restrict__ Tm) {
+    extern __shared__ double lds[];
+    double (*G)[kBkS] = (double (*)[kBkS])lds;        // V^T V
+    BlockLds& bl = *(BlockLds*)(lds + kBk * kBkS);     // slices, then T
+    double (*T)[kBkS] = bl.m;
+    const SubDesc d = desc[sub_of_block(order)];
+    const int n = d.n, ld = d.ld, nr = n - 2;
+    const int k0 = kBk * blockIdx.y;
+    if (k0 >= nr) return;
+    const int nb = min(kBk, nr - k0);
     const double* a = A + d.off2;
     const double* tau = Tau + d.offv;
-    for (int k = 0; k < n - 2; ++k) {
-        const double t = tau[k];
-        if (t == 0.0) continue;
-        reflect_rows(row, act, k + 1, n - k - 1, a + (int64_t)k * ld + k + 1, t, stg);
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+    double acc[4][4];
+    zero_acc(acc);
+    auto vt = [&](int q, int t) { return q < nb ? refl(a, ld, n, k0 + q, k0 + 1 + t) : 0.0; };
+    tile_mm<true, true>(acc, n - k0 - 1, vt, [&](int t, int q) { return vt(q, t); }, bl.s);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) G[tr + 16 * i][tc + 16 * j] = acc[i][j];
+    for (int e = tid; e < kBk * kBk; e += 256) T[e >> 6][e & 63] = 0.0;
+    __syncthreads();
+    for (int i = 0; i < nb; ++i) {
+        double v = 0.0;
+        if (tid < i)
+            for (int p = tid; p < i; ++p) v += T[tid][p] * G[p][i];
+        __syncthreads();
+        if (tid < i) T[tid][i] = -tau[k0 + i] * v;
+        if (tid == i) T[i][i] = tau[k0 + i];
+        __syncthreads();
     }
+    double* out = Tm + d.offt + (int64_t)kBk * kBk * blockIdx.y;
+    for (int e = tid; e < kBk * kBk; e += 256) out[e] = T[e >> 6][e & 63];
+}
+
+// Y[:, k0+1:] <- Y[:, k0+1:] (I - V T' V^T) for one row tile (T' = T, or T^T
+// when TRANS), Y column-interleaved with leading dimension R.
+template <bool TRANS>
+__device__ void apply_block(double* __restrict__ Y, int R, int r0, int n, const double* __restrict__ a, int ld,
+                            int k0, int nb, const double* __restrict__ Tb, double (*W)[kBkS], BlockLds& bl) {
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+    const int m = n - k0 - 1;
+    auto xa = [&](int r, int t) { return r0 + r < R ? Y[(int64_t)(k0 + 1 + t) * R + r0 + r] : 0.0; };
+    auto vb = [&](int t, int q) { return q < nb ? refl(a, ld, n, k0 + q, k0 + 1 + t) : 0.0; };
+    double acc[4][4];
+    zero_acc(acc);
+    tile_mm<false, true>(acc, m, xa, vb, bl.s);                     // P = Y V
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) W[tr + 16 * i][tc + 16 * j] = acc[i][j];
+    __syncthreads();
+    zero_acc(acc);
+    if (TRANS)
+        tile_mm<false, true>(acc, kBk, [&](int r, int t) { return W[r][t]; },
+                             [&](int t, int c) { return Tb[c * kBk + t]; }, bl.s);
+    else
+        tile_mm<false, false>(acc, kBk, [&](int r, int t) { return W[r][t]; },
+                              [&](int t, int c) { return Tb[t * kBk + c]; }, bl.s);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) W[tr + 16 * i][tc + 16 * j] = acc[i][j];
+    __syncthreads();
+    for (int c0 = 0; c0 < m; c0 += kBk) {                              // Y -= (P T') V^T
+        zero_acc(acc);
+        tile_mm<false, false>(acc, nb, [&](int r, int t) { return W[r][t]; },
+                              [&](int t, int c) { return c0 + c < m ? refl(a, ld, n, k0 + t, k0 + 1 + c0 + c) : 0.0; },
+                              bl.s);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + tc + 16 * j;
+            if (c >= m) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + tr + 16 * i;
+                if (r < R) Y[(int64_t)(k0 + 1 + c) * R + r] -= acc[i][j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_core_rows(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                                  const double* __restrict__ Lm, const double* __restrict__ A,
+                                                  const double* __restrict__ Tm, double* __restrict__ G,
+                                                  double* __restrict__ G2) {
+    extern __shared__ double lds[];
+    double (*W)[kBkS] = (double (*)[kBkS])lds;
+    BlockLds& bl = *(BlockLds*)(lds + kBk * kBkS);
+    const SubDesc d = desc[sub_of_block(order)];
+    const int n = d.n, nc = d.nc, ld = d.ld, R = 2 * nc;
+    const int r0 = kBk * blockIdx.y;
+    if (r0 >= R) return;
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+    const double* l = Lm + d.off2;
+    const double* a = A + d.off2;
     // into the buffer the leaf level of the divide-and-conquer products reads
-    double* g = (((d.dc_depth + 1) & 1) ? G2 : G) + 2 * d.offc;
-    for (int i = 0; i < n; ++i)
-        if (act) g[(int64_t)i * R + r] = row[i];
+    double* X = (((d.dc_depth + 1) & 1) ? G2 : G) + 2 * d.offc;
+    auto xa = [&](int r, int t) { return r0 + r < R ? X[(int64_t)t * R + r0 + r] : 0.0; };
+    for (int b0 = 0; b0 < n; b0 += kBk) {
+        const int bw = min(kBk, n - b0);
+        double acc[4][4];
+        zero_acc(acc);
+        if (b0 > 0)
+            tile_mm<false, true>(acc, b0, xa, [&](int t, int c) { return c < bw ? l[(int64_t)(b0 + c) * ld + t] : 0.0; },
+                                 bl.s);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = r0 + tr + 16 * i, c = b0 + tc + 16 * j;
+                W[tr + 16 * i][tc + 16 * j] = (r >= nc && c == r - nc ? 1.0 : 0.0) - acc[i][j];
+            }
+        for (int e = tid; e < kBk * kBk; e += 256) {
+            const int i = e >> 6, j = e & 63;
+            bl.m[i][j] = (i < bw && j <= i) ? l[(int64_t)(b0 + i) * ld + b0 + j] : 0.0;
+        }
+        __syncthreads();
+        if (tid < kBk) {
+            const int r = r0 + tid;
+            double* w = W[tid];
+            if (r >= nc && r < R)
+                for (int i = 0; i < bw; ++i) {
+                    double v = w[i];
+                    for (int p = 0; p < i; ++p) v -= bl.m[i][p] * w[p];
+                    w[i] = v / bl.m[i][i];
+                }
+        }
+        __syncthreads();
+        for (int e = tid; e < kBk * kBk; e += 256) {
+            const int c = e >> 6, rr = e & 63, r = r0 + rr;
+            if (c < bw && r < R) X[(int64_t)(b0 + c) * R + r] = r < nc ? (b0 + c == r ? 1.0 : 0.0) : W[rr][c];
+        }
+        __syncthreads();
+    }
+    const int nr = n - 2;
+    for (int k0 = 0; k0 < nr; k0 += kBk)
+        apply_block<false>(X, R, r0, n, a, ld, k0, min(kBk, nr - k0), Tm + d.offt + (int64_t)k0 * kBk, W, bl);
 }
 
 // w_k = sum_{a<nc} C[a][k] * (L_cc Q_core)[a][k]: the core weight of
@@ -569,59 +686,67 @@ __global__ void __launch_bounds__(kThreads) k_dcore_init(const SubDesc* __restri
     }
 }
 
-// Core rows r < nc in LDS chunks as above: u = (C[core,:] diag(f) V_T^T)[r,:]
-// from the density row buffer, u <- u H_{n-3} ... H_0, and D[r,:] from
-// D L = u by columns from the right (D_j = u_j / L_jj, then u_i -= D_j L_ji
-// for i < j, row j of L staged), written row-wise.
-__global__ void __launch_bounds__(kRowThreads) k_dcore(const SubDesc* __restrict__ desc,
-                                                  const int32_t* __restrict__ order,
-                                                  const double* __restrict__ Lm, const double* __restrict__ A,
-                                                  const double* __restrict__ Tau, const double* __restrict__ Y,
-                                                  double* __restrict__ Dout) {
-    extern __shared__ double rows[];
-    __shared__ double stg[kStage];
-    const int sub = sub_of_block(order);
-    const SubDesc d = desc[sub];
+// Density rows r < nc, one row tile per workgroup: u = (C[core,:] diag(f)
+// V_T^T)[tile,:] in the density row buffer, u <- u H_{n-3} ... H_0 (blocks of
+// reflectors in reverse order, T transposed), then D from D L = u by column
+// blocks from the right: rhs = u[:, B] - D[:, >B] L[>B, B] (tile products),
+// then a backward substitution with the diagonal block of L; D written
+// row-wise (nc x n).
+__global__ void __launch_bounds__(256) k_dcore(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                              const double* __restrict__ Lm, const double* __restrict__ A,
+                                              const double* __restrict__ Tm, double* __restrict__ Y,
+                                              double* __restrict__ Dout) {
+    extern __shared__ double lds[];
+    double (*W)[kBkS] = (double (*)[kBkS])lds;
+    BlockLds& bl = *(BlockLds*)(lds + kBk * kBkS);
+    const SubDesc d = desc[sub_of_block(order)];
     const int n = d.n, nc = d.nc, ld = d.ld;
-    const int RC = chunk_rows(n), S = n + 1;
-    const int r0 = blockIdx.y * RC;
+    const int r0 = kBk * blockIdx.y;
     if (r0 >= nc) return;
-    const int nr = min(RC, nc - r0);
-    const int lane = threadIdx.x;
-    const bool act = lane < nr;
-    const int r = r0 + lane;
-    double* row = rows + (int64_t)(act ? lane : 0) * S;
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
     const double* l = Lm + d.off2;
-    const double* y = Y + 2 * d.offc;
-    for (int k = 0; k < n; ++k)
-        if (act) row[k] = y[(int64_t)k * nc + r];
     const double* a = A + d.off2;
-    const double* tau = Tau + d.offv;
-    for (int k = n - 3; k >= 0; --k) {
-        const double t = tau[k];
-        if (t == 0.0) continue;
-        reflect_rows(row, act, k + 1, n - k - 1, a + (int64_t)k * ld + k + 1, t, stg);
-    }
-    // D L = u by columns from the right
-    for (int j = n - 1; j >= 0; --j) {
-        for (int c0 = 0; c0 <= j; c0 += kStage) {
-            const int cm = min(kStage, j + 1 - c0);
-            __syncthreads();
-            for (int k = lane; k < cm; k += kRowThreads) stg[k] = l[(int64_t)j * ld + c0 + k];
-            __syncthreads();
-            if (act) {
-                const double dj = row[j] / l[(int64_t)j * ld + j];
-                const int kend = min(cm, j - c0);
-                double* x = row + c0;
-                for (int k = 0; k < kend; ++k) x[k] -= dj * stg[k];
-                if (c0 + cm == j + 1) row[j] = dj;
+    double* y = Y + 2 * d.offc;
+    const int nr = n - 2;
+    for (int k0 = (nr - 1) / kBk * kBk; nr > 0 && k0 >= 0; k0 -= kBk)
+        apply_block<true>(y, nc, r0, n, a, ld, k0, min(kBk, nr - k0), Tm + d.offt + (int64_t)k0 * kBk, W, bl);
+    double* D = Dout + d.offd;
+    const int nbc = (n + kBk - 1) / kBk;
+    for (int bi = nbc - 1; bi >= 0; --bi) {
+        const int b0 = bi * kBk, bw = min(kBk, n - b0), b1 = b0 + bw;
+        double acc[4][4];
+        zero_acc(acc);
+        if (b1 < n)
+            tile_mm<true, false>(acc, n - b1,
+                                 [&](int r, int t) { return r0 + r < nc ? D[(int64_t)(r0 + r) * n + b1 + t] : 0.0; },
+                                 [&](int t, int c) { return c < bw ? l[(int64_t)(b1 + t) * ld + b0 + c] : 0.0; }, bl.s);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = r0 + tr + 16 * i, c = tc + 16 * j;
+                W[tr + 16 * i][c] = (r < nc && c < bw ? y[(int64_t)(b0 + c) * nc + r] : 0.0) - acc[i][j];
+            }
+        for (int e = tid; e < kBk * kBk; e += 256) {
+            const int i = e >> 6, j = e & 63;
+            bl.m[i][j] = (i < bw && j <= i) ? l[(int64_t)(b0 + i) * ld + b0 + j] : 0.0;
+        }
+        __syncthreads();
+        if (tid < kBk && r0 + tid < nc) {
+            double* w = W[tid];
+            for (int j = bw - 1; j >= 0; --j) {
+                double v = w[j];
+                for (int i = j + 1; i < bw; ++i) v -= w[i] * bl.m[i][j];
+                w[j] = v / bl.m[j][j];
             }
         }
+        __syncthreads();
+        for (int e = tid; e < kBk * kBk; e += 256) {
+            const int rr = e >> 6, c = e & 63, r = r0 + rr;
+            if (c < bw && r < nc) D[(int64_t)r * n + b0 + c] = W[rr][c];
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    double* out = Dout + d.offd;
-    for (int rr = 0; rr < nr; ++rr)
-        for (int jj = lane; jj < n; jj += kRowThreads) out[(int64_t)(r0 + rr) * n + jj] = rows[(int64_t)rr * S + jj];
 }
 
 // ------------------------------------------------ chemical potential
@@ -746,24 +871,19 @@ static int set_lds(gdm_ctx* ctx, const void* fn, size_t bytes) {
 }
 
 // LDS bytes of the FP64 kernels for a plan: one matrix row or column
-// (lds_n), the core-row kernel's row chunks and the density kernel's.
+// (lds_n); the row-tile kernels use a fixed kRowsLds.  Grid extents: row
+// tiles of the 2 nc core rows and of the nc density rows, reflector blocks.
 struct Fp64Lds {
-    size_t n = 0, core_rows = 0, dcore = 0;
-    int core_chunks = 1, dcore_chunks = 1;
+    size_t n = 0;
+    int core_tiles = 1, dcore_tiles = 1, refl_blocks = 1;
 };
 
 static Fp64Lds fp64_lds(const Plan& P) {
     Fp64Lds L;
     L.n = sizeof(double) * (size_t)P.max_n;
-    for (int s = 0; s < P.n_sub; ++s) {
-        const SubDesc& dd = P.desc[s];
-        const int rcn = chunk_rows(dd.n);
-        const size_t rows = sizeof(double) * (size_t)rcn * (dd.n + 1);
-        L.core_rows = std::max(L.core_rows, rows);
-        L.dcore = std::max(L.dcore, rows);
-        L.core_chunks = std::max(L.core_chunks, (2 * dd.nc + rcn - 1) / rcn);
-        L.dcore_chunks = std::max(L.dcore_chunks, (dd.nc + rcn - 1) / rcn);
-    }
+    L.core_tiles = (2 * P.max_nc + kBk - 1) / kBk;
+    L.dcore_tiles = (P.max_nc + kBk - 1) / kBk;
+    L.refl_blocks = std::max(1, (P.max_n - 2 + kBk - 1) / kBk);
     return L;
 }
 
@@ -772,9 +892,10 @@ int gdm_fp64_plan_lds(gdm_ctx* ctx) {
     int rc;
     if ((rc = set_lds(ctx, (const void*)k_potrf, L.n))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * L.n))) return rc;
-    if ((rc = set_lds(ctx, (const void*)k_core_rows, L.core_rows))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_house_t, kRowsLds))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_core_rows, kRowsLds))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_mu_partial, 2 * L.n))) return rc;
-    return set_lds(ctx, (const void*)k_dcore, L.dcore);
+    return set_lds(ctx, (const void*)k_dcore, kRowsLds);
 }
 
 int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg, const int32_t* row_ptr,
@@ -826,17 +947,18 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     }
     GDM_LAUNCH_CHECK(ctx);
     if ((rc = gdm_dc_solve(ctx))) return rc;
+    double* Tm = (double*)ctx->b[BUF_HT].p;
     {
-        const size_t lds_rows = L.core_rows;
-        const int chunks = L.core_chunks;
-        if ((rc = set_lds(ctx, (const void*)k_core_rows, lds_rows))) return rc;
-        {
-            GDM_TIMED(ctx, "core_rows");
-            hipLaunchKernelGGL(k_core_rows, dim3(ns, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, order,
-                               Sd, A, Tau, G, G2);
-        }
+        GDM_TIMED(ctx, "core_rows");
+        hipLaunchKernelGGL(k_house_t, dim3(ns, L.refl_blocks), dim3(256), kRowsLds, ctx->stream, desc, order, A, Tau,
+                           Tm);
         GDM_LAUNCH_CHECK(ctx);
-        if ((rc = gdm_dc_apply(ctx, 0))) return rc;
+        hipLaunchKernelGGL(k_core_rows, dim3(ns, L.core_tiles), dim3(256), kRowsLds, ctx->stream, desc, order, Sd, A,
+                           Tm, G, G2);
+    }
+    GDM_LAUNCH_CHECK(ctx);
+    if ((rc = gdm_dc_apply(ctx, 0))) return rc;
+    {
         GDM_TIMED(ctx, "core_weights");
         hipLaunchKernelGGL(k_core_weights, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, Sd, G, Wt);
     }
@@ -895,14 +1017,11 @@ int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const dou
     GDM_LAUNCH_CHECK(ctx);
     if ((rc = gdm_dc_apply(ctx, 1))) return rc;
     const Fp64Lds L = fp64_lds(P);
-    const size_t lds_rows = L.dcore;
-    const int chunks = L.dcore_chunks;
-    if ((rc = set_lds(ctx, (const void*)k_dcore, lds_rows))) return rc;
     {
         GDM_TIMED(ctx, "dcore");
-        hipLaunchKernelGGL(k_dcore, dim3(P.n_sub, chunks), dim3(kRowThreads), lds_rows, ctx->stream, desc, order,
+        hipLaunchKernelGGL(k_dcore, dim3(P.n_sub, L.dcore_tiles), dim3(256), kRowsLds, ctx->stream, desc, order,
                            (const double*)ctx->b[BUF_S].p, (const double*)ctx->b[BUF_A].p,
-                           (const double*)ctx->b[BUF_TAU].p, (const double*)Y, D_core);
+                           (const double*)ctx->b[BUF_HT].p, Y, D_core);
     }
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;

@@ -31,6 +31,7 @@ struct SubDesc {
     int64_t offc;     // offset of nc*ld core blocks
     int64_t offd;     // offset of the packed D core rows (nc*n)
     int64_t offe;     // offset of packed eigenvalues (n)
+    int64_t offt;     // FP64 path: offset of the 64 x 64 T factors of the reflector blocks
 };
 
 // FP64 path, tridiagonal divide and conquer: a leaf or merge block [lo, hi)
@@ -57,7 +58,7 @@ struct Plan {
     std::vector<int32_t> n, nc;
     std::vector<SubDesc> desc;
     std::vector<int32_t> order;     // subgraph processing order (largest first)
-    int64_t tot2 = 0, totv = 0, totc = 0, totd = 0, tote = 0;
+    int64_t tot2 = 0, totv = 0, totc = 0, totd = 0, tote = 0, tott = 0;
     int32_t max_n = 0, max_nc = 0, max_natoms = 0;
     int generation = 0;
     // FP64 path: divide-and-conquer work lists (leaves, then merges by round;
@@ -140,7 +141,7 @@ struct GdmTimed {
 // Buffer slots.
 enum {
     BUF_DESC = 0, BUF_ORDER, BUF_A, BUF_S, BUF_L, BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W,
-    BUF_DCU, BUF_DCAUX, BUF_DCIDX, BUF_DCLIST, BUF_QC, BUF_QC2, BUF_CC, BUF_MU, BUF_MUPART,
+    BUF_DCU, BUF_DCAUX, BUF_DCIDX, BUF_DCLIST, BUF_QC, BUF_QC2, BUF_HT, BUF_CC, BUF_MU, BUF_MUPART,
     BUF_G_CELL, BUF_G_CELLCNT, BUF_G_CELLSTART, BUF_G_CELLATOMS, BUF_G_CNT, BUF_G_TMP,
     BUF_G_FLAGS, BUF_G_COUNTS, BUF_G_SCAN, BUF_G_TOTAL, BUF_G_W,
     BUF_X_HI, BUF_X_LO, BUF_X_F, BUF_Y_HI, BUF_Y_LO, BUF_Y_F, BUF_T_HI, BUF_T_LO, BUF_T_F,
