@@ -319,18 +319,39 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
             __syncthreads();
             for (int i = threadIdx.x; i < m; i += kTrd) v[i] = i == 0 ? 1.0 : v[i] * scale;
             __syncthreads();
-            // p = A22 v, A22 = A[k+1:, k+1:] as at the panel's start; one wave per row
-            for (int i = wave; i < m; i += kTrd / 64) {
-                const double* ri = a + (int64_t)(k + 1 + i) * ld + (k + 1);
-                double a0 = 0.0, a1 = 0.0;
-                int c = lane;
-                for (; c + 64 < m; c += 128) {
-                    a0 += ri[c] * v[c];
-                    a1 += ri[c + 64] * v[c + 64];
+            // p = A22 v, A22 = A[k+1:, k+1:] as at the panel's start (symmetric):
+            // thread t accumulates columns t, t + kTrd, ... over all rows, so
+            // every load is a coalesced piece of a row and the loads of
+            // successive rows are independent (many in flight per thread)
+            for (int c0 = threadIdx.x; c0 < m; c0 += 2 * kTrd) {
+                const int c1 = c0 + kTrd;
+                const bool two = c1 < m;
+                const double* col = a + (int64_t)(k + 1) * ld + (k + 1);
+                double s0 = 0.0, s1 = 0.0, u0 = 0.0, u1 = 0.0;
+                int i = 0;
+                for (; i + 7 < m; i += 8) {
+                    double x[8], y[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const double* rq = col + (int64_t)(i + q) * ld;
+                        x[q] = rq[c0];
+                        y[q] = two ? rq[c1] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; q += 2) {
+                        s0 += x[q] * v[i + q];
+                        s1 += x[q + 1] * v[i + q + 1];
+                        u0 += y[q] * v[i + q];
+                        u1 += y[q + 1] * v[i + q + 1];
+                    }
                 }
-                if (c < m) a0 += ri[c] * v[c];
-                const double acc = gdm_wave_sum(a0 + a1);
-                if (lane == 0) p[i] = acc;
+                for (; i < m; ++i) {
+                    const double* r0 = col + (int64_t)i * ld;
+                    s0 += r0[c0] * v[i];
+                    if (two) u0 += r0[c1] * v[i];
+                }
+                p[c0] = s0 + s1;
+                if (two) p[c1] = u0 + u1;
             }
             // W^T v and V^T v over rows k+1.. (one wave per panel column)
             for (int l = wave; l < 2 * j; l += kTrd / 64) {
