@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(kThreads) k_symmetrize(const SubDesc* __restri
 // panel's earlier steps, A - V W^T - W V^T, are applied on the fly to the
 // column being reduced and to the product p = A22 v; w = tau p - tau^2/2
 // (p^T v) v.  The trailing matrix takes the whole panel's rank-2nb update
-// once, in 32 x 32 tiles with the panel rows of V and W staged in LDS.  So
+// once (64-row chunks, waves on 64-column strips).  So
 // the trailing matrix is read once per column (the product) and read and
 // written once per panel, instead of read twice and written once per column.
 // V and W live column-major (n x nb each) in the subgraph's scratch tile W2
@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
     extern __shared__ double sm[];
     __shared__ double red[kTrd / 64];
     __shared__ double corr[4 * kPanel];     // V[k,:], W[k,:], W^T v, V^T v of the current step
-    __shared__ double tV[2][32][kPanel + 1], tW[2][32][kPanel + 1];   // trailing-update staging (rows, cols)
+    __shared__ double sVr[64][kPanel + 1], sWr[64][kPanel + 1];   // trailing update: rows of V, W
     const SubDesc dsc = desc[sub_of_block(order)];
     const int n = dsc.n, ld = dsc.ld;
     double* a = A + dsc.off2;
@@ -383,29 +383,37 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
             }
             __syncthreads();
         }
-        // trailing update of rows and columns >= kend: A -= V W^T + W V^T
-        const int m2 = n - kend;
-        const int nt = (m2 + 31) / 32;
-        for (int tile = 0; tile < nt * nt; ++tile) {
-            const int ti = tile / nt, tj = tile % nt;
-            const int rb = kend + 32 * ti, cb = kend + 32 * tj;
+        // trailing update of rows and columns >= kend: A -= V W^T + W V^T.
+        // Rows go in chunks of 64 whose rows of V and W are staged in LDS;
+        // each wave takes 64-column strips (lane = column, the strip's rows
+        // of V and W in registers) down the chunk: coalesced row pieces,
+        // independent rows, the row factors read as LDS broadcasts.
+        for (int rb = kend; rb < n; rb += 64) {
+            const int rn = min(64, n - rb);
             __syncthreads();
-            for (int e = threadIdx.x; e < 32 * jb; e += kTrd) {
-                const int rr = e % 32, l = e / 32;
-                const int r = rb + rr, c = cb + rr;
-                tV[0][rr][l] = r < n ? Vm[(int64_t)l * n + r] : 0.0;
-                tW[0][rr][l] = r < n ? Wm[(int64_t)l * n + r] : 0.0;
-                tV[1][rr][l] = c < n ? Vm[(int64_t)l * n + c] : 0.0;
-                tW[1][rr][l] = c < n ? Wm[(int64_t)l * n + c] : 0.0;
+            for (int e = threadIdx.x; e < 64 * jb; e += kTrd) {
+                const int rr = e & 63, l = e >> 6;
+                sVr[rr][l] = rr < rn ? Vm[(int64_t)l * n + rb + rr] : 0.0;
+                sWr[rr][l] = rr < rn ? Wm[(int64_t)l * n + rb + rr] : 0.0;
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < 32 * 32; e += kTrd) {
-                const int rr = e / 32, cc = e % 32;
-                const int r = rb + rr, c = cb + cc;
-                if (r >= n || c >= n) continue;
-                double acc = 0.0;
-                for (int l = 0; l < jb; ++l) acc += tV[0][rr][l] * tW[1][cc][l] + tW[0][rr][l] * tV[1][cc][l];
-                a[(int64_t)r * ld + c] -= acc;
+            for (int cs = kend + 64 * wave; cs < n; cs += 64 * (kTrd / 64)) {
+                const int c = cs + lane;
+                const bool cok = c < n;
+                double vc[kPanel], wc[kPanel];
+#pragma unroll
+                for (int l = 0; l < kPanel; ++l) {
+                    vc[l] = (cok && l < jb) ? Vm[(int64_t)l * n + c] : 0.0;
+                    wc[l] = (cok && l < jb) ? Wm[(int64_t)l * n + c] : 0.0;
+                }
+                if (!cok) continue;
+#pragma unroll 4
+                for (int rr = 0; rr < rn; ++rr) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int l = 0; l < kPanel; ++l) acc += sVr[rr][l] * wc[l] + sWr[rr][l] * vc[l];
+                    a[(int64_t)(rb + rr) * ld + c] -= acc;
+                }
             }
         }
         __syncthreads();
