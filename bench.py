@@ -368,7 +368,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--paths", default="fp64,mixed")
+    ap.add_argument("--paths", default="fp64,mixed,mixed_bf16")
     ap.add_argument("--ns-z", type=int, default=0, help="coupled Newton-Schulz iterations for s^-1/2 (0: library "
                                                         "default)")
     ap.add_argument("--ns-inv", type=int, default=0, help="Newton-Schulz iterations per inverse in each doubling "
@@ -420,7 +420,7 @@ def main():
     results = {}
     paths = [p for p in args.paths.split(",") if p]
     for path in paths:
-        prec = pipeline.FP64_EIG if path == "fp64" else pipeline.MIXED_F16
+        prec = {"fp64": pipeline.FP64_EIG, "mixed": pipeline.MIXED_F16, "mixed_bf16": pipeline.MIXED_BF16}[path]
         try:
             # mixed: mu is warm-started from the previous step, as in MD; the first
             # warm-up step starts from a crude guess (midpoint of the onsite energies)
@@ -431,7 +431,7 @@ def main():
             results[path] = {"ms_per_step": ms, "solves_per_s": part.sg.n_sub / (ms * 1e-3), "mu": sol.mu,
                              "n_count": sol.n_count, "kernels": prof, "q": sol.q.cpu().numpy(),
                              "D": sol.D_core}
-            if path == "mixed":
+            if path != "fp64":
                 results[path]["stats"] = ctx.mixed_stats()
             log(f"[bench] {path}: {ms:.2f} ms/step, {results[path]['solves_per_s']:.1f} solves/s")
         except GDMError as e:
@@ -550,6 +550,13 @@ def main():
             "self_consistent_mu": {"mu_mixed": results["mixed"]["mu"], "mu_fp64": mu64,
                                    "max_abs_dD": dD, "max_abs_dq_e": float(dq),
                                    "mixed_count_error_e": float(results["mixed"]["q"].sum())}}
+    if "mixed_bf16" in results and "fp64" in results:
+        rb = results["mixed_bf16"]
+        out["paths"]["mixed_bf16"]["vs_fp64"] = {
+            "mu_fp64": results["fp64"]["mu"],
+            "max_abs_dD": (rb["D"] - results["fp64"]["D"]).abs().max().item(),
+            "max_abs_dq_e": float(np.abs(rb["q"] - results["fp64"]["q"]).max()),
+            "note": "split-BF16 path with its own mu against the FP64 path"}
     if not args.no_cpu:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s sample)")
         out["cpu_baseline"] = cpu_baseline(box, wl, args.cpu_seconds)

@@ -67,11 +67,16 @@ enum {
 enum { GDM_GRAPH_CUTOFF = 0, GDM_GRAPH_DM = 1, GDM_GRAPH_ADAPTIVE = 2 };
 
 /* Subgraph solver.  GDM_FP64_EIG: FP64 Cholesky basis + FP64 symmetric
- * eigendecomposition (the "direct diagonalization" option).  GDM_MIXED_F16:
- * GEMM-only recursive Fermi-operator expansion with split FP16 operands and
- * FP32 accumulation on the matrix cores, FP64 for bounds, traces, mu and
- * the final step (the recursive-FOE option). */
-enum { GDM_FP64_EIG = 0, GDM_MIXED_F16 = 1 };
+ * eigendecomposition (the "direct diagonalization" option; subgraphs of at
+ * most 2048 orbitals).  GDM_MIXED_F16: GEMM-only recursive Fermi-operator
+ * expansion with split FP16 operands (x = hi + 2^-11 lo, 22 significant
+ * bits) and FP32 accumulation on the matrix cores, FP64 for bounds, traces,
+ * mu and the final step (the recursive-FOE option).  GDM_MIXED_BF16: the
+ * same expansion with split BF16 operands (x = hi + 2^-8 lo, 16 significant
+ * bits, BF16 MFMA): same data volume and speed, rounding errors 2^6 times
+ * larger.  Every call documented for GDM_MIXED_F16 (options, capture,
+ * statistics, charge response) applies to GDM_MIXED_BF16 alike. */
+enum { GDM_FP64_EIG = 0, GDM_MIXED_F16 = 1, GDM_MIXED_BF16 = 2 };
 
 typedef struct gdm_ctx gdm_ctx;
 

@@ -21,7 +21,7 @@ GDM_OK = 0
 ERRORS = {-1: "E_ARG", -2: "E_CAPACITY", -3: "E_NOT_PD", -4: "E_NO_BRACKET", -5: "E_NOT_CONVERGED",
           -6: "E_NAN", -7: "E_HIP", -8: "E_STATE"}
 GRAPH_CUTOFF, GRAPH_DM, GRAPH_ADAPTIVE = 0, 1, 2
-FP64_EIG, MIXED_F16 = 0, 1
+FP64_EIG, MIXED_F16, MIXED_BF16 = 0, 1, 2
 
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_set_stream", "gdm_last_error", "gdm_check", "gdm_build_graph",
             "gdm_grid_cores", "gdm_extract_subgraphs", "gdm_build_hs", "gdm_plan", "gdm_find_mu",

@@ -166,7 +166,7 @@ static int round_up(int v, int m) { return (v + m - 1) / m * m; }
 static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
     if (!sg || sg->n_sub <= 0 || !sg->atom_ptr || !sg->atoms || !sg->n_core || !sg->h_norb || !sg->h_ncore_orb)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_plan: incomplete subgraph set");
-    if (precision != GDM_FP64_EIG && precision != GDM_MIXED_F16)
+    if (precision != GDM_FP64_EIG && !gdm_is_mixed(precision))
         return gdm_fail(ctx, GDM_E_ARG, "gdm_plan: unknown precision %d", precision);
     const int ns = sg->n_sub;
     Plan& P = ctx->plan;
@@ -189,7 +189,7 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         SubDesc& d = P.desc[s];
         d.n = n;
         d.nc = nc;
-        d.ld = precision == GDM_MIXED_F16 ? round_up(n, 64) : round_up(n, 16);
+        d.ld = gdm_is_mixed(precision) ? round_up(n, 64) : round_up(n, 16);
         d.natoms = aptr[s + 1] - aptr[s];
         d.ncore_atoms = ncore[s];
         d.atom0 = aptr[s];
@@ -399,11 +399,13 @@ extern "C" int gdm_density_response(gdm_ctx* ctx, const gdm_system* sys, const g
     if (!ctx) return GDM_E_ARG;
     int rc = check_system(ctx, sys, "gdm_density_response");
     if (rc) return rc;
-    if ((rc = check_plan(ctx, sg, GDM_MIXED_F16, "gdm_density_response"))) return rc;
+    if (!gdm_is_mixed(ctx->plan.precision))
+        return gdm_fail(ctx, GDM_E_STATE, "gdm_density_response: the plan is not a mixed-precision plan");
+    if ((rc = check_plan(ctx, sg, ctx->plan.precision, "gdm_density_response"))) return rc;
     if (!row_ptr || (!col && nnz > 0) || !dV || !dq_out)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_density_response: null argument");
-    if (!ctx->solved || ctx->solved_precision != GDM_MIXED_F16)
-        return gdm_fail(ctx, GDM_E_STATE, "gdm_density_response: call gdm_find_mu (GDM_MIXED_F16) first");
+    if (!ctx->solved || ctx->solved_precision != ctx->plan.precision)
+        return gdm_fail(ctx, GDM_E_STATE, "gdm_density_response: call gdm_find_mu (mixed precision) first");
     if ((rc = gdm_mixed_response(ctx, sys, sg, row_ptr, col, nnz, S, dV, dq_out, dmu_out))) return rc;
     return gdm_check(ctx);
 }

@@ -16,6 +16,10 @@
 #define GDM_STATUS_CAPACITY 8
 #define GDM_STATUS_NO_BRACKET 16
 
+__host__ __device__ inline bool gdm_is_mixed(int precision) {
+    return precision == GDM_MIXED_F16 || precision == GDM_MIXED_BF16;
+}
+
 // Per-subgraph descriptor for the dense solve (device resident).
 struct SubDesc {
     int32_t n;        // orbitals

@@ -32,6 +32,7 @@
 #include <cmath>
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -44,10 +45,14 @@ constexpr int kXcds = 8;        // workgroup b is dispatched to XCD b mod 8
 constexpr float kLoScale = 2048.0f;            // 2^11
 constexpr float kLoInv = 1.0f / 2048.0f;
 
+// A matrix as FP32 (f, nullable) and/or as a split pair of 16-bit halves:
+// FP16 x = hi + 2^-11 lo, or (bf = 1) BF16 x = hi + 2^-8 lo, each half the
+// nearest value of its format to what is left of x.
 struct SplitMat {
     float* f;
-    _Float16* hi;
+    _Float16* hi;       // 16-bit halves (BF16 bit patterns when bf = 1)
     _Float16* lo;
+    int bf;
 };
 
 // State of the chemical-potential search, in device memory (doubles): the
@@ -142,12 +147,40 @@ struct GemmArgs {
                          // predication of launches whose count is fixed at capture time)
 };
 
+constexpr float kLoScaleBf = 256.0f;            // 2^8
+constexpr float kLoInvBf = 1.0f / 256.0f;
+
+// FP32 -> BF16 (round to nearest even) and back, as bit patterns
+__device__ __forceinline__ _Float16 bf16_of(float x) {
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
+}
+__device__ __forceinline__ float f32_of_bf16(_Float16 b) {
+    return __builtin_bit_cast(float, (uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+__device__ __forceinline__ void split_one(float v, int bf, _Float16& h, _Float16& l) {
+    if (bf) {
+        h = bf16_of(v);
+        l = bf16_of((v - f32_of_bf16(h)) * kLoScaleBf);
+    } else {
+        h = (_Float16)v;
+        l = (_Float16)((v - (float)h) * kLoScale);
+    }
+}
+
+__device__ __forceinline__ float join_one(_Float16 h, _Float16 l, int bf) {
+    return bf ? f32_of_bf16(h) + kLoInvBf * f32_of_bf16(l) : (float)h + kLoInv * (float)l;
+}
+
 __device__ __forceinline__ void store_split(SplitMat m, int64_t idx, float v) {
     if (m.f) m.f[idx] = v;
     if (m.hi) {
-        _Float16 h = (_Float16)v;
+        _Float16 h, l;
+        split_one(v, m.bf, h, l);
         m.hi[idx] = h;
-        m.lo[idx] = (_Float16)((v - (float)h) * kLoScale);
+        m.lo[idx] = l;
     }
 }
 
@@ -177,26 +210,28 @@ __device__ __forceinline__ void store4(SplitMat m, int64_t idx, float4 v) {
         half4 h, l;
         const float x[4] = {v.x, v.y, v.z, v.w};
         for (int q = 0; q < 4; ++q) {
-            const _Float16 hh = (_Float16)x[q];
+            _Float16 hh, ll;
+            split_one(x[q], m.bf, hh, ll);
             h[q] = hh;
-            l[q] = (_Float16)((x[q] - (float)hh) * kLoScale);
+            l[q] = ll;
         }
         *(half4*)(m.hi + idx) = h;
         *(half4*)(m.lo + idx) = l;
     }
 }
 
-// x = hi + 2^-11 lo for four consecutive elements
+// x = hi + 2^-11 lo (BF16: hi + 2^-8 lo) for four consecutive elements
 __device__ __forceinline__ float4 load4(SplitMat m, int64_t idx) {
     if (m.f) return *(const float4*)(m.f + idx);
     const half4 h = *(const half4*)(m.hi + idx);
     const half4 l = *(const half4*)(m.lo + idx);
-    return make_float4((float)h[0] + kLoInv * (float)l[0], (float)h[1] + kLoInv * (float)l[1],
-                       (float)h[2] + kLoInv * (float)l[2], (float)h[3] + kLoInv * (float)l[3]);
+    return make_float4(join_one(h[0], l[0], m.bf), join_one(h[1], l[1], m.bf), join_one(h[2], l[2], m.bf),
+                       join_one(h[3], l[3], m.bf));
 }
 
 // Four waves per SIMD (four workgroups per CU, as the LDS allows): the
 // register budget is held to 128 per lane (no spills).
+template <bool BF>
 __global__ void __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(4))) k_gemm_split(const SubDesc* __restrict__ desc,
                                                             const int4* __restrict__ tiles, GemmArgs g) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[kGemmLds];
@@ -326,9 +361,17 @@ __global__ void __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_
             for (int i = 0; i < 2; ++i)
                 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    acc_hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
-                    acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc_x[i][j], 0, 0, 0);
-                    acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc_x[i][j], 0, 0, 0);
+                    if constexpr (BF) {
+                        const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah[i]), Al = __builtin_bit_cast(bf16x8, al[i]);
+                        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[j]), Bl = __builtin_bit_cast(bf16x8, bl[j]);
+                        acc_hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, acc_hh[i][j], 0, 0, 0);
+                        acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, acc_x[i][j], 0, 0, 0);
+                        acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acc_x[i][j], 0, 0, 0);
+                    } else {
+                        acc_hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
+                        acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc_x[i][j], 0, 0, 0);
+                        acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc_x[i][j], 0, 0, 0);
+                    }
                 }
         }
     }
@@ -342,7 +385,7 @@ __global__ void __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_
             for (int r = 0; r < 4; ++r) {
                 const int ml = wm * 32 + i * 16 + 4 * gq + r;
                 const int nl = wn * 32 + j * 16 + fr;
-                sC[ml * kOutRow + nl] = acc_hh[i][j][r] + kLoInv * acc_x[i][j][r];
+                sC[ml * kOutRow + nl] = acc_hh[i][j][r] + (BF ? kLoInvBf : kLoInv) * acc_x[i][j][r];
             }
     __syncthreads();
     const bool diag_tile = tl.y == tl.z;
@@ -384,7 +427,7 @@ __global__ void __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_
         for (int j = 0; j < 2; ++j) {
             float x[4];
             #pragma unroll
-            for (int r = 0; r < 4; ++r) x[r] = acc_hh[i][j][r] + kLoInv * acc_x[i][j][r];
+            for (int r = 0; r < 4; ++r) x[r] = acc_hh[i][j][r] + (BF ? kLoInvBf : kLoInv) * acc_x[i][j][r];
             const int gm = n0 + wn * 32 + j * 16 + fr;
             const int gn = m0 + wm * 32 + i * 16 + 4 * gq;
             const int64_t idx = base + (int64_t)gm * P + gn;
@@ -1157,10 +1200,10 @@ static SplitMat slot(gdm_ctx* ctx, int k) {
     float* f = fi < 0 ? nullptr : (float*)ctx->b[BUF_X_F].p + (int64_t)fi * tot;
     _Float16* hi = (_Float16*)ctx->b[BUF_X_HI].p + (int64_t)k * tot;
     _Float16* lo = (_Float16*)ctx->b[BUF_X_LO].p + (int64_t)k * tot;
-    return SplitMat{f, hi, lo};
+    return SplitMat{f, hi, lo, ctx->plan.precision == GDM_MIXED_BF16};
 }
 
-static SplitMat none() { return SplitMat{nullptr, nullptr, nullptr}; }
+static SplitMat none() { return SplitMat{nullptr, nullptr, nullptr, 0}; }
 
 #define GDM_TRY(x)          \
     do {                    \
@@ -1247,7 +1290,7 @@ int gdm_mixed_plan(gdm_ctx* ctx) {
 // C = A B for symmetric B (read row-major as B^T).  sym = 1 when A and B
 // commute (products of polynomials in the same matrix): only upper tiles are
 // computed and mirrored.
-static SplitMat hl(SplitMat m) { return SplitMat{nullptr, m.hi, m.lo}; }
+static SplitMat hl(SplitMat m) { return SplitMat{nullptr, m.hi, m.lo, m.bf}; }
 
 static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, SplitMat E, float alpha,
                 float beta, float gamma, const char* tag, int sym = 1, int packed = 0, const int* skip = nullptr) {
@@ -1258,8 +1301,12 @@ static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, 
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + (sym ? ctx->mixed_tiles : 0);
     const int64_t nt = sym ? ctx->mixed_tiles_sym : ctx->mixed_tiles;
     GDM_TIMED(ctx, tag);
-    hipLaunchKernelGGL(k_gemm_split, dim3((unsigned)nt), dim3(kGemmThreads), 0, ctx->stream,
-                       (const SubDesc*)ctx->b[BUF_DESC].p, tl, g);
+    if (ctx->plan.precision == GDM_MIXED_BF16)
+        hipLaunchKernelGGL(k_gemm_split<true>, dim3((unsigned)nt), dim3(kGemmThreads), 0, ctx->stream,
+                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, g);
+    else
+        hipLaunchKernelGGL(k_gemm_split<false>, dim3((unsigned)nt), dim3(kGemmThreads), 0, ctx->stream,
+                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, g);
     GDM_LAUNCH_CHECK(ctx);
     ctx->mixed_gemms += 1;
     ctx->mixed_flops += sym ? ctx->mixed_flops_sym : ctx->mixed_flops_full;
@@ -1292,7 +1339,8 @@ static constexpr float kStart7[3] = {0.0208103713f, -0.000615022611f, 5.41684949
 // FP16 hi/lo pairs.
 static SplitMat hist(gdm_ctx* ctx, int k, int which) {
     const int64_t off = (int64_t)(2 * k + which) * ctx->plan.tot2;
-    return SplitMat{nullptr, (_Float16*)ctx->b[BUF_HIST_HI].p + off, (_Float16*)ctx->b[BUF_HIST_LO].p + off};
+    return SplitMat{nullptr, (_Float16*)ctx->b[BUF_HIST_HI].p + off, (_Float16*)ctx->b[BUF_HIST_LO].p + off,
+                    ctx->plan.precision == GDM_MIXED_BF16};
 }
 
 static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const int* skip);
@@ -1758,7 +1806,7 @@ int gdm_mixed_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const do
 // the orbital potentials (totv).  Released when recording is off.
 int gdm_mixed_response_alloc(gdm_ctx* ctx) {
     const Plan& P = ctx->plan;
-    if (ctx->mixed_rec_cap <= 0 || P.precision != GDM_MIXED_F16 || P.n_sub <= 0) {
+    if (ctx->mixed_rec_cap <= 0 || !gdm_is_mixed(P.precision) || P.n_sub <= 0) {
         GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
         for (int b : {BUF_HIST_HI, BUF_HIST_LO, BUF_RESP}) gdm_buf_release(ctx, b);
         return GDM_OK;
@@ -1904,7 +1952,7 @@ extern "C" int gdm_set_mixed_capture(gdm_ctx* ctx, int passes, int nd_launch) {
 
 extern "C" int gdm_mixed_mu_state(gdm_ctx* ctx, double* mu_pass, double* n_pass, double* slope) {
     if (!ctx) return GDM_E_ARG;
-    if (ctx->plan.precision != GDM_MIXED_F16 || !ctx->b[BUF_MSTATE].p)
+    if (!gdm_is_mixed(ctx->plan.precision) || !ctx->b[BUF_MSTATE].p)
         return gdm_fail(ctx, GDM_E_STATE, "gdm_mixed_mu_state: no mixed plan");
     double hs[kStCount];
     GDM_TRY(read_state(ctx, hs));
@@ -1948,7 +1996,7 @@ extern "C" int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out) {
     if (!ctx) return GDM_E_ARG;
     const Plan& P = ctx->plan;
     static const int kDebugSlots[3] = {SL_Z, SL_HP, SL_X};
-    if (P.precision != GDM_MIXED_F16 || which < 0 || which >= 3 || sub < 0 || sub >= P.n_sub || !out)
+    if (!gdm_is_mixed(P.precision) || which < 0 || which >= 3 || sub < 0 || sub >= P.n_sub || !out)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_debug_slot: bad argument");
     const SubDesc& d = P.desc[sub];
     GDM_HIP(ctx, hipMemcpyAsync(out, slot(ctx, kDebugSlots[which]).f + d.off2, sizeof(float) * (size_t)d.ld * d.ld,

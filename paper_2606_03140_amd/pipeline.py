@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from ._lib import (FP64_EIG, GRAPH_ADAPTIVE, GRAPH_DM, MIXED_F16, Context, Graph, Subgraphs, System,
+from ._lib import (FP64_EIG, GRAPH_ADAPTIVE, GRAPH_DM, MIXED_BF16, MIXED_F16, Context, Graph, Subgraphs, System,
                    TBParams)
 
 
@@ -113,5 +113,5 @@ def rebuild_adaptive(ctx: Context, system: System, tb: TBParams, part: Partition
 
 
 __all__ = ["Partition", "Solution", "solve", "cutoff_partition", "full_system_partition", "adaptive_partition",
-           "graph_from_full_dm", "rebuild_adaptive", "repartition", "FP64_EIG", "MIXED_F16", "GRAPH_DM",
+           "graph_from_full_dm", "rebuild_adaptive", "repartition", "FP64_EIG", "MIXED_F16", "MIXED_BF16", "GRAPH_DM",
            "GRAPH_ADAPTIVE"]
