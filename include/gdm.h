@@ -169,6 +169,28 @@ int gdm_build_graph(gdm_ctx* ctx, const gdm_system* sys, int mode, double cutoff
 int gdm_grid_cores(gdm_ctx* ctx, const gdm_system* sys, const int32_t grid[3],
                    int32_t* core_of_atom, int32_t* n_cores_out);
 
+/* Cost-balanced core partition for re-partitioning (Determining the
+ * Subgraphs: a new core partitioning when the halos have grown, Fig.
+ * graph_partition f; Scalability section: subgraph cost grows as its size
+ * cubed).  Weighted recursive coordinate bisection of the molecules (atoms
+ * with anchor[a] == a, at their wrapped positions): a set that must form k
+ * cores is sorted along its widest axis (ties by index) and cut where the
+ * running weight is closest to k/2 / k of its total, keeping at least one
+ * molecule per core; both sides recurse.  A molecule weighs the number of its
+ * atoms plus their degrees in the graph row_ptr (DEVICE [n_atoms + 1],
+ * nullable: atom counts only), so cores shrink where the graph is dense.
+ * core_of_atom DEVICE [n_atoms] (cores 0 .. n_cores-1, every core
+ * non-empty).  GDM_E_ARG for n_cores outside [1, molecules] or an atom whose
+ * anchor does not anchor itself.  Synchronises the stream (host algorithm). */
+int gdm_balanced_cores(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, int32_t n_cores,
+                       int32_t* core_of_atom);
+
+/* The bisection of gdm_balanced_cores on host arrays (no context, no GPU):
+ * xyz HOST [n x 3], weight HOST [n] (nullable: all 1; each > 0),
+ * part HOST [n] out (0 .. n_parts-1).  GDM_E_ARG for n <= 0,
+ * n_parts outside [1, n] or a non-finite value. */
+int gdm_rcb_partition(const double* xyz, const double* weight, int32_t n, int32_t n_parts, int32_t* part);
+
 /* Core+halo subgraphs (Fig. graph_partition b-c; SI section A): the halo of a
  * core is every atom outside it with an edge to one of its atoms.  Outputs
  * atom_ptr [n_cores+1], atoms [cap_atoms], n_core [n_cores]; HOST outputs

@@ -7,6 +7,14 @@
   cell = min(g - 1, floor((x * inv_L) * g)), id = (i * g_y + j) * g_z + k;
   hydrogens follow their O; empty cells are skipped and the remaining cells are
   numbered in ascending id order.
+* Cost-balanced cores for re-partitioning (stand-in for community detection
+  when the halos have grown, Fig. graph_partition f; subgraph cost grows as
+  size cubed, Scalability section): weighted recursive coordinate bisection
+  of the molecules at their wrapped anchor positions; a set forming k cores
+  is sorted along its widest axis (ties by index) and cut where the running
+  weight is closest to floor(k/2)/k of its total (first such cut, at least one
+  molecule per core); a molecule weighs its atom count plus its atoms'
+  graph degrees.
 * Halo = every atom outside the core with an edge to some core atom (one hop,
   Fig. graph_partition c; SI section A).  Subgraph atom order: core ascending,
   then halo ascending.
@@ -57,6 +65,60 @@ def grid_cores(pos: np.ndarray, anchor: np.ndarray, L: float, grid):
     remap = -np.ones(gx * gy * gz, dtype=np.int64)
     remap[used] = np.arange(len(used))
     return remap[cid], len(used)
+
+
+def rcb_parts(xyz, w, k):
+    """Recursive coordinate bisection of points xyz [m, 3] with weights w into
+    k parts (plain loops: running sums in sorted order)."""
+    m = len(w)
+    part = [0] * m
+
+    def split(idx, k, first):
+        if k == 1:
+            for i in idx:
+                part[i] = first
+            return
+        ext = [max(xyz[i][a] for i in idx) - min(xyz[i][a] for i in idx) for a in range(3)]
+        ax = 0
+        for a in (1, 2):
+            if ext[a] > ext[ax]:
+                ax = a
+        idx = sorted(idx, key=lambda i: (xyz[i][ax], i))
+        k1 = k // 2
+        tot = 0.0
+        for i in idx:
+            tot += w[i]
+        target = tot * k1 / k
+        run = 0.0
+        for i in idx[:k1]:
+            run += w[i]
+        best, cut = abs(run - target), k1
+        for s in range(k1, len(idx) - (k - k1)):
+            run += w[idx[s]]
+            if abs(run - target) < best:
+                best, cut = abs(run - target), s + 1
+        split(idx[:cut], k1, first)
+        split(idx[cut:], k - k1, first + k1)
+
+    split(list(range(m)), k, 0)
+    return part
+
+
+def balanced_cores(pos: np.ndarray, anchor: np.ndarray, L: float, n_cores: int, row_ptr=None):
+    """Core of every atom from the weighted bisection of the molecules."""
+    n = len(anchor)
+    mols = [a for a in range(n) if anchor[a] == a]
+    mol_of = {a: i for i, a in enumerate(mols)}
+    inv_L = 1.0 / L
+    xyz = []
+    for a in mols:
+        xyz.append([float(pos[a][c] - L * np.floor(pos[a][c] * inv_L)) for c in range(3)])
+    w = [0.0] * len(mols)
+    for a in range(n):
+        deg = 0 if row_ptr is None else int(row_ptr[a + 1] - row_ptr[a])
+        w[mol_of[int(anchor[a])]] += 1.0 + deg
+    part = rcb_parts(xyz, w, n_cores)
+    return np.array([part[mol_of[int(anchor[a])]] for a in range(n)], dtype=np.int64)
 
 
 def extract_subgraphs(row_ptr: np.ndarray, col: np.ndarray, core_of_atom: np.ndarray, n_cores: int):

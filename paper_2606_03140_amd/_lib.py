@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     sig["gdm_mixed_stats"] = (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)])
     sig["gdm_debug_slot"] = (C.c_int, [P, C.c_int, C.c_int, P])
+    sig["gdm_balanced_cores"] = (C.c_int, [P, C.POINTER(SystemT), P, I32, P])
+    sig["gdm_rcb_partition"] = (C.c_int, [P, P, I32, I32, P])
     sig["gdm_ewald_potential"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double),
                                             C.POINTER(C.c_double), P, P])
     sig["gdm_ewald_potential_noalloc"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double),
@@ -121,6 +123,19 @@ def lib() -> C.CDLL:
     if _LIB is None:
         _LIB = load_library()
     return _LIB
+
+
+def rcb_partition(xyz: np.ndarray, n_parts: int, weight: np.ndarray | None = None) -> np.ndarray:
+    """Weighted recursive coordinate bisection on host arrays
+    (gdm_rcb_partition; runs on the host, no GPU)."""
+    x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    w = None if weight is None else np.ascontiguousarray(weight, dtype=np.float64)
+    part = np.zeros(len(x), dtype=np.int32)
+    rc = lib().gdm_rcb_partition(x.ctypes.data_as(C.c_void_p), None if w is None else w.ctypes.data_as(C.c_void_p),
+                                 len(x), int(n_parts), part.ctypes.data_as(C.c_void_p))
+    if rc:
+        raise GDMError(rc, f"gdm_rcb_partition: error {rc}")
+    return part
 
 
 def _ptr(t):
@@ -302,6 +317,14 @@ class Context:
         n = C.c_int32(0)
         self._check(self.lib.gdm_grid_cores(self.h, C.byref(system.struct()), g, _ptr(core), C.byref(n)))
         return core, int(n.value)
+
+    def balanced_cores(self, system: System, n_cores: int, graph: Graph | None = None) -> torch.Tensor:
+        """Cost-balanced cores (weighted recursive bisection; gdm_balanced_cores)."""
+        core = torch.empty(system.n_atoms, dtype=torch.int32, device=self.dev)
+        self._check(self.lib.gdm_balanced_cores(self.h, C.byref(system.struct()),
+                                                _ptr(graph.row_ptr) if graph is not None else None, int(n_cores),
+                                                _ptr(core)))
+        return core
 
     def extract_subgraphs(self, system: System, tb: TBParams, graph: Graph, core_of_atom, n_cores) -> Subgraphs:
         atom_ptr = torch.empty(n_cores + 1, dtype=torch.int32, device=self.dev)

@@ -26,6 +26,14 @@ class Partition:
     sg: Subgraphs
     rounds: int = 0
     sizes: list = field(default_factory=list)
+    cost0: float = 0.0         # sum of n^3 of the subgraphs when the cores were last chosen
+    repartitions: int = 0
+
+
+def subgraph_cost(sg: Subgraphs) -> float:
+    """Dense-solve cost of a subgraph set: sum of n^3 (Scalability section)."""
+    n = sg.norb.astype(np.float64)
+    return float(np.sum(n ** 3))
 
 
 @dataclass
@@ -53,7 +61,42 @@ def cutoff_partition(ctx: Context, system: System, tb: TBParams, grid) -> Partit
     nbr = ctx.build_graph_cutoff(system, tb.cutoff)
     core, nco = ctx.grid_cores(system, grid)
     sg = ctx.extract_subgraphs(system, tb, nbr, core, nco)
-    return Partition(nbr=nbr, graph=nbr, core_of_atom=core, n_cores=nco, sg=sg, sizes=[sg.norb.copy()])
+    return Partition(nbr=nbr, graph=nbr, core_of_atom=core, n_cores=nco, sg=sg, sizes=[sg.norb.copy()],
+                     cost0=subgraph_cost(sg))
+
+
+def balanced_partition(ctx: Context, system: System, tb: TBParams, n_cores: int, graph: Graph | None = None,
+                       nbr: Graph | None = None) -> Partition:
+    """Cores from the weighted recursive bisection (gdm_balanced_cores), each
+    molecule weighted by its atoms' degrees in `graph` (default: the
+    neighbour graph), and their one-hop halos in `graph`."""
+    if nbr is None:
+        nbr = ctx.build_graph_cutoff(system, tb.cutoff)
+    g = nbr if graph is None else graph
+    core = ctx.balanced_cores(system, n_cores, g)
+    sg = ctx.extract_subgraphs(system, tb, g, core, n_cores)
+    return Partition(nbr=nbr, graph=g, core_of_atom=core, n_cores=n_cores, sg=sg, sizes=[sg.norb.copy()],
+                     cost0=subgraph_cost(sg))
+
+
+def maybe_repartition(ctx: Context, system: System, tb: TBParams, part: Partition, graph: Graph,
+                      growth: float = 1.5) -> tuple[Partition, bool]:
+    """Subgraphs of the new graph on the current cores; when their sum of n^3
+    exceeds `growth` times its value when the cores were chosen, new
+    cost-balanced cores are drawn from the new graph (Determining the
+    Subgraphs, Fig. graph_partition f).  Returns the partition and whether
+    the cores changed."""
+    p = repartition(ctx, system, tb, part, graph)
+    cost0 = part.cost0 if part.cost0 > 0 else subgraph_cost(part.sg)
+    p.cost0 = cost0
+    p.repartitions = part.repartitions
+    if subgraph_cost(p.sg) <= growth * cost0:
+        return p, False
+    core = ctx.balanced_cores(system, part.n_cores, graph)
+    sg = ctx.extract_subgraphs(system, tb, graph, core, part.n_cores)
+    q = Partition(nbr=part.nbr, graph=graph, core_of_atom=core, n_cores=part.n_cores, sg=sg, rounds=part.rounds,
+                  sizes=part.sizes + [sg.norb.copy()], cost0=subgraph_cost(sg), repartitions=part.repartitions + 1)
+    return q, True
 
 
 def full_system_partition(ctx: Context, system: System, tb: TBParams) -> Partition:
@@ -67,7 +110,8 @@ def full_system_partition(ctx: Context, system: System, tb: TBParams) -> Partiti
 def repartition(ctx: Context, system: System, tb: TBParams, part: Partition, graph: Graph) -> Partition:
     sg = ctx.extract_subgraphs(system, tb, graph, part.core_of_atom, part.n_cores)
     return Partition(nbr=part.nbr, graph=graph, core_of_atom=part.core_of_atom, n_cores=part.n_cores, sg=sg,
-                     rounds=part.rounds, sizes=part.sizes + [sg.norb.copy()])
+                     rounds=part.rounds, sizes=part.sizes + [sg.norb.copy()], cost0=part.cost0,
+                     repartitions=part.repartitions)
 
 
 def adaptive_partition(ctx: Context, system: System, tb: TBParams, grid, tau: float, kT: float,
@@ -113,5 +157,6 @@ def rebuild_adaptive(ctx: Context, system: System, tb: TBParams, part: Partition
 
 
 __all__ = ["Partition", "Solution", "solve", "cutoff_partition", "full_system_partition", "adaptive_partition",
-           "graph_from_full_dm", "rebuild_adaptive", "repartition", "FP64_EIG", "MIXED_F16", "MIXED_BF16", "GRAPH_DM",
+           "graph_from_full_dm", "rebuild_adaptive", "repartition", "balanced_partition", "maybe_repartition",
+           "subgraph_cost", "FP64_EIG", "MIXED_F16", "MIXED_BF16", "GRAPH_DM",
            "GRAPH_ADAPTIVE"]
