@@ -45,7 +45,7 @@ def dc_block_sum(n: int, leaf: int = 64) -> int:
     return tot
 
 
-def fp64_flops(n: np.ndarray, nc: np.ndarray) -> dict:
+def fp64_flops(n: np.ndarray, nc: np.ndarray, leaf: int = 64) -> dict:
     """Nominal FP64 flops of the executed route, summed over subgraphs:
     Cholesky n^3/3, each triangular solve n^3, tridiagonalisation 4/3 n^3,
     reflectors and forward substitution on the 2 nc core rows 5 nc n^2, the
@@ -53,7 +53,7 @@ def fp64_flops(n: np.ndarray, nc: np.ndarray) -> dict:
     reverse reflectors and the solve with L 3 nc n^2."""
     n = n.astype(np.float64)
     nc = nc.astype(np.float64)
-    ks = np.array([dc_block_sum(int(v)) for v in n], dtype=np.float64)
+    ks = np.array([dc_block_sum(int(v), leaf) for v in n], dtype=np.float64)
     return {
         "potrf": float(np.sum(n ** 3 / 3)),
         "trsm": float(np.sum(n ** 3)),          # per launch (two launches)
@@ -167,6 +167,8 @@ def time_graph(system, part, H, S, kT, steps, warmup, mu_start):
     with torch.cuda.stream(side):
         c = Context(0)
         try:
+            from paper_2606_03140_amd import autotune
+            autotune.apply_table(c, autotune.load_table(), int(part.sg.norb.max()), paths=("mixed",))
             c.plan(part.sg, pipeline.MIXED_F16)
             c.set_mu_outputs(True)
             c.set_mixed_capture(3, 10)
@@ -214,10 +216,10 @@ def time_graph(system, part, H, S, kT, steps, warmup, mu_start):
 BATCHED = dict(name="water3000", n_waters=3000, seed=7, grid=(5, 5, 6), tau=1e-5, kT=0.1, alpha=0.7)
 
 
-def fp64_roofline(prof: dict, ms: float, n: np.ndarray, nc: np.ndarray, steps: int) -> dict:
+def fp64_roofline(prof: dict, ms: float, n: np.ndarray, nc: np.ndarray, steps: int, leaf: int = 64) -> dict:
     """The FP64 path against the FP64 peak: nominal flops of the route it
     executes per step over the step time, and the dominant kernel."""
-    fl = fp64_flops(n, nc)
+    fl = fp64_flops(n, nc, leaf)
     work = (fl["potrf"] + 2 * fl["trsm"] + fl["sytrd"] + fl["core_rows"] + fl["dc_apply"] + fl["dc_apply_rev"]
             + fl["dcore"])
     dom = max(prof.items(), key=lambda kv: kv[1]["ms_total"])
@@ -248,6 +250,8 @@ def time_fp64_batched(steps: int, warmup: int):
                              nbr=part.nbr)
         part = pipeline.repartition(c, system, tb, part, g)
         n, nc = part.sg.norb, part.sg.ncore_orb
+        from paper_2606_03140_amd import autotune
+        tuned = autotune.apply_table(c, autotune.load_table(), int(n.max()), paths=("fp64",))
         log(f"[bench] batched FP64 workload: {part.sg.n_sub} subgraphs, n {n.min()}-{n.max()}; warmup {warmup}, "
             f"steps {steps}")
         sol, ms, wall, prof = time_path(c, system, part, H, S, wl["kT"], pipeline.FP64_EIG, steps, warmup)
@@ -256,9 +260,9 @@ def time_fp64_batched(steps: int, warmup: int):
                             f"tau {wl['tau']}",
                 "n_subgraphs": part.sg.n_sub, "orbitals_min": int(n.min()), "orbitals_max": int(n.max()),
                 "ms_per_step": ms, "solves_per_s": part.sg.n_sub / (ms * 1e-3), "mu": sol.mu,
-                "electron_count": sol.n_count,
+                "electron_count": sol.n_count, "tuning": tuned,
                 "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
-                "roofline": fp64_roofline(prof, ms, n, nc, steps)}
+                "roofline": fp64_roofline(prof, ms, n, nc, steps, tuned["fp64"]["leaf_rows"])}
     finally:
         c.close()
 
@@ -416,6 +420,11 @@ def main():
     log(f"[bench] partition: {part.sg.n_sub} subgraphs, n {n.min()}-{n.max()} (median {int(np.median(n))}), "
         f"setup {setup_s:.1f} s")
 
+    # run-time options chosen by the autotuner for this size bucket (library
+    # defaults where its table has no entry); the command line overrides
+    from paper_2606_03140_amd import autotune
+    tuning = autotune.apply_table(ctx, autotune.load_table(), int(n.max()))
+    log(f"[bench] tuned options ({autotune.bucket(int(n.max()))}): {tuning}")
     ctx.set_mixed_options(ns_z=args.ns_z, ns_inv=args.ns_inv)
     results = {}
     paths = [p for p in args.paths.split(",") if p]
@@ -439,7 +448,8 @@ def main():
 
     if "fp64" in results:
         r64 = results["fp64"]
-        r64["roofline"] = fp64_roofline(r64["kernels"], r64["ms_per_step"], n, nc, args.steps)
+        r64["roofline"] = fp64_roofline(r64["kernels"], r64["ms_per_step"], n, nc, args.steps,
+                                        tuning["fp64"]["leaf_rows"])
     head = "mixed" if "mixed" in results else "fp64"
     R = results[head]
     fl = fp64_flops(n, nc)
@@ -502,7 +512,8 @@ def main():
                                f"{wl['grid'][2]} cores, tau {wl['tau']} ({wl['rounds']} graph rounds)",
                    "n_subgraphs": part.sg.n_sub, "orbitals_min": int(n.min()), "orbitals_median": int(np.median(n)),
                    "orbitals_max": int(n.max()), "path": head,
-                   "mixed_options": {"ns_z": args.ns_z or 3, "ns_inv": args.ns_inv or 2}},
+                   "mixed_options": {"ns_z": args.ns_z or 3, "ns_inv": args.ns_inv or tuning["mixed"]["ns_inv"]},
+                   "tuning": tuning},
         "paths": {k: {"ms_per_step": v["ms_per_step"], "solves_per_s": v["solves_per_s"], "mu": v["mu"],
                       "electron_count": v["n_count"],
                       "kernels_ms_per_step": {kk: round(vv["ms_per_step"], 4) for kk, vv in v["kernels"].items()},

@@ -344,6 +344,13 @@ int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
  * <= 0 (ns_z_extra: < 0) keep the current setting. */
 int gdm_set_mixed_options(gdm_ctx* ctx, int ns_z, int ns_inv, int max_passes, int ns_z_extra);
 
+/* Options of the FP64 path, read by the next gdm_plan: the largest leaf of
+ * the tridiagonal divide and conquer (leaves are solved by QL with the
+ * eigenvectors accumulated, one wave each; smaller leaves shorten that
+ * serial chain and add a merge level).  leaf_rows in [8, 64] (default 64);
+ * GDM_E_ARG otherwise.  Results agree to FP64 rounding for every value. */
+int gdm_set_fp64_options(gdm_ctx* ctx, int leaf_rows);
+
 /* Storage of the symmetric matrices of a MIXED_F16 expansion pass (the start
  * polynomial, X_k, X_k^2, 2 X_k^2 - 2 X_k + I, its inverse and Newton-Schulz
  * factors).  upper_tiles = 1 (default): only the upper 64 x 64 tiles are

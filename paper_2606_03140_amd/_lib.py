@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     sig["gdm_debug_slot"] = (C.c_int, [P, C.c_int, C.c_int, P])
     sig["gdm_balanced_cores"] = (C.c_int, [P, C.POINTER(SystemT), P, I32, P])
     sig["gdm_rcb_partition"] = (C.c_int, [P, P, I32, I32, P])
+    sig["gdm_set_fp64_options"] = (C.c_int, [P, C.c_int])
     sig["gdm_ewald_potential"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double),
                                             C.POINTER(C.c_double), P, P])
     sig["gdm_ewald_potential_noalloc"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double),
@@ -317,6 +318,10 @@ class Context:
         n = C.c_int32(0)
         self._check(self.lib.gdm_grid_cores(self.h, C.byref(system.struct()), g, _ptr(core), C.byref(n)))
         return core, int(n.value)
+
+    def set_fp64_options(self, leaf_rows: int = 64):
+        """Largest leaf of the FP64 path's divide and conquer (next plan)."""
+        self._check(self.lib.gdm_set_fp64_options(self.h, int(leaf_rows)))
 
     def balanced_cores(self, system: System, n_cores: int, graph: Graph | None = None) -> torch.Tensor:
         """Cost-balanced cores (weighted recursive bisection; gdm_balanced_cores)."""

@@ -97,6 +97,7 @@ struct gdm_ctx {
     int mixed_ns_z_extra = 8;    // iterations that may be added while the residual is too large
     int mixed_ns_z_used = 0;     // iterations the last find_mu took
     int mu_out_device = 0;       // gdm_find_mu writes mu and N to device scalars (FP64 path)
+    int fp64_leaf = 64;          // FP64 path: largest leaf of the divide-and-conquer tree (gdm_set_fp64_options)
     int mixed_packed = 1;        // expansion matrices stored as upper tiles (gdm_set_mixed_storage)
     int mixed_ns_inv = 2;        // Newton-Schulz iterations per inverse after the quadratic start
     int mixed_max_passes = 16;   // expansion passes allowed for mu
@@ -195,7 +196,7 @@ int gdm_fp64_plan_lds(gdm_ctx* ctx);
 // plan time; eigenvalues and factors from the tridiagonal (BUF_D, BUF_E);
 // products of the core rows with the eigenvector matrix (reverse: with its
 // transpose)
-int gdm_dc_depth(int n);
+int gdm_dc_depth(int n, int leaf);
 int gdm_dc_plan(gdm_ctx* ctx);
 int gdm_dc_solve(gdm_ctx* ctx);
 int gdm_dc_apply(gdm_ctx* ctx, int reverse);

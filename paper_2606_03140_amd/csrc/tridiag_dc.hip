@@ -538,10 +538,18 @@ static int dc_set_lds(gdm_ctx* ctx, const void* fn, size_t bytes) {
     return GDM_OK;
 }
 
-int gdm_dc_depth(int n) {
+int gdm_dc_depth(int n, int leaf) {
     int L = 0;
-    while (((int64_t)n + (1LL << L) - 1) >> L > kLeafMax) ++L;
+    while (((int64_t)n + (1LL << L) - 1) >> L > leaf) ++L;
     return L;
+}
+
+extern "C" int gdm_set_fp64_options(gdm_ctx* ctx, int leaf_rows) {
+    if (!ctx) return GDM_E_ARG;
+    if (leaf_rows < 8 || leaf_rows > kLeafMax)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_set_fp64_options: leaf_rows %d outside [8, %d]", leaf_rows, kLeafMax);
+    ctx->fp64_leaf = leaf_rows;
+    return GDM_OK;
 }
 
 int gdm_dc_plan(gdm_ctx* ctx) {
@@ -554,7 +562,7 @@ int gdm_dc_plan(gdm_ctx* ctx) {
         if (P.n[s] > kDcMaxRows)
             return gdm_fail(ctx, GDM_E_ARG, "gdm_plan: subgraph %d has %d orbitals; the FP64 path takes at most %d", s,
                             P.n[s], kDcMaxRows);
-        P.desc[s].dc_depth = gdm_dc_depth(P.n[s]);
+        P.desc[s].dc_depth = gdm_dc_depth(P.n[s], ctx->fp64_leaf);
         maxL = std::max(maxL, P.desc[s].dc_depth);
     }
     P.dc_max_depth = maxL;
