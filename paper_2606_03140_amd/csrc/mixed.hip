@@ -457,15 +457,17 @@ typedef double double4v __attribute__((ext_vector_type(4)));
 // (four waves of 32 x 32, each 2 x 2 v_mfma_f64_16x16x4f64 blocks).  Operands
 // stream through LDS in k-slabs of 32: each thread loads 8 consecutive
 // elements of A and of B with 16-byte loads, and the next slab is held in
-// registers while the current one is multiplied.  LDS rows are padded to 36
-// (A) and 80 (B) doubles, so the operand reads of a wave (rows fr, k fk of
-// A; k fk, columns fr of B) hit every bank exactly twice.  The tile is staged
+// registers while the current one is multiplied, written to LDS with 16-byte
+// stores.  LDS rows are padded to 34 (A) and 80 (B) doubles: with 64 banks
+// of 4 bytes, the 32 lanes of a half-wave reading rows fr, k fk of A (2 fr +
+// fk distinct mod 32) or k fk, columns fr of B (16 fk + fr distinct mod 32)
+// touch every bank once.  The tile is staged
 // in LDS (row stride 65) and written as coalesced rows; SYM (products of
 // commuting symmetric matrices, upper tiles only) also writes the mirror
 // tile from the transposed LDS read, and on a diagonal tile takes both
 // halves from the upper triangle, so C is exactly symmetric.
 constexpr int kK64 = 32;
-constexpr int kA64Row = kK64 + 4;        // doubles per LDS row of the A slab
+constexpr int kA64Row = kK64 + 2;        // doubles per LDS row of the A slab
 constexpr int kB64Row = 64 + 16;         // doubles per LDS row of the B slab
 constexpr int kC64Row = 64 + 1;          // doubles per LDS row of the staged tile
 constexpr int kG64Lds = 64 * kA64Row + kK64 * kB64Row;    // doubles
@@ -485,7 +487,7 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
                                                const double* __restrict__ Cin, double* __restrict__ C,
                                                double alpha, double beta, double gamma,
                                                const int* __restrict__ skip) {
-    __shared__ double lds[kG64Lds];
+    __shared__ __align__(16) double lds[kG64Lds];
     if (skip && *skip) return;
     double* sA = lds;                        // [64][kA64Row]
     double* sB = lds + 64 * kA64Row;         // [kK64][kB64Row]
@@ -513,9 +515,9 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
     for (int k0 = 0; k0 < P; k0 += kK64) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            sA[ra * kA64Row + ca + q] = va[q];
-            sB[rb * kB64Row + cb + q] = vb[q];
+        for (int q = 0; q < 8; q += 2) {
+            *(double2*)(sA + ra * kA64Row + ca + q) = make_double2(va[q], va[q + 1]);
+            *(double2*)(sB + rb * kB64Row + cb + q) = make_double2(vb[q], vb[q + 1]);
         }
         __syncthreads();
         if (k0 + kK64 < P) {
