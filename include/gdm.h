@@ -97,7 +97,13 @@ typedef struct {
 /* Synthetic two-centre tight-binding model (stand-in for the SCC-DFTB tables):
  * V(r) = v0 exp(-(r - v_r0)/v_decay), S(r) = s0 exp(-(r - s_r0)/s_decay) for
  * r < cutoff, Slater-Koster sigma blocks with direction cosines from the row
- * atom, V_pp_pi = 0. */
+ * atom, V_pp_pi = 0.  For molecular dynamics (forces) the radial functions
+ * can be tapered to zero with two continuous derivatives: with
+ * taper_on > 0 they are multiplied by t(r) = 1 - x^3 (10 - 15 x + 6 x^2),
+ * x = (r - taper_on)/(cutoff - taper_on), between taper_on and cutoff; the
+ * repulsive pair energy sum_{I<J} rep_A[pair] exp(-r/rep_rho) t(r) (pair 0
+ * O-O, 1 O-H, 2 H-H; used by gdm_forces only) stands in for the repulsive
+ * term of SCC-DFTB, which the synthetic model otherwise lacks. */
 typedef struct {
     double onsite[2][4];      /* eV per species and orbital type (s, px, py, pz) */
     int32_t n_orb[2];         /* orbitals per species: 4 and 1                  */
@@ -105,6 +111,9 @@ typedef struct {
     double s0, s_r0, s_decay;
     double cutoff;            /* A, strict r < cutoff                            */
     int32_t orthogonal;       /* 1: S = I                                        */
+    double taper_on;          /* A; 0: hard cutoff (no taper)                    */
+    double rep_A[3];          /* eV, repulsive prefactors O-O, O-H, H-H           */
+    double rep_rho;           /* A, repulsive decay length (> 0 when rep_A used)  */
 } gdm_tb_params;
 
 /* Subgraph set.  Device arrays plus HOST copies of the per-subgraph sizes

@@ -14,6 +14,12 @@ stand-in model is:
   row orbital:  [s_I, s_J] = V, [s_I, p_J^b] = u_b V, [p_I^a, s_J] = -u_a V,
   [p_I^a, p_J^b] = u_a u_b V; the overlap uses the same pattern with S(r).
 * SCC shift (SI section D): H_ab += 1/2 S_ab (V_I + V_J) with V = gamma q.
+* For molecular dynamics: with taper_on > 0 the radial functions are
+  multiplied by t(r) = 1 - x^3 (10 - 15 x + 6 x^2), x = (r - taper_on) /
+  (cutoff - taper_on) on [taper_on, cutoff] (value, slope and curvature
+  continuous at both ends), and a repulsive pair energy
+  sum_{I<J} A_pair exp(-r/rho) t(r) (pairs O-O, O-H, H-H) stands in for the
+  repulsive term of SCC-DFTB.
 
 Minimum image: d = x_j - x_i; d -= L * rint(d * inv_L) with inv_L = 1/L
 computed once; r^2 = (dx*dx + dy*dy) + dz*dz evaluated in exactly this order
@@ -55,6 +61,9 @@ class TBModel:
     orthogonal: bool = False
     kT: float = 0.1
     hubbard_U: tuple = (0.5 * HARTREE_EV, 0.4 * HARTREE_EV)
+    taper_on: float = 0.0
+    rep_A: tuple = (0.0, 0.0, 0.0)
+    rep_rho: float = 0.3
 
     @property
     def beta(self) -> float:
@@ -167,6 +176,10 @@ def dense_hs(pos: np.ndarray, species: np.ndarray, L: float, model: TBModel, ato
     u[~nb] = 0.0
     V = np.where(nb, model.v0 * np.exp(-(r - model.v_r0) / model.v_decay), 0.0)
     Sr = np.where(nb, model.s0 * np.exp(-(r - model.s_r0) / model.s_decay), 0.0)
+    if model.taper_on > 0:
+        t = taper(np.where(nb, r, model.cutoff), model.taper_on, model.cutoff)
+        V = V * t
+        Sr = Sr * t
     # orbital-level expansion
     uo = u[a_of][:, a_of]                                    # [n, n, 3]
     g = _pair_factor(uo, t_of, t_of)
@@ -183,6 +196,28 @@ def dense_hs(pos: np.ndarray, species: np.ndarray, L: float, model: TBModel, ato
         sm = np.eye(len(a_of)) if s is None else s
         h = h + 0.5 * sm * (v[:, None] + v[None, :])
     return h, s
+
+
+def taper(r, r_on: float, r_c: float):
+    """1 below r_on, 1 - x^3 (10 - 15 x + 6 x^2) for x = (r - r_on)/(r_c - r_on)
+    in [0, 1], 0 beyond."""
+    x = np.clip((np.asarray(r, dtype=np.float64) - r_on) / (r_c - r_on), 0.0, 1.0)
+    return 1.0 - x ** 3 * (10.0 - 15.0 * x + 6.0 * x * x)
+
+
+def repulsion_energy(pos: np.ndarray, species: np.ndarray, L: float, model: TBModel) -> float:
+    """sum over neighbour pairs I < J of A_pair exp(-r/rho) t(r) (eV); pair
+    index O-O 0, O-H 1, H-H 2."""
+    rp, col = neighbour_list(pos, L, model.cutoff)
+    n = len(species)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    keep = rows < col
+    i, j = rows[keep], col[keep]
+    r = np.sqrt(r2_of(min_image(pos[j] - pos[i], L, 1.0 / L)))
+    pair = species[i] + species[j]
+    A = np.asarray(model.rep_A, dtype=np.float64)[pair]
+    t = taper(r, model.taper_on, model.cutoff) if model.taper_on > 0 else 1.0
+    return float(np.sum(A * np.exp(-r / model.rep_rho) * t))
 
 
 def single_water_reference(model: TBModel):

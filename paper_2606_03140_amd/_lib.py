@@ -43,7 +43,8 @@ class SystemT(C.Structure):
 class TBParamsT(C.Structure):
     _fields_ = [("onsite", (C.c_double * 4) * 2), ("n_orb", C.c_int32 * 2), ("v0", C.c_double),
                 ("v_r0", C.c_double), ("v_decay", C.c_double), ("s0", C.c_double), ("s_r0", C.c_double),
-                ("s_decay", C.c_double), ("cutoff", C.c_double), ("orthogonal", C.c_int32)]
+                ("s_decay", C.c_double), ("cutoff", C.c_double), ("orthogonal", C.c_int32),
+                ("taper_on", C.c_double), ("rep_A", C.c_double * 3), ("rep_rho", C.c_double)]
 
 
 class SubgraphsT(C.Structure):
@@ -157,6 +158,9 @@ class TBParams:
     s_decay: float = 0.6
     cutoff: float = 4.0
     orthogonal: bool = False
+    taper_on: float = 0.0              # > 0: radial functions tapered to 0 between taper_on and cutoff
+    rep_A: tuple = (0.0, 0.0, 0.0)     # repulsive pair prefactors (eV): O-O, O-H, H-H
+    rep_rho: float = 0.3               # repulsive decay length (A)
 
     def struct(self) -> TBParamsT:
         p = TBParamsT()
@@ -168,6 +172,10 @@ class TBParams:
         p.s0, p.s_r0, p.s_decay = self.s0, self.s_r0, self.s_decay
         p.cutoff = self.cutoff
         p.orthogonal = int(self.orthogonal)
+        p.taper_on = float(self.taper_on)
+        for i in range(3):
+            p.rep_A[i] = float(self.rep_A[i])
+        p.rep_rho = float(self.rep_rho)
         return p
 
 

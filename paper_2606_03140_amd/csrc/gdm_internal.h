@@ -246,6 +246,22 @@ __device__ __forceinline__ int gdm_wave_sumi(int v) {
     return v;
 }
 
+// Taper of the radial functions: 1 below r_on, 1 - x^3 (10 - 15 x + 6 x^2)
+// with x = (r - r_on)/(r_c - r_on) up to r_c; *dt (nullable) = dt/dr
+__host__ __device__ inline double gdm_taper(double r, double r_on, double r_c, double* dt) {
+    if (r <= r_on) {
+        if (dt) *dt = 0.0;
+        return 1.0;
+    }
+    const double w = r_c - r_on, x = (r - r_on) / w;
+    if (x >= 1.0) {
+        if (dt) *dt = 0.0;
+        return 0.0;
+    }
+    if (dt) *dt = -30.0 * x * x * (1.0 - x) * (1.0 - x) / w;
+    return 1.0 - x * x * x * (10.0 - 15.0 * x + 6.0 * x * x);
+}
+
 __device__ __forceinline__ void gdm_raise(int* status, int flag) {
     atomicOr(status, flag);
 }

@@ -58,6 +58,11 @@ __global__ void k_build_hs(int n_atoms, const double* __restrict__ pos, const in
         double u[3] = {dx / r, dy / r, dz / r};
         double V = tb.v0 * exp(-(r - tb.v_r0) / tb.v_decay);
         double Sr = tb.orthogonal ? 0.0 : tb.s0 * exp(-(r - tb.s_r0) / tb.s_decay);
+        if (tb.taper_on > 0.0) {
+            const double t = gdm_taper(r, tb.taper_on, tb.cutoff, nullptr);
+            V = V * t;
+            Sr = Sr * t;
+        }
         const double vj = V_atom ? V_atom[j] : 0.0;
         double* hb = H + (int64_t)k * 16;
         double* sb = S ? S + (int64_t)k * 16 : nullptr;
@@ -254,6 +259,8 @@ extern "C" int gdm_build_hs(gdm_ctx* ctx, const gdm_system* sys, const gdm_tb_pa
         return gdm_fail(ctx, GDM_E_ARG, "gdm_build_hs: null argument or bad size");
     if (tb->n_orb[0] < 1 || tb->n_orb[0] > 4 || tb->n_orb[1] < 1 || tb->n_orb[1] > 4)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_build_hs: orbitals per species must be 1..4");
+    if (tb->taper_on < 0.0 || (tb->taper_on > 0.0 && !(tb->taper_on < tb->cutoff)))
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_build_hs: taper_on must be 0 or in (0, cutoff)");
     double3 L = make_double3(sys->box[0], sys->box[1], sys->box[2]);
     double3 iL = make_double3(sys->inv_box[0], sys->inv_box[1], sys->inv_box[2]);
     const int n = sys->n_atoms;
