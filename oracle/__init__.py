@@ -28,6 +28,12 @@ defines, written in NumPy/SciPy with float64 throughout:
              quasi-Newton SCF built on it (SI sections B and C).
 * learned.py per-atom radial descriptors and the per-species MLP with
              analytic gradients and Adam.
+* forces.py  shadow Born-Oppenheimer potential U(R, n) of the linearised
+             SCC energy and its forces at fixed n (Shadow MD section):
+             band (Hellmann-Feynman, Pulay, SCC shift) from the collected
+             core rows of D and of the energy-weighted W, Coulomb, repulsion.
+* xlbomd.py  extended-Lagrangian MD: velocity Verlet for the nuclei, Verlet
+             with dissipation for the extended charges.
 
 Parity status of each function is listed in its module docstring; a module
 that cannot be pinned says "parity unpinned".
