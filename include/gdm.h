@@ -330,6 +330,71 @@ int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraph
                          const double* S, const double* D_core, const double n0[2],
                          double* q_out);
 
+/* ------------------------------------------------- forces and XL-BOMD (MD) */
+
+/* Energy-weighted density core rows W[core,:] = C[core,:] diag(f lam) C^T of
+ * every subgraph (C the generalized eigenvectors, lam the eigenvalues, f the
+ * Fermi occupations at mu, kT), the matrix of the Pulay term of the forces
+ * (Shadow MD section: forces of the shadow potential at fixed n).  FP64_EIG
+ * path only, after gdm_find_mu, with the same mu and kT as the density.
+ * W_core packed like gdm_subgraph_density's D_core.  GDM_E_STATE before
+ * gdm_find_mu or on another planned precision. */
+int gdm_subgraph_edm(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT, double* W_core);
+
+/* Electronic free energy of the collected solve (the band term of the shadow
+ * potential, Shadow MD section):
+ *   Omega = 2 sum_s sum_k w_k [f_k lam_k + kT (f_k ln f_k + (1 - f_k) ln(1 - f_k))]
+ * with the core weights w_k of each subgraph (0 ln 0 = 0), at mu and kT.
+ * FP64_EIG path only, after gdm_find_mu.  *omega_out HOST (eV).
+ * Synchronises the stream. */
+int gdm_band_energy(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT, double* omega_out);
+
+/* Forces of the shadow Born-Oppenheimer potential at fixed extended charges n
+ * (Shadow MD section, nuclear equation of motion), except the Coulomb term
+ * (gdm_ewald_forces adds it):
+ *   F_I = sum_{J in nbr(I)} grad_d e_IJ(d),  d = R_J - R_I (minimum image),
+ *   e_IJ = 4 sum_{a in I, b in J} [Dbar_ab (H0_ab + S_ab (V_I + V_J)/2) - Wbar_ab S_ab]
+ *          + rep_A[pair] exp(-r/rep_rho) t(r),
+ * the Hellmann-Feynman, Pulay and SCC-shift terms of -2 Tr[D dH[n]/dR] +
+ * 2 Tr[W dS/dR] and the repulsion, with Dbar = (D_IJ + D_JI^T)/2 from the core
+ * rows of I's and J's subgraphs (a block whose far atom is outside the
+ * subgraph counts as zero) and Wbar likewise; H0, S, the taper t and the
+ * repulsion as in gdm_tb_params.  row_ptr/col/nnz: the neighbour CSR H and S
+ * were built on; sg: the planned subgraph set (every atom a core atom of
+ * exactly one subgraph, else the status word reports GDM_E_ARG at
+ * gdm_check); D_core, W_core: gdm_subgraph_density and gdm_subgraph_edm
+ * output; V_atom [n_atoms] (nullable: no SCC shift) the potential H was
+ * built with.  F [n_atoms x 3] eV/A, overwritten.  energy (DEVICE [2],
+ * nullable): energy[0] = the repulsive energy, energy[1] =
+ * -sum_I (n0[species_I] + n_vec_I / 2) V_I (0 when V_atom or n_vec is NULL;
+ * n0 HOST [2] then required); with gdm_band_energy they give
+ * U(R, n) = Omega + energy[0] + energy[1].  Enqueues kernels only; the
+ * per-pair workspace (32 B per CSR entry) grows on demand. */
+int gdm_forces(gdm_ctx* ctx, const gdm_system* sys, const gdm_tb_params* tb, const int32_t* row_ptr,
+               const int32_t* col, int64_t nnz, const gdm_subgraphs* sg, const double* D_core,
+               const double* W_core, const double* V_atom, const double n0[2], const double* n_vec,
+               double* F, double* energy);
+
+/* Velocity Verlet half step of XL-BOMD (Shadow MD section, nuclear equation
+ * of motion): vel += dt/2 F / m (m = mass[species], HOST [2] amu; F eV/A;
+ * vel A/fs, [n x 3]); then, when pos is not NULL, pos += dt vel (A).
+ * kinetic (DEVICE [1], nullable): 1/2 sum m vel^2 in eV after the update.
+ * Enqueues kernels only. */
+int gdm_md_verlet(gdm_ctx* ctx, int32_t n, const int32_t* species, const double mass[2], double dt,
+                  const double* F, double* vel, double* pos, double* kinetic);
+
+/* Extended charges of XL-BOMD (Shadow MD section, harmonic equation of the
+ * extended density, Verlet form with the dissipation of Niklasson et al.,
+ * J. Chem. Phys. 130, 214109 (2009), K = 5):
+ *   n_{t+1} = 2 n_t - n_{t-1} + kappa_c (q - n_t) + alpha sum_k c_k n_{t-k},
+ *   c = (-6, 14, -8, -3, 4, -1), with kappa_c = kappa c for the kernel
+ *   K = c I (kappa = 1.82, alpha = 0.018 in that reference).
+ * hist DEVICE [6 x n]: row k holds n_{t-k}; it is shifted in place so that
+ * row 0 becomes n_{t+1}.  q = q[n_t] [n]; n_out [n] (nullable) receives
+ * n_{t+1}.  Enqueues one kernel. */
+int gdm_xlbomd_charges(gdm_ctx* ctx, int32_t n, const double* q, double* hist, double kappa_c, double alpha,
+                       double* n_out);
+
 /* Options of the mixed-precision expansion (GDM_MIXED_F16; its last doubling
  * of every pass runs in FP64 on the matrix cores, which squares away the
  * split products' errors in the fully occupied and empty states so that the
@@ -415,6 +480,22 @@ int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out);
 int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr,
                         const int32_t* col, double rcut, double eta, int32_t k_max,
                         const double hubbard_U[2], const double* tau, const double* q, double* V);
+
+/* Coulomb forces of the shadow potential (Shadow MD section): F += -d/dR of
+ * q^T gamma n - n^T gamma n / 2 = 1/2 (2q - n)^T gamma n at fixed q and n,
+ * with gamma the kernel of gdm_ewald_potential without the on-site U (which
+ * does not depend on the positions); q = q[n] the Mulliken charges, n_vec
+ * the extended charges (q = n_vec gives the plain Coulomb force of
+ * 1/2 q^T gamma q).  Real space over
+ * row_ptr/col (pairs at r >= rcut skipped), reciprocal space over the
+ * half space of k with |k| <= 2 pi k_max / max(L); tau (HOST [2], nullable)
+ * adds the derivative of the screening.  Same limits as
+ * gdm_ewald_potential (2 rcut < every box side, 1 <= k_max <= 64).
+ * q, n_vec [n_atoms]; F [n_atoms x 3] eV/A, ADDED to.  Enqueues kernels
+ * only; its k-vector table and structure factors use context workspace. */
+int gdm_ewald_forces(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, const int32_t* col,
+                     double rcut, double eta, int32_t k_max, const double* tau, const double* q,
+                     const double* n_vec, double* F);
 
 /* gdm_ewald_potential without any allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,

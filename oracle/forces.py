@@ -196,6 +196,7 @@ class Ewald:
     n_real: int = 2
     k_max: int = 8
     screened: bool = True
+    short_cut: float = np.inf       # screening over pairs closer than this (A)
 
 
 @dataclass
@@ -215,7 +216,7 @@ def shadow_point(pos, species, L, model: TBModel, subs, n: np.ndarray, ew: Ewald
     (a single subgraph of every atom for the full system)."""
     U_h = np.asarray(model.hubbard_U)
     V = coulomb_potential(pos, species, n, L, U_h, eta=ew.eta, n_real=ew.n_real, k_max=ew.k_max,
-                          screened=ew.screened)
+                          screened=ew.screened, short_cut=ew.short_cut)
     res = solve_system(pos, species, L, model, subs, V_atom=V)
     beta = model.beta
     omega = band_free_energy(res.sols, res.mu, beta)
@@ -229,7 +230,7 @@ def shadow_point(pos, species, L, model: TBModel, subs, n: np.ndarray, ew: Ewald
         Wblk = core_blocks(subs, w_rows, species, rp, col)
         F = band_forces(pos, species, L, model, rp, col, Dblk, Wblk, V)
         F += coulomb_forces(pos, species, 2.0 * res.q - n, n, L, U_h, eta=ew.eta, n_real=ew.n_real,
-                            k_max=ew.k_max, screened=ew.screened)
+                            k_max=ew.k_max, screened=ew.screened, short_cut=ew.short_cut)
         if any(model.rep_A):
             F += repulsion_forces(pos, species, L, model)
     return ShadowResult(U=U, F=F, q=res.q, V=V, omega=omega, e_rep=e_rep, system=res)

@@ -108,6 +108,13 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     sig["gdm_mlp_loss"] = (C.c_int, [P, I32, P, P, P])
     sig["gdm_mlp_backward"] = (C.c_int, [P, I32, P, P, P, P, P, P, P, P, P])
     sig["gdm_adam_step"] = (C.c_int, [P, I32, P, P, P, P, I32, C.c_float, C.c_float, C.c_float, C.c_float])
+    sig["gdm_subgraph_edm"] = (C.c_int, [P, C.POINTER(SubgraphsT), D, D, P])
+    sig["gdm_band_energy"] = (C.c_int, [P, C.POINTER(SubgraphsT), D, D, C.POINTER(C.c_double)])
+    sig["gdm_forces"] = (C.c_int, [P, C.POINTER(SystemT), C.POINTER(TBParamsT), P, P, I64, C.POINTER(SubgraphsT), P,
+                                   P, P, C.POINTER(C.c_double), P, P, P])
+    sig["gdm_ewald_forces"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double), P, P, P])
+    sig["gdm_md_verlet"] = (C.c_int, [P, I32, P, C.POINTER(C.c_double), D, P, P, P, P])
+    sig["gdm_xlbomd_charges"] = (C.c_int, [P, I32, P, P, D, D, P])
     sig["gdm_profile"] = (C.c_int, [P, C.c_int])
     sig["gdm_profile_query"] = (C.c_int, [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)])
     for name, (res, args) in sig.items():
@@ -431,6 +438,48 @@ class Context:
                                                   _ptr(graph.row_ptr), _ptr(graph.col), graph.nnz, _ptr(S),
                                                   _ptr(D_core), n0, _ptr(q)))
         return q
+
+    # ------------------------------------------------------ forces (XL-BOMD)
+    def subgraph_edm(self, sg: Subgraphs, mu: float, kT: float, out: torch.Tensor | None = None):
+        """Energy-weighted density core rows (FP64 path, after find_mu)."""
+        W = out if out is not None else torch.empty(int(sg.dcore_off[-1]), dtype=torch.float64, device=self.dev)
+        self._check(self.lib.gdm_subgraph_edm(self.h, C.byref(sg.struct()), mu, kT, _ptr(W)))
+        return W
+
+    def band_energy(self, sg: Subgraphs, mu: float, kT: float) -> float:
+        e = C.c_double(0.0)
+        self._check(self.lib.gdm_band_energy(self.h, C.byref(sg.struct()), mu, kT, C.byref(e)))
+        return e.value
+
+    def forces(self, system: System, tb: TBParams, graph: Graph, sg: Subgraphs, D_core, W_core, V_atom=None,
+               n_vec=None, out: torch.Tensor | None = None, energy: torch.Tensor | None = None):
+        """Band, Pulay, SCC-shift and repulsive forces [n_atoms, 3]; energy
+        (device [2], optional): repulsion and -sum (n0 + n/2) V."""
+        F = out if out is not None else torch.empty(system.n_atoms, 3, dtype=torch.float64, device=self.dev)
+        n0 = (C.c_double * 2)(*VALENCE)
+        self._check(self.lib.gdm_forces(self.h, C.byref(system.struct()), C.byref(tb.struct()), _ptr(graph.row_ptr),
+                                        _ptr(graph.col), graph.nnz, C.byref(sg.struct()), _ptr(D_core),
+                                        _ptr(W_core), _ptr(V_atom), n0, _ptr(n_vec), _ptr(F), _ptr(energy)))
+        return F
+
+    def ewald_forces(self, system: System, graph: Graph, rcut: float, eta: float, k_max: int, q, n_vec, F,
+                     tau=None):
+        """F += -d/dR (1/2 (2q - n)^T gamma n) (Coulomb part of the shadow forces)."""
+        T = None if tau is None else (C.c_double * 2)(*[float(t) for t in tau])
+        self._check(self.lib.gdm_ewald_forces(self.h, C.byref(system.struct()), _ptr(graph.row_ptr),
+                                              _ptr(graph.col), rcut, eta, int(k_max), T, _ptr(q), _ptr(n_vec),
+                                              _ptr(F)))
+        return F
+
+    def md_verlet(self, system: System, mass, dt: float, F, vel, drift: bool, kinetic=None):
+        m = (C.c_double * 2)(*[float(x) for x in mass])
+        self._check(self.lib.gdm_md_verlet(self.h, system.n_atoms, _ptr(system.species), m, dt, _ptr(F), _ptr(vel),
+                                           _ptr(system.pos) if drift else C.c_void_p(0), _ptr(kinetic)))
+
+    def xlbomd_charges(self, q, hist, kappa_c: float, alpha: float, out=None):
+        self._check(self.lib.gdm_xlbomd_charges(self.h, int(q.numel()), _ptr(q), _ptr(hist), kappa_c, alpha,
+                                                _ptr(out)))
+        return out
 
     def check(self):
         self._check(self.lib.gdm_check(self.h))

@@ -108,6 +108,8 @@ static int status_to_code(gdm_ctx* ctx, int st) {
                                                          "gdm_set_mixed_options ns_z)");
     if (st & GDM_STATUS_NO_BRACKET) return gdm_fail(ctx, GDM_E_NO_BRACKET, "electron count outside the bracket");
     if (st & GDM_STATUS_NAN) return gdm_fail(ctx, GDM_E_NAN, "NaN produced");
+    if (st & GDM_STATUS_PARTITION)
+        return gdm_fail(ctx, GDM_E_ARG, "an atom is not a core atom of exactly one subgraph of the set");
     return gdm_fail(ctx, GDM_E_STATE, "unknown device status %d", st);
 }
 
@@ -338,7 +340,7 @@ extern "C" int gdm_subgraph_density(gdm_ctx* ctx, const gdm_subgraphs* sg, doubl
         return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density: null output or bad mu / kT");
     if (!ctx->solved || ctx->solved_precision != precision)
         return gdm_fail(ctx, GDM_E_STATE, "gdm_subgraph_density: call gdm_find_mu first");
-    if (precision == GDM_FP64_EIG) return gdm_fp64_density(ctx, sg, mu, nullptr, kT, D_core, eig_out);
+    if (precision == GDM_FP64_EIG) return gdm_fp64_density(ctx, sg, mu, nullptr, kT, D_core, eig_out, 0);
     if (eig_out) return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density: eigenvalues exist only for FP64_EIG");
     // the expansion holds X at (mu_pass, kT_solved); other points are reached
     // by the first-order term only, inside its linear range
@@ -364,12 +366,40 @@ extern "C" int gdm_subgraph_density_dmu(gdm_ctx* ctx, const gdm_subgraphs* sg, c
         return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_density_dmu: null argument or bad kT");
     if (!ctx->solved || ctx->solved_precision != precision)
         return gdm_fail(ctx, GDM_E_STATE, "gdm_subgraph_density_dmu: call gdm_find_mu first");
-    if (precision == GDM_FP64_EIG) return gdm_fp64_density(ctx, sg, 0.0, mu_device, kT, D_core, nullptr);
+    if (precision == GDM_FP64_EIG) return gdm_fp64_density(ctx, sg, 0.0, mu_device, kT, D_core, nullptr, 0);
     if (std::fabs(kT - ctx->kT_solved) > 1e-12 * ctx->kT_solved)
         return gdm_fail(ctx, GDM_E_ARG,
                         "gdm_subgraph_density_dmu: kT %.17g differs from gdm_find_mu's %.17g (mixed path)", kT,
                         ctx->kT_solved);
     return gdm_mixed_density(ctx, sg, 0.0, mu_device, kT, D_core);
+}
+
+extern "C" int gdm_subgraph_edm(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT, double* W_core) {
+    if (!ctx) return GDM_E_ARG;
+    int rc;
+    if ((rc = check_plan(ctx, sg, GDM_FP64_EIG, "gdm_subgraph_edm"))) return rc;
+    if (!W_core || !(kT > 0.0) || !std::isfinite(mu))
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_subgraph_edm: null output or bad mu / kT");
+    if (!ctx->solved || ctx->solved_precision != GDM_FP64_EIG)
+        return gdm_fail(ctx, GDM_E_STATE, "gdm_subgraph_edm: call gdm_find_mu (FP64_EIG) first");
+    return gdm_fp64_density(ctx, sg, mu, nullptr, kT, W_core, nullptr, 1);
+}
+
+extern "C" int gdm_band_energy(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, double kT, double* omega_out) {
+    if (!ctx) return GDM_E_ARG;
+    int rc;
+    if ((rc = check_plan(ctx, sg, GDM_FP64_EIG, "gdm_band_energy"))) return rc;
+    if (!omega_out || !(kT > 0.0) || !std::isfinite(mu))
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_band_energy: null output or bad mu / kT");
+    if (!ctx->solved || ctx->solved_precision != GDM_FP64_EIG)
+        return gdm_fail(ctx, GDM_E_STATE, "gdm_band_energy: call gdm_find_mu (FP64_EIG) first");
+    bool ok = true;
+    double* dev = (double*)gdm_buf(ctx, BUF_ESUM, 64, &ok);
+    if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_band_energy: workspace allocation failed");
+    if ((rc = gdm_fp64_band_energy(ctx, mu, kT, dev))) return rc;
+    GDM_HIP(ctx, hipMemcpyAsync(omega_out, dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return GDM_OK;
 }
 
 extern "C" int gdm_mulliken_charges(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* sg,

@@ -695,21 +695,24 @@ __device__ __forceinline__ double fermi_fp64(double x, double beta) {
     return 1.0 / (1.0 + e);
 }
 
-// u = C[core,:] diag(f) (eigenvector order), into the half of the density
-// row buffer that the first (top-level) transposed product reads; the
-// eigenvalues are copied out when asked for.
+// u = C[core,:] diag(f) (eigenvector order), or C[core,:] diag(f lam) for
+// the energy-weighted density, into the half of the density row buffer that
+// the first (top-level) transposed product reads; the eigenvalues are copied
+// out when asked for.
 __global__ void __launch_bounds__(kThreads) k_dcore_init(const SubDesc* __restrict__ desc,
                                                         const int32_t* __restrict__ order,
                                                         const double* __restrict__ G, const double* __restrict__ Lam,
                                                         double mu_host, const double* __restrict__ mu_dev, double beta,
-                                                        double* __restrict__ Y, double* __restrict__ EigOut) {
+                                                        int energy, double* __restrict__ Y,
+                                                        double* __restrict__ EigOut) {
     const double mu = mu_dev ? *mu_dev : mu_host;      // mu from device memory when given
     const SubDesc d = desc[sub_of_block(order)];
     const int n = d.n, nc = d.nc, R2 = 2 * nc;
     const double* g = G + 2 * d.offc;
     double* y = Y + 2 * d.offc + (((d.dc_depth + 1) & 1) ? (int64_t)nc * d.ld : 0);
     for (int k = blockIdx.y; k < n; k += gridDim.y) {
-        const double f = fermi_fp64(Lam[d.offv + k] - mu, beta);
+        const double lam = Lam[d.offv + k];
+        const double f = energy ? fermi_fp64(lam - mu, beta) * lam : fermi_fp64(lam - mu, beta);
         for (int r = threadIdx.x; r < nc; r += kThreads) y[(int64_t)k * nc + r] = g[(int64_t)k * R2 + nc + r] * f;
         if (EigOut && threadIdx.x == 0) EigOut[d.offe + k] = Lam[d.offv + k];
     }
@@ -879,6 +882,46 @@ __global__ void k_mu_out(const double* __restrict__ state, double n_e, double to
     else if (fabs(n - n_e) > tol) gdm_raise(status, GDM_STATUS_NO_BRACKET);
 }
 
+// ------------------------------------------------ band free energy
+// partial[s] = sum_k w_k [f lam + kT (f ln f + (1 - f) ln(1 - f))] over
+// subgraph s (0 ln 0 = 0), then one workgroup adds the partials in subgraph
+// order and doubles the sum (two spins)
+__global__ void __launch_bounds__(kMuK) k_band_partial(const SubDesc* __restrict__ desc,
+                                                      const double* __restrict__ Lam, const double* __restrict__ Wt,
+                                                      double mu, double kT, double* __restrict__ partial) {
+    __shared__ double red[kMuK];
+    const SubDesc d = desc[blockIdx.x];
+    const double beta = 1.0 / kT;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < d.n; k += kMuK) {
+        const double lam = Lam[d.offv + k];
+        const double f = fermi_fp64(lam - mu, beta);
+        const double ent = (f > 0.0 && f < 1.0) ? f * log(f) + (1.0 - f) * log1p(-f) : 0.0;
+        acc += Wt[d.offv + k] * (f * lam + kT * ent);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kMuK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kMuK) k_band_sum(int n_sub, const double* __restrict__ partial,
+                                                  double* __restrict__ out) {
+    __shared__ double red[kMuK];
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < n_sub; s += kMuK) acc += partial[s];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kMuK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = 2.0 * red[0];
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- host
@@ -1031,7 +1074,7 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
 }
 
 int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const double* mu_dev, double kT,
-                     double* D_core, double* eig_out) {
+                     double* D_core, double* eig_out, int energy) {
     Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
     const int32_t* order = (const int32_t*)ctx->b[BUF_ORDER].p;
@@ -1040,8 +1083,8 @@ int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const dou
     {
         GDM_TIMED(ctx, "dcore");
         hipLaunchKernelGGL(k_dcore_init, dim3(P.n_sub, 32), dim3(kThreads), 0, ctx->stream, desc, order,
-                           (const double*)ctx->b[BUF_QC].p, (const double*)ctx->b[BUF_LAM].p, mu, mu_dev, 1.0 / kT, Y,
-                           eig_out);
+                           (const double*)ctx->b[BUF_QC].p, (const double*)ctx->b[BUF_LAM].p, mu, mu_dev, 1.0 / kT, energy,
+                           Y, eig_out);
     }
     GDM_LAUNCH_CHECK(ctx);
     if ((rc = gdm_dc_apply(ctx, 1))) return rc;
@@ -1052,6 +1095,17 @@ int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const dou
                            (const double*)ctx->b[BUF_S].p, (const double*)ctx->b[BUF_A].p,
                            (const double*)ctx->b[BUF_HT].p, Y, D_core);
     }
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+int gdm_fp64_band_energy(gdm_ctx* ctx, double mu, double kT, double* out_dev) {
+    const Plan& P = ctx->plan;
+    double* partial = (double*)ctx->b[BUF_MUPART].p;
+    hipLaunchKernelGGL(k_band_partial, dim3(P.n_sub), dim3(kMuK), 0, ctx->stream, (const SubDesc*)ctx->b[BUF_DESC].p,
+                       (const double*)ctx->b[BUF_LAM].p, (const double*)ctx->b[BUF_W].p, mu, kT, partial);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_band_sum, dim3(1), dim3(kMuK), 0, ctx->stream, P.n_sub, partial, out_dev);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }

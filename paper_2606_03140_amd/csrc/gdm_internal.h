@@ -15,6 +15,7 @@
 #define GDM_STATUS_NAN 4
 #define GDM_STATUS_CAPACITY 8
 #define GDM_STATUS_NO_BRACKET 16
+#define GDM_STATUS_PARTITION 32
 
 __host__ __device__ inline bool gdm_is_mixed(int precision) {
     return precision == GDM_MIXED_F16 || precision == GDM_MIXED_BF16;
@@ -152,7 +153,7 @@ enum {
     BUF_X_HI, BUF_X_LO, BUF_X_F, BUF_Y_HI, BUF_Y_LO, BUF_Y_F, BUF_T_HI, BUF_T_LO, BUF_T_F,
     BUF_Z_HI, BUF_Z_LO, BUF_Z_F, BUF_H_HI, BUF_H_LO, BUF_H_F, BUF_TR, BUF_GERSH, BUF_NDBL,
     BUF_TILES, BUF_PASS, BUF_EWALD, BUF_MIXPART,
-    BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_KRYLOV, BUF_MSTATE,
+    BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_KRYLOV, BUF_MSTATE, BUF_FPAIR, BUF_FMAP, BUF_ESUM,
     BUF_COUNT_
 };
 
@@ -188,8 +189,11 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
                      const double* H, const double* S, double n_e, double kT,
                      double* mu_out, double* n_out);
 // mu_dev: when non-null, the kernel reads mu from this device scalar instead
+// energy != 0: the energy-weighted rows C[core,:] diag(f lam) C^T instead of D
 int gdm_fp64_density(gdm_ctx* ctx, const gdm_subgraphs* sg, double mu, const double* mu_dev, double kT,
-                     double* D_core, double* eig_out);
+                     double* D_core, double* eig_out, int energy);
+// electronic free energy 2 sum_s sum_k w_k [f lam + kT s(f)] of the last FP64 solve (device scalar out)
+int gdm_fp64_band_energy(gdm_ctx* ctx, double mu, double kT, double* out_dev);
 // raise the dynamic-LDS attributes the FP64 kernels need for the current plan
 int gdm_fp64_plan_lds(gdm_ctx* ctx);
 // tridiagonal divide and conquer (FP64 path): work lists and workspace at

@@ -719,6 +719,80 @@ __global__ void k_krylov_apply(int n, int rank, int cap, double alpha, int compl
     nv[i] -= alpha * d;
 }
 
+// a = 2 q - n
+__global__ void k_two_q_minus_n(int n, const double* __restrict__ q, const double* __restrict__ nv,
+                                double* __restrict__ a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 2.0 * q[i] - nv[i];
+}
+
+// dS/dR of slater_short, term by term from its closed form
+__device__ double slater_short_deriv(double ta, double tb, double R) {
+    if (fabs(ta - tb) < 1e-6 * (ta + tb)) {
+        const double t = 0.5 * (ta + tb);
+        const double p = 1.0 / R + 11.0 * t / 16.0 + 3.0 * t * t * R / 16.0 + t * t * t * R * R / 48.0;
+        const double dp = -1.0 / (R * R) + 3.0 * t * t / 16.0 + t * t * t * R / 24.0;
+        return exp(-t * R) * (dp - t * p);
+    }
+    double out = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        const double a = side ? tb : ta, b = side ? ta : tb;
+        const double a2 = a * a, b2 = b * b, d = a2 - b2;
+        const double A = b2 * b2 * a / (2.0 * d * d);
+        const double Bc = (b2 * b2 * b2 - 3.0 * b2 * b2 * a2) / (d * d * d);
+        out += exp(-a * R) * (-a * (A - Bc / R) + Bc / (R * R));
+    }
+    return out;
+}
+
+// F_K += -d/dR_K (1/2 a^T gamma b) with gamma_KJ = k_e [psi(R_J - R_K) - S]:
+//   real space over the cutoff CSR (r < rc): 1/2 k_e sum_J (a_K b_J + a_J b_K) g'(r) u,
+//     g(r) = erfc(eta r)/r (- S(tau_K, tau_J, r) when screened), u = (R_J - R_K)/r;
+//   reciprocal space over the half space of k (weights w_k = 4 pi/V exp(-k^2/4eta^2)/k^2):
+//     -k_e sum_k w_k k [a_K (S_b cos - C_b sin) + b_K (S_a cos - C_a sin)](k . R_K)
+//   with (C_x, S_x)(k) = sum_J x_J (cos, sin)(k . R_J) (the k and -k terms are equal).
+__global__ void k_ewald_force(int n, int nk, const double* __restrict__ pos, const int32_t* __restrict__ species,
+                              double3 L, double3 iL, const int32_t* __restrict__ rp, const int32_t* __restrict__ cl,
+                              double rc, double eta, int screened, double tau0, double tau1,
+                              const double* __restrict__ qa, const double* __restrict__ qb,
+                              const double4* __restrict__ kv, const double* __restrict__ CSa,
+                              const double* __restrict__ CSb, double ke, double* __restrict__ F) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double ti = species[i] == 0 ? tau0 : tau1;
+    const double ai = qa[i], bi = qb[i];
+    const double c2 = 2.0 / sqrt(M_PI);
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = cl[k];
+        double dx, dy, dz;
+        min_image(pos, i, j, L, iL, &dx, &dy, &dz);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(r < rc)) continue;
+        double gp = -erfc(eta * r) / (r * r) - c2 * eta * exp(-eta * eta * r * r) / r;
+        if (screened) gp -= slater_short_deriv(ti, species[j] == 0 ? tau0 : tau1, r);
+        const double w = 0.5 * (ai * qb[j] + qa[j] * bi) * gp / r;
+        fx += w * dx;
+        fy += w * dy;
+        fz += w * dz;
+    }
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int k = 0; k < nk; ++k) {
+        const double4 kk = kv[k];
+        if (kk.w == 0.0) continue;
+        const double ph = kk.x * pos[3 * i] + kk.y * pos[3 * i + 1] + kk.z * pos[3 * i + 2];
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double t = kk.w * (ai * (CSb[2 * k + 1] * cs - CSb[2 * k] * sn) + bi * (CSa[2 * k + 1] * cs - CSa[2 * k] * sn));
+        gx += t * kk.x;
+        gy += t * kk.y;
+        gz += t * kk.z;
+    }
+    F[3 * i] += ke * (fx - gx);
+    F[3 * i + 1] += ke * (fy - gy);
+    F[3 * i + 2] += ke * (fz - gz);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------- host
@@ -941,6 +1015,46 @@ extern "C" int gdm_ewald_potential_noalloc(gdm_ctx* ctx, const gdm_system* sys, 
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_recip, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nk, sys->pos,
                        sys->species, q, dkv, CS, eta, 14.399645, hubbard_U[0], hubbard_U[1], V);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_ewald_forces(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, const int32_t* col,
+                                double rcut, double eta, int32_t k_max, const double* tau, const double* q,
+                                const double* n_vec, double* F) {
+    if (!ctx) return GDM_E_ARG;
+    const double U_unused[2] = {0.0, 0.0};
+    int rc = check_ewald(ctx, sys, row_ptr, col, rcut, eta, k_max, 64, U_unused, tau, q, F, "gdm_ewald_forces");
+    if (rc) return rc;
+    if (!n_vec) return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_forces: null charge vector n_vec");
+    const int w = 2 * k_max + 1;
+    const int nk = (k_max + 1) * w * w;
+    bool ok = true;
+    double* ws = (double*)gdm_buf(ctx, BUF_EWALD, sizeof(double) * (8 * (size_t)nk + sys->n_atoms), &ok);
+    if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_ewald_forces: workspace allocation failed");
+    double4* dkv = (double4*)ws;
+    double* CSa = ws + 4 * (int64_t)nk;
+    double* CSb = CSa + 2 * (int64_t)nk;
+    double* a = CSb + 2 * (int64_t)nk;     // a = 2 q - n
+    const double* b = n_vec;
+    const double V3 = sys->box[0] * sys->box[1] * sys->box[2];
+    const double kc2 = std::pow(2.0 * M_PI * k_max / std::max(sys->box[0], std::max(sys->box[1], sys->box[2])), 2);
+    const int n = sys->n_atoms;
+    const double3 L = make_double3(sys->box[0], sys->box[1], sys->box[2]);
+    const double3 iL = make_double3(sys->inv_box[0], sys->inv_box[1], sys->inv_box[2]);
+    GDM_TIMED(ctx, "ewald_forces");
+    hipLaunchKernelGGL(k_two_q_minus_n, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, q, n_vec, a);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_ktable, dim3((nk + 255) / 256), dim3(256), 0, ctx->stream, k_max, sys->box[0],
+                       sys->box[1], sys->box[2], eta, kc2, V3, dkv);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, a, dkv, CSa);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, b, dkv, CSb);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_force, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nk, sys->pos,
+                       sys->species, L, iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0,
+                       tau ? tau[1] : 0.0, a, b, dkv, CSa, CSb, 14.399645, F);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }

@@ -1,0 +1,203 @@
+"""Extended-Lagrangian Born-Oppenheimer molecular dynamics over the libgdm
+kernels (Shadow MD section).
+
+Each step moves the nuclei by velocity Verlet on the forces of the shadow
+potential U(R, n) at fixed extended charges n (gdm_md_verlet), propagates n
+in a harmonic well centred on its Mulliken charges q[n] with the dissipative
+Verlet form (gdm_xlbomd_charges), and evaluates the new point in one
+linear solve, with no SCF iterations:
+
+    neighbour graph -> halos (cutoff graph, or the adaptive graph G_tau of
+    the previous step's density matrix) -> V[n] (gdm_ewald_potential) ->
+    H[n], S -> mu, D, W (FP64 path) -> q[n], Omega -> forces (gdm_forces +
+    gdm_ewald_forces).
+
+The total free energy E = K + U(R, n), U = Omega + E_rep - sum (N0 + n/2) V,
+is conserved up to the integrator's O(dt^2) fluctuation.  Only orchestration
+lives here; every step is a libgdm call.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from ._lib import FP64_EIG, GRAPH_ADAPTIVE, Context, Subgraphs, System, TBParams
+from .scc import HUBBARD_U, EwaldSetup, ewald_setup, scc_loop, slater_tau
+from .pipeline import Partition, subgraph_cost
+
+MASS = (15.999, 1.008)             # amu, O and H
+KAPPA, ALPHA = 1.82, 0.018         # Niklasson et al. 2009, K = 5
+# tapered radial functions and a repulsive pair term for the synthetic model:
+# an isolated water has zero SCC force at r_OH = 0.96 A, 104.5 degrees
+MD_TB = dict(taper_on=3.5, rep_A=(500.0, 67.92, 12.79), rep_rho=0.3)
+
+
+def md_params(**kw) -> TBParams:
+    return TBParams(**{**MD_TB, **kw})
+
+
+def molecule_cores(system: System, anchor: np.ndarray) -> tuple[torch.Tensor, int]:
+    """One core per molecule (the atoms sharing an anchor), numbered in
+    anchor order."""
+    anchor = np.asarray(anchor)
+    mols = np.unique(anchor)
+    core = np.searchsorted(mols, anchor).astype(np.int32)
+    return torch.as_tensor(core).to(system.pos.device), int(len(mols))
+
+
+@dataclass
+class Point:
+    """Shadow potential and forces at (R, n)."""
+    F: torch.Tensor
+    q: torch.Tensor
+    U: float
+    omega: float
+    e_rep: float
+    e_shift: float
+    mu: float
+    part: Partition
+    D: torch.Tensor
+
+
+@dataclass
+class Record:
+    t: list = field(default_factory=list)
+    e_tot: list = field(default_factory=list)
+    e_pot: list = field(default_factory=list)
+    e_kin: list = field(default_factory=list)
+    rms_qn: list = field(default_factory=list)
+    sizes: list = field(default_factory=list)     # orbitals of each subgraph per step
+
+
+class XLBOMD:
+    """State and steps of one XL-BOMD run on the FP64 path.
+
+    graph: "cutoff" (halos one hop in the neighbour graph) or "adaptive"
+    (G_tau = (G^N G^D + G^D G^N)|_tau from the previous step's D, Eq.
+    Graph_Adaptation, rebuilt every step so that halos expand and contract
+    with the motion)."""
+
+    def __init__(self, ctx: Context, system: System, tb: TBParams, core_of_atom: torch.Tensor, n_cores: int,
+                 kT: float = 0.1, dt: float = 0.25, c: float = 0.3, graph: str = "cutoff", tau: float = 1e-5,
+                 alpha: float = 0.7, screened: bool = True, ewald_tol: float = 1e-10):
+        self.ctx, self.system, self.tb = ctx, system, tb
+        self.core, self.n_cores = core_of_atom, n_cores
+        self.kT, self.dt, self.c = kT, dt, c
+        self.graph_mode, self.tau, self.alpha = graph, tau, alpha
+        self.tau_s = slater_tau(HUBBARD_U) if screened else None
+        self.ewald_tol = ewald_tol
+        n = system.n_atoms
+        dev = system.pos.device
+        self.vel = torch.zeros(n, 3, dtype=torch.float64, device=dev)
+        self.hist = torch.zeros(6, n, dtype=torch.float64, device=dev)
+        self.energy = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.kin = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.mu = 0.0
+        self.point: Point | None = None
+        self.rec = Record()
+        self.t = 0.0
+
+    # ------------------------------------------------------------ pieces
+    def _ewald(self) -> EwaldSetup:
+        return ewald_setup(self.ctx, self.system, tol=self.ewald_tol)
+
+    def _partition(self, prev: Point | None) -> Partition:
+        ctx, sysm = self.ctx, self.system
+        nbr = ctx.build_graph_cutoff(sysm, self.tb.cutoff)
+        g = nbr
+        if self.graph_mode == "adaptive" and prev is not None:
+            g = ctx.build_graph_dm(sysm, GRAPH_ADAPTIVE, prev.part.sg, prev.D, self.tau, alpha=self.alpha, nbr=nbr)
+        sg = ctx.extract_subgraphs(sysm, self.tb, g, self.core, self.n_cores)
+        return Partition(nbr=nbr, graph=g, core_of_atom=self.core, n_cores=self.n_cores, sg=sg,
+                         sizes=[sg.norb.copy()], cost0=subgraph_cost(sg))
+
+    def evaluate(self, n_vec: torch.Tensor, prev: Point | None = None) -> Point:
+        """U(R, n), q[n] and the forces at the current positions."""
+        ctx, sysm, tb = self.ctx, self.system, self.tb
+        part = self._partition(prev)
+        ew = self._ewald()
+        V = ctx.ewald_potential(sysm, ew.graph, ew.rcut, ew.eta, ew.k_max, HUBBARD_U, n_vec, tau=self.tau_s)
+        H, S = ctx.build_hs(sysm, tb, part.nbr, V)
+        ctx.plan(part.sg, FP64_EIG)
+        mu, _ = ctx.find_mu(sysm, part.sg, part.nbr, H, S, self.kT, FP64_EIG, self.mu)
+        self.mu = mu
+        D = ctx.subgraph_density(part.sg, mu, self.kT, FP64_EIG)
+        W = ctx.subgraph_edm(part.sg, mu, self.kT)
+        q = ctx.mulliken_charges(sysm, part.sg, part.nbr, S, D)
+        omega = ctx.band_energy(part.sg, mu, self.kT)
+        F = ctx.forces(sysm, tb, part.nbr, part.sg, D, W, V_atom=V, n_vec=n_vec, energy=self.energy)
+        ctx.ewald_forces(sysm, ew.graph, ew.rcut, ew.eta, ew.k_max, q, n_vec, F, tau=self.tau_s)
+        e_rep, e_shift = (float(x) for x in self.energy.cpu())
+        ctx.check()
+        return Point(F=F, q=q, U=omega + e_rep + e_shift, omega=omega, e_rep=e_rep, e_shift=e_shift, mu=mu,
+                     part=part, D=D)
+
+    # ------------------------------------------------------------ run
+    def start(self, n0: torch.Tensor, vel0) -> None:
+        """n = n0 (the converged SCC charges) in every history slot."""
+        self.hist.copy_(n0.to(self.hist.dtype).expand(6, -1))
+        self.vel.copy_(torch.as_tensor(np.asarray(vel0, dtype=np.float64)))
+        self.point = self.evaluate(self.hist[0].clone())
+        if self.graph_mode == "adaptive":      # halos from the solved D
+            self.point = self.evaluate(self.hist[0].clone(), self.point)
+        self.ctx.md_verlet(self.system, MASS, 0.0, self.point.F, self.vel, drift=False, kinetic=self.kin)
+        self._record()
+
+    def _record(self) -> None:
+        p = self.point
+        ek = float(self.kin.cpu()[0])
+        r = self.rec
+        r.t.append(self.t)
+        r.e_kin.append(ek)
+        r.e_pot.append(p.U)
+        r.e_tot.append(ek + p.U)
+        d = p.q.cpu().numpy() - self.hist[0].cpu().numpy()
+        r.rms_qn.append(float(np.sqrt(np.mean(d * d))))
+        r.sizes.append(p.part.sg.norb.copy())
+
+    def step(self) -> None:
+        ctx, sysm = self.ctx, self.system
+        p = self.point
+        ctx.md_verlet(sysm, MASS, self.dt, p.F, self.vel, drift=True)
+        ctx.xlbomd_charges(p.q, self.hist, KAPPA * self.c, ALPHA)
+        self.point = self.evaluate(self.hist[0].clone(), p)
+        ctx.md_verlet(sysm, MASS, self.dt, self.point.F, self.vel, drift=False, kinetic=self.kin)
+        self.t += self.dt
+        self._record()
+
+    def run(self, steps: int) -> Record:
+        for _ in range(steps):
+            self.step()
+        return self.rec
+
+
+def converged_charges(ctx: Context, system: System, tb: TBParams, core, n_cores: int, kT: float = 0.1,
+                      tol: float = 1e-9, screened: bool = True, mixer: str = "anderson", mix: float = 0.03,
+                      depth: int = 8) -> torch.Tensor:
+    """SCC ground-state charges on the cutoff-graph halos (the starting n).
+    Anderson needs a memory well below the number of atoms; a few molecules
+    converge with linear mixing (mixer="linear", mix=0.3)."""
+    nbr = ctx.build_graph_cutoff(system, tb.cutoff)
+    sg = ctx.extract_subgraphs(system, tb, nbr, core, n_cores)
+    part = Partition(nbr=nbr, graph=nbr, core_of_atom=core, n_cores=n_cores, sg=sg)
+    res = scc_loop(ctx, system, tb, part, kT, FP64_EIG, tol=tol, max_iter=400, screened=screened, mixer=mixer,
+                   mix=mix, depth=depth)
+    if not res.converged:
+        raise RuntimeError(f"SCC did not converge in {res.iterations} iterations")
+    return res.q
+
+
+def maxwell_velocities(species: np.ndarray, temperature: float, seed: int) -> np.ndarray:
+    """Seeded Maxwell velocities (A/fs) at `temperature` K, zero total momentum."""
+    kB = 8.617333262e-5
+    m = np.array(MASS)[species]
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=(len(species), 3)) * np.sqrt(kB * temperature / (m[:, None] * 103.6426965))
+    v -= (m[:, None] * v).sum(axis=0) / m.sum()
+    return v
+
+
+__all__ = ["XLBOMD", "MD_TB", "MASS", "KAPPA", "ALPHA", "md_params", "molecule_cores", "converged_charges",
+           "maxwell_velocities"]
