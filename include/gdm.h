@@ -384,16 +384,25 @@ int gdm_md_verlet(gdm_ctx* ctx, int32_t n, const int32_t* species, const double 
                   const double* F, double* vel, double* pos, double* kinetic);
 
 /* Extended charges of XL-BOMD (Shadow MD section, harmonic equation of the
- * extended density, Verlet form with the dissipation of Niklasson et al.,
- * J. Chem. Phys. 130, 214109 (2009), K = 5):
- *   n_{t+1} = 2 n_t - n_{t-1} + kappa_c (q - n_t) + alpha sum_k c_k n_{t-k},
- *   c = (-6, 14, -8, -3, 4, -1), with kappa_c = kappa c for the kernel
- *   K = c I (kappa = 1.82, alpha = 0.018 in that reference).
+ * extended density with the kernel K, Verlet form with the dissipation of
+ * Niklasson et al., J. Chem. Phys. 130, 214109 (2009), K = 5):
+ *   n_{t+1} = 2 n_t - n_{t-1} + kappa_c d + alpha sum_k c_k n_{t-k},
+ *   c = (-6, 14, -8, -3, 4, -1), d = K (q[n_t] - n_t):
+ *   delta NULL: d = q - n_t (the kernel c I with kappa_c = kappa c);
+ *   else d = delta (e.g. -J^-1 (q - n_t) from the low-rank Krylov kernel of
+ *   gdm_krylov_*, with kappa_c = kappa);  kappa = 1.82, alpha = 0.018 in
+ *   that reference.
  * hist DEVICE [6 x n]: row k holds n_{t-k}; it is shifted in place so that
- * row 0 becomes n_{t+1}.  q = q[n_t] [n]; n_out [n] (nullable) receives
- * n_{t+1}.  Enqueues one kernel. */
-int gdm_xlbomd_charges(gdm_ctx* ctx, int32_t n, const double* q, double* hist, double kappa_c, double alpha,
-                       double* n_out);
+ * row 0 becomes n_{t+1}.  q = q[n_t] [n] (used when delta is NULL), delta
+ * [n] (nullable); n_out [n] (nullable) receives n_{t+1}.  Enqueues one
+ * kernel. */
+int gdm_xlbomd_charges(gdm_ctx* ctx, int32_t n, const double* q, const double* delta, double* hist,
+                       double kappa_c, double alpha, double* n_out);
+
+/* out = a x + b y over n doubles (device; out may alias x or y): the charge
+ * vectors of the finite-difference responses of the XL-BOMD kernel.
+ * Enqueues one kernel. */
+int gdm_axpby(gdm_ctx* ctx, int32_t n, double a, const double* x, double b, const double* y, double* out);
 
 /* Options of the mixed-precision expansion (GDM_MIXED_F16; its last doubling
  * of every pass runs in FP64 on the matrix cores, which squares away the

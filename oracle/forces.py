@@ -204,6 +204,7 @@ class ShadowResult:
     U: float                 # shadow potential (eV)
     F: np.ndarray            # [N, 3] eV/A
     q: np.ndarray            # Mulliken charges q[n]
+    n: np.ndarray            # the extended charges n
     V: np.ndarray            # V[n]
     omega: float
     e_rep: float
@@ -233,7 +234,8 @@ def shadow_point(pos, species, L, model: TBModel, subs, n: np.ndarray, ew: Ewald
                             k_max=ew.k_max, screened=ew.screened, short_cut=ew.short_cut)
         if any(model.rep_A):
             F += repulsion_forces(pos, species, L, model)
-    return ShadowResult(U=U, F=F, q=res.q, V=V, omega=omega, e_rep=e_rep, system=res)
+    return ShadowResult(U=U, F=F, q=res.q, n=np.array(n, dtype=np.float64), V=V, omega=omega, e_rep=e_rep,
+                        system=res)
 
 
 def whole(n_atoms: int):

@@ -74,12 +74,13 @@ def fixed_point(charge_map, n0, mix: float = 0.3, tol: float = 1e-5, max_iter: i
 
 def scc(pos, species, L, model: TBModel, subs, q_start=None, mix: float = 0.03, tol: float = 1e-5,
         max_iter: int = 200, eta=None, n_real: int = 2, k_max: int = 8, mixer: str = "anderson", depth: int = 8,
-        short_cut: float = np.inf):
+        short_cut: float = np.inf, screened: bool = True):
     """Returns (q, iterations, residual history)."""
     U = np.asarray(model.hubbard_U)
 
     def charge_map(n):
-        V = coulomb_potential(pos, species, n, L, U, eta=eta, n_real=n_real, k_max=k_max, short_cut=short_cut)
+        V = coulomb_potential(pos, species, n, L, U, eta=eta, n_real=n_real, k_max=k_max, short_cut=short_cut,
+                              screened=screened)
         return solve_system(pos, species, L, model, subs, V_atom=V).q
 
     n0 = np.zeros(len(species)) if q_start is None else q_start

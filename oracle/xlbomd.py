@@ -32,8 +32,10 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from .ewald import coulomb_potential
 from .forces import Ewald, shadow_point
 from .model import TBModel
+from .response import charge_response, krylov_step
 
 KAPPA = 1.82
 ALPHA = 0.018
@@ -43,11 +45,32 @@ KE_EV = 103.6426965           # eV per amu A^2/fs^2
 MASS = np.array([15.999, 1.008])
 
 
-def next_charges(hist: list, q_t: np.ndarray, c: float) -> np.ndarray:
-    """n_{t+1} from hist = [n_t, n_{t-1}, ..., n_{t-5}] and q_t = q[n_t]."""
+def next_charges(hist: list, q_t: np.ndarray, c: float, delta: np.ndarray | None = None) -> np.ndarray:
+    """n_{t+1} from hist = [n_t, n_{t-1}, ..., n_{t-5}] and q_t = q[n_t]; the
+    driving term is kappa c (q_t - n_t), or kappa delta with delta = K (q_t - n_t)
+    of another kernel."""
     n_t, n_m1 = hist[0], hist[1]
     diss = sum(ck * hk for ck, hk in zip(C_DISS, hist))
-    return 2.0 * n_t - n_m1 + KAPPA * c * (q_t - n_t) + ALPHA * diss
+    drive = KAPPA * c * (q_t - n_t) if delta is None else KAPPA * delta
+    return 2.0 * n_t - n_m1 + drive + ALPHA * diss
+
+
+def krylov_kernel(st, pos, species, L, model: TBModel, subs, ew: Ewald, rank_tol: float, max_rank: int,
+                  k0: float) -> np.ndarray:
+    """delta = -J^-1 (q[n] - n) by the low-rank preconditioned Krylov kernel
+    (response.krylov_step, completed), J v = dq[gamma v] - v from the
+    first-order charge response at the solve of `st`."""
+    U = np.asarray(model.hubbard_U)
+
+    def jv(v):
+        dV = coulomb_potential(pos, species, v, L, U, eta=ew.eta, n_real=ew.n_real, k_max=ew.k_max,
+                               screened=ew.screened, short_cut=ew.short_cut)
+        dq, _, _ = charge_response(pos, species, L, model, subs, st.V, dV, mu=st.system.mu, sols=st.system.sols)
+        return dq - v
+
+    f = st.q - st.n
+    dn, _, _ = krylov_step(f, jv, rank_tol=rank_tol, max_rank=max_rank, k0=k0, complete=True)
+    return dn
 
 
 def kinetic(v: np.ndarray, m: np.ndarray) -> float:
@@ -64,9 +87,12 @@ class Trajectory:
 
 
 def run(pos0, vel0, species, L, model: TBModel, subs, n0, ew: Ewald, dt: float, steps: int, c: float = 1.0,
-        keep_pos: bool = False) -> Trajectory:
+        keep_pos: bool = False, kernel: str = "scaled", rank_tol: float = 0.1, max_rank: int = 6,
+        k0: float = 0.1) -> Trajectory:
     """XL-BOMD from (pos0, vel0) with n = n0 (converged SCC charges);
-    `subs(pos)` returns the subgraph set at a geometry."""
+    `subs(pos)` returns the subgraph set at a geometry.  kernel "scaled":
+    K = c I; "krylov": K = -J^-1 by the low-rank Krylov kernel, rebuilt at
+    every step."""
     m = MASS[species]
     R = np.array(pos0, dtype=np.float64)
     v = np.array(vel0, dtype=np.float64)
@@ -85,8 +111,11 @@ def run(pos0, vel0, species, L, model: TBModel, subs, n0, ew: Ewald, dt: float, 
     record(0.0, st)
     for k in range(1, steps + 1):
         v += 0.5 * dt * ACCEL * st.F / m[:, None]
+        delta = None
+        if kernel == "krylov":
+            delta = krylov_kernel(st, R, species, L, model, subs(R), ew, rank_tol, max_rank, k0)
         R = R + dt * v
-        n_new = next_charges(hist, st.q, c)
+        n_new = next_charges(hist, st.q, c, delta)
         hist = [n_new] + hist[:5]
         st = shadow_point(R, species, L, model, subs(R), n_new, ew)
         v += 0.5 * dt * ACCEL * st.F / m[:, None]

@@ -114,7 +114,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                    P, P, C.POINTER(C.c_double), P, P, P])
     sig["gdm_ewald_forces"] = (C.c_int, [P, C.POINTER(SystemT), P, P, D, D, I32, C.POINTER(C.c_double), P, P, P])
     sig["gdm_md_verlet"] = (C.c_int, [P, I32, P, C.POINTER(C.c_double), D, P, P, P, P])
-    sig["gdm_xlbomd_charges"] = (C.c_int, [P, I32, P, P, D, D, P])
+    sig["gdm_xlbomd_charges"] = (C.c_int, [P, I32, P, P, P, D, D, P])
+    sig["gdm_axpby"] = (C.c_int, [P, I32, D, P, D, P, P])
     sig["gdm_profile"] = (C.c_int, [P, C.c_int])
     sig["gdm_profile_query"] = (C.c_int, [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)])
     for name, (res, args) in sig.items():
@@ -476,9 +477,14 @@ class Context:
         self._check(self.lib.gdm_md_verlet(self.h, system.n_atoms, _ptr(system.species), m, dt, _ptr(F), _ptr(vel),
                                            _ptr(system.pos) if drift else C.c_void_p(0), _ptr(kinetic)))
 
-    def xlbomd_charges(self, q, hist, kappa_c: float, alpha: float, out=None):
-        self._check(self.lib.gdm_xlbomd_charges(self.h, int(q.numel()), _ptr(q), _ptr(hist), kappa_c, alpha,
-                                                _ptr(out)))
+    def xlbomd_charges(self, q, hist, kappa_c: float, alpha: float, out=None, delta=None):
+        self._check(self.lib.gdm_xlbomd_charges(self.h, int(hist.shape[1]), _ptr(q), _ptr(delta), _ptr(hist),
+                                                kappa_c, alpha, _ptr(out)))
+        return out
+
+    def axpby(self, a: float, x, b: float, y, out):
+        """out = a x + b y (device vectors)."""
+        self._check(self.lib.gdm_axpby(self.h, int(x.numel()), a, _ptr(x), b, _ptr(y), _ptr(out)))
         return out
 
     def check(self):

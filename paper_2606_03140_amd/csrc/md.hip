@@ -4,10 +4,11 @@
 // Verlet scheme with weak dissipation):
 //
 //   nuclei:  v += dt/2 a(F), R += dt v, (forces at R, n), v += dt/2 a(F);
-//   charges: n_{t+1} = 2 n_t - n_{t-1} + kappa c (q[n_t] - n_t)
+//   charges: n_{t+1} = 2 n_t - n_{t-1} + kappa K (q[n_t] - n_t)
 //                      + alpha sum_{k=0..5} c_k n_{t-k},
 //
-// kappa = dt^2 w^2, the kernel K = c I, and the dissipation coefficients of
+// kappa = dt^2 w^2, the kernel K = c I or K = -J^-1 supplied by the caller
+// (the low-rank Krylov approximation), and the dissipation coefficients of
 // Niklasson et al., J. Chem. Phys. 130, 214109 (2009) for K = 5 (kappa 1.82,
 // alpha 0.018, c_k = -6, 14, -8, -3, 4, -1).  Units: A, fs, eV, amu.
 #include "gdm_internal.h"
@@ -60,9 +61,11 @@ __global__ void __launch_bounds__(kThreads) k_sum(int nb, const double* __restri
     if (threadIdx.x == 0) out[0] = s;
 }
 
-// n_{t+1} from the history hist[k * n + i] = n_{t-k} (k = 0..5) and q = q[n_t];
-// the history shifts by one in place (each thread owns its element)
+// n_{t+1} from the history hist[k * n + i] = n_{t-k} (k = 0..5) and the
+// driving term kc (q - n_t), or kc delta when delta is given; the history
+// shifts by one in place (each thread owns its element)
 __global__ void __launch_bounds__(kThreads) k_xl_charges(int n, const double* __restrict__ q,
+                                                        const double* __restrict__ delta,
                                                         double* __restrict__ hist, double kc, double alpha,
                                                         double* __restrict__ n_out) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
@@ -72,10 +75,18 @@ __global__ void __launch_bounds__(kThreads) k_xl_charges(int n, const double* __
     for (int k = 0; k < 6; ++k) h[k] = hist[(int64_t)k * n + i];
     double diss = 0.0;
     for (int k = 0; k < 6; ++k) diss += c[k] * h[k];
-    const double nn = 2.0 * h[0] - h[1] + kc * (q[i] - h[0]) + alpha * diss;
+    const double drive = delta ? delta[i] : q[i] - h[0];
+    const double nn = 2.0 * h[0] - h[1] + kc * drive + alpha * diss;
     for (int k = 5; k > 0; --k) hist[(int64_t)k * n + i] = h[k - 1];
     hist[i] = nn;
     if (n_out) n_out[i] = nn;
+}
+
+// out = a x + b y (out may alias x or y: each element is read before it is written)
+__global__ void __launch_bounds__(kThreads) k_axpby(int n, double a, const double* x, double b, const double* y,
+                                                   double* out) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) out[i] = a * x[i] + b * y[i];
 }
 
 }  // namespace
@@ -102,13 +113,23 @@ extern "C" int gdm_md_verlet(gdm_ctx* ctx, int32_t n, const int32_t* species, co
     return GDM_OK;
 }
 
-extern "C" int gdm_xlbomd_charges(gdm_ctx* ctx, int32_t n, const double* q, double* hist, double kappa_c,
-                                  double alpha, double* n_out) {
+extern "C" int gdm_xlbomd_charges(gdm_ctx* ctx, int32_t n, const double* q, const double* delta, double* hist,
+                                  double kappa_c, double alpha, double* n_out) {
     if (!ctx) return GDM_E_ARG;
-    if (n <= 0 || !q || !hist || !std::isfinite(kappa_c) || !std::isfinite(alpha))
+    if (n <= 0 || (!q && !delta) || !hist || !std::isfinite(kappa_c) || !std::isfinite(alpha))
         return gdm_fail(ctx, GDM_E_ARG, "gdm_xlbomd_charges: bad argument");
-    hipLaunchKernelGGL(k_xl_charges, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, ctx->stream, n, q, hist,
-                       kappa_c, alpha, n_out);
+    hipLaunchKernelGGL(k_xl_charges, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, ctx->stream, n, q, delta,
+                       hist, kappa_c, alpha, n_out);
+    GDM_LAUNCH_CHECK(ctx);
+    return GDM_OK;
+}
+
+extern "C" int gdm_axpby(gdm_ctx* ctx, int32_t n, double a, const double* x, double b, const double* y,
+                         double* out) {
+    if (!ctx) return GDM_E_ARG;
+    if (n <= 0 || !x || !y || !out) return gdm_fail(ctx, GDM_E_ARG, "gdm_axpby: bad argument");
+    hipLaunchKernelGGL(k_axpby, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, ctx->stream, n, a, x, b, y,
+                       out);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }

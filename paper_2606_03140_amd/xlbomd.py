@@ -18,6 +18,7 @@ lives here; every step is a libgdm call.
 """
 from __future__ import annotations
 
+import time
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -59,6 +60,8 @@ class Point:
     mu: float
     part: Partition
     D: torch.Tensor
+    S: torch.Tensor | None = None
+    ew: EwaldSetup | None = None
 
 
 @dataclass
@@ -76,16 +79,36 @@ class XLBOMD:
 
     graph: "cutoff" (halos one hop in the neighbour graph) or "adaptive"
     (G_tau = (G^N G^D + G^D G^N)|_tau from the previous step's D, Eq.
-    Graph_Adaptation, rebuilt every step so that halos expand and contract
-    with the motion)."""
+    Graph_Adaptation, redrawn every `rebuild` steps so that halos expand and
+    contract with the motion).
+
+    kernel: "scaled" drives n with c (q[n] - n) (the kernel c I; stable only
+    while kappa c times the largest |eigenvalue| of the charge Jacobian J
+    stays below about 4, i.e. for a few molecules), or "krylov": with
+    -J^-1 (q[n] - n) from the low-rank preconditioned Krylov kernel
+    (gdm_krylov_*, K0 = -k0 I, completed on the unfitted remainder), rebuilt
+    at every step.  Its directional derivatives J v = dq - v are one-sided
+    finite differences of the FP64 solve, dq = (q[n + eps v] - q[n]) / eps
+    (the FP64 path forms core rows only, so no perturbation-theory response
+    exists on it); the kernel only preconditions the charge dynamics, so
+    their O(eps) error does not enter the forces or the energy."""
 
     def __init__(self, ctx: Context, system: System, tb: TBParams, core_of_atom: torch.Tensor, n_cores: int,
                  kT: float = 0.1, dt: float = 0.25, c: float = 0.3, graph: str = "cutoff", tau: float = 1e-5,
-                 alpha: float = 0.7, screened: bool = True, ewald_tol: float = 1e-10):
+                 alpha: float = 0.7, screened: bool = True, ewald_tol: float = 1e-10, rebuild: int = 1,
+                 timing: bool = False, kernel: str = "scaled", rank_tol: float = 0.1, max_rank: int = 6,
+                 k0: float = 0.1, fd_eps: float = 1e-5):
+        if kernel not in ("scaled", "krylov"):
+            raise ValueError(f"kernel {kernel!r}")
+        self.kernel, self.rank_tol, self.max_rank, self.k0, self.fd_eps = kernel, rank_tol, max_rank, k0, fd_eps
+        self.ranks: list = []
         self.ctx, self.system, self.tb = ctx, system, tb
         self.core, self.n_cores = core_of_atom, n_cores
         self.kT, self.dt, self.c = kT, dt, c
         self.graph_mode, self.tau, self.alpha = graph, tau, alpha
+        self.rebuild = max(1, int(rebuild))      # halos redrawn every `rebuild` steps
+        self.steps_done = 0
+        self.timing = {} if timing else None
         self.tau_s = slater_tau(HUBBARD_U) if screened else None
         self.ewald_tol = ewald_tol
         n = system.n_atoms
@@ -94,6 +117,11 @@ class XLBOMD:
         self.hist = torch.zeros(6, n, dtype=torch.float64, device=dev)
         self.energy = torch.zeros(2, dtype=torch.float64, device=dev)
         self.kin = torch.zeros(1, dtype=torch.float64, device=dev)
+        if kernel == "krylov":
+            self.kwork = torch.zeros(Context.krylov_work_size(n, max_rank), dtype=torch.float64, device=dev)
+            self.delta = torch.zeros(n, dtype=torch.float64, device=dev)
+            self.n_eps = torch.zeros(n, dtype=torch.float64, device=dev)
+            self.dq = torch.zeros(n, dtype=torch.float64, device=dev)
         self.mu = 0.0
         self.point: Point | None = None
         self.rec = Record()
@@ -104,8 +132,15 @@ class XLBOMD:
         return ewald_setup(self.ctx, self.system, tol=self.ewald_tol)
 
     def _partition(self, prev: Point | None) -> Partition:
+        """Neighbour graph at the current positions; the halos are redrawn
+        every `rebuild` steps (from the previous D in adaptive mode) and
+        otherwise keep the previous subgraph atom lists."""
         ctx, sysm = self.ctx, self.system
         nbr = ctx.build_graph_cutoff(sysm, self.tb.cutoff)
+        if prev is not None and self.steps_done % self.rebuild != 0:
+            p = prev.part
+            return Partition(nbr=nbr, graph=p.graph, core_of_atom=p.core_of_atom, n_cores=p.n_cores, sg=p.sg,
+                             sizes=p.sizes, cost0=p.cost0)
         g = nbr
         if self.graph_mode == "adaptive" and prev is not None:
             g = ctx.build_graph_dm(sysm, GRAPH_ADAPTIVE, prev.part.sg, prev.D, self.tau, alpha=self.alpha, nbr=nbr)
@@ -113,26 +148,74 @@ class XLBOMD:
         return Partition(nbr=nbr, graph=g, core_of_atom=self.core, n_cores=self.n_cores, sg=sg,
                          sizes=[sg.norb.copy()], cost0=subgraph_cost(sg))
 
+    def _lap(self, name: str, t0: float) -> float:
+        if self.timing is None:
+            return t0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        self.timing[name] = self.timing.get(name, 0.0) + (t1 - t0)
+        return t1
+
     def evaluate(self, n_vec: torch.Tensor, prev: Point | None = None) -> Point:
         """U(R, n), q[n] and the forces at the current positions."""
         ctx, sysm, tb = self.ctx, self.system, self.tb
+        t = time.perf_counter()
         part = self._partition(prev)
         ew = self._ewald()
+        t = self._lap("graphs", t)
         V = ctx.ewald_potential(sysm, ew.graph, ew.rcut, ew.eta, ew.k_max, HUBBARD_U, n_vec, tau=self.tau_s)
         H, S = ctx.build_hs(sysm, tb, part.nbr, V)
-        ctx.plan(part.sg, FP64_EIG)
+        t = self._lap("potential_hs", t)
+        if prev is None or part.sg is not prev.part.sg:
+            ctx.plan(part.sg, FP64_EIG)
         mu, _ = ctx.find_mu(sysm, part.sg, part.nbr, H, S, self.kT, FP64_EIG, self.mu)
         self.mu = mu
         D = ctx.subgraph_density(part.sg, mu, self.kT, FP64_EIG)
+        t = self._lap("solve", t)
         W = ctx.subgraph_edm(part.sg, mu, self.kT)
+        t = self._lap("edm", t)
         q = ctx.mulliken_charges(sysm, part.sg, part.nbr, S, D)
         omega = ctx.band_energy(part.sg, mu, self.kT)
+        t = self._lap("charges_energy", t)
         F = ctx.forces(sysm, tb, part.nbr, part.sg, D, W, V_atom=V, n_vec=n_vec, energy=self.energy)
+        t = self._lap("forces", t)
         ctx.ewald_forces(sysm, ew.graph, ew.rcut, ew.eta, ew.k_max, q, n_vec, F, tau=self.tau_s)
+        t = self._lap("ewald_forces", t)
         e_rep, e_shift = (float(x) for x in self.energy.cpu())
         ctx.check()
         return Point(F=F, q=q, U=omega + e_rep + e_shift, omega=omega, e_rep=e_rep, e_shift=e_shift, mu=mu,
-                     part=part, D=D)
+                     part=part, D=D, S=S, ew=ew)
+
+    def _charges_at(self, p: Point, n_vec: torch.Tensor) -> torch.Tensor:
+        """q[n_vec] at the positions and subgraphs of point p (FP64 solve)."""
+        ctx, sysm = self.ctx, self.system
+        ew = p.ew
+        V = ctx.ewald_potential(sysm, ew.graph, ew.rcut, ew.eta, ew.k_max, HUBBARD_U, n_vec, tau=self.tau_s)
+        H, S = ctx.build_hs(sysm, self.tb, p.part.nbr, V)
+        mu, _ = ctx.find_mu(sysm, p.part.sg, p.part.nbr, H, S, self.kT, FP64_EIG, p.mu)
+        D = ctx.subgraph_density(p.part.sg, mu, self.kT, FP64_EIG)
+        return ctx.mulliken_charges(sysm, p.part.sg, p.part.nbr, S, D)
+
+    def _krylov_delta(self, p: Point, n_t: torch.Tensor) -> torch.Tensor:
+        """-J^-1 (q[n_t] - n_t) at point p by the low-rank Krylov kernel."""
+        ctx, N = self.ctx, self.system.n_atoms
+        t = time.perf_counter()
+        ctx.krylov_begin(n_t, p.q, self.max_rank, self.kwork, self.k0)
+        rank = 0
+        for j in range(self.max_rank):
+            v = Context.krylov_vector(self.kwork, N, j)
+            ctx.axpby(1.0, n_t, self.fd_eps, v, self.n_eps)
+            q_eps = self._charges_at(p, self.n_eps)
+            ctx.axpby(1.0 / self.fd_eps, q_eps, -1.0 / self.fd_eps, p.q, self.dq)
+            rel, exhausted = ctx.krylov_add(N, j, self.dq, self.max_rank, self.kwork)
+            rank = j + 1
+            if rel <= self.rank_tol or exhausted:
+                break
+        self.ranks.append(rank)
+        self.delta.zero_()
+        ctx.krylov_apply(self.delta, rank, self.max_rank, self.kwork, 1.0, complete=True)
+        self._lap("kernel", t)
+        return self.delta
 
     # ------------------------------------------------------------ run
     def start(self, n0: torch.Tensor, vel0) -> None:
@@ -160,8 +243,13 @@ class XLBOMD:
     def step(self) -> None:
         ctx, sysm = self.ctx, self.system
         p = self.point
+        if self.kernel == "krylov":
+            delta = self._krylov_delta(p, self.hist[0])
+            ctx.xlbomd_charges(p.q, self.hist, KAPPA, ALPHA, delta=delta)
+        else:
+            ctx.xlbomd_charges(p.q, self.hist, KAPPA * self.c, ALPHA)
         ctx.md_verlet(sysm, MASS, self.dt, p.F, self.vel, drift=True)
-        ctx.xlbomd_charges(p.q, self.hist, KAPPA * self.c, ALPHA)
+        self.steps_done += 1
         self.point = self.evaluate(self.hist[0].clone(), p)
         ctx.md_verlet(sysm, MASS, self.dt, self.point.F, self.vel, drift=False, kinetic=self.kin)
         self.t += self.dt

@@ -124,13 +124,13 @@ def dimer_box(gap=(3.3, 3.1, 5.9), L=24.0):
     return pos, sp, anchor, L
 
 
-def gpu_md(c, pos, sp, anchor, L, vel, dt, steps, graph="cutoff", n0=None):
+def gpu_md(c, pos, sp, anchor, L, vel, dt, steps, graph="cutoff", n0=None, **kw):
     system = System(pos, sp, anchor, (L, L, L))
     tb = xlbomd.md_params()
     core, nco = xlbomd.molecule_cores(system, anchor)
     if n0 is None:
         n0 = xlbomd.converged_charges(c, system, tb, core, nco, tol=1e-10, mixer="linear", mix=0.3)
-    md = xlbomd.XLBOMD(c, system, tb, core, nco, dt=dt, c=0.3, graph=graph)
+    md = xlbomd.XLBOMD(c, system, tb, core, nco, dt=dt, c=0.3, graph=graph, **kw)
     md.start(n0, vel)
     md.run(steps)
     return md, system
@@ -157,6 +157,33 @@ def test_xlbomd_follows_oracle_trajectory(c):
     np.testing.assert_allclose(system.pos.cpu().numpy(), tr.pos[-1], rtol=0, atol=1e-9)
 
 
+def test_xlbomd_krylov_kernel_follows_oracle(c):
+    """The Krylov kernel at full rank (every charge direction fitted) is
+    -J^-1 itself; the GPU's finite-difference responses and the oracle's
+    perturbation theory then agree to the difference step (1e-5)."""
+    pos, sp, anchor, L = dimer_box()
+    vel = xlbomd.maxwell_velocities(sp, 600.0, 5)
+    kw = dict(kernel="krylov", max_rank=6, rank_tol=1e-9, k0=0.1)
+    md, system = gpu_md(c, pos, sp, anchor, L, vel, 0.25, 8, **kw)
+    ew = ewald_setup(c, system)
+    model = om.TBModel(**MD)
+    oew = oracle_ewald(ew)
+    core = np.array([0, 0, 0, 1, 1, 1])
+
+    def subs(R):
+        rp, col = om.neighbour_list(R, L)
+        return og.extract_subgraphs(rp, col, core, 2)
+
+    q0, _, _ = oscc.scc(pos, sp, L, model, subs(pos), mix=0.3, tol=1e-11, max_iter=400, eta=oew.eta,
+                        n_real=oew.n_real, k_max=oew.k_max, short_cut=oew.short_cut)
+    tr = oxl.run(pos, vel, sp, L, model, subs, q0, oew, 0.25, 8, keep_pos=True, **kw)
+    log(f"dimer, Krylov kernel (ranks {md.ranks}): max rms(q - n) GPU {max(md.rec.rms_qn):.2e} "
+        f"oracle {max(tr.rms_qn):.2e}")
+    np.testing.assert_allclose(md.rec.rms_qn, tr.rms_qn, rtol=1e-3, atol=1e-9)
+    np.testing.assert_allclose(md.rec.e_tot, tr.e_tot, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(system.pos.cpu().numpy(), tr.pos[-1], rtol=0, atol=1e-8)
+
+
 def test_xlbomd_energy_fluctuation_fourfold(c):
     pos, sp, anchor, L = dimer_box()
     vel = xlbomd.maxwell_velocities(sp, 600.0, 7)
@@ -168,6 +195,33 @@ def test_xlbomd_energy_fluctuation_fourfold(c):
         log(f"dt {dt}: fluctuation {amp[-1]:.3e} eV, max rms(q - n) {max(md.rec.rms_qn):.2e}")
     log(f"ratios {amp[0] / amp[1]:.2f} {amp[1] / amp[2]:.2f}")
     assert 3.3 < amp[0] / amp[1] < 4.7 and 3.3 < amp[1] / amp[2] < 4.7
+
+
+def test_xlbomd_condensed_phase_krylov_kernel(c):
+    """96 waters in their periodic box, 8 grid cores with one-hop halos: the
+    strong collective charge response makes the kernel c I unstable, the
+    Krylov kernel keeps q[n] - n small and the total free energy
+    fluctuation falls with dt (Shadow MD results: about four per
+    doubling)."""
+    box = waterbox.water_box(96, 1)
+    system = System(box.pos, box.species, box.anchor, box.box)
+    tb = xlbomd.md_params()
+    core, nco = c.grid_cores(system, (2, 2, 2))
+    n0 = xlbomd.converged_charges(c, system, tb, core, nco, tol=1e-8)
+    vel = xlbomd.maxwell_velocities(box.species, 300.0, 5005)
+    amp = []
+    for dt in (0.5, 0.25):
+        sysm = System(box.pos, box.species, box.anchor, box.box)
+        md = xlbomd.XLBOMD(c, sysm, tb, core, nco, dt=dt, kernel="krylov")
+        md.start(n0, vel)
+        md.run(int(round(6.0 / dt)))
+        e = np.array(md.rec.e_tot)
+        amp.append(e.max() - e.min())
+        log(f"96 waters dt {dt}: fluctuation {amp[-1]:.3e} eV, max rms(q - n) {max(md.rec.rms_qn):.2e}, "
+            f"kernel ranks {np.mean(md.ranks):.1f}")
+        assert max(md.rec.rms_qn) < 1e-2
+    log(f"ratio {amp[0] / amp[1]:.2f}")
+    assert amp[1] < 1e-2 and 3.0 < amp[0] / amp[1] < 7.0
 
 
 def test_halos_expand_and_contract(c):
