@@ -138,20 +138,27 @@ __global__ void __launch_bounds__(kThreads) k_pair_forces(
     const double r = sqrt((dx * dx + dy * dy) + dz * dz);
     const double u[3] = {dx / r, dy / r, dz / r};
     // symmetrised blocks Dbar, Wbar (rows: orbitals of I, columns: of J)
+    // (loops over the 4 x 4 block fully unrolled so that the blocks stay
+    // in registers; entries beyond the atoms' orbital counts stay zero)
     double Db[4][4], Wb[4][4];
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
         for (int b = 0; b < 4; ++b) Db[a][b] = Wb[a][b] = 0.0;
     {
         const SubDesc d = desc[sub_of[I]];
         const int kj = find_local(d, atoms, J);
         if (kj >= 0) {
             const int64_t row0 = loff[d.atom0 + loc_of[I]], c0 = loff[d.atom0 + kj];
-            for (int a = 0; a < ni; ++a)
-                for (int b = 0; b < nj; ++b) {
-                    const int64_t e = d.offd + (row0 + a) * d.n + c0 + b;
-                    Db[a][b] += 0.5 * Dc[e];
-                    Wb[a][b] += 0.5 * Wc[e];
-                }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (a < ni && b < nj) {
+                        const int64_t e = d.offd + (row0 + a) * d.n + c0 + b;
+                        Db[a][b] += 0.5 * Dc[e];
+                        Wb[a][b] += 0.5 * Wc[e];
+                    }
         }
     }
     {
@@ -159,12 +166,15 @@ __global__ void __launch_bounds__(kThreads) k_pair_forces(
         const int ki = find_local(d, atoms, I);
         if (ki >= 0) {
             const int64_t row0 = loff[d.atom0 + loc_of[J]], c0 = loff[d.atom0 + ki];
-            for (int b = 0; b < nj; ++b)
-                for (int a = 0; a < ni; ++a) {
-                    const int64_t e = d.offd + (row0 + b) * d.n + c0 + a;
-                    Db[a][b] += 0.5 * Dc[e];
-                    Wb[a][b] += 0.5 * Wc[e];
-                }
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    if (a < ni && b < nj) {
+                        const int64_t e = d.offd + (row0 + b) * d.n + c0 + a;
+                        Db[a][b] += 0.5 * Dc[e];
+                        Wb[a][b] += 0.5 * Wc[e];
+                    }
         }
     }
     double V, dV, Sr = 0.0, dS = 0.0;
@@ -174,8 +184,11 @@ __global__ void __launch_bounds__(kThreads) k_pair_forces(
     // A = sum XH g, B = sum XS g and their gradients in u (Slater-Koster
     // factor g: s,s 1; s,p_b u_b; p_a,s -u_a; p_a,p_b u_a u_b)
     double A = 0.0, B = 0.0, gA[3] = {0.0, 0.0, 0.0}, gB[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < ni; ++a)
-        for (int b = 0; b < nj; ++b) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (a >= ni || b >= nj) continue;
             const double xh = 4.0 * Db[a][b];
             const double xs = 4.0 * (Db[a][b] * vs - Wb[a][b]);
             double g;
