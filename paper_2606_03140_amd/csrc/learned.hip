@@ -417,6 +417,39 @@ __global__ void k_ewald_recip(int n, int nk, const double* __restrict__ pos, con
     V[i] = (species[i] == 0 ? U0 : U1) * q[i] + ke * (V[i] + 2.0 * acc + self);
 }
 
+// The same reciprocal sum split over chunks of k-vectors so that the launch
+// has (atom blocks) x (k chunks) workgroups: part[y * n + i] = sum over the
+// k in chunk y of w(k) (cos(k.R_i) C + sin(k.R_i) S); k_ewald_finish adds the
+// chunks in order.
+__global__ void __launch_bounds__(128) k_ewald_recip_part(int n, int nk, int kchunk, const double* __restrict__ pos,
+                                                         const double4* __restrict__ kv,
+                                                         const double* __restrict__ CS, double* __restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k0 = blockIdx.y * kchunk, k1 = min(nk, k0 + kchunk);
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    double acc = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const double4 kk = kv[k];
+        if (kk.w == 0.0) continue;          // uniform over the wave
+        double sn, cs;
+        sincos(kk.x * x + kk.y * y + kk.z * z, &sn, &cs);
+        acc += kk.w * (cs * CS[2 * k] + sn * CS[2 * k + 1]);
+    }
+    part[(int64_t)blockIdx.y * n + i] = acc;
+}
+
+__global__ void k_ewald_finish(int n, int nchunk, const double* __restrict__ part,
+                               const int32_t* __restrict__ species, const double* __restrict__ q, double eta,
+                               double ke, double U0, double U1, double* __restrict__ V) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int y = 0; y < nchunk; ++y) acc += part[(int64_t)y * n + i];
+    const double self = -2.0 * eta / sqrt(M_PI) * q[i];
+    V[i] = (species[i] == 0 ? U0 : U1) * q[i] + ke * (V[i] + 2.0 * acc + self);
+}
+
 // k-vector table over the full grid a = 0..K, b, c = -K..K (index
 // (a (2K+1) + b + K) (2K+1) + c + K), with the same half space and sphere
 // k^2 <= kc2 as the host-built table of gdm_ewald_potential; grid points
@@ -751,12 +784,11 @@ __device__ double slater_short_deriv(double ta, double tb, double R) {
 //   reciprocal space over the half space of k (weights w_k = 4 pi/V exp(-k^2/4eta^2)/k^2):
 //     -k_e sum_k w_k k [a_K (S_b cos - C_b sin) + b_K (S_a cos - C_a sin)](k . R_K)
 //   with (C_x, S_x)(k) = sum_J x_J (cos, sin)(k . R_J) (the k and -k terms are equal).
-__global__ void k_ewald_force(int n, int nk, const double* __restrict__ pos, const int32_t* __restrict__ species,
-                              double3 L, double3 iL, const int32_t* __restrict__ rp, const int32_t* __restrict__ cl,
-                              double rc, double eta, int screened, double tau0, double tau1,
-                              const double* __restrict__ qa, const double* __restrict__ qb,
-                              const double4* __restrict__ kv, const double* __restrict__ CSa,
-                              const double* __restrict__ CSb, double ke, double* __restrict__ F) {
+__global__ void k_ewald_force_real(int n, const double* __restrict__ pos, const int32_t* __restrict__ species,
+                                   double3 L, double3 iL, const int32_t* __restrict__ rp,
+                                   const int32_t* __restrict__ cl, double rc, double eta, int screened, double tau0,
+                                   double tau1, const double* __restrict__ qa, const double* __restrict__ qb,
+                                   double ke, double* __restrict__ F) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double ti = species[i] == 0 ? tau0 : tau1;
@@ -776,21 +808,58 @@ __global__ void k_ewald_force(int n, int nk, const double* __restrict__ pos, con
         fy += w * dy;
         fz += w * dz;
     }
+    F[3 * i] += ke * fx;
+    F[3 * i + 1] += ke * fy;
+    F[3 * i + 2] += ke * fz;
+}
+
+// reciprocal part over chunk blockIdx.y of the k-vectors (atom blocks x k
+// chunks workgroups): part[(y * n + i) * 3 + x] = sum_k w_k k_x [...]
+__global__ void __launch_bounds__(128) k_ewald_force_recip_part(int n, int nk, int kchunk,
+                                                               const double* __restrict__ pos,
+                                                               const double* __restrict__ qa,
+                                                               const double* __restrict__ qb,
+                                                               const double4* __restrict__ kv,
+                                                               const double* __restrict__ CSa,
+                                                               const double* __restrict__ CSb,
+                                                               double* __restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k0 = blockIdx.y * kchunk, k1 = min(nk, k0 + kchunk);
+    const double ai = qa[i], bi = qb[i];
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int k = 0; k < nk; ++k) {
+    for (int k = k0; k < k1; ++k) {
         const double4 kk = kv[k];
-        if (kk.w == 0.0) continue;
-        const double ph = kk.x * pos[3 * i] + kk.y * pos[3 * i + 1] + kk.z * pos[3 * i + 2];
+        if (kk.w == 0.0) continue;          // uniform over the wave
         double sn, cs;
-        sincos(ph, &sn, &cs);
-        const double t = kk.w * (ai * (CSb[2 * k + 1] * cs - CSb[2 * k] * sn) + bi * (CSa[2 * k + 1] * cs - CSa[2 * k] * sn));
+        sincos(kk.x * x + kk.y * y + kk.z * z, &sn, &cs);
+        const double t =
+            kk.w * (ai * (CSb[2 * k + 1] * cs - CSb[2 * k] * sn) + bi * (CSa[2 * k + 1] * cs - CSa[2 * k] * sn));
         gx += t * kk.x;
         gy += t * kk.y;
         gz += t * kk.z;
     }
-    F[3 * i] += ke * (fx - gx);
-    F[3 * i + 1] += ke * (fy - gy);
-    F[3 * i + 2] += ke * (fz - gz);
+    double* o = part + ((int64_t)blockIdx.y * n + i) * 3;
+    o[0] = gx;
+    o[1] = gy;
+    o[2] = gz;
+}
+
+__global__ void k_ewald_force_finish(int n, int nchunk, const double* __restrict__ part, double ke,
+                                     double* __restrict__ F) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int y = 0; y < nchunk; ++y) {
+        const double* o = part + ((int64_t)y * n + i) * 3;
+        gx += o[0];
+        gy += o[1];
+        gz += o[2];
+    }
+    F[3 * i] -= ke * gx;
+    F[3 * i + 1] -= ke * gy;
+    F[3 * i + 2] -= ke * gz;
 }
 
 }  // namespace
@@ -896,6 +965,17 @@ extern "C" int gdm_adam_step(gdm_ctx* ctx, int32_t n, float* params, const float
     return GDM_OK;
 }
 
+// k chunks of the reciprocal sums: enough (atom blocks) x (chunks)
+// workgroups to fill the chip, at least 64 k-vectors per chunk
+static void ewald_chunks(int n, int nk, int* nchunk, int* kchunk) {
+    nk = std::max(nk, 1);
+    const int ablocks = (n + 127) / 128;
+    int c = std::max(1, 4096 / ablocks);
+    c = std::min(c, std::max(1, nk / 64));
+    *kchunk = (nk + c - 1) / c;
+    *nchunk = (nk + *kchunk - 1) / *kchunk;
+}
+
 static int check_ewald(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, const int32_t* col, double rcut,
                        double eta, int32_t k_max, int32_t k_max_limit, const double hubbard_U[2], const double* tau,
                        const double* q, double* V, const char* who) {
@@ -931,12 +1011,16 @@ extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const in
                 kv.push_back(make_double4(kx, ky, kz, w));
             }
     const int nk = (int)kv.size();
+    const int n = sys->n_atoms;
+    int nchunk = 1, kchunk = 1;
+    ewald_chunks(n, nk, &nchunk, &kchunk);
     bool ok = true;
-    double4* dkv = (double4*)gdm_buf(ctx, BUF_EWALD, sizeof(double4) * nk + sizeof(double) * 2 * nk, &ok);
+    double4* dkv = (double4*)gdm_buf(
+        ctx, BUF_EWALD, sizeof(double4) * nk + sizeof(double) * (2 * (size_t)nk + (size_t)nchunk * n), &ok);
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_ewald_potential: workspace allocation failed");
     double* CS = (double*)(dkv + nk);
+    double* part = CS + 2 * (int64_t)nk;
     GDM_HIP(ctx, hipMemcpyAsync(dkv, kv.data(), sizeof(double4) * nk, hipMemcpyHostToDevice, ctx->stream));
-    const int n = sys->n_atoms;
     const double3 L = make_double3(sys->box[0], sys->box[1], sys->box[2]);
     const double3 iL = make_double3(sys->inv_box[0], sys->inv_box[1], sys->inv_box[2]);
     GDM_TIMED(ctx, "ewald");
@@ -945,8 +1029,11 @@ extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const in
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, q, dkv, CS);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_recip, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nk, sys->pos,
-                       sys->species, q, dkv, CS, eta, 14.399645, hubbard_U[0], hubbard_U[1], V);
+    hipLaunchKernelGGL(k_ewald_recip_part, dim3((n + 127) / 128, nchunk), dim3(128), 0, ctx->stream, n, nk, kchunk,
+                       sys->pos, dkv, CS, part);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_finish, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nchunk, part, sys->species,
+                       q, eta, 14.399645, hubbard_U[0], hubbard_U[1], V);
     GDM_LAUNCH_CHECK(ctx);
     // keep the staging vector alive until the copy has been consumed
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -1029,13 +1116,17 @@ extern "C" int gdm_ewald_forces(gdm_ctx* ctx, const gdm_system* sys, const int32
     if (!n_vec) return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_forces: null charge vector n_vec");
     const int w = 2 * k_max + 1;
     const int nk = (k_max + 1) * w * w;
+    int nchunk = 1, kchunk = 1;
+    ewald_chunks(sys->n_atoms, nk, &nchunk, &kchunk);
     bool ok = true;
-    double* ws = (double*)gdm_buf(ctx, BUF_EWALD, sizeof(double) * (8 * (size_t)nk + sys->n_atoms), &ok);
+    double* ws = (double*)gdm_buf(
+        ctx, BUF_EWALD, sizeof(double) * (8 * (size_t)nk + sys->n_atoms + 3 * (size_t)nchunk * sys->n_atoms), &ok);
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_ewald_forces: workspace allocation failed");
     double4* dkv = (double4*)ws;
     double* CSa = ws + 4 * (int64_t)nk;
     double* CSb = CSa + 2 * (int64_t)nk;
     double* a = CSb + 2 * (int64_t)nk;     // a = 2 q - n
+    double* part = a + sys->n_atoms;
     const double* b = n_vec;
     const double V3 = sys->box[0] * sys->box[1] * sys->box[2];
     const double kc2 = std::pow(2.0 * M_PI * k_max / std::max(sys->box[0], std::max(sys->box[1], sys->box[2])), 2);
@@ -1052,9 +1143,15 @@ extern "C" int gdm_ewald_forces(gdm_ctx* ctx, const gdm_system* sys, const int32
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, b, dkv, CSb);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_force, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nk, sys->pos,
+    hipLaunchKernelGGL(k_ewald_force_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos,
                        sys->species, L, iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0,
-                       tau ? tau[1] : 0.0, a, b, dkv, CSa, CSb, 14.399645, F);
+                       tau ? tau[1] : 0.0, a, b, 14.399645, F);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_force_recip_part, dim3((n + 127) / 128, nchunk), dim3(128), 0, ctx->stream, n, nk,
+                       kchunk, sys->pos, a, b, dkv, CSa, CSb, part);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_ewald_force_finish, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nchunk, part,
+                       14.399645, F);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }
