@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from ._lib import FP64_EIG, GRAPH_ADAPTIVE, Context, Subgraphs, System, TBParams
+from ._lib import FP64_EIG, GRAPH_ADAPTIVE, MIXED_F16, Context, Subgraphs, System, TBParams
 from .scc import HUBBARD_U, EwaldSetup, ewald_setup, scc_loop, slater_tau
 from .pipeline import Partition, subgraph_cost
 
@@ -62,6 +62,7 @@ class Point:
     D: torch.Tensor
     S: torch.Tensor | None = None
     ew: EwaldSetup | None = None
+    H: torch.Tensor | None = None
 
 
 @dataclass
@@ -87,20 +88,28 @@ class XLBOMD:
     stays below about 4, i.e. for a few molecules), or "krylov": with
     -J^-1 (q[n] - n) from the low-rank preconditioned Krylov kernel
     (gdm_krylov_*, K0 = -k0 I, completed on the unfitted remainder), rebuilt
-    at every step.  Its directional derivatives J v = dq - v are one-sided
-    finite differences of the FP64 solve, dq = (q[n + eps v] - q[n]) / eps
-    (the FP64 path forms core rows only, so no perturbation-theory response
-    exists on it); the kernel only preconditions the charge dynamics, so
-    their O(eps) error does not enter the forces or the energy."""
+    at every step.  Its directional derivatives J v = dq - v come from
+    response="mixed": the perturbation-theory response of the
+    mixed-precision expansion solved at the same H and S on a second
+    context (gdm_density_response), or response="fd": one-sided finite
+    differences of the FP64 solve, dq = (q[n + eps v] - q[n]) / eps (the
+    FP64 path forms core rows only, so it has no perturbation-theory
+    response of its own).  The kernel only preconditions the charge
+    dynamics, so the responses' error (1e-5 relative either way) does not
+    enter the forces or the energy."""
 
     def __init__(self, ctx: Context, system: System, tb: TBParams, core_of_atom: torch.Tensor, n_cores: int,
                  kT: float = 0.1, dt: float = 0.25, c: float = 0.3, graph: str = "cutoff", tau: float = 1e-5,
                  alpha: float = 0.7, screened: bool = True, ewald_tol: float = 1e-10, rebuild: int = 1,
                  timing: bool = False, kernel: str = "scaled", rank_tol: float = 0.1, max_rank: int = 6,
-                 k0: float = 0.1, fd_eps: float = 1e-5):
-        if kernel not in ("scaled", "krylov"):
-            raise ValueError(f"kernel {kernel!r}")
+                 k0: float = 0.1, fd_eps: float = 1e-5, response: str = "mixed"):
+        if kernel not in ("scaled", "krylov") or response not in ("mixed", "fd"):
+            raise ValueError(f"kernel {kernel!r}, response {response!r}")
         self.kernel, self.rank_tol, self.max_rank, self.k0, self.fd_eps = kernel, rank_tol, max_rank, k0, fd_eps
+        self.response = response
+        self.ctx_m = None
+        self._m_sg = None
+        self._m_cap = 20
         self.ranks: list = []
         self.ctx, self.system, self.tb = ctx, system, tb
         self.core, self.n_cores = core_of_atom, n_cores
@@ -122,6 +131,10 @@ class XLBOMD:
             self.delta = torch.zeros(n, dtype=torch.float64, device=dev)
             self.n_eps = torch.zeros(n, dtype=torch.float64, device=dev)
             self.dq = torch.zeros(n, dtype=torch.float64, device=dev)
+            self.dV = torch.zeros(n, dtype=torch.float64, device=dev)
+            if response == "mixed":
+                self.ctx_m = Context(ctx.device)
+                self.ctx_m.set_response(self._m_cap)
         self.mu = 0.0
         self.point: Point | None = None
         self.rec = Record()
@@ -184,7 +197,7 @@ class XLBOMD:
         e_rep, e_shift = (float(x) for x in self.energy.cpu())
         ctx.check()
         return Point(F=F, q=q, U=omega + e_rep + e_shift, omega=omega, e_rep=e_rep, e_shift=e_shift, mu=mu,
-                     part=part, D=D, S=S, ew=ew)
+                     part=part, D=D, S=S, ew=ew, H=H)
 
     def _charges_at(self, p: Point, n_vec: torch.Tensor) -> torch.Tensor:
         """q[n_vec] at the positions and subgraphs of point p (FP64 solve)."""
@@ -196,18 +209,45 @@ class XLBOMD:
         D = ctx.subgraph_density(p.part.sg, mu, self.kT, FP64_EIG)
         return ctx.mulliken_charges(sysm, p.part.sg, p.part.nbr, S, D)
 
+    def _mixed_solve(self, p: Point) -> None:
+        """Mixed-precision solve at p's H and S on the second context, with
+        the expansion recorded for its charge response."""
+        cm, sysm = self.ctx_m, self.system
+        if p.part.sg is not self._m_sg:
+            cm.plan(p.part.sg, MIXED_F16)
+            self._m_sg = p.part.sg
+        cm.find_mu(sysm, p.part.sg, p.part.nbr, p.H, p.S, self.kT, MIXED_F16, p.mu)
+        nd = cm.mixed_stats()["n_doublings"]
+        if nd > self._m_cap:          # more doublings than the record holds: grow it, solve again
+            self._m_cap = nd + 2
+            cm.set_response(self._m_cap)
+            cm.find_mu(sysm, p.part.sg, p.part.nbr, p.H, p.S, self.kT, MIXED_F16, p.mu)
+
+    def _response(self, p: Point, n_t: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
+        """dq = J v + v, the charge response to the potential of v."""
+        ctx, sysm = self.ctx, self.system
+        if self.response == "mixed":
+            ew = p.ew
+            ctx.ewald_potential(sysm, ew.graph, ew.rcut, ew.eta, ew.k_max, HUBBARD_U, v, tau=self.tau_s, out=self.dV)
+            self.ctx_m.density_response(sysm, p.part.sg, p.part.nbr, p.S, self.dV, out=self.dq)
+            return self.dq
+        ctx.axpby(1.0, n_t, self.fd_eps, v, self.n_eps)
+        q_eps = self._charges_at(p, self.n_eps)
+        ctx.axpby(1.0 / self.fd_eps, q_eps, -1.0 / self.fd_eps, p.q, self.dq)
+        return self.dq
+
     def _krylov_delta(self, p: Point, n_t: torch.Tensor) -> torch.Tensor:
         """-J^-1 (q[n_t] - n_t) at point p by the low-rank Krylov kernel."""
         ctx, N = self.ctx, self.system.n_atoms
         t = time.perf_counter()
+        if self.response == "mixed":
+            self._mixed_solve(p)
         ctx.krylov_begin(n_t, p.q, self.max_rank, self.kwork, self.k0)
         rank = 0
         for j in range(self.max_rank):
             v = Context.krylov_vector(self.kwork, N, j)
-            ctx.axpby(1.0, n_t, self.fd_eps, v, self.n_eps)
-            q_eps = self._charges_at(p, self.n_eps)
-            ctx.axpby(1.0 / self.fd_eps, q_eps, -1.0 / self.fd_eps, p.q, self.dq)
-            rel, exhausted = ctx.krylov_add(N, j, self.dq, self.max_rank, self.kwork)
+            dq = self._response(p, n_t, v)
+            rel, exhausted = ctx.krylov_add(N, j, dq, self.max_rank, self.kwork)
             rank = j + 1
             if rel <= self.rank_tol or exhausted:
                 break

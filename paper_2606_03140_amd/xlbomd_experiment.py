@@ -34,12 +34,12 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_one(ctx, box, grid, dt, steps, graph, rebuild, tau, n0, vel, c, kernel, max_rank, rank_tol):
+def run_one(ctx, box, grid, dt, steps, graph, rebuild, tau, n0, vel, c, kernel, max_rank, rank_tol, response):
     system = System(box.pos, box.species, box.anchor, box.box)
     tb = xlbomd.md_params()
     core, nco = ctx.grid_cores(system, grid)
     md = xlbomd.XLBOMD(ctx, system, tb, core, nco, dt=dt, c=c, graph=graph, tau=tau, rebuild=rebuild, timing=True,
-                       kernel=kernel, max_rank=max_rank, rank_tol=rank_tol)
+                       kernel=kernel, max_rank=max_rank, rank_tol=rank_tol, response=response)
     md.start(n0, vel)
     md.timing.clear()
     t0 = time.perf_counter()
@@ -81,6 +81,7 @@ def main(argv=None):
     ap.add_argument("--kernel", default="krylov", choices=("scaled", "krylov"))
     ap.add_argument("--max-rank", type=int, default=6)
     ap.add_argument("--rank-tol", type=float, default=0.1)
+    ap.add_argument("--response", default="mixed", choices=("mixed", "fd"))
     ap.add_argument("--temperature", type=float, default=300.0)
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
@@ -99,12 +100,12 @@ def main(argv=None):
     for dt in dts:
         steps = int(round(args.steps * dts[0] / dt))
         runs.append(run_one(ctx, box, tuple(args.grid), dt, steps, args.graph, args.rebuild, args.tau, n0, vel,
-                            args.c, args.kernel, args.max_rank, args.rank_tol))
+                            args.c, args.kernel, args.max_rank, args.rank_tol, args.response))
         _log(f"[xlbomd] dt {dt}: {json.dumps(runs[-1])}")
     ratios = [runs[i]["e_fluct_ev"] / runs[i + 1]["e_fluct_ev"] for i in range(len(runs) - 1)]
     out = {"experiment": "xlbomd", "waters": args.waters, "atoms": system.n_atoms, "grid": list(args.grid),
            "graph": args.graph, "rebuild": args.rebuild, "tau": args.tau, "kernel": args.kernel,
-           "kernel_c": args.c, "max_rank": args.max_rank, "rank_tol": args.rank_tol,
+           "kernel_c": args.c, "max_rank": args.max_rank, "rank_tol": args.rank_tol, "response": args.response,
            "scc_start_s": t_scc, "runs": runs, "fluct_ratio_per_dt_doubling": ratios}
     line = json.dumps(out)
     print(line, flush=True)

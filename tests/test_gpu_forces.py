@@ -157,14 +157,16 @@ def test_xlbomd_follows_oracle_trajectory(c):
     np.testing.assert_allclose(system.pos.cpu().numpy(), tr.pos[-1], rtol=0, atol=1e-9)
 
 
-def test_xlbomd_krylov_kernel_follows_oracle(c):
+@pytest.mark.parametrize("response", ["fd", "mixed"])
+def test_xlbomd_krylov_kernel_follows_oracle(c, response):
     """The Krylov kernel at full rank (every charge direction fitted) is
-    -J^-1 itself; the GPU's finite-difference responses and the oracle's
-    perturbation theory then agree to the difference step (1e-5)."""
+    -J^-1 itself; the GPU's responses (finite differences of the FP64
+    solve, or the perturbation theory of the mixed expansion) and the
+    oracle's perturbation theory then agree to about 1e-5."""
     pos, sp, anchor, L = dimer_box()
     vel = xlbomd.maxwell_velocities(sp, 600.0, 5)
     kw = dict(kernel="krylov", max_rank=6, rank_tol=1e-9, k0=0.1)
-    md, system = gpu_md(c, pos, sp, anchor, L, vel, 0.25, 8, **kw)
+    md, system = gpu_md(c, pos, sp, anchor, L, vel, 0.25, 8, response=response, **kw)
     ew = ewald_setup(c, system)
     model = om.TBModel(**MD)
     oew = oracle_ewald(ew)
