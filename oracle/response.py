@@ -51,8 +51,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from .ewald import coulomb_potential
-from .model import N_ORB, TBModel, dense_hs
+from .ewald import coulomb_potential, slater_short, slater_tau
+from .model import COULOMB_EV_A, N_ORB, TBModel, dense_hs, min_image, r2_of
 from .solve import fermi, solve_system
 
 
@@ -113,13 +113,15 @@ def charge_response(pos, species, L, model: TBModel, subs, V_atom, dV, mu=None, 
     return dq_mu0 + dmu * dq_mu1, dmu, mu
 
 
-def krylov_step(f: np.ndarray, jv, rank_tol: float = 1e-2, max_rank: int = 8, k0: float = 1.0,
+def krylov_step(f: np.ndarray, jv, rank_tol: float = 1e-2, max_rank: int = 8, k0=1.0,
                 complete: bool = False):
     """Quasi-Newton update -(K0 J)^-1 K0 f from the low-rank preconditioned
-    Krylov kernel with K0 = -k0 I; complete=True adds the unfitted remainder
-    -(r - F_v c).  jv(v) returns J v.  Returns (dn, rank, relative residual
-    of the low-rank fit)."""
-    r = -k0 * f
+    Krylov kernel with K0 = -k0 I (k0 a number) or K0 x = k0(x) (k0 a
+    function, e.g. BlockPreconditioner.apply); complete=True adds the
+    unfitted remainder -(r - F_v c).  jv(v) returns J v.  Returns (dn, rank,
+    relative residual of the low-rank fit)."""
+    precond = k0 if callable(k0) else (lambda x: -k0 * x)
+    r = precond(f)
     nr = np.linalg.norm(r)
     if nr == 0.0:
         return np.zeros_like(f), 0, 0.0
@@ -128,7 +130,7 @@ def krylov_step(f: np.ndarray, jv, rank_tol: float = 1e-2, max_rank: int = 8, k0
     rel = 1.0
     c = np.zeros(0)
     for _ in range(max_rank):
-        fv = -k0 * jv(v)                              # K0 J v
+        fv = precond(jv(v))                           # K0 J v
         V.append(v)
         FV.append(fv)
         Fm = np.stack(FV, axis=1)
@@ -153,9 +155,76 @@ def krylov_step(f: np.ndarray, jv, rank_tol: float = 1e-2, max_rank: int = 8, k0
     return dn, len(V), rel
 
 
+class BlockPreconditioner:
+    """Block-diagonal preconditioner K0 ~ J^-1 over the cores (SI sections B,
+    C: low-rank updates combined with a block-diagonal preconditioner
+    built on the graph).  For each core c, with its atoms in ascending
+    order, K0_c = (chi_c G_c - I)^-1, where
+      chi_c[:, j] = dq over the core's atoms for a unit potential on its j-th
+        atom, probed for all cores at once (dV = 1 on the j-th core atom of
+        every core; canonical response, charge_response);
+      G_c = the charge-potential kernel inside the core: "local" gives
+        U_I on the diagonal and k_e (1/r - S(tau_I, tau_J, r)) off it at the
+        minimum image; "ewald" gives the periodic kernel of coulomb_potential
+        restricted to the core (exact: with one core holding every atom and
+        every atom probed alone, K0 = J^-1).
+    apply(x) returns K0 x."""
+
+    def __init__(self, subs, n_atoms: int):
+        self.cores = [np.asarray(atoms[:nc], dtype=np.int64) for atoms, nc in subs]
+        self.blocks = []
+        self.n = n_atoms
+
+    def apply(self, x: np.ndarray) -> np.ndarray:
+        y = np.zeros(self.n)
+        for idx, K in zip(self.cores, self.blocks):
+            y[idx] = K @ x[idx]
+        return y
+
+
+def block_preconditioner(pos, species, L, model: TBModel, subs, V_atom, mu, sols, gamma: str = "local",
+                         eta=None, n_real: int = 2, k_max: int = 8, short_cut: float = np.inf):
+    U = np.asarray(model.hubbard_U)
+    P = BlockPreconditioner(subs, len(species))
+    width = max(len(c) for c in P.cores)
+    chi = [np.zeros((len(c), len(c))) for c in P.cores]
+    for j in range(width):
+        dV = np.zeros(len(species))
+        for c in P.cores:
+            if j < len(c):
+                dV[c[j]] = 1.0
+        dq, _, _ = charge_response(pos, species, L, model, subs, V_atom, dV, mu=mu, sols=sols)
+        for k, c in enumerate(P.cores):
+            if j < len(c):
+                chi[k][:, j] = dq[c]
+    tau = slater_tau(U)
+    for k, c in enumerate(P.cores):
+        nc = len(c)
+        if gamma == "ewald":
+            G = np.zeros((nc, nc))
+            for j in range(nc):
+                e = np.zeros(len(species))
+                e[c[j]] = 1.0
+                G[:, j] = coulomb_potential(pos, species, e, L, U, eta=eta, n_real=n_real, k_max=k_max,
+                                            short_cut=short_cut)[c]
+        else:
+            d = min_image(pos[c][None, :, :] - pos[c][:, None, :], L, 1.0 / L)
+            r = np.sqrt(r2_of(d))
+            G = np.zeros((nc, nc))
+            for a in range(nc):
+                for b in range(nc):
+                    if a == b:
+                        G[a, b] = U[species[c[a]]]
+                    else:
+                        G[a, b] = COULOMB_EV_A * (1.0 / r[a, b]
+                                                  - slater_short(tau[species[c[a]]], tau[species[c[b]]], r[a, b]))
+        P.blocks.append(np.linalg.inv(chi[k] @ G - np.eye(nc)))
+    return P
+
+
 def quasi_newton(charge_map, jacobian_vector, n0, tol: float = 1e-5, max_iter: int = 100,
-                 rank_tol: float = 1e-2, max_rank: int = 8, k0: float = 1.0, complete: bool = False,
-                 backtrack: int = 0):
+                 rank_tol: float = 1e-2, max_rank: int = 8, k0=1.0, complete: bool = False,
+                 backtrack: int = 0, make_k0=None):
     """Kernel-accelerated SCF: n <- n - alpha (K0 J)^-1 K0 f(n).  charge_map(n)
     returns q0[n] (or raises ArithmeticError where it has no solution);
     jacobian_vector(n, v) returns J(n) v at the n of the last accepted
@@ -167,6 +236,8 @@ def quasi_newton(charge_map, jacobian_vector, n0, tol: float = 1e-5, max_iter: i
     q = charge_map(n)
     f = q - n
     rms = float(np.sqrt(np.mean(f * f)))
+    if make_k0 is not None:          # preconditioner built once, at the starting charges
+        k0 = make_k0()
     for it in range(1, max_iter + 1):
         hist.append(rms)
         if rms < tol:
@@ -194,10 +265,11 @@ def quasi_newton(charge_map, jacobian_vector, n0, tol: float = 1e-5, max_iter: i
 def scc_quasi_newton(pos, species, L, model: TBModel, subs, q_start=None, tol: float = 1e-5,
                      max_iter: int = 100, rank_tol: float = 1e-2, max_rank: int = 8, k0: float = 0.1,
                      complete: bool = True, backtrack: int = 4, eta=None, n_real: int = 2, k_max: int = 8,
-                     short_cut: float = np.inf):
+                     short_cut: float = np.inf, block: bool = False):
     """The SCC problem of scc.scc solved by the quasi-Newton iteration, the
-    Jacobian-vector products from charge_response.  Returns (q, iterations,
-    residual history, ranks)."""
+    Jacobian-vector products from charge_response; block=True uses the
+    block-diagonal preconditioner (local kernel) built at the start instead
+    of K0 = -k0 I.  Returns (q, iterations, residual history, ranks)."""
     U = np.asarray(model.hubbard_U)
 
     def gamma(q):
@@ -217,8 +289,11 @@ def scc_quasi_newton(pos, species, L, model: TBModel, subs, q_start=None, tol: f
                                    sols=state["sols"])
         return dq - v
 
+    def make_k0():
+        return block_preconditioner(pos, species, L, model, subs, state["V"], state["mu"], state["sols"]).apply
+
     n0 = np.zeros(len(species)) if q_start is None else q_start
     q, it, hist, ranks, _ = quasi_newton(charge_map, jacobian_vector, n0, tol=tol, max_iter=max_iter,
                                          rank_tol=rank_tol, max_rank=max_rank, k0=k0, complete=complete,
-                                         backtrack=backtrack)
+                                         backtrack=backtrack, make_k0=make_k0 if block else None)
     return q, it, hist, ranks

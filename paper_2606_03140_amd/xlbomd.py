@@ -25,7 +25,7 @@ import numpy as np
 import torch
 
 from ._lib import FP64_EIG, GRAPH_ADAPTIVE, MIXED_F16, Context, Subgraphs, System, TBParams
-from .scc import HUBBARD_U, EwaldSetup, ewald_setup, scc_loop, slater_tau
+from .scc import HUBBARD_U, EwaldSetup, ewald_setup, scc_loop, scc_quasi_newton, slater_tau
 from .pipeline import Partition, subgraph_cost
 
 MASS = (15.999, 1.008)             # amu, O and H
@@ -109,7 +109,7 @@ class XLBOMD:
         self.response = response
         self.ctx_m = None
         self._m_sg = None
-        self._m_cap = 20
+        self._m_cap = 8
         self.ranks: list = []
         self.ctx, self.system, self.tb = ctx, system, tb
         self.core, self.n_cores = core_of_atom, n_cores
@@ -117,6 +117,7 @@ class XLBOMD:
         self.graph_mode, self.tau, self.alpha = graph, tau, alpha
         self.rebuild = max(1, int(rebuild))      # halos redrawn every `rebuild` steps
         self.steps_done = 0
+        self._ew: EwaldSetup | None = None
         self.timing = {} if timing else None
         self.tau_s = slater_tau(HUBBARD_U) if screened else None
         self.ewald_tol = ewald_tol
@@ -142,7 +143,12 @@ class XLBOMD:
 
     # ------------------------------------------------------------ pieces
     def _ewald(self) -> EwaldSetup:
-        return ewald_setup(self.ctx, self.system, tol=self.ewald_tol)
+        """Ewald split and real-space pair list; the list is built with a
+        1 A skin and kept for `rebuild` steps (the kernels skip pairs at
+        r >= rcut, so it stays valid while no atom moves 0.5 A)."""
+        if self._ew is None or self.steps_done % self.rebuild == 0:
+            self._ew = ewald_setup(self.ctx, self.system, tol=self.ewald_tol, skin=1.0)
+        return self._ew
 
     def _partition(self, prev: Point | None) -> Partition:
         """Neighbour graph at the current positions; the halos are redrawn
@@ -303,14 +309,22 @@ class XLBOMD:
 
 def converged_charges(ctx: Context, system: System, tb: TBParams, core, n_cores: int, kT: float = 0.1,
                       tol: float = 1e-9, screened: bool = True, mixer: str = "anderson", mix: float = 0.03,
-                      depth: int = 8) -> torch.Tensor:
+                      depth: int = 8, max_iter: int = 400, log=None) -> torch.Tensor:
     """SCC ground-state charges on the cutoff-graph halos (the starting n).
     Anderson needs a memory well below the number of atoms; a few molecules
-    converge with linear mixing (mixer="linear", mix=0.3)."""
+    converge with linear mixing (mixer="linear", mix=0.3); large boxes with
+    the kernel-accelerated quasi-Newton SCF (mixer="quasi_newton", mixed
+    path, whose fixed point lies within its 1e-5 accuracy of the FP64 one)."""
     nbr = ctx.build_graph_cutoff(system, tb.cutoff)
     sg = ctx.extract_subgraphs(system, tb, nbr, core, n_cores)
     part = Partition(nbr=nbr, graph=nbr, core_of_atom=core, n_cores=n_cores, sg=sg)
-    res = scc_loop(ctx, system, tb, part, kT, FP64_EIG, tol=tol, max_iter=400, screened=screened, mixer=mixer,
+    if mixer == "quasi_newton":       # kernel-accelerated SCF on the mixed path (SI section C)
+        res = scc_quasi_newton(ctx, system, tb, part, kT, tol=tol, max_iter=max_iter, screened=screened,
+                               max_doublings=10, log=log)
+        if not res.converged:
+            raise RuntimeError(f"SCC did not converge in {res.iterations} iterations")
+        return res.q
+    res = scc_loop(ctx, system, tb, part, kT, FP64_EIG, tol=tol, max_iter=max_iter, screened=screened, mixer=mixer,
                    mix=mix, depth=depth)
     if not res.converged:
         raise RuntimeError(f"SCC did not converge in {res.iterations} iterations")

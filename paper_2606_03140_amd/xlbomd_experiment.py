@@ -83,6 +83,8 @@ def main(argv=None):
     ap.add_argument("--rank-tol", type=float, default=0.1)
     ap.add_argument("--response", default="mixed", choices=("mixed", "fd"))
     ap.add_argument("--temperature", type=float, default=300.0)
+    ap.add_argument("--scc-tol", type=float, default=1e-7)
+    ap.add_argument("--scc", default="anderson", choices=("anderson", "quasi_newton"))
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     ctx = Context(0)
@@ -91,7 +93,11 @@ def main(argv=None):
     tb = xlbomd.md_params()
     core, nco = ctx.grid_cores(system, tuple(args.grid))
     t0 = time.perf_counter()
-    n0 = xlbomd.converged_charges(ctx, system, tb, core, nco, tol=1e-7)
+    def scc_log(it, rms, rank, rel, alpha, mu):
+        _log(f"[xlbomd] SCC start {it}: rms {rms:.2e}, rank {rank}, fit {rel:.2e}, step {alpha}")
+
+    n0 = xlbomd.converged_charges(ctx, system, tb, core, nco, tol=args.scc_tol, mixer=args.scc,
+                                  max_iter=200 if args.scc == "anderson" else 60, log=scc_log)
     t_scc = time.perf_counter() - t0
     _log(f"[xlbomd] {args.waters} waters, {nco} cores: SCC start in {t_scc:.1f} s")
     vel = xlbomd.maxwell_velocities(box.species, args.temperature, 5005)
@@ -106,7 +112,7 @@ def main(argv=None):
     out = {"experiment": "xlbomd", "waters": args.waters, "atoms": system.n_atoms, "grid": list(args.grid),
            "graph": args.graph, "rebuild": args.rebuild, "tau": args.tau, "kernel": args.kernel,
            "kernel_c": args.c, "max_rank": args.max_rank, "rank_tol": args.rank_tol, "response": args.response,
-           "scc_start_s": t_scc, "runs": runs, "fluct_ratio_per_dt_doubling": ratios}
+           "scc_start_s": t_scc, "scc_tol": args.scc_tol, "scc": args.scc, "runs": runs, "fluct_ratio_per_dt_doubling": ratios}
     line = json.dumps(out)
     print(line, flush=True)
     if args.out:

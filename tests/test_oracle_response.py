@@ -166,3 +166,32 @@ def test_quasi_newton_scc_reaches_anderson_fixed_point():
     assert hist[-1] < 1e-5
     assert it_n < it_a / 3
     assert math.sqrt(np.mean((q_n - q_a) ** 2)) < 1e-5 and np.abs(q_n - q_a).max() < 5e-5
+
+
+def test_block_preconditioner_is_inverse_jacobian_for_one_core():
+    """With one core holding every atom, every atom probed alone and the
+    periodic kernel, the block-diagonal preconditioner is J^-1 itself
+    (J v = dq[gamma v] - v from the canonical response)."""
+    th = np.radians(52.25)
+    w = np.array([[0.0, 0.0, 0.0], [0.96 * np.sin(th), 0.0, 0.96 * np.cos(th)],
+                  [-0.96 * np.sin(th), 0.0, 0.96 * np.cos(th)]])
+    pos = np.concatenate([w + [1.0, 1.0, 1.0], w + [4.0, 1.5, 1.2], w + [1.3, 4.2, 1.0], w + [3.8, 4.0, 3.9]])
+    sp = np.array([0, 1, 1] * 4)
+    L, eta = 10.0, 0.56
+    m = om.TBModel()
+    N = len(sp)
+    subs = [(np.arange(N), N)]
+    U = np.asarray(m.hubbard_U)
+    V = orsp.coulomb_potential(pos, sp, np.random.default_rng(0).normal(scale=0.1, size=N), L, U, eta=eta)
+    res = osv.solve_system(pos, sp, L, m, subs, V_atom=V)
+    P = orsp.block_preconditioner(pos, sp, L, m, subs, V, res.mu, res.sols, gamma="ewald", eta=eta)
+    J = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1.0
+        dq, _, _ = orsp.charge_response(pos, sp, L, m, subs, V, orsp.coulomb_potential(pos, sp, e, L, U, eta=eta),
+                                        mu=res.mu, sols=res.sols)
+        J[:, j] = dq - e
+    np.testing.assert_allclose(P.blocks[0] @ J, np.eye(N), rtol=0, atol=1e-10)
+    x = np.random.default_rng(1).normal(size=N)
+    np.testing.assert_allclose(P.apply(x), P.blocks[0] @ x, rtol=0, atol=1e-14)
