@@ -663,24 +663,55 @@ __global__ void __launch_bounds__(256) k_core_rows(const SubDesc* __restrict__ d
 }
 
 // w_k = sum_{a<nc} C[a][k] * (L_cc Q_core)[a][k]: the core weight of
-// eigenvector k, (C^T s C)_core diagonal contribution, with s C = L Q
-__global__ void __launch_bounds__(kThreads) k_core_weights(const SubDesc* __restrict__ desc,
-                                                          const int32_t* __restrict__ order,
-                                                          const double* __restrict__ Lm,
-                                                          const double* __restrict__ G, double* __restrict__ W) {
+// eigenvector k, (C^T s C)_core diagonal contribution, with s C = L Q.  One
+// workgroup per (subgraph, block of 64 eigenvectors): for each block of 64
+// core rows the 64 x 64 tile of L_cc Q_core (lower-triangular L, tile
+// products through LDS), multiplied by the matching tile of C and summed
+// over the rows; the 16 threads that share a column add their sums with
+// lane shuffles.
+__global__ void __launch_bounds__(256) k_core_weights(const SubDesc* __restrict__ desc,
+                                                     const int32_t* __restrict__ order,
+                                                     const double* __restrict__ Lm,
+                                                     const double* __restrict__ G, double* __restrict__ W) {
+    __shared__ SliceLds sl;
     const SubDesc d = desc[sub_of_block(order)];
     const int n = d.n, nc = d.nc, ld = d.ld, R = 2 * nc;
+    const int c0 = kBk * blockIdx.y;
+    if (c0 >= n) return;
     const double* l = Lm + d.off2;
     const double* g = G + 2 * d.offc;
-    for (int k = threadIdx.x; k < n; k += kThreads) {
-        double acc = 0.0;
-        for (int aa = 0; aa < nc; ++aa) {
-            const double* la = l + (int64_t)aa * ld;
-            double lq = 0.0;
-            for (int b = 0; b <= aa; ++b) lq += la[b] * g[(int64_t)k * R + b];
-            acc += g[(int64_t)k * R + nc + aa] * lq;
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+    double colsum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < nc; r0 += kBk) {
+        double acc[4][4];
+        zero_acc(acc);
+        tile_mm<true, true>(acc, min(nc, r0 + kBk),
+                            [&](int r, int t) {
+                                const int a = r0 + r;
+                                return (a < nc && t <= a) ? l[(int64_t)a * ld + t] : 0.0;
+                            },
+                            [&](int t, int c) {
+                                const int k = c0 + c;
+                                return (k < n && t < nc) ? g[(int64_t)k * R + t] : 0.0;
+                            },
+                            sl);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int a = r0 + tr + 16 * i;
+            if (a >= nc) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = c0 + tc + 16 * j;
+                if (k < n) colsum[j] += g[(int64_t)k * R + nc + a] * acc[i][j];
+            }
         }
-        W[d.offv + k] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double v = colsum[j];
+        for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+        const int k = c0 + tc + 16 * j;
+        if (tr == 0 && k < n) W[d.offv + k] = v;
     }
 }
 
@@ -784,8 +815,11 @@ __global__ void __launch_bounds__(256) k_dcore(const SubDesc* __restrict__ desc,
 // ------------------------------------------------ chemical potential
 // Multisection on N(mu) = 2 sum w f(lam - mu): each round evaluates K
 // candidates mu_j = lo + (hi - lo) j/(K+1); the new interval is the one where
-// N crosses n_e (same rule as bisection: N(mid) < n_e -> lo = mid).
+// N crosses n_e (same rule as bisection: N(mid) < n_e -> lo = mid).  K = 32
+// candidates per round, each summed by 8 threads (kMuK = 256 per workgroup).
 constexpr int kMuK = 256;
+constexpr int kMuC = 32;
+constexpr int kMuRounds = 11;    // 33^11 > 1e16: any bracket narrower than 1e4 eV reaches 1e-12 eV
 
 __global__ void __launch_bounds__(kMuK) k_mu_bounds(const SubDesc* __restrict__ desc, int n_sub,
                                                    const double* __restrict__ Lam, double* __restrict__ state) {
@@ -817,7 +851,9 @@ __global__ void __launch_bounds__(kMuK) k_mu_bounds(const SubDesc* __restrict__ 
     }
 }
 
-// partial[s * K + j] = 2 sum_k w_k f(lam_k - mu_j) over subgraph s
+// partial[s * K + j] = 2 sum_k w_k f(lam_k - mu_j) over subgraph s; thread
+// t sums candidate t / 8 over the eigenvalues k = t % 8 (mod 8), and the 8
+// partial sums are added by lane shuffles
 __global__ void __launch_bounds__(kMuK) k_mu_partial(const SubDesc* __restrict__ desc,
                                                     const double* __restrict__ Lam, const double* __restrict__ Wt,
                                                     const double* __restrict__ state, double beta, int final_pass,
@@ -831,37 +867,39 @@ __global__ void __launch_bounds__(kMuK) k_mu_partial(const SubDesc* __restrict__
     }
     __syncthreads();
     const double lo = state[0], hi = state[1];
-    const int j = threadIdx.x;
-    const double mu = final_pass ? state[2] : lo + (hi - lo) * ((double)(j + 1) / (double)(kMuK + 1));
+    const int j = threadIdx.x >> 3, part = threadIdx.x & 7;
+    const double mu = final_pass ? state[2] : lo + (hi - lo) * ((double)(j + 1) / (double)(kMuC + 1));
     double acc = 0.0;
-    for (int k = 0; k < n; ++k) acc += lw[n + k] * fermi_fp64(lw[k] - mu, beta);
-    partial[(int64_t)blockIdx.x * kMuK + j] = 2.0 * acc;
+    for (int k = part; k < n; k += 8) acc += lw[n + k] * fermi_fp64(lw[k] - mu, beta);
+    for (int o = 1; o < 8; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    if (part == 0) partial[(int64_t)blockIdx.x * kMuC + j] = 2.0 * acc;
 }
 
 __global__ void __launch_bounds__(kMuK) k_mu_pick(int n_sub, const double* __restrict__ partial, double n_e,
                                                  int final_pass, double tol, double* __restrict__ state,
                                                  int* __restrict__ status) {
-    __shared__ double Nj[kMuK];
-    const int j = threadIdx.x;
+    __shared__ double Nj[kMuC];
+    const int j = threadIdx.x >> 3, part = threadIdx.x & 7;
     double acc = 0.0;
-    for (int s = 0; s < n_sub; ++s) acc += partial[(int64_t)s * kMuK + j];
-    Nj[j] = acc;
+    for (int s = part; s < n_sub; s += 8) acc += partial[(int64_t)s * kMuC + j];
+    for (int o = 1; o < 8; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    if (part == 0) Nj[j] = acc;
     __syncthreads();
-    if (j == 0) {
+    if (threadIdx.x == 0) {
         if (final_pass) {
             state[3] = Nj[0];
             return;
         }
         double lo = state[0], hi = state[1];
         if (hi - lo > tol) {
-            int first = kMuK;   // first candidate with N >= n_e
-            for (int q = 0; q < kMuK; ++q)
+            int first = kMuC;   // first candidate with N >= n_e
+            for (int q = 0; q < kMuC; ++q)
                 if (!(Nj[q] < n_e)) {
                     first = q;
                     break;
                 }
-            double nlo = first == 0 ? lo : lo + (hi - lo) * ((double)first / (double)(kMuK + 1));
-            double nhi = first == kMuK ? hi : lo + (hi - lo) * ((double)(first + 1) / (double)(kMuK + 1));
+            double nlo = first == 0 ? lo : lo + (hi - lo) * ((double)first / (double)(kMuC + 1));
+            double nhi = first == kMuC ? hi : lo + (hi - lo) * ((double)(first + 1) / (double)(kMuC + 1));
             state[0] = nlo;
             state[1] = nhi;
         }
@@ -1032,7 +1070,8 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     if ((rc = gdm_dc_apply(ctx, 0))) return rc;
     {
         GDM_TIMED(ctx, "core_weights");
-        hipLaunchKernelGGL(k_core_weights, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, Sd, G, Wt);
+        hipLaunchKernelGGL(k_core_weights, dim3(ns, (P.max_n + kBk - 1) / kBk), dim3(256), 0, ctx->stream, desc,
+                           order, Sd, G, Wt);
     }
     GDM_LAUNCH_CHECK(ctx);
     // chemical potential: multisection rounds
@@ -1042,8 +1081,7 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     GDM_LAUNCH_CHECK(ctx);
     const size_t lds_lw = 2 * lds_n;
     if ((rc = set_lds(ctx, (const void*)k_mu_partial, lds_lw))) return rc;
-    const int rounds = 7;   // 257^7 > 1e16: any bracket narrower than 1e4 eV reaches 1e-12 eV
-    for (int it = 0; it < rounds; ++it) {
+    for (int it = 0; it < kMuRounds; ++it) {
         hipLaunchKernelGGL(k_mu_partial, dim3(ns), dim3(kMuK), lds_lw, ctx->stream, desc, Lam, Wt, state, beta, 0,
                            partial);
         GDM_LAUNCH_CHECK(ctx);
