@@ -460,9 +460,24 @@ constexpr size_t kRowsLds = sizeof(double) * kBk * kBkS + sizeof(BlockLds);
 // acc[i][j] (rows tr + 16 i, columns tc + 16 j of a 64 x 64 tile, tr = tid % 16,
 // tc = tid / 16) += sum_{t < K} fa(r, t) fb(t, c).  fa / fb return 0 outside
 // their operands; AT / BT: the loaders' contiguous index is t (else r / c).
+// The products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64): k-slices
+// of 16 staged in LDS, each wave a 32 x 32 block of 2 x 2 MFMA tiles (lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register r of
+// lane l is D[4 r + l / 16][l % 16]); the finished tile goes through LDS
+// (the union's 64 x 64 block) into the callers' layout.
+typedef double dbl4v __attribute__((ext_vector_type(4)));
+
 template <bool AT, bool BT, class FA, class FB>
-__device__ __forceinline__ void tile_mm(double (&acc)[4][4], int K, FA fa, FB fb, SliceLds& L) {
+__device__ __forceinline__ void tile_mm(double (&acc)[4][4], int K, FA fa, FB fb, BlockLds& bl) {
+    SliceLds& L = bl.s;
     const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+    const int lane = tid & 63, w = tid >> 6, fr = lane & 15, fk = lane >> 4;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    dbl4v m[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) m[i][j] = dbl4v{0.0, 0.0, 0.0, 0.0};
     for (int t0 = 0; t0 < K; t0 += kBkK) {
         for (int e = tid; e < kBk * kBkK; e += 256) {
             int rr, tt;
@@ -488,19 +503,31 @@ __device__ __forceinline__ void tile_mm(double (&acc)[4][4], int K, FA fa, FB fb
         }
         __syncthreads();
 #pragma unroll
-        for (int tt = 0; tt < kBkK; ++tt) {
-            double a[4], b[4];
+        for (int kk = 0; kk < kBkK; kk += 4) {
+            double a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = L.a[tt][tr + 16 * i];
+            for (int i = 0; i < 2; ++i) a[i] = L.a[kk + fk][wm + 16 * i + fr];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = L.b[tt][tc + 16 * j];
+            for (int j = 0; j < 2; ++j) b[j] = L.b[kk + fk][wn + 16 * j + fr];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < 2; ++j) m[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], m[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bl.m[wm + 16 * i + 4 * r + fk][wn + 16 * j + fr] = m[i][j][r];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += bl.m[tr + 16 * i][tc + 16 * j];
+    __syncthreads();
 }
 
 __device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
@@ -536,7 +563,7 @@ __global__ void __launch_bounds__(256) k_house_t(const SubDesc* __restrict__ des
     double acc[4][4];
     zero_acc(acc);
     auto vt = [&](int q, int t) { return q < nb ? refl(a, ld, n, k0 + q, k0 + 1 + t) : 0.0; };
-    tile_mm<true, true>(acc, n - k0 - 1, vt, [&](int t, int q) { return vt(q, t); }, bl.s);
+    tile_mm<true, true>(acc, n - k0 - 1, vt, [&](int t, int q) { return vt(q, t); }, bl);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -567,7 +594,7 @@ __device__ void apply_block(double* __restrict__ Y, int R, int r0, int n, const 
     auto vb = [&](int t, int q) { return q < nb ? refl(a, ld, n, k0 + q, k0 + 1 + t) : 0.0; };
     double acc[4][4];
     zero_acc(acc);
-    tile_mm<false, true>(acc, m, xa, vb, bl.s);                     // P = Y V
+    tile_mm<false, true>(acc, m, xa, vb, bl);                     // P = Y V
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -576,10 +603,10 @@ __device__ void apply_block(double* __restrict__ Y, int R, int r0, int n, const 
     zero_acc(acc);
     if (TRANS)
         tile_mm<false, true>(acc, kBk, [&](int r, int t) { return W[r][t]; },
-                             [&](int t, int c) { return Tb[c * kBk + t]; }, bl.s);
+                             [&](int t, int c) { return Tb[c * kBk + t]; }, bl);
     else
         tile_mm<false, false>(acc, kBk, [&](int r, int t) { return W[r][t]; },
-                              [&](int t, int c) { return Tb[t * kBk + c]; }, bl.s);
+                              [&](int t, int c) { return Tb[t * kBk + c]; }, bl);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -589,7 +616,7 @@ __device__ void apply_block(double* __restrict__ Y, int R, int r0, int n, const 
         zero_acc(acc);
         tile_mm<false, false>(acc, nb, [&](int r, int t) { return W[r][t]; },
                               [&](int t, int c) { return c0 + c < m ? refl(a, ld, n, k0 + t, k0 + 1 + c0 + c) : 0.0; },
-                              bl.s);
+                              bl);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int c = c0 + tc + 16 * j;
@@ -627,7 +654,7 @@ __global__ void __launch_bounds__(256) k_core_rows(const SubDesc* __restrict__ d
         zero_acc(acc);
         if (b0 > 0)
             tile_mm<false, true>(acc, b0, xa, [&](int t, int c) { return c < bw ? l[(int64_t)(b0 + c) * ld + t] : 0.0; },
-                                 bl.s);
+                                 bl);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -673,7 +700,7 @@ __global__ void __launch_bounds__(256) k_core_weights(const SubDesc* __restrict_
                                                      const int32_t* __restrict__ order,
                                                      const double* __restrict__ Lm,
                                                      const double* __restrict__ G, double* __restrict__ W) {
-    __shared__ SliceLds sl;
+    __shared__ BlockLds bl;
     const SubDesc d = desc[sub_of_block(order)];
     const int n = d.n, nc = d.nc, ld = d.ld, R = 2 * nc;
     const int c0 = kBk * blockIdx.y;
@@ -694,7 +721,7 @@ __global__ void __launch_bounds__(256) k_core_weights(const SubDesc* __restrict_
                                 const int k = c0 + c;
                                 return (k < n && t < nc) ? g[(int64_t)k * R + t] : 0.0;
                             },
-                            sl);
+                            bl);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int a = r0 + tr + 16 * i;
@@ -782,7 +809,7 @@ __global__ void __launch_bounds__(256) k_dcore(const SubDesc* __restrict__ desc,
         if (b1 < n)
             tile_mm<true, false>(acc, n - b1,
                                  [&](int r, int t) { return r0 + r < nc ? D[(int64_t)(r0 + r) * n + b1 + t] : 0.0; },
-                                 [&](int t, int c) { return c < bw ? l[(int64_t)(b1 + t) * ld + b0 + c] : 0.0; }, bl.s);
+                                 [&](int t, int c) { return c < bw ? l[(int64_t)(b1 + t) * ld + b0 + c] : 0.0; }, bl);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
