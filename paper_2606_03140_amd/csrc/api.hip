@@ -206,7 +206,7 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         P.totc += (int64_t)nc * d.ld;
         P.totd += (int64_t)nc * n;
         P.tote += n;
-        P.tott += 4096LL * std::max(0, (n - 2 + 63) / 64);
+        P.tott += 4096LL * ((n + 63) / 64);   // T factors of the reflector blocks (and, before them, L_JJ^-1)
         P.max_n = std::max(P.max_n, n);
         P.max_nc = std::max(P.max_nc, nc);
         P.max_natoms = std::max(P.max_natoms, d.natoms);

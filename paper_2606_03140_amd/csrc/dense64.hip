@@ -26,192 +26,6 @@ constexpr int kThreads = 256;   // threads per workgroup for the per-subgraph ke
 // subgraph handled by this workgroup (longest first)
 __device__ __forceinline__ int sub_of_block(const int32_t* __restrict__ order) { return order[blockIdx.x]; }
 
-// 32 x 32 tiles staged in LDS with a padded row (33 doubles): the row-wise
-// stores and the column-wise reads of the tile products hit distinct banks.
-constexpr int kTb = 32;
-
-// acc[2][2] += sA[r][k] * sB[c][k] over k < kn for this thread's 2 x 2
-// outputs (rows 2 (t / 16) + {0, 1}, columns 2 (t % 16) + {0, 1} of a
-// 32 x 32 tile, 256 threads; the B operand is staged as rows of the
-// transposed operand)
-__device__ __forceinline__ void tile_nt(double acc[2][2], const double (*sA)[kTb + 1], const double (*sB)[kTb + 1],
-                                        int kn) {
-    const int t = threadIdx.x;
-    const int r = 2 * (t >> 4), c = 2 * (t & 15);
-    for (int k = 0; k < kn; ++k) {
-        const double a0 = sA[r][k], a1 = sA[r + 1][k];
-        const double b0 = sB[c][k], b1 = sB[c + 1][k];
-        acc[0][0] += a0 * b0;
-        acc[0][1] += a0 * b1;
-        acc[1][0] += a1 * b0;
-        acc[1][1] += a1 * b1;
-    }
-}
-
-// ------------------------------------------------------------- Cholesky
-// Left-looking blocked Cholesky s = L L^T in place (lower triangle), one
-// workgroup per subgraph, block columns of 32: the panel rows of block column
-// J take the update - L[:, 0:J] L[J, 0:J]^T tile by tile (32 x 32 tiles of the
-// two factors staged in LDS, 2 x 4 outputs per thread), then the 32 x 32
-// diagonal block is factored in LDS and the rows below are solved against it
-// (one thread per row).  A non-positive pivot raises GDM_STATUS_NOT_PD.
-__global__ void __launch_bounds__(kThreads) k_potrf(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
-                                             double* __restrict__ Sd, int* __restrict__ status) {
-    __shared__ double sA[kTb][kTb + 1], sB[kTb][kTb + 1];
-    const SubDesc d = desc[sub_of_block(order)];
-    const int n = d.n, ld = d.ld;
-    double* a = Sd + d.off2;
-    const int t = threadIdx.x;
-    const int tr = 2 * (t >> 4), tc = 2 * (t & 15);
-    const int nbk = (n + kTb - 1) / kTb;
-    for (int J = 0; J < nbk; ++J) {
-        const int j0 = J * kTb, jn = min(kTb, n - j0);
-        // panel update, row blocks I >= J
-        for (int I = J; I < nbk; ++I) {
-            const int i0 = I * kTb;
-            double acc[2][2] = {{0, 0}, {0, 0}};
-            for (int K = 0; K < J; ++K) {
-                const int k0 = K * kTb;
-                __syncthreads();
-                for (int e = t; e < kTb * kTb; e += kThreads) {
-                    const int rr = e >> 5, kk = e & 31;
-                    sA[rr][kk] = i0 + rr < n ? a[(int64_t)(i0 + rr) * ld + k0 + kk] : 0.0;
-                    sB[rr][kk] = j0 + rr < n ? a[(int64_t)(j0 + rr) * ld + k0 + kk] : 0.0;
-                }
-                __syncthreads();
-                tile_nt(acc, sA, sB, kTb);
-            }
-            if (J > 0)
-                for (int rr = 0; rr < 2; ++rr)
-                    for (int q = 0; q < 2; ++q) {
-                        const int i = i0 + tr + rr, j = j0 + tc + q;
-                        if (i < n && j < n && j <= i) a[(int64_t)i * ld + j] -= acc[rr][q];
-                    }
-        }
-        __syncthreads();
-        // factor the diagonal block in LDS
-        for (int e = t; e < kTb * kTb; e += kThreads) {
-            const int rr = e >> 5, cc = e & 31;
-            sA[rr][cc] = (rr < jn && cc <= rr) ? a[(int64_t)(j0 + rr) * ld + j0 + cc] : 0.0;
-        }
-        __syncthreads();
-        for (int c = 0; c < jn; ++c) {
-            if (t == 0) {
-                double v = sA[c][c];
-                if (!(v > 0.0)) {
-                    gdm_raise(status, GDM_STATUS_NOT_PD);
-                    v = 1.0;
-                }
-                sA[c][c] = sqrt(v);
-            }
-            __syncthreads();
-            if (t > c && t < jn) sA[t][c] /= sA[c][c];
-            __syncthreads();
-            for (int e = t; e < kTb * kTb; e += kThreads) {
-                const int rr = e >> 5, cc = e & 31;
-                if (rr > c && cc > c && cc <= rr && rr < jn) sA[rr][cc] -= sA[rr][c] * sA[cc][c];
-            }
-            __syncthreads();
-        }
-        for (int e = t; e < kTb * kTb; e += kThreads) {
-            const int rr = e >> 5, cc = e & 31;
-            if (rr < jn && cc <= rr) a[(int64_t)(j0 + rr) * ld + j0 + cc] = sA[rr][cc];
-        }
-        // rows below: L[i, J] L_JJ^T = A[i, J], one thread per row
-        for (int i = j0 + jn + t; i < n; i += kThreads) {
-            double* ri = a + (int64_t)i * ld + j0;
-            for (int c = 0; c < jn; ++c) {
-                double v = ri[c];
-                for (int cc = 0; cc < c; ++cc) v -= ri[cc] * sA[c][cc];
-                ri[c] = v / sA[c][c];
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------- triangular solves, h_perp
-// X = L^-1 B for 64 right-hand-side columns per workgroup (grid: subgraph x
-// column block), left-looking in row blocks of 32: a row block takes
-// B - L[I, 0:I] X[0:I, :] (32 x 32 tiles of L and of the rows of X already
-// solved, staged in LDS), then the 32 x 32 diagonal block is solved in LDS
-// by columns.  MODE 0: B = A (h), result into T.  MODE 1: B = T^T, result
-// into A (so A becomes L^-1 h L^-T).
-constexpr int kTc = 64;
-
-template <int MODE>
-__global__ void __launch_bounds__(kThreads) k_trsm(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
-                                            const double* __restrict__ Lm, double* __restrict__ A,
-                                            double* __restrict__ T) {
-    __shared__ double sL[kTb][kTb + 1];
-    __shared__ double sX[kTc][kTb + 1];     // transposed: sX[col][k]
-    __shared__ double sR[kTb][kTc + 1];     // the row block being solved
-    const SubDesc d = desc[sub_of_block(order)];
-    const int n = d.n, ld = d.ld;
-    const int c0 = blockIdx.y * kTc;
-    if (c0 >= n) return;
-    const double* l = Lm + d.off2;
-    double* a = A + d.off2;
-    double* tt = T + d.off2;
-    double* X = MODE == 0 ? tt : a;
-    const int t = threadIdx.x;
-    // outputs: rows 2 (t / 16) + {0, 1}, columns 4 (t % 16) + {0..3} of the 32 x 64 block
-    const int tr = 2 * (t >> 4), tc = 4 * (t & 15);
-    const int nbk = (n + kTb - 1) / kTb;
-    for (int I = 0; I < nbk; ++I) {
-        const int i0 = I * kTb, in = min(kTb, n - i0);
-        double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-        for (int K = 0; K < I; ++K) {
-            const int k0 = K * kTb;
-            __syncthreads();
-            for (int e = t; e < kTb * kTb; e += kThreads) {
-                const int rr = e >> 5, kk = e & 31;
-                sL[rr][kk] = i0 + rr < n ? l[(int64_t)(i0 + rr) * ld + k0 + kk] : 0.0;
-            }
-            for (int e = t; e < kTb * kTc; e += kThreads) {
-                const int kk = e >> 6, cc = e & 63;
-                sX[cc][kk] = c0 + cc < n ? X[(int64_t)(k0 + kk) * ld + c0 + cc] : 0.0;
-            }
-            __syncthreads();
-            for (int k = 0; k < kTb; ++k) {
-                const double a0 = sL[tr][k], a1 = sL[tr + 1][k];
-                for (int q = 0; q < 4; ++q) {
-                    const double bq = sX[tc + q][k];
-                    acc[0][q] += a0 * bq;
-                    acc[1][q] += a1 * bq;
-                }
-            }
-        }
-        __syncthreads();
-        // right-hand side minus the update, and the diagonal block of L
-        for (int rr = 0; rr < 2; ++rr)
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + tr + rr, c = c0 + tc + q;
-                double b = 0.0;
-                if (i < n && c < n) b = MODE == 0 ? a[(int64_t)i * ld + c] : tt[(int64_t)c * ld + i];
-                sR[tr + rr][tc + q] = b - acc[rr][q];
-            }
-        for (int e = t; e < kTb * kTb; e += kThreads) {
-            const int rr = e >> 5, kk = e & 31;
-            sL[rr][kk] = (rr < in && kk <= rr) ? l[(int64_t)(i0 + rr) * ld + i0 + kk] : 0.0;
-        }
-        __syncthreads();
-        for (int r = 0; r < in; ++r) {
-            if (t < kTc) sR[r][t] /= sL[r][r];
-            __syncthreads();
-            for (int e = t; e < (in - r - 1) * kTc; e += kThreads) {
-                const int rr = r + 1 + (e >> 6), cc = e & 63;
-                sR[rr][cc] -= sL[rr][r] * sR[r][cc];
-            }
-            __syncthreads();
-        }
-        for (int e = t; e < in * kTc; e += kThreads) {
-            const int rr = e >> 6, cc = e & 63;
-            if (c0 + cc < n) X[(int64_t)(i0 + rr) * ld + c0 + cc] = sR[rr][cc];
-        }
-    }
-}
-
 // A <- (A + A^T)/2 (exact symmetry for the reduction)
 __global__ void __launch_bounds__(kThreads) k_symmetrize(const SubDesc* __restrict__ desc,
                                                   const int32_t* __restrict__ order, double* __restrict__ A) {
@@ -631,6 +445,170 @@ __device__ void apply_block(double* __restrict__ Y, int R, int r0, int n, const 
     }
 }
 
+// ------------------------------------------------------------- Cholesky
+// Left-looking blocked Cholesky s = L L^T (lower triangle, in place), one
+// workgroup per subgraph, block columns of 64.  For block column J: the
+// diagonal block takes - L[J, 0:J] L[J, 0:J]^T (one tile product on the FP64
+// matrix cores), is factored in LDS and inverted there (forward
+// substitution of the identity, one column per lane); the inverse is kept
+// (Linv, 64 x 64 per block, in the region the reflector factors use later)
+// for the rows below, L[I, J] = (A[I, J] - L[I, 0:J] L[J, 0:J]^T) L_JJ^-T
+// (two tile products), and for the triangular solves.  A non-positive pivot
+// raises GDM_STATUS_NOT_PD.
+__global__ void __launch_bounds__(256) k_potrf(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                              double* __restrict__ Sd, double* __restrict__ Linv,
+                                              int* __restrict__ status) {
+    extern __shared__ double lds[];
+    double (*W)[kBkS] = (double (*)[kBkS])lds;
+    BlockLds& bl = *(BlockLds*)(lds + kBk * kBkS);
+    const SubDesc d = desc[sub_of_block(order)];
+    const int n = d.n, ld = d.ld;
+    double* a = Sd + d.off2;
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+    for (int j0 = 0; j0 < n; j0 += kBk) {
+        const int jn = min(kBk, n - j0);
+        double* li = Linv + d.offt + (int64_t)kBk * j0;
+        double acc[4][4];
+        zero_acc(acc);
+        if (j0 > 0)
+            tile_mm<true, true>(acc, j0, [&](int r, int t) { return r < jn ? a[(int64_t)(j0 + r) * ld + t] : 0.0; },
+                                [&](int t, int c) { return c < jn ? a[(int64_t)(j0 + c) * ld + t] : 0.0; }, bl);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = tr + 16 * i, c = tc + 16 * j;
+                double v = r == c ? 1.0 : 0.0;                     // identity beyond the block
+                if (r < jn && c <= r) v = a[(int64_t)(j0 + r) * ld + j0 + c] - acc[i][j];
+                W[r][c] = v;
+            }
+        __syncthreads();
+        // factor the diagonal block in LDS (right-looking, column by column)
+        for (int c = 0; c < jn; ++c) {
+            if (tid == 0) {
+                double v = W[c][c];
+                if (!(v > 0.0)) {
+                    gdm_raise(status, GDM_STATUS_NOT_PD);
+                    v = 1.0;
+                }
+                W[c][c] = sqrt(v);
+            }
+            __syncthreads();
+            if (tid > c && tid < jn) W[tid][c] /= W[c][c];
+            __syncthreads();
+            for (int e = tid; e < kBk * kBk; e += 256) {
+                const int rr = e >> 6, cc = e & 63;
+                if (rr > c && cc > c && cc <= rr && rr < jn) W[rr][cc] -= W[rr][c] * W[cc][c];
+            }
+            __syncthreads();
+        }
+        // inverse of the lower-triangular factor: lane j owns column j
+        if (tid < kBk) {
+            const int j = tid;
+            for (int r = 0; r < kBk; ++r) {
+                double v = 0.0;
+                if (r >= j) {
+                    v = r == j ? 1.0 : 0.0;
+                    for (int k = j; k < r; ++k) v -= W[r][k] * bl.m[k][j];
+                    v /= W[r][r];
+                }
+                bl.m[r][j] = v;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < kBk * kBk; e += 256) {
+            const int rr = e >> 6, cc = e & 63;
+            li[e] = bl.m[rr][cc];
+            if (rr < jn && cc <= rr) a[(int64_t)(j0 + rr) * ld + j0 + cc] = W[rr][cc];
+        }
+        __syncthreads();
+        // rows below the diagonal block
+        for (int i0 = j0 + jn; i0 < n; i0 += kBk) {
+            zero_acc(acc);
+            if (j0 > 0)
+                tile_mm<true, true>(acc, j0,
+                                    [&](int r, int t) { return i0 + r < n ? a[(int64_t)(i0 + r) * ld + t] : 0.0; },
+                                    [&](int t, int c) { return c < jn ? a[(int64_t)(j0 + c) * ld + t] : 0.0; }, bl);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = i0 + tr + 16 * i, c = tc + 16 * j;
+                    W[tr + 16 * i][c] = (r < n && c < jn) ? a[(int64_t)r * ld + j0 + c] - acc[i][j] : 0.0;
+                }
+            __syncthreads();
+            zero_acc(acc);
+            tile_mm<false, true>(acc, jn, [&](int r, int t) { return W[r][t]; },
+                                 [&](int t, int c) { return li[c * kBk + t]; }, bl);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = i0 + tr + 16 * i, c = tc + 16 * j;
+                    if (r < n && c < jn) a[(int64_t)r * ld + j0 + c] = acc[i][j];
+                }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------- triangular solves, h_perp
+// X = L^-1 B for 64 right-hand-side columns per workgroup (grid: subgraph x
+// column block), left-looking in row blocks of 64: a row block takes
+// R = B - L[I, 0:I] X[0:I, :] as one tile product over every row already
+// solved, then X_I = L_II^-1 R with the inverse kept by the Cholesky (both
+// on the FP64 matrix cores).  MODE 0: B = A (h), result into T.  MODE 1:
+// B = T^T, result into A (so A becomes L^-1 h L^-T).
+constexpr int kTc = 64;
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_trsm(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+                                             const double* __restrict__ Lm, const double* __restrict__ Linv,
+                                             double* __restrict__ A, double* __restrict__ T) {
+    extern __shared__ double lds[];
+    double (*W)[kBkS] = (double (*)[kBkS])lds;       // the row block being solved
+    BlockLds& bl = *(BlockLds*)(lds + kBk * kBkS);
+    const SubDesc d = desc[sub_of_block(order)];
+    const int n = d.n, ld = d.ld;
+    const int c0 = blockIdx.y * kTc;
+    if (c0 >= n) return;
+    const double* l = Lm + d.off2;
+    double* a = A + d.off2;
+    double* tt = T + d.off2;
+    double* X = MODE == 0 ? tt : a;
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+    for (int i0 = 0; i0 < n; i0 += kBk) {
+        const int in = min(kBk, n - i0);
+        const double* li = Linv + d.offt + (int64_t)kBk * i0;
+        double acc[4][4];
+        zero_acc(acc);
+        if (i0 > 0)
+            tile_mm<true, false>(acc, i0, [&](int r, int t) { return i0 + r < n ? l[(int64_t)(i0 + r) * ld + t] : 0.0; },
+                                 [&](int t, int c) { return c0 + c < n ? X[(int64_t)t * ld + c0 + c] : 0.0; }, bl);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = i0 + tr + 16 * i, c = c0 + tc + 16 * j;
+                double b = 0.0;
+                if (r < n && c < n) b = MODE == 0 ? a[(int64_t)r * ld + c] : tt[(int64_t)c * ld + r];
+                W[tr + 16 * i][tc + 16 * j] = b - acc[i][j];
+            }
+        __syncthreads();
+        zero_acc(acc);
+        tile_mm<true, false>(acc, in, [&](int r, int t) { return li[r * kBk + t]; },
+                             [&](int t, int c) { return W[t][c]; }, bl);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = i0 + tr + 16 * i, c = c0 + tc + 16 * j;
+                if (r < n && c < n) X[(int64_t)r * ld + c] = acc[i][j];
+            }
+        __syncthreads();
+    }
+}
+
 __global__ void __launch_bounds__(256) k_core_rows(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
                                                   const double* __restrict__ Lm, const double* __restrict__ A,
                                                   const double* __restrict__ Tm, double* __restrict__ G,
@@ -1027,11 +1005,13 @@ static Fp64Lds fp64_lds(const Plan& P) {
 int gdm_fp64_plan_lds(gdm_ctx* ctx) {
     const Fp64Lds L = fp64_lds(ctx->plan);
     int rc;
-    if ((rc = set_lds(ctx, (const void*)k_potrf, L.n))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_potrf, kRowsLds))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * L.n))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_house_t, kRowsLds))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_core_rows, kRowsLds))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_mu_partial, 2 * L.n))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_trsm<0>, kRowsLds))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_trsm<1>, kRowsLds))) return rc;
     return set_lds(ctx, (const void*)k_dcore, kRowsLds);
 }
 
@@ -1059,19 +1039,22 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     if ((rc = gdm_launch_gather(ctx, sys, sg, row_ptr, col, nnz, H, S, A, Sd, orth))) return rc;
     const Fp64Lds L = fp64_lds(P);
     const size_t lds_n = L.n;
-    if ((rc = set_lds(ctx, (const void*)k_potrf, lds_n))) return rc;
+    double* Linv = (double*)ctx->b[BUF_HT].p;     // L_JJ^-1 blocks, until the reflector factors take the region
+    if ((rc = set_lds(ctx, (const void*)k_potrf, kRowsLds))) return rc;
     GDM_LAUNCH_CHECK(ctx);
     { GDM_TIMED(ctx, "potrf");
-    hipLaunchKernelGGL(k_potrf, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, Sd, ctx->d_status);
+    hipLaunchKernelGGL(k_potrf, dim3(ns), dim3(256), kRowsLds, ctx->stream, desc, order, Sd, Linv, ctx->d_status);
     }
     GDM_LAUNCH_CHECK(ctx);
     const dim3 tgrid((unsigned)ns, (unsigned)((P.max_n + kTc - 1) / kTc));
+    if ((rc = set_lds(ctx, (const void*)k_trsm<0>, kRowsLds))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_trsm<1>, kRowsLds))) return rc;
     { GDM_TIMED(ctx, "trsm");
-    hipLaunchKernelGGL(k_trsm<0>, tgrid, dim3(kThreads), 0, ctx->stream, desc, order, Sd, A, T);
+    hipLaunchKernelGGL(k_trsm<0>, tgrid, dim3(256), kRowsLds, ctx->stream, desc, order, Sd, Linv, A, T);
     }
     GDM_LAUNCH_CHECK(ctx);
     { GDM_TIMED(ctx, "trsm");
-    hipLaunchKernelGGL(k_trsm<1>, tgrid, dim3(kThreads), 0, ctx->stream, desc, order, Sd, A, T);
+    hipLaunchKernelGGL(k_trsm<1>, tgrid, dim3(256), kRowsLds, ctx->stream, desc, order, Sd, Linv, A, T);
     }
     GDM_LAUNCH_CHECK(ctx);
     { GDM_TIMED(ctx, "symmetrize");
