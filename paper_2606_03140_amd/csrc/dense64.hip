@@ -292,30 +292,49 @@ __device__ __forceinline__ void tile_mm(double (&acc)[4][4], int K, FA fa, FB fb
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) m[i][j] = dbl4v{0.0, 0.0, 0.0, 0.0};
-    for (int t0 = 0; t0 < K; t0 += kBkK) {
-        for (int e = tid; e < kBk * kBkK; e += 256) {
-            int rr, tt;
-            if (AT) {
-                tt = e & (kBkK - 1);
-                rr = e >> 4;
-            } else {
-                rr = e & (kBk - 1);
-                tt = e >> 6;
-            }
-            L.a[tt][rr] = t0 + tt < K ? fa(rr, t0 + tt) : 0.0;
+    // this thread's four elements of each 64 x 16 slice, loaded one slice
+    // ahead into registers so that the loads overlap the products
+    auto idx_a = [](int e, int& rr, int& tt) {
+        if (AT) {
+            tt = e & (kBkK - 1);
+            rr = e >> 4;
+        } else {
+            rr = e & (kBk - 1);
+            tt = e >> 6;
         }
-        for (int e = tid; e < kBk * kBkK; e += 256) {
-            int cc, tt;
-            if (BT) {
-                tt = e & (kBkK - 1);
-                cc = e >> 4;
-            } else {
-                cc = e & (kBk - 1);
-                tt = e >> 6;
-            }
-            L.b[tt][cc] = t0 + tt < K ? fb(t0 + tt, cc) : 0.0;
+    };
+    auto idx_b = [](int e, int& cc, int& tt) {
+        if (BT) {
+            tt = e & (kBkK - 1);
+            cc = e >> 4;
+        } else {
+            cc = e & (kBk - 1);
+            tt = e >> 6;
+        }
+    };
+    double ra[4], rb[4];
+    auto load = [&](int t0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int rr, tt, cc, tb;
+            idx_a(tid + 256 * q, rr, tt);
+            idx_b(tid + 256 * q, cc, tb);
+            ra[q] = t0 + tt < K ? fa(rr, t0 + tt) : 0.0;
+            rb[q] = t0 + tb < K ? fb(t0 + tb, cc) : 0.0;
+        }
+    };
+    if (K > 0) load(0);
+    for (int t0 = 0; t0 < K; t0 += kBkK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int rr, tt, cc, tb;
+            idx_a(tid + 256 * q, rr, tt);
+            idx_b(tid + 256 * q, cc, tb);
+            L.a[tt][rr] = ra[q];
+            L.b[tb][cc] = rb[q];
         }
         __syncthreads();
+        if (t0 + kBkK < K) load(t0 + kBkK);
 #pragma unroll
         for (int kk = 0; kk < kBkK; kk += 4) {
             double a[2], b[2];
