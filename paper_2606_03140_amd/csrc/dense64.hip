@@ -845,17 +845,34 @@ constexpr int kMuK = 256;
 constexpr int kMuC = 32;
 constexpr int kMuRounds = 11;    // 33^11 > 1e16: any bracket narrower than 1e4 eV reaches 1e-12 eV
 
-__global__ void __launch_bounds__(kMuK) k_mu_bounds(const SubDesc* __restrict__ desc, int n_sub,
-                                                   const double* __restrict__ Lam, double* __restrict__ state) {
+// spectral bounds: one wave per subgraph (min and max of its eigenvalues),
+// then one workgroup over the subgraphs (min and max are exact in any order)
+__global__ void __launch_bounds__(64) k_mu_bounds_part(const SubDesc* __restrict__ desc,
+                                                      const double* __restrict__ Lam, double* __restrict__ part) {
+    const SubDesc d = desc[blockIdx.x];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int k = threadIdx.x; k < d.n; k += 64) {
+        const double v = Lam[d.offv + k];
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmax(hi, __shfl_xor(hi, o, 64));
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = lo;
+        part[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+__global__ void __launch_bounds__(kMuK) k_mu_bounds(int n_sub, const double* __restrict__ part,
+                                                   double* __restrict__ state) {
     __shared__ double smin[kMuK], smax[kMuK];
     double lo = INFINITY, hi = -INFINITY;
-    for (int s = 0; s < n_sub; ++s) {
-        const SubDesc d = desc[s];
-        for (int k = threadIdx.x; k < d.n; k += kMuK) {
-            double v = Lam[d.offv + k];
-            lo = fmin(lo, v);
-            hi = fmax(hi, v);
-        }
+    for (int s = threadIdx.x; s < n_sub; s += kMuK) {
+        lo = fmin(lo, part[2 * s]);
+        hi = fmax(hi, part[2 * s + 1]);
     }
     smin[threadIdx.x] = lo;
     smax[threadIdx.x] = hi;
@@ -1106,7 +1123,9 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     // chemical potential: multisection rounds
     const double beta = 1.0 / kT;
     GDM_TIMED(ctx, "mu");
-    hipLaunchKernelGGL(k_mu_bounds, dim3(1), dim3(kMuK), 0, ctx->stream, desc, ns, Lam, state);
+    hipLaunchKernelGGL(k_mu_bounds_part, dim3(ns), dim3(64), 0, ctx->stream, desc, Lam, partial);
+    GDM_LAUNCH_CHECK(ctx);
+    hipLaunchKernelGGL(k_mu_bounds, dim3(1), dim3(kMuK), 0, ctx->stream, ns, partial, state);
     GDM_LAUNCH_CHECK(ctx);
     const size_t lds_lw = 2 * lds_n;
     if ((rc = set_lds(ctx, (const void*)k_mu_partial, lds_lw))) return rc;
