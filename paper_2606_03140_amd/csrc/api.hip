@@ -215,7 +215,7 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
     // solvers on one context holds one solver's arena, not both
     static const int kFp64Only[] = {BUF_TAU, BUF_D, BUF_E, BUF_LAM, BUF_W, BUF_DCU, BUF_DCAUX,
                                     BUF_DCIDX, BUF_DCLIST, BUF_QC, BUF_QC2, BUF_HT, BUF_MU,
-                                    BUF_MUPART};
+                                    BUF_MUPART, BUF_TRDP};
     static const int kMixedOnly[] = {BUF_X_F, BUF_X_HI, BUF_X_LO, BUF_GERSH, BUF_TR, BUF_NDBL, BUF_TILES,
                                      BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_MSTATE};
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -236,6 +236,9 @@ static int plan_impl(gdm_ctx* ctx, const gdm_subgraphs* sg, int precision) {
         gdm_buf(ctx, BUF_CC, sizeof(double) * P.totc, &ok);
         gdm_buf(ctx, BUF_MU, sizeof(double) * 8, &ok);
         gdm_buf(ctx, BUF_MUPART, sizeof(double) * 256 * (size_t)ns, &ok);
+        // tile sums of the tridiagonalisation's product, per subgraph
+        // 64 T (T + 1) doubles with T = ceil(ld / 64), below ld^2/64 + 3 ld + 128
+        gdm_buf(ctx, BUF_TRDP, sizeof(double) * (size_t)(P.tot2 / 64 + 3 * P.totv + 128LL * ns), &ok);
         // workgroups take the subgraphs in decreasing size (ties by index)
         P.order.resize(ns);
         for (int s = 0; s < ns; ++s) P.order[s] = s;

@@ -70,9 +70,32 @@ __device__ __forceinline__ double block_sum_n(double v, double* red, int nthread
     return s;
 }
 
+// columns 0..j-1 of row r of the panel's V and W (zero beyond j): all loads
+// issued before any is used
+__device__ __forceinline__ void panel_row(const double* __restrict__ Vm, const double* __restrict__ Wm, int n, int r,
+                                          int j, double (&vr)[kPanel], double (&wr)[kPanel]) {
+#pragma unroll
+    for (int l = 0; l < kPanel; ++l) {
+        vr[l] = l < j ? Vm[(int64_t)l * n + r] : 0.0;
+        wr[l] = l < j ? Wm[(int64_t)l * n + r] : 0.0;
+    }
+}
+
+// one exchange of the row-sum butterfly: lanes with `up` keep rows h..2h-1,
+// the others rows 0..h-1, each adding its partner's copy of the rows it keeps
+template <int H>
+__device__ __forceinline__ void fold_half(double* x, bool up, int mask) {
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+        const double keep = up ? x[H + r] : x[r], give = up ? x[r] : x[H + r];
+        x[r] = keep + __shfl_xor(give, mask, 64);
+    }
+}
+
 __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
                                              double* __restrict__ A, double* __restrict__ W2, double* __restrict__ Dg,
-                                             double* __restrict__ Eg, double* __restrict__ Tau) {
+                                             double* __restrict__ Eg, double* __restrict__ Tau,
+                                             double* __restrict__ TrdPart) {
     extern __shared__ double sm[];
     __shared__ double red[kTrd / 64];
     __shared__ double corr[4 * kPanel];     // V[k,:], W[k,:], W^T v, V^T v of the current step
@@ -88,6 +111,9 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int nb = kPanel;
     while (nb > 1 && 2LL * n * nb > (int64_t)ld * ld) nb >>= 1;
+    // tile sums of the product: T (T + 1)/2 slots of 128 doubles, T = ceil(n / 64);
+    // 64 T (T + 1) <= (ld + 63)(ld + 127)/64 < ld^2/64 + 3 ld + 128 per subgraph
+    double* Pt = TrdPart + dsc.off2 / 64 + 3 * dsc.offv + 128LL * sub_of_block(order);
     double* Vm = W2 + dsc.off2;              // V[r][l] = Vm[l * n + r]
     double* Wm = Vm + (int64_t)n * nb;
     for (int k0 = 0; k0 < n - 2; k0 += nb) {
@@ -106,8 +132,11 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
             for (int i = threadIdx.x; i < m; i += kTrd) {
                 const int r = k + 1 + i;
                 double x = a[(int64_t)k * ld + r];
-                for (int l = 0; l < j; ++l)
-                    x -= Vm[(int64_t)l * n + r] * corr[kPanel + l] + Wm[(int64_t)l * n + r] * corr[l];
+                double vr[kPanel], wr[kPanel];
+                panel_row(Vm, Wm, n, r, j, vr, wr);
+#pragma unroll
+                for (int l = 0; l < kPanel; ++l)
+                    if (l < j) x -= vr[l] * corr[kPanel + l] + wr[l] * corr[l];
                 v[i] = x;
                 if (i > 0) part += x * x;
             }
@@ -133,46 +162,78 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
             __syncthreads();
             for (int i = threadIdx.x; i < m; i += kTrd) v[i] = i == 0 ? 1.0 : v[i] * scale;
             __syncthreads();
-            // p = A22 v, A22 = A[k+1:, k+1:] as at the panel's start (symmetric):
-            // thread t accumulates columns t, t + kTrd, ... over all rows, so
-            // every load is a coalesced piece of a row and the loads of
-            // successive rows are independent (many in flight per thread)
-            for (int c0 = threadIdx.x; c0 < m; c0 += 2 * kTrd) {
-                const int c1 = c0 + kTrd;
-                const bool two = c1 < m;
+            // p = A22 v, A22 = A[k+1:, k+1:] as at the panel's start (symmetric),
+            // reading the lower triangle only: 64 x 64 tiles (I >= J) dealt
+            // round-robin to the waves, lane = column j, 32 rows of the tile
+            // loaded at once.  A tile gives its column sums A_IJ^T v_I in
+            // registers (for p[J]) and its row sums A_IJ v_J (for p[I],
+            // strictly lower part on the diagonal tile) by a butterfly: at
+            // the exchange over lane bit b each lane keeps the half of its
+            // rows selected by that bit, so after bits 0..4 lane l holds one
+            // row's sum over 32 lanes and the exchange over bit 5 completes
+            // it.  Both go to the tile's slot in Pt and are added per row in
+            // tile order afterwards.
+            {
                 const double* col = a + (int64_t)(k + 1) * ld + (k + 1);
-                double s0 = 0.0, s1 = 0.0, u0 = 0.0, u1 = 0.0;
-                int i = 0;
-                for (; i + 7 < m; i += 8) {
-                    double x[8], y[8];
+                const int T = (m + 63) >> 6, ntile = T * (T + 1) / 2;
+                const int rsel = 16 * (lane & 1) + 8 * ((lane >> 1) & 1) + 4 * ((lane >> 2) & 1) +
+                                 2 * ((lane >> 3) & 1) + ((lane >> 4) & 1);
+                for (int tile = wave; tile < ntile; tile += kTrd / 64) {
+                    int I = 0;
+                    while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+                    const int J = tile - I * (I + 1) / 2;
+                    const int j = J * 64 + lane;
+                    const double vj = j < m ? v[j] : 0.0;
+                    // loads from clamped indices (row uniform, one lane offset), masked after
+                    const uint32_t jc = (uint32_t)min(j, m - 1);
+                    double colacc = 0.0;
+                    double* pt = Pt + (int64_t)tile * 128;
+                    for (int c0 = 0; c0 < 64; c0 += 32) {
+                        double x[32];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const double* rq = col + (int64_t)(i + q) * ld;
-                        x[q] = rq[c0];
-                        y[q] = two ? rq[c1] : 0.0;
-                    }
+                        for (int q = 0; q < 32; ++q) {
+                            const int i = I * 64 + c0 + q;
+                            const double* row = col + (int64_t)min(i, m - 1) * ld;
+                            const double xv = row[jc];
+                            x[q] = (i < m && j < m && (I > J || i >= j)) ? xv : 0.0;
+                        }
 #pragma unroll
-                    for (int q = 0; q < 8; q += 2) {
-                        s0 += x[q] * v[i + q];
-                        s1 += x[q + 1] * v[i + q + 1];
-                        u0 += y[q] * v[i + q];
-                        u1 += y[q + 1] * v[i + q + 1];
+                        for (int q = 0; q < 32; ++q) {
+                            const int i = I * 64 + c0 + q;
+                            colacc += x[q] * (i < m ? v[i] : 0.0);
+                            x[q] = (I > J || i > j) ? x[q] * vj : 0.0;
+                        }
+                        fold_half<16>(x, lane & 1, 1);
+                        fold_half<8>(x, lane & 2, 2);
+                        fold_half<4>(x, lane & 4, 4);
+                        fold_half<2>(x, lane & 8, 8);
+                        fold_half<1>(x, lane & 16, 16);
+                        x[0] += __shfl_xor(x[0], 32, 64);
+                        if (lane < 32) pt[64 + c0 + rsel] = x[0];
                     }
+                    pt[lane] = colacc;
                 }
-                for (; i < m; ++i) {
-                    const double* r0 = col + (int64_t)i * ld;
-                    s0 += r0[c0] * v[i];
-                    if (two) u0 += r0[c1] * v[i];
+                __syncthreads();
+                for (int xr = threadIdx.x; xr < m; xr += kTrd) {
+                    const int B = xr >> 6, xl = xr & 63;
+                    double acc = 0.0;
+                    for (int J = 0; J <= B; ++J) acc += Pt[(int64_t)(B * (B + 1) / 2 + J) * 128 + 64 + xl];
+                    for (int I = B; I < T; ++I) acc += Pt[(int64_t)(I * (I + 1) / 2 + B) * 128 + xl];
+                    p[xr] = acc;
                 }
-                p[c0] = s0 + s1;
-                if (two) p[c1] = u0 + u1;
             }
             // W^T v and V^T v over rows k+1.. (one wave per panel column)
             for (int l = wave; l < 2 * j; l += kTrd / 64) {
                 const double* col = (l < j ? Wm + (int64_t)l * n : Vm + (int64_t)(l - j) * n) + (k + 1);
-                double acc = 0.0;
-                for (int i = lane; i < m; i += 64) acc += col[i] * v[i];
-                acc = gdm_wave_sum(acc);
+                double acc = 0.0, acc2 = 0.0;
+                int i = lane;
+                for (; i + 192 < m; i += 256) {
+                    const double c0 = col[i], c1 = col[i + 64], c2 = col[i + 128], c3 = col[i + 192];
+                    acc += c0 * v[i] + c2 * v[i + 128];
+                    acc2 += c1 * v[i + 64] + c3 * v[i + 192];
+                }
+                for (; i < m; i += 64) acc += col[i] * v[i];
+                acc = gdm_wave_sum(acc + acc2);
                 if (lane == 0) corr[2 * kPanel + l] = acc;      // [0, j): W^T v, [j, 2j): V^T v
             }
             __syncthreads();
@@ -181,8 +242,11 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
             for (int i = threadIdx.x; i < m; i += kTrd) {
                 const int r = k + 1 + i;
                 double x = p[i];
-                for (int l = 0; l < j; ++l)
-                    x -= Vm[(int64_t)l * n + r] * corr[2 * kPanel + l] + Wm[(int64_t)l * n + r] * corr[2 * kPanel + j + l];
+                double vr[kPanel], wr[kPanel];
+                panel_row(Vm, Wm, n, r, j, vr, wr);
+#pragma unroll
+                for (int l = 0; l < kPanel; ++l)
+                    if (l < j) x -= vr[l] * corr[2 * kPanel + l] + wr[l] * corr[2 * kPanel + j + l];
                 x *= t;
                 p[i] = x;
                 part += x * v[i];
@@ -205,10 +269,11 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
         for (int rb = kend; rb < n; rb += 64) {
             const int rn = min(64, n - rb);
             __syncthreads();
-            for (int e = threadIdx.x; e < 64 * jb; e += kTrd) {
+            for (int e = threadIdx.x; e < 64 * kPanel; e += kTrd) {     // zero beyond jb: no stale LDS
                 const int rr = e & 63, l = e >> 6;
-                sVr[rr][l] = rr < rn ? Vm[(int64_t)l * n + rb + rr] : 0.0;
-                sWr[rr][l] = rr < rn ? Wm[(int64_t)l * n + rb + rr] : 0.0;
+                const bool in = rr < rn && l < jb;
+                sVr[rr][l] = in ? Vm[(int64_t)l * n + rb + rr] : 0.0;
+                sWr[rr][l] = in ? Wm[(int64_t)l * n + rb + rr] : 0.0;
             }
             __syncthreads();
             for (int cs = kend + 64 * wave; cs < n; cs += 64 * (kTrd / 64)) {
@@ -221,12 +286,19 @@ __global__ void __launch_bounds__(kTrd) k_sytrd(const SubDesc* __restrict__ desc
                     wc[l] = (cok && l < jb) ? Wm[(int64_t)l * n + c] : 0.0;
                 }
                 if (!cok) continue;
-#pragma unroll 4
-                for (int rr = 0; rr < rn; ++rr) {
-                    double acc = 0.0;
+                // 8 rows' loads in flight, then their updates
+                for (int r0 = 0; r0 < rn; r0 += 8) {
+                    double av[8];
 #pragma unroll
-                    for (int l = 0; l < kPanel; ++l) acc += sVr[rr][l] * wc[l] + sWr[rr][l] * vc[l];
-                    a[(int64_t)(rb + rr) * ld + c] -= acc;
+                    for (int u = 0; u < 8; ++u) av[u] = r0 + u < rn ? a[(int64_t)(rb + r0 + u) * ld + c] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (r0 + u >= rn) break;
+                        double acc = 0.0;
+#pragma unroll
+                        for (int l = 0; l < kPanel; ++l) acc += sVr[r0 + u][l] * wc[l] + sWr[r0 + u][l] * vc[l];
+                        a[(int64_t)(rb + r0 + u) * ld + c] = av[u] - acc;
+                    }
                 }
             }
         }
@@ -1099,7 +1171,8 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     GDM_LAUNCH_CHECK(ctx);
     if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * lds_n))) return rc;
     { GDM_TIMED(ctx, "sytrd");
-    hipLaunchKernelGGL(k_sytrd, dim3(ns), dim3(kTrd), 2 * lds_n, ctx->stream, desc, order, A, T, Dg, Eg, Tau);
+    hipLaunchKernelGGL(k_sytrd, dim3(ns), dim3(kTrd), 2 * lds_n, ctx->stream, desc, order, A, T, Dg, Eg, Tau,
+                       (double*)ctx->b[BUF_TRDP].p);
     }
     GDM_LAUNCH_CHECK(ctx);
     if ((rc = gdm_dc_solve(ctx))) return rc;

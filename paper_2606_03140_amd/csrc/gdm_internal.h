@@ -153,7 +153,7 @@ enum {
     BUF_X_HI, BUF_X_LO, BUF_X_F, BUF_Y_HI, BUF_Y_LO, BUF_Y_F, BUF_T_HI, BUF_T_LO, BUF_T_F,
     BUF_Z_HI, BUF_Z_LO, BUF_Z_F, BUF_H_HI, BUF_H_LO, BUF_H_F, BUF_TR, BUF_GERSH, BUF_NDBL,
     BUF_TILES, BUF_PASS, BUF_EWALD, BUF_MIXPART,
-    BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_KRYLOV, BUF_MSTATE, BUF_FPAIR, BUF_FMAP, BUF_ESUM,
+    BUF_HIST_HI, BUF_HIST_LO, BUF_RESP, BUF_KRYLOV, BUF_MSTATE, BUF_FPAIR, BUF_FMAP, BUF_ESUM, BUF_TRDP,
     BUF_COUNT_
 };
 
