@@ -1468,24 +1468,27 @@ static int gemm64_core(gdm_ctx* ctx, const double* A, const TB* B, double* C, co
 static double* fp64_region(gdm_ctx* ctx, int k) { return (double*)ctx->b[BUF_L].p + (int64_t)k * ctx->plan.tot2; }
 
 // The last doubling of a pass in FP64 on the matrix cores (the final
-// refinement step of the expansion): X2 = X X, A = 2 X2 - 2 X + I,
-// Y = A^-1 from Y0 = 4I - 5A + 2A^2 by kFinalNs Newton-Schulz steps,
-// X <- X2 Y.  1 - a y0(a) = (1 - a)^2 (1 - 2a) vanishes to second order at
-// a = 1 (the occupied and empty states, where X is 1 or 0 to far below FP32
-// rounding) and at a = 1/2, and is at most 1/27 between; k steps leave
-// 27^-(2^k), and since that residual is never negative after a step every
-// partly occupied state comes out low by up to that much, a bias of the
-// electron count: two steps (1.9e-6) shift it by ~1e-3 e at 80,000
-// electrons, three (3.6e-12) do not.  The doubling map is superattracting at 0 and 1, so the FP32-level
-// errors of the split-product doublings in those states are squared away
-// here instead of summing into a systematic bias of the electron count
-// (~2e-8 per orbital), which would move mu inside a gap by that bias over
-// N'(mu).  The result goes to SL_X (FP32 copy and split, whole) and, for the
-// traces and the density, stays in FP64 region 5; a recorded pass also keeps
-// the split Y for the response.  All matrices commute (polynomials in
-// h_perp), so every product computes upper tiles and mirrors them.
-constexpr int kFinalNs = 3;
-
+// refinement step of the expansion): X2 = X X, A = 2 X2 - 2 X + I in FP64,
+// Y = A^-1, X <- X2 Y.  The inverse starts on the split products: A as split
+// operands, the minimax quadratic start Y0 = (420 I - 576 A + 256 A^2)/99
+// (|1 - a y0| <= 1/99 on [1/2, 1]) and the split Newton-Schulz steps of the
+// other doublings leave I - A Y at the split products' rounding level
+// (~1e-7 for FP16 pairs, ~1e-5 for BF16 pairs).  Then FP64 steps
+// R = 2I - A Y, Y <- Y R: each maps I - A Y to (I - A Y)^2 exactly, for any
+// Y, so one step (FP16 pairs) or two (BF16 pairs) leave ~1e-14 / ~1e-20,
+// below the 3.6e-12 that three FP64 steps from Y0 = 4I - 5A + 2A^2 reached
+// (a residual left after an exact step is a square, never negative, so it
+// lowers every partly occupied state: ~1.9e-6 would bias the count by ~1e-3
+// e at 80,000 electrons).  The doubling map is superattracting at 0 and 1,
+// so the FP32-level errors of the split-product doublings in those states
+// are squared away here instead of summing into a systematic bias of the
+// electron count (~2e-8 per orbital), which would move mu inside a gap by
+// that bias over N'(mu).  The result goes to SL_X (FP32 copy and split,
+// whole) and, for the traces and the density, stays in FP64 region 5; a
+// recorded pass also keeps the split Y for the response.  All matrices
+// commute (polynomials in h_perp) up to the residual, so every product
+// computes upper tiles and mirrors them (the asymmetry a mirrored Y R drops
+// is of the order of the residual times the split error).
 static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const int* skip) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
@@ -1505,11 +1508,29 @@ static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const in
     {
         GDM_TIMED(ctx, "last64");
         hipLaunchKernelGGL(k_doubling_a, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, X, X2, A, skip);
+        GDM_LAUNCH_CHECK(ctx);
+        hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, n4, A, slot(ctx, SL_A), skip);
     }
     GDM_LAUNCH_CHECK(ctx);
-    GDM_TRY(gemm64_dd(ctx, A, A, A, Ya, 2.0, -5.0, 4.0, 1, skip, "last64"));     // Y0 = 2 A^2 - 5 A + 4 I
+    // split start and Newton-Schulz steps (whole storage: A comes whole)
+    const SplitMat As = slot(ctx, SL_A), Rs = slot(ctx, SL_R), Ysa = slot(ctx, SL_Y), Ysb = slot(ctx, SL_YI);
+    SplitMat Ys = Ysa;
+    GDM_TRY(gemm(ctx, As, As, none(), hl(Ys), hl(As), 256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f, "foe_gemm", 1,
+                 0, skip));
+    for (int k = 0; k < ctx->mixed_ns_inv; ++k) {
+        GDM_TRY(gemm(ctx, As, Ys, none(), hl(Rs), none(), -1.0f, 0.0f, 2.0f, "foe_gemm", 1, 0, skip));
+        const SplitMat Yn = Ys.hi == Ysa.hi ? Ysb : Ysa;
+        GDM_TRY(gemm(ctx, Ys, Rs, hl(Yn), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, 0, skip));
+        Ys = Yn;
+    }
+    {
+        GDM_TIMED(ctx, "last64");
+        hipLaunchKernelGGL(k_split_to_f64, dim3(4096), dim3(256), 0, ctx->stream, n4, hl(Ys), Ya, skip);
+    }
+    GDM_LAUNCH_CHECK(ctx);
     double* Y = Ya;
-    for (int k = 0; k < kFinalNs; ++k) {
+    const int final_ns = P.precision == GDM_MIXED_BF16 ? 2 : 1;
+    for (int k = 0; k < final_ns; ++k) {
         GDM_TRY(gemm64_dd(ctx, A, Y, nullptr, R, -1.0, 0.0, 2.0, 1, skip, "last64"));   // R = 2I - A Y
         double* Yn = Y == Ya ? Yb : Ya;
         GDM_TRY(gemm64_dd(ctx, Y, R, nullptr, Yn, 1.0, 0.0, 0.0, 1, skip, "last64"));   // Y <- Y R
