@@ -56,8 +56,7 @@ __global__ void __launch_bounds__(kThreads) k_symmetrize(const SubDesc* __restri
 // (needs 2 n nb <= ld^2; nb shrinks for the smallest subgraphs).  v (without
 // the unit) is stored in row k of A from column k+2 on; d, e, tau per
 // subgraph, as the core-row kernels read them.
-constexpr int kTrdWide = 512;          // threads of the tridiagonalisation: few subgraphs per CU
-constexpr int kTrdNarrow = 256;        // two or more subgraphs per CU: two workgroups share a CU
+constexpr int kTrd = 512;              // threads of the tridiagonalisation
 constexpr int kPanel = 16;             // panel width nb
 
 __device__ __forceinline__ double block_sum_n(double v, double* red, int nthreads) {
@@ -93,13 +92,12 @@ __device__ __forceinline__ void fold_half(double* x, bool up, int mask) {
     }
 }
 
-template <int NT>
-__global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+__global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
                                              double* __restrict__ A, double* __restrict__ W2, double* __restrict__ Dg,
                                              double* __restrict__ Eg, double* __restrict__ Tau,
                                              double* __restrict__ TrdPart) {
     extern __shared__ double sm[];
-    __shared__ double red[NT / 64];
+    __shared__ double red[kTrd / 64];
     __shared__ double corr[4 * kPanel];     // V[k,:], W[k,:], W^T v, V^T v of the current step
     __shared__ double sVr[64][kPanel + 1], sWr[64][kPanel + 1];   // trailing update: rows of V, W
     const SubDesc dsc = desc[sub_of_block(order)];
@@ -131,7 +129,7 @@ __global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ des
             __syncthreads();
             // x = A[k+1:, k] - V W[k,:]^T - W V[k,:]^T (held in v), and the diagonal
             double part = 0.0;
-            for (int i = threadIdx.x; i < m; i += NT) {
+            for (int i = threadIdx.x; i < m; i += kTrd) {
                 const int r = k + 1 + i;
                 double x = a[(int64_t)k * ld + r];
                 double vr[kPanel], wr[kPanel];
@@ -142,7 +140,7 @@ __global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ des
                 v[i] = x;
                 if (i > 0) part += x * x;
             }
-            const double xn2 = block_sum_n(part, red, NT);
+            const double xn2 = block_sum_n(part, red, kTrd);
             const double alpha = v[0];
             double beta, t, scale;
             if (xn2 == 0.0) {
@@ -162,7 +160,7 @@ __global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ des
                 tau[k] = t;
             }
             __syncthreads();
-            for (int i = threadIdx.x; i < m; i += NT) v[i] = i == 0 ? 1.0 : v[i] * scale;
+            for (int i = threadIdx.x; i < m; i += kTrd) v[i] = i == 0 ? 1.0 : v[i] * scale;
             __syncthreads();
             // p = A22 v, A22 = A[k+1:, k+1:] as at the panel's start (symmetric),
             // reading the lower triangle only: 64 x 64 tiles (I >= J) dealt
@@ -180,7 +178,7 @@ __global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ des
                 const int T = (m + 63) >> 6, ntile = T * (T + 1) / 2;
                 const int rsel = 16 * (lane & 1) + 8 * ((lane >> 1) & 1) + 4 * ((lane >> 2) & 1) +
                                  2 * ((lane >> 3) & 1) + ((lane >> 4) & 1);
-                for (int tile = wave; tile < ntile; tile += NT / 64) {
+                for (int tile = wave; tile < ntile; tile += kTrd / 64) {
                     int I = 0;
                     while ((I + 1) * (I + 2) / 2 <= tile) ++I;
                     const int J = tile - I * (I + 1) / 2;
@@ -216,7 +214,7 @@ __global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ des
                     pt[lane] = colacc;
                 }
                 __syncthreads();
-                for (int xr = threadIdx.x; xr < m; xr += NT) {
+                for (int xr = threadIdx.x; xr < m; xr += kTrd) {
                     const int B = xr >> 6, xl = xr & 63;
                     // the T + 1 slots of row block B (row sums of tiles (B, 0..B), then
                     // column sums of tiles (B..T-1, B)), 8 loads in flight, added in that order
@@ -237,7 +235,7 @@ __global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ des
                 }
             }
             // W^T v and V^T v over rows k+1.. (one wave per panel column)
-            for (int l = wave; l < 2 * j; l += NT / 64) {
+            for (int l = wave; l < 2 * j; l += kTrd / 64) {
                 const double* col = (l < j ? Wm + (int64_t)l * n : Vm + (int64_t)(l - j) * n) + (k + 1);
                 double acc = 0.0, acc2 = 0.0;
                 int i = lane;
@@ -253,7 +251,7 @@ __global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ des
             __syncthreads();
             // p -= V (W^T v) + W (V^T v); then w = t p - t^2/2 (p^T v) v
             part = 0.0;
-            for (int i = threadIdx.x; i < m; i += NT) {
+            for (int i = threadIdx.x; i < m; i += kTrd) {
                 const int r = k + 1 + i;
                 double x = p[i];
                 double vr[kPanel], wr[kPanel];
@@ -265,9 +263,9 @@ __global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ des
                 p[i] = x;
                 part += x * v[i];
             }
-            const double pv = block_sum_n(part, red, NT);
+            const double pv = block_sum_n(part, red, kTrd);
             const double half = 0.5 * t * pv;
-            for (int i = threadIdx.x; i < m; i += NT) {
+            for (int i = threadIdx.x; i < m; i += kTrd) {
                 const int r = k + 1 + i;
                 Vm[(int64_t)j * n + r] = v[i];
                 Wm[(int64_t)j * n + r] = p[i] - half * v[i];
@@ -283,14 +281,14 @@ __global__ void __launch_bounds__(NT, 2) k_sytrd(const SubDesc* __restrict__ des
         for (int rb = kend; rb < n; rb += 64) {
             const int rn = min(64, n - rb);
             __syncthreads();
-            for (int e = threadIdx.x; e < 64 * kPanel; e += NT) {     // zero beyond jb: no stale LDS
+            for (int e = threadIdx.x; e < 64 * kPanel; e += kTrd) {     // zero beyond jb: no stale LDS
                 const int rr = e & 63, l = e >> 6;
                 const bool in = rr < rn && l < jb;
                 sVr[rr][l] = in ? Vm[(int64_t)l * n + rb + rr] : 0.0;
                 sWr[rr][l] = in ? Wm[(int64_t)l * n + rb + rr] : 0.0;
             }
             __syncthreads();
-            for (int cs = kend + 64 * wave; cs < n; cs += 64 * (NT / 64)) {
+            for (int cs = kend + 64 * wave; cs < n; cs += 64 * (kTrd / 64)) {
                 const int c = cs + lane;
                 const bool cok = c < n;
                 double vc[kPanel], wc[kPanel];
@@ -1128,8 +1126,7 @@ int gdm_fp64_plan_lds(gdm_ctx* ctx) {
     const Fp64Lds L = fp64_lds(ctx->plan);
     int rc;
     if ((rc = set_lds(ctx, (const void*)k_potrf, kRowsLds))) return rc;
-    if ((rc = set_lds(ctx, (const void*)k_sytrd<kTrdWide>, 2 * L.n))) return rc;
-    if ((rc = set_lds(ctx, (const void*)k_sytrd<kTrdNarrow>, 2 * L.n))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * L.n))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_house_t, kRowsLds))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_core_rows, kRowsLds))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_mu_partial, 2 * L.n))) return rc;
@@ -1184,18 +1181,10 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     hipLaunchKernelGGL(k_symmetrize, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, A);
     }
     GDM_LAUNCH_CHECK(ctx);
-    // a workgroup per subgraph; with at least two subgraphs per CU the narrow
-    // form lets two of them share a CU (one waits on memory while the other runs)
-    const bool narrow = ns >= 2 * ctx->n_cu;
-    const void* trd = narrow ? (const void*)k_sytrd<kTrdNarrow> : (const void*)k_sytrd<kTrdWide>;
-    if ((rc = set_lds(ctx, trd, 2 * lds_n))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * lds_n))) return rc;
     { GDM_TIMED(ctx, "sytrd");
-    if (narrow)
-        hipLaunchKernelGGL(k_sytrd<kTrdNarrow>, dim3(ns), dim3(kTrdNarrow), 2 * lds_n, ctx->stream, desc, order, A, T,
-                           Dg, Eg, Tau, (double*)ctx->b[BUF_TRDP].p);
-    else
-        hipLaunchKernelGGL(k_sytrd<kTrdWide>, dim3(ns), dim3(kTrdWide), 2 * lds_n, ctx->stream, desc, order, A, T,
-                           Dg, Eg, Tau, (double*)ctx->b[BUF_TRDP].p);
+    hipLaunchKernelGGL(k_sytrd, dim3(ns), dim3(kTrd), 2 * lds_n, ctx->stream, desc, order, A, T, Dg, Eg, Tau,
+                       (double*)ctx->b[BUF_TRDP].p);
     }
     GDM_LAUNCH_CHECK(ctx);
     if ((rc = gdm_dc_solve(ctx))) return rc;
