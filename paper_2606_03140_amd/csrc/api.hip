@@ -64,6 +64,9 @@ extern "C" int gdm_create(gdm_ctx** out, int device, void* hip_stream) {
         delete ctx;
         return GDM_E_HIP;
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        ctx->n_cu = ncu;
     if (hipMemsetAsync(ctx->d_status, 0, sizeof(int), ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
         (void)hipFree(ctx->d_status);

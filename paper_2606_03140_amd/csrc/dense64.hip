@@ -56,7 +56,8 @@ __global__ void __launch_bounds__(kThreads) k_symmetrize(const SubDesc* __restri
 // (needs 2 n nb <= ld^2; nb shrinks for the smallest subgraphs).  v (without
 // the unit) is stored in row k of A from column k+2 on; d, e, tau per
 // subgraph, as the core-row kernels read them.
-constexpr int kTrd = 512;              // threads of the tridiagonalisation
+constexpr int kTrd = 512;              // threads of the tridiagonalisation (product chunks of 32 rows)
+constexpr int kTrdFew = 1024;          // when every subgraph has a CU of its own (chunks of 16 rows)
 constexpr int kPanel = 16;             // panel width nb
 
 __device__ __forceinline__ double block_sum_n(double v, double* red, int nthreads) {
@@ -92,12 +93,13 @@ __device__ __forceinline__ void fold_half(double* x, bool up, int mask) {
     }
 }
 
-__global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
+template <int NT, int CH>
+__global__ void __launch_bounds__(NT, NT / 256) k_sytrd(const SubDesc* __restrict__ desc, const int32_t* __restrict__ order,
                                              double* __restrict__ A, double* __restrict__ W2, double* __restrict__ Dg,
                                              double* __restrict__ Eg, double* __restrict__ Tau,
                                              double* __restrict__ TrdPart) {
     extern __shared__ double sm[];
-    __shared__ double red[kTrd / 64];
+    __shared__ double red[NT / 64];
     __shared__ double corr[4 * kPanel];     // V[k,:], W[k,:], W^T v, V^T v of the current step
     __shared__ double sVr[64][kPanel + 1], sWr[64][kPanel + 1];   // trailing update: rows of V, W
     const SubDesc dsc = desc[sub_of_block(order)];
@@ -129,7 +131,7 @@ __global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ d
             __syncthreads();
             // x = A[k+1:, k] - V W[k,:]^T - W V[k,:]^T (held in v), and the diagonal
             double part = 0.0;
-            for (int i = threadIdx.x; i < m; i += kTrd) {
+            for (int i = threadIdx.x; i < m; i += NT) {
                 const int r = k + 1 + i;
                 double x = a[(int64_t)k * ld + r];
                 double vr[kPanel], wr[kPanel];
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ d
                 v[i] = x;
                 if (i > 0) part += x * x;
             }
-            const double xn2 = block_sum_n(part, red, kTrd);
+            const double xn2 = block_sum_n(part, red, NT);
             const double alpha = v[0];
             double beta, t, scale;
             if (xn2 == 0.0) {
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ d
                 tau[k] = t;
             }
             __syncthreads();
-            for (int i = threadIdx.x; i < m; i += kTrd) v[i] = i == 0 ? 1.0 : v[i] * scale;
+            for (int i = threadIdx.x; i < m; i += NT) v[i] = i == 0 ? 1.0 : v[i] * scale;
             __syncthreads();
             // p = A22 v, A22 = A[k+1:, k+1:] as at the panel's start (symmetric),
             // reading the lower triangle only: 64 x 64 tiles (I >= J) dealt
@@ -178,7 +180,7 @@ __global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ d
                 const int T = (m + 63) >> 6, ntile = T * (T + 1) / 2;
                 const int rsel = 16 * (lane & 1) + 8 * ((lane >> 1) & 1) + 4 * ((lane >> 2) & 1) +
                                  2 * ((lane >> 3) & 1) + ((lane >> 4) & 1);
-                for (int tile = wave; tile < ntile; tile += kTrd / 64) {
+                for (int tile = wave; tile < ntile; tile += NT / 64) {
                     int I = 0;
                     while ((I + 1) * (I + 2) / 2 <= tile) ++I;
                     const int J = tile - I * (I + 1) / 2;
@@ -188,33 +190,42 @@ __global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ d
                     const uint32_t jc = (uint32_t)min(j, m - 1);
                     double colacc = 0.0;
                     double* pt = Pt + (int64_t)tile * 128;
-                    for (int c0 = 0; c0 < 64; c0 += 32) {
-                        double x[32];
+                    for (int c0 = 0; c0 < 64; c0 += CH) {
+                        double x[CH];
 #pragma unroll
-                        for (int q = 0; q < 32; ++q) {
+                        for (int q = 0; q < CH; ++q) {
                             const int i = I * 64 + c0 + q;
                             const double* row = col + (int64_t)min(i, m - 1) * ld;
                             const double xv = row[jc];
                             x[q] = (i < m && j < m && (I > J || i >= j)) ? xv : 0.0;
                         }
 #pragma unroll
-                        for (int q = 0; q < 32; ++q) {
+                        for (int q = 0; q < CH; ++q) {
                             const int i = I * 64 + c0 + q;
                             colacc += x[q] * (i < m ? v[i] : 0.0);
                             x[q] = (I > J || i > j) ? x[q] * vj : 0.0;
                         }
-                        fold_half<16>(x, lane & 1, 1);
-                        fold_half<8>(x, lane & 2, 2);
-                        fold_half<4>(x, lane & 4, 4);
-                        fold_half<2>(x, lane & 8, 8);
-                        fold_half<1>(x, lane & 16, 16);
-                        x[0] += __shfl_xor(x[0], 32, 64);
-                        if (lane < 32) pt[64 + c0 + rsel] = x[0];
+                        if (CH == 32) {
+                            fold_half<CH / 2>(x, lane & 1, 1);
+                            fold_half<CH / 4>(x, lane & 2, 2);
+                            fold_half<CH / 8>(x, lane & 4, 4);
+                            fold_half<CH / 16>(x, lane & 8, 8);
+                            fold_half<CH / 32>(x, lane & 16, 16);
+                            x[0] += __shfl_xor(x[0], 32, 64);
+                        } else {
+                            fold_half<CH / 2>(x, lane & 1, 1);
+                            fold_half<CH / 4>(x, lane & 2, 2);
+                            fold_half<CH / 8>(x, lane & 4, 4);
+                            fold_half<CH / 16>(x, lane & 8, 8);
+                            x[0] += __shfl_xor(x[0], 16, 64);
+                            x[0] += __shfl_xor(x[0], 32, 64);
+                        }
+                        if (lane < CH) pt[64 + c0 + (CH == 32 ? rsel : rsel >> 1)] = x[0];
                     }
                     pt[lane] = colacc;
                 }
                 __syncthreads();
-                for (int xr = threadIdx.x; xr < m; xr += kTrd) {
+                for (int xr = threadIdx.x; xr < m; xr += NT) {
                     const int B = xr >> 6, xl = xr & 63;
                     // the T + 1 slots of row block B (row sums of tiles (B, 0..B), then
                     // column sums of tiles (B..T-1, B)), 8 loads in flight, added in that order
@@ -235,7 +246,7 @@ __global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ d
                 }
             }
             // W^T v and V^T v over rows k+1.. (one wave per panel column)
-            for (int l = wave; l < 2 * j; l += kTrd / 64) {
+            for (int l = wave; l < 2 * j; l += NT / 64) {
                 const double* col = (l < j ? Wm + (int64_t)l * n : Vm + (int64_t)(l - j) * n) + (k + 1);
                 double acc = 0.0, acc2 = 0.0;
                 int i = lane;
@@ -251,7 +262,7 @@ __global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ d
             __syncthreads();
             // p -= V (W^T v) + W (V^T v); then w = t p - t^2/2 (p^T v) v
             part = 0.0;
-            for (int i = threadIdx.x; i < m; i += kTrd) {
+            for (int i = threadIdx.x; i < m; i += NT) {
                 const int r = k + 1 + i;
                 double x = p[i];
                 double vr[kPanel], wr[kPanel];
@@ -263,9 +274,9 @@ __global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ d
                 p[i] = x;
                 part += x * v[i];
             }
-            const double pv = block_sum_n(part, red, kTrd);
+            const double pv = block_sum_n(part, red, NT);
             const double half = 0.5 * t * pv;
-            for (int i = threadIdx.x; i < m; i += kTrd) {
+            for (int i = threadIdx.x; i < m; i += NT) {
                 const int r = k + 1 + i;
                 Vm[(int64_t)j * n + r] = v[i];
                 Wm[(int64_t)j * n + r] = p[i] - half * v[i];
@@ -281,14 +292,14 @@ __global__ void __launch_bounds__(kTrd, 2) k_sytrd(const SubDesc* __restrict__ d
         for (int rb = kend; rb < n; rb += 64) {
             const int rn = min(64, n - rb);
             __syncthreads();
-            for (int e = threadIdx.x; e < 64 * kPanel; e += kTrd) {     // zero beyond jb: no stale LDS
+            for (int e = threadIdx.x; e < 64 * kPanel; e += NT) {     // zero beyond jb: no stale LDS
                 const int rr = e & 63, l = e >> 6;
                 const bool in = rr < rn && l < jb;
                 sVr[rr][l] = in ? Vm[(int64_t)l * n + rb + rr] : 0.0;
                 sWr[rr][l] = in ? Wm[(int64_t)l * n + rb + rr] : 0.0;
             }
             __syncthreads();
-            for (int cs = kend + 64 * wave; cs < n; cs += 64 * (kTrd / 64)) {
+            for (int cs = kend + 64 * wave; cs < n; cs += 64 * (NT / 64)) {
                 const int c = cs + lane;
                 const bool cok = c < n;
                 double vc[kPanel], wc[kPanel];
@@ -1126,7 +1137,8 @@ int gdm_fp64_plan_lds(gdm_ctx* ctx) {
     const Fp64Lds L = fp64_lds(ctx->plan);
     int rc;
     if ((rc = set_lds(ctx, (const void*)k_potrf, kRowsLds))) return rc;
-    if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * L.n))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_sytrd<kTrd, 32>, 2 * L.n))) return rc;
+    if ((rc = set_lds(ctx, (const void*)k_sytrd<kTrdFew, 16>, 2 * L.n))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_house_t, kRowsLds))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_core_rows, kRowsLds))) return rc;
     if ((rc = set_lds(ctx, (const void*)k_mu_partial, 2 * L.n))) return rc;
@@ -1181,10 +1193,18 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     hipLaunchKernelGGL(k_symmetrize, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, A);
     }
     GDM_LAUNCH_CHECK(ctx);
-    if ((rc = set_lds(ctx, (const void*)k_sytrd, 2 * lds_n))) return rc;
+    // one workgroup per subgraph: 1024 threads when every subgraph has a CU
+    // of its own (otherwise CUs would idle), else 512
+    const bool few = ns <= ctx->n_cu;
+    const void* trd = few ? (const void*)k_sytrd<kTrdFew, 16> : (const void*)k_sytrd<kTrd, 32>;
+    if ((rc = set_lds(ctx, trd, 2 * lds_n))) return rc;
     { GDM_TIMED(ctx, "sytrd");
-    hipLaunchKernelGGL(k_sytrd, dim3(ns), dim3(kTrd), 2 * lds_n, ctx->stream, desc, order, A, T, Dg, Eg, Tau,
-                       (double*)ctx->b[BUF_TRDP].p);
+    if (few)
+        hipLaunchKernelGGL((k_sytrd<kTrdFew, 16>), dim3(ns), dim3(kTrdFew), 2 * lds_n, ctx->stream, desc, order, A, T,
+                           Dg, Eg, Tau, (double*)ctx->b[BUF_TRDP].p);
+    else
+        hipLaunchKernelGGL((k_sytrd<kTrd, 32>), dim3(ns), dim3(kTrd), 2 * lds_n, ctx->stream, desc, order, A, T, Dg,
+                           Eg, Tau, (double*)ctx->b[BUF_TRDP].p);
     }
     GDM_LAUNCH_CHECK(ctx);
     if ((rc = gdm_dc_solve(ctx))) return rc;

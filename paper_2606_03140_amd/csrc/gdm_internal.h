@@ -83,6 +83,7 @@ struct ProfRec {
 
 struct gdm_ctx {
     int device = 0;
+    int n_cu = 256;             // compute units of the device
     hipStream_t stream = nullptr;
     int* d_status = nullptr;
     std::string err;
