@@ -417,28 +417,8 @@ __global__ void k_ewald_recip(int n, int nk, const double* __restrict__ pos, con
     V[i] = (species[i] == 0 ? U0 : U1) * q[i] + ke * (V[i] + 2.0 * acc + self);
 }
 
-// The same reciprocal sum split over chunks of k-vectors so that the launch
-// has (atom blocks) x (k chunks) workgroups: part[y * n + i] = sum over the
-// k in chunk y of w(k) (cos(k.R_i) C + sin(k.R_i) S); k_ewald_finish adds the
-// chunks in order.
-__global__ void __launch_bounds__(128) k_ewald_recip_part(int n, int nk, int kchunk, const double* __restrict__ pos,
-                                                         const double4* __restrict__ kv,
-                                                         const double* __restrict__ CS, double* __restrict__ part) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int k0 = blockIdx.y * kchunk, k1 = min(nk, k0 + kchunk);
-    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
-    double acc = 0.0;
-    for (int k = k0; k < k1; ++k) {
-        const double4 kk = kv[k];
-        if (kk.w == 0.0) continue;          // uniform over the wave
-        double sn, cs;
-        sincos(kk.x * x + kk.y * y + kk.z * z, &sn, &cs);
-        acc += kk.w * (cs * CS[2 * k] + sn * CS[2 * k + 1]);
-    }
-    part[(int64_t)blockIdx.y * n + i] = acc;
-}
-
+// V_I from the real-space part already in V and the chunks of the
+// reciprocal sum (k_ewald_recip_lines), added in chunk order
 __global__ void k_ewald_finish(int n, int nchunk, const double* __restrict__ part,
                                const int32_t* __restrict__ species, const double* __restrict__ q, double eta,
                                double ke, double U0, double U1, double* __restrict__ V) {
@@ -448,6 +428,148 @@ __global__ void k_ewald_finish(int n, int nchunk, const double* __restrict__ par
     for (int y = 0; y < nchunk; ++y) acc += part[(int64_t)y * n + i];
     const double self = -2.0 * eta / sqrt(M_PI) * q[i];
     V[i] = (species[i] == 0 ? U0 : U1) * q[i] + ke * (V[i] + 2.0 * acc + self);
+}
+
+// Structure factors and reciprocal sums over lines of the full k grid
+// (k_ewald_ktable order: line (a, b) holds c = -K..K, consecutive kz apart by
+// dkz = 2 pi / Lz).  Along a line the phase advances by the same factor
+// e^{i dkz z}, so e^{i k.R} of the next point is one complex product away:
+// one sincos per atom for a line's (or block's) first point and one for the
+// step, instead of one per point.  Points of weight 0 (outside the sphere or
+// the half space) contribute nothing.
+
+// a line is non-empty iff its c = 0 point is inside (that point has the
+// smallest |k| of the line), or it is the line a = b = 0 (c > 0 only)
+__device__ __forceinline__ bool line_live(const double4* __restrict__ kv, int line, int K) {
+    const int w = 2 * K + 1;
+    return kv[line * w + K].w != 0.0 || line == K;
+}
+
+// C(k), S(k) for kSkC consecutive points of one line per workgroup
+constexpr int kSkC = 8;
+__global__ void __launch_bounds__(256) k_ewald_sk_lines(int n, int K, const double* __restrict__ pos,
+                                                       const double* __restrict__ q, const double4* __restrict__ kv,
+                                                       double dkz, double* __restrict__ CS) {
+    __shared__ double red[4][2 * kSkC];
+    const int w = 2 * K + 1, nb = (w + kSkC - 1) / kSkC;
+    const int line = blockIdx.x / nb, g0 = line * w + (blockIdx.x % nb) * kSkC;
+    const int cnt = min(kSkC, line * w + w - g0);
+    bool any = false;
+    for (int t = 0; t < cnt; ++t) any = any || kv[g0 + t].w != 0.0;
+    if (!any) {
+        if (threadIdx.x < 2 * cnt) CS[2 * (int64_t)g0 + threadIdx.x] = 0.0;
+        return;
+    }
+    const double4 k0 = kv[g0];
+    double ac[kSkC], as[kSkC];
+#pragma unroll
+    for (int t = 0; t < kSkC; ++t) ac[t] = as[t] = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const double x = pos[3 * j], y = pos[3 * j + 1], z = pos[3 * j + 2], qj = q[j];
+        double sn, cs, sd, cd;
+        sincos(k0.x * x + k0.y * y + k0.z * z, &sn, &cs);
+        sincos(dkz * z, &sd, &cd);
+#pragma unroll
+        for (int t = 0; t < kSkC; ++t) {
+            ac[t] += qj * cs;
+            as[t] += qj * sn;
+            const double c2 = cs * cd - sn * sd;
+            sn = sn * cd + cs * sd;
+            cs = c2;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < kSkC; ++t) {
+        const double c = gdm_wave_sum(ac[t]), sv = gdm_wave_sum(as[t]);
+        if (lane == 0) {
+            red[wave][2 * t] = c;
+            red[wave][2 * t + 1] = sv;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * cnt) {
+        const int t = threadIdx.x >> 1;
+        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        CS[2 * (int64_t)g0 + threadIdx.x] = kv[g0 + t].w != 0.0 ? v : 0.0;
+    }
+}
+
+// part[y * n + i] = sum over the lines of chunk y of w(k) (cos(k.R_i) C + sin(k.R_i) S)
+__global__ void __launch_bounds__(128) k_ewald_recip_lines(int n, int K, int lines_per_chunk,
+                                                          const double* __restrict__ pos,
+                                                          const double4* __restrict__ kv,
+                                                          const double* __restrict__ CS, double dkz,
+                                                          double* __restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int w = 2 * K + 1, nlines = (K + 1) * w;
+    const int l0 = blockIdx.y * lines_per_chunk, l1 = min(nlines, l0 + lines_per_chunk);
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    double sd, cd;
+    sincos(dkz * z, &sd, &cd);
+    double acc = 0.0;
+    for (int line = l0; line < l1; ++line) {
+        if (!line_live(kv, line, K)) continue;          // uniform over the wave
+        const int g0 = line * w;
+        const double4 k0 = kv[g0];
+        double sn, cs;
+        sincos(k0.x * x + k0.y * y + k0.z * z, &sn, &cs);
+        for (int c = 0; c < w; ++c) {
+            const double wk = kv[g0 + c].w;
+            acc += wk * (cs * CS[2 * (int64_t)(g0 + c)] + sn * CS[2 * (int64_t)(g0 + c) + 1]);
+            const double c2 = cs * cd - sn * sd;
+            sn = sn * cd + cs * sd;
+            cs = c2;
+        }
+    }
+    part[(int64_t)blockIdx.y * n + i] = acc;
+}
+
+// the force's reciprocal part over the lines of chunk blockIdx.y:
+// part[(y * n + i) * 3 + x] = sum_k w_k k_x [a_i (S_b cos - C_b sin) + b_i (S_a cos - C_a sin)]
+__global__ void __launch_bounds__(128) k_ewald_force_recip_lines(int n, int K, int lines_per_chunk,
+                                                                const double* __restrict__ pos,
+                                                                const double* __restrict__ qa,
+                                                                const double* __restrict__ qb,
+                                                                const double4* __restrict__ kv,
+                                                                const double* __restrict__ CSa,
+                                                                const double* __restrict__ CSb, double dkz,
+                                                                double* __restrict__ part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int w = 2 * K + 1, nlines = (K + 1) * w;
+    const int l0 = blockIdx.y * lines_per_chunk, l1 = min(nlines, l0 + lines_per_chunk);
+    const double ai = qa[i], bi = qb[i];
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    double sd, cd;
+    sincos(dkz * z, &sd, &cd);
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int line = l0; line < l1; ++line) {
+        if (!line_live(kv, line, K)) continue;
+        const int g0 = line * w;
+        const double4 k0 = kv[g0];
+        double sn, cs;
+        sincos(k0.x * x + k0.y * y + k0.z * z, &sn, &cs);
+        double tx = 0.0, tz = 0.0;       // sum of t and of t kz over the line
+        for (int c = 0; c < w; ++c) {
+            const double4 kk = kv[g0 + c];
+            const int64_t e = 2 * (int64_t)(g0 + c);
+            const double t = kk.w * (ai * (CSb[e + 1] * cs - CSb[e] * sn) + bi * (CSa[e + 1] * cs - CSa[e] * sn));
+            tx += t;
+            tz += t * kk.z;
+            const double c2 = cs * cd - sn * sd;
+            sn = sn * cd + cs * sd;
+            cs = c2;
+        }
+        gx += tx * k0.x;
+        gy += tx * k0.y;
+        gz += tz;
+    }
+    double* o = part + ((int64_t)blockIdx.y * n + i) * 3;
+    o[0] = gx;
+    o[1] = gy;
+    o[2] = gz;
 }
 
 // k-vector table over the full grid a = 0..K, b, c = -K..K (index
@@ -813,39 +935,6 @@ __global__ void k_ewald_force_real(int n, const double* __restrict__ pos, const 
     F[3 * i + 2] += ke * fz;
 }
 
-// reciprocal part over chunk blockIdx.y of the k-vectors (atom blocks x k
-// chunks workgroups): part[(y * n + i) * 3 + x] = sum_k w_k k_x [...]
-__global__ void __launch_bounds__(128) k_ewald_force_recip_part(int n, int nk, int kchunk,
-                                                               const double* __restrict__ pos,
-                                                               const double* __restrict__ qa,
-                                                               const double* __restrict__ qb,
-                                                               const double4* __restrict__ kv,
-                                                               const double* __restrict__ CSa,
-                                                               const double* __restrict__ CSb,
-                                                               double* __restrict__ part) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int k0 = blockIdx.y * kchunk, k1 = min(nk, k0 + kchunk);
-    const double ai = qa[i], bi = qb[i];
-    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int k = k0; k < k1; ++k) {
-        const double4 kk = kv[k];
-        if (kk.w == 0.0) continue;          // uniform over the wave
-        double sn, cs;
-        sincos(kk.x * x + kk.y * y + kk.z * z, &sn, &cs);
-        const double t =
-            kk.w * (ai * (CSb[2 * k + 1] * cs - CSb[2 * k] * sn) + bi * (CSa[2 * k + 1] * cs - CSa[2 * k] * sn));
-        gx += t * kk.x;
-        gy += t * kk.y;
-        gz += t * kk.z;
-    }
-    double* o = part + ((int64_t)blockIdx.y * n + i) * 3;
-    o[0] = gx;
-    o[1] = gy;
-    o[2] = gz;
-}
-
 __global__ void k_ewald_force_finish(int n, int nchunk, const double* __restrict__ part, double ke,
                                      double* __restrict__ F) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -967,13 +1056,14 @@ extern "C" int gdm_adam_step(gdm_ctx* ctx, int32_t n, float* params, const float
 
 // k chunks of the reciprocal sums: enough (atom blocks) x (chunks)
 // workgroups to fill the chip, at least 64 k-vectors per chunk
-static void ewald_chunks(int n, int nk, int* nchunk, int* kchunk) {
-    nk = std::max(nk, 1);
+// chunks of whole k-grid lines for the (atom blocks) x (chunks) launches:
+// enough workgroups to fill the device, at least 2 lines per chunk
+static void ewald_line_chunks(int n, int nlines, int* nchunk, int* lines_per_chunk) {
     const int ablocks = (n + 127) / 128;
     int c = std::max(1, 4096 / ablocks);
-    c = std::min(c, std::max(1, nk / 64));
-    *kchunk = (nk + c - 1) / c;
-    *nchunk = (nk + *kchunk - 1) / *kchunk;
+    c = std::min(c, std::max(1, nlines / 2));
+    *lines_per_chunk = (nlines + c - 1) / c;
+    *nchunk = (nlines + *lines_per_chunk - 1) / *lines_per_chunk;
 }
 
 static int check_ewald(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr, const int32_t* col, double rcut,
@@ -995,48 +1085,40 @@ extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const in
     if (!ctx) return GDM_E_ARG;
     int rc = check_ewald(ctx, sys, row_ptr, col, rcut, eta, k_max, 64, hubbard_U, tau, q, V, "gdm_ewald_potential");
     if (rc) return rc;
-    // half space of k = 2 pi (a/Lx, b/Ly, c/Lz): (a > 0) or (a = 0, b > 0) or (a = b = 0, c > 0)
+    // the full k grid a = 0..K, b, c = -K..K on the device (weight 0 outside
+    // the half space (a > 0) or (a = 0, b > 0) or (a = b = 0, c > 0) and the
+    // sphere |k| <= 2 pi K / max L), summed line by line
     const double V3 = sys->box[0] * sys->box[1] * sys->box[2];
     const double kc2 = std::pow(2.0 * M_PI * k_max / std::max(sys->box[0], std::max(sys->box[1], sys->box[2])), 2);
-    std::vector<double4> kv;
-    for (int a = 0; a <= k_max; ++a)
-        for (int b = -k_max; b <= k_max; ++b)
-            for (int c = -k_max; c <= k_max; ++c) {
-                if (a == 0 && (b < 0 || (b == 0 && c <= 0))) continue;
-                const double kx = 2 * M_PI * a / sys->box[0], ky = 2 * M_PI * b / sys->box[1],
-                             kz = 2 * M_PI * c / sys->box[2];
-                const double k2 = kx * kx + ky * ky + kz * kz;
-                if (k2 > kc2) continue;
-                const double w = 4.0 * M_PI / V3 * std::exp(-k2 / (4.0 * eta * eta)) / k2;
-                kv.push_back(make_double4(kx, ky, kz, w));
-            }
-    const int nk = (int)kv.size();
+    const int w = 2 * k_max + 1, nk = (k_max + 1) * w * w, nlines = (k_max + 1) * w;
     const int n = sys->n_atoms;
-    int nchunk = 1, kchunk = 1;
-    ewald_chunks(n, nk, &nchunk, &kchunk);
+    int nchunk = 1, lpc = 1;
+    ewald_line_chunks(n, nlines, &nchunk, &lpc);
     bool ok = true;
     double4* dkv = (double4*)gdm_buf(
         ctx, BUF_EWALD, sizeof(double4) * nk + sizeof(double) * (2 * (size_t)nk + (size_t)nchunk * n), &ok);
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_ewald_potential: workspace allocation failed");
     double* CS = (double*)(dkv + nk);
     double* part = CS + 2 * (int64_t)nk;
-    GDM_HIP(ctx, hipMemcpyAsync(dkv, kv.data(), sizeof(double4) * nk, hipMemcpyHostToDevice, ctx->stream));
     const double3 L = make_double3(sys->box[0], sys->box[1], sys->box[2]);
     const double3 iL = make_double3(sys->inv_box[0], sys->inv_box[1], sys->inv_box[2]);
+    const double dkz = 2.0 * M_PI / sys->box[2];
     GDM_TIMED(ctx, "ewald");
+    hipLaunchKernelGGL(k_ewald_ktable, dim3((nk + 255) / 256), dim3(256), 0, ctx->stream, k_max, sys->box[0],
+                       sys->box[1], sys->box[2], eta, kc2, V3, dkv);
+    GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos, sys->species, L,
                        iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0, tau ? tau[1] : 0.0, q, V);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, q, dkv, CS);
+    hipLaunchKernelGGL(k_ewald_sk_lines, dim3(nlines * ((w + kSkC - 1) / kSkC)), dim3(256), 0, ctx->stream, n, k_max,
+                       sys->pos, q, dkv, dkz, CS);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_recip_part, dim3((n + 127) / 128, nchunk), dim3(128), 0, ctx->stream, n, nk, kchunk,
-                       sys->pos, dkv, CS, part);
+    hipLaunchKernelGGL(k_ewald_recip_lines, dim3((n + 127) / 128, nchunk), dim3(128), 0, ctx->stream, n, k_max, lpc,
+                       sys->pos, dkv, CS, dkz, part);
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_finish, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nchunk, part, sys->species,
                        q, eta, 14.399645, hubbard_U[0], hubbard_U[1], V);
     GDM_LAUNCH_CHECK(ctx);
-    // keep the staging vector alive until the copy has been consumed
-    GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return GDM_OK;
 }
 
@@ -1115,13 +1197,15 @@ extern "C" int gdm_ewald_forces(gdm_ctx* ctx, const gdm_system* sys, const int32
     if (rc) return rc;
     if (!n_vec) return gdm_fail(ctx, GDM_E_ARG, "gdm_ewald_forces: null charge vector n_vec");
     const int w = 2 * k_max + 1;
-    const int nk = (k_max + 1) * w * w;
-    int nchunk = 1, kchunk = 1;
-    ewald_chunks(sys->n_atoms, nk, &nchunk, &kchunk);
+    const int nk = (k_max + 1) * w * w, nlines = (k_max + 1) * w;
+    int nchunk = 1, lpc = 1;
+    ewald_line_chunks(sys->n_atoms, nlines, &nchunk, &lpc);
     bool ok = true;
     double* ws = (double*)gdm_buf(
         ctx, BUF_EWALD, sizeof(double) * (8 * (size_t)nk + sys->n_atoms + 3 * (size_t)nchunk * sys->n_atoms), &ok);
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_ewald_forces: workspace allocation failed");
+    const double dkz = 2.0 * M_PI / sys->box[2];
+    const int skb = nlines * ((w + kSkC - 1) / kSkC);
     double4* dkv = (double4*)ws;
     double* CSa = ws + 4 * (int64_t)nk;
     double* CSb = CSa + 2 * (int64_t)nk;
@@ -1139,16 +1223,16 @@ extern "C" int gdm_ewald_forces(gdm_ctx* ctx, const gdm_system* sys, const int32
     hipLaunchKernelGGL(k_ewald_ktable, dim3((nk + 255) / 256), dim3(256), 0, ctx->stream, k_max, sys->box[0],
                        sys->box[1], sys->box[2], eta, kc2, V3, dkv);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, a, dkv, CSa);
+    hipLaunchKernelGGL(k_ewald_sk_lines, dim3(skb), dim3(256), 0, ctx->stream, n, k_max, sys->pos, a, dkv, dkz, CSa);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, b, dkv, CSb);
+    hipLaunchKernelGGL(k_ewald_sk_lines, dim3(skb), dim3(256), 0, ctx->stream, n, k_max, sys->pos, b, dkv, dkz, CSb);
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_force_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos,
                        sys->species, L, iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0,
                        tau ? tau[1] : 0.0, a, b, 14.399645, F);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_force_recip_part, dim3((n + 127) / 128, nchunk), dim3(128), 0, ctx->stream, n, nk,
-                       kchunk, sys->pos, a, b, dkv, CSa, CSb, part);
+    hipLaunchKernelGGL(k_ewald_force_recip_lines, dim3((n + 127) / 128, nchunk), dim3(128), 0, ctx->stream, n, k_max,
+                       lpc, sys->pos, a, b, dkv, CSa, CSb, dkz, part);
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_force_finish, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, nchunk, part,
                        14.399645, F);
