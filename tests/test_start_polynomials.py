@@ -15,6 +15,8 @@ kernel source, so a change there is checked here).
   with alternating signs at four points.
 * Inverse square root start: z0(x) = c0 + c1 x has |1 - x z0(x)^2| <= 0.417
   on [0.1, 1], the range of s / c.
+* Last doubling's inverse: the same split start and steps, then FP64
+  Newton-Schulz steps, each squaring the residual I - A Y exactly for any Y.
 """
 import os
 import re
@@ -83,18 +85,41 @@ def test_inverse_sqrt_start_bound():
 
 
 def test_final_doubling_inverse_start():
-    # the FP64 last doubling: y0(a) = 4 - 5a + 2a^2 (GEMM epilogue 2 A^2 - 5 A + 4 I)
-    assert "gemm64_dd(ctx, A, A, A, Ya, 2.0, -5.0, 4.0" in SRC
+    # the last doubling's inverse starts on the split products like the others
+    # (the quadratic start y0 = (420 - 576 a + 256 a^2) / 99 and the split
+    # Newton-Schulz steps), then FP64 steps: one for FP16 pairs, two for BF16
+    body = SRC[SRC.index("static int last_doubling_f64"):SRC.index("// FP64 core traces of the last pass")]
+    assert "256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f" in body
+    assert "final_ns = P.precision == GDM_MIXED_BF16 ? 2 : 1" in body
+    assert "ctx->mixed_ns_inv" in body
+    # a Newton-Schulz step Y' = Y (2I - A Y) maps the residual I - A Y to its
+    # square exactly for any Y (no commutation assumed): check it on random
+    # non-symmetric matrices in exact rational arithmetic
+    from fractions import Fraction
+    rng = np.random.default_rng(3)
+    n = 4
+    A = [[Fraction(int(x), 7) for x in row] for row in rng.integers(-9, 10, (n, n))]
+    Y = [[Fraction(int(x), 5) for x in row] for row in rng.integers(-9, 10, (n, n))]
+
+    def mul(X, Z):
+        return [[sum(X[i][k] * Z[k][j] for k in range(n)) for j in range(n)] for i in range(n)]
+
+    def sub(X, Z):
+        return [[X[i][j] - Z[i][j] for j in range(n)] for i in range(n)]
+
+    I2 = [[Fraction(2 if i == j else 0) for j in range(n)] for i in range(n)]
+    I1 = [[Fraction(1 if i == j else 0) for j in range(n)] for i in range(n)]
+    R = sub(I1, mul(A, Y))
+    Yn = mul(Y, sub(I2, mul(A, Y)))
+    assert sub(I1, mul(A, Yn)) == mul(R, R)
+    # the split start and two split steps leave |1 - a y| <= 99^-4 in exact
+    # arithmetic, below the split products' rounding (FP16 pairs ~1e-7 relative,
+    # BF16 pairs ~1e-5); one FP64 step squares 2e-7 to 4e-14, two square 2e-5
+    # to 1.6e-19: both below the 3.6e-12 of three FP64 steps from 4 - 5a + 2a^2
     a = np.linspace(0.5, 1.0, 200001)
-    r = 1.0 - a * (4.0 - 5.0 * a + 2.0 * a * a)
-    # residual (1 - a)^2 (1 - 2a): zero at a = 1/2 and to second order at a = 1
-    # (the occupied and empty states), at most 1/27 (at a = 2/3) in between
-    assert np.allclose(r, (1.0 - a) ** 2 * (1.0 - 2.0 * a), atol=1e-15)
-    assert abs(np.abs(r).max() - 1.0 / 27.0) < 1e-9
-    assert "constexpr int kFinalNs = 3;" in SRC
-    assert (np.abs(r) ** 8).max() <= 27.0 ** -8 + 1e-30 and 27.0 ** -8 < 4e-12
-    # two Newton-Schulz steps would square the residual twice: <= 27^-4 everywhere,
-    # and a state 1e-4 from a = 1 is left with about (1e-8)^4, far below FP64 rounding
-    assert (np.abs(r) ** 4).max() <= 27.0 ** -4 + 1e-18
-    e = 1e-4
-    assert abs((e * e * (1 - 2 * (1 - e))) ** 4) < 1e-31
+    r = 1.0 - a * (420.0 - 576.0 * a + 256.0 * a * a) / 99.0
+    assert np.abs(r).max() <= 1.0 / 99.0 + 1e-15
+    assert (np.abs(r) ** 4).max() <= 99.0 ** -4 + 1e-20 and 99.0 ** -4 < 1.1e-8
+    assert (2e-7) ** 2 < 3.6e-12 and ((2e-5) ** 2) ** 2 < 3.6e-12
+    r_old = 1.0 - a * (4.0 - 5.0 * a + 2.0 * a * a)
+    assert abs((np.abs(r_old) ** 8).max() - 27.0 ** -8) < 1e-20 and 27.0 ** -8 > 3.5e-12
