@@ -30,6 +30,7 @@ from .pipeline import Partition, subgraph_cost
 
 MASS = (15.999, 1.008)             # amu, O and H
 KAPPA, ALPHA = 1.82, 0.018         # Niklasson et al. 2009, K = 5
+EWALD_SKIN = 1.0                   # A, skin of the Ewald real-space pair list
 # tapered radial functions and a repulsive pair term for the synthetic model:
 # an isolated water has zero SCC force at r_OH = 0.96 A, 104.5 degrees
 MD_TB = dict(taper_on=3.5, rep_A=(500.0, 67.92, 12.79), rep_rho=0.3)
@@ -118,6 +119,7 @@ class XLBOMD:
         self.rebuild = max(1, int(rebuild))      # halos redrawn every `rebuild` steps
         self.steps_done = 0
         self._ew: EwaldSetup | None = None
+        self._ew_pos: np.ndarray | None = None
         self.timing = {} if timing else None
         self.tau_s = slater_tau(HUBBARD_U) if screened else None
         self.ewald_tol = ewald_tol
@@ -143,11 +145,17 @@ class XLBOMD:
 
     # ------------------------------------------------------------ pieces
     def _ewald(self) -> EwaldSetup:
-        """Ewald split and real-space pair list; the list is built with a
-        1 A skin and kept for `rebuild` steps (the kernels skip pairs at
-        r >= rcut, so it stays valid while no atom moves 0.5 A)."""
-        if self._ew is None or self.steps_done % self.rebuild == 0:
-            self._ew = ewald_setup(self.ctx, self.system, tol=self.ewald_tol, skin=1.0)
+        """Ewald split and real-space pair list, built with a 1 A skin and
+        rebuilt once some atom has moved more than half the skin since the
+        list was built (the kernels skip pairs at r >= rcut, so until then
+        the list holds every pair within rcut)."""
+        pos = self.system.pos.cpu().numpy()
+        if self._ew is not None:
+            moved = float(np.sqrt(((pos - self._ew_pos) ** 2).sum(axis=1).max()))
+            if moved <= 0.5 * EWALD_SKIN:
+                return self._ew
+        self._ew = ewald_setup(self.ctx, self.system, tol=self.ewald_tol, skin=EWALD_SKIN)
+        self._ew_pos = pos
         return self._ew
 
     def _partition(self, prev: Point | None) -> Partition:
