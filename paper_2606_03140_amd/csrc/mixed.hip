@@ -17,7 +17,10 @@
 //               Y = A^-1 by Newton-Schulz from the minimax quadratic start
 //               Y0 = (420 I - 576 A + 256 A^2) / 99 (|I - A Y0| <= 1/99 on
 //               [1/2, 1]), then ns_inv iterations,
-//               X <- X2 Y            (f_b -> f_2b),
+//               X <- X2 Y            (f_b -> f_2b);
+//   the last of them with X2, A and X2 Y in FP64 on the FP64 matrix cores,
+//       its inverse started on the split products as above and finished by
+//       one FP64 Newton-Schulz step (two for BF16 pairs),
 //   N(mu) = 2 sum_core (Z X Z s)_aa,  N'(mu) = 2 beta sum_core (Z (X - X^2) Z s)_aa
 //   in FP64, Newton steps on mu with a bisection bracket, and the final
 //   collected core rows D = Z[core,:] (X + dmu beta (X - X^2)) Z in FP64.
