@@ -26,23 +26,10 @@ constexpr int kThreads = 256;   // threads per workgroup for the per-subgraph ke
 // subgraph handled by this workgroup (longest first)
 __device__ __forceinline__ int sub_of_block(const int32_t* __restrict__ order) { return order[blockIdx.x]; }
 
-// A <- (A + A^T)/2 (exact symmetry for the reduction)
-__global__ void __launch_bounds__(kThreads) k_symmetrize(const SubDesc* __restrict__ desc,
-                                                  const int32_t* __restrict__ order, double* __restrict__ A) {
-    const SubDesc d = desc[sub_of_block(order)];
-    const int n = d.n, ld = d.ld;
-    double* a = A + d.off2;
-    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kThreads) {
-        int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-        if (j <= i) continue;
-        double v = 0.5 * (a[(int64_t)i * ld + j] + a[(int64_t)j * ld + i]);
-        a[(int64_t)i * ld + j] = v;
-        a[(int64_t)j * ld + i] = v;
-    }
-}
-
 // ------------------------------------------------ Householder tridiagonal
-// Reduction on full symmetric storage, blocked in panels of nb columns (the
+// Reduction on full storage of L^-1 h L^-T as the triangular solves leave it
+// (both triangles, equal to rounding: the products read the lower triangle,
+// each column x is read from its row), blocked in panels of nb columns (the
 // delayed-update form of the Householder tridiagonalisation): step k reflects
 // x = A[k+1:, k] onto beta e_1 with H = I - tau v v^T, v_0 = 1, where within a
 // panel A is kept as it was at the panel's start and the updates of the
@@ -1187,10 +1174,6 @@ int gdm_fp64_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* s
     GDM_LAUNCH_CHECK(ctx);
     { GDM_TIMED(ctx, "trsm");
     hipLaunchKernelGGL(k_trsm<1>, tgrid, dim3(256), kRowsLds, ctx->stream, desc, order, Sd, Linv, A, T);
-    }
-    GDM_LAUNCH_CHECK(ctx);
-    { GDM_TIMED(ctx, "symmetrize");
-    hipLaunchKernelGGL(k_symmetrize, dim3(ns), dim3(kThreads), 0, ctx->stream, desc, order, A);
     }
     GDM_LAUNCH_CHECK(ctx);
     // one workgroup per subgraph: 1024 threads when every subgraph has a CU
