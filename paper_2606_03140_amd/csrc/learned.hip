@@ -337,16 +337,21 @@ __device__ double slater_short(double ta, double tb, double R) {
 }
 
 // real space over the cutoff CSR (r < rc): sum_J q_J (erfc(eta r)/r - S(tau_I, tau_J, r)),
-// the screening term only when screened != 0
-__global__ void k_ewald_real(int n, const double* __restrict__ pos, const int32_t* __restrict__ species, double3 L,
-                             double3 iL, const int32_t* __restrict__ rp, const int32_t* __restrict__ cl, double rc,
-                             double eta, int screened, double tau0, double tau1, const double* __restrict__ q,
-                             double* __restrict__ V) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// the screening term only when screened != 0.  One wave per atom: the lanes
+// take every 64th pair of its row (rows hold hundreds of pairs at 12 A), then
+// a wave sum, so a launch has as many waves as atoms.
+constexpr int kRealAtoms = 4;      // atoms (waves) per workgroup
+__global__ void __launch_bounds__(64 * kRealAtoms) k_ewald_real(int n, const double* __restrict__ pos,
+                                                                const int32_t* __restrict__ species, double3 L,
+                                                                double3 iL, const int32_t* __restrict__ rp,
+                                                                const int32_t* __restrict__ cl, double rc, double eta,
+                                                                int screened, double tau0, double tau1,
+                                                                const double* __restrict__ q, double* __restrict__ V) {
+    const int i = blockIdx.x * kRealAtoms + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= n) return;                 // uniform over the wave
     const double ti = species[i] == 0 ? tau0 : tau1;
     double acc = 0.0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += 64) {
         const int j = cl[k];
         double dx, dy, dz;
         min_image(pos, i, j, L, iL, &dx, &dy, &dz);
@@ -356,7 +361,8 @@ __global__ void k_ewald_real(int n, const double* __restrict__ pos, const int32_
         if (screened) g -= slater_short(ti, species[j] == 0 ? tau0 : tau1, r);
         acc += q[j] * g;
     }
-    V[i] = acc;
+    acc = gdm_wave_sum(acc);
+    if (lane == 0) V[i] = acc;
 }
 
 // structure factors over the half space of k-vectors: C(k) = sum q cos(k.R), S(k) = sum q sin(k.R)
@@ -906,18 +912,17 @@ __device__ double slater_short_deriv(double ta, double tb, double R) {
 //   reciprocal space over the half space of k (weights w_k = 4 pi/V exp(-k^2/4eta^2)/k^2):
 //     -k_e sum_k w_k k [a_K (S_b cos - C_b sin) + b_K (S_a cos - C_a sin)](k . R_K)
 //   with (C_x, S_x)(k) = sum_J x_J (cos, sin)(k . R_J) (the k and -k terms are equal).
-__global__ void k_ewald_force_real(int n, const double* __restrict__ pos, const int32_t* __restrict__ species,
-                                   double3 L, double3 iL, const int32_t* __restrict__ rp,
-                                   const int32_t* __restrict__ cl, double rc, double eta, int screened, double tau0,
-                                   double tau1, const double* __restrict__ qa, const double* __restrict__ qb,
-                                   double ke, double* __restrict__ F) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ void __launch_bounds__(64 * kRealAtoms) k_ewald_force_real(
+    int n, const double* __restrict__ pos, const int32_t* __restrict__ species, double3 L, double3 iL,
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ cl, double rc, double eta, int screened, double tau0,
+    double tau1, const double* __restrict__ qa, const double* __restrict__ qb, double ke, double* __restrict__ F) {
+    const int i = blockIdx.x * kRealAtoms + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= n) return;                 // uniform over the wave
     const double ti = species[i] == 0 ? tau0 : tau1;
     const double ai = qa[i], bi = qb[i];
     const double c2 = 2.0 / sqrt(M_PI);
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += 64) {
         const int j = cl[k];
         double dx, dy, dz;
         min_image(pos, i, j, L, iL, &dx, &dy, &dz);
@@ -930,9 +935,14 @@ __global__ void k_ewald_force_real(int n, const double* __restrict__ pos, const 
         fy += w * dy;
         fz += w * dz;
     }
-    F[3 * i] += ke * fx;
-    F[3 * i + 1] += ke * fy;
-    F[3 * i + 2] += ke * fz;
+    fx = gdm_wave_sum(fx);
+    fy = gdm_wave_sum(fy);
+    fz = gdm_wave_sum(fz);
+    if (lane == 0) {
+        F[3 * i] += ke * fx;
+        F[3 * i + 1] += ke * fy;
+        F[3 * i + 2] += ke * fz;
+    }
 }
 
 __global__ void k_ewald_force_finish(int n, int nchunk, const double* __restrict__ part, double ke,
@@ -1107,8 +1117,9 @@ extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const in
     hipLaunchKernelGGL(k_ewald_ktable, dim3((nk + 255) / 256), dim3(256), 0, ctx->stream, k_max, sys->box[0],
                        sys->box[1], sys->box[2], eta, kc2, V3, dkv);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos, sys->species, L,
-                       iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0, tau ? tau[1] : 0.0, q, V);
+    hipLaunchKernelGGL(k_ewald_real, dim3((n + kRealAtoms - 1) / kRealAtoms), dim3(64 * kRealAtoms), 0, ctx->stream,
+                       n, sys->pos, sys->species, L, iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0,
+                       tau ? tau[1] : 0.0, q, V);
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_sk_lines, dim3(nlines * ((w + kSkC - 1) / kSkC)), dim3(256), 0, ctx->stream, n, k_max,
                        sys->pos, q, dkv, dkz, CS);
@@ -1177,8 +1188,9 @@ extern "C" int gdm_ewald_potential_noalloc(gdm_ctx* ctx, const gdm_system* sys, 
     hipLaunchKernelGGL(k_ewald_ktable, dim3((nk + 255) / 256), dim3(256), 0, ctx->stream, k_max, sys->box[0],
                        sys->box[1], sys->box[2], eta, kc2, V3, dkv);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos, sys->species, L,
-                       iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0, tau ? tau[1] : 0.0, q, V);
+    hipLaunchKernelGGL(k_ewald_real, dim3((n + kRealAtoms - 1) / kRealAtoms), dim3(64 * kRealAtoms), 0, ctx->stream,
+                       n, sys->pos, sys->species, L, iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0,
+                       tau ? tau[1] : 0.0, q, V);
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_sk, dim3(nk), dim3(256), 0, ctx->stream, n, sys->pos, q, dkv, CS);
     GDM_LAUNCH_CHECK(ctx);
@@ -1227,9 +1239,9 @@ extern "C" int gdm_ewald_forces(gdm_ctx* ctx, const gdm_system* sys, const int32
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_sk_lines, dim3(skb), dim3(256), 0, ctx->stream, n, k_max, sys->pos, b, dkv, dkz, CSb);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_force_real, dim3((n + 127) / 128), dim3(128), 0, ctx->stream, n, sys->pos,
-                       sys->species, L, iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0,
-                       tau ? tau[1] : 0.0, a, b, 14.399645, F);
+    hipLaunchKernelGGL(k_ewald_force_real, dim3((n + kRealAtoms - 1) / kRealAtoms), dim3(64 * kRealAtoms), 0,
+                       ctx->stream, n, sys->pos, sys->species, L, iL, row_ptr, col, rcut, eta, tau ? 1 : 0,
+                       tau ? tau[0] : 0.0, tau ? tau[1] : 0.0, a, b, 14.399645, F);
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_force_recip_lines, dim3((n + 127) / 128, nchunk), dim3(128), 0, ctx->stream, n, k_max,
                        lpc, sys->pos, a, b, dkv, CSa, CSb, dkz, part);
