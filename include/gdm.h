@@ -485,7 +485,10 @@ int gdm_debug_slot(gdm_ctx* ctx, int which, int sub, float* out);
  * eta > 0, 1 <= k_max <= 64; hubbard_U HOST [2] eV.  q, V: [n_atoms] FP64.
  * Accuracy is the caller's choice of (rcut, eta, k_max): erfc(eta rcut),
  * exp(-(pi k_max / (eta L))^2) and S(rcut) bound the truncation.
- * Synchronises the stream. */
+ * Enqueues kernels only (no host synchronisation): the k-vector table is
+ * built on the device over the full grid a = 0..k_max, b, c = -k_max..k_max
+ * with zero weight outside the half space and the sphere, in context
+ * workspace (grown on the first call for a larger k_max or atom count). */
 int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const int32_t* row_ptr,
                         const int32_t* col, double rcut, double eta, int32_t k_max,
                         const double hubbard_U[2], const double* tau, const double* q, double* V);
