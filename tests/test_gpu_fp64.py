@@ -142,6 +142,37 @@ def test_fp64_solve_cutoff_partition(c, nw, seed, grid, orth):
         assert np.abs(e - so.lam).max() < 1e-10
 
 
+def test_fp64_many_small_subgraphs(c):
+    """More subgraphs than compute units (the 512-thread form of the
+    tridiagonalisation) and small, ragged sizes: 600 waters, 9x9x9 cores."""
+    from paper_2606_03140_amd import pipeline
+    box = waterbox.water_box(600, 7)
+    sysm = system_of(box)
+    L = box.box[0]
+    grid = (9, 9, 9)
+    tb = tb_params(False)
+    part = pipeline.cutoff_partition(c, sysm, tb, grid)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    log(f"fp64 solve 600 waters grid {grid}: {part.sg.n_sub} subgraphs of {part.sg.norb.min()}-"
+        f"{part.sg.norb.max()} orbitals, {n_cu} CUs")
+    assert part.sg.n_sub > n_cu
+    H, S = c.build_hs(sysm, tb, part.nbr)
+    sol = pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.FP64_EIG, eig=True)
+    subs = _oracle_partition(box, grid, L)
+    ref = osv.solve_system(box.pos, box.species, L, oracle_model(False), subs)
+    assert abs(sol.n_count - sysm.n_electrons) < 1e-9
+    gd = unpack_dcore(part.sg, sol.D_core)
+    err_d = max(np.abs(a - b).max() for a, b in zip(gd, ref.d_core))
+    err_q = np.abs(sol.q.cpu().numpy() - ref.q).max()
+    log(f"  mu gpu {sol.mu:.10f} oracle {ref.mu:.10f}  max|dD| {err_d:.2e}  max|dq| {err_q:.2e}")
+    assert err_d < 1e-9
+    assert err_q < 1e-9
+    E = sol.eig.cpu().numpy()
+    for s_, so in enumerate(ref.sols):
+        e = np.sort(E[part.sg.eig_off[s_]:part.sg.eig_off[s_ + 1]])
+        assert np.abs(e - so.lam).max() < 1e-10
+
+
 def test_fp64_tiny_config_full_dm_graph(c):
     """96 waters, orthogonal, halos from |D_full| > 1e-5, 2x2x2 cores; parity
     with the oracle and with full-system diagonalisation."""
