@@ -451,34 +451,47 @@ __device__ __forceinline__ bool line_live(const double4* __restrict__ kv, int li
     return kv[line * w + K].w != 0.0 || line == K;
 }
 
-// C(k), S(k) for kSkC consecutive points of one line per workgroup
-constexpr int kSkC = 8;
+// C(k), S(k) of NQ charge vectors for C consecutive points of one line per
+// workgroup (the phases are shared by the vectors)
+template <int NQ, int C>
 __global__ void __launch_bounds__(256) k_ewald_sk_lines(int n, int K, const double* __restrict__ pos,
-                                                       const double* __restrict__ q, const double4* __restrict__ kv,
-                                                       double dkz, double* __restrict__ CS) {
-    __shared__ double red[4][2 * kSkC];
-    const int w = 2 * K + 1, nb = (w + kSkC - 1) / kSkC;
-    const int line = blockIdx.x / nb, g0 = line * w + (blockIdx.x % nb) * kSkC;
-    const int cnt = min(kSkC, line * w + w - g0);
+                                                       const double* __restrict__ q0, const double* __restrict__ q1,
+                                                       const double4* __restrict__ kv, double dkz,
+                                                       double* __restrict__ CS0, double* __restrict__ CS1) {
+    __shared__ double red[4][2 * C * NQ];
+    const int w = 2 * K + 1, nb = (w + C - 1) / C;
+    const int line = blockIdx.x / nb, g0 = line * w + (blockIdx.x % nb) * C;
+    const int cnt = min(C, line * w + w - g0);
     bool any = false;
     for (int t = 0; t < cnt; ++t) any = any || kv[g0 + t].w != 0.0;
     if (!any) {
-        if (threadIdx.x < 2 * cnt) CS[2 * (int64_t)g0 + threadIdx.x] = 0.0;
+        if (threadIdx.x < 2 * cnt) {
+            CS0[2 * (int64_t)g0 + threadIdx.x] = 0.0;
+            if (NQ == 2) CS1[2 * (int64_t)g0 + threadIdx.x] = 0.0;
+        }
         return;
     }
     const double4 k0 = kv[g0];
-    double ac[kSkC], as[kSkC];
+    double ac[NQ][C], as[NQ][C];
 #pragma unroll
-    for (int t = 0; t < kSkC; ++t) ac[t] = as[t] = 0.0;
+    for (int v = 0; v < NQ; ++v)
+#pragma unroll
+        for (int t = 0; t < C; ++t) ac[v][t] = as[v][t] = 0.0;
     for (int j = threadIdx.x; j < n; j += 256) {
-        const double x = pos[3 * j], y = pos[3 * j + 1], z = pos[3 * j + 2], qj = q[j];
+        const double x = pos[3 * j], y = pos[3 * j + 1], z = pos[3 * j + 2];
+        double qj[NQ];
+        qj[0] = q0[j];
+        if (NQ == 2) qj[NQ - 1] = q1[j];
         double sn, cs, sd, cd;
         sincos(k0.x * x + k0.y * y + k0.z * z, &sn, &cs);
         sincos(dkz * z, &sd, &cd);
 #pragma unroll
-        for (int t = 0; t < kSkC; ++t) {
-            ac[t] += qj * cs;
-            as[t] += qj * sn;
+        for (int t = 0; t < C; ++t) {
+#pragma unroll
+            for (int v = 0; v < NQ; ++v) {
+                ac[v][t] += qj[v] * cs;
+                as[v][t] += qj[v] * sn;
+            }
             const double c2 = cs * cd - sn * sd;
             sn = sn * cd + cs * sd;
             cs = c2;
@@ -486,20 +499,25 @@ __global__ void __launch_bounds__(256) k_ewald_sk_lines(int n, int K, const doub
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int t = 0; t < kSkC; ++t) {
-        const double c = gdm_wave_sum(ac[t]), sv = gdm_wave_sum(as[t]);
-        if (lane == 0) {
-            red[wave][2 * t] = c;
-            red[wave][2 * t + 1] = sv;
+    for (int v = 0; v < NQ; ++v)
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            const double c = gdm_wave_sum(ac[v][t]), sv = gdm_wave_sum(as[v][t]);
+            if (lane == 0) {
+                red[wave][2 * (v * C + t)] = c;
+                red[wave][2 * (v * C + t) + 1] = sv;
+            }
         }
-    }
     __syncthreads();
-    if (threadIdx.x < 2 * cnt) {
-        const int t = threadIdx.x >> 1;
-        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-        CS[2 * (int64_t)g0 + threadIdx.x] = kv[g0 + t].w != 0.0 ? v : 0.0;
+    if (threadIdx.x < 2 * cnt * NQ) {
+        const int v = threadIdx.x / (2 * cnt), e = threadIdx.x - v * 2 * cnt, t = e >> 1;
+        const int slot = 2 * (v * C + t) + (e & 1);
+        const double val = red[0][slot] + red[1][slot] + red[2][slot] + red[3][slot];
+        (v == 0 ? CS0 : CS1)[2 * (int64_t)g0 + e] = kv[g0 + t].w != 0.0 ? val : 0.0;
     }
 }
+constexpr int kSkC = 16;       // points per workgroup, one charge vector
+constexpr int kSkC2 = 8;       // points per workgroup, two charge vectors
 
 // part[y * n + i] = sum over the lines of chunk y of w(k) (cos(k.R_i) C + sin(k.R_i) S)
 __global__ void __launch_bounds__(128) k_ewald_recip_lines(int n, int K, int lines_per_chunk,
@@ -1121,8 +1139,8 @@ extern "C" int gdm_ewald_potential(gdm_ctx* ctx, const gdm_system* sys, const in
                        n, sys->pos, sys->species, L, iL, row_ptr, col, rcut, eta, tau ? 1 : 0, tau ? tau[0] : 0.0,
                        tau ? tau[1] : 0.0, q, V);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_sk_lines, dim3(nlines * ((w + kSkC - 1) / kSkC)), dim3(256), 0, ctx->stream, n, k_max,
-                       sys->pos, q, dkv, dkz, CS);
+    hipLaunchKernelGGL((k_ewald_sk_lines<1, kSkC>), dim3(nlines * ((w + kSkC - 1) / kSkC)), dim3(256), 0, ctx->stream,
+                       n, k_max, sys->pos, q, q, dkv, dkz, CS, CS);
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_recip_lines, dim3((n + 127) / 128, nchunk), dim3(128), 0, ctx->stream, n, k_max, lpc,
                        sys->pos, dkv, CS, dkz, part);
@@ -1217,7 +1235,7 @@ extern "C" int gdm_ewald_forces(gdm_ctx* ctx, const gdm_system* sys, const int32
         ctx, BUF_EWALD, sizeof(double) * (8 * (size_t)nk + sys->n_atoms + 3 * (size_t)nchunk * sys->n_atoms), &ok);
     if (!ok) return gdm_fail(ctx, GDM_E_HIP, "gdm_ewald_forces: workspace allocation failed");
     const double dkz = 2.0 * M_PI / sys->box[2];
-    const int skb = nlines * ((w + kSkC - 1) / kSkC);
+    const int skb = nlines * ((w + kSkC2 - 1) / kSkC2);
     double4* dkv = (double4*)ws;
     double* CSa = ws + 4 * (int64_t)nk;
     double* CSb = CSa + 2 * (int64_t)nk;
@@ -1235,9 +1253,8 @@ extern "C" int gdm_ewald_forces(gdm_ctx* ctx, const gdm_system* sys, const int32
     hipLaunchKernelGGL(k_ewald_ktable, dim3((nk + 255) / 256), dim3(256), 0, ctx->stream, k_max, sys->box[0],
                        sys->box[1], sys->box[2], eta, kc2, V3, dkv);
     GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_sk_lines, dim3(skb), dim3(256), 0, ctx->stream, n, k_max, sys->pos, a, dkv, dkz, CSa);
-    GDM_LAUNCH_CHECK(ctx);
-    hipLaunchKernelGGL(k_ewald_sk_lines, dim3(skb), dim3(256), 0, ctx->stream, n, k_max, sys->pos, b, dkv, dkz, CSb);
+    hipLaunchKernelGGL((k_ewald_sk_lines<2, kSkC2>), dim3(skb), dim3(256), 0, ctx->stream, n, k_max, sys->pos, a, b,
+                       dkv, dkz, CSa, CSb);
     GDM_LAUNCH_CHECK(ctx);
     hipLaunchKernelGGL(k_ewald_force_real, dim3((n + kRealAtoms - 1) / kRealAtoms), dim3(64 * kRealAtoms), 0,
                        ctx->stream, n, sys->pos, sys->species, L, iL, row_ptr, col, rcut, eta, tau ? 1 : 0,
