@@ -1082,8 +1082,6 @@ extern "C" int gdm_adam_step(gdm_ctx* ctx, int32_t n, float* params, const float
     return GDM_OK;
 }
 
-// k chunks of the reciprocal sums: enough (atom blocks) x (chunks)
-// workgroups to fill the chip, at least 64 k-vectors per chunk
 // chunks of whole k-grid lines for the (atom blocks) x (chunks) launches:
 // enough workgroups to fill the device, at least 2 lines per chunk
 static void ewald_line_chunks(int n, int nlines, int* nchunk, int* lines_per_chunk) {
