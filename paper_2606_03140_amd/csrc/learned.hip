@@ -597,9 +597,10 @@ __global__ void __launch_bounds__(128) k_ewald_force_recip_lines(int n, int K, i
 }
 
 // k-vector table over the full grid a = 0..K, b, c = -K..K (index
-// (a (2K+1) + b + K) (2K+1) + c + K), with the same half space and sphere
-// k^2 <= kc2 as the host-built table of gdm_ewald_potential; grid points
-// outside them get weight 0 (skipped by k_ewald_sk and k_ewald_recip).
+// (a (2K+1) + b + K) (2K+1) + c + K): weight w(k) inside the half space
+// (a > 0) or (a = 0, b > 0) or (a = b = 0, c > 0) and the sphere k^2 <= kc2,
+// 0 outside (those points contribute nothing to the structure factors and
+// reciprocal sums that read the table).
 __global__ void k_ewald_ktable(int K, double Lx, double Ly, double Lz, double eta, double kc2, double V3,
                                double4* __restrict__ kv) {
     const int w = 2 * K + 1;
