@@ -151,6 +151,22 @@ __global__ void __launch_bounds__(NT, NT / 256) k_sytrd(const SubDesc* __restric
             __syncthreads();
             for (int i = threadIdx.x; i < m; i += NT) v[i] = i == 0 ? 1.0 : v[i] * scale;
             __syncthreads();
+            part = 0.0;
+            // W^T v and V^T v over rows k+1.. (one wave per panel column; they need
+            // only v, so they go ahead of the product and its loads overlap them)
+            for (int l = wave; l < 2 * j; l += NT / 64) {
+                const double* col = (l < j ? Wm + (int64_t)l * n : Vm + (int64_t)(l - j) * n) + (k + 1);
+                double acc = 0.0, acc2 = 0.0;
+                int i = lane;
+                for (; i + 192 < m; i += 256) {
+                    const double c0 = col[i], c1 = col[i + 64], c2 = col[i + 128], c3 = col[i + 192];
+                    acc += c0 * v[i] + c2 * v[i + 128];
+                    acc2 += c1 * v[i + 64] + c3 * v[i + 192];
+                }
+                for (; i < m; i += 64) acc += col[i] * v[i];
+                acc = gdm_wave_sum(acc + acc2);
+                if (lane == 0) corr[2 * kPanel + l] = acc;      // [0, j): W^T v, [j, 2j): V^T v
+            }
             // p = A22 v, A22 = A[k+1:, k+1:] as at the panel's start (symmetric),
             // reading the lower triangle only: 64 x 64 tiles (I >= J) dealt
             // round-robin to the waves, lane = column j, 32 rows of the tile
@@ -171,10 +187,10 @@ __global__ void __launch_bounds__(NT, NT / 256) k_sytrd(const SubDesc* __restric
                     int I = 0;
                     while ((I + 1) * (I + 2) / 2 <= tile) ++I;
                     const int J = tile - I * (I + 1) / 2;
-                    const int j = J * 64 + lane;
-                    const double vj = j < m ? v[j] : 0.0;
+                    const int jc = J * 64 + lane;
+                    const double vj = jc < m ? v[jc] : 0.0;
                     // loads from clamped indices (row uniform, one lane offset), masked after
-                    const uint32_t jc = (uint32_t)min(j, m - 1);
+                    const uint32_t jcl = (uint32_t)min(jc, m - 1);
                     double colacc = 0.0;
                     double* pt = Pt + (int64_t)tile * 128;
                     for (int c0 = 0; c0 < 64; c0 += CH) {
@@ -183,14 +199,14 @@ __global__ void __launch_bounds__(NT, NT / 256) k_sytrd(const SubDesc* __restric
                         for (int q = 0; q < CH; ++q) {
                             const int i = I * 64 + c0 + q;
                             const double* row = col + (int64_t)min(i, m - 1) * ld;
-                            const double xv = row[jc];
-                            x[q] = (i < m && j < m && (I > J || i >= j)) ? xv : 0.0;
+                            const double xv = row[jcl];
+                            x[q] = (i < m && jc < m && (I > J || i >= jc)) ? xv : 0.0;
                         }
 #pragma unroll
                         for (int q = 0; q < CH; ++q) {
                             const int i = I * 64 + c0 + q;
                             colacc += x[q] * (i < m ? v[i] : 0.0);
-                            x[q] = (I > J || i > j) ? x[q] * vj : 0.0;
+                            x[q] = (I > J || i > jc) ? x[q] * vj : 0.0;
                         }
                         if (CH == 32) {
                             fold_half<CH / 2>(x, lane & 1, 1);
@@ -221,45 +237,26 @@ __global__ void __launch_bounds__(NT, NT / 256) k_sytrd(const SubDesc* __restric
                         double t8[8];
 #pragma unroll
                         for (int u = 0; u < 8; ++u) {
-                            const int t = u0 + u, I = t - 1;
-                            const int64_t slot = t <= B ? (int64_t)(B * (B + 1) / 2 + t) * 128 + 64 + xl
-                                                        : (int64_t)(I * (I + 1) / 2 + B) * 128 + xl;
-                            t8[u] = t <= T ? Pt[slot] : 0.0;
+                            const int ts = u0 + u, I = ts - 1;
+                            const int64_t slot = ts <= B ? (int64_t)(B * (B + 1) / 2 + ts) * 128 + 64 + xl
+                                                         : (int64_t)(I * (I + 1) / 2 + B) * 128 + xl;
+                            t8[u] = ts <= T ? Pt[slot] : 0.0;
                         }
 #pragma unroll
                         for (int u = 0; u < 8; ++u) acc += t8[u];
                     }
-                    p[xr] = acc;
-                }
-            }
-            // W^T v and V^T v over rows k+1.. (one wave per panel column)
-            for (int l = wave; l < 2 * j; l += NT / 64) {
-                const double* col = (l < j ? Wm + (int64_t)l * n : Vm + (int64_t)(l - j) * n) + (k + 1);
-                double acc = 0.0, acc2 = 0.0;
-                int i = lane;
-                for (; i + 192 < m; i += 256) {
-                    const double c0 = col[i], c1 = col[i + 64], c2 = col[i + 128], c3 = col[i + 192];
-                    acc += c0 * v[i] + c2 * v[i + 128];
-                    acc2 += c1 * v[i + 64] + c3 * v[i + 192];
-                }
-                for (; i < m; i += 64) acc += col[i] * v[i];
-                acc = gdm_wave_sum(acc + acc2);
-                if (lane == 0) corr[2 * kPanel + l] = acc;      // [0, j): W^T v, [j, 2j): V^T v
-            }
-            __syncthreads();
-            // p -= V (W^T v) + W (V^T v); then w = t p - t^2/2 (p^T v) v
-            part = 0.0;
-            for (int i = threadIdx.x; i < m; i += NT) {
-                const int r = k + 1 + i;
-                double x = p[i];
-                double vr[kPanel], wr[kPanel];
-                panel_row(Vm, Wm, n, r, j, vr, wr);
+                    // p -= V (W^T v) + W (V^T v); then w = t p - t^2/2 (p^T v) v
+                    const int r = k + 1 + xr;
+                    double x = acc;
+                    double vr[kPanel], wr[kPanel];
+                    panel_row(Vm, Wm, n, r, j, vr, wr);
 #pragma unroll
-                for (int l = 0; l < kPanel; ++l)
-                    if (l < j) x -= vr[l] * corr[2 * kPanel + l] + wr[l] * corr[2 * kPanel + j + l];
-                x *= t;
-                p[i] = x;
-                part += x * v[i];
+                    for (int l = 0; l < kPanel; ++l)
+                        if (l < j) x -= vr[l] * corr[2 * kPanel + l] + wr[l] * corr[2 * kPanel + j + l];
+                    x *= t;
+                    p[xr] = x;
+                    part += x * v[xr];
+                }
             }
             const double pv = block_sum_n(part, red, NT);
             const double half = 0.5 * t * pv;
