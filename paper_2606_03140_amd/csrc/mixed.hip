@@ -1012,9 +1012,10 @@ __global__ void __launch_bounds__(256) k_split_to_f64(int64_t n4, SplitMat X, do
     }
 }
 
-// A <- 2 X2 - 2 X + I over the padded P x P tile (padding: X = X2 = 0, so A = I there)
+// A <- 2 X2 - 2 X + I over the padded P x P tile (padding: X = X2 = 0, so A = I
+// there), in FP64 and as split operands As (from its FP32 rounding)
 __global__ void __launch_bounds__(kEw) k_doubling_a(const SubDesc* __restrict__ desc, const double* __restrict__ X,
-                                                   const double* __restrict__ X2, double* __restrict__ A,
+                                                   const double* __restrict__ X2, double* __restrict__ A, SplitMat As,
                                                    const int* __restrict__ skip) {
     if (skip && *skip) return;
     const SubDesc d = desc[blockIdx.x];
@@ -1032,6 +1033,7 @@ __global__ void __launch_bounds__(kEw) k_doubling_a(const SubDesc* __restrict__ 
         if (i == j0 + 2) a.z += 1.0;
         if (i == j0 + 3) a.w += 1.0;
         *(double4*)(A + idx) = a;
+        store4(As, idx, make_float4((float)a.x, (float)a.y, (float)a.z, (float)a.w));
     }
 }
 
@@ -1510,9 +1512,8 @@ static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const in
     GDM_TRY(gemm64_dd(ctx, X, X, nullptr, X2, 1.0, 0.0, 0.0, 1, skip, "last64"));
     {
         GDM_TIMED(ctx, "last64");
-        hipLaunchKernelGGL(k_doubling_a, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, X, X2, A, skip);
-        GDM_LAUNCH_CHECK(ctx);
-        hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, n4, A, slot(ctx, SL_A), skip);
+        hipLaunchKernelGGL(k_doubling_a, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, X, X2, A, slot(ctx, SL_A),
+                           skip);
     }
     GDM_LAUNCH_CHECK(ctx);
     // split start and Newton-Schulz steps (whole storage: A comes whole)
