@@ -778,10 +778,11 @@ __global__ void __launch_bounds__(256) k_scale_sym_to_f64(const SubDesc* __restr
 
 // dst <- src^T over every subgraph's P x P tile, on the upper-tile list (both
 // tiles of a pair through LDS); FP64 (dst64) and, when dsplit.hi is set, the
-// split halves and FP32 copy of the transpose
+// split halves and FP32 copy of the transpose; copy (nullable) <- src
 __global__ void __launch_bounds__(256) k_transpose64(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
-                                                    const double* __restrict__ src, double* __restrict__ dst64,
-                                                    SplitMat dsplit, const int* __restrict__ skip) {
+                                                    const double* __restrict__ src, double* __restrict__ copy,
+                                                    double* __restrict__ dst64, SplitMat dsplit,
+                                                    const int* __restrict__ skip) {
     __shared__ double a[64][65], b2[64][65];
     if (skip && *skip) return;
     const int4 tl = tiles[blockIdx.x];
@@ -791,8 +792,13 @@ __global__ void __launch_bounds__(256) k_transpose64(const SubDesc* __restrict__
     const int I0 = tl.y * 64, J0 = tl.z * 64;
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int r = e >> 6, c = e & 63;
-        a[r][c] = src[d.off2 + (int64_t)(I0 + r) * P + J0 + c];
-        b2[r][c] = src[d.off2 + (int64_t)(J0 + r) * P + I0 + c];
+        const int64_t j1 = d.off2 + (int64_t)(I0 + r) * P + J0 + c, j2 = d.off2 + (int64_t)(J0 + r) * P + I0 + c;
+        a[r][c] = src[j1];
+        b2[r][c] = src[j2];
+        if (copy) {                     // src as it is (both tiles of the pair)
+            copy[j1] = a[r][c];
+            copy[j2] = b2[r][c];
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
@@ -1168,12 +1174,6 @@ __global__ void __launch_bounds__(256) k_copy_split(int64_t n4, SplitMat src, Sp
         *(half4*)(dst.hi + 4 * e) = *(const half4*)(src.hi + 4 * e);
         *(half4*)(dst.lo + 4 * e) = *(const half4*)(src.lo + 4 * e);
     }
-}
-
-__global__ void __launch_bounds__(256) k_copy_f64(int64_t n4, const double* __restrict__ src,
-                                                 double* __restrict__ dst) {
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256)
-        *(double4*)(dst + 4 * e) = *(const double4*)(src + 4 * e);
 }
 
 __global__ void k_zero1(double* p, const int* skip) {
@@ -1717,17 +1717,16 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
             double* T64 = fp64_region(ctx, 3);
             GDM_TRY(gemm64_dd(ctx, E, E, E, T64, 0.375, -0.5, 0.0, 1));        // T = 3/8 E^2 - E/2
             GDM_TRY(gemm64_dd(ctx, Z64, T64, Z64, F, 1.0, 1.0, 0.0, 0));      // F <- Z + Z T (all tiles)
-            hipLaunchKernelGGL(k_copy_f64, dim3(4096), dim3(256), 0, ctx->stream, P.tot2 / 4, F, Z64);
-            GDM_LAUNCH_CHECK(ctx);
         }
-        // Z1^T in FP64 (the density's right factor) and as split operands with
-        // an FP32 copy (the split products of h_perp and of the response)
+        // Z1 into Z64 (from F after the refinement), Z1^T in FP64 (the
+        // density's right factor) and as split operands with an FP32 copy (the
+        // split products of h_perp and of the response), in one pass
         Z = slot(ctx, SL_Z);
         {
             GDM_TIMED(ctx, "refine64");
             hipLaunchKernelGGL(k_transpose64, dim3((unsigned)ctx->mixed_tiles_sym), dim3(256), 0, ctx->stream, desc,
-                               (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles, Z64, z64t(ctx), Z,
-                               (const int*)nullptr);
+                               (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles, orth ? Z64 : F,
+                               orth ? (double*)nullptr : Z64, z64t(ctx), Z, (const int*)nullptr);
         }
         GDM_LAUNCH_CHECK(ctx);
         GDM_TRY(gemm64_core<double>(ctx, s64, Z64, F, "refine64"));   // V = s[core,:] Z
