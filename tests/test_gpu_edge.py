@@ -110,6 +110,33 @@ def test_one_large_subgraph_mixed(c):
     assert err_d < 1e-4 and err_q < 1e-4
 
 
+def test_one_large_subgraph_fp64(c):
+    """The largest subgraph the FP64 path takes (2,048 orbitals): 340 waters as
+    one subgraph, 2,040 orbitals, every row a core row; D, charges, mu and
+    eigenvalues against the oracle's full diagonalisation."""
+    from paper_2606_03140_amd import pipeline
+    from tests.gpu_common import system_of
+    log("340 waters as one subgraph (2,040 orbitals), FP64 path")
+    box = waterbox.water_box(340, 21)
+    sysm = system_of(box)
+    tb = tb_params(False)
+    part = pipeline.full_system_partition(c, sysm, tb)
+    assert part.sg.n_sub == 1 and int(part.sg.norb[0]) == 2040
+    H, S = c.build_hs(sysm, tb, part.nbr)
+    sol = pipeline.solve(c, sysm, part, H, S, 0.1, pipeline.FP64_EIG, eig=True)
+    ref = osv.full_system(box.pos, box.species, box.box[0], oracle_model(False))
+    err_d = np.abs(unpack_dcore(part.sg, sol.D_core)[0] - ref.d_core[0]).max()
+    err_q = np.abs(sol.q.cpu().numpy() - ref.q).max()
+    err_l = np.abs(np.sort(sol.eig.cpu().numpy()) - np.sort(ref.sols[0].lam)).max()
+    log(f"  mu gpu {sol.mu:.10f} oracle {ref.mu:.10f}  max|dD| {err_d:.2e} max|dq| {err_q:.2e} max|dlam| {err_l:.2e}")
+    # mu sits in the gap of the whole system, where the count is flat to its
+    # rounding: D does not depend on where (1e-14 above), so mu is bounded
+    # loosely and the count exactly
+    assert abs(sol.mu - ref.mu) < 1e-6
+    assert err_d < 1e-9 and err_q < 1e-9 and err_l < 1e-10
+    assert abs(sol.n_count - sysm.n_electrons) < 1e-9
+
+
 def test_host_validation(c):
     from paper_2606_03140_amd import pipeline
     from paper_2606_03140_amd._lib import GDMError, Subgraphs, System
