@@ -208,22 +208,16 @@ __global__ void __launch_bounds__(NT, NT / 256) k_sytrd(const SubDesc* __restric
                             colacc += x[q] * (i < m ? v[i] : 0.0);
                             x[q] = (I > J || i > jc) ? x[q] * vj : 0.0;
                         }
-                        if (CH == 32) {
-                            fold_half<CH / 2>(x, lane & 1, 1);
-                            fold_half<CH / 4>(x, lane & 2, 2);
-                            fold_half<CH / 8>(x, lane & 4, 4);
-                            fold_half<CH / 16>(x, lane & 8, 8);
-                            fold_half<CH / 32>(x, lane & 16, 16);
-                            x[0] += __shfl_xor(x[0], 32, 64);
-                        } else {
-                            fold_half<CH / 2>(x, lane & 1, 1);
-                            fold_half<CH / 4>(x, lane & 2, 2);
-                            fold_half<CH / 8>(x, lane & 4, 4);
-                            fold_half<CH / 16>(x, lane & 8, 8);
-                            x[0] += __shfl_xor(x[0], 16, 64);
-                            x[0] += __shfl_xor(x[0], 32, 64);
-                        }
-                        if (lane < CH) pt[64 + c0 + (CH == 32 ? rsel : rsel >> 1)] = x[0];
+                        // log2(CH) exchanges (those with H = 0 do nothing), then plain
+                        // sums over the remaining lane bits
+                        fold_half<CH / 2>(x, lane & 1, 1);
+                        fold_half<CH / 4>(x, lane & 2, 2);
+                        fold_half<CH / 8>(x, lane & 4, 4);
+                        fold_half<CH / 16>(x, lane & 8, 8);
+                        fold_half<CH / 32>(x, lane & 16, 16);
+#pragma unroll
+                        for (int mask = CH; mask < 64; mask <<= 1) x[0] += __shfl_xor(x[0], mask, 64);
+                        if (lane < CH) pt[64 + c0 + rsel / (32 / CH)] = x[0];
                     }
                     pt[lane] = colacc;
                 }
