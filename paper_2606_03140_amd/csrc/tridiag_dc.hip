@@ -36,7 +36,8 @@ namespace {
 
 constexpr double kEps = 2.220446049250313e-16;   // 2^-52
 constexpr int kLeafMax = 64;                     // leaf rows (one wave)
-constexpr int kMergeThreads = 512;
+constexpr int kMergeThreads = 512;      // threads per merge workgroup
+constexpr int kMergeThreadsFew = 1024;  // when a round has fewer merges than CUs
 constexpr int kMergeBytesPerRow = 7 * 8 + 4 * 4; // LDS of the merge kernel per row of the block
 
 __host__ __device__ inline int dc_bound(int n, int level, int i) {
@@ -233,7 +234,8 @@ __device__ double dc_root(const double* __restrict__ dn, const double* __restric
 // parity (level + 1) & 1; the merge writes its own at parity level & 1 and
 // its factor U (k x k, row-major) at offu.  Chain records (cosine, sine,
 // next, previous) live in global scratch at [lo, hi).
-__global__ void __launch_bounds__(kMergeThreads) k_dc_merge(
+template <int MT>
+__global__ void __launch_bounds__(MT) k_dc_merge(
     const SubDesc* __restrict__ desc, const DcNode* __restrict__ nodes, const double* __restrict__ Eg,
     double* __restrict__ LamA, double* __restrict__ LamB, double* __restrict__ FrA, double* __restrict__ FrB,
     double* __restrict__ LrA, double* __restrict__ LrB, double* __restrict__ Cs, double* __restrict__ Sn,
@@ -267,7 +269,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_dc_merge(
     double* sn = Sn + o;
     int32_t* nx = Nx + o;
     int32_t* pv = Pv + o;
-    for (int t = tid; t < k; t += kMergeThreads) {
+    for (int t = tid; t < k; t += MT) {
         dn[t] = lamc[t];
         zh[t] = (t < k1 ? lc[t] : sg * fc[t]) * 0.70710678118654752440;
         f1x[t] = t < k1 ? fc[t] : 0.0;
@@ -278,7 +280,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_dc_merge(
     }
     __syncthreads();
     // stable rank sort of the poles
-    for (int t = tid; t < k; t += kMergeThreads) {
+    for (int t = tid; t < k; t += MT) {
         const double v = dn[t];
         int r = 0;
         for (int u = 0; u < k; ++u) {
@@ -340,13 +342,13 @@ __global__ void __launch_bounds__(kMergeThreads) k_dc_merge(
     }
     __syncthreads();
     const int K = sK;
-    for (int i = tid; i < K; i += kMergeThreads) {
+    for (int i = tid; i < K; i += MT) {
         const int p = ndp[i];
         dn[i] = ds[p];
         zh[i] = ws[p];
     }
     __syncthreads();
-    for (int j = tid; j < K; j += kMergeThreads) {
+    for (int j = tid; j < K; j += MT) {
         int og;
         tau[j] = dc_root(dn, zh, K, r2, j, &og);
         org[j] = og;
@@ -354,7 +356,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_dc_merge(
     __syncthreads();
     // zhat_i^2 = prod_j (x_j - d_i) / (r2 prod_{j != i} (d_j - d_i)), each
     // root paired with an adjacent pole so every factor is a positive ratio
-    for (int i = tid; i < K; i += kMergeThreads) {
+    for (int i = tid; i < K; i += MT) {
         const double di = dn[i];
         double v = ((dn[org[K - 1]] - di) + tau[K - 1]) / r2;
         for (int j = 0; j < K - 1; ++j) v *= ((dn[org[j]] - di) + tau[j]) / ((j < i ? dn[j] : dn[j + 1]) - di);
@@ -364,9 +366,9 @@ __global__ void __launch_bounds__(kMergeThreads) k_dc_merge(
     // weights: an undeflated position owns itself (weight 1); a chain
     // a_1 .. a_m (rotations (a_t, a_t+1)) is owned by its survivor a_m with
     // weight c_{i-1} prod_{t >= i} s_t at a_i
-    for (int p = tid; p < k; p += kMergeThreads)
+    for (int p = tid; p < k; p += MT)
         if (own[p] == -2) ws[p] = 0.0;
-    for (int i = tid; i < K; i += kMergeThreads) {
+    for (int i = tid; i < K; i += MT) {
         int q = ndp[i];
         double P = 1.0;
         for (;;) {
@@ -384,7 +386,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_dc_merge(
     double* fo = (ob ? FrB : FrA) + o;
     double* lo_ = (ob ? LrB : LrA) + o;
     double* u = U + nd.offu;
-    for (int t = tid; t < k; t += kMergeThreads) {
+    for (int t = tid; t < k; t += MT) {
         double fs = 0.0, ls = 0.0, ev;
         if (t < K) {
             const double dor = dn[org[t]], tt = tau[t];
@@ -666,7 +668,9 @@ int gdm_dc_plan(gdm_ctx* ctx) {
     GDM_HIP(ctx, hipMemcpyAsync(lst, P.dc_nodes.data(), nb, hipMemcpyHostToDevice, ctx->stream));
     GDM_HIP(ctx, hipMemcpyAsync(lst + toff, P.dc_tiles.data(), tb, hipMemcpyHostToDevice, ctx->stream));
     GDM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return dc_set_lds(ctx, (const void*)k_dc_merge, P.dc_merge_lds);
+    int rc = dc_set_lds(ctx, (const void*)k_dc_merge<kMergeThreads>, P.dc_merge_lds);
+    if (rc) return rc;
+    return dc_set_lds(ctx, (const void*)k_dc_merge<kMergeThreadsFew>, P.dc_merge_lds);
 }
 
 // Eigenvalues (parity-0 buffer = the plan's eigenvalue array) and factors.
@@ -694,8 +698,14 @@ int gdm_dc_solve(gdm_ctx* ctx) {
     for (int r = 1; r <= P.dc_max_depth; ++r) {
         const int a = P.dc_round[r], b = P.dc_round[r + 1];
         if (b <= a) continue;
-        hipLaunchKernelGGL(k_dc_merge, dim3(b - a), dim3(kMergeThreads), P.dc_merge_lds, ctx->stream, desc,
-                           nodes + a, Eg, LamA, LamB, FrA, FrB, LrA, LrB, Cs, Sn, idx, idx + tv, U);
+        // a round with fewer merges than CUs takes 1024 threads per merge (the
+        // secular roots, weights and factor columns spread over more lanes)
+        if (b - a < ctx->n_cu)
+            hipLaunchKernelGGL((k_dc_merge<kMergeThreadsFew>), dim3(b - a), dim3(kMergeThreadsFew), P.dc_merge_lds,
+                               ctx->stream, desc, nodes + a, Eg, LamA, LamB, FrA, FrB, LrA, LrB, Cs, Sn, idx, idx + tv, U);
+        else
+            hipLaunchKernelGGL((k_dc_merge<kMergeThreads>), dim3(b - a), dim3(kMergeThreads), P.dc_merge_lds,
+                               ctx->stream, desc, nodes + a, Eg, LamA, LamB, FrA, FrB, LrA, LrB, Cs, Sn, idx, idx + tv, U);
         GDM_LAUNCH_CHECK(ctx);
     }
     return GDM_OK;
