@@ -512,7 +512,8 @@ def main():
                                f"{wl['grid'][2]} cores, tau {wl['tau']} ({wl['rounds']} graph rounds)",
                    "n_subgraphs": part.sg.n_sub, "orbitals_min": int(n.min()), "orbitals_median": int(np.median(n)),
                    "orbitals_max": int(n.max()), "path": head,
-                   "mixed_options": {"ns_z": args.ns_z or 3, "ns_inv": args.ns_inv or tuning["mixed"]["ns_inv"]},
+                   "mixed_options": {"ns_z": args.ns_z or 3, "ns_inv": args.ns_inv or tuning["mixed"]["ns_inv"],
+                                     "inv_start": tuning["mixed"].get("inv_start", 2)},
                    "tuning": tuning},
         "paths": {k: {"ms_per_step": v["ms_per_step"], "solves_per_s": v["solves_per_s"], "mu": v["mu"],
                       "electron_count": v["n_count"],

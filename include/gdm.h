@@ -418,9 +418,9 @@ int gdm_axpby(gdm_ctx* ctx, int32_t n, double a, const double* x, double b, cons
  * more iteration,
  * at most ns_z_extra times (default 8), after which it returns
  * GDM_E_NOT_CONVERGED (overlap too ill-conditioned).  ns_inv: Newton-Schulz
- * iterations per inverse in each doubling after the minimax quadratic start
- * (default 2; the start has error <= 1/99, so k iterations reach
- * (1/99)^(2^k)).  max_passes: expansion
+ * iterations per inverse in each doubling after its minimax start (default
+ * 1; a start with error e0 reaches e0^(2^k) after k iterations, see
+ * gdm_set_mixed_inverse_start).  max_passes: expansion
  * passes allowed while matching the electron count (default 16: a cold
  * start next to subgraph states near mu can need 9 Newton/bisection passes;
  * a warm start from the previous mu takes 1).  Values
@@ -446,6 +446,16 @@ int gdm_set_fp64_options(gdm_ctx* ctx, int leaf_rows);
  * recorded for the charge response are always stored whole.  GDM_E_ARG for
  * other values. */
 int gdm_set_mixed_storage(gdm_ctx* ctx, int upper_tiles);
+
+/* Start of the Newton-Schulz inverse of A = 2 X^2 - 2 X + I in every doubling
+ * of a MIXED_F16 / MIXED_BF16 pass (the A^-1 of Eq. 3's recursive expansion;
+ * eigenvalues of A in [1/2, 1]): the minimax polynomial of the given degree,
+ * whose residual |1 - a y(a)| on [1/2, 1] is at most 1/|T_{d+1}(3)| (T the
+ * Chebyshev polynomial).  degree = 4 (default): two products, residual
+ * <= 1/3363, then ns_inv = 1 step reaches 8.8e-8; degree = 2: one product,
+ * residual <= 1/99, two steps reach 1.0e-8 (one product more per doubling).
+ * Read by the next gdm_find_mu; GDM_E_ARG for other degrees. */
+int gdm_set_mixed_inverse_start(gdm_ctx* ctx, int degree);
 
 /* Statistics of the last GDM_MIXED_F16 gdm_find_mu (HOST outputs, nullable):
  * expansion passes, doublings per pass, split GEMM launches, and the mean

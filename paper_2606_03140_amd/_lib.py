@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     sig["gdm_set_mixed_options"] = (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int])
     sig["gdm_set_mu_outputs"] = (C.c_int, [P, C.c_int])
     sig["gdm_set_mixed_storage"] = (C.c_int, [P, C.c_int])
+    sig["gdm_set_mixed_inverse_start"] = (C.c_int, [P, C.c_int])
     sig["gdm_set_mixed_capture"] = (C.c_int, [P, C.c_int, C.c_int])
     sig["gdm_mixed_mu_state"] = (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)])
     sig["gdm_subgraph_density_dmu"] = (C.c_int, [P, C.POINTER(SubgraphsT), P, D, C.c_int, P])
@@ -492,6 +493,9 @@ class Context:
 
     def set_mixed_storage(self, upper_tiles: bool):
         self._check(self.lib.gdm_set_mixed_storage(self.h, 1 if upper_tiles else 0))
+
+    def set_mixed_inverse_start(self, degree: int):
+        self._check(self.lib.gdm_set_mixed_inverse_start(self.h, int(degree)))
 
     def set_mixed_options(self, ns_z: int = 0, ns_inv: int = 0, max_passes: int = 0, ns_z_extra: int = -1):
         self._check(self.lib.gdm_set_mixed_options(self.h, ns_z, ns_inv, max_passes, ns_z_extra))

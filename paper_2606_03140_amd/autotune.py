@@ -6,8 +6,9 @@ setting of the options that change speed but not the method:
 * FP64 path: the largest leaf of the tridiagonal divide and conquer
   (gdm_set_fp64_options; results agree to FP64 rounding for every value);
 * mixed paths: upper-tile or whole storage of the expansion's symmetric
-  matrices (gdm_set_mixed_storage) and the Newton-Schulz iterations per
-  inverse after the quadratic start (gdm_set_mixed_options).  These change
+  matrices (gdm_set_mixed_storage), the degree of the minimax start of each
+  doubling's inverse (gdm_set_mixed_inverse_start) and the Newton-Schulz
+  iterations after it (gdm_set_mixed_options).  These change
   the rounding, so a candidate is kept only when its density and charges
   stay within `tol` of the FP64 path's on the same workload.
 
@@ -31,11 +32,12 @@ import numpy as np
 PATHS = ("fp64", "mixed", "mixed_bf16")
 CANDIDATES = {
     "fp64": [{"leaf_rows": v} for v in (16, 24, 32, 48, 64)],
-    "mixed": [{"upper_tiles": u, "ns_inv": k} for u in (1, 0) for k in (2, 3)],
-    "mixed_bf16": [{"upper_tiles": u, "ns_inv": k} for u in (1, 0) for k in (2, 3)],
+    "mixed": [{"upper_tiles": u, "inv_start": d, "ns_inv": k} for u in (1, 0) for d, k in ((4, 1), (2, 2), (4, 2))],
+    "mixed_bf16": [{"upper_tiles": u, "inv_start": d, "ns_inv": k}
+                   for u in (1, 0) for d, k in ((4, 1), (2, 2), (4, 2))],
 }
-DEFAULTS = {"fp64": {"leaf_rows": 64}, "mixed": {"upper_tiles": 1, "ns_inv": 2},
-            "mixed_bf16": {"upper_tiles": 1, "ns_inv": 2}}
+DEFAULTS = {"fp64": {"leaf_rows": 64}, "mixed": {"upper_tiles": 1, "inv_start": 4, "ns_inv": 1},
+            "mixed_bf16": {"upper_tiles": 1, "inv_start": 4, "ns_inv": 1}}
 TABLE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 
@@ -61,7 +63,9 @@ def apply(ctx, path: str, opts: dict) -> None:
     if path == "fp64":
         ctx.set_fp64_options(int(opts.get("leaf_rows", 64)))
     else:
+        # a table entry without "inv_start" was tuned with the quadratic start
         ctx.set_mixed_storage(bool(opts.get("upper_tiles", 1)))
+        ctx.set_mixed_inverse_start(int(opts.get("inv_start", 2)))
         ctx.set_mixed_options(ns_inv=int(opts.get("ns_inv", 2)))
 
 

@@ -101,7 +101,8 @@ struct gdm_ctx {
     int mu_out_device = 0;       // gdm_find_mu writes mu and N to device scalars (FP64 path)
     int fp64_leaf = 64;          // FP64 path: largest leaf of the divide-and-conquer tree (gdm_set_fp64_options)
     int mixed_packed = 1;        // expansion matrices stored as upper tiles (gdm_set_mixed_storage)
-    int mixed_ns_inv = 2;        // Newton-Schulz iterations per inverse after the quadratic start
+    int mixed_ns_inv = 1;        // Newton-Schulz iterations per inverse after its minimax start
+    int mixed_inv_deg = 4;       // degree of that start: 4 (two products) or 2 (one product)
     int mixed_max_passes = 16;   // expansion passes allowed for mu
     int mixed_dev_passes = 3;    // passes launched by the device-side search (gdm_set_mixed_capture)
     int mixed_nd_launch = 12;    // doublings launched per pass by the device-side search

@@ -14,9 +14,11 @@
 //       the cubic I/2 - K/4 + K^3/108, or the linear I/2 - K/4 when the pass is
 //       recorded for the charge response,
 //   n_d times:  X2 = X X,  A = 2 X2 - 2 X + I = X^2 + (I - X)^2,
-//               Y = A^-1 by Newton-Schulz from the minimax quadratic start
-//               Y0 = (420 I - 576 A + 256 A^2) / 99 (|I - A Y0| <= 1/99 on
-//               [1/2, 1]), then ns_inv iterations,
+//               Y = A^-1 by Newton-Schulz from a minimax start on [1/2, 1]:
+//               the quartic y4 of kInvStart4 (two products, |I - A Y0| <=
+//               1/3363) and ns_inv = 1 iteration by default, or the
+//               quadratic (420 I - 576 A + 256 A^2) / 99 (one product, <= 1/99)
+//               and ns_inv = 2,
 //               X <- X2 Y            (f_b -> f_2b);
 //   the last of them with X2, A and X2 Y in FP64 on the FP64 matrix cores,
 //       its inverse started on the split products as above and finished by
@@ -1341,6 +1343,30 @@ static int gemm(gdm_ctx* ctx, SplitMat A, SplitMat B, SplitMat O1, SplitMat O2, 
 // monotone in K, which the doublings do not need.
 static constexpr float kStart7[3] = {0.0208103713f, -0.000615022611f, 5.41684949e-06f};
 
+// Minimax starts of the inverse of A = 2 X^2 - 2 X + I, whose eigenvalues lie
+// in [1/2, 1].  For a start y(a) of degree d the residual 1 - a y(a) is a
+// polynomial of degree d + 1 equal to 1 at a = 0; its smallest maximum on
+// [1/2, 1] is 1 / |T_{d+1}(-3)| (T the Chebyshev polynomial of the first kind,
+// 4a - 3 mapping [1/2, 1] onto [-1, 1]), reached by the scaled T_{d+1} itself:
+// 1/99 for the quadratic, 1/3363 for the quartic
+// y4(a) = (23780 - 66240 a + 90880 a^2 - 61440 a^3 + 16384 a^4) / 3363.
+// The quartic takes two products: Q = c4 A^2 + c3 A + c2 I (with A^2 kept as
+// the raw product), then Y0 = Q A^2 + c1 A + c0 I; one Newton-Schulz step then
+// leaves 3363^-2 = 8.8e-8, the split products' own rounding level, in one
+// product fewer than the quadratic start's two steps (99^-4 = 1.0e-8).
+static constexpr float kInvStart4[5] = {23780.0f / 3363.0f, -66240.0f / 3363.0f, 90880.0f / 3363.0f,
+                                        -61440.0f / 3363.0f, 16384.0f / 3363.0f};
+
+static int inv_start(gdm_ctx* ctx, SplitMat A, SplitMat Y, SplitMat T1, SplitMat T2, int pk, const int* sk) {
+    if (ctx->mixed_inv_deg == 4) {
+        const float* c = kInvStart4;
+        GDM_TRY(gemm(ctx, A, A, hl(T1), hl(T2), hl(A), c[4], c[3], c[2], "foe_gemm", 1, pk, sk));
+        return gemm(ctx, T2, T1, none(), hl(Y), hl(A), 1.0f, c[1], c[0], "foe_gemm", 1, pk, sk);
+    }
+    return gemm(ctx, A, A, none(), hl(Y), hl(A), 256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f, "foe_gemm", 1, pk,
+                sk);
+}
+
 // Doubling history for the charge response: X_k (which = 0), the input of
 // doubling k, and Y_k (which = 1), its inverse (2 X_k^2 - 2 X_k + I)^-1, as
 // FP16 hi/lo pairs.
@@ -1413,12 +1439,10 @@ static int foe_pass(gdm_ctx* ctx, double mu, double b, int nd, int start, const 
         // X2 = X X ; A = 2 X2 - 2 X + I
         GDM_TRY(gemm(ctx, Xk, Xk, hl(X2), hl(A), hl(Xk), 2.0f, -2.0f, 1.0f, "foe_gemm", 1, pk, sk));
         // Newton-Schulz inverse of A (eigenvalues in [1/2, 1]) from the minimax
-        // quadratic start Y0 = (420 I - 576 A + 256 A^2) / 99: 1 - a y0(a) is the
-        // Chebyshev T3 on [1/2, 1] scaled to 1 at a = 0, so |1 - a y0| <= 1/99;
-        // each iteration R = 2I - A Y, Y <- Y R squares the error
+        // start (Rm and Yb hold the quartic start's A^2 and Q); each iteration
+        // R = 2I - A Y, Y <- Y R squares the error
         SplitMat Y = (rec && ns == 0) ? hist(ctx, it, 1) : Ya;
-        GDM_TRY(gemm(ctx, A, A, none(), hl(Y), hl(A), 256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f, "foe_gemm", 1,
-                     pk, sk));
+        GDM_TRY(inv_start(ctx, A, Y, Rm, Yb, pk, sk));
         for (int k = 0; k < ns; ++k) {
             GDM_TRY(gemm(ctx, A, Y, none(), hl(Rm), none(), -1.0f, 0.0f, 2.0f, "foe_gemm", 1, pk, sk));
             const SplitMat Yn = (rec && k == ns - 1) ? hist(ctx, it, 1) : (Y.hi == Ya.hi ? Yb : Ya);
@@ -1475,9 +1499,10 @@ static double* fp64_region(gdm_ctx* ctx, int k) { return (double*)ctx->b[BUF_L].
 // The last doubling of a pass in FP64 on the matrix cores (the final
 // refinement step of the expansion): X2 = X X, A = 2 X2 - 2 X + I in FP64,
 // Y = A^-1, X <- X2 Y.  The inverse starts on the split products: A as split
-// operands, the minimax quadratic start Y0 = (420 I - 576 A + 256 A^2)/99
-// (|1 - a y0| <= 1/99 on [1/2, 1]) and the split Newton-Schulz steps of the
-// other doublings leave I - A Y at the split products' rounding level
+// operands, the minimax start of the other doublings (the quartic of
+// kInvStart4 with one split Newton-Schulz step by default, or the quadratic
+// (420 I - 576 A + 256 A^2)/99 with two) leave I - A Y at the split
+// products' rounding level
 // (~1e-7 for FP16 pairs, ~1e-5 for BF16 pairs).  Then FP64 steps
 // R = 2I - A Y, Y <- Y R: each maps I - A Y to (I - A Y)^2 exactly, for any
 // Y, so one step (FP16 pairs) or two (BF16 pairs) leave ~1e-14 / ~1e-20,
@@ -1519,8 +1544,7 @@ static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const in
     // split start and Newton-Schulz steps (whole storage: A comes whole)
     const SplitMat As = slot(ctx, SL_A), Rs = slot(ctx, SL_R), Ysa = slot(ctx, SL_Y), Ysb = slot(ctx, SL_YI);
     SplitMat Ys = Ysa;
-    GDM_TRY(gemm(ctx, As, As, none(), hl(Ys), hl(As), 256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f, "foe_gemm", 1,
-                 0, skip));
+    GDM_TRY(inv_start(ctx, As, Ys, Rs, Ysb, 0, skip));
     for (int k = 0; k < ctx->mixed_ns_inv; ++k) {
         GDM_TRY(gemm(ctx, As, Ys, none(), hl(Rs), none(), -1.0f, 0.0f, 2.0f, "foe_gemm", 1, 0, skip));
         const SplitMat Yn = Ys.hi == Ysa.hi ? Ysb : Ysa;
@@ -1953,6 +1977,14 @@ extern "C" int gdm_set_mixed_storage(gdm_ctx* ctx, int upper_tiles) {
     if (upper_tiles != 0 && upper_tiles != 1)
         return gdm_fail(ctx, GDM_E_ARG, "gdm_set_mixed_storage: upper_tiles must be 0 or 1");
     ctx->mixed_packed = upper_tiles;
+    return GDM_OK;
+}
+
+extern "C" int gdm_set_mixed_inverse_start(gdm_ctx* ctx, int degree) {
+    if (!ctx) return GDM_E_ARG;
+    if (degree != 2 && degree != 4)
+        return gdm_fail(ctx, GDM_E_ARG, "gdm_set_mixed_inverse_start: degree must be 2 or 4");
+    ctx->mixed_inv_deg = degree;
     return GDM_OK;
 }
 

@@ -32,6 +32,9 @@ class FakeCtx:
     def set_mixed_storage(self, upper):
         self.calls.append(("storage", upper))
 
+    def set_mixed_inverse_start(self, degree):
+        self.calls.append(("inv_start", degree))
+
     def set_mixed_options(self, ns_inv=0):
         self.calls.append(("ns_inv", ns_inv))
 
@@ -46,8 +49,10 @@ def test_table_round_trip_and_apply(tmp_path):
     c = FakeCtx()
     used = autotune.apply_table(c, table, 628, paths=("fp64", "mixed"))
     assert used == {"fp64": {"leaf_rows": 32}, "mixed": {"upper_tiles": 0, "ns_inv": 3}}
-    assert c.calls == [("fp64", 32), ("storage", False), ("ns_inv", 3)]
+    # an entry without "inv_start" predates the quartic start: quadratic
+    assert c.calls == [("fp64", 32), ("storage", False), ("inv_start", 2), ("ns_inv", 3)]
     # a bucket without an entry falls back to the library defaults
     c = FakeCtx()
     used = autotune.apply_table(c, table, 1673, paths=("fp64", "mixed"))
-    assert used == {"fp64": {"leaf_rows": 64}, "mixed": {"upper_tiles": 1, "ns_inv": 2}}
+    assert used == {"fp64": {"leaf_rows": 64}, "mixed": {"upper_tiles": 1, "inv_start": 4, "ns_inv": 1}}
+    assert c.calls == [("fp64", 64), ("storage", True), ("inv_start", 4), ("ns_inv", 1)]

@@ -12,7 +12,10 @@ kernel source, so a change there is checked here).
   doublings is at most 1.4e-5 (n = 6).
 * Inverse start in each doubling: y0(a) = (420 - 576 a + 256 a^2) / 99 has
   |1 - a y0(a)| <= 1/99 on [1/2, 1] (a Chebyshev T3 residual), attained
-  with alternating signs at four points.
+  with alternating signs at four points; the quartic y4 has the scaled T5 as
+  its residual, |1 - a y4(a)| <= 1/3363, also with its FP32 coefficients and
+  evaluated the way the kernel does (Q = c4 a^2 + c3 a + c2, y = Q a^2 +
+  c1 a + c0).
 * Inverse square root start: z0(x) = c0 + c1 x has |1 - x z0(x)^2| <= 0.417
   on [0.1, 1], the range of s / c.
 * Last doubling's inverse: the same split start and steps, then FP64
@@ -76,6 +79,53 @@ def test_quadratic_inverse_start_is_minimax():
     assert np.allclose(r, (4 * x**3 - 3 * x) / -99.0, atol=1e-15)
 
 
+def inv_start4():
+    m = re.search(r"kInvStart4\[5\]\s*=\s*\{([^}]*)\}", SRC)
+    out = []
+    for v in m.group(1).split(","):
+        num, den = v.strip().split("/")
+        out.append(float(np.float32(float(num.strip().rstrip("f")) / float(den.strip().rstrip("f")))))
+    return out
+
+
+def chebyshev_t(n, x):
+    return np.cos(n * np.arccos(np.clip(x, -1.0, 1.0)))
+
+
+def test_quartic_inverse_start_is_minimax():
+    c0, c1, c2, c3, c4 = inv_start4()
+    # exact rational coefficients: a y4(a) = 1 + T5(4a - 3) / 3363, T5(-3) = -3363
+    from fractions import Fraction as Fr
+    num = [23780, -66240, 90880, -61440, 16384]
+    a_r = [Fr(1, 2) + Fr(k, 16) for k in range(9)]
+    for a in a_r:
+        x = 4 * a - 3
+        t5 = 16 * x**5 - 20 * x**3 + 5 * x
+        assert a * sum(Fr(c, 3363) * a**i for i, c in enumerate(num)) == 1 + t5 / 3363
+    a = np.linspace(0.5, 1.0, 200001)
+    y = (c4 * a * a + c3 * a + c2) * a * a + c1 * a + c0       # the kernel's two products
+    r = 1.0 - a * y
+    # FP32 coefficients (|c| up to 27) move the residual by at most ~5e-6
+    assert np.abs(r).max() <= 1.0 / 3363.0 + 5e-6
+    assert np.allclose(r, chebyshev_t(5, 4.0 * a - 3.0) / -3363.0, atol=5e-6)
+    # six alternating extrema of size 1/3363 at the Chebyshev points
+    # (equioscillation of the minimax residual)
+    a_ext = 0.5 + 0.25 * (1.0 + np.cos(np.pi * np.arange(6) / 5))
+    r_ext = 1.0 - a_ext * np.polyval([c4, c3, c2, c1, c0], a_ext)
+    assert np.all(np.abs(np.abs(r_ext) - 1.0 / 3363.0) < 5e-6)
+    assert np.all(np.sign(r_ext[:-1]) != np.sign(r_ext[1:]))
+    # one Newton-Schulz step squares it below the split products' rounding
+    assert (np.abs(r).max()) ** 2 < 9.3e-8
+    # plausible mistakes fail: a sign slip in c3, or the quadratic's scale
+    y_bad = (c4 * a * a - c3 * a + c2) * a * a + c1 * a + c0
+    assert np.abs(1.0 - a * y_bad).max() > 1e-2
+    y_bad = (c4 * a * a + c3 * a + c2) * a * a + c1 * a + c0 * 99.0 / 3363.0
+    assert np.abs(1.0 - a * y_bad).max() > 1e-2
+    # the library's default: the quartic with one step
+    assert "int mixed_inv_deg = 4;" in open(os.path.join(ROOT, "paper_2606_03140_amd", "csrc",
+                                                        "gdm_internal.h")).read()
+
+
 def test_inverse_sqrt_start_bound():
     m = re.search(r"kZ0a\s*=\s*([-0-9.e]+)f,\s*kZ0b\s*=\s*([-0-9.e]+)f", SRC)
     c0, c1 = float(np.float32(m.group(1))), float(np.float32(m.group(2)))
@@ -89,7 +139,9 @@ def test_final_doubling_inverse_start():
     # (the quadratic start y0 = (420 - 576 a + 256 a^2) / 99 and the split
     # Newton-Schulz steps), then FP64 steps: one for FP16 pairs, two for BF16
     body = SRC[SRC.index("static int last_doubling_f64"):SRC.index("// FP64 core traces of the last pass")]
-    assert "256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f" in body
+    start = SRC[SRC.index("static int inv_start"):SRC.index("// Doubling history for the charge response")]
+    assert "inv_start(ctx, As, Ys, Rs, Ysb, 0, skip)" in body
+    assert "256.0f / 99.0f, -576.0f / 99.0f, 420.0f / 99.0f" in start and "kInvStart4" in start
     assert "final_ns = P.precision == GDM_MIXED_BF16 ? 2 : 1" in body
     assert "ctx->mixed_ns_inv" in body
     # a Newton-Schulz step Y' = Y (2I - A Y) maps the residual I - A Y to its
