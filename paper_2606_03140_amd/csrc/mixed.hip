@@ -648,6 +648,7 @@ __global__ void __launch_bounds__(256) k_pack_core(const SubDesc* __restrict__ d
 // ------------------------------------------------------- elementwise kernels
 constexpr int kEw = 256;
 constexpr double kZResidMax = 1e-3;   // largest |Z s Z - I| entry accepted before refinement
+constexpr double kRefineSig = 65536.0;  // scale of E and T as split operands in the refinement
 
 __device__ __forceinline__ double block_reduce_max(double v, double* red) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -781,8 +782,11 @@ __global__ void __launch_bounds__(256) k_scale_sym_to_f64(const SubDesc* __restr
 // dst <- src^T over every subgraph's P x P tile, on the upper-tile list (both
 // tiles of a pair through LDS); FP64 (dst64) and, when dsplit.hi is set, the
 // split halves and FP32 copy of the transpose; copy (nullable) <- src
+// With add: src + add * scale_s^-1/2 * inv_sig in place of src (copy may
+// then be src itself: each element is read and written by one thread only).
 __global__ void __launch_bounds__(256) k_transpose64(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
-                                                    const double* __restrict__ src, double* __restrict__ copy,
+                                                    const double* src, double* copy, const float* __restrict__ add,
+                                                    const double* __restrict__ scale, double inv_sig,
                                                     double* __restrict__ dst64, SplitMat dsplit,
                                                     const int* __restrict__ skip) {
     __shared__ double a[64][65], b2[64][65];
@@ -792,11 +796,12 @@ __global__ void __launch_bounds__(256) k_transpose64(const SubDesc* __restrict__
     const SubDesc d = desc[tl.x];
     const int P = d.ld;
     const int I0 = tl.y * 64, J0 = tl.z * 64;
+    const double f = add ? inv_sig / sqrt(scale[tl.x]) : 0.0;
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int r = e >> 6, c = e & 63;
         const int64_t j1 = d.off2 + (int64_t)(I0 + r) * P + J0 + c, j2 = d.off2 + (int64_t)(J0 + r) * P + I0 + c;
-        a[r][c] = src[j1];
-        b2[r][c] = src[j2];
+        a[r][c] = add ? src[j1] + f * (double)add[j1] : src[j1];
+        b2[r][c] = add ? src[j2] + f * (double)add[j2] : src[j2];
         if (copy) {                     // src as it is (both tiles of the pair)
             copy[j1] = a[r][c];
             copy[j2] = b2[r][c];
@@ -900,8 +905,12 @@ __global__ void k_sum_parts(int n_sub, const double* __restrict__ part, double* 
 // Largest |E_ij| = |(Z s Z - I)_ij| over every subgraph's n x n block, as an
 // atomic max on the bit pattern (non-negative doubles order as integers; NaN
 // counts as infinite).
+// max |E_ij| over the subgraph's n x n block (atomic, as the bit pattern of a
+// non-negative double); with Es.hi, sig E is also written as split operands
+// over the whole padded strip (for the refinement's split products)
 __global__ void __launch_bounds__(kEw) k_resid_max(const SubDesc* __restrict__ desc, const double* __restrict__ E,
-                                                  unsigned long long* __restrict__ out, const int* __restrict__ skip) {
+                                                  unsigned long long* __restrict__ out, SplitMat Es, double sig,
+                                                  const int* __restrict__ skip) {
     if (skip && *skip) return;
     const SubDesc d = desc[blockIdx.x];
     const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
@@ -909,10 +918,12 @@ __global__ void __launch_bounds__(kEw) k_resid_max(const SubDesc* __restrict__ d
     double m = 0.0;
     for (int e = threadIdx.x; e < 64 * P; e += kEw) {
         const int i = r0 + e / P, j = e % P;
+        const int64_t idx = d.off2 + (int64_t)i * P + j;
         if (i < n && j < n) {
-            const double v = fabs(E[d.off2 + (int64_t)i * P + j]);
+            const double v = fabs(E[idx]);
             m = v == v ? fmax(m, v) : INFINITY;
         }
+        if (Es.hi) store_split(Es, idx, (float)(sig * E[idx]));
     }
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
@@ -1705,7 +1716,7 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
                 hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, ctx->stream, emax_d, sk);
                 GDM_LAUNCH_CHECK(ctx);
                 hipLaunchKernelGGL(k_resid_max, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, E,
-                                   (unsigned long long*)emax_d, sk);
+                                   (unsigned long long*)emax_d, hl(slot(ctx, SL_A)), kRefineSig, sk);
             }
             GDM_LAUNCH_CHECK(ctx);
             if (dev) {
@@ -1729,6 +1740,7 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
             std::swap(Z, Z2);
             ++ctx->mixed_ns_z_used;
         }
+        const SplitMat W{slot(ctx, SL_X).f, nullptr, nullptr, 0};
         if (!orth) {
             // third-order refinement Z1 = Z (I + E)^-1/2 = Z (I - E/2 + 3/8 E^2 + O(E^3)) with
             // E = Z s Z - I for the symmetric Z: T = 3/8 E^2 - E/2 is a polynomial in E, so
@@ -1738,19 +1750,27 @@ int gdm_mixed_find_mu(gdm_ctx* ctx, const gdm_system* sys, const gdm_subgraphs* 
             // Z1^T h Z1 and Z1 X Z1^T (D does not depend on which factor of s^-1 is used).
             // A symmetric step would leave those errors in place: Z s Z - I stays at the
             // FP32 level (1e-7) with a negative trace, a bias of the electron count.
-            double* T64 = fp64_region(ctx, 3);
-            GDM_TRY(gemm64_dd(ctx, E, E, E, T64, 0.375, -0.5, 0.0, 1));        // T = 3/8 E^2 - E/2
-            GDM_TRY(gemm64_dd(ctx, Z64, T64, Z64, F, 1.0, 1.0, 0.0, 0));      // F <- Z + Z T (all tiles)
+            // Only E needs FP64 (a difference from I); the correction Z T is below
+            // |E| <= 1e-3 (the guard) and needs ~1e-9 relative accuracy, which the split
+            // products give: with sig E as split operands (written by k_resid_max, sig =
+            // 2^16 keeping |E| down to 1e-9 in normal FP16), sig T = 3/(8 sig) (sig E)^2 -
+            // (sig E)/2 and W = Z (sig T) on the split products, and
+            // Z1 = Z64 + W / (sig sqrt(c)) in FP64 by the transpose pass below.  A rounding
+            // error of T or W perturbs Z1^T s Z1 by its own size (~1e-13), not by |E|^2.
+            const SplitMat Es = hl(slot(ctx, SL_A)), Ts = hl(slot(ctx, SL_R));
+            GDM_TRY(gemm(ctx, Es, Es, none(), Ts, Es, (float)(0.375 / kRefineSig), -0.5f, 0.0f, "ns_gemm", 1, 0));
+            GDM_TRY(gemm(ctx, Z, Ts, W, none(), none(), 1.0f, 0.0f, 0.0f, "ns_gemm", 0));
         }
-        // Z1 into Z64 (from F after the refinement), Z1^T in FP64 (the
-        // density's right factor) and as split operands with an FP32 copy (the
-        // split products of h_perp and of the response), in one pass
+        // Z1 into Z64 (in place), Z1^T in FP64 (the density's right factor) and as
+        // split operands with an FP32 copy (the split products of h_perp and of the
+        // response), in one pass
         Z = slot(ctx, SL_Z);
         {
             GDM_TIMED(ctx, "refine64");
             hipLaunchKernelGGL(k_transpose64, dim3((unsigned)ctx->mixed_tiles_sym), dim3(256), 0, ctx->stream, desc,
-                               (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles, orth ? Z64 : F,
-                               orth ? (double*)nullptr : Z64, z64t(ctx), Z, (const int*)nullptr);
+                               (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles, (const double*)Z64,
+                               orth ? (double*)nullptr : Z64, orth ? (const float*)nullptr : (const float*)W.f, scale,
+                               1.0 / kRefineSig, z64t(ctx), Z, (const int*)nullptr);
         }
         GDM_LAUNCH_CHECK(ctx);
         GDM_TRY(gemm64_core<double>(ctx, s64, Z64, F, "refine64"));   // V = s[core,:] Z
