@@ -486,12 +486,28 @@ __device__ __forceinline__ void load8(const float* p, double* v) {
     v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w; v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
 }
 
+// Optional parts of an FP64 product: B + badd_scale * badd as the B operand
+// (an FP32 correction added as the operand is staged), and the result also
+// (or only, C = nullptr) written as split operands of cs_scale * C.
+struct G64Extra {
+    const float* badd;
+    double badd_scale;
+    SplitMat cs;
+    double cs_scale;
+};
+
+__device__ __forceinline__ void add8(const float* p, double s, double* v) {
+    const float4 x = *(const float4*)p, y = *(const float4*)(p + 4);
+    v[0] += s * x.x; v[1] += s * x.y; v[2] += s * x.z; v[3] += s * x.w;
+    v[4] += s * y.x; v[5] += s * y.y; v[6] += s * y.z; v[7] += s * y.w;
+}
+
 template <typename TA, typename TB, bool SYM>
 __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
                                                const TA* __restrict__ A, const TB* __restrict__ B,
                                                const double* __restrict__ Cin, double* __restrict__ C,
                                                double alpha, double beta, double gamma,
-                                               const int* __restrict__ skip) {
+                                               const int* __restrict__ skip, G64Extra x64) {
     __shared__ __align__(16) double lds[kG64Lds];
     if (skip && *skip) return;
     double* sA = lds;                        // [64][kA64Row]
@@ -511,9 +527,11 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
     const int rb = t >> 3, cb = (t & 7) * 8;
     const TA* pa = A + base + (int64_t)(m0 + ra) * P + ca;
     const TB* pb = B + base + (int64_t)rb * P + n0 + cb;
+    const float* pba = x64.badd ? x64.badd + base + (int64_t)rb * P + n0 + cb : nullptr;
     double va[8], vb[8];
     load8(pa, va);
     load8(pb, vb);
+    if (pba) add8(pba, x64.badd_scale, vb);
     double4v acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = double4v{0.0, 0.0, 0.0, 0.0};
@@ -528,6 +546,7 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
         if (k0 + kK64 < P) {
             load8(pa + k0 + kK64, va);
             load8(pb + (int64_t)(k0 + kK64) * P, vb);
+            if (pba) add8(pba + (int64_t)(k0 + kK64) * P, x64.badd_scale, vb);
         }
 #pragma unroll
         for (int kk = 0; kk < kK64; kk += 4) {
@@ -560,7 +579,8 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
         double v = alpha * x;
         if (Cin) v += beta * Cin[idx];
         if (m0 + m == n0 + n) v += gamma;
-        C[idx] = v;
+        if (C) C[idx] = v;
+        if (x64.cs.hi) store_split(x64.cs, idx, (float)(x64.cs_scale * v));
     }
     if (SYM && !diag)
         for (int e = t; e < 64 * 64; e += 256) {
@@ -568,7 +588,8 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
             const int64_t idx = base + (int64_t)(n0 + nn) * P + m0 + mm;
             double v = alpha * sC[mm * kC64Row + nn];
             if (Cin) v += beta * Cin[idx];
-            C[idx] = v;
+            if (C) C[idx] = v;
+            if (x64.cs.hi) store_split(x64.cs, idx, (float)(x64.cs_scale * v));
         }
 }
 
@@ -649,6 +670,7 @@ __global__ void __launch_bounds__(256) k_pack_core(const SubDesc* __restrict__ d
 constexpr int kEw = 256;
 constexpr double kZResidMax = 1e-3;   // largest |Z s Z - I| entry accepted before refinement
 constexpr double kRefineSig = 65536.0;  // scale of E and T as split operands in the refinement
+constexpr double kLastSig = 16384.0;    // scale of the last doubling's residual I - A Y as split operands
 
 __device__ __forceinline__ double block_reduce_max(double v, double* red) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -1480,16 +1502,17 @@ static double* z64t(gdm_ctx* ctx) { return (double*)ctx->b[BUF_L].p + 8 * ctx->p
 // FP64 products on all tiles (sym = 0) or on the upper tiles with mirrored
 // output (sym = 1, symmetric products only)
 static int gemm64_dd(gdm_ctx* ctx, const double* A, const double* B, const double* Cin, double* C, double alpha,
-                     double beta, double gamma, int sym, const int* skip = nullptr, const char* tag = "refine64") {
+                     double beta, double gamma, int sym, const int* skip = nullptr, const char* tag = "refine64",
+                     G64Extra x64 = G64Extra{nullptr, 0.0, SplitMat{nullptr, nullptr, nullptr, 0}, 0.0}) {
     GDM_TIMED(ctx, tag);
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + (sym ? ctx->mixed_tiles : 0);
     const unsigned nt = (unsigned)(sym ? ctx->mixed_tiles_sym : ctx->mixed_tiles);
     if (sym)
         hipLaunchKernelGGL((k_gemm64<double, double, true>), dim3(nt), dim3(256), 0, ctx->stream,
-                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip);
+                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip, x64);
     else
         hipLaunchKernelGGL((k_gemm64<double, double, false>), dim3(nt), dim3(256), 0, ctx->stream,
-                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip);
+                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip, x64);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }
@@ -1500,7 +1523,8 @@ static int gemm64_core(gdm_ctx* ctx, const double* A, const TB* B, double* C, co
     GDM_TIMED(ctx, tag);
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles + ctx->mixed_tiles_sym;
     hipLaunchKernelGGL((k_gemm64<double, TB, false>), dim3((unsigned)ctx->mixed_tiles_core), dim3(256), 0, ctx->stream,
-                       (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, (const double*)nullptr, C, 1.0, 0.0, 0.0, skip);
+                       (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, (const double*)nullptr, C, 1.0, 0.0, 0.0, skip,
+                       G64Extra{nullptr, 0.0, SplitMat{nullptr, nullptr, nullptr, 0}, 0.0});
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }
@@ -1569,13 +1593,26 @@ static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const in
     GDM_LAUNCH_CHECK(ctx);
     double* Y = Ya;
     const int final_ns = P.precision == GDM_MIXED_BF16 ? 2 : 1;
-    for (int k = 0; k < final_ns; ++k) {
+    for (int k = 0; k + 1 < final_ns; ++k) {
         GDM_TRY(gemm64_dd(ctx, A, Y, nullptr, R, -1.0, 0.0, 2.0, 1, skip, "last64"));   // R = 2I - A Y
         double* Yn = Y == Ya ? Yb : Ya;
         GDM_TRY(gemm64_dd(ctx, Y, R, nullptr, Yn, 1.0, 0.0, 0.0, 1, skip, "last64"));   // Y <- Y R
         Y = Yn;
     }
-    GDM_TRY(gemm64_dd(ctx, X2, Y, nullptr, X, 1.0, 0.0, 0.0, 1, skip, "last64"));     // X <- X2 Y
+    // The last step as a correction, Y R = Y + Y rho with rho = I - A Y: only rho
+    // needs FP64 (a residual of ~1e-7, ~1e-10 after an FP64 step for BF16 pairs);
+    // Y rho needs ~1e-7 relative accuracy for an error of ~1e-14, which the split
+    // products give.  rho leaves its FP64 product as split operands of
+    // kLastSig rho (no FP64 copy), W = Y (kLastSig rho) on the split products
+    // (with the split Y: it differs from the FP64 Y by ~1e-7 relative, which
+    // changes Y rho by ~1e-14), and X2 (Y + W / kLastSig) is one FP64 product
+    // whose B operand adds the correction as it is staged.
+    const SplitMat W{slot(ctx, SL_Z2).f, nullptr, nullptr, 0};
+    GDM_TRY(gemm64_dd(ctx, A, Y, nullptr, nullptr, -1.0, 0.0, 1.0, 1, skip, "last64",
+                      G64Extra{nullptr, 0.0, hl(Rs), kLastSig}));                       // rho = I - A Y
+    GDM_TRY(gemm(ctx, Ys, hl(Rs), W, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, 0, skip));
+    GDM_TRY(gemm64_dd(ctx, X2, Y, nullptr, X, 1.0, 0.0, 0.0, 1, skip, "last64",
+                      G64Extra{W.f, 1.0 / kLastSig, none(), 0.0}));                  // X <- X2 (Y + Y rho)
     GDM_TIMED(ctx, "last64");
     if (Yrec.hi) {
         hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, n4, Y, Yrec, skip);
