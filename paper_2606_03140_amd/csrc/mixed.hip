@@ -791,13 +791,17 @@ __global__ void __launch_bounds__(256) k_scale_sym_to_f64(const SubDesc* __restr
         bt[r][c] = Zf[d.off2 + (int64_t)(J0 + r) * P + I0 + c];
     }
     __syncthreads();
+    // both tiles written row by row (coalesced): element (I0 + r, J0 + c) from
+    // a[r][c] and its mirror partner, element (J0 + r, I0 + c) from bt[r][c] and
+    // its partner a[c][r]; the average is the same expression for both
+    // members of a pair, so a diagonal tile gets one value per element
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         const int r = e >> 6, c = e & 63;
-        const int i = I0 + r, j = J0 + c;
-        const double v = 0.5 * ((double)a[r][c] + (double)bt[c][r]);
-        const bool in = i < n && j < n;
-        Z64[d.off2 + (int64_t)i * P + j] = in ? v * f : (double)a[r][c];
-        Z64[d.off2 + (int64_t)j * P + i] = in ? v * f : (double)bt[c][r];
+        const bool in1 = I0 + r < n && J0 + c < n, in2 = J0 + r < n && I0 + c < n;
+        const double v1 = 0.5 * ((double)a[r][c] + (double)bt[c][r]);
+        const double v2 = 0.5 * ((double)a[c][r] + (double)bt[r][c]);
+        Z64[d.off2 + (int64_t)(I0 + r) * P + J0 + c] = in1 ? v1 * f : (double)a[r][c];
+        Z64[d.off2 + (int64_t)(J0 + r) * P + I0 + c] = in2 ? v2 * f : (double)bt[r][c];
     }
 }
 
@@ -1501,17 +1505,18 @@ static double* z64t(gdm_ctx* ctx) { return (double*)ctx->b[BUF_L].p + 8 * ctx->p
 
 // FP64 products on all tiles (sym = 0) or on the upper tiles with mirrored
 // output (sym = 1, symmetric products only)
-static int gemm64_dd(gdm_ctx* ctx, const double* A, const double* B, const double* Cin, double* C, double alpha,
+template <typename TB>
+static int gemm64_dd(gdm_ctx* ctx, const double* A, const TB* B, const double* Cin, double* C, double alpha,
                      double beta, double gamma, int sym, const int* skip = nullptr, const char* tag = "refine64",
                      G64Extra x64 = G64Extra{nullptr, 0.0, SplitMat{nullptr, nullptr, nullptr, 0}, 0.0}) {
     GDM_TIMED(ctx, tag);
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + (sym ? ctx->mixed_tiles : 0);
     const unsigned nt = (unsigned)(sym ? ctx->mixed_tiles_sym : ctx->mixed_tiles);
     if (sym)
-        hipLaunchKernelGGL((k_gemm64<double, double, true>), dim3(nt), dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL((k_gemm64<double, TB, true>), dim3(nt), dim3(256), 0, ctx->stream,
                            (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip, x64);
     else
-        hipLaunchKernelGGL((k_gemm64<double, double, false>), dim3(nt), dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL((k_gemm64<double, TB, false>), dim3(nt), dim3(256), 0, ctx->stream,
                            (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip, x64);
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
@@ -1580,17 +1585,23 @@ static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const in
     const SplitMat As = slot(ctx, SL_A), Rs = slot(ctx, SL_R), Ysa = slot(ctx, SL_Y), Ysb = slot(ctx, SL_YI);
     SplitMat Ys = Ysa;
     GDM_TRY(inv_start(ctx, As, Ys, Rs, Ysb, 0, skip));
+    // FP16 pairs: the last split step also keeps its FP32 result Yf (in the FP32
+    // copy of SL_X, free until this doubling's output), and Yf is the Y of the
+    // FP64 steps below, read as FP32 operands (no FP64 copy of Y)
+    const bool yf = P.precision != GDM_MIXED_BF16 && ctx->mixed_ns_inv > 0;
+    float* Yf = slot(ctx, SL_X).f;
     for (int k = 0; k < ctx->mixed_ns_inv; ++k) {
         GDM_TRY(gemm(ctx, As, Ys, none(), hl(Rs), none(), -1.0f, 0.0f, 2.0f, "foe_gemm", 1, 0, skip));
         const SplitMat Yn = Ys.hi == Ysa.hi ? Ysb : Ysa;
-        GDM_TRY(gemm(ctx, Ys, Rs, hl(Yn), none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, 0, skip));
+        const SplitMat Yo = (yf && k + 1 == ctx->mixed_ns_inv) ? SplitMat{Yf, Yn.hi, Yn.lo, Yn.bf} : hl(Yn);
+        GDM_TRY(gemm(ctx, Ys, Rs, Yo, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, 0, skip));
         Ys = Yn;
     }
-    {
+    if (!yf) {
         GDM_TIMED(ctx, "last64");
         hipLaunchKernelGGL(k_split_to_f64, dim3(4096), dim3(256), 0, ctx->stream, n4, hl(Ys), Ya, skip);
+        GDM_LAUNCH_CHECK(ctx);
     }
-    GDM_LAUNCH_CHECK(ctx);
     double* Y = Ya;
     const int final_ns = P.precision == GDM_MIXED_BF16 ? 2 : 1;
     for (int k = 0; k + 1 < final_ns; ++k) {
@@ -1608,14 +1619,22 @@ static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const in
     // changes Y rho by ~1e-14), and X2 (Y + W / kLastSig) is one FP64 product
     // whose B operand adds the correction as it is staged.
     const SplitMat W{slot(ctx, SL_Z2).f, nullptr, nullptr, 0};
-    GDM_TRY(gemm64_dd(ctx, A, Y, nullptr, nullptr, -1.0, 0.0, 1.0, 1, skip, "last64",
-                      G64Extra{nullptr, 0.0, hl(Rs), kLastSig}));                       // rho = I - A Y
+    const G64Extra to_rho{nullptr, 0.0, hl(Rs), kLastSig}, add_w{W.f, 1.0 / kLastSig, none(), 0.0};
+    if (yf)
+        GDM_TRY(gemm64_dd(ctx, A, (const float*)Yf, nullptr, nullptr, -1.0, 0.0, 1.0, 1, skip, "last64", to_rho));
+    else
+        GDM_TRY(gemm64_dd(ctx, A, (const double*)Y, nullptr, nullptr, -1.0, 0.0, 1.0, 1, skip, "last64", to_rho));
     GDM_TRY(gemm(ctx, Ys, hl(Rs), W, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, 0, skip));
-    GDM_TRY(gemm64_dd(ctx, X2, Y, nullptr, X, 1.0, 0.0, 0.0, 1, skip, "last64",
-                      G64Extra{W.f, 1.0 / kLastSig, none(), 0.0}));                  // X <- X2 (Y + Y rho)
+    if (yf)       // X <- X2 (Y + Y rho)
+        GDM_TRY(gemm64_dd(ctx, X2, (const float*)Yf, nullptr, X, 1.0, 0.0, 0.0, 1, skip, "last64", add_w));
+    else
+        GDM_TRY(gemm64_dd(ctx, X2, (const double*)Y, nullptr, X, 1.0, 0.0, 0.0, 1, skip, "last64", add_w));
     GDM_TIMED(ctx, "last64");
     if (Yrec.hi) {
-        hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, n4, Y, Yrec, skip);
+        if (yf)
+            hipLaunchKernelGGL(k_copy_split, dim3(2048), dim3(256), 0, ctx->stream, n4, hl(Ys), Yrec, skip);
+        else
+            hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, n4, Y, Yrec, skip);
         GDM_LAUNCH_CHECK(ctx);
     }
     hipLaunchKernelGGL(k_z64_to_split, dim3(4096), dim3(256), 0, ctx->stream, n4, X, slot(ctx, SL_X), skip);
