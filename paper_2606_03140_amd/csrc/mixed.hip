@@ -494,6 +494,7 @@ struct G64Extra {
     double badd_scale;
     SplitMat cs;
     double cs_scale;
+    double a_shift;      // A - a_shift I as the A operand (subtracted on the diagonal as it is staged)
 };
 
 __device__ __forceinline__ void add8(const float* p, double s, double* v) {
@@ -502,7 +503,7 @@ __device__ __forceinline__ void add8(const float* p, double s, double* v) {
     v[4] += s * y.x; v[5] += s * y.y; v[6] += s * y.z; v[7] += s * y.w;
 }
 
-template <typename TA, typename TB, bool SYM>
+template <typename TA, typename TB, bool SYM, bool SHIFT = false>
 __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc, const int4* __restrict__ tiles,
                                                const TA* __restrict__ A, const TB* __restrict__ B,
                                                const double* __restrict__ Cin, double* __restrict__ C,
@@ -529,7 +530,14 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
     const TB* pb = B + base + (int64_t)rb * P + n0 + cb;
     const float* pba = x64.badd ? x64.badd + base + (int64_t)rb * P + n0 + cb : nullptr;
     double va[8], vb[8];
+    // SHIFT: the A slab's element (m0 + ra, k + ca + u) is on the diagonal for
+    // u = m0 + ra - k - ca
     load8(pa, va);
+    if constexpr (SHIFT) {
+        const int q = m0 + ra - ca;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) va[u] -= u == q ? x64.a_shift : 0.0;
+    }
     load8(pb, vb);
     if (pba) add8(pba, x64.badd_scale, vb);
     double4v acc[2][2];
@@ -545,6 +553,11 @@ __global__ void __launch_bounds__(256) k_gemm64(const SubDesc* __restrict__ desc
         __syncthreads();
         if (k0 + kK64 < P) {
             load8(pa + k0 + kK64, va);
+            if constexpr (SHIFT) {
+                const int q = m0 + ra - (k0 + kK64) - ca;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) va[u] -= u == q ? x64.a_shift : 0.0;
+            }
             load8(pb + (int64_t)(k0 + kK64) * P, vb);
             if (pba) add8(pba + (int64_t)(k0 + kK64) * P, x64.badd_scale, vb);
         }
@@ -1057,31 +1070,6 @@ __global__ void __launch_bounds__(256) k_split_to_f64(int64_t n4, SplitMat X, do
     }
 }
 
-// A <- 2 X2 - 2 X + I over the padded P x P tile (padding: X = X2 = 0, so A = I
-// there), in FP64 and as split operands As (from its FP32 rounding)
-__global__ void __launch_bounds__(kEw) k_doubling_a(const SubDesc* __restrict__ desc, const double* __restrict__ X,
-                                                   const double* __restrict__ X2, double* __restrict__ A, SplitMat As,
-                                                   const int* __restrict__ skip) {
-    if (skip && *skip) return;
-    const SubDesc d = desc[blockIdx.x];
-    const int P = d.ld, r0 = blockIdx.y * 64;
-    if (r0 >= P) return;
-    const int q4 = P >> 2;
-    for (int e = threadIdx.x; e < 64 * q4; e += kEw) {
-        const int i = r0 + e / q4, j0 = (e % q4) * 4;
-        const int64_t idx = d.off2 + (int64_t)i * P + j0;
-        const double4 x = *(const double4*)(X + idx), x2 = *(const double4*)(X2 + idx);
-        double4 a = make_double4(2.0 * x2.x - 2.0 * x.x, 2.0 * x2.y - 2.0 * x.y, 2.0 * x2.z - 2.0 * x.z,
-                                 2.0 * x2.w - 2.0 * x.w);
-        if (i == j0) a.x += 1.0;
-        if (i == j0 + 1) a.y += 1.0;
-        if (i == j0 + 2) a.z += 1.0;
-        if (i == j0 + 3) a.w += 1.0;
-        *(double4*)(A + idx) = a;
-        store4(As, idx, make_float4((float)a.x, (float)a.y, (float)a.z, (float)a.w));
-    }
-}
-
 // ------------------------------------------------- chemical-potential search
 // Parameters of the search, fixed per gdm_find_mu call.
 struct MuCfg {
@@ -1508,11 +1496,14 @@ static double* z64t(gdm_ctx* ctx) { return (double*)ctx->b[BUF_L].p + 8 * ctx->p
 template <typename TB>
 static int gemm64_dd(gdm_ctx* ctx, const double* A, const TB* B, const double* Cin, double* C, double alpha,
                      double beta, double gamma, int sym, const int* skip = nullptr, const char* tag = "refine64",
-                     G64Extra x64 = G64Extra{nullptr, 0.0, SplitMat{nullptr, nullptr, nullptr, 0}, 0.0}) {
+                     G64Extra x64 = G64Extra{nullptr, 0.0, SplitMat{nullptr, nullptr, nullptr, 0}, 0.0, 0.0}) {
     GDM_TIMED(ctx, tag);
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + (sym ? ctx->mixed_tiles : 0);
     const unsigned nt = (unsigned)(sym ? ctx->mixed_tiles_sym : ctx->mixed_tiles);
-    if (sym)
+    if (sym && x64.a_shift != 0.0)
+        hipLaunchKernelGGL((k_gemm64<double, TB, true, true>), dim3(nt), dim3(256), 0, ctx->stream,
+                           (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip, x64);
+    else if (sym)
         hipLaunchKernelGGL((k_gemm64<double, TB, true>), dim3(nt), dim3(256), 0, ctx->stream,
                            (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, Cin, C, alpha, beta, gamma, skip, x64);
     else
@@ -1529,7 +1520,7 @@ static int gemm64_core(gdm_ctx* ctx, const double* A, const TB* B, double* C, co
     const int4* tl = (const int4*)ctx->b[BUF_TILES].p + ctx->mixed_tiles + ctx->mixed_tiles_sym;
     hipLaunchKernelGGL((k_gemm64<double, TB, false>), dim3((unsigned)ctx->mixed_tiles_core), dim3(256), 0, ctx->stream,
                        (const SubDesc*)ctx->b[BUF_DESC].p, tl, A, B, (const double*)nullptr, C, 1.0, 0.0, 0.0, skip,
-                       G64Extra{nullptr, 0.0, SplitMat{nullptr, nullptr, nullptr, 0}, 0.0});
+                       G64Extra{nullptr, 0.0, SplitMat{nullptr, nullptr, nullptr, 0}, 0.0, 0.0});
     GDM_LAUNCH_CHECK(ctx);
     return GDM_OK;
 }
@@ -1537,8 +1528,9 @@ static int gemm64_core(gdm_ctx* ctx, const double* A, const TB* B, double* C, co
 static double* fp64_region(gdm_ctx* ctx, int k) { return (double*)ctx->b[BUF_L].p + (int64_t)k * ctx->plan.tot2; }
 
 // The last doubling of a pass in FP64 on the matrix cores (the final
-// refinement step of the expansion): X2 = X X, A = 2 X2 - 2 X + I in FP64,
-// Y = A^-1, X <- X2 Y.  The inverse starts on the split products: A as split
+// refinement step of the expansion): A = 2 X^2 - 2 X + I in FP64 (one
+// product, which also writes A as split operands), Y = A^-1, and
+// X <- X^2 Y = I/2 + (X - I/2) Y.  The inverse starts on the split products: A as split
 // operands, the minimax start of the other doublings (the quartic of
 // kInvStart4 with one split Newton-Schulz step by default, or the quadratic
 // (420 I - 576 A + 256 A^2)/99 with two) leave I - A Y at the split
@@ -1562,8 +1554,8 @@ static double* fp64_region(gdm_ctx* ctx, int k) { return (double*)ctx->b[BUF_L].
 static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const int* skip) {
     const Plan& P = ctx->plan;
     const SubDesc* desc = (const SubDesc*)ctx->b[BUF_DESC].p;
-    double* X = fp64_region(ctx, 5);
-    double* X2 = fp64_region(ctx, 6);
+    double* X = fp64_region(ctx, 5);        // the result
+    double* Xi = fp64_region(ctx, 6);       // the input
     double* A = fp64_region(ctx, 7);
     double* Ya = fp64_region(ctx, 4);
     double* Yb = fp64_region(ctx, 3);
@@ -1571,16 +1563,12 @@ static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const in
     const int64_t n4 = P.tot2 / 4;
     {
         GDM_TIMED(ctx, "last64");
-        hipLaunchKernelGGL(k_split_to_f64, dim3(4096), dim3(256), 0, ctx->stream, n4, Xin, X, skip);
+        hipLaunchKernelGGL(k_split_to_f64, dim3(4096), dim3(256), 0, ctx->stream, n4, Xin, Xi, skip);
     }
     GDM_LAUNCH_CHECK(ctx);
-    GDM_TRY(gemm64_dd(ctx, X, X, nullptr, X2, 1.0, 0.0, 0.0, 1, skip, "last64"));
-    {
-        GDM_TIMED(ctx, "last64");
-        hipLaunchKernelGGL(k_doubling_a, strip_grid(P), dim3(kEw), 0, ctx->stream, desc, X, X2, A, slot(ctx, SL_A),
-                           skip);
-    }
-    GDM_LAUNCH_CHECK(ctx);
+    // A = 2 X^2 - 2 X + I by one product, in FP64 and as split operands
+    GDM_TRY(gemm64_dd(ctx, Xi, (const double*)Xi, Xi, A, 2.0, -2.0, 1.0, 1, skip, "last64",
+                      G64Extra{nullptr, 0.0, slot(ctx, SL_A), 1.0, 0.0}));
     // split start and Newton-Schulz steps (whole storage: A comes whole)
     const SplitMat As = slot(ctx, SL_A), Rs = slot(ctx, SL_R), Ysa = slot(ctx, SL_Y), Ysb = slot(ctx, SL_YI);
     SplitMat Ys = Ysa;
@@ -1619,16 +1607,19 @@ static int last_doubling_f64(gdm_ctx* ctx, SplitMat Xin, SplitMat Yrec, const in
     // changes Y rho by ~1e-14), and X2 (Y + W / kLastSig) is one FP64 product
     // whose B operand adds the correction as it is staged.
     const SplitMat W{slot(ctx, SL_Z2).f, nullptr, nullptr, 0};
-    const G64Extra to_rho{nullptr, 0.0, hl(Rs), kLastSig}, add_w{W.f, 1.0 / kLastSig, none(), 0.0};
+    // X2 A^-1 = I/2 + (X - I/2) A^-1 (2 X^2 = A + 2 X - I): the product takes X
+    // with I/2 subtracted on its diagonal as it is staged and adds I/2, so
+    // neither X^2 nor X - I/2 is stored
+    const G64Extra to_rho{nullptr, 0.0, hl(Rs), kLastSig, 0.0}, add_w{W.f, 1.0 / kLastSig, none(), 0.0, 0.5};
     if (yf)
         GDM_TRY(gemm64_dd(ctx, A, (const float*)Yf, nullptr, nullptr, -1.0, 0.0, 1.0, 1, skip, "last64", to_rho));
     else
         GDM_TRY(gemm64_dd(ctx, A, (const double*)Y, nullptr, nullptr, -1.0, 0.0, 1.0, 1, skip, "last64", to_rho));
     GDM_TRY(gemm(ctx, Ys, hl(Rs), W, none(), none(), 1.0f, 0.0f, 0.0f, "foe_gemm", 1, 0, skip));
-    if (yf)       // X <- X2 (Y + Y rho)
-        GDM_TRY(gemm64_dd(ctx, X2, (const float*)Yf, nullptr, X, 1.0, 0.0, 0.0, 1, skip, "last64", add_w));
+    if (yf)       // X <- I/2 + (X - I/2)(Y + Y rho)
+        GDM_TRY(gemm64_dd(ctx, Xi, (const float*)Yf, nullptr, X, 1.0, 0.0, 0.5, 1, skip, "last64", add_w));
     else
-        GDM_TRY(gemm64_dd(ctx, X2, (const double*)Y, nullptr, X, 1.0, 0.0, 0.0, 1, skip, "last64", add_w));
+        GDM_TRY(gemm64_dd(ctx, Xi, (const double*)Y, nullptr, X, 1.0, 0.0, 0.5, 1, skip, "last64", add_w));
     GDM_TIMED(ctx, "last64");
     if (Yrec.hi) {
         if (yf)
