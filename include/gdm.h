@@ -412,8 +412,9 @@ int gdm_axpby(gdm_ctx* ctx, int32_t n, double a, const double* x, double b, cons
  * eigenvalues of s/c (c the largest absolute row sum) and the start
  * Z0 = 2.598551 I - 1.834840 s/c (the linear minimax approximation of
  * x^-1/2 for |1 - x z^2| on [0.1, 1]: e0 <= 0.417 there), the error falls
- * as e -> 3/4 e^2 + 1/4 e^3, and one third-order FP64 residual refinement
- * step Z <- Z (I - E/2 + 3/8 E^2), E = Z s Z - I, then cubes it; before that
+ * as e -> 3/4 e^2 + 1/4 e^3, and one third-order residual refinement
+ * step Z <- Z (I - E/2 + 3/8 E^2), E = Z s Z - I (E in FP64, the correction
+ * terms on the split products), then cubes it; before that
  * step gdm_find_mu checks max |E_ij| and, while it exceeds 1e-3, runs one
  * more iteration,
  * at most ns_z_extra times (default 8), after which it returns
