@@ -20,6 +20,9 @@ kernel source, so a change there is checked here).
   on [0.1, 1], the range of s / c.
 * Last doubling's inverse: the same split start and steps, then FP64
   Newton-Schulz steps, each squaring the residual I - A Y exactly for any Y.
+* The FP64 steps taken as corrections: X^2 A^-1 = I/2 + (X - I/2) A^-1,
+  Y (2I - A Y) = Y + Y (I - A Y), and the refinement of Z leaving an O(E^3)
+  residual (exact rational arithmetic).
 """
 import os
 import re
@@ -175,3 +178,65 @@ def test_final_doubling_inverse_start():
     assert (2e-7) ** 2 < 3.6e-12 and ((2e-5) ** 2) ** 2 < 3.6e-12
     r_old = 1.0 - a * (4.0 - 5.0 * a + 2.0 * a * a)
     assert abs((np.abs(r_old) ** 8).max() - 27.0 ** -8) < 1e-20 and 27.0 ** -8 > 3.5e-12
+
+
+def test_fp64_steps_taken_as_corrections():
+    # The last doubling forms X^2 A^-1 as I/2 + (X - I/2) A^-1 with
+    # A = 2 X^2 - 2 X + I, and takes its last Newton-Schulz step as
+    # Y + Y (I - A Y); the refinement of Z uses T = 3/8 E^2 - E/2 so that
+    # (I + T)(I + E)(I + T) = I + O(E^3).  Checked in exact rational
+    # arithmetic on a symmetric X (A then commutes with X) and a symmetric E.
+    from fractions import Fraction
+    rng = np.random.default_rng(5)
+    n = 3
+
+    def mat(m):
+        return [[Fraction(int(v), 11) for v in row] for row in m]
+
+    def mul(X, Z):
+        return [[sum(X[i][k] * Z[k][j] for k in range(n)) for j in range(n)] for i in range(n)]
+
+    def add(X, Z, a=1, b=1):
+        return [[a * X[i][j] + b * Z[i][j] for j in range(n)] for i in range(n)]
+
+    I = [[Fraction(1 if i == j else 0) for j in range(n)] for i in range(n)]
+    M = rng.integers(-5, 6, (n, n))
+    X = mat(M + M.T)
+    A = add(add(mul(X, X), X, 2, -2), I)
+    # A^-1 by Gauss-Jordan in rationals
+    aug = [row[:] + I[i][:] for i, row in enumerate(A)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if aug[r][c] != 0)
+        aug[c], aug[p] = aug[p], aug[c]
+        piv = aug[c][c]
+        aug[c] = [v / piv for v in aug[c]]
+        for r in range(n):
+            if r != c and aug[r][c] != 0:
+                f = aug[r][c]
+                aug[r] = [a - f * b for a, b in zip(aug[r], aug[c])]
+    Ainv = [row[n:] for row in aug]
+    half = [[Fraction(1, 2) if i == j else Fraction(0) for j in range(n)] for i in range(n)]
+    assert mul(mul(X, X), Ainv) == add(half, mul(add(X, half, 1, -1), Ainv))
+    # a plausible slip (I instead of I/2 in the shift) fails
+    assert mul(mul(X, X), Ainv) != add(half, mul(add(X, I, 1, -1), Ainv))
+    Y = mat(rng.integers(-5, 6, (n, n)))
+    rho = add(I, mul(A, Y), 1, -1)
+    assert add(Y, mul(Y, rho)) == mul(Y, add(add(I, I), mul(A, Y), 1, -1))
+    # refinement: with E = t E0 the residual (I + T)(I + E)(I + T) - I has no
+    # t and t^2 terms for T = 3/8 E^2 - E/2, so R(t) / t^2 -> 0
+    M = rng.integers(-5, 6, (n, n))
+    E0 = mat(M + M.T)
+
+    def resid(t):
+        E = [[t * v for v in row] for row in E0]
+        T = add(mul(E, E), E, Fraction(3, 8), Fraction(-1, 2))
+        return add(mul(mul(add(I, T), add(I, E)), add(I, T)), I, 1, -1)
+    for i in range(n):
+        for j in range(n):
+            r1, r2 = resid(Fraction(1, 1000))[i][j], resid(Fraction(1, 2000))[i][j]
+            assert abs(r1) * 1000**2 < Fraction(1, 10) and abs(r2) * 2000**2 < Fraction(1, 20)
+    # T = -E/2 alone (second order) leaves a t^2 term
+    E = [[Fraction(1, 1000) * v for v in row] for row in E0]
+    T2 = [[-v / 2 for v in row] for row in E]
+    R2 = add(mul(mul(add(I, T2), add(I, E)), add(I, T2)), I, 1, -1)
+    assert max(abs(R2[i][j]) for i in range(n) for j in range(n)) * 1000**2 > Fraction(1, 10)
