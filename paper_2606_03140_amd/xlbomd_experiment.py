@@ -72,7 +72,7 @@ def main(argv=None):
     ap.add_argument("--waters", type=int, default=3000)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--grid", type=int, nargs=3, default=(5, 5, 6))
-    ap.add_argument("--steps", type=int, default=40, help="steps at the largest dt")
+    ap.add_argument("--steps", type=int, default=16, help="steps at the largest dt")
     ap.add_argument("--dt", type=float, nargs="+", default=(0.5, 0.25))
     ap.add_argument("--graph", default="cutoff", choices=("cutoff", "adaptive"))
     ap.add_argument("--rebuild", type=int, default=10)
