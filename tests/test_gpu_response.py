@@ -22,6 +22,7 @@ from oracle import graph as og
 from oracle import model as om
 from oracle import response as orsp
 from oracle import scc as osc
+from oracle import solve as osv
 from tests.gpu_common import ctx, log, oracle_model, system_of, tb_params
 
 pytestmark = pytest.mark.gpu
@@ -71,6 +72,11 @@ def test_density_response_matches_oracle(c, orthogonal, nw, seed):
         dq2 = dq2.cpu().numpy()
     finally:
         c.set_response(0)
+    # the GPU's mu against the oracle's own search on the same potential
+    # (the response below is then compared at the GPU's mu)
+    mu_oracle = osv.solve_system(box.pos, box.species, L, oracle_model(orthogonal), subs, V_atom=V).mu
+    log(f"  mu gpu {sol.mu:.6f}, oracle {mu_oracle:.6f} (|d| {abs(sol.mu - mu_oracle):.2e} eV)")
+    assert abs(sol.mu - mu_oracle) < 5e-3
     ref, dmu_ref, _ = orsp.charge_response(box.pos, box.species, L, oracle_model(orthogonal), subs, V, dV,
                                            mu=sol.mu)
     scale = np.abs(ref).max()
