@@ -955,14 +955,21 @@ __global__ void __launch_bounds__(kEw) k_resid_max(const SubDesc* __restrict__ d
     const int P = d.ld, n = d.n, r0 = blockIdx.y * 64;
     if (r0 >= n) return;
     double m = 0.0;
-    for (int e = threadIdx.x; e < 64 * P; e += kEw) {
-        const int i = r0 + e / P, j = e % P;
-        const int64_t idx = d.off2 + (int64_t)i * P + j;
-        if (i < n && j < n) {
-            const double v = fabs(E[idx]);
-            m = v == v ? fmax(m, v) : INFINITY;
-        }
-        if (Es.hi) store_split(Es, idx, (float)(sig * E[idx]));
+    const int q4 = P >> 2;
+    for (int e = threadIdx.x; e < 64 * q4; e += kEw) {
+        const int i = r0 + e / q4, j0 = (e % q4) * 4;
+        const int64_t idx = d.off2 + (int64_t)i * P + j0;
+        const double4 x = *(const double4*)(E + idx);
+        const double xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (i < n && j0 + q < n) {
+                const double v = fabs(xv[q]);
+                m = v == v ? fmax(m, v) : INFINITY;
+            }
+        if (Es.hi)
+            store4(Es, idx, make_float4((float)(sig * x.x), (float)(sig * x.y), (float)(sig * x.z),
+                                        (float)(sig * x.w)));
     }
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
