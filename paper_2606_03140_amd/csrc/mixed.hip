@@ -828,7 +828,10 @@ __global__ void __launch_bounds__(256) k_transpose64(const SubDesc* __restrict__
                                                     const double* __restrict__ scale, double inv_sig,
                                                     double* __restrict__ dst64, SplitMat dsplit,
                                                     const int* __restrict__ skip) {
-    __shared__ double a[64][65], b2[64][65];
+    // one 64 x 64 LDS tile, used twice: first the tile at (J0, I0), whose
+    // transpose is the output at (I0, J0), then the tile at (I0, J0) for the
+    // output at (J0, I0) (a diagonal tile is done after the first)
+    __shared__ double t[64][65];
     if (skip && *skip) return;
     const int4 tl = tiles[blockIdx.x];
     if (tl.x < 0) return;
@@ -836,30 +839,25 @@ __global__ void __launch_bounds__(256) k_transpose64(const SubDesc* __restrict__
     const int P = d.ld;
     const int I0 = tl.y * 64, J0 = tl.z * 64;
     const double f = add ? inv_sig / sqrt(scale[tl.x]) : 0.0;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        const int64_t j1 = d.off2 + (int64_t)(I0 + r) * P + J0 + c, j2 = d.off2 + (int64_t)(J0 + r) * P + I0 + c;
-        a[r][c] = add ? src[j1] + f * (double)add[j1] : src[j1];
-        b2[r][c] = add ? src[j2] + f * (double)add[j2] : src[j2];
-        if (copy) {                     // src as it is (both tiles of the pair)
-            copy[j1] = a[r][c];
-            copy[j2] = b2[r][c];
+    for (int pass = 0; pass < 2; ++pass) {
+        const int R0 = pass == 0 ? J0 : I0, C0 = pass == 0 ? I0 : J0;     // tile read: rows R0.., cols C0..
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int r = e >> 6, c = e & 63;
+            const int64_t j = d.off2 + (int64_t)(R0 + r) * P + C0 + c;
+            const double v = add ? src[j] + f * (double)add[j] : src[j];
+            t[r][c] = v;
+            if (copy) copy[j] = v;          // src as it is (with the addend), in place allowed
         }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        const int64_t i1 = d.off2 + (int64_t)(I0 + r) * P + J0 + c;     // dst[I0+r][J0+c] = src[J0+c][I0+r]
-        const int64_t i2 = d.off2 + (int64_t)(J0 + r) * P + I0 + c;
-        const double v1 = b2[c][r], v2 = a[c][r];
-        if (dst64) {
-            dst64[i1] = v1;
-            dst64[i2] = v2;
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int r = e >> 6, c = e & 63;
+            const int64_t i = d.off2 + (int64_t)(C0 + r) * P + R0 + c;     // dst[C0+r][R0+c] = src[R0+c][C0+r]
+            const double v = t[c][r];
+            if (dst64) dst64[i] = v;
+            if (dsplit.hi) store_split(dsplit, i, (float)v);
         }
-        if (dsplit.hi) {
-            store_split(dsplit, i1, (float)v1);
-            store_split(dsplit, i2, (float)v2);
-        }
+        if (I0 == J0) return;
+        __syncthreads();
     }
 }
 
