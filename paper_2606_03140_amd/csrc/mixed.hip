@@ -627,12 +627,22 @@ __global__ void __launch_bounds__(256) k_trace_dot(const SubDesc* __restrict__ d
     const SubDesc d = desc[blockIdx.x];
     const int n = d.n, P = d.ld, nc = d.nc;
     double an = 0.0, am = 0.0;
-    for (int64_t e = threadIdx.x; e < (int64_t)nc * n; e += 256) {
-        const int a = (int)(e / n), c = (int)(e - (int64_t)a * n);
-        const int64_t idx = d.off2 + (int64_t)a * P + c;
-        const double g = G[idx], v = V[idx];
-        an += g * v;
-        am += (g - G2[idx]) * v;
+    // four consecutive columns per thread (32-byte loads; the padded row
+    // length P is a multiple of 64, columns from n on are skipped)
+    const int q4 = P >> 2;
+    for (int e = threadIdx.x; e < nc * q4; e += 256) {
+        const int a = e / q4, c0 = (e - a * q4) * 4;
+        if (c0 >= n) continue;
+        const int64_t idx = d.off2 + (int64_t)a * P + c0;
+        const double4 g = *(const double4*)(G + idx), g2 = *(const double4*)(G2 + idx),
+                      v = *(const double4*)(V + idx);
+        const double gv[4] = {g.x, g.y, g.z, g.w}, g2v[4] = {g2.x, g2.y, g2.z, g2.w}, vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (c0 + q < n) {
+                an += gv[q] * vv[q];
+                am += (gv[q] - g2v[q]) * vv[q];
+            }
     }
     for (int o = 32; o > 0; o >>= 1) {
         an += __shfl_xor(an, o, 64);
